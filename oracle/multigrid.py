@@ -1,0 +1,141 @@
+"""ORACLE (test infrastructure only): geometric V-cycle approximating M^-1.
+
+The paper preconditions its Krylov data-modelling engine with the
+shifted-Laplace operator M = -Laplace - (beta1 - j beta2) omega^2 m^2 (section
+on FWI, where the GMRES engine is preconditioned; Examples: complex shift
+"1 + j"). It does not say how M^-1 is applied. The method applied here is one
+geometric multigrid V-cycle, written out plainly:
+
+* levels l = 0..L-1, grid n_l = (n - 1) / 2^l + 1 per axis, spacing 2^l h;
+* the slowness on level l is m injected at the coincident nodes, and M_l is
+  rediscretised there with the same formula as the fine operator;
+* damped Jacobi smoothing u <- u + w_l (b - M_l u) / diag(M_l), nu1 sweeps
+  before and nu2 after the coarse correction, starting from u = 0;
+* restriction R = 2^-dim P^T of the weighted residual (full weighting in the
+  interior), bilinear prolongation P (linear in 1D);
+* exact solve on the coarsest level (SuperLU here; any exact method is the
+  same operator).
+
+With L = 1 the V-cycle is the exact solve of M on the fine grid.
+"""
+
+import numpy as np
+import scipy.sparse as sp
+
+from .operator import operator_M
+from .direct import factor_superlu
+
+
+def coarse_shape(shape):
+    """Shape of the next coarser grid; raises if an axis cannot be halved."""
+    out = []
+    for n in shape:
+        if (n - 1) % 2 or (n - 1) // 2 + 1 < 3:
+            raise ValueError(f"grid axis {n} cannot be coarsened")
+        out.append((n - 1) // 2 + 1)
+    return tuple(out)
+
+
+def inject(m):
+    """Slowness on the next coarser grid: values at the coincident nodes."""
+    m = np.asarray(m)
+    return m[::2] if m.ndim == 1 else m[::2, ::2]
+
+
+def linear_interp_1d(nc):
+    """(2 nc - 1) x nc linear interpolation: copy at even, average at odd."""
+    nf = 2 * (nc - 1) + 1
+    rows, cols, vals = [], [], []
+    for I in range(nc):
+        rows.append(2 * I)
+        cols.append(I)
+        vals.append(1.0)
+    for I in range(nc - 1):
+        rows += [2 * I + 1, 2 * I + 1]
+        cols += [I, I + 1]
+        vals += [0.5, 0.5]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+
+
+def prolongation(coarse):
+    """Bilinear (2D) or linear (1D) prolongation from a coarse grid shape."""
+    if len(coarse) == 1:
+        return linear_interp_1d(coarse[0])
+    nzc, nxc = coarse
+    # flat order iz * nx + ix: z is the slow (outer) factor of the Kronecker product
+    return sp.kron(linear_interp_1d(nzc), linear_interp_1d(nxc)).tocsr()
+
+
+def restriction(coarse):
+    """R = 2^-dim P^T (full weighting in the interior)."""
+    return (prolongation(coarse).T * (0.5 ** len(coarse))).tocsr()
+
+
+class VCycle:
+    """One V-cycle V(nu1, nu2) as a fixed linear map b -> u ~ M^-1 b.
+
+    wj: one damped-Jacobi weight per smoothing level (levels 0..L-2).
+    """
+
+    def __init__(self, m, h, omega, beta1, beta2, levels, nu1=2, nu2=2, wj=None):
+        m = np.asarray(m, dtype=np.float64)
+        if levels < 1:
+            raise ValueError("levels must be >= 1")
+        if wj is None:
+            wj = [0.8] * (levels - 1)
+        wj = list(wj)
+        if len(wj) < levels - 1:
+            raise ValueError("need one Jacobi weight per smoothing level")
+        self.nu1, self.nu2 = nu1, nu2
+        self.wj = wj
+        self.shapes, self.M, self.D, self.P, self.R = [], [], [], [], []
+        ml, hl = m, h
+        for l in range(levels):
+            self.shapes.append(ml.shape)
+            Ml = operator_M(ml, hl, omega, beta1, beta2)
+            self.M.append(Ml)
+            self.D.append(Ml.diagonal())
+            if l < levels - 1:
+                cs = coarse_shape(ml.shape)
+                self.P.append(prolongation(cs))
+                self.R.append(restriction(cs))
+                ml, hl = inject(ml), 2 * hl
+        self.coarse_lu = factor_superlu(self.M[-1])
+        self.levels = levels
+
+    def smooth(self, l, u, b, sweeps):
+        for _ in range(sweeps):
+            u = u + self.wj[l] * (b - self.M[l] @ u) / self.D[l]
+        return u
+
+    def cycle(self, l, b):
+        if l == self.levels - 1:
+            return self.coarse_lu.solve(b)
+        u = np.zeros_like(b)
+        u = self.smooth(l, u, b, self.nu1)
+        rc = self.R[l] @ (b - self.M[l] @ u)
+        u = u + self.P[l] @ self.cycle(l + 1, rc)
+        return self.smooth(l, u, b, self.nu2)
+
+    def __call__(self, b):
+        return self.cycle(0, np.asarray(b, dtype=np.complex128))
+
+
+def vcycle_matrix(vc):
+    """Dense matrix of the V-cycle built from its error-propagation form.
+
+    For the two levels l, l+1 the error after one cycle is
+    E_l = S_l^nu2 (I - P_l C_{l+1} R_l M_l) S_l^nu1 with S_l = I - w_l D_l^-1 M_l,
+    where C_{l+1} is the coarse map (exact inverse on the coarsest level,
+    else the coarser V-cycle's matrix). The V-cycle's matrix is then
+    C_l = (I - E_l) M_l^-1. Dense; for tiny grids only.
+    """
+    C = np.linalg.inv(vc.M[-1].toarray())
+    for l in range(vc.levels - 2, -1, -1):
+        M = vc.M[l].toarray()
+        n = M.shape[0]
+        S = np.eye(n) - vc.wj[l] * (M / vc.D[l][:, None])
+        cg = np.eye(n) - vc.P[l].toarray() @ C @ vc.R[l].toarray() @ M
+        E = np.linalg.matrix_power(S, vc.nu2) @ cg @ np.linalg.matrix_power(S, vc.nu1)
+        C = (np.eye(n) - E) @ np.linalg.inv(M)
+    return C

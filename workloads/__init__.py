@@ -1,0 +1,99 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This package holds no arithmetic of the method: it only builds velocity
+models, source and receiver positions and random vectors. Both the HIP path
+and the oracle receive these arrays as inputs.
+
+The paper's own models exist only in figures (the 1D well model and the 2D
+true model of its Examples section), so synthetic models of the same kind
+stand in for them:
+
+* ``model_1d_layers``    1D, 1001 nodes, h = 5 m, three layers
+                         1500/2200/3000 m/s, source at the first node, 10 Hz;
+* ``model_2d_lens``      2D 201 x 201, h = 10 m, 2000 m/s background with a
+                         Gaussian anomaly (sigma 300 m, +-800 m/s), 5 Hz;
+* ``model_2d_layered``   2D 401 x 801, h = 10 m, eight horizontal layers
+                         1500-4500 m/s with a smooth seeded random
+                         perturbation (5 % rms, 200 m correlation), 64
+                         surface shots, frequencies 3/5/8/12 Hz.
+"""
+
+import numpy as np
+from scipy.ndimage import gaussian_filter
+
+
+class Workload(dict):
+    """A dict with attribute access: velocity c, slowness m, h, freqs, ..."""
+
+    __getattr__ = dict.__getitem__
+
+
+def model_1d_layers(n=1001, h=5.0):
+    """Three equal layers over [0, (n-1) h]; an interface node carries the mean
+    of the squared slowness of its two sides."""
+    c1, c2, c3 = 1500.0, 2200.0, 3000.0
+    i1, i2 = n // 3, (2 * n) // 3
+    m = np.empty(n)
+    m[:i1] = 1 / c1
+    m[i1 + 1:i2] = 1 / c2
+    m[i2 + 1:] = 1 / c3
+    m[i1] = np.sqrt(0.5 * (1 / c1 ** 2 + 1 / c2 ** 2))
+    m[i2] = np.sqrt(0.5 * (1 / c2 ** 2 + 1 / c3 ** 2))
+    return Workload(name=f"1d-3layer-{n}", m=m, c=1 / m, h=h, shape=(n,),
+                    freqs=[10.0], alpha=0.01, src=[0], beta=(1.0, 0.5), tol=1e-10)
+
+
+def model_2d_lens(n=201, h=10.0, sign=-1.0):
+    """Gaussian velocity anomaly 2000 + sign*800*exp(-r^2/(2*300^2)) m/s,
+    centred in the square; one source at the middle of the surface row."""
+    x = np.arange(n) * h
+    z = np.arange(n) * h
+    cx = cz = 0.5 * (n - 1) * h
+    Z, X = np.meshgrid(z, x, indexing="ij")
+    r2 = (X - cx) ** 2 + (Z - cz) ** 2
+    c = 2000.0 + sign * 800.0 * np.exp(-r2 / (2 * 300.0 ** 2))
+    src = [0 * n + (n - 1) // 2]
+    return Workload(name=f"2d-lens{'-' if sign < 0 else '+'}-{n}", m=1 / c, c=c, h=h,
+                    shape=(n, n), freqs=[5.0], alpha=0.01, src=src,
+                    beta=(1.0, 0.5), levels=4, nu=(2, 2), wj=0.8, tol=1e-8)
+
+
+def model_2d_layered(nz=401, nx=801, h=10.0, seed=0, nshots=64,
+                     freqs=(3.0, 5.0, 8.0, 12.0)):
+    """Eight horizontal layers 1500-4500 m/s (each 50 cells thick, the last to
+    the bottom) times (1 + p), p a Gaussian-filtered white-noise field
+    (covariance length 200 m), scaled to 5 % rms and clipped to +-15 %.
+    Shots on the surface row at ix = 22 + 12 k (k < 64 for the full grid;
+    spread evenly otherwise)."""
+    layer_v = np.linspace(1500.0, 4500.0, 8)
+    iz = np.arange(nz)
+    c = np.repeat(layer_v[np.minimum(iz // 50, 7)][:, None], nx, axis=1)
+    rng = np.random.default_rng(seed)
+    p = gaussian_filter(rng.standard_normal((nz, nx)), sigma=200.0 / (h * np.sqrt(2.0)))
+    p *= 0.05 / np.sqrt(np.mean(p ** 2))
+    p = np.clip(p, -0.15, 0.15)
+    c = c * (1.0 + p)
+    if nx == 801 and nshots == 64:
+        ix = 22 + 12 * np.arange(64)
+    else:
+        ix = np.round(np.linspace(0.03 * (nx - 1), 0.97 * (nx - 1), nshots)).astype(int)
+    src = [int(i) for i in ix]  # surface row iz = 0: flat index = ix
+    return Workload(name=f"2d-layered-{nz}x{nx}", m=1 / c, c=c, h=h, shape=(nz, nx),
+                    freqs=list(freqs), alpha=0.01, src=src, beta=(1.0, 0.5), tol=1e-8)
+
+
+def random_vectors(nvec, size, seed):
+    """complex128 [nvec, size] with independent standard normal parts."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nvec, size)) + 1j * rng.standard_normal((nvec, size))
+
+
+def smooth_random_vectors(nvec, shape, seed, sigma=3.0):
+    """Smooth complex fields (Gaussian-filtered noise), flattened, [nvec, size]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nvec):
+        re = gaussian_filter(rng.standard_normal(shape), sigma)
+        im = gaussian_filter(rng.standard_normal(shape), sigma)
+        out.append((re + 1j * im).ravel())
+    return np.array(out)
