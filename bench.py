@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched shifted-Laplace preconditioned Helmholtz
+solve on one MI355X.
+
+Workload: the 401 x 801 layered model (h = 10 m, eight layers 1500-4500 m/s
+with a seeded 5 % rms, 200 m correlation perturbation), 64 surface shots x
+frequencies {3, 5, 8, 12} Hz = 256 right-hand sides, complex128, BiCGSTAB
+to relative residual 1e-8 with the LFA-planned V(2,2) shifted-Laplace
+(1, 0.5) preconditioner, all right-hand sides in one batch.
+
+A step = set the model (level hierarchy, coarse inverses per frequency) +
+solve all 256 right-hand sides; inputs are resident in HBM before timing.
+Prints one JSON line (see the field list at the end of main()).
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py --copy-calibration     # a plain copy kernel of known size,
+                                         # for scaling rocprofv3 byte counters
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "Helmholtz solves/s (2D 401x801, 64 RHS), HBM GB/s, p50/p99 solve latency"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("hz_kernels.hip", "hz_internal.h"):
+        with open(os.path.join(ROOT, "paper_1712_08743_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def level_sizes(shape, levels):
+    sizes, shp = [], tuple(shape)
+    for _ in range(levels):
+        sizes.append(int(shp[0] * shp[1]))
+        shp = tuple((s - 1) // 2 + 1 for s in shp)
+    return sizes
+
+
+def bytes_per_iteration(sizes, nu1=2, nu2=2):
+    """Algorithmic HBM bytes of one BiCGSTAB iteration of one right-hand side:
+    each complex vector read or written once per kernel (16 B per node), the
+    shared slowness not counted. Two V-cycles per iteration."""
+    z = 16
+    n0 = sizes[0]
+    krylov = n0 * z * (4 + 3 + 3 + 3 + 8)  # p update, B p^, s update, B s^, x/r update
+    vc = 0
+    for l, n in enumerate(sizes[:-1]):
+        nc = sizes[l + 1]
+        sm = n * z * (2 + 3 * (nu1 - 1) + 3 * nu2)  # first sweep from zero, the rest
+        rs = n * z * 2 + nc * z                     # residual + restriction
+        pr = n * z * 2 + nc * z                     # prolongation + correction
+        vc += sm + rs + pr
+    nc = sizes[-1]
+    vc += 2 * nc * z + nc * nc * z  # coarse solve (dense inverse read once per cycle)
+    return krylov + 2 * vc
+
+
+def smooth_bytes_per_launch_per_rhs(n0):
+    return 48 * n0  # reads b and u_in, writes u_out
+
+
+def percentile(vals, q):
+    s = sorted(vals)
+    if not s:
+        return None
+    k = (len(s) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(s) - 1)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def cpu_baseline(w, iters_per_freq, sample_iters=8, shot=31):
+    """Time the oracle (plain FP64 CPU: SciPy sparse matrices, BiCGSTAB, V-cycle)
+    on a bounded sample: one shot per frequency, capped at sample_iters
+    BiCGSTAB iterations after its setup. Scaled to the full 256-right-hand-side
+    step with the oracle's own iteration counts to convergence."""
+    import numpy as np
+    from oracle import operator as op, multigrid as mg, krylov, lfa
+    per_freq = {}
+    total = 0.0
+    t_all = time.perf_counter()
+    for f in w.freqs:
+        om = 2 * np.pi * f
+        t0 = time.perf_counter()
+        B = op.operator_B(w.m, w.h, om, w.alpha)
+        L, wj = lfa.plan(w.shape, w.h, om, w.m.min(), w.m.max(), 1.0, 0.5)
+        V = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj)
+        t_setup = time.perf_counter() - t0
+        b = op.point_source(w.shape, w.h, [w.src[shot]])
+        t0 = time.perf_counter()
+        _, it, _, _ = krylov.bicgstab(B, b, V, tol=1e-30, maxit=sample_iters)
+        t_it = (time.perf_counter() - t0) / it
+        n_it = iters_per_freq[str(f)]
+        per_freq[str(f)] = {"setup_s": t_setup, "s_per_iteration": t_it, "iterations": n_it}
+        total += t_setup + len(w.src) * n_it * t_it
+    sample_s = time.perf_counter() - t_all
+    nrhs = len(w.src) * len(w.freqs)
+    return {"value": nrhs / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"shot {shot} at each of {len(w.freqs)} frequencies, oracle setup plus "
+                       f"{sample_iters} BiCGSTAB iterations each ({sample_s:.1f} s of CPU); scaled to "
+                       f"{len(w.src)} shots x the oracle's mean iterations to 1e-8 "
+                       "(tests/golden/c3_oracle_iterations.json)"),
+            "host_cpus": os.cpu_count(), "per_freq": per_freq}
+
+
+def copy_calibration():
+    """A plain copy of a known size through the library's copy kernel (the
+    identity preconditioner): 64 vectors of 401 x 801 complex128 read and
+    written once, for scaling hardware byte counters."""
+    import torch
+    import paper_1712_08743_amd as hz
+    import workloads
+    w = workloads.model_2d_layered()
+    c = hz.Context(0)
+    c.set_model(torch.from_numpy(w.m).cuda(), w.h)
+    x = torch.randn((64,) + w.shape, dtype=torch.complex128, device="cuda")
+    for _ in range(5):
+        c.precond(3.0, x, precond="none")
+    torch.cuda.synchronize()
+    nbytes = x.numel() * 16
+    print(json.dumps({"copy_kernel": "k_copy", "read_bytes": nbytes, "write_bytes": nbytes,
+                      "launches": 5}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--kernel", default="smooth", help="kernel class timed with HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the batched solve of one GPU's share); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+    import paper_1712_08743_amd as hz
+    import workloads
+
+    w = workloads.model_2d_layered()
+    nshot, nfreq = len(w.src), len(w.freqs)
+    nrhs = nshot * nfreq
+    ctx = hz.Context(0)
+    m = torch.from_numpy(w.m).cuda()
+    ctx.set_model(m, w.h)
+    b1 = ctx.point_rhs([0] * nshot, w.src)
+    b = torch.stack([b1] * nfreq).contiguous()
+    u = torch.empty_like(b)
+    tol = 1e-8
+
+    def step():
+        ctx.set_model(m, w.h)
+        _, info = ctx.solve(w.freqs, w.alpha, b, out=u, tol=tol)
+        return info
+
+    print(f"# warmup {args.warmup} step(s) on {w.name}, {nrhs} right-hand sides", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_start(args.kernel)
+    infos, lat = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        infos.append(step())
+        lat.extend(ctx.last_seconds)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kern_ms = ctx.timing_read()
+    ctx.timing_start(-1)
+    sec = (t1 - t0) / args.steps
+    print(f"# timed {args.steps} step(s): {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+
+    info = infos[-1]
+    conv = sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED and i[2] <= tol)
+    iters = [i[1] for i in info]
+    L, _ = ctx.plan(w.freqs[0])
+    sizes = level_sizes(w.shape, L)
+    per_freq_iters = {str(f): float(np.mean(iters[k * nshot:(k + 1) * nshot])) for k, f in enumerate(w.freqs)}
+    total_iters = sum(iters)
+    step_bytes = total_iters * bytes_per_iteration(sizes)
+
+    # dominant kernel: fine-level damped-Jacobi sweeps (6 per iteration)
+    sweeps_per_it = 2 * ((2 - 1) + 2)
+    kbytes = total_iters * sweeps_per_it * smooth_bytes_per_launch_per_rhs(sizes[0]) * args.steps
+    achieved = kbytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "smooth_fine_c3_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "k_smooth<2D> (finest level, nonzero start)",
+                "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": (achieved / PEAK_HBM_GBS) if achieved else None, "traffic": traffic,
+                "launches": launches, "avg_launch_ms": kern_ms / max(launches, 1),
+                "algorithmic_bytes_per_launch": kbytes / max(launches, 1)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        gpath = os.path.join(ROOT, "tests", "golden", "c3_oracle_iterations.json")
+        with open(gpath) as fh:
+            gold = json.load(fh)
+        its = {k: v["mean_iterations"] for k, v in gold["freqs"].items()}
+        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, its)
+
+    out = {
+        "metric": METRIC,
+        "value": nrhs / sec,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "2d-layered-401x801, 64 surface shots x {3,5,8,12} Hz = 256 RHS, "
+                               "BiCGSTAB tol 1e-8, V(2,2) shifted-Laplace (1,0.5), LFA-planned weights",
+                   "grid": list(w.shape), "h": w.h, "rhs": nrhs, "levels": L, "tol": tol},
+        "converged": conv,
+        "iterations_mean_per_freq": per_freq_iters,
+        "hbm_gbps_step_model": step_bytes / sec / 1e9,
+        "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * hz.h -- C ABI of the MI355X (gfx950) shifted-Laplace preconditioned
+ * Helmholtz solver.
+ *
+ * Problem (Kazemi, arXiv:1712.08743, section "Full waveform inversion in the
+ * space-frequency domain"): given the real slowness model m = 1/c, the
+ * angular frequency omega = 2 pi f, the damping alpha and sources f, solve
+ * the discretised constant-density Helmholtz equation of Eq. (2)-(3),
+ *     B u = f,   B = -Laplace_h - omega^2 m^2 (1 - j alpha),
+ * with a first-order absorbing boundary (Eq. (1)), and evaluate the misfit
+ * J(m) of Eq. (4) at the receivers. The solve is a right-preconditioned
+ * Krylov method (BiCGSTAB, or GMRES(m) as in the paper's own data-modelling
+ * engine) whose preconditioner is the shifted Laplacian
+ *     M = -Laplace_h - (beta1 - j beta2) omega^2 m^2
+ * applied approximately by one geometric multigrid V-cycle.
+ *
+ * Discretisation (the paper leaves it open; this library's reading):
+ *   nodes (iz, ix), z = iz h, x = ix h, flat index iz*nx + ix, z = 0 is the
+ *   surface; every edge absorbs with du/dn + j omega m u = 0; centred second
+ *   differences with the ghost node eliminated; rows scaled by the control
+ *   volume weight (1/2 per axis on end nodes), so that
+ *     B = L/h^2 + (j omega/h) diag(g m) - omega^2 (1 - j alpha) diag(w m^2)
+ *   is complex symmetric. Right-hand sides are in this weighted form: a unit
+ *   point source at node p is b = e_p / h^dim.
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device memory on the context's device; the
+ *     others are host memory. The caller owns all of them; the library never
+ *     keeps a caller pointer after a call returns.
+ *   - Complex values are interleaved (re, im) doubles: hz_c128 has the layout
+ *     of C99 double _Complex and of a torch.complex128 element.
+ *   - Vectors are stored [rhs][nz][nx] with x fastest (1D: [rhs][n]).
+ *   - All device work is ordered on the stream given to hz_create; each call
+ *     returns after that work has completed.
+ *   - A context is not thread-safe; use one context per host thread/stream.
+ *   - Return value: HZ_OK (0), a positive warning, or a negative error. No
+ *     exception crosses the ABI. hz_last_error() describes the last failure.
+ */
+#ifndef HZ_H
+#define HZ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } hz_c128;
+
+typedef struct hz_ctx hz_ctx;
+
+/* return codes */
+#define HZ_OK            0
+#define HZ_WARN_NOCONV   1   /* output written; some right-hand side did not converge */
+#define HZ_ERR_ARG      -1   /* null pointer, bad size or value, non-finite or non-positive slowness */
+#define HZ_ERR_SHAPE    -2   /* grid cannot be coarsened to the requested level count */
+#define HZ_ERR_NOMEM    -3   /* device allocation failed or workspace budget exceeded */
+#define HZ_ERR_DEVICE   -4   /* a HIP runtime error */
+#define HZ_ERR_STATE    -5   /* no model set */
+
+/* Krylov method */
+#define HZ_BICGSTAB      0
+#define HZ_GMRES         1
+
+/* preconditioner */
+#define HZ_PRECOND_MG    0   /* one V-cycle approximating M^-1 */
+#define HZ_PRECOND_EXACT 1   /* exact M^-1 (1D only: tridiagonal solve) */
+#define HZ_PRECOND_NONE  2
+
+/* per right-hand-side status */
+#define HZ_RHS_CONVERGED 0
+#define HZ_RHS_MAXIT     1
+#define HZ_RHS_BREAKDOWN 2
+#define HZ_RHS_NONFINITE 3
+
+#define HZ_MAX_LEVELS   12
+
+typedef struct {
+    int    device;                  /* HIP device ordinal */
+    void  *hip_stream;              /* hipStream_t to order work on; NULL = the null stream */
+    size_t workspace_budget_bytes;  /* 0 = no limit beyond the device's memory */
+} hz_ctx_opts;
+
+typedef struct {
+    int    krylov;          /* HZ_BICGSTAB (default) or HZ_GMRES */
+    int    gmres_m;         /* GMRES restart length (default 30, at most 200) */
+    double tol;             /* stop when ||b - B u|| <= tol ||b|| (default 1e-8) */
+    int    maxit;           /* iteration cap per right-hand side (default 10000) */
+    int    precond;         /* HZ_PRECOND_* (default HZ_PRECOND_MG) */
+    double beta1, beta2;    /* shift of M (default 1, 0.5); beta2 must be > 0 */
+    int    levels;          /* V-cycle levels incl. the finest; 0 = as many as the grid allows */
+    int    nu1, nu2;        /* pre- and post-smoothing sweeps (default 2, 2) */
+    double jacobi_w;        /* largest damped-Jacobi weight the plan may use (default 0.8) */
+    const double *jacobi_w_level; /* host, optional: fixed weight per smoothing level
+                                     (levels-1 values, every frequency); NULL = plan by LFA */
+} hz_solve_opts;
+
+typedef struct {
+    int    status;          /* HZ_RHS_* */
+    int    iters;           /* Krylov iterations (BiCGSTAB: two preconditioner and two
+                               operator applications each; GMRES: one of each) */
+    double relres;          /* true ||b - B u|| / ||b|| of the returned u (0 if b = 0) */
+    double seconds;         /* device time from the start of the solve to this right-hand
+                               side's last iteration (device wall clock) */
+} hz_rhs_info;
+
+/* Fill *o with the defaults listed above. */
+void hz_default_opts(hz_solve_opts *o);
+
+/* Create a context on a device and stream. *out receives the context.
+ * Errors: HZ_ERR_ARG (null out or o, bad device), HZ_ERR_DEVICE. */
+int  hz_create(hz_ctx **out, const hz_ctx_opts *o);
+
+/* Release every device buffer of the context. NULL is allowed. */
+void hz_destroy(hz_ctx *c);
+
+/* Set the slowness model m (Eq. (2): m = 1/c, real, s/m), dim 1 or 2.
+ * dim 1: nz must be 1 and nx >= 3 is the node count. dim 2: nz, nx >= 3.
+ * m_dev: device, [nz][nx] doubles, copied (the caller may free it after).
+ * Builds the injected slowness of every coarser level.
+ * Errors: HZ_ERR_ARG (bad sizes, h <= 0, non-finite or non-positive m). */
+int  hz_set_model(hz_ctx *c, int dim, int nz, int nx, double h, const double *m_dev);
+
+/* Point sources in weighted form: b_dev[s] = amp[s] / h^dim at node
+ * (iz[s], ix[s]) and zero elsewhere, for s < nsrc. iz, ix, amp are host
+ * arrays (amp NULL = unit amplitude); b_dev is [nsrc][nz][nx].
+ * Errors: HZ_ERR_STATE, HZ_ERR_ARG (node outside the grid). */
+int  hz_point_rhs(hz_ctx *c, int nsrc, const int *iz, const int *ix,
+                  const hz_c128 *amp, hz_c128 *b_dev);
+
+/* Solve B(omega_f) u = b for nfreq frequencies (Hz, > 0) times nrhs
+ * right-hand sides each, all in one batch. b_dev and u_dev are
+ * [nfreq][nrhs][nz][nx] and must not overlap. info (host, optional) receives
+ * nfreq*nrhs records. Returns HZ_WARN_NOCONV if some record's status is not
+ * HZ_RHS_CONVERGED (its u is the last iterate).
+ * Errors: HZ_ERR_ARG, HZ_ERR_SHAPE, HZ_ERR_NOMEM, HZ_ERR_STATE, HZ_ERR_DEVICE. */
+int  hz_solve(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+              double alpha, int nrhs, const hz_c128 *b_dev, hz_c128 *u_dev,
+              hz_rhs_info *info);
+
+/* Misfit of Eq. (4): J = sum over frequencies, shots and receivers of
+ * |d_obs - u(receiver)|^2 + lambda * sum m^2, where u solves B u = b for
+ * each shot (point source at (src_iz, src_ix) with amplitude src_amp,
+ * host arrays, amp NULL = unit). Receivers are nodes (rec_iz, rec_ix), host
+ * arrays. d_obs_dev is [nfreq][nsrc][nrec] on the device; d_cal_dev
+ * (optional, same shape) receives the modelled data. *J is written on the
+ * host. info as in hz_solve (nfreq*nsrc records). */
+int  hz_misfit(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+               double alpha, int nsrc, const int *src_iz, const int *src_ix,
+               const hz_c128 *src_amp, int nrec, const int *rec_iz, const int *rec_ix,
+               const hz_c128 *d_obs_dev, double lambda, double *J,
+               hz_c128 *d_cal_dev, hz_rhs_info *info);
+
+/* The level count and damped-Jacobi weights the solver will use for one
+ * frequency (host computation, no device work): *levels and w[0..levels-2].
+ * w must hold HZ_MAX_LEVELS doubles. The plan: coarsen while every axis has
+ * n-1 even and a coarse size >= 3 (or o->levels if set); per smoothing
+ * level, the largest weight in {0.8,...,0.2} not above o->jacobi_w whose
+ * local-Fourier smoothing factor stays <= 1 over the level's kh range. */
+int  hz_plan(const hz_ctx *c, const hz_solve_opts *o, double freq_hz,
+             int *levels, double *w);
+
+/* The same plan from the grid and the slowness range alone (host only, no
+ * context or device needed): dim, nz, nx, h as in hz_set_model, m_min and
+ * m_max the extreme slowness values. Errors: HZ_ERR_ARG, HZ_ERR_SHAPE. */
+int  hz_plan_grid(int dim, int nz, int nx, double h, double m_min, double m_max,
+                  const hz_solve_opts *o, double freq_hz, int *levels, double *w);
+
+/* ---- single steps of the path, for verification ------------------------ */
+
+/* y = A x on multigrid level `level` (0 = finest) for nrhs vectors, with
+ * A = B (op 0, mass shift 1 - j alpha) or A = M (op 1, shift beta1 - j beta2),
+ * rediscretised on that level's grid with its injected slowness. */
+int  hz_apply(hz_ctx *c, int op, int level, double freq_hz, double alpha,
+              double beta1, double beta2, int nrhs, const hz_c128 *x_dev,
+              hz_c128 *y_dev);
+
+/* One damped-Jacobi sweep of M on a level: u_out = u_in + w (b - M u_in) / diag(M).
+ * u_in_dev may be NULL (u_in = 0). u_out_dev must not alias u_in_dev. */
+int  hz_smooth(hz_ctx *c, int level, double freq_hz, double beta1, double beta2,
+               double w, int nrhs, const hz_c128 *b_dev, const hz_c128 *u_in_dev,
+               hz_c128 *u_out_dev);
+
+/* Weighted-residual restriction: bc = 2^-dim P^T (b - M u) from level to level+1. */
+int  hz_restrict(hz_ctx *c, int level, double freq_hz, double beta1, double beta2,
+                 int nrhs, const hz_c128 *b_dev, const hz_c128 *u_dev, hz_c128 *bc_dev);
+
+/* Bilinear (1D: linear) prolongation and correction: u += P e, e on level+1. */
+int  hz_prolong(hz_ctx *c, int level, int nrhs, const hz_c128 *e_dev, hz_c128 *u_dev);
+
+/* One application of the preconditioner selected by o (V-cycle, exact, or
+ * identity) at one frequency: u = V b for nrhs vectors on the finest grid. */
+int  hz_precond(hz_ctx *c, const hz_solve_opts *o, double freq_hz, int nrhs,
+                const hz_c128 *b_dev, hz_c128 *u_dev);
+
+/* ---- measurement --------------------------------------------------------- */
+
+/* kernel classes that can be timed */
+#define HZ_KERNEL_SMOOTH   0   /* damped-Jacobi sweep from a nonzero start, finest level */
+#define HZ_KERNEL_APPLY    1   /* operator application with fused dot products, finest level */
+#define HZ_KERNEL_RESTRICT 2   /* residual and restriction, finest level */
+#define HZ_KERNEL_PROLONG  3   /* prolongation and correction, finest level */
+#define HZ_KERNEL_UPDATE   4   /* Krylov iterate and residual update */
+#define HZ_KERNEL_COARSE   5   /* dense coarse solve */
+
+/* Start timing one kernel class (resetting its totals), or stop with -1:
+ * every later launch of that class is bracketed by two HIP events on the
+ * context's stream. hz_timing_read returns the launches and the summed
+ * elapsed milliseconds since the start. */
+int  hz_timing_start(hz_ctx *c, int kernel);
+int  hz_timing_read(hz_ctx *c, int *launches, double *total_ms);
+
+/* Text for a return code / the context's last error message. */
+const char *hz_status_str(int status);
+const char *hz_last_error(const hz_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HZ_H */

@@ -1,0 +1,350 @@
+"""Python binding of the HIP Helmholtz solver library (``libhz.so``).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels. PyTorch supplies device memory (tensors passed by data pointer) and
+the stream the work is ordered on. Importing fails loudly when the built
+library is missing; there is no CPU fallback.
+
+The functions mirror the C ABI in ``include/hz.h`` (same names without the
+``hz_`` prefix on the methods of :class:`Context`).
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhz.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built: run `python -m paper_1712_08743_amd.build` "
+        "(hipcc for gfx950) before using the solver")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+HZ_OK, HZ_WARN_NOCONV = 0, 1
+HZ_ERR_ARG, HZ_ERR_SHAPE, HZ_ERR_NOMEM, HZ_ERR_DEVICE, HZ_ERR_STATE = -1, -2, -3, -4, -5
+HZ_BICGSTAB, HZ_GMRES = 0, 1
+HZ_PRECOND_MG, HZ_PRECOND_EXACT, HZ_PRECOND_NONE = 0, 1, 2
+HZ_RHS_CONVERGED, HZ_RHS_MAXIT, HZ_RHS_BREAKDOWN, HZ_RHS_NONFINITE = 0, 1, 2, 3
+HZ_MAX_LEVELS = 12
+HZ_KERNEL = {"smooth": 0, "apply": 1, "restrict": 2, "prolong": 3, "update": 4, "coarse": 5}
+
+PRECOND = {"mg": HZ_PRECOND_MG, "exact": HZ_PRECOND_EXACT, "none": HZ_PRECOND_NONE}
+KRYLOV = {"bicgstab": HZ_BICGSTAB, "gmres": HZ_GMRES}
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
+                ("workspace_budget_bytes", ctypes.c_size_t)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("krylov", ctypes.c_int), ("gmres_m", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("precond", ctypes.c_int), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("levels", ctypes.c_int), ("nu1", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("jacobi_w", ctypes.c_double),
+                ("jacobi_w_level", ctypes.POINTER(ctypes.c_double))]
+
+
+class RhsInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("relres", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_vp, _ip, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+_i, _d = ctypes.c_int, ctypes.c_double
+
+_SIGS = {
+    "hz_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+    "hz_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(CtxOpts)]),
+    "hz_destroy": (None, [_vp]),
+    "hz_set_model": (_i, [_vp, _i, _i, _i, _d, _vp]),
+    "hz_point_rhs": (_i, [_vp, _i, _ip, _ip, _vp, _vp]),
+    "hz_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _vp, _vp,
+                      ctypes.POINTER(RhsInfo)]),
+    "hz_misfit": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
+                       _ip, _vp, _d, _dp, _vp, ctypes.POINTER(RhsInfo)]),
+    "hz_plan": (_i, [_vp, ctypes.POINTER(SolveOpts), _d, _ip, _dp]),
+    "hz_plan_grid": (_i, [_i, _i, _i, _d, _d, _d, ctypes.POINTER(SolveOpts), _d, _ip, _dp]),
+    "hz_apply": (_i, [_vp, _i, _i, _d, _d, _d, _d, _i, _vp, _vp]),
+    "hz_smooth": (_i, [_vp, _i, _d, _d, _d, _d, _i, _vp, _vp, _vp]),
+    "hz_restrict": (_i, [_vp, _i, _d, _d, _d, _i, _vp, _vp, _vp]),
+    "hz_prolong": (_i, [_vp, _i, _i, _vp, _vp]),
+    "hz_precond": (_i, [_vp, ctypes.POINTER(SolveOpts), _d, _i, _vp, _vp]),
+    "hz_timing_start": (_i, [_vp, _i]),
+    "hz_timing_read": (_i, [_vp, _ip, _dp]),
+    "hz_status_str": (ctypes.c_char_p, [_i]),
+    "hz_last_error": (ctypes.c_char_p, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class HzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.hz_status_str(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def default_opts():
+    o = SolveOpts()
+    _lib.hz_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg", beta=(1.0, 0.5),
+              levels=0, nu=(2, 2), jacobi_w=0.8, jacobi_w_level=None):
+    """Build an hz_solve_opts; returns (opts, keepalive)."""
+    o = default_opts()
+    o.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
+    o.gmres_m = int(gmres_m)
+    o.tol = float(tol)
+    o.maxit = int(maxit)
+    o.precond = PRECOND[precond] if isinstance(precond, str) else int(precond)
+    o.beta1, o.beta2 = float(beta[0]), float(beta[1])
+    o.levels = int(levels)
+    o.nu1, o.nu2 = int(nu[0]), int(nu[1])
+    o.jacobi_w = float(jacobi_w)
+    keep = None
+    if jacobi_w_level is not None:
+        keep = (ctypes.c_double * max(1, len(jacobi_w_level)))(*[float(w) for w in jacobi_w_level])
+        o.jacobi_w_level = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+    return o, keep
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _int_array(vals):
+    return (ctypes.c_int * len(vals))(*[int(v) for v in vals])
+
+
+class Context:
+    """One library context bound to a device and torch's current stream there."""
+
+    def __init__(self, device=0, budget_bytes=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        co = CtxOpts(device, ctypes.c_void_p(stream.cuda_stream), budget_bytes)
+        h = ctypes.c_void_p()
+        rc = _lib.hz_create(ctypes.byref(h), ctypes.byref(co))
+        if rc != HZ_OK:
+            raise HzError(rc, "hz_create failed")
+        self._h = h
+        self.shape = None
+        self.h = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hz_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_warn=False):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise HzError(rc, _lib.hz_last_error(self._h).decode())
+        return rc
+
+    # -- model and sources -------------------------------------------------
+    def set_model(self, m, h):
+        """m: float64 tensor (n,) for 1D or (nz, nx) for 2D, slowness in s/m."""
+        t = self.torch
+        m = m.to(device=self.device, dtype=t.float64).contiguous()
+        if m.dim() == 1:
+            dim, nz, nx = 1, 1, m.shape[0]
+        elif m.dim() == 2:
+            dim, nz, nx = 2, m.shape[0], m.shape[1]
+        else:
+            raise ValueError("m must be 1D or 2D")
+        self._check(_lib.hz_set_model(self._h, dim, nz, nx, float(h), _ptr(m)))
+        self.shape = tuple(m.shape)
+        self.dim = dim
+        self.h = float(h)
+        self._m = m
+        return self
+
+    @property
+    def n(self):
+        n = 1
+        for s in self.shape:
+            n *= s
+        return n
+
+    def point_rhs(self, iz, ix, amp=None):
+        """Weighted point sources, complex128 tensor [nsrc, *shape]."""
+        t = self.torch
+        nsrc = len(ix)
+        b = t.empty((nsrc,) + self.shape, dtype=t.complex128, device=self.device)
+        ampbuf = None
+        if amp is not None:
+            ampbuf = (ctypes.c_double * (2 * nsrc))()
+            for k, a in enumerate(amp):
+                ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
+        self._check(_lib.hz_point_rhs(self._h, nsrc, _int_array(iz), _int_array(ix),
+                                      ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
+                                      _ptr(b)))
+        return b
+
+    # -- solves ------------------------------------------------------------
+    def solve(self, freqs, alpha, b, out=None, **opt):
+        """Solve for every frequency and every right-hand side.
+
+        b: complex128 tensor [nfreq, nrhs, *shape] (or [nrhs, *shape] for one
+        frequency). Returns (u, info) with info a list of (status, iters, relres).
+        """
+        t = self.torch
+        freqs = [float(f) for f in freqs]
+        nf = len(freqs)
+        b = b.to(self.device).contiguous()
+        if b.dim() == len(self.shape) + 1:
+            b = b.reshape((1,) + tuple(b.shape))
+        if b.dtype != t.complex128 or b.shape[0] != nf or tuple(b.shape[2:]) != self.shape:
+            raise ValueError(f"b must be complex128 [{nf}, nrhs, {self.shape}], got {b.dtype} {tuple(b.shape)}")
+        nrhs = b.shape[1]
+        u = out if out is not None else t.empty_like(b)
+        if u.shape != b.shape or u.dtype != b.dtype or not u.is_contiguous() or u.device != b.device:
+            raise ValueError("out must be a contiguous tensor like b")
+        o, keep = make_opts(**opt)
+        info = (RhsInfo * (nf * nrhs))()
+        fa = (ctypes.c_double * nf)(*freqs)
+        rc = _lib.hz_solve(self._h, ctypes.byref(o), nf, fa, float(alpha), nrhs, _ptr(b), _ptr(u), info)
+        self._check(rc, allow_warn=True)
+        del keep
+        self.last_seconds = [i.seconds for i in info]
+        return u, [(i.status, i.iters, i.relres) for i in info]
+
+    def misfit(self, freqs, alpha, src, rec, d_obs, lam, src_amp=None, **opt):
+        """J(m) of Eq. (4); src, rec: lists of (iz, ix). Returns (J, d_cal, info)."""
+        t = self.torch
+        freqs = [float(f) for f in freqs]
+        nf, ns, nr = len(freqs), len(src), len(rec)
+        d_obs = d_obs.to(self.device, t.complex128).contiguous()
+        assert tuple(d_obs.shape) == (nf, ns, nr)
+        d_cal = t.empty_like(d_obs)
+        o, keep = make_opts(**opt)
+        info = (RhsInfo * (nf * ns))()
+        J = ctypes.c_double()
+        ampbuf = None
+        if src_amp is not None:
+            ampbuf = (ctypes.c_double * (2 * ns))()
+            for k, a in enumerate(src_amp):
+                ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
+        rc = _lib.hz_misfit(self._h, ctypes.byref(o), nf, (ctypes.c_double * nf)(*freqs), float(alpha), ns,
+                            _int_array([s[0] for s in src]), _int_array([s[1] for s in src]),
+                            ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
+                            nr, _int_array([r[0] for r in rec]), _int_array([r[1] for r in rec]),
+                            _ptr(d_obs), float(lam), ctypes.byref(J), _ptr(d_cal), info)
+        self._check(rc, allow_warn=True)
+        del keep
+        return J.value, d_cal, [(i.status, i.iters, i.relres) for i in info]
+
+    def plan(self, freq, **opt):
+        o, keep = make_opts(**opt)
+        L = ctypes.c_int()
+        w = (ctypes.c_double * HZ_MAX_LEVELS)()
+        self._check(_lib.hz_plan(self._h, ctypes.byref(o), float(freq), ctypes.byref(L), w))
+        return L.value, [w[i] for i in range(L.value - 1)]
+
+    # -- measurement -------------------------------------------------------
+    def timing_start(self, kernel):
+        """Time every launch of one kernel class (name in HZ_KERNEL) with HIP events."""
+        self._check(_lib.hz_timing_start(self._h, HZ_KERNEL[kernel] if isinstance(kernel, str) else kernel))
+
+    def timing_read(self):
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        self._check(_lib.hz_timing_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    # -- single steps ------------------------------------------------------
+    def level_shape(self, level):
+        shp = self.shape
+        for _ in range(level):
+            shp = tuple((s - 1) // 2 + 1 for s in shp)
+        return shp
+
+    def _vecs(self, v, level):
+        """Device complex128 [nrhs, *level_shape] (the library reads exactly that)."""
+        t = self.torch
+        v = v.to(self.device)
+        if v.dtype != t.complex128 or tuple(v.shape[1:]) != self.level_shape(level) or v.shape[0] < 1:
+            raise ValueError(f"expected complex128 [nrhs, {self.level_shape(level)}], got {v.dtype} {tuple(v.shape)}")
+        return v.contiguous()
+
+    def apply(self, op, level, freq, x, alpha=0.0, beta=(1.0, 0.5)):
+        """y = B x (op 'B') or M x (op 'M') on a level; x: [nrhs, *level_shape]."""
+        x = self._vecs(x, level)
+        y = self.torch.empty_like(x)
+        opi = {"B": 0, "M": 1}[op]
+        self._check(_lib.hz_apply(self._h, opi, level, float(freq), float(alpha), float(beta[0]),
+                                  float(beta[1]), x.shape[0], _ptr(x), _ptr(y)))
+        return y
+
+    def smooth(self, level, freq, b, u_in=None, w=0.8, beta=(1.0, 0.5)):
+        b = self._vecs(b, level)
+        out = self.torch.empty_like(b)
+        if u_in is not None:
+            u_in = self._vecs(u_in, level)
+            assert u_in.shape == b.shape
+        uin = _ptr(u_in) if u_in is not None else None
+        self._check(_lib.hz_smooth(self._h, level, float(freq), float(beta[0]), float(beta[1]), float(w),
+                                   b.shape[0], _ptr(b), uin, _ptr(out)))
+        return out
+
+    def restrict(self, level, freq, b, u, beta=(1.0, 0.5)):
+        b = self._vecs(b, level)
+        u = self._vecs(u, level)
+        assert u.shape == b.shape
+        bc = self.torch.empty((b.shape[0],) + self.level_shape(level + 1), dtype=b.dtype, device=self.device)
+        self._check(_lib.hz_restrict(self._h, level, float(freq), float(beta[0]), float(beta[1]),
+                                     b.shape[0], _ptr(b), _ptr(u), _ptr(bc)))
+        return bc
+
+    def prolong(self, level, e, u):
+        """Returns u + P e (u is not modified)."""
+        e = self._vecs(e, level + 1)
+        out = self._vecs(u, level).clone()
+        assert out.shape[0] == e.shape[0]
+        self._check(_lib.hz_prolong(self._h, level, e.shape[0], _ptr(e), _ptr(out)))
+        return out
+
+    def precond(self, freq, b, **opt):
+        b = self._vecs(b, 0)
+        u = self.torch.empty_like(b)
+        o, keep = make_opts(**opt)
+        self._check(_lib.hz_precond(self._h, ctypes.byref(o), float(freq), b.shape[0], _ptr(b), _ptr(u)))
+        del keep
+        return u
+
+
+def plan_grid(shape, h, m_min, m_max, freq, **opt):
+    """Level count and Jacobi weights for a grid (host computation, no device)."""
+    o, keep = make_opts(**opt)
+    dim = len(shape)
+    nz, nx = (1, shape[0]) if dim == 1 else shape
+    L = ctypes.c_int()
+    w = (ctypes.c_double * HZ_MAX_LEVELS)()
+    rc = _lib.hz_plan_grid(dim, nz, nx, float(h), float(m_min), float(m_max), ctypes.byref(o),
+                           float(freq), ctypes.byref(L), w)
+    if rc != HZ_OK:
+        raise HzError(rc, "hz_plan_grid failed")
+    del keep
+    return L.value, [w[i] for i in range(L.value - 1)]
+
+
+def exported_symbols():
+    """Names of the C-ABI functions this binding resolves."""
+    return sorted(_SIGS)

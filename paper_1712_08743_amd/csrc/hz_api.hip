@@ -1,0 +1,1154 @@
+// C-ABI of the Helmholtz solver library: context, model, plan, setup of the
+// multigrid hierarchy and coarse inverses, and the host drivers of the
+// batched Krylov solvers. Device work is enqueued on the context's stream;
+// the host only marshals arguments, sizes launches and polls a small summary
+// that the device writes into mapped host memory.
+
+#include "hz.h"
+#include "hz_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <deque>
+#include <string>
+#include <vector>
+
+using namespace hz;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t nb) {
+    if (nb <= bytes && p) return hipSuccess;
+    release();
+    if (nb == 0) nb = 256;
+    hipError_t e = hipMalloc(&p, nb);
+    if (e == hipSuccess) bytes = nb;
+    else p = nullptr;
+    return e;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct LevelInfo {
+  int nz = 0, nx = 0;
+  double h = 0.0;
+  DevBuf m;
+  size_t n() const { return (size_t)nz * nx; }
+};
+
+// Fine-level vectors of the solvers (x is the caller's output buffer).
+enum FineVec { kR, kRh, kP, kV, kPh, kS, kSh, kT, kT1, kT2, kNumFine };
+// Per coarse level: right-hand side, result, two smoothing buffers.
+enum LevelVec { kLb, kLu, kLx, kLy, kNumLevelVec };
+
+constexpr int kRing = 8;
+constexpr int kLag = 2;
+
+}  // namespace
+
+struct hz_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  std::string err;
+  // model
+  int dim = 0, nz = 0, nx = 0;
+  double h = 0.0, mmin = 0.0, mmax = 0.0;
+  int maxlev = 0;
+  LevelInfo lv[kMaxLevels];
+  int model_version = 0;
+  // solver workspace
+  DevBuf fine[kNumFine];
+  DevBuf lev[kMaxLevels][kNumLevelVec];
+  int ws_slots = 0, ws_levels = 0;
+  DevBuf slots, active, nactive, freqtab, partials, counters, resid;
+  int partial_tiles = 0;
+  int slot_cap = 0;
+  // coarse inverses for the current frequencies
+  DevBuf cinv_a, cinv_b;
+  std::vector<double> cinv_key;  // omega, beta1, beta2 per frequency + levels + version
+  const double2* cinv_base = nullptr;
+  // small uploads
+  DevBuf scratch_int, scratch_c;
+  DevBuf misfit_b, misfit_u, misfit_d, misfit_out;
+  DevBuf gm_V, gm_small, gm_part;
+  // host polling
+  Summary* ring_host = nullptr;
+  Summary* ring_dev = nullptr;
+  hipEvent_t ev[kRing] = {};
+  size_t max_lds = 0;
+  double wall_khz = 0.0;
+  // kernel timing for measurement
+  int timing_cls = -1;
+  std::vector<hipEvent_t> tpool;   // free events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tpairs;  // recorded, not yet folded
+  long long t_launches = 0;
+  double t_ms = 0.0;
+};
+
+namespace {
+
+int fail(hz_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HZ_HIP(c, call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((c), HZ_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+#define HZ_ALLOC(c, buf, bytes)                                                            \
+  do {                                                                                     \
+    hipError_t e_ = (buf).ensure(bytes);                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((c), HZ_ERR_NOMEM, "device allocation of %zu bytes failed: %s",          \
+                  (size_t)(bytes), hipGetErrorString(e_));                                 \
+  } while (0)
+
+Grid grid_of(const hz_ctx* c, int l) {
+  Grid g;
+  g.nz = c->lv[l].nz;
+  g.nx = c->lv[l].nx;
+  g.h = c->lv[l].h;
+  g.m = c->lv[l].m.as<double>();
+  return g;
+}
+
+// Local Fourier analysis of damped Jacobi on h^2 M: for a mode with Laplacian
+// symbol l the error factor is 1 - w (l - s q)/(2 dim - s q), s = beta1 - j
+// beta2, q = (kh)^2; over the high-frequency modes l runs through
+// [2, 4 dim], and the modulus of this affine function of l peaks at an end.
+double smoothing_factor(double kh, double b1, double b2, double w, int dim) {
+  const std::complex<double> s(b1, -b2);
+  const double q = kh * kh;
+  const std::complex<double> den = 2.0 * dim - s * q;
+  auto amp = [&](double l) { return std::abs(1.0 - w * (l - s * q) / den); };
+  return std::max(amp(2.0), amp(4.0 * dim));
+}
+
+const double kWeights[] = {0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2};
+constexpr int kKhSamples = 65;
+
+// Largest level count a grid allows: halve while every axis has n - 1 even
+// and at least 3 nodes after halving.
+int grid_max_levels(int dim, int nz, int nx) {
+  int L = 1;
+  while (L < kMaxLevels) {
+    const bool okx = (nx - 1) % 2 == 0 && (nx - 1) / 2 + 1 >= 3;
+    const bool okz = dim == 1 || ((nz - 1) % 2 == 0 && (nz - 1) / 2 + 1 >= 3);
+    if (!okx || !okz) break;
+    nx = (nx - 1) / 2 + 1;
+    if (dim == 2) nz = (nz - 1) / 2 + 1;
+    ++L;
+  }
+  return L;
+}
+
+int plan_grid(int dim, int maxlev, double h, double mmin, double mmax, const hz_solve_opts* o,
+              double omega, int* levels, double* w) {
+  int L = o->levels > 0 ? o->levels : maxlev;
+  if (L > maxlev) return HZ_ERR_SHAPE;
+  *levels = L;
+  for (int l = 0; l < L - 1; ++l) {
+    if (o->jacobi_w_level) {
+      w[l] = o->jacobi_w_level[l];
+      continue;
+    }
+    const double hl = h * ldexp(1.0, l);
+    const double lo = omega * hl * mmin, hi = omega * hl * mmax;
+    double chosen = -1.0, best = -1.0, best_mu = 0.0;
+    for (double cand : kWeights) {
+      if (cand > o->jacobi_w + 1e-12) continue;
+      double worst = 0.0;
+      for (int i = 0; i < kKhSamples; ++i) {
+        const double kh = lo + (hi - lo) * i / (double)(kKhSamples - 1);
+        worst = std::max(worst, smoothing_factor(kh, o->beta1, o->beta2, cand, dim));
+      }
+      if (worst <= 1.0) {
+        chosen = cand;
+        break;
+      }
+      if (best < 0.0 || worst < best_mu) {
+        best = cand;
+        best_mu = worst;
+      }
+    }
+    w[l] = chosen > 0.0 ? chosen : (best > 0.0 ? best : o->jacobi_w);
+  }
+  return HZ_OK;
+}
+
+int make_plan(const hz_ctx* c, const hz_solve_opts* o, double omega, int* levels, double* w) {
+  return plan_grid(c->dim, c->maxlev, c->h, c->mmin, c->mmax, o, omega, levels, w);
+}
+
+int check_opts(hz_ctx* c, const hz_solve_opts* o) {
+  if (!(o->tol > 0.0) || !isfinite(o->tol)) return fail(c, HZ_ERR_ARG, "tol must be positive");
+  if (o->maxit < 1) return fail(c, HZ_ERR_ARG, "maxit must be >= 1");
+  if (o->krylov != HZ_BICGSTAB && o->krylov != HZ_GMRES) return fail(c, HZ_ERR_ARG, "unknown krylov method");
+  if (o->krylov == HZ_GMRES && (o->gmres_m < 1 || o->gmres_m > 200))
+    return fail(c, HZ_ERR_ARG, "gmres_m must be in [1, 200]");
+  if (o->precond < HZ_PRECOND_MG || o->precond > HZ_PRECOND_NONE) return fail(c, HZ_ERR_ARG, "unknown preconditioner");
+  if (o->precond != HZ_PRECOND_NONE) {
+    if (!(o->beta2 > 0.0) || !isfinite(o->beta1) || !isfinite(o->beta2))
+      return fail(c, HZ_ERR_ARG, "the shift needs beta2 > 0 and finite beta1");
+  }
+  if (o->precond == HZ_PRECOND_MG) {
+    if (o->nu1 < 1 || o->nu2 < 0 || o->nu1 > 16 || o->nu2 > 16)
+      return fail(c, HZ_ERR_ARG, "need 1 <= nu1 <= 16 and 0 <= nu2 <= 16");
+    if (!(o->jacobi_w > 0.0 && o->jacobi_w <= 1.0)) return fail(c, HZ_ERR_ARG, "jacobi_w must be in (0, 1]");
+    if (o->levels < 0) return fail(c, HZ_ERR_ARG, "levels must be >= 0");
+    if (o->levels > c->maxlev)
+      return fail(c, HZ_ERR_SHAPE, "grid %dx%d allows at most %d levels", c->nz, c->nx, c->maxlev);
+    if (o->jacobi_w_level) {
+      const int L = o->levels > 0 ? o->levels : c->maxlev;
+      for (int l = 0; l < L - 1; ++l)
+        if (!(o->jacobi_w_level[l] > 0.0 && o->jacobi_w_level[l] <= 1.0))
+          return fail(c, HZ_ERR_ARG, "jacobi_w_level[%d] must be in (0, 1]", l);
+    }
+  }
+  if (o->precond == HZ_PRECOND_EXACT) {
+    if (c->dim != 1) return fail(c, HZ_ERR_ARG, "the exact preconditioner is the 1D tridiagonal solve");
+    const size_t lds = (size_t)4 * c->nx * sizeof(double2);
+    if (c->nx > kPcrMax || lds > c->max_lds)
+      return fail(c, HZ_ERR_ARG, "1D grid of %d nodes is too long for the exact tridiagonal solve", c->nx);
+  }
+  return HZ_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+int ensure_workspace(hz_ctx* c, int nslots, int levels) {
+  const size_t n0 = c->lv[0].n();
+  size_t total = 0;
+  total += (size_t)kNumFine * nslots * n0 * sizeof(double2);
+  for (int l = 1; l < levels; ++l) total += (size_t)kNumLevelVec * nslots * c->lv[l].n() * sizeof(double2);
+  if (c->budget && total > c->budget)
+    return fail(c, HZ_ERR_NOMEM, "workspace of %zu bytes exceeds the budget of %zu", total, c->budget);
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < kNumFine; ++k) HZ_ALLOC(c, c->fine[k], (size_t)nslots * n0 * sizeof(double2));
+  for (int l = 1; l < levels; ++l)
+    for (int k = 0; k < kNumLevelVec; ++k)
+      HZ_ALLOC(c, c->lev[l][k], (size_t)nslots * c->lv[l].n() * sizeof(double2));
+  // reduction scratch: enough tiles for any kernel on the fine grid
+  const Tiles t = grid_tiles(c->lv[0].nz, c->lv[0].nx, c->dim);
+  const int tiles = std::max(t.per_slot, vec_tiles(n0));
+  if (nslots > c->slot_cap || tiles > c->partial_tiles) {
+    const int cap = std::max(nslots, c->slot_cap);
+    HZ_ALLOC(c, c->partials, (size_t)cap * tiles * 4 * sizeof(double));
+    HZ_ALLOC(c, c->counters, (size_t)cap * sizeof(unsigned));
+    HZ_HIP(c, hipMemsetAsync(c->counters.p, 0, (size_t)cap * sizeof(unsigned), c->stream));
+    HZ_ALLOC(c, c->slots, (size_t)cap * sizeof(Slot));
+    HZ_ALLOC(c, c->active, (size_t)cap * sizeof(int));
+    HZ_ALLOC(c, c->nactive, sizeof(int) * 4);
+    HZ_ALLOC(c, c->resid, (size_t)cap * 2 * sizeof(double));
+    c->slot_cap = cap;
+    c->partial_tiles = tiles;
+  }
+  c->ws_slots = nslots;
+  c->ws_levels = levels;
+  return HZ_OK;
+}
+
+Reduce reducer(const hz_ctx* c) {
+  Reduce r;
+  r.partials = c->partials.as<double>();
+  r.counters = c->counters.as<unsigned>();
+  r.max_tiles = c->partial_tiles;
+  return r;
+}
+
+Batch batch_of(const hz_ctx* c) {
+  Batch b;
+  b.active = c->active.as<int>();
+  b.nactive = c->nactive.as<int>();
+  b.slots = c->slots.as<Slot>();
+  b.ft = c->freqtab.as<FreqTab>();
+  return b;
+}
+
+// Upload slot records (all active, frequency = slot / nrhs) and the list 0..n-1.
+int reset_slots(hz_ctx* c, int nslots, int nrhs) {
+  std::vector<Slot> s(nslots);
+  std::vector<int> act(nslots);
+  for (int i = 0; i < nslots; ++i) {
+    memset(&s[i], 0, sizeof(Slot));
+    s[i].status = kActive;
+    s[i].freq = i / nrhs;
+    act[i] = i;
+  }
+  HZ_HIP(c, hipMemcpyAsync(c->slots.p, s.data(), nslots * sizeof(Slot), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(c->active.p, act.data(), nslots * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(c->nactive.p, &nslots, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+// Build the per-frequency table; invert the coarsest M when the V-cycle needs it.
+int setup_freqs(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+                int levels, const std::vector<std::vector<double>>& wj) {
+  std::vector<FreqTab> ft(nfreq);
+  for (int f = 0; f < nfreq; ++f) {
+    memset(&ft[f], 0, sizeof(FreqTab));
+    ft[f].omega = 2.0 * M_PI * freq_hz[f];
+    ft[f].sB_re = 1.0;
+    ft[f].sB_im = -alpha;
+    ft[f].sM_re = o->beta1;
+    ft[f].sM_im = -o->beta2;
+    for (int l = 0; l < levels - 1 && l < (int)wj[f].size(); ++l) ft[f].wj[l] = wj[f][l];
+  }
+  HZ_ALLOC(c, c->freqtab, (size_t)nfreq * sizeof(FreqTab));
+  const bool need_coarse = o->precond == HZ_PRECOND_MG;
+  if (need_coarse) {
+    const int cl = levels - 1;
+    const size_t nc = c->lv[cl].n();
+    if (nc > (size_t)kCoarseMax)
+      return fail(c, HZ_ERR_SHAPE, "coarsest level has %zu unknowns (limit %d); allow more levels", nc, kCoarseMax);
+    std::vector<double> key;
+    key.push_back(c->model_version);
+    key.push_back(levels);
+    key.push_back(o->beta1);
+    key.push_back(o->beta2);
+    for (int f = 0; f < nfreq; ++f) key.push_back(ft[f].omega);
+    if (key != c->cinv_key || !c->cinv_base) {
+      const size_t bytes = nc * nc * nfreq * sizeof(double2);
+      if (c->budget && bytes * 2 > c->budget)
+        return fail(c, HZ_ERR_NOMEM, "coarse inverses need %zu bytes", bytes * 2);
+      HZ_ALLOC(c, c->cinv_a, bytes);
+      HZ_ALLOC(c, c->cinv_b, bytes);
+      HZ_HIP(c, hipMemcpyAsync(c->freqtab.p, ft.data(), nfreq * sizeof(FreqTab), hipMemcpyHostToDevice, c->stream));
+      HZ_HIP(c, launch_assemble_dense(c->dim, grid_of(c, cl), nfreq, c->freqtab.as<FreqTab>(),
+                                      c->cinv_a.as<double2>(), c->stream));
+      double2* src = c->cinv_a.as<double2>();
+      double2* dst = c->cinv_b.as<double2>();
+      for (size_t k = 0; k < nc; ++k) {
+        HZ_HIP(c, launch_gj_step((int)nc, nfreq, (int)k, src, dst, c->stream));
+        std::swap(src, dst);
+      }
+      c->cinv_base = src;
+      c->cinv_key = key;
+    }
+    for (int f = 0; f < nfreq; ++f) ft[f].cinv = c->cinv_base + (size_t)f * nc * nc;
+  }
+  HZ_HIP(c, hipMemcpyAsync(c->freqtab.p, ft.data(), nfreq * sizeof(FreqTab), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+// Event pair around one launch of the timed kernel class (no-op otherwise).
+hipEvent_t take_event(hz_ctx* c) {
+  if (!c->tpool.empty()) {
+    hipEvent_t e = c->tpool.back();
+    c->tpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <class F>
+hipError_t timed(hz_ctx* c, int cls, F&& launch) {
+  if (c->timing_cls != cls) return launch();
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, c->stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+  c->tpairs.emplace_back(a, b);
+  return e;
+}
+
+// Fold recorded pairs into the totals (the stream must have been synchronised).
+void fold_timing(hz_ctx* c) {
+  for (auto& pr : c->tpairs) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      c->t_ms += ms;
+      c->t_launches += 1;
+    }
+    c->tpool.push_back(pr.first);
+    c->tpool.push_back(pr.second);
+  }
+  c->tpairs.clear();
+}
+
+// ---------------------------------------------------------------- V-cycle
+struct Cycle {
+  int levels, nu1, nu2, precond;
+};
+
+// out = V b on the finest grid for the slots of the active list.
+hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0, double2* out) {
+  const Batch bt = batch_of(c);
+  const int dim = c->dim;
+  hipStream_t st = c->stream;
+  const size_t n0 = c->lv[0].n();
+  if (cy.precond == HZ_PRECOND_NONE) return launch_copy(bt, cap, n0, b0, out, n0, st);
+  if (cy.precond == HZ_PRECOND_EXACT) return launch_pcr(grid_of(c, 0), bt, cap, b0, out, n0, st);
+  const int L = cy.levels;
+  if (L == 1) return launch_coarse_solve((int)n0, bt, cap, b0, out, n0, st);
+  hipError_t e;
+  // descend
+  const double2* bl = b0;
+  double2* cur[kMaxLevels];
+  for (int l = 0; l < L - 1; ++l) {
+    const Grid g = grid_of(c, l);
+    const size_t nl = c->lv[l].n();
+    double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
+    double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
+    double2* u = nullptr;
+    for (int k = 0; k < cy.nu1; ++k) {
+      double2* dst = (u == X) ? Y : X;
+      const int cls = (l == 0 && u) ? HZ_KERNEL_SMOOTH : -2;
+      if ((e = timed(c, cls, [&] { return launch_smooth(dim, g, l, 0.0, bt, cap, bl, u, dst, nl, st); })) != hipSuccess)
+        return e;
+      u = dst;
+    }
+    cur[l] = u;
+    double2* bc = c->lev[l + 1][kLb].as<double2>();
+    if ((e = timed(c, l == 0 ? HZ_KERNEL_RESTRICT : -2, [&] {
+           return launch_restrict(dim, g, grid_of(c, l + 1), bt, cap, bl, u, bc, nl, c->lv[l + 1].n(), st);
+         })) != hipSuccess)
+      return e;
+    bl = bc;
+  }
+  // coarsest
+  {
+    const int cl = L - 1;
+    if ((e = timed(c, HZ_KERNEL_COARSE, [&] {
+           return launch_coarse_solve((int)c->lv[cl].n(), bt, cap, c->lev[cl][kLb].as<double2>(),
+                                      c->lev[cl][kLu].as<double2>(), c->lv[cl].n(), st);
+         })) != hipSuccess)
+      return e;
+  }
+  // ascend
+  for (int l = L - 2; l >= 0; --l) {
+    const Grid g = grid_of(c, l);
+    const size_t nl = c->lv[l].n();
+    double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
+    double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
+    double2* R = l == 0 ? out : c->lev[l][kLu].as<double2>();
+    const double2* bll = l == 0 ? b0 : c->lev[l][kLb].as<double2>();
+    double2* u = cur[l];
+    double2* pdst = cy.nu2 == 0 ? R : u;
+    if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
+           return launch_prolong(dim, g, grid_of(c, l + 1), bt, cap, c->lev[l + 1][kLu].as<double2>(), u,
+                                 pdst, nl, c->lv[l + 1].n(), st);
+         })) != hipSuccess)
+      return e;
+    u = pdst;
+    for (int k = 0; k < cy.nu2; ++k) {
+      double2* dst = (k == cy.nu2 - 1) ? R : ((u == X) ? Y : X);
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : -2, [&] {
+             return launch_smooth(dim, g, l, 0.0, bt, cap, bll, u, dst, nl, st);
+           })) != hipSuccess)
+        return e;
+      u = dst;
+    }
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------- BiCGSTAB driver
+int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
+                 const double2* b, double2* x) {
+  const size_t n0 = c->lv[0].n();
+  const Batch bt = batch_of(c);
+  const Reduce rd = reducer(c);
+  const Grid g0 = grid_of(c, 0);
+  hipStream_t st = c->stream;
+  double2* r = c->fine[kR].as<double2>();
+  double2* rh = c->fine[kRh].as<double2>();
+  double2* p = c->fine[kP].as<double2>();
+  double2* v = c->fine[kV].as<double2>();
+  double2* s = c->fine[kS].as<double2>();
+  double2* t = c->fine[kT].as<double2>();
+  double2* ph = cy.precond == HZ_PRECOND_NONE ? p : c->fine[kPh].as<double2>();
+  double2* sh = cy.precond == HZ_PRECOND_NONE ? s : c->fine[kSh].as<double2>();
+  const bool identity = cy.precond == HZ_PRECOND_NONE;
+
+  long long seq = 0;                 // units issued
+  long long restart_seq = -1;        // last unit that was a restart
+  std::deque<std::pair<long long, int>> pending;  // (unit, ring slot)
+  int ring_next = 0;
+  auto close_unit = [&]() -> int {
+    const int k = ring_next;
+    ring_next = (ring_next + 1) % kRing;
+    HZ_HIP(c, launch_compact(nslots, bt.slots, c->active.as<int>(), c->nactive.as<int>(), c->ring_dev + k, 0, st));
+    HZ_HIP(c, hipEventRecord(c->ev[k], st));
+    pending.emplace_back(seq++, k);
+    return HZ_OK;
+  };
+
+  int rc;
+  HZ_HIP(c, launch_bicg_init(n0, bt, nslots, rd, b, x, r, rh, p, v, n0, st));
+  if ((rc = close_unit()) != HZ_OK) return rc;
+
+  int cap = nslots;
+  long long iters_issued = 0;
+  const long long guard = 2LL * (o->maxit + 2) + 16;
+  bool done = false;
+  while (!done) {
+    while (!pending.empty() && ((int)pending.size() > kLag || cap == 0)) {
+      const auto [useq, k] = pending.front();
+      pending.pop_front();
+      HZ_HIP(c, hipEventSynchronize(c->ev[k]));
+      const Summary sm = c->ring_host[k];
+      const bool stale = restart_seq > useq;
+      if (!stale) {
+        cap = std::min(cap, sm.nactive);
+        if (sm.nrestart > 0) {
+          HZ_HIP(c, launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st));
+          restart_seq = seq;
+          if ((rc = close_unit()) != HZ_OK) return rc;
+          cap = nslots;
+        } else if (sm.nactive == 0) {
+          done = true;
+          break;
+        }
+      }
+    }
+    if (done) break;
+    if (cap == 0) {
+      if (pending.empty()) break;
+      continue;
+    }
+    if (iters_issued >= guard) break;
+    HZ_HIP(c, launch_bicg_p(n0, bt, cap, r, p, v, n0, st));
+    if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, p, ph));
+    HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] {
+             return launch_bicg_apply_sigma(c->dim, g0, bt, cap, rd, ph, rh, v, n0, st);
+           }));
+    HZ_HIP(c, launch_bicg_s(n0, bt, cap, r, v, s, n0, st));
+    if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, s, sh));
+    HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] {
+             return launch_bicg_apply_omega(c->dim, g0, bt, cap, rd, sh, s, t, n0, st);
+           }));
+    HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
+             return launch_bicg_xr(n0, bt, cap, rd, o->tol, o->maxit, x, ph, sh, s, t, r, rh, n0, st);
+           }));
+    ++iters_issued;
+    if ((rc = close_unit()) != HZ_OK) return rc;
+  }
+  HZ_HIP(c, hipStreamSynchronize(st));
+  fold_timing(c);
+  return HZ_OK;
+}
+
+// ---------------------------------------------------------------- GMRES(m) driver
+// All slots run one restart cycle in lockstep: Arnoldi step j is launched for
+// the slots still in phase 0; a slot whose residual estimate meets tol (or
+// that reaches maxit or step m) moves to phase 1 and waits. When none is left
+// in phase 0 the cycle ends for all: y = H^-1 g, x += M^-1 (V y), and the
+// true residual starts the next cycle or finishes the slot.
+int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, const double2* b,
+              double2* x) {
+  const int m = o->gmres_m;
+  const size_t n0 = c->lv[0].n();
+  const size_t vstride = (size_t)nslots * n0;
+  const int tiles = vec_tiles(n0);
+  const size_t vbytes = (size_t)(m + 1) * vstride * sizeof(double2);
+  if (c->budget && vbytes > c->budget)
+    return fail(c, HZ_ERR_NOMEM, "GMRES basis of %zu bytes exceeds the budget", vbytes);
+  HZ_ALLOC(c, c->gm_V, vbytes);
+  const size_t m1 = (size_t)m + 1;
+  const size_t nH = (size_t)nslots * m1 * m, ng = (size_t)nslots * m1, nsn = (size_t)nslots * m;
+  const size_t nhc = (size_t)nslots * 2 * m1;
+  HZ_ALLOC(c, c->gm_small, (nH + ng + nsn + nsn + nhc) * sizeof(double2) + nsn * sizeof(double));
+  HZ_ALLOC(c, c->gm_part, (size_t)nslots * tiles * 2 * m1 * sizeof(double));
+  Gmres gm;
+  double2* base = c->gm_small.as<double2>();
+  gm.H = base;
+  gm.g = gm.H + nH;
+  gm.sn = gm.g + ng;
+  gm.y = gm.sn + nsn;
+  gm.hc = gm.y + nsn;
+  gm.cs = reinterpret_cast<double*>(gm.hc + nhc);
+  gm.partials = c->gm_part.as<double>();
+  gm.m = m;
+  gm.max_tiles = tiles;
+
+  const Batch bt = batch_of(c);
+  const Reduce rd = reducer(c);
+  const Grid g0 = grid_of(c, 0);
+  hipStream_t st = c->stream;
+  const bool identity = cy.precond == HZ_PRECOND_NONE;
+  double2* V = c->gm_V.as<double2>();
+  double2* z = c->fine[kPh].as<double2>();
+  double2* t = c->fine[kT].as<double2>();
+
+  std::deque<std::pair<long long, int>> pending;
+  long long seq = 0;
+  int ring_next = 0;
+  auto close_unit = [&](int phase) -> int {
+    const int k = ring_next;
+    ring_next = (ring_next + 1) % kRing;
+    HZ_HIP(c, launch_compact(nslots, bt.slots, c->active.as<int>(), c->nactive.as<int>(), c->ring_dev + k, phase, st));
+    HZ_HIP(c, hipEventRecord(c->ev[k], st));
+    pending.emplace_back(seq++, k);
+    return HZ_OK;
+  };
+  auto drain = [&](Summary* last) -> int {
+    while (!pending.empty()) {
+      const int k = pending.front().second;
+      pending.pop_front();
+      HZ_HIP(c, hipEventSynchronize(c->ev[k]));
+      *last = c->ring_host[k];
+    }
+    return HZ_OK;
+  };
+
+  int rc;
+  Summary sm{};
+  HZ_HIP(c, launch_gm_residual(c->dim, g0, bt, nslots, rd, gm, 1, o->tol, o->maxit, b, x, V, n0, st));
+  if ((rc = close_unit(0)) != HZ_OK) return rc;
+  if ((rc = drain(&sm)) != HZ_OK) return rc;
+  int cap = sm.nactive;
+  const long long guard = (long long)o->maxit + 2;
+  long long cycles = 0;
+  while (cap > 0 && cycles++ <= guard) {
+    for (int j = 0; j < m && cap > 0; ++j) {
+      const double2* vj = V + (size_t)j * vstride;
+      double2* w = V + (size_t)(j + 1) * vstride;
+      const double2* zin = vj;
+      if (!identity) {
+        HZ_HIP(c, precond_apply(c, cy, cap, vj, z));
+        zin = z;
+      }
+      HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] { return launch_apply(c->dim, g0, 0, 0, bt, cap, zin, w, n0, st); }));
+      HZ_HIP(c, launch_gm_dots(n0, bt, cap, rd, gm, j, 0, V, vstride, w, n0, st));
+      HZ_HIP(c, launch_gm_orth(n0, bt, cap, rd, gm, j, 0, o->tol, o->maxit, V, vstride, w, n0, st));
+      HZ_HIP(c, launch_gm_dots(n0, bt, cap, rd, gm, j, 1, V, vstride, w, n0, st));
+      HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
+               return launch_gm_orth(n0, bt, cap, rd, gm, j, 1, o->tol, o->maxit, V, vstride, w, n0, st);
+             }));
+      HZ_HIP(c, launch_gm_scale(n0, bt, cap, w, n0, st));
+      if ((rc = close_unit(0)) != HZ_OK) return rc;
+      while ((int)pending.size() > kLag) {
+        const int k = pending.front().second;
+        pending.pop_front();
+        HZ_HIP(c, hipEventSynchronize(c->ev[k]));
+        cap = std::min(cap, c->ring_host[k].nactive);
+      }
+    }
+    if ((rc = drain(&sm)) != HZ_OK) return rc;
+    // cycle end for every slot waiting in phase 1
+    if ((rc = close_unit(1)) != HZ_OK) return rc;
+    if ((rc = drain(&sm)) != HZ_OK) return rc;
+    const int n1 = sm.nactive;
+    if (n1 == 0) break;
+    HZ_HIP(c, launch_gm_solve(bt, n1, gm, st));
+    HZ_HIP(c, launch_gm_combine(n0, bt, n1, gm, V, vstride, t, n0, st));
+    const double2* upd = t;
+    if (!identity) {
+      HZ_HIP(c, precond_apply(c, cy, n1, t, z));
+      upd = z;
+    }
+    HZ_HIP(c, launch_axpy1(n0, bt, n1, upd, x, n0, st));
+    HZ_HIP(c, launch_gm_residual(c->dim, g0, bt, n1, rd, gm, 0, o->tol, o->maxit, b, x, V, n0, st));
+    if ((rc = close_unit(0)) != HZ_OK) return rc;
+    if ((rc = drain(&sm)) != HZ_OK) return rc;
+    cap = sm.nactive;
+    if (cap > 0) HZ_HIP(c, launch_gm_scale(n0, bt, cap, V, n0, st));
+  }
+  HZ_HIP(c, hipStreamSynchronize(st));
+  fold_timing(c);
+  return HZ_OK;
+}
+
+// Final statuses and true residuals for every slot.
+int collect_info(hz_ctx* c, int nslots, const double2* b, const double2* x, hz_rhs_info* info,
+                 int* any_fail) {
+  std::vector<int> act(nslots);
+  for (int i = 0; i < nslots; ++i) act[i] = i;
+  HZ_HIP(c, hipMemcpyAsync(c->active.p, act.data(), nslots * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(c->nactive.p, &nslots, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, launch_true_residual(c->dim, grid_of(c, 0), batch_of(c), nslots, reducer(c), b, x,
+                                 c->resid.as<double>(), c->lv[0].n(), c->stream));
+  std::vector<Slot> s(nslots);
+  std::vector<double> res(2 * nslots);
+  HZ_HIP(c, hipMemcpyAsync(s.data(), c->slots.p, nslots * sizeof(Slot), hipMemcpyDeviceToHost, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(res.data(), c->resid.p, 2 * nslots * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  *any_fail = 0;
+  for (int i = 0; i < nslots; ++i) {
+    int stt = s[i].status;
+    if (stt == kActive) stt = kMaxit;
+    if (stt == kRestart) stt = kBreakdown;
+    if (stt != kConverged) *any_fail = 1;
+    if (info) {
+      info[i].status = stt;
+      info[i].iters = s[i].iters;
+      info[i].relres = res[2 * i + 1] > 0.0 ? sqrt(res[2 * i]) / sqrt(res[2 * i + 1]) : 0.0;
+      info[i].seconds = c->wall_khz > 0.0 ? (double)(s[i].t1 - s[i].t0) / (c->wall_khz * 1e3) : 0.0;
+    }
+  }
+  return HZ_OK;
+}
+
+int require_model(hz_ctx* c) {
+  if (!c) return HZ_ERR_ARG;
+  if (c->dim == 0) return fail(c, HZ_ERR_STATE, "no model set");
+  return HZ_OK;
+}
+
+int setup_debug_batch(hz_ctx* c, int nrhs, double freq_hz, double alpha, double beta1, double beta2,
+                      const double* wj, int nwj) {
+  if (nrhs < 1) return fail(c, HZ_ERR_ARG, "nrhs must be >= 1");
+  if (!(freq_hz > 0.0) || !isfinite(freq_hz)) return fail(c, HZ_ERR_ARG, "frequency must be positive");
+  int rc = ensure_workspace(c, nrhs, std::max(c->ws_levels, 1));
+  if (rc) return rc;
+  FreqTab ft;
+  memset(&ft, 0, sizeof ft);
+  ft.omega = 2.0 * M_PI * freq_hz;
+  ft.sB_re = 1.0;
+  ft.sB_im = -alpha;
+  ft.sM_re = beta1;
+  ft.sM_im = -beta2;
+  for (int l = 0; l < nwj && l < kMaxLevels; ++l) ft.wj[l] = wj[l];
+  HZ_ALLOC(c, c->freqtab, sizeof(FreqTab));
+  HZ_HIP(c, hipMemcpyAsync(c->freqtab.p, &ft, sizeof ft, hipMemcpyHostToDevice, c->stream));
+  return reset_slots(c, nrhs, nrhs);
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+void hz_default_opts(hz_solve_opts* o) {
+  if (!o) return;
+  o->krylov = HZ_BICGSTAB;
+  o->gmres_m = 30;
+  o->tol = 1e-8;
+  o->maxit = 10000;
+  o->precond = HZ_PRECOND_MG;
+  o->beta1 = 1.0;
+  o->beta2 = 0.5;
+  o->levels = 0;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->jacobi_w = 0.8;
+  o->jacobi_w_level = nullptr;
+}
+
+int hz_create(hz_ctx** out, const hz_ctx_opts* o) {
+  if (!out || !o) return HZ_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || o->device < 0 || o->device >= ndev) return HZ_ERR_ARG;
+  hz_ctx* c = new hz_ctx();
+  c->device = o->device;
+  c->stream = static_cast<hipStream_t>(o->hip_stream);
+  c->budget = o->workspace_budget_bytes;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    delete c;
+    return HZ_ERR_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+    delete c;
+    return HZ_ERR_DEVICE;
+  }
+  c->max_lds = prop.sharedMemPerBlock;
+  int wkhz = 0;
+  if (hipDeviceGetAttribute(&wkhz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess) c->wall_khz = wkhz;
+  void* ring = nullptr;
+  if (hipHostMalloc(&ring, kRing * sizeof(Summary), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    delete c;
+    return HZ_ERR_NOMEM;
+  }
+  c->ring_host = static_cast<Summary*>(ring);
+  memset(ring, 0, kRing * sizeof(Summary));
+  void* dptr = nullptr;
+  if (hipHostGetDevicePointer(&dptr, ring, 0) != hipSuccess) {
+    (void)hipHostFree(ring);
+    delete c;
+    return HZ_ERR_DEVICE;
+  }
+  c->ring_dev = static_cast<Summary*>(dptr);
+  for (int k = 0; k < kRing; ++k) {
+    if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) {
+      hz_destroy(c);
+      return HZ_ERR_DEVICE;
+    }
+  }
+  *out = c;
+  return HZ_OK;
+}
+
+void hz_destroy(hz_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < kRing; ++k)
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+  fold_timing(c);
+  for (hipEvent_t e : c->tpool) (void)hipEventDestroy(e);
+  if (c->ring_host) (void)hipHostFree(c->ring_host);
+  delete c;
+}
+
+int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_dev) {
+  if (!c) return HZ_ERR_ARG;
+  if (!m_dev) return fail(c, HZ_ERR_ARG, "m_dev is NULL");
+  if (dim != 1 && dim != 2) return fail(c, HZ_ERR_ARG, "dim must be 1 or 2");
+  if (dim == 1 && (nz != 1 || nx < 3)) return fail(c, HZ_ERR_ARG, "1D needs nz = 1 and nx >= 3");
+  if (dim == 2 && (nz < 3 || nx < 3)) return fail(c, HZ_ERR_ARG, "2D needs nz, nx >= 3");
+  if ((size_t)nz * nx > (size_t)1 << 30) return fail(c, HZ_ERR_ARG, "grid too large");
+  if (!(h > 0.0) || !isfinite(h)) return fail(c, HZ_ERR_ARG, "h must be positive");
+  HZ_HIP(c, hipSetDevice(c->device));
+  const size_t n = (size_t)nz * nx;
+  HZ_ALLOC(c, c->lv[0].m, n * sizeof(double));
+  HZ_HIP(c, hipMemcpyAsync(c->lv[0].m.p, m_dev, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  DevBuf chk;
+  HZ_ALLOC(c, chk, 4 * sizeof(double));
+  HZ_HIP(c, launch_check_model(n, c->lv[0].m.as<double>(), chk.as<double>(), c->stream));
+  double out3[3];
+  HZ_HIP(c, hipMemcpyAsync(out3, chk.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  if (out3[2] > 0.0) {
+    c->dim = 0;
+    return fail(c, HZ_ERR_ARG, "slowness has %.0f entries that are not finite and positive", out3[2]);
+  }
+  c->dim = dim;
+  c->nz = nz;
+  c->nx = nx;
+  c->h = h;
+  c->mmin = out3[0];
+  c->mmax = out3[1];
+  c->lv[0].nz = nz;
+  c->lv[0].nx = nx;
+  c->lv[0].h = h;
+  int L = 1;
+  while (L < kMaxLevels) {
+    const LevelInfo& f = c->lv[L - 1];
+    const bool okx = (f.nx - 1) % 2 == 0 && (f.nx - 1) / 2 + 1 >= 3;
+    const bool okz = dim == 1 || ((f.nz - 1) % 2 == 0 && (f.nz - 1) / 2 + 1 >= 3);
+    if (!okx || !okz) break;
+    LevelInfo& cl = c->lv[L];
+    cl.nx = (f.nx - 1) / 2 + 1;
+    cl.nz = dim == 1 ? 1 : (f.nz - 1) / 2 + 1;
+    cl.h = 2.0 * f.h;
+    HZ_ALLOC(c, cl.m, cl.n() * sizeof(double));
+    HZ_HIP(c, launch_inject(grid_of(c, L - 1), dim, cl.m.as<double>(), c->stream));
+    ++L;
+  }
+  c->maxlev = L;
+  c->model_version += 1;
+  c->cinv_key.clear();
+  c->cinv_base = nullptr;
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+int hz_point_rhs(hz_ctx* c, int nsrc, const int* iz, const int* ix, const hz_c128* amp,
+                 hz_c128* b_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (nsrc < 1 || !iz || !ix || !b_dev) return fail(c, HZ_ERR_ARG, "bad point-source arguments");
+  std::vector<int> nodes(nsrc);
+  for (int s = 0; s < nsrc; ++s) {
+    if (iz[s] < 0 || iz[s] >= c->nz || ix[s] < 0 || ix[s] >= c->nx)
+      return fail(c, HZ_ERR_ARG, "source %d at (%d, %d) is outside the grid", s, iz[s], ix[s]);
+    nodes[s] = iz[s] * c->nx + ix[s];
+  }
+  HZ_HIP(c, hipSetDevice(c->device));
+  HZ_ALLOC(c, c->scratch_int, (size_t)nsrc * sizeof(int));
+  HZ_HIP(c, hipMemcpyAsync(c->scratch_int.p, nodes.data(), nsrc * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  const double2* ampd = nullptr;
+  if (amp) {
+    HZ_ALLOC(c, c->scratch_c, (size_t)nsrc * sizeof(double2));
+    HZ_HIP(c, hipMemcpyAsync(c->scratch_c.p, amp, nsrc * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    ampd = c->scratch_c.as<double2>();
+  }
+  const double scale = c->dim == 2 ? 1.0 / (c->h * c->h) : 1.0 / c->h;
+  HZ_HIP(c, launch_point_rhs(c->lv[0].n(), nsrc, c->scratch_int.as<int>(), ampd, scale,
+                             reinterpret_cast<double2*>(b_dev), c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+int hz_plan(const hz_ctx* c, const hz_solve_opts* o, double freq_hz, int* levels, double* w) {
+  if (!c || !levels || !w) return HZ_ERR_ARG;
+  if (c->dim == 0) return HZ_ERR_STATE;
+  hz_solve_opts d;
+  if (!o) {
+    hz_default_opts(&d);
+    o = &d;
+  }
+  if (!(freq_hz > 0.0)) return HZ_ERR_ARG;
+  for (int l = 0; l < HZ_MAX_LEVELS; ++l) w[l] = 0.0;
+  return make_plan(c, o, 2.0 * M_PI * freq_hz, levels, w);
+}
+
+int hz_plan_grid(int dim, int nz, int nx, double h, double m_min, double m_max,
+                 const hz_solve_opts* o, double freq_hz, int* levels, double* w) {
+  if (!levels || !w) return HZ_ERR_ARG;
+  if ((dim != 1 && dim != 2) || nx < 3 || (dim == 1 ? nz != 1 : nz < 3)) return HZ_ERR_ARG;
+  if (!(h > 0.0) || !(m_min > 0.0) || !(m_max >= m_min) || !(freq_hz > 0.0)) return HZ_ERR_ARG;
+  hz_solve_opts d;
+  if (!o) {
+    hz_default_opts(&d);
+    o = &d;
+  }
+  for (int l = 0; l < HZ_MAX_LEVELS; ++l) w[l] = 0.0;
+  return plan_grid(dim, grid_max_levels(dim, nz, nx), h, m_min, m_max, o, 2.0 * M_PI * freq_hz, levels, w);
+}
+
+int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+             int nrhs, const hz_c128* b_dev, hz_c128* u_dev, hz_rhs_info* info) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  hz_solve_opts d;
+  if (!o) {
+    hz_default_opts(&d);
+    o = &d;
+  }
+  if (nfreq < 1 || nrhs < 1 || !freq_hz || !b_dev || !u_dev)
+    return fail(c, HZ_ERR_ARG, "bad solve arguments");
+  if (!(alpha >= 0.0) || !isfinite(alpha)) return fail(c, HZ_ERR_ARG, "alpha must be >= 0");
+  for (int f = 0; f < nfreq; ++f)
+    if (!(freq_hz[f] > 0.0) || !isfinite(freq_hz[f])) return fail(c, HZ_ERR_ARG, "frequency %d must be positive", f);
+  if ((rc = check_opts(c, o)) != HZ_OK) return rc;
+  if ((long long)nfreq * nrhs > (1 << 20)) return fail(c, HZ_ERR_ARG, "too many right-hand sides");
+  const int nslots = nfreq * nrhs;
+  const size_t n0 = c->lv[0].n();
+  {
+    const char* bb = reinterpret_cast<const char*>(b_dev);
+    const char* uu = reinterpret_cast<const char*>(u_dev);
+    const size_t bytes = (size_t)nslots * n0 * sizeof(double2);
+    if (bb < uu + bytes && uu < bb + bytes) return fail(c, HZ_ERR_ARG, "b_dev and u_dev overlap");
+  }
+  HZ_HIP(c, hipSetDevice(c->device));
+  int levels = 1;
+  std::vector<std::vector<double>> wj(nfreq, std::vector<double>(kMaxLevels, 0.0));
+  if (o->precond == HZ_PRECOND_MG) {
+    for (int f = 0; f < nfreq; ++f) {
+      int L = 0;
+      if ((rc = make_plan(c, o, 2.0 * M_PI * freq_hz[f], &L, wj[f].data())) != HZ_OK)
+        return fail(c, rc, "cannot plan the V-cycle");
+      levels = L;
+    }
+  }
+  if ((rc = ensure_workspace(c, nslots, levels)) != HZ_OK) return rc;
+  if ((rc = setup_freqs(c, o, nfreq, freq_hz, alpha, levels, wj)) != HZ_OK) return rc;
+  if ((rc = reset_slots(c, nslots, nrhs)) != HZ_OK) return rc;
+  const Cycle cy{levels, o->nu1, o->nu2, o->precond};
+  const double2* b = reinterpret_cast<const double2*>(b_dev);
+  double2* x = reinterpret_cast<double2*>(u_dev);
+  if (o->krylov == HZ_BICGSTAB) {
+    rc = run_bicgstab(c, o, cy, nslots, b, x);
+  } else {
+    rc = run_gmres(c, o, cy, nslots, b, x);
+  }
+  if (rc) return rc;
+  int any_fail = 0;
+  if ((rc = collect_info(c, nslots, b, x, info, &any_fail)) != HZ_OK) return rc;
+  return any_fail ? HZ_WARN_NOCONV : HZ_OK;
+}
+
+int hz_misfit(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+              int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
+              const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda,
+              double* J, hz_c128* d_cal_dev, hz_rhs_info* info) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
+      !d_obs_dev || !J)
+    return fail(c, HZ_ERR_ARG, "bad misfit arguments");
+  if (!(lambda >= 0.0) || !isfinite(lambda)) return fail(c, HZ_ERR_ARG, "lambda must be >= 0");
+  std::vector<int> rnodes(nrec);
+  for (int r = 0; r < nrec; ++r) {
+    if (rec_iz[r] < 0 || rec_iz[r] >= c->nz || rec_ix[r] < 0 || rec_ix[r] >= c->nx)
+      return fail(c, HZ_ERR_ARG, "receiver %d is outside the grid", r);
+    rnodes[r] = rec_iz[r] * c->nx + rec_ix[r];
+  }
+  HZ_HIP(c, hipSetDevice(c->device));
+  const size_t n0 = c->lv[0].n();
+  const size_t nb = (size_t)nfreq * nsrc * n0;
+  HZ_ALLOC(c, c->misfit_b, nb * sizeof(double2));
+  HZ_ALLOC(c, c->misfit_u, nb * sizeof(double2));
+  for (int f = 0; f < nfreq; ++f) {
+    rc = hz_point_rhs(c, nsrc, src_iz, src_ix, src_amp,
+                      reinterpret_cast<hz_c128*>(c->misfit_b.as<double2>() + (size_t)f * nsrc * n0));
+    if (rc) return rc;
+  }
+  rc = hz_solve(c, o, nfreq, freq_hz, alpha, nsrc, reinterpret_cast<const hz_c128*>(c->misfit_b.p),
+                reinterpret_cast<hz_c128*>(c->misfit_u.p), info);
+  if (rc < 0) return rc;
+  const int solve_rc = rc;
+  const size_t nd = (size_t)nfreq * nsrc * nrec;
+  double2* dcal = reinterpret_cast<double2*>(d_cal_dev);
+  if (!dcal) {
+    HZ_ALLOC(c, c->misfit_d, nd * sizeof(double2));
+    dcal = c->misfit_d.as<double2>();
+  }
+  HZ_ALLOC(c, c->scratch_int, (size_t)nrec * sizeof(int));
+  HZ_HIP(c, hipMemcpyAsync(c->scratch_int.p, rnodes.data(), nrec * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, launch_gather(nfreq * nsrc, nrec, c->scratch_int.as<int>(), c->misfit_u.as<double2>(), n0, dcal, c->stream));
+  HZ_ALLOC(c, c->misfit_out, 4 * sizeof(double));
+  HZ_HIP(c, launch_misfit(nd, reinterpret_cast<const double2*>(d_obs_dev), dcal, n0,
+                          c->lv[0].m.as<double>(), lambda, c->misfit_out.as<double>(), c->stream));
+  double out[3];
+  HZ_HIP(c, hipMemcpyAsync(out, c->misfit_out.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  *J = out[0];
+  return solve_rc;
+}
+
+int hz_apply(hz_ctx* c, int op, int level, double freq_hz, double alpha, double beta1, double beta2,
+             int nrhs, const hz_c128* x_dev, hz_c128* y_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (op != 0 && op != 1) return fail(c, HZ_ERR_ARG, "op must be 0 (B) or 1 (M)");
+  if (level < 0 || level >= c->maxlev) return fail(c, HZ_ERR_SHAPE, "level %d does not exist", level);
+  if (!x_dev || !y_dev) return fail(c, HZ_ERR_ARG, "null vector");
+  HZ_HIP(c, hipSetDevice(c->device));
+  if ((rc = setup_debug_batch(c, nrhs, freq_hz, alpha, beta1, beta2, nullptr, 0)) != HZ_OK) return rc;
+  HZ_HIP(c, launch_apply(c->dim, grid_of(c, level), level, op, batch_of(c), nrhs,
+                         reinterpret_cast<const double2*>(x_dev), reinterpret_cast<double2*>(y_dev),
+                         c->lv[level].n(), c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+int hz_smooth(hz_ctx* c, int level, double freq_hz, double beta1, double beta2, double w, int nrhs,
+              const hz_c128* b_dev, const hz_c128* u_in_dev, hz_c128* u_out_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (level < 0 || level >= c->maxlev) return fail(c, HZ_ERR_SHAPE, "level %d does not exist", level);
+  if (!b_dev || !u_out_dev || u_in_dev == u_out_dev) return fail(c, HZ_ERR_ARG, "bad vectors");
+  if (!(w > 0.0)) return fail(c, HZ_ERR_ARG, "w must be positive");
+  HZ_HIP(c, hipSetDevice(c->device));
+  if ((rc = setup_debug_batch(c, nrhs, freq_hz, 0.0, beta1, beta2, nullptr, 0)) != HZ_OK) return rc;
+  HZ_HIP(c, launch_smooth(c->dim, grid_of(c, level), level, w, batch_of(c), nrhs,
+                          reinterpret_cast<const double2*>(b_dev), reinterpret_cast<const double2*>(u_in_dev),
+                          reinterpret_cast<double2*>(u_out_dev), c->lv[level].n(), c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+int hz_restrict(hz_ctx* c, int level, double freq_hz, double beta1, double beta2, int nrhs,
+                const hz_c128* b_dev, const hz_c128* u_dev, hz_c128* bc_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (level < 0 || level + 1 >= c->maxlev) return fail(c, HZ_ERR_SHAPE, "level %d has no coarser level", level);
+  if (!b_dev || !u_dev || !bc_dev) return fail(c, HZ_ERR_ARG, "null vector");
+  HZ_HIP(c, hipSetDevice(c->device));
+  if ((rc = setup_debug_batch(c, nrhs, freq_hz, 0.0, beta1, beta2, nullptr, 0)) != HZ_OK) return rc;
+  HZ_HIP(c, launch_restrict(c->dim, grid_of(c, level), grid_of(c, level + 1), batch_of(c), nrhs,
+                            reinterpret_cast<const double2*>(b_dev), reinterpret_cast<const double2*>(u_dev),
+                            reinterpret_cast<double2*>(bc_dev), c->lv[level].n(), c->lv[level + 1].n(),
+                            c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+int hz_prolong(hz_ctx* c, int level, int nrhs, const hz_c128* e_dev, hz_c128* u_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (level < 0 || level + 1 >= c->maxlev) return fail(c, HZ_ERR_SHAPE, "level %d has no coarser level", level);
+  if (!e_dev || !u_dev) return fail(c, HZ_ERR_ARG, "null vector");
+  HZ_HIP(c, hipSetDevice(c->device));
+  if ((rc = setup_debug_batch(c, nrhs, 1.0, 0.0, 1.0, 0.5, nullptr, 0)) != HZ_OK) return rc;
+  double2* u = reinterpret_cast<double2*>(u_dev);
+  HZ_HIP(c, launch_prolong(c->dim, grid_of(c, level), grid_of(c, level + 1), batch_of(c), nrhs,
+                           reinterpret_cast<const double2*>(e_dev), u, u, c->lv[level].n(),
+                           c->lv[level + 1].n(), c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+int hz_precond(hz_ctx* c, const hz_solve_opts* o, double freq_hz, int nrhs, const hz_c128* b_dev,
+               hz_c128* u_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  hz_solve_opts d;
+  if (!o) {
+    hz_default_opts(&d);
+    o = &d;
+  }
+  if (!b_dev || !u_dev || nrhs < 1) return fail(c, HZ_ERR_ARG, "bad vectors");
+  if (!(freq_hz > 0.0) || !isfinite(freq_hz)) return fail(c, HZ_ERR_ARG, "frequency must be positive");
+  if ((rc = check_opts(c, o)) != HZ_OK) return rc;
+  HZ_HIP(c, hipSetDevice(c->device));
+  int levels = 1;
+  std::vector<std::vector<double>> wj(1, std::vector<double>(kMaxLevels, 0.0));
+  if (o->precond == HZ_PRECOND_MG) {
+    if ((rc = make_plan(c, o, 2.0 * M_PI * freq_hz, &levels, wj[0].data())) != HZ_OK)
+      return fail(c, rc, "cannot plan the V-cycle");
+  }
+  if ((rc = ensure_workspace(c, nrhs, levels)) != HZ_OK) return rc;
+  if ((rc = setup_freqs(c, o, 1, &freq_hz, 0.0, levels, wj)) != HZ_OK) return rc;
+  if ((rc = reset_slots(c, nrhs, nrhs)) != HZ_OK) return rc;
+  const Cycle cy{levels, o->nu1, o->nu2, o->precond};
+  HZ_HIP(c, precond_apply(c, cy, nrhs, reinterpret_cast<const double2*>(b_dev), reinterpret_cast<double2*>(u_dev)));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  return HZ_OK;
+}
+
+int hz_timing_start(hz_ctx* c, int kernel) {
+  if (!c) return HZ_ERR_ARG;
+  if (kernel < -1 || kernel > HZ_KERNEL_COARSE) return fail(c, HZ_ERR_ARG, "unknown kernel class %d", kernel);
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  fold_timing(c);
+  c->timing_cls = kernel;
+  c->t_launches = 0;
+  c->t_ms = 0.0;
+  return HZ_OK;
+}
+
+int hz_timing_read(hz_ctx* c, int* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return HZ_ERR_ARG;
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  fold_timing(c);
+  *launches = (int)c->t_launches;
+  *total_ms = c->t_ms;
+  return HZ_OK;
+}
+
+const char* hz_status_str(int status) {
+  switch (status) {
+    case HZ_OK: return "ok";
+    case HZ_WARN_NOCONV: return "some right-hand side did not converge";
+    case HZ_ERR_ARG: return "invalid argument";
+    case HZ_ERR_SHAPE: return "grid cannot be coarsened as requested";
+    case HZ_ERR_NOMEM: return "out of device memory or workspace budget";
+    case HZ_ERR_DEVICE: return "HIP runtime error";
+    case HZ_ERR_STATE: return "no model set";
+    default: return "unknown status";
+  }
+}
+
+const char* hz_last_error(const hz_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

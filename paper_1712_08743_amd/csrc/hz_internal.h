@@ -1,0 +1,186 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code.
+// Everything here is complex128 (double2 = interleaved re, im) and FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hz {
+
+constexpr int kMaxLevels = 12;
+constexpr int kBlock = 256;        // threads per block of the grid kernels
+constexpr int kVecPerThread = 4;   // nodes per thread in the pointwise Krylov kernels
+constexpr int kCoarseRows = 128;   // rows of the coarse inverse per block
+constexpr int kCoarseGroup = 8;    // right-hand sides per block of the coarse solve
+constexpr int kPcrMax = 2048;      // longest 1D grid for the exact tridiagonal solve
+constexpr int kCoarseMax = 16384;  // most unknowns on the coarsest level (dense inverse)
+
+// Per right-hand-side solver status. Finished states equal the HZ_RHS_* codes.
+enum : int {
+  kActive = -1,
+  kConverged = 0,
+  kMaxit = 1,
+  kBreakdown = 2,
+  kNonfinite = 3,
+  kRestart = 4,  // breakdown seen; waits for the one restart with rhat = r
+};
+
+// One multigrid level's grid: node counts, spacing and injected slowness.
+struct Grid {
+  int nz, nx;
+  double h;
+  const double* m;  // device, [nz][nx]
+};
+
+// Per-frequency constants (device table).
+struct FreqTab {
+  double omega;
+  double sB_re, sB_im;  // mass shift of B: 1 - j alpha
+  double sM_re, sM_im;  // mass shift of M: beta1 - j beta2
+  double wj[kMaxLevels];
+  const double2* cinv;  // inverse of M on the coarsest level, [nc][nc]
+};
+
+// Per right-hand-side Krylov scalars (device array, one per slot).
+struct Slot {
+  double2 rho, alpha, omega, beta;
+  double bnorm2, rnorm2;
+  int iters, status, restarted, freq;
+  unsigned long long t0, t1;  // device wall clock at the start and at the last iteration
+  int phase;                  // GMRES: 0 = Arnoldi steps, 1 = cycle end pending
+  int cyc_k;                  // GMRES: Arnoldi steps taken in the current cycle
+  double2 scal;               // GMRES: divisor of the newest basis vector (real part)
+};
+
+// GMRES(m) per-slot small arrays (device): Hessenberg matrix column-major
+// H[slot][j*(m+1) + i], right-hand side g, rotations (cs, sn), solution y and the
+// two Gram-Schmidt coefficient vectors of the current column.
+struct Gmres {
+  double2* H;
+  double2* g;
+  double* cs;
+  double2* sn;
+  double2* y;
+  double2* hc;       // [slots][2][m+1]
+  double* partials;  // [slots][max_tiles][2 (m+1)]
+  int m;
+  int max_tiles;
+};
+
+// The batch every kernel works on: the compacted list of active slots.
+struct Batch {
+  const int* active;   // [capacity] slot ids, valid up to *nactive
+  const int* nactive;  // device count
+  Slot* slots;
+  const FreqTab* ft;
+};
+
+// Scratch for deterministic per-slot reductions.
+struct Reduce {
+  double* partials;     // [slots][max_tiles][4]
+  unsigned* counters;   // [slots], zero between kernels
+  int max_tiles;
+};
+
+// Summary the host polls: counts of active and restart-pending slots.
+struct Summary {
+  int nactive, nrestart, nother, pad1;  // nother: active slots in the other GMRES phase
+};
+
+struct Tiles {
+  int tx, tz;     // block shape (tx * tz == kBlock)
+  int ntx, ntz;   // tiles per axis
+  int per_slot;   // ntx * ntz
+};
+
+Tiles grid_tiles(int nz, int nx, int dim);
+int vec_tiles(size_t n);
+
+// ---- kernel launchers (hz_kernels.hip) ----------------------------------------
+// All take the stream last and return the launch status.
+// `which` selects the mass shift: 0 = B (1 - j alpha), 1 = M (beta1 - j beta2).
+
+hipError_t launch_apply(int dim, const Grid& g, int lvl, int which, const Batch& bt, int cap,
+                        const double2* x, double2* y, size_t stride, hipStream_t st);
+hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, const Batch& bt,
+                         int cap, const double2* b, const double2* u_in, double2* u_out,
+                         size_t stride, hipStream_t st);
+hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
+                           const double2* b, const double2* u, double2* bc, size_t sf,
+                           size_t sc, hipStream_t st);
+hipError_t launch_prolong(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
+                          const double2* e, const double2* u_in, double2* u_out, size_t sf,
+                          size_t sc, hipStream_t st);
+hipError_t launch_coarse_solve(int nc, const Batch& bt, int cap, const double2* bc, double2* uc,
+                               size_t stride, hipStream_t st);
+hipError_t launch_pcr(const Grid& g, const Batch& bt, int cap, const double2* b, double2* u,
+                      size_t stride, hipStream_t st);
+hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,
+                       size_t stride, hipStream_t st);
+
+// Gauss-Jordan inversion of the coarsest M for nfreq frequencies.
+hipError_t launch_assemble_dense(int dim, const Grid& g, int nfreq, const FreqTab* ft,
+                                 double2* A, hipStream_t st);
+hipError_t launch_gj_step(int nc, int nfreq, int k, const double2* A_in, double2* A_out,
+                          hipStream_t st);
+
+// BiCGSTAB pieces
+hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd,
+                            const double2* b, double2* x, double2* r, double2* rh, double2* p,
+                            double2* v, size_t stride, hipStream_t st);
+hipError_t launch_bicg_p(size_t n, const Batch& bt, int cap, const double2* r, double2* p,
+                         const double2* v, size_t stride, hipStream_t st);
+hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int cap,
+                                   const Reduce& rd, const double2* ph, const double2* rh,
+                                   double2* v, size_t stride, hipStream_t st);
+hipError_t launch_bicg_s(size_t n, const Batch& bt, int cap, const double2* r, const double2* v,
+                         double2* s, size_t stride, hipStream_t st);
+hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int cap,
+                                   const Reduce& rd, const double2* sh, const double2* s,
+                                   double2* t, size_t stride, hipStream_t st);
+hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, double tol,
+                          int maxit, double2* x, const double2* ph, const double2* sh,
+                          const double2* s, const double2* t, double2* r, const double2* rh,
+                          size_t stride, hipStream_t st);
+hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
+                               const double2* r, double2* rh, double2* p, double2* v,
+                               size_t stride, hipStream_t st);
+hipError_t launch_compact(int nslots, Slot* slots, int* active, int* nactive, Summary* sum,
+                          int want_phase, hipStream_t st);
+
+// GMRES pieces
+hipError_t launch_gm_residual(int dim, const Grid& g, const Batch& bt, int cap, const Reduce& rd,
+                              const Gmres& gm, int first, double tol, int maxit, const double2* b,
+                              const double2* x, double2* v0, size_t stride, hipStream_t st);
+hipError_t launch_gm_scale(size_t n, const Batch& bt, int cap, double2* v, size_t stride,
+                           hipStream_t st);
+hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm,
+                          int j, int pass, const double2* V, size_t vstride, const double2* w,
+                          size_t stride, hipStream_t st);
+hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm,
+                          int j, int pass, double tol, int maxit, const double2* V,
+                          size_t vstride, double2* w, size_t stride, hipStream_t st);
+hipError_t launch_gm_solve(const Batch& bt, int cap, const Gmres& gm, hipStream_t st);
+hipError_t launch_gm_combine(size_t n, const Batch& bt, int cap, const Gmres& gm,
+                             const double2* V, size_t vstride, double2* t, size_t stride,
+                             hipStream_t st);
+hipError_t launch_axpy1(size_t n, const Batch& bt, int cap, const double2* z, double2* x,
+                        size_t stride, hipStream_t st);
+
+// true residual norms ||b - B x||^2 and ||b||^2 per slot into out[slot*2 + {0,1}]
+hipError_t launch_true_residual(int dim, const Grid& g, const Batch& bt, int cap,
+                                const Reduce& rd, const double2* b, const double2* x,
+                                double* out, size_t stride, hipStream_t st);
+
+// misfit helpers
+hipError_t launch_point_rhs(size_t n, int nsrc, const int* nodes, const double2* amp,
+                            double scale, double2* b, hipStream_t st);
+hipError_t launch_gather(int nrhs, int nrec, const int* rec_nodes, const double2* u,
+                         size_t stride, double2* d, hipStream_t st);
+hipError_t launch_misfit(size_t nd, const double2* d_obs, const double2* d_cal, size_t nm,
+                         const double* m, double lambda, double* out, hipStream_t st);
+hipError_t launch_inject(const Grid& gf, int dim, double* mc, hipStream_t st);
+hipError_t launch_check_model(size_t n, const double* m, double* out3, hipStream_t st);
+
+}  // namespace hz

@@ -1,0 +1,82 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/hz.h declares, the binding resolves them all, and the host-only
+V-cycle plan agrees with the oracle's plan (no device work)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hz.h")
+LIB = os.path.join(ROOT, "paper_1712_08743_amd", "libhz.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const\s+char)\s*\*?\s*(hz_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for required in ("hz_create", "hz_destroy", "hz_set_model", "hz_point_rhs", "hz_solve",
+                     "hz_misfit", "hz_plan", "hz_apply", "hz_smooth", "hz_restrict", "hz_prolong",
+                     "hz_precond", "hz_status_str", "hz_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first (python -m paper_1712_08743_amd.build)"
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    import paper_1712_08743_amd as hz
+    assert set(hz.exported_symbols()) == set(declared_functions())
+
+
+def test_status_strings_and_defaults():
+    import paper_1712_08743_amd as hz
+    lib = ctypes.CDLL(LIB)
+    lib.hz_status_str.restype = ctypes.c_char_p
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert lib.hz_status_str(code)
+    o = hz.default_opts()
+    assert o.krylov == hz.HZ_BICGSTAB and o.tol == 1e-8 and o.nu1 == 2 and o.nu2 == 2
+    assert (o.beta1, o.beta2) == (1.0, 0.5) and o.jacobi_w == 0.8 and o.gmres_m == 30
+
+
+@pytest.mark.parametrize("shape,h,f,cmin,cmax", [
+    ((201, 201), 10.0, 5.0, 1200.0, 2800.0),
+    ((401, 801), 10.0, 3.0, 1275.0, 5175.0),
+    ((401, 801), 10.0, 5.0, 1275.0, 5175.0),
+    ((401, 801), 10.0, 8.0, 1275.0, 5175.0),
+    ((401, 801), 10.0, 12.0, 1275.0, 5175.0),
+    ((301, 601), 10.0, 10.0, 1500.0, 3500.0),
+    ((129, 129), 10.0, 15.0, 1500.0, 3000.0),
+    ((513, 513), 10.0, 2.0, 1500.0, 3000.0),
+    ((1001,), 5.0, 10.0, 1500.0, 3000.0),
+    ((257,), 20.0, 25.0, 1400.0, 3000.0),
+])
+def test_host_plan_matches_oracle_plan(shape, h, f, cmin, cmax):
+    import paper_1712_08743_amd as hz
+    from oracle import lfa
+    om = 2 * np.pi * f
+    for beta in ((1.0, 0.5), (1.0, 1.0)):
+        for wdef in (0.8, 0.6):
+            L0, w0 = lfa.plan(shape, h, om, 1 / cmax, 1 / cmin, beta[0], beta[1], w_default=wdef)
+            L1, w1 = hz.plan_grid(shape, h, 1 / cmax, 1 / cmin, f, beta=beta, jacobi_w=wdef)
+            assert L0 == L1 and np.allclose(w0, w1, rtol=0, atol=1e-15), (w0, w1)
+
+
+def test_host_plan_rejects_bad_input():
+    import paper_1712_08743_amd as hz
+    with pytest.raises(hz.HzError):
+        hz.plan_grid((201, 201), 10.0, 1e-3, 5e-4, 5.0)  # m_max < m_min
+    with pytest.raises(hz.HzError):
+        hz.plan_grid((201, 201), 10.0, 1 / 3000, 1 / 1500, 5.0, levels=9)

@@ -1,0 +1,266 @@
+"""GPU parity of the whole solve against the oracle: wavefields against the
+oracle's direct (LU) solution, iteration counts against the oracle's own
+preconditioned Krylov solve, the true residual recomputed by the oracle from
+the GPU's u, batch invariance, failure paths, the misfit of Eq. (4), and the
+full 401 x 801 x 256-right-hand-side configuration checked on sampled shots.
+
+Tolerances: the solver stops at relative residual tol; the wavefield error
+against LU must stay below 1e-6 (relative, 2-norm) at tol = 1e-8, and
+iteration counts may differ from the oracle's by max(2, 5 %) because the two
+sides round differently (fused multiply-adds, reduction order)."""
+
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle import multigrid as mg
+from oracle import krylov
+from oracle import direct
+from oracle import lfa
+from oracle import misfit as omisfit
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def iters_close(a, b):
+    return abs(a - b) <= max(2, int(0.05 * max(a, b)))
+
+
+def make_ctx(hz, m, h):
+    import torch
+    c = hz.Context(0)
+    c.set_model(torch.from_numpy(np.asarray(m)), h)
+    return c
+
+
+def test_c1_1d_three_layers_exact_preconditioner(hz):
+    import torch
+    w = workloads.model_1d_layers()
+    c = make_ctx(hz, w.m, w.h)
+    f = w.freqs[0]
+    om = 2 * np.pi * f
+    b = c.point_rhs([0], w.src)
+    u, info = c.solve([f], w.alpha, b[None], precond="exact", tol=w.tol)
+    st, it, rr = info[0]
+    assert st == hz.HZ_RHS_CONVERGED and rr <= w.tol
+    B = op.operator_B(w.m, w.h, om, w.alpha)
+    bn = op.point_source(w.shape, w.h, w.src)
+    assert np.array_equal(to_np(b)[0], bn)
+    ulu = direct.solve_superlu(B, bn)
+    ug = to_np(u)[0, 0]
+    assert rel(ug, ulu) < 1e-6
+    assert np.linalg.norm(bn - B @ ug) / np.linalg.norm(bn) <= 2 * w.tol
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 1)
+    _, it_o, _, st_o = krylov.bicgstab(B, bn, vc, tol=w.tol, maxit=1000)
+    assert st_o == krylov.CONVERGED and iters_close(it, it_o), (it, it_o)
+
+
+@pytest.mark.parametrize("sign", [-1.0, 1.0])
+@pytest.mark.parametrize("tol", [1e-8, 1e-12])
+def test_c2_lens_vcycle(hz, sign, tol):
+    w = workloads.model_2d_lens(sign=sign)
+    c = make_ctx(hz, w.m, w.h)
+    f = w.freqs[0]
+    om = 2 * np.pi * f
+    b = c.point_rhs([0], [w.src[0] % w.shape[1]])
+    u, info = c.solve([f], w.alpha, b[None], levels=4, nu=(2, 2), jacobi_w_level=[0.8] * 3, tol=tol)
+    st, it, rr = info[0]
+    assert st == hz.HZ_RHS_CONVERGED and rr <= tol
+    B = op.operator_B(w.m, w.h, om, w.alpha)
+    bn = op.point_source(w.shape, w.h, w.src)
+    ulu = direct.solve_superlu(B, bn)
+    ug = to_np(u)[0, 0].ravel()
+    err = rel(ug, ulu)
+    assert err < (1e-6 if tol == 1e-8 else 1e-9), err
+    assert np.linalg.norm(bn - B @ ug) / np.linalg.norm(bn) <= 2 * tol
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 4, 2, 2, [0.8] * 3)
+    _, it_o, _, _ = krylov.bicgstab(B, bn, vc, tol=tol, maxit=500)
+    assert iters_close(it, it_o), (it, it_o)
+
+
+def test_multi_frequency_multi_shot_batch(hz):
+    """Several frequencies and shots in one batch, planned weights, each
+    right-hand side against its own LU solution."""
+    import torch
+    w = workloads.model_2d_layered(nz=101, nx=201, h=20.0, nshots=5, freqs=(2.0, 4.0, 6.5))
+    c = make_ctx(hz, w.m, w.h)
+    ns = len(w.src)
+    b1 = c.point_rhs([0] * ns, w.src)
+    b = torch.stack([b1] * len(w.freqs))
+    u, info = c.solve(w.freqs, w.alpha, b, tol=1e-8)
+    u = to_np(u)
+    for fi, f in enumerate(w.freqs):
+        om = 2 * np.pi * f
+        B = op.operator_B(w.m, w.h, om, w.alpha)
+        lu = direct.factor_superlu(B)
+        L, wj = lfa.plan(w.shape, w.h, om, w.m.min(), w.m.max(), 1.0, 0.5)
+        vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj)
+        for s in range(ns):
+            st, it, rr = info[fi * ns + s]
+            assert st == hz.HZ_RHS_CONVERGED and rr <= 1e-8
+            bn = op.point_source(w.shape, w.h, [w.src[s]])
+            assert rel(u[fi, s].ravel(), lu.solve(bn)) < 1e-6
+            if s == 0:
+                _, it_o, _, _ = krylov.bicgstab(B, bn, vc, tol=1e-8, maxit=2000)
+                assert iters_close(it, it_o), (f, it, it_o)
+
+
+def test_batch_invariance_bitwise(hz):
+    """A right-hand side gives the same bits alone and inside a batch."""
+    import torch
+    w = workloads.model_2d_lens(n=129, h=15.0)
+    c = make_ctx(hz, w.m, w.h)
+    rng = np.random.default_rng(3)
+    xs = rng.integers(0, 129, size=6)
+    b = c.point_rhs([0] * 6, xs)
+    u_all, info_all = c.solve([4.0, 6.0], 0.01, torch.stack([b, b.flip(0)]))
+    u_one, info_one = c.solve([6.0], 0.01, b[2:3][None])
+    assert torch.equal(u_all[1, 3], u_one[0, 0])  # b.flip(0)[3] == b[2]
+    assert info_all[6 + 3][1] == info_one[0][1]
+    u_one4, _ = c.solve([4.0], 0.01, b[4:5][None])
+    assert torch.equal(u_all[0, 4], u_one4[0, 0])
+
+
+def test_unpreconditioned_path(hz):
+    """No preconditioner: a small, heavily damped problem still converges."""
+    w = workloads.model_2d_lens(n=33, h=60.0)
+    c = make_ctx(hz, w.m, w.h)
+    b = c.point_rhs([0], [16])
+    u, info = c.solve([2.0], 0.2, b[None], precond="none", tol=1e-10, maxit=5000)
+    assert info[0][0] == hz.HZ_RHS_CONVERGED
+    B = op.operator_B(w.m, w.h, 2 * np.pi * 2.0, 0.2)
+    assert rel(to_np(u)[0, 0].ravel(), direct.solve_superlu(B, op.point_source(w.shape, w.h, [16]))) < 1e-8
+
+
+def test_failure_paths(hz):
+    import torch
+    w = workloads.model_2d_lens(n=65, h=30.0)
+    c = make_ctx(hz, w.m, w.h)
+    b = c.point_rhs([0, 0, 0], [10, 20, 30])
+    b[1].zero_()
+    b[2, 5, 5] = complex(float("nan"), 0.0)
+    u, info = c.solve([5.0], 0.01, b[None], tol=1e-10)
+    assert info[0][0] == hz.HZ_RHS_CONVERGED
+    assert info[1] == (hz.HZ_RHS_CONVERGED, 0, 0.0)
+    assert not torch.any(u[0, 1] != 0)
+    assert info[2][0] == hz.HZ_RHS_NONFINITE
+    # iteration cap
+    u, info = c.solve([5.0], 0.01, b[:1][None], tol=1e-14, maxit=1)
+    assert info[0][0] == hz.HZ_RHS_MAXIT and info[0][1] == 1
+    # argument errors
+    with pytest.raises(hz.HzError) as e:
+        c.solve([-1.0], 0.01, b[:1][None])
+    assert e.value.code == hz.HZ_ERR_ARG
+    with pytest.raises(hz.HzError) as e:
+        c.solve([5.0], 0.01, b[:1][None], levels=12)
+    assert e.value.code == hz.HZ_ERR_SHAPE
+    with pytest.raises(hz.HzError) as e:
+        c.solve([5.0], 0.01, b[:1][None], beta=(1.0, 0.0))
+    assert e.value.code == hz.HZ_ERR_ARG
+    with pytest.raises(hz.HzError) as e:
+        c.point_rhs([0], [65])
+    assert e.value.code == hz.HZ_ERR_ARG
+    bad = torch.from_numpy(w.m.copy())
+    bad[3, 3] = -1.0
+    with pytest.raises(hz.HzError) as e:
+        c.set_model(bad, w.h)
+    assert e.value.code == hz.HZ_ERR_ARG
+    with pytest.raises(hz.HzError) as e:
+        c.solve([5.0], 0.01, b[:1][None])
+    assert e.value.code == hz.HZ_ERR_STATE
+
+
+def test_misfit_matches_oracle(hz):
+    import torch
+    true = workloads.model_2d_layered(nz=65, nx=129, h=25.0, nshots=4, freqs=(2.0, 3.5))
+    start = workloads.model_2d_layered(nz=65, nx=129, h=25.0, nshots=4, freqs=(2.0, 3.5), seed=1)
+    src = [(0, s) for s in true.src]
+    rec = [(0, r) for r in range(0, 129, 8)]
+    rec_nodes = [r[1] for r in rec]
+    lam = 1e-3
+    d_obs = np.zeros((2, 4, len(rec)), dtype=complex)
+    d_cal = np.zeros_like(d_obs)
+    for fi, f in enumerate(true.freqs):
+        om = 2 * np.pi * f
+        lu_t = direct.factor_superlu(op.operator_B(true.m, true.h, om, true.alpha))
+        lu_s = direct.factor_superlu(op.operator_B(start.m, start.h, om, start.alpha))
+        for s, (iz, ix) in enumerate(src):
+            bn = op.point_source(true.shape, true.h, [ix])
+            d_obs[fi, s] = omisfit.sample(lu_t.solve(bn), rec_nodes)
+            d_cal[fi, s] = omisfit.sample(lu_s.solve(bn), rec_nodes)
+    J_o = omisfit.misfit(d_obs, d_cal, start.m, lam)
+    c = make_ctx(hz, start.m, start.h)
+    J, dc, info = c.misfit(true.freqs, true.alpha, src, rec, torch.from_numpy(d_obs), lam, tol=1e-10)
+    assert all(i[0] == hz.HZ_RHS_CONVERGED for i in info)
+    assert rel(to_np(dc), d_cal) < 1e-7
+    assert abs(J - J_o) <= 1e-7 * J_o
+
+
+def test_full_size_batched_configuration_sampled(hz):
+    """401 x 801 grid, 64 surface shots x {3, 5, 8, 12} Hz = 256 right-hand
+    sides in one batch (the benchmark's launch configuration); two shots per
+    frequency are checked against LU, and every right-hand side's true
+    residual against the tolerance."""
+    import torch
+    w = workloads.model_2d_layered()
+    c = make_ctx(hz, w.m, w.h)
+    ns = len(w.src)
+    b1 = c.point_rhs([0] * ns, w.src)
+    b = torch.stack([b1] * len(w.freqs))
+    u, info = c.solve(w.freqs, w.alpha, b, tol=1e-8)
+    assert all(i[0] == hz.HZ_RHS_CONVERGED and i[2] <= 1e-8 for i in info), info
+    for fi, f in enumerate(w.freqs):
+        om = 2 * np.pi * f
+        lu = direct.factor_superlu(op.operator_B(w.m, w.h, om, w.alpha))
+        for s in (0, 41):
+            bn = op.point_source(w.shape, w.h, [w.src[s]])
+            assert rel(to_np(u[fi, s]).ravel(), lu.solve(bn)) < 1e-6
+
+
+@pytest.mark.parametrize("m,tol", [(30, 1e-8), (5, 1e-10)])
+def test_gmres_matches_oracle(hz, m, tol):
+    """GMRES(m) (the paper's data-modelling engine) with the V-cycle: the
+    wavefield against LU and the inner-step count against the oracle's
+    GMRES(m) (modified vs classical-twice Gram-Schmidt: same mathematics)."""
+    w = workloads.model_2d_lens(sign=-1.0)
+    c = make_ctx(hz, w.m, w.h)
+    f = w.freqs[0]
+    om = 2 * np.pi * f
+    b = c.point_rhs([0, 0], [100, 37])
+    u, info = c.solve([f], w.alpha, b[None], krylov="gmres", gmres_m=m, levels=4, nu=(2, 2),
+                      jacobi_w_level=[0.8] * 3, tol=tol, maxit=3000)
+    B = op.operator_B(w.m, w.h, om, w.alpha)
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 4, 2, 2, [0.8] * 3)
+    for s, ix in enumerate((100, 37)):
+        st, it, rr = info[s]
+        assert st == hz.HZ_RHS_CONVERGED and rr <= tol
+        bn = op.point_source(w.shape, w.h, [ix])
+        ulu = direct.solve_superlu(B, bn)
+        assert rel(to_np(u)[0, s].ravel(), ulu) < 1e-6
+        _, it_o, _, st_o = krylov.gmres(B, bn, vc, m=m, tol=tol, maxit=3000)
+        assert st_o == krylov.CONVERGED and iters_close(it, it_o), (it, it_o)
+
+
+def test_gmres_unpreconditioned_and_maxit(hz):
+    w = workloads.model_2d_lens(n=33, h=60.0)
+    c = make_ctx(hz, w.m, w.h)
+    b = c.point_rhs([0], [16])
+    u, info = c.solve([2.0], 0.2, b[None], krylov="gmres", gmres_m=40, precond="none", tol=1e-10,
+                      maxit=4000)
+    assert info[0][0] == hz.HZ_RHS_CONVERGED
+    B = op.operator_B(w.m, w.h, 2 * np.pi * 2.0, 0.2)
+    bn = op.point_source(w.shape, w.h, [16])
+    assert rel(to_np(u)[0, 0].ravel(), direct.solve_superlu(B, bn)) < 1e-8
+    _, it_o, _, _ = krylov.gmres(B, bn, None, m=40, tol=1e-10, maxit=4000)
+    assert iters_close(info[0][1], it_o), (info[0][1], it_o)
+    u, info = c.solve([2.0], 0.2, b[None], krylov="gmres", gmres_m=10, tol=1e-14, maxit=7)
+    assert info[0][0] == hz.HZ_RHS_MAXIT and info[0][1] == 7
