@@ -33,7 +33,7 @@ METRIC = "Helmholtz solves/s (2D 401x801, 64 RHS), HBM GB/s, p50/p99 solve laten
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("hz_kernels.hip", "hz_internal.h"):
+    for f in ("hz_kernels.hip", "hz_krylov.hip", "hz_device.h", "hz_internal.h"):
         with open(os.path.join(ROOT, "paper_1712_08743_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -47,27 +47,41 @@ def level_sizes(shape, levels):
     return sizes
 
 
-def bytes_per_iteration(sizes, nu1=2, nu2=2):
-    """Algorithmic HBM bytes of one BiCGSTAB iteration of one right-hand side:
-    each complex vector read or written once per kernel (16 B per node), the
-    shared slowness not counted. Two V-cycles per iteration."""
+def bytes_per_iteration(sizes):
+    """Algorithmic HBM bytes of one BiCGSTAB iteration of one right-hand side
+    with two V(2,2) cycles, as the kernels run it: each complex vector a
+    kernel touches is read or written once (16 B per node), the shared
+    slowness not counted, the dense coarse inverse read once per cycle."""
     z = 16
     n0 = sizes[0]
-    krylov = n0 * z * (4 + 3 + 3 + 3 + 8)  # p update, B p^, s update, B s^, x/r update
-    vc = 0
+    total = n0 * z * (5 + 4)        # fused p and s updates with their two sweeps
+    total += n0 * z * (3 + 3 + 8)   # B p^, B s^ (with dots), x/r update
     for l, n in enumerate(sizes[:-1]):
         nc = sizes[l + 1]
-        sm = n * z * (2 + 3 * (nu1 - 1) + 3 * nu2)  # first sweep from zero, the rest
-        rs = n * z * 2 + nc * z                     # residual + restriction
-        pr = n * z * 2 + nc * z                     # prolongation + correction
-        vc += sm + rs + pr
+        per_cycle = n * z * 2 + nc * z          # residual + restriction
+        per_cycle += n * z * 3 + nc * z         # prolongation + first post-sweep
+        per_cycle += n * z * 3                  # second post-sweep
+        if l > 0:
+            per_cycle += n * z * 2              # two pre-sweeps from zero (given b)
+        total += 2 * per_cycle
     nc = sizes[-1]
-    vc += 2 * nc * z + nc * nc * z  # coarse solve (dense inverse read once per cycle)
-    return krylov + 2 * vc
+    total += 2 * (2 * nc * z + nc * nc * z)
+    return total
 
 
-def smooth_bytes_per_launch_per_rhs(n0):
-    return 48 * n0  # reads b and u_in, writes u_out
+# Per fine-level kernel class: algorithmic bytes per right-hand side per
+# BiCGSTAB iteration (two launches of each V-cycle kernel per iteration).
+def class_bytes_per_iteration(sizes):
+    z = 16
+    n0, n1 = sizes[0], sizes[1]
+    return {
+        "presmooth": n0 * z * (5 + 4),          # reads r, p_old, v / r, v; writes p / s and u2
+        "restrict": 2 * (n0 * z * 2 + n1 * z),  # reads b, u; writes the coarse rhs
+        "prolong": 2 * (n0 * z * 3 + n1 * z),   # reads u2, b, coarse e; writes u
+        "smooth": 2 * n0 * z * 3,               # reads b, u; writes u
+        "apply": 2 * n0 * z * 3,                # reads x, shadow/s; writes B x
+        "update": n0 * z * 8,                   # reads x, p^, s^, s, t, r^; writes x, r
+    }
 
 
 def percentile(vals, q):
@@ -140,7 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--kernel", default="smooth", help="kernel class timed with HIP events")
+    ap.add_argument("--maxit", type=int, default=10000,
+                    help="iteration cap (below convergence only for short hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the batched solve of one GPU's share); "
@@ -168,14 +183,15 @@ def main():
 
     def step():
         ctx.set_model(m, w.h)
-        _, info = ctx.solve(w.freqs, w.alpha, b, out=u, tol=tol)
+        _, info = ctx.solve(w.freqs, w.alpha, b, out=u, tol=tol, maxit=args.maxit)
         return info
 
     print(f"# warmup {args.warmup} step(s) on {w.name}, {nrhs} right-hand sides", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.timing_start(args.kernel)
+    classes = ["presmooth", "restrict", "prolong", "smooth", "apply", "update", "coarse"]
+    ctx.timing_start(classes)
     infos, lat = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -184,8 +200,8 @@ def main():
         lat.extend(ctx.last_seconds)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    launches, kern_ms = ctx.timing_read()
-    ctx.timing_start(-1)
+    timing = {k: ctx.timing_read(k) for k in classes}
+    ctx.timing_start([])
     sec = (t1 - t0) / args.steps
     print(f"# timed {args.steps} step(s): {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
 
@@ -195,25 +211,35 @@ def main():
     L, _ = ctx.plan(w.freqs[0])
     sizes = level_sizes(w.shape, L)
     per_freq_iters = {str(f): float(np.mean(iters[k * nshot:(k + 1) * nshot])) for k, f in enumerate(w.freqs)}
-    total_iters = sum(iters)
-    step_bytes = total_iters * bytes_per_iteration(sizes)
+    slot_iters = sum(sum(i[1] for i in inf) for inf in infos)  # over the timed steps
+    step_bytes = sum(iters) * bytes_per_iteration(sizes)
 
-    # dominant kernel: fine-level damped-Jacobi sweeps (6 per iteration)
-    sweeps_per_it = 2 * ((2 - 1) + 2)
-    kbytes = total_iters * sweeps_per_it * smooth_bytes_per_launch_per_rhs(sizes[0]) * args.steps
-    achieved = kbytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    # per-class achieved bandwidth; the dominant class is the one with the most time
+    cb = class_bytes_per_iteration(sizes)
+    breakdown = {}
+    for k in classes:
+        n, ms = timing[k]
+        entry = {"launches": n, "ms": ms}
+        if k in cb and ms > 0:
+            entry["GB/s"] = slot_iters * cb[k] / (ms * 1e-3) / 1e9
+        if k == "coarse" and ms > 0:
+            entry["TFLOP/s"] = slot_iters * 2 * 8 * sizes[-1] ** 2 / (ms * 1e-3) / 1e12
+        breakdown[k] = entry
+    dom = max((k for k in classes if k in cb), key=lambda k: timing[k][1])
+    n_dom, ms_dom = timing[dom]
+    dom_bytes = slot_iters * cb[dom]
+    achieved = dom_bytes / (ms_dom * 1e-3) / 1e9 if ms_dom > 0 else None
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "smooth_fine_c3_traffic.json")
+    tpath = os.path.join(ROOT, "profiles", "dominant_kernel_traffic.json")
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_source_hash") == kernel_source_hash():
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("kernel_class") == dom:
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "k_smooth<2D> (finest level, nonzero start)",
-                "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": (achieved / PEAK_HBM_GBS) if achieved else None, "traffic": traffic,
-                "launches": launches, "avg_launch_ms": kern_ms / max(launches, 1),
-                "algorithmic_bytes_per_launch": kbytes / max(launches, 1)}
+                "launches": n_dom, "avg_launch_ms": ms_dom / max(n_dom, 1),
+                "algorithmic_bytes_per_launch": dom_bytes / max(n_dom, 1)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -245,6 +271,7 @@ def main():
         "hbm_gbps_step_model": step_bytes / sec / 1e9,
         "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "roofline": roofline,
+        "kernel_breakdown": breakdown,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

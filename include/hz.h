@@ -151,6 +151,40 @@ int  hz_misfit(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_
                const hz_c128 *d_obs_dev, double lambda, double *J,
                hz_c128 *d_cal_dev, hz_rhs_info *info);
 
+/* Misfit and its gradient by the adjoint-state method (Eq. (7) of the
+ * paper, the exact derivative of J as written in Eq. (4)):
+ *   dJ/dm_i = -2 Re sum_{f,s} delta_i u_i mu_i + 2 lambda m_i,
+ *   delta_i = dB_ii/dm_i = j omega g_i/h - 2 omega^2 (1 - j alpha) w_i m_i,
+ * with u the forward fields and mu the adjoint fields, B mu = P^T conj(P u -
+ * d_obs) (B is complex symmetric: the adjoint solve uses the same solver and
+ * preconditioner). Arguments as in hz_misfit; grad_dev is a device [nz][nx]
+ * array of doubles (written). info (host, optional) receives 2*nfreq*nsrc
+ * records: the forward solves, then the adjoint solves. Frequencies are
+ * processed in chunks whose wavefields fit the workspace budget (forward
+ * fields are kept only for the chunk being differentiated). */
+int  hz_gradient(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+                 double alpha, int nsrc, const int *src_iz, const int *src_ix,
+                 const hz_c128 *src_amp, int nrec, const int *rec_iz, const int *rec_ix,
+                 const hz_c128 *d_obs_dev, double lambda, double *J, double *grad_dev,
+                 hz_rhs_info *info);
+
+/* One Gauss-Newton model update (Eq. (8)-(9)): with the gradient g of J
+ * (as in hz_gradient) and the Gauss-Newton operator
+ *   H v = 2 Re[G^H G v] + 2 lambda v,   G v = -P B^-1 (delta * u * v),
+ * solve H dm = -g by conjugate gradients from dm = 0 (the paper uses CG since
+ * the Hessian is dense), at most cg_iters iterations or until the CG residual
+ * falls to cg_tol times ||g||. Every CG iteration is one batch of Born solves
+ * and one batch of adjoint solves over all shots and frequencies; the forward
+ * fields are kept on the device for the whole step. dm_dev (device,
+ * [nz][nx] doubles) receives the update (the caller forms m + dm); *J the
+ * misfit at m; *cg_done the CG iterations taken; info (optional) the
+ * forward-solve records (nfreq*nsrc). Other arguments as in hz_gradient. */
+int  hz_gn_step(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+                double alpha, int nsrc, const int *src_iz, const int *src_ix,
+                const hz_c128 *src_amp, int nrec, const int *rec_iz, const int *rec_ix,
+                const hz_c128 *d_obs_dev, double lambda, int cg_iters, double cg_tol,
+                double *J, double *dm_dev, int *cg_done, hz_rhs_info *info);
+
 /* The level count and damped-Jacobi weights the solver will use for one
  * frequency (host computation, no device work): *levels and w[0..levels-2].
  * w must hold HZ_MAX_LEVELS doubles. The plan: coarsen while every axis has
@@ -196,19 +230,23 @@ int  hz_precond(hz_ctx *c, const hz_solve_opts *o, double freq_hz, int nrhs,
 /* ---- measurement --------------------------------------------------------- */
 
 /* kernel classes that can be timed */
-#define HZ_KERNEL_SMOOTH   0   /* damped-Jacobi sweep from a nonzero start, finest level */
+#define HZ_KERNEL_SMOOTH   0   /* single damped-Jacobi sweep from a nonzero start, finest level */
 #define HZ_KERNEL_APPLY    1   /* operator application with fused dot products, finest level */
 #define HZ_KERNEL_RESTRICT 2   /* residual and restriction, finest level */
-#define HZ_KERNEL_PROLONG  3   /* prolongation and correction, finest level */
+#define HZ_KERNEL_PROLONG  3   /* prolongation and correction (with the first post-sweep), finest level */
 #define HZ_KERNEL_UPDATE   4   /* Krylov iterate and residual update */
 #define HZ_KERNEL_COARSE   5   /* dense coarse solve */
+#define HZ_KERNEL_PRESMOOTH 6  /* right-hand side update and two Jacobi sweeps from zero, finest level */
 
-/* Start timing one kernel class (resetting its totals), or stop with -1:
- * every later launch of that class is bracketed by two HIP events on the
- * context's stream. hz_timing_read returns the launches and the summed
- * elapsed milliseconds since the start. */
-int  hz_timing_start(hz_ctx *c, int kernel);
-int  hz_timing_read(hz_ctx *c, int *launches, double *total_ms);
+#define HZ_KERNEL_CLASSES  7
+
+/* Start timing the kernel classes whose bit (1 << HZ_KERNEL_*) is set in
+ * mask, resetting all totals (mask 0 stops): every later launch of such a
+ * class is bracketed by two HIP events on the context's stream.
+ * hz_timing_read returns, for one class, the launches and the summed elapsed
+ * milliseconds since the start. Errors: HZ_ERR_ARG. */
+int  hz_timing_start(hz_ctx *c, unsigned mask);
+int  hz_timing_read(hz_ctx *c, int kernel, int *launches, double *total_ms);
 
 /* Text for a return code / the context's last error message. */
 const char *hz_status_str(int status);

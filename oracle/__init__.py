@@ -26,6 +26,8 @@ krylov      right-preconditioned BiCGSTAB and GMRES(m)     -- "Krylov
             subspace ... GMRES" (section on FWI, Conclusion)
 lfa         local Fourier analysis of damped Jacobi and the level/weight plan
 misfit      receiver sampling and J(m)                      -- Eq. (4)
+gradient    adjoint-state gradient, Born modelling and the Gauss-Newton
+            operator                                       -- Eq. (7)-(9)
 """
 
-from . import operator, direct, multigrid, krylov, lfa, misfit  # noqa: F401
+from . import operator, direct, multigrid, krylov, lfa, misfit, gradient  # noqa: F401

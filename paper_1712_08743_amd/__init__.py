@@ -28,7 +28,7 @@ HZ_BICGSTAB, HZ_GMRES = 0, 1
 HZ_PRECOND_MG, HZ_PRECOND_EXACT, HZ_PRECOND_NONE = 0, 1, 2
 HZ_RHS_CONVERGED, HZ_RHS_MAXIT, HZ_RHS_BREAKDOWN, HZ_RHS_NONFINITE = 0, 1, 2, 3
 HZ_MAX_LEVELS = 12
-HZ_KERNEL = {"smooth": 0, "apply": 1, "restrict": 2, "prolong": 3, "update": 4, "coarse": 5}
+HZ_KERNEL = {"smooth": 0, "apply": 1, "restrict": 2, "prolong": 3, "update": 4, "coarse": 5, "presmooth": 6}
 
 PRECOND = {"mg": HZ_PRECOND_MG, "exact": HZ_PRECOND_EXACT, "none": HZ_PRECOND_NONE}
 KRYLOV = {"bicgstab": HZ_BICGSTAB, "gmres": HZ_GMRES}
@@ -65,6 +65,10 @@ _SIGS = {
                       ctypes.POINTER(RhsInfo)]),
     "hz_misfit": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
                        _ip, _vp, _d, _dp, _vp, ctypes.POINTER(RhsInfo)]),
+    "hz_gradient": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
+                         _ip, _vp, _d, _dp, _vp, ctypes.POINTER(RhsInfo)]),
+    "hz_gn_step": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
+                        _ip, _vp, _d, _i, _d, _dp, _vp, _ip, ctypes.POINTER(RhsInfo)]),
     "hz_plan": (_i, [_vp, ctypes.POINTER(SolveOpts), _d, _ip, _dp]),
     "hz_plan_grid": (_i, [_i, _i, _i, _d, _d, _d, ctypes.POINTER(SolveOpts), _d, _ip, _dp]),
     "hz_apply": (_i, [_vp, _i, _i, _d, _d, _d, _d, _i, _vp, _vp]),
@@ -72,8 +76,8 @@ _SIGS = {
     "hz_restrict": (_i, [_vp, _i, _d, _d, _d, _i, _vp, _vp, _vp]),
     "hz_prolong": (_i, [_vp, _i, _i, _vp, _vp]),
     "hz_precond": (_i, [_vp, ctypes.POINTER(SolveOpts), _d, _i, _vp, _vp]),
-    "hz_timing_start": (_i, [_vp, _i]),
-    "hz_timing_read": (_i, [_vp, _ip, _dp]),
+    "hz_timing_start": (_i, [_vp, ctypes.c_uint]),
+    "hz_timing_read": (_i, [_vp, _i, _ip, _dp]),
     "hz_status_str": (ctypes.c_char_p, [_i]),
     "hz_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -251,6 +255,61 @@ class Context:
         del keep
         return J.value, d_cal, [(i.status, i.iters, i.relres) for i in info]
 
+    def gradient(self, freqs, alpha, src, rec, d_obs, lam, src_amp=None, **opt):
+        """J(m) and dJ/dm (float64 tensor shaped like m) by the adjoint-state
+        method. Returns (J, grad, info) with 2 * nfreq * nsrc info records
+        (forward solves, then adjoint solves)."""
+        t = self.torch
+        freqs = [float(f) for f in freqs]
+        nf, ns, nr = len(freqs), len(src), len(rec)
+        d_obs = d_obs.to(self.device, t.complex128).contiguous()
+        assert tuple(d_obs.shape) == (nf, ns, nr)
+        grad = t.empty(self.shape, dtype=t.float64, device=self.device)
+        o, keep = make_opts(**opt)
+        info = (RhsInfo * (2 * nf * ns))()
+        J = ctypes.c_double()
+        ampbuf = None
+        if src_amp is not None:
+            ampbuf = (ctypes.c_double * (2 * ns))()
+            for k, a in enumerate(src_amp):
+                ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
+        rc = _lib.hz_gradient(self._h, ctypes.byref(o), nf, (ctypes.c_double * nf)(*freqs), float(alpha), ns,
+                              _int_array([q[0] for q in src]), _int_array([q[1] for q in src]),
+                              ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
+                              nr, _int_array([r[0] for r in rec]), _int_array([r[1] for r in rec]),
+                              _ptr(d_obs), float(lam), ctypes.byref(J), _ptr(grad), info)
+        self._check(rc, allow_warn=True)
+        del keep
+        return J.value, grad, [(i.status, i.iters, i.relres) for i in info]
+
+    def gn_step(self, freqs, alpha, src, rec, d_obs, lam, cg_iters, cg_tol=0.0, src_amp=None, **opt):
+        """One Gauss-Newton update (Eq. (9)) of the current model by CG on the
+        Gauss-Newton system. Returns (dm, J, cg_iterations, info)."""
+        t = self.torch
+        freqs = [float(f) for f in freqs]
+        nf, ns, nr = len(freqs), len(src), len(rec)
+        d_obs = d_obs.to(self.device, t.complex128).contiguous()
+        assert tuple(d_obs.shape) == (nf, ns, nr)
+        dm = t.empty(self.shape, dtype=t.float64, device=self.device)
+        o, keep = make_opts(**opt)
+        info = (RhsInfo * (nf * ns))()
+        J = ctypes.c_double()
+        done = ctypes.c_int()
+        ampbuf = None
+        if src_amp is not None:
+            ampbuf = (ctypes.c_double * (2 * ns))()
+            for k, a in enumerate(src_amp):
+                ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
+        rc = _lib.hz_gn_step(self._h, ctypes.byref(o), nf, (ctypes.c_double * nf)(*freqs), float(alpha), ns,
+                             _int_array([q[0] for q in src]), _int_array([q[1] for q in src]),
+                             ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
+                             nr, _int_array([r[0] for r in rec]), _int_array([r[1] for r in rec]),
+                             _ptr(d_obs), float(lam), int(cg_iters), float(cg_tol), ctypes.byref(J), _ptr(dm),
+                             ctypes.byref(done), info)
+        self._check(rc, allow_warn=True)
+        del keep
+        return dm, J.value, done.value, [(i.status, i.iters, i.relres) for i in info]
+
     def plan(self, freq, **opt):
         o, keep = make_opts(**opt)
         L = ctypes.c_int()
@@ -259,14 +318,18 @@ class Context:
         return L.value, [w[i] for i in range(L.value - 1)]
 
     # -- measurement -------------------------------------------------------
-    def timing_start(self, kernel):
-        """Time every launch of one kernel class (name in HZ_KERNEL) with HIP events."""
-        self._check(_lib.hz_timing_start(self._h, HZ_KERNEL[kernel] if isinstance(kernel, str) else kernel))
+    def timing_start(self, kernels=()):
+        """Time every launch of the named kernel classes (names in HZ_KERNEL) with HIP events."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << (HZ_KERNEL[k] if isinstance(k, str) else int(k))
+        self._check(_lib.hz_timing_start(self._h, mask))
 
-    def timing_read(self):
+    def timing_read(self, kernel):
         n = ctypes.c_int()
         ms = ctypes.c_double()
-        self._check(_lib.hz_timing_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        k = HZ_KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
+        self._check(_lib.hz_timing_read(self._h, k, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
 
     # -- single steps ------------------------------------------------------
@@ -343,6 +406,44 @@ def plan_grid(shape, h, m_min, m_max, freq, **opt):
         raise HzError(rc, "hz_plan_grid failed")
     del keep
     return L.value, [w[i] for i in range(L.value - 1)]
+
+
+class Misfit:
+    """J(m) of Eq. (4) as a differentiable function of the slowness tensor.
+
+    ``Misfit(ctx, freqs, alpha, src, rec, d_obs, lam)(m)`` returns a 0-d
+    float64 tensor; its backward pass returns dJ/dm from the adjoint-state
+    gradient (Eq. (7)) computed by the library (forward and adjoint solves on
+    the GPU). The gradient is formed together with J in the forward call,
+    where the forward wavefields are at hand, and kept for the backward pass.
+    """
+
+    def __init__(self, ctx, freqs, alpha, src, rec, d_obs, lam, **opt):
+        import torch
+        self.ctx, self.freqs, self.alpha = ctx, list(freqs), float(alpha)
+        self.src, self.rec, self.d_obs, self.lam, self.opt = src, rec, d_obs, float(lam), opt
+        self.last_info = None
+        outer = self
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(fctx, m):
+                outer.ctx.set_model(m.detach(), outer.ctx.h)
+                J, grad, info = outer.ctx.gradient(outer.freqs, outer.alpha, outer.src, outer.rec,
+                                                   outer.d_obs, outer.lam, **outer.opt)
+                outer.last_info = info
+                fctx.save_for_backward(grad)
+                return torch.tensor(J, dtype=torch.float64, device=m.device)
+
+            @staticmethod
+            def backward(fctx, gJ):
+                (grad,) = fctx.saved_tensors
+                return gJ * grad
+
+        self._fn = _Fn
+
+    def __call__(self, m):
+        return self._fn.apply(m)
 
 
 def exported_symbols():

@@ -55,7 +55,7 @@ struct LevelInfo {
 };
 
 // Fine-level vectors of the solvers (x is the caller's output buffer).
-enum FineVec { kR, kRh, kP, kV, kPh, kS, kSh, kT, kT1, kT2, kNumFine };
+enum FineVec { kR, kRh, kP, kP2, kV, kPh, kS, kSh, kT, kT1, kT2, kNumFine };
 // Per coarse level: right-hand side, result, two smoothing buffers.
 enum LevelVec { kLb, kLu, kLx, kLy, kNumLevelVec };
 
@@ -79,17 +79,21 @@ struct hz_ctx {
   DevBuf fine[kNumFine];
   DevBuf lev[kMaxLevels][kNumLevelVec];
   int ws_slots = 0, ws_levels = 0;
-  DevBuf slots, active, nactive, freqtab, partials, counters, resid;
+  DevBuf slots, active, nactive, freqtab, partials, resid, fstart;
+  int cur_nfreq = 1, cur_nrhs = 1;  // layout of the slots of the current batch
   int partial_tiles = 0;
   int slot_cap = 0;
   // coarse inverses for the current frequencies
   DevBuf cinv_a, cinv_b;
+  DevBuf winv;  // w_l / diag(M_l) per frequency and smoothing level
   std::vector<double> cinv_key;  // omega, beta1, beta2 per frequency + levels + version
   const double2* cinv_base = nullptr;
   // small uploads
   DevBuf scratch_int, scratch_c;
   DevBuf misfit_b, misfit_u, misfit_d, misfit_out;
   DevBuf gm_V, gm_small, gm_part;
+  DevBuf fwi_b, fwi_u, fwi_mu, fwi_d, fwi_int, fwi_omega, fwi_out;
+  DevBuf gn_g, gn_r, gn_p, gn_hp, gn_state;
   // host polling
   Summary* ring_host = nullptr;
   Summary* ring_dev = nullptr;
@@ -97,11 +101,15 @@ struct hz_ctx {
   size_t max_lds = 0;
   double wall_khz = 0.0;
   // kernel timing for measurement
-  int timing_cls = -1;
+  unsigned timing_mask = 0;
   std::vector<hipEvent_t> tpool;   // free events
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> tpairs;  // recorded, not yet folded
-  long long t_launches = 0;
-  double t_ms = 0.0;
+  struct Pair {
+    hipEvent_t a, b;
+    int cls;
+  };
+  std::vector<Pair> tpairs;        // recorded, not yet folded
+  long long t_launches[HZ_KERNEL_CLASSES] = {};
+  double t_ms[HZ_KERNEL_CLASSES] = {};
 };
 
 namespace {
@@ -262,9 +270,7 @@ int ensure_workspace(hz_ctx* c, int nslots, int levels) {
   const int tiles = std::max(t.per_slot, vec_tiles(n0));
   if (nslots > c->slot_cap || tiles > c->partial_tiles) {
     const int cap = std::max(nslots, c->slot_cap);
-    HZ_ALLOC(c, c->partials, (size_t)cap * tiles * 4 * sizeof(double));
-    HZ_ALLOC(c, c->counters, (size_t)cap * sizeof(unsigned));
-    HZ_HIP(c, hipMemsetAsync(c->counters.p, 0, (size_t)cap * sizeof(unsigned), c->stream));
+    HZ_ALLOC(c, c->partials, (size_t)cap * tiles * kPartialWidth * sizeof(double));
     HZ_ALLOC(c, c->slots, (size_t)cap * sizeof(Slot));
     HZ_ALLOC(c, c->active, (size_t)cap * sizeof(int));
     HZ_ALLOC(c, c->nactive, sizeof(int) * 4);
@@ -280,7 +286,6 @@ int ensure_workspace(hz_ctx* c, int nslots, int levels) {
 Reduce reducer(const hz_ctx* c) {
   Reduce r;
   r.partials = c->partials.as<double>();
-  r.counters = c->counters.as<unsigned>();
   r.max_tiles = c->partial_tiles;
   return r;
 }
@@ -291,24 +296,36 @@ Batch batch_of(const hz_ctx* c) {
   b.nactive = c->nactive.as<int>();
   b.slots = c->slots.as<Slot>();
   b.ft = c->freqtab.as<FreqTab>();
+  b.fstart = c->fstart.as<int>();
   return b;
 }
 
-// Upload slot records (all active, frequency = slot / nrhs) and the list 0..n-1.
+// The list 0..n-1 of every slot and its per-frequency ranges.
+int reset_list(hz_ctx* c, int nslots, int nrhs) {
+  const int nfreq = nslots / nrhs;
+  std::vector<int> act(nslots), fs(nfreq + 1);
+  for (int i = 0; i < nslots; ++i) act[i] = i;
+  for (int f = 0; f <= nfreq; ++f) fs[f] = f * nrhs;
+  HZ_ALLOC(c, c->fstart, (size_t)(nfreq + 1) * sizeof(int));
+  HZ_HIP(c, hipMemcpyAsync(c->active.p, act.data(), nslots * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(c->nactive.p, &nslots, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(c->fstart.p, fs.data(), (nfreq + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  c->cur_nfreq = nfreq;
+  c->cur_nrhs = nrhs;
+  return HZ_OK;
+}
+
+// Upload slot records (all active, frequency = slot / nrhs) and the full list.
 int reset_slots(hz_ctx* c, int nslots, int nrhs) {
   std::vector<Slot> s(nslots);
-  std::vector<int> act(nslots);
   for (int i = 0; i < nslots; ++i) {
     memset(&s[i], 0, sizeof(Slot));
     s[i].status = kActive;
     s[i].freq = i / nrhs;
-    act[i] = i;
   }
   HZ_HIP(c, hipMemcpyAsync(c->slots.p, s.data(), nslots * sizeof(Slot), hipMemcpyHostToDevice, c->stream));
-  HZ_HIP(c, hipMemcpyAsync(c->active.p, act.data(), nslots * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  HZ_HIP(c, hipMemcpyAsync(c->nactive.p, &nslots, sizeof(int), hipMemcpyHostToDevice, c->stream));
-  HZ_HIP(c, hipStreamSynchronize(c->stream));
-  return HZ_OK;
+  return reset_list(c, nslots, nrhs);
 }
 
 // Build the per-frequency table; invert the coarsest M when the V-cycle needs it.
@@ -325,6 +342,20 @@ int setup_freqs(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq
     for (int l = 0; l < levels - 1 && l < (int)wj[f].size(); ++l) ft[f].wj[l] = wj[f][l];
   }
   HZ_ALLOC(c, c->freqtab, (size_t)nfreq * sizeof(FreqTab));
+  if (o->precond == HZ_PRECOND_MG && levels > 1) {
+    size_t tot = 0;
+    for (int l = 0; l < levels - 1; ++l) tot += c->lv[l].n();
+    HZ_ALLOC(c, c->winv, tot * nfreq * sizeof(double2));
+    double2* wp = c->winv.as<double2>();
+    for (int f = 0; f < nfreq; ++f) {
+      for (int l = 0; l < levels - 1; ++l) {
+        HZ_HIP(c, launch_winv(c->dim, grid_of(c, l), ft[f].omega, ft[f].sM_re, ft[f].sM_im, ft[f].wj[l], wp,
+                              c->stream));
+        ft[f].winv[l] = wp;
+        wp += c->lv[l].n();
+      }
+    }
+  }
   const bool need_coarse = o->precond == HZ_PRECOND_MG;
   if (need_coarse) {
     const int cl = levels - 1;
@@ -376,13 +407,13 @@ hipEvent_t take_event(hz_ctx* c) {
 
 template <class F>
 hipError_t timed(hz_ctx* c, int cls, F&& launch) {
-  if (c->timing_cls != cls) return launch();
+  if (cls < 0 || !(c->timing_mask & (1u << cls))) return launch();
   hipEvent_t a = take_event(c), b = take_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, c->stream);
   if (e == hipSuccess) e = launch();
   if (e == hipSuccess) e = hipEventRecord(b, c->stream);
-  c->tpairs.emplace_back(a, b);
+  c->tpairs.push_back({a, b, cls});
   return e;
 }
 
@@ -390,12 +421,12 @@ hipError_t timed(hz_ctx* c, int cls, F&& launch) {
 void fold_timing(hz_ctx* c) {
   for (auto& pr : c->tpairs) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
-      c->t_ms += ms;
-      c->t_launches += 1;
+    if (hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess) {
+      c->t_ms[pr.cls] += ms;
+      c->t_launches[pr.cls] += 1;
     }
-    c->tpool.push_back(pr.first);
-    c->tpool.push_back(pr.second);
+    c->tpool.push_back(pr.a);
+    c->tpool.push_back(pr.b);
   }
   c->tpairs.clear();
 }
@@ -405,8 +436,23 @@ struct Cycle {
   int levels, nu1, nu2, precond;
 };
 
-// out = V b on the finest grid for the slots of the active list.
-hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0, double2* out) {
+// How the finest level's right-hand side is formed: read (mode 0), or the
+// BiCGSTAB vector p = a + beta (b - omega c) (mode 1) or s = a - alpha b
+// (mode 2), stored to `out` by the kernel that forms it.
+struct FineRhs {
+  int mode;
+  const double2* a;
+  const double2* b;
+  const double2* c;
+  double2* out;
+};
+
+bool fused_pre(const Cycle& cy) { return cy.precond == HZ_PRECOND_MG && cy.levels >= 2 && cy.nu1 == 2; }
+
+// out = V b on the finest grid for the slots of the active list. With rhs
+// (fused path only) the finest right-hand side is formed by the first kernel.
+hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0, double2* out,
+                         const FineRhs* rhs = nullptr) {
   const Batch bt = batch_of(c);
   const int dim = c->dim;
   hipStream_t st = c->stream;
@@ -414,8 +460,9 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   if (cy.precond == HZ_PRECOND_NONE) return launch_copy(bt, cap, n0, b0, out, n0, st);
   if (cy.precond == HZ_PRECOND_EXACT) return launch_pcr(grid_of(c, 0), bt, cap, b0, out, n0, st);
   const int L = cy.levels;
-  if (L == 1) return launch_coarse_solve((int)n0, bt, cap, b0, out, n0, st);
+  if (L == 1) return launch_coarse_solve((int)n0, c->cur_nfreq, c->cur_nrhs, bt, b0, out, n0, st);
   hipError_t e;
+  if (rhs) b0 = rhs->out;
   // descend
   const double2* bl = b0;
   double2* cur[kMaxLevels];
@@ -425,12 +472,23 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
     double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
     double2* u = nullptr;
-    for (int k = 0; k < cy.nu1; ++k) {
-      double2* dst = (u == X) ? Y : X;
-      const int cls = (l == 0 && u) ? HZ_KERNEL_SMOOTH : -2;
-      if ((e = timed(c, cls, [&] { return launch_smooth(dim, g, l, 0.0, bt, cap, bl, u, dst, nl, st); })) != hipSuccess)
+    if (cy.nu1 == 2) {
+      const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
+      const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : -2, [&] {
+             return launch_pre2(dim, g, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, X, nl, st);
+           })) != hipSuccess)
         return e;
-      u = dst;
+      u = X;
+    } else {
+      for (int k = 0; k < cy.nu1; ++k) {
+        double2* dst = (u == X) ? Y : X;
+        const int cls = (l == 0 && u) ? HZ_KERNEL_SMOOTH : -2;
+        if ((e = timed(c, cls, [&] { return launch_smooth(dim, g, l, 0.0, bt, cap, bl, u, dst, nl, st); })) !=
+            hipSuccess)
+          return e;
+        u = dst;
+      }
     }
     cur[l] = u;
     double2* bc = c->lev[l + 1][kLb].as<double2>();
@@ -444,7 +502,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   {
     const int cl = L - 1;
     if ((e = timed(c, HZ_KERNEL_COARSE, [&] {
-           return launch_coarse_solve((int)c->lv[cl].n(), bt, cap, c->lev[cl][kLb].as<double2>(),
+           return launch_coarse_solve((int)c->lv[cl].n(), c->cur_nfreq, c->cur_nrhs, bt, c->lev[cl][kLb].as<double2>(),
                                       c->lev[cl][kLu].as<double2>(), c->lv[cl].n(), st);
          })) != hipSuccess)
       return e;
@@ -452,26 +510,35 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   // ascend
   for (int l = L - 2; l >= 0; --l) {
     const Grid g = grid_of(c, l);
+    const Grid gc = grid_of(c, l + 1);
     const size_t nl = c->lv[l].n();
     double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
     double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
     double2* R = l == 0 ? out : c->lev[l][kLu].as<double2>();
     const double2* bll = l == 0 ? b0 : c->lev[l][kLb].as<double2>();
+    const double2* ec = c->lev[l + 1][kLu].as<double2>();
     double2* u = cur[l];
-    double2* pdst = cy.nu2 == 0 ? R : u;
-    if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
-           return launch_prolong(dim, g, grid_of(c, l + 1), bt, cap, c->lev[l + 1][kLu].as<double2>(), u,
-                                 pdst, nl, c->lv[l + 1].n(), st);
-         })) != hipSuccess)
-      return e;
-    u = pdst;
-    for (int k = 0; k < cy.nu2; ++k) {
-      double2* dst = (k == cy.nu2 - 1) ? R : ((u == X) ? Y : X);
-      if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : -2, [&] {
-             return launch_smooth(dim, g, l, 0.0, bt, cap, bll, u, dst, nl, st);
+    if (cy.nu2 == 0) {
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
+             return launch_prolong(dim, g, gc, bt, cap, ec, u, R, nl, c->lv[l + 1].n(), st);
            })) != hipSuccess)
         return e;
-      u = dst;
+      continue;
+    }
+    // prolongation fused with the first post-sweep
+    double2* dst = (cy.nu2 == 1) ? R : ((u == X) ? Y : X);
+    if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
+           return launch_prolong_smooth(dim, g, gc, l, bt, cap, ec, bll, u, dst, nl, c->lv[l + 1].n(), st);
+         })) != hipSuccess)
+      return e;
+    u = dst;
+    for (int k = 1; k < cy.nu2; ++k) {
+      double2* d2 = (k == cy.nu2 - 1) ? R : ((u == X) ? Y : X);
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : -2, [&] {
+             return launch_smooth(dim, g, l, 0.0, bt, cap, bll, u, d2, nl, st);
+           })) != hipSuccess)
+        return e;
+      u = d2;
     }
   }
   return hipSuccess;
@@ -487,13 +554,15 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   hipStream_t st = c->stream;
   double2* r = c->fine[kR].as<double2>();
   double2* rh = c->fine[kRh].as<double2>();
-  double2* p = c->fine[kP].as<double2>();
+  double2* pbuf[2] = {c->fine[kP].as<double2>(), c->fine[kP2].as<double2>()};
+  double2* p = pbuf[0];
   double2* v = c->fine[kV].as<double2>();
   double2* s = c->fine[kS].as<double2>();
   double2* t = c->fine[kT].as<double2>();
-  double2* ph = cy.precond == HZ_PRECOND_NONE ? p : c->fine[kPh].as<double2>();
-  double2* sh = cy.precond == HZ_PRECOND_NONE ? s : c->fine[kSh].as<double2>();
   const bool identity = cy.precond == HZ_PRECOND_NONE;
+  const bool fused = fused_pre(cy);
+  double2* ph = c->fine[kPh].as<double2>();
+  double2* sh = identity ? s : c->fine[kSh].as<double2>();
 
   long long seq = 0;                 // units issued
   long long restart_seq = -1;        // last unit that was a restart
@@ -502,14 +571,18 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   auto close_unit = [&]() -> int {
     const int k = ring_next;
     ring_next = (ring_next + 1) % kRing;
-    HZ_HIP(c, launch_compact(nslots, bt.slots, c->active.as<int>(), c->nactive.as<int>(), c->ring_dev + k, 0, st));
+    HZ_HIP(c, launch_compact(nslots, c->cur_nrhs, c->cur_nfreq, bt.slots, c->active.as<int>(),
+                             c->nactive.as<int>(), c->fstart.as<int>(), c->ring_dev + k, 0, st));
     HZ_HIP(c, hipEventRecord(c->ev[k], st));
     pending.emplace_back(seq++, k);
     return HZ_OK;
   };
 
+  const int vt = vec_tiles(n0);
+  const int gt = grid_tiles(c->lv[0].nz, c->lv[0].nx, c->dim).per_slot;
   int rc;
   HZ_HIP(c, launch_bicg_init(n0, bt, nslots, rd, b, x, r, rh, p, v, n0, st));
+  HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, st));
   if ((rc = close_unit()) != HZ_OK) return rc;
 
   int cap = nslots;
@@ -526,7 +599,8 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       if (!stale) {
         cap = std::min(cap, sm.nactive);
         if (sm.nrestart > 0) {
-          HZ_HIP(c, launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st));
+          HZ_HIP(c, launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st));  // current p buffer
+          HZ_HIP(c, launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, st));
           restart_seq = seq;
           if ((rc = close_unit()) != HZ_OK) return rc;
           cap = nslots;
@@ -542,19 +616,36 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       continue;
     }
     if (iters_issued >= guard) break;
-    HZ_HIP(c, launch_bicg_p(n0, bt, cap, r, p, v, n0, st));
-    if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, p, ph));
+    // p_new = r + beta (p_old - omega v) into the other p buffer, then ph = V p_new
+    double2* pn = (p == pbuf[0]) ? pbuf[1] : pbuf[0];
+    if (fused) {
+      const FineRhs fr{1, r, p, v, pn};
+      HZ_HIP(c, precond_apply(c, cy, cap, nullptr, ph, &fr));
+    } else {
+      HZ_HIP(c, launch_bicg_p(n0, bt, cap, r, p, v, pn, n0, st));
+      if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, pn, ph));
+    }
+    p = pn;
+    if (identity) ph = p;
     HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] {
              return launch_bicg_apply_sigma(c->dim, g0, bt, cap, rd, ph, rh, v, n0, st);
            }));
-    HZ_HIP(c, launch_bicg_s(n0, bt, cap, r, v, s, n0, st));
-    if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, s, sh));
+    HZ_HIP(c, launch_bicg_fin(kFinSigma, gt, bt, cap, rd, o->tol, o->maxit, st));
+    if (fused) {
+      const FineRhs fr{2, r, v, nullptr, s};
+      HZ_HIP(c, precond_apply(c, cy, cap, nullptr, sh, &fr));
+    } else {
+      HZ_HIP(c, launch_bicg_s(n0, bt, cap, r, v, s, n0, st));
+      if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, s, sh));
+    }
     HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] {
              return launch_bicg_apply_omega(c->dim, g0, bt, cap, rd, sh, s, t, n0, st);
            }));
+    HZ_HIP(c, launch_bicg_fin(kFinOmega, gt, bt, cap, rd, o->tol, o->maxit, st));
     HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
-             return launch_bicg_xr(n0, bt, cap, rd, o->tol, o->maxit, x, ph, sh, s, t, r, rh, n0, st);
+             return launch_bicg_xr(n0, bt, cap, rd, x, ph, sh, s, t, r, rh, n0, st);
            }));
+    HZ_HIP(c, launch_bicg_fin(kFinStep, vt, bt, cap, rd, o->tol, o->maxit, st));
     ++iters_issued;
     if ((rc = close_unit()) != HZ_OK) return rc;
   }
@@ -611,7 +702,8 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
   auto close_unit = [&](int phase) -> int {
     const int k = ring_next;
     ring_next = (ring_next + 1) % kRing;
-    HZ_HIP(c, launch_compact(nslots, bt.slots, c->active.as<int>(), c->nactive.as<int>(), c->ring_dev + k, phase, st));
+    HZ_HIP(c, launch_compact(nslots, c->cur_nrhs, c->cur_nfreq, bt.slots, c->active.as<int>(),
+                             c->nactive.as<int>(), c->fstart.as<int>(), c->ring_dev + k, phase, st));
     HZ_HIP(c, hipEventRecord(c->ev[k], st));
     pending.emplace_back(seq++, k);
     return HZ_OK;
@@ -632,6 +724,7 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
   if ((rc = close_unit(0)) != HZ_OK) return rc;
   if ((rc = drain(&sm)) != HZ_OK) return rc;
   int cap = sm.nactive;
+  if (cap > 0) HZ_HIP(c, launch_gm_scale(n0, bt, cap, V, n0, st));
   const long long guard = (long long)o->maxit + 2;
   long long cycles = 0;
   while (cap > 0 && cycles++ <= guard) {
@@ -644,9 +737,9 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
         zin = z;
       }
       HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] { return launch_apply(c->dim, g0, 0, 0, bt, cap, zin, w, n0, st); }));
-      HZ_HIP(c, launch_gm_dots(n0, bt, cap, rd, gm, j, 0, V, vstride, w, n0, st));
+      HZ_HIP(c, launch_gm_dots(n0, bt, cap, gm, j, 0, V, vstride, w, n0, st));
       HZ_HIP(c, launch_gm_orth(n0, bt, cap, rd, gm, j, 0, o->tol, o->maxit, V, vstride, w, n0, st));
-      HZ_HIP(c, launch_gm_dots(n0, bt, cap, rd, gm, j, 1, V, vstride, w, n0, st));
+      HZ_HIP(c, launch_gm_dots(n0, bt, cap, gm, j, 1, V, vstride, w, n0, st));
       HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
                return launch_gm_orth(n0, bt, cap, rd, gm, j, 1, o->tol, o->maxit, V, vstride, w, n0, st);
              }));
@@ -687,10 +780,8 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
 // Final statuses and true residuals for every slot.
 int collect_info(hz_ctx* c, int nslots, const double2* b, const double2* x, hz_rhs_info* info,
                  int* any_fail) {
-  std::vector<int> act(nslots);
-  for (int i = 0; i < nslots; ++i) act[i] = i;
-  HZ_HIP(c, hipMemcpyAsync(c->active.p, act.data(), nslots * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  HZ_HIP(c, hipMemcpyAsync(c->nactive.p, &nslots, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  int rc = reset_list(c, nslots, c->cur_nrhs);
+  if (rc) return rc;
   HZ_HIP(c, launch_true_residual(c->dim, grid_of(c, 0), batch_of(c), nslots, reducer(c), b, x,
                                  c->resid.as<double>(), c->lv[0].n(), c->stream));
   std::vector<Slot> s(nslots);
@@ -1025,6 +1116,232 @@ int hz_misfit(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_h
   return solve_rc;
 }
 
+int hz_gradient(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+                int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
+                const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda, double* J,
+                double* grad_dev, hz_rhs_info* info) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
+      !d_obs_dev || !J || !grad_dev)
+    return fail(c, HZ_ERR_ARG, "bad gradient arguments");
+  if (!(lambda >= 0.0) || !isfinite(lambda)) return fail(c, HZ_ERR_ARG, "lambda must be >= 0");
+  for (int f = 0; f < nfreq; ++f)
+    if (!(freq_hz[f] > 0.0) || !isfinite(freq_hz[f])) return fail(c, HZ_ERR_ARG, "frequency %d must be positive", f);
+  // distinct receiver nodes and, for each, its receivers (in receiver order)
+  std::vector<int> rnode(nrec);
+  for (int r = 0; r < nrec; ++r) {
+    if (rec_iz[r] < 0 || rec_iz[r] >= c->nz || rec_ix[r] < 0 || rec_ix[r] >= c->nx)
+      return fail(c, HZ_ERR_ARG, "receiver %d is outside the grid", r);
+    rnode[r] = rec_iz[r] * c->nx + rec_ix[r];
+  }
+  std::vector<int> order(nrec);
+  for (int r = 0; r < nrec; ++r) order[r] = r;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rnode[a] < rnode[b]; });
+  std::vector<int> uniq, ptr, idx;
+  for (int q = 0; q < nrec; ++q) {
+    if (q == 0 || rnode[order[q]] != rnode[order[q - 1]]) {
+      uniq.push_back(rnode[order[q]]);
+      ptr.push_back(q);
+    }
+    idx.push_back(order[q]);
+  }
+  ptr.push_back(nrec);
+  const int nuniq = (int)uniq.size();
+  HZ_HIP(c, hipSetDevice(c->device));
+  const size_t n0 = c->lv[0].n();
+  // frequencies per chunk: three wavefield sets (rhs, u, mu) per right-hand side
+  int chunk = nfreq;
+  if (c->budget) {
+    const size_t per_freq = (size_t)nsrc * n0 * sizeof(double2) * (3 + 12);
+    chunk = (int)std::max<size_t>(1, std::min<size_t>(nfreq, c->budget / std::max<size_t>(per_freq, 1)));
+  }
+  const size_t nb = (size_t)chunk * nsrc * n0;
+  HZ_ALLOC(c, c->fwi_b, nb * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_u, nb * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_mu, nb * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_d, (size_t)chunk * nsrc * nrec * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_int, (size_t)(3 * nrec + 2) * sizeof(int));
+  HZ_ALLOC(c, c->fwi_omega, (size_t)nfreq * sizeof(double));
+  HZ_ALLOC(c, c->fwi_out, 4 * sizeof(double));
+  int* d_uniq = c->fwi_int.as<int>();
+  int* d_ptr = d_uniq + nrec;
+  int* d_idx = d_ptr + nrec + 1;
+  HZ_HIP(c, hipMemcpyAsync(d_uniq, uniq.data(), nuniq * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(d_ptr, ptr.data(), (nuniq + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(d_idx, idx.data(), nrec * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  std::vector<double> om(nfreq);
+  for (int f = 0; f < nfreq; ++f) om[f] = 2.0 * M_PI * freq_hz[f];
+  HZ_HIP(c, hipMemcpyAsync(c->fwi_omega.p, om.data(), nfreq * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  double jdata = 0.0, msum = 0.0;
+  int worst = HZ_OK;
+  for (int f0 = 0; f0 < nfreq; f0 += chunk) {
+    const int nf = std::min(chunk, nfreq - f0);
+    for (int f = 0; f < nf; ++f) {
+      rc = hz_point_rhs(c, nsrc, src_iz, src_ix, src_amp,
+                        reinterpret_cast<hz_c128*>(c->fwi_b.as<double2>() + (size_t)f * nsrc * n0));
+      if (rc) return rc;
+    }
+    hz_rhs_info* inf_fwd = info ? info + (size_t)f0 * nsrc : nullptr;
+    hz_rhs_info* inf_adj = info ? info + (size_t)(nfreq + f0) * nsrc : nullptr;
+    rc = hz_solve(c, o, nf, freq_hz + f0, alpha, nsrc, reinterpret_cast<const hz_c128*>(c->fwi_b.p),
+                  reinterpret_cast<hz_c128*>(c->fwi_u.p), inf_fwd);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+    const double2* dobs = reinterpret_cast<const double2*>(d_obs_dev) + (size_t)f0 * nsrc * nrec;
+    // data misfit of the chunk
+    HZ_ALLOC(c, c->scratch_int, (size_t)nrec * sizeof(int));
+    HZ_HIP(c, hipMemcpyAsync(c->scratch_int.p, rnode.data(), nrec * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HZ_HIP(c, launch_gather(nf * nsrc, nrec, c->scratch_int.as<int>(), c->fwi_u.as<double2>(), n0,
+                            c->fwi_d.as<double2>(), c->stream));
+    HZ_HIP(c, launch_misfit((size_t)nf * nsrc * nrec, dobs, c->fwi_d.as<double2>(), n0, c->lv[0].m.as<double>(),
+                            0.0, c->fwi_out.as<double>(), c->stream));
+    double out[3];
+    HZ_HIP(c, hipMemcpyAsync(out, c->fwi_out.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    // adjoint sources and solves
+    HZ_HIP(c, launch_adjoint_src(nf * nsrc, n0, nuniq, d_uniq, d_ptr, d_idx, nrec, c->fwi_u.as<double2>(), dobs,
+                                 c->fwi_b.as<double2>(), c->stream));
+    HZ_HIP(c, hipStreamSynchronize(c->stream));
+    jdata += out[1];
+    msum = out[2];
+    rc = hz_solve(c, o, nf, freq_hz + f0, alpha, nsrc, reinterpret_cast<const hz_c128*>(c->fwi_b.p),
+                  reinterpret_cast<hz_c128*>(c->fwi_mu.p), inf_adj);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+    HZ_HIP(c, launch_grad_accum(c->dim, grid_of(c, 0), nf, nsrc, c->fwi_omega.as<double>() + f0, alpha,
+                                c->fwi_u.as<double2>(), c->fwi_mu.as<double2>(), lambda, c->lv[0].m.as<double>(),
+                                f0 > 0 ? 1 : 0, grad_dev, c->stream));
+  }
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  *J = jdata + lambda * msum;
+  return worst;
+}
+
+int hz_gn_step(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+               int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
+               const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda, int cg_iters,
+               double cg_tol, double* J, double* dm_dev, int* cg_done, hz_rhs_info* info) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
+      !d_obs_dev || !J || !dm_dev || !cg_done || cg_iters < 0)
+    return fail(c, HZ_ERR_ARG, "bad Gauss-Newton arguments");
+  if (!(lambda >= 0.0) || !isfinite(lambda) || !(cg_tol >= 0.0)) return fail(c, HZ_ERR_ARG, "bad lambda or cg_tol");
+  for (int f = 0; f < nfreq; ++f)
+    if (!(freq_hz[f] > 0.0) || !isfinite(freq_hz[f])) return fail(c, HZ_ERR_ARG, "frequency %d must be positive", f);
+  std::vector<int> rnode(nrec);
+  for (int r = 0; r < nrec; ++r) {
+    if (rec_iz[r] < 0 || rec_iz[r] >= c->nz || rec_ix[r] < 0 || rec_ix[r] >= c->nx)
+      return fail(c, HZ_ERR_ARG, "receiver %d is outside the grid", r);
+    rnode[r] = rec_iz[r] * c->nx + rec_ix[r];
+  }
+  std::vector<int> order(nrec);
+  for (int r = 0; r < nrec; ++r) order[r] = r;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rnode[a] < rnode[b]; });
+  std::vector<int> uniq, ptr, idx;
+  for (int q = 0; q < nrec; ++q) {
+    if (q == 0 || rnode[order[q]] != rnode[order[q - 1]]) {
+      uniq.push_back(rnode[order[q]]);
+      ptr.push_back(q);
+    }
+    idx.push_back(order[q]);
+  }
+  ptr.push_back(nrec);
+  const int nuniq = (int)uniq.size();
+  HZ_HIP(c, hipSetDevice(c->device));
+  const size_t n0 = c->lv[0].n();
+  const int nslots = nfreq * nsrc;
+  const size_t nb = (size_t)nslots * n0;
+  HZ_ALLOC(c, c->fwi_b, nb * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_u, nb * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_mu, nb * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_d, (size_t)nslots * nrec * sizeof(double2));
+  HZ_ALLOC(c, c->fwi_int, (size_t)(3 * nrec + 2) * sizeof(int));
+  HZ_ALLOC(c, c->fwi_omega, (size_t)nfreq * sizeof(double));
+  HZ_ALLOC(c, c->fwi_out, 4 * sizeof(double));
+  HZ_ALLOC(c, c->gn_g, n0 * sizeof(double));
+  HZ_ALLOC(c, c->gn_r, n0 * sizeof(double));
+  HZ_ALLOC(c, c->gn_p, n0 * sizeof(double));
+  HZ_ALLOC(c, c->gn_hp, n0 * sizeof(double));
+  HZ_ALLOC(c, c->gn_state, 4 * sizeof(double));
+  int* d_uniq = c->fwi_int.as<int>();
+  int* d_ptr = d_uniq + nrec;
+  int* d_idx = d_ptr + nrec + 1;
+  HZ_HIP(c, hipMemcpyAsync(d_uniq, uniq.data(), nuniq * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(d_ptr, ptr.data(), (nuniq + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(d_idx, idx.data(), nrec * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  std::vector<double> om(nfreq);
+  for (int f = 0; f < nfreq; ++f) om[f] = 2.0 * M_PI * freq_hz[f];
+  HZ_HIP(c, hipMemcpyAsync(c->fwi_omega.p, om.data(), nfreq * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  double2* B = c->fwi_b.as<double2>();
+  double2* U = c->fwi_u.as<double2>();
+  double2* MU = c->fwi_mu.as<double2>();
+  double2* D = c->fwi_d.as<double2>();
+  const double* omg = c->fwi_omega.as<double>();
+  const Grid g0 = grid_of(c, 0);
+  int worst = HZ_OK;
+  // forward fields, kept for every Born product
+  for (int f = 0; f < nfreq; ++f) {
+    rc = hz_point_rhs(c, nsrc, src_iz, src_ix, src_amp, reinterpret_cast<hz_c128*>(B + (size_t)f * nsrc * n0));
+    if (rc) return rc;
+  }
+  rc = hz_solve(c, o, nfreq, freq_hz, alpha, nsrc, reinterpret_cast<const hz_c128*>(B), reinterpret_cast<hz_c128*>(U),
+                info);
+  if (rc < 0) return rc;
+  worst = std::max(worst, rc);
+  HZ_ALLOC(c, c->scratch_int, (size_t)nrec * sizeof(int));
+  HZ_HIP(c, hipMemcpyAsync(c->scratch_int.p, rnode.data(), nrec * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, launch_gather(nslots, nrec, c->scratch_int.as<int>(), U, n0, D, c->stream));
+  HZ_HIP(c, launch_misfit((size_t)nslots * nrec, reinterpret_cast<const double2*>(d_obs_dev), D, n0,
+                          c->lv[0].m.as<double>(), lambda, c->fwi_out.as<double>(), c->stream));
+  double out[3];
+  HZ_HIP(c, hipMemcpyAsync(out, c->fwi_out.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  // gradient g = -2 Re sum delta u mu + 2 lambda m
+  HZ_HIP(c, launch_adjoint_src(nslots, n0, nuniq, d_uniq, d_ptr, d_idx, nrec, U,
+                               reinterpret_cast<const double2*>(d_obs_dev), B, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  *J = out[0];
+  rc = hz_solve(c, o, nfreq, freq_hz, alpha, nsrc, reinterpret_cast<const hz_c128*>(B), reinterpret_cast<hz_c128*>(MU),
+                nullptr);
+  if (rc < 0) return rc;
+  worst = std::max(worst, rc);
+  double* gv = c->gn_g.as<double>();
+  double* xr = c->gn_r.as<double>();
+  double* xp = c->gn_p.as<double>();
+  double* hp = c->gn_hp.as<double>();
+  double* stt = c->gn_state.as<double>();
+  HZ_HIP(c, launch_grad_accum(c->dim, g0, nfreq, nsrc, omg, alpha, U, MU, lambda, c->lv[0].m.as<double>(), 0, gv,
+                              c->stream));
+  // conjugate gradients on H dm = -g; each product is one Born and one adjoint batch
+  HZ_HIP(c, launch_cg(0, n0, gv, nullptr, dm_dev, xr, xp, stt, cg_tol, c->stream));
+  int it = 0;
+  while (it < cg_iters) {
+    double st3[3];
+    HZ_HIP(c, hipMemcpyAsync(st3, stt, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HZ_HIP(c, hipStreamSynchronize(c->stream));
+    if (st3[2] != 0.0) break;
+    HZ_HIP(c, launch_born_src(c->dim, g0, nslots, nsrc, omg, alpha, U, xp, B, c->stream));
+    rc = hz_solve(c, o, nfreq, freq_hz, alpha, nsrc, reinterpret_cast<const hz_c128*>(B),
+                  reinterpret_cast<hz_c128*>(MU), nullptr);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+    HZ_HIP(c, launch_gather(nslots, nrec, c->scratch_int.as<int>(), MU, n0, D, c->stream));
+    HZ_HIP(c, launch_adjoint_data(nslots, n0, nuniq, d_uniq, d_ptr, d_idx, nrec, D, B, c->stream));
+    rc = hz_solve(c, o, nfreq, freq_hz, alpha, nsrc, reinterpret_cast<const hz_c128*>(B),
+                  reinterpret_cast<hz_c128*>(MU), nullptr);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+    HZ_HIP(c, launch_grad_accum(c->dim, g0, nfreq, nsrc, omg, alpha, U, MU, lambda, xp, 0, hp, c->stream));
+    HZ_HIP(c, launch_cg(1, n0, gv, hp, dm_dev, xr, xp, stt, cg_tol, c->stream));
+    ++it;
+  }
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  *cg_done = it;
+  return worst;
+}
+
 int hz_apply(hz_ctx* c, int op, int level, double freq_hz, double alpha, double beta1, double beta2,
              int nrhs, const hz_c128* x_dev, hz_c128* y_dev) {
   int rc = require_model(c);
@@ -1116,23 +1433,26 @@ int hz_precond(hz_ctx* c, const hz_solve_opts* o, double freq_hz, int nrhs, cons
   return HZ_OK;
 }
 
-int hz_timing_start(hz_ctx* c, int kernel) {
+int hz_timing_start(hz_ctx* c, unsigned mask) {
   if (!c) return HZ_ERR_ARG;
-  if (kernel < -1 || kernel > HZ_KERNEL_COARSE) return fail(c, HZ_ERR_ARG, "unknown kernel class %d", kernel);
+  if (mask >> HZ_KERNEL_CLASSES) return fail(c, HZ_ERR_ARG, "unknown kernel class in mask 0x%x", mask);
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   fold_timing(c);
-  c->timing_cls = kernel;
-  c->t_launches = 0;
-  c->t_ms = 0.0;
+  c->timing_mask = mask;
+  for (int k = 0; k < HZ_KERNEL_CLASSES; ++k) {
+    c->t_launches[k] = 0;
+    c->t_ms[k] = 0.0;
+  }
   return HZ_OK;
 }
 
-int hz_timing_read(hz_ctx* c, int* launches, double* total_ms) {
+int hz_timing_read(hz_ctx* c, int kernel, int* launches, double* total_ms) {
   if (!c || !launches || !total_ms) return HZ_ERR_ARG;
+  if (kernel < 0 || kernel >= HZ_KERNEL_CLASSES) return fail(c, HZ_ERR_ARG, "unknown kernel class %d", kernel);
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   fold_timing(c);
-  *launches = (int)c->t_launches;
-  *total_ms = c->t_ms;
+  *launches = (int)c->t_launches[kernel];
+  *total_ms = c->t_ms[kernel];
   return HZ_OK;
 }
 

@@ -11,8 +11,10 @@ namespace hz {
 constexpr int kMaxLevels = 12;
 constexpr int kBlock = 256;        // threads per block of the grid kernels
 constexpr int kVecPerThread = 4;   // nodes per thread in the pointwise Krylov kernels
-constexpr int kCoarseRows = 128;   // rows of the coarse inverse per block
-constexpr int kCoarseGroup = 8;    // right-hand sides per block of the coarse solve
+constexpr int kCoarseRows = 64;    // rows of the coarse inverse per block (one per lane)
+constexpr int kCoarseSlots = 4;    // right-hand sides per wave of the coarse solve
+constexpr int kCoarseWaves = 4;    // waves per block (each its own right-hand sides)
+constexpr int kCoarseK = 32;       // columns of the inverse staged in LDS at a time
 constexpr int kPcrMax = 2048;      // longest 1D grid for the exact tridiagonal solve
 constexpr int kCoarseMax = 16384;  // most unknowns on the coarsest level (dense inverse)
 
@@ -39,7 +41,8 @@ struct FreqTab {
   double sB_re, sB_im;  // mass shift of B: 1 - j alpha
   double sM_re, sM_im;  // mass shift of M: beta1 - j beta2
   double wj[kMaxLevels];
-  const double2* cinv;  // inverse of M on the coarsest level, [nc][nc]
+  const double2* cinv;               // inverse of M on the coarsest level, [nc][nc]
+  const double2* winv[kMaxLevels];   // w_l / diag(M_l) on each smoothing level, [n_l]
 };
 
 // Per right-hand-side Krylov scalars (device array, one per slot).
@@ -74,12 +77,13 @@ struct Batch {
   const int* nactive;  // device count
   Slot* slots;
   const FreqTab* ft;
+  const int* fstart;   // [nfreq + 1]: the list's entries of frequency f are fstart[f]..fstart[f+1]-1
 };
 
-// Scratch for deterministic per-slot reductions.
+// Scratch for deterministic per-slot reductions: block partial sums.
+constexpr int kPartialWidth = 4;
 struct Reduce {
-  double* partials;     // [slots][max_tiles][4]
-  unsigned* counters;   // [slots], zero between kernels
+  double* partials;  // [slots][max_tiles][kPartialWidth]
   int max_tiles;
 };
 
@@ -96,6 +100,7 @@ struct Tiles {
 
 Tiles grid_tiles(int nz, int nx, int dim);
 int vec_tiles(size_t n);
+long long tile_blocks(int per_slot, int cap);  // XCD-aware grid size of a 2D-tiled kernel
 
 // ---- kernel launchers (hz_kernels.hip) ----------------------------------------
 // All take the stream last and return the launch status.
@@ -112,12 +117,22 @@ hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch&
 hipError_t launch_prolong(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                           const double2* e, const double2* u_in, double2* u_out, size_t sf,
                           size_t sc, hipStream_t st);
-hipError_t launch_coarse_solve(int nc, const Batch& bt, int cap, const double2* bc, double2* uc,
-                               size_t stride, hipStream_t st);
+// mode 0: b given (in_a); 1: b = p = in_a + beta (in_b - omega in_c) stored to bout;
+// 2: b = s = in_a - alpha in_b stored to bout. u2 = two Jacobi sweeps from zero.
+hipError_t launch_pre2(int dim, const Grid& g, int lvl, int mode, const Batch& bt, int cap,
+                       const double2* in_a, const double2* in_b, const double2* in_c, double2* bout,
+                       double2* u2, size_t stride, hipStream_t st);
+// u_out = S(u2 + P e): prolongation, correction and one sweep.
+hipError_t launch_prolong_smooth(int dim, const Grid& gf, const Grid& gc, int lvl, const Batch& bt,
+                                 int cap, const double2* e, const double2* b, const double2* u2,
+                                 double2* u_out, size_t sf, size_t sc, hipStream_t st);
+hipError_t launch_coarse_solve(int nc, int nfreq, int nrhs, const Batch& bt, const double2* bc,
+                               double2* uc, size_t stride, hipStream_t st);
 hipError_t launch_pcr(const Grid& g, const Batch& bt, int cap, const double2* b, double2* u,
                       size_t stride, hipStream_t st);
-hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,
-                       size_t stride, hipStream_t st);
+// winv[p] = w / diag(M)[p] on one level for one frequency.
+hipError_t launch_winv(int dim, const Grid& g, double omega, double s_re, double s_im, double w,
+                       double2* winv, hipStream_t st);
 
 // Gauss-Jordan inversion of the coarsest M for nfreq frequencies.
 hipError_t launch_assemble_dense(int dim, const Grid& g, int nfreq, const FreqTab* ft,
@@ -125,12 +140,14 @@ hipError_t launch_assemble_dense(int dim, const Grid& g, int nfreq, const FreqTa
 hipError_t launch_gj_step(int nc, int nfreq, int k, const double2* A_in, double2* A_out,
                           hipStream_t st);
 
-// BiCGSTAB pieces
+// BiCGSTAB pieces. Each producer stores block partials; launch_bicg_fin
+// (one block per slot) sums them in a fixed order and updates the slot's
+// scalars and status.
 hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd,
                             const double2* b, double2* x, double2* r, double2* rh, double2* p,
                             double2* v, size_t stride, hipStream_t st);
-hipError_t launch_bicg_p(size_t n, const Batch& bt, int cap, const double2* r, double2* p,
-                         const double2* v, size_t stride, hipStream_t st);
+hipError_t launch_bicg_p(size_t n, const Batch& bt, int cap, const double2* r, const double2* p_old,
+                         const double2* v, double2* p_new, size_t stride, hipStream_t st);
 hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int cap,
                                    const Reduce& rd, const double2* ph, const double2* rh,
                                    double2* v, size_t stride, hipStream_t st);
@@ -139,25 +156,35 @@ hipError_t launch_bicg_s(size_t n, const Batch& bt, int cap, const double2* r, c
 hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int cap,
                                    const Reduce& rd, const double2* sh, const double2* s,
                                    double2* t, size_t stride, hipStream_t st);
-hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, double tol,
-                          int maxit, double2* x, const double2* ph, const double2* sh,
-                          const double2* s, const double2* t, double2* r, const double2* rh,
-                          size_t stride, hipStream_t st);
+hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, double2* x,
+                          const double2* ph, const double2* sh, const double2* s, const double2* t,
+                          double2* r, const double2* rh, size_t stride, hipStream_t st);
 hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
                                const double2* r, double2* rh, double2* p, double2* v,
                                size_t stride, hipStream_t st);
-hipError_t launch_compact(int nslots, Slot* slots, int* active, int* nactive, Summary* sum,
-                          int want_phase, hipStream_t st);
+enum : int { kFinInit = 0, kFinSigma = 1, kFinOmega = 2, kFinStep = 3, kFinRestart = 4 };
+// tiles: the producer's tiles per slot; restart runs over all nslots slots.
+hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
+                           double tol, int maxit, hipStream_t st);
+hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* active, int* nactive,
+                          int* fstart, Summary* sum, int want_phase, hipStream_t st);
+hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,
+                       size_t stride, hipStream_t st);
+
+// ||b - B x||^2 and ||b||^2 per slot of the list into out[slot*2 + {0,1}]
+hipError_t launch_true_residual(int dim, const Grid& g, const Batch& bt, int cap,
+                                const Reduce& rd, const double2* b, const double2* x,
+                                double* out, size_t stride, hipStream_t st);
 
 // GMRES pieces
 hipError_t launch_gm_residual(int dim, const Grid& g, const Batch& bt, int cap, const Reduce& rd,
                               const Gmres& gm, int first, double tol, int maxit, const double2* b,
-                              const double2* x, double2* v0, size_t stride, hipStream_t st);
+                              double2* x, double2* v0, size_t stride, hipStream_t st);
 hipError_t launch_gm_scale(size_t n, const Batch& bt, int cap, double2* v, size_t stride,
                            hipStream_t st);
-hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm,
-                          int j, int pass, const double2* V, size_t vstride, const double2* w,
-                          size_t stride, hipStream_t st);
+hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, int pass,
+                          const double2* V, size_t vstride, const double2* w, size_t stride,
+                          hipStream_t st);
 hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm,
                           int j, int pass, double tol, int maxit, const double2* V,
                           size_t vstride, double2* w, size_t stride, hipStream_t st);
@@ -168,11 +195,6 @@ hipError_t launch_gm_combine(size_t n, const Batch& bt, int cap, const Gmres& gm
 hipError_t launch_axpy1(size_t n, const Batch& bt, int cap, const double2* z, double2* x,
                         size_t stride, hipStream_t st);
 
-// true residual norms ||b - B x||^2 and ||b||^2 per slot into out[slot*2 + {0,1}]
-hipError_t launch_true_residual(int dim, const Grid& g, const Batch& bt, int cap,
-                                const Reduce& rd, const double2* b, const double2* x,
-                                double* out, size_t stride, hipStream_t st);
-
 // misfit helpers
 hipError_t launch_point_rhs(size_t n, int nsrc, const int* nodes, const double2* amp,
                             double scale, double2* b, hipStream_t st);
@@ -181,6 +203,20 @@ hipError_t launch_gather(int nrhs, int nrec, const int* rec_nodes, const double2
 hipError_t launch_misfit(size_t nd, const double2* d_obs, const double2* d_cal, size_t nm,
                          const double* m, double lambda, double* out, hipStream_t st);
 hipError_t launch_inject(const Grid& gf, int dim, double* mc, hipStream_t st);
+
+// FWI gradient pieces (hz_fwi.hip)
+hipError_t launch_adjoint_src(int nslots, size_t n, int nuniq, const int* uniq_node, const int* rec_ptr,
+                              const int* rec_idx, int nrec, const double2* u, const double2* d_obs,
+                              double2* out, hipStream_t st);
+hipError_t launch_grad_accum(int dim, const Grid& g, int nfreq, int nsrc, const double* omega, double alpha,
+                             const double2* u, const double2* mu, double lambda, const double* reg,
+                             int accumulate, double* grad, hipStream_t st);
+hipError_t launch_born_src(int dim, const Grid& g, int nslots, int nsrc, const double* omega, double alpha,
+                           const double2* u, const double* v, double2* rhs, hipStream_t st);
+hipError_t launch_adjoint_data(int nslots, size_t n, int nuniq, const int* uniq_node, const int* rec_ptr,
+                               const int* rec_idx, int nrec, const double2* y, double2* out, hipStream_t st);
+hipError_t launch_cg(int mode, size_t n, const double* g, const double* Hp, double* x, double* r, double* p,
+                     double* state, double tol, hipStream_t st);
 hipError_t launch_check_model(size_t n, const double* m, double* out3, hipStream_t st);
 
 }  // namespace hz

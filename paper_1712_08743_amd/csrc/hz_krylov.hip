@@ -1,0 +1,886 @@
+// HIP kernels of the batched Krylov solvers (gfx950): right-preconditioned
+// BiCGSTAB and restarted GMRES(m) over many right-hand sides ("slots") at
+// once, the device-side compaction of the active slot list, and the true
+// residual. Vector kernels stream complex128 vectors with 16-byte accesses,
+// kVecPerThread nodes per thread; per-slot reductions are two-kernel and in
+// a fixed order (see store_partial / sum_partials).
+
+#include "hz_device.h"
+
+namespace hz {
+
+__device__ __forceinline__ bool decode_vec(const Batch& bt, int tiles, int& slot, int& tile) {
+  return decode_block(bt, tiles, slot, tile);
+}
+
+// ---------------------------------------------------------------- BiCGSTAB producers
+__global__ void __launch_bounds__(kBlock) k_copy(Batch bt, int tiles, size_t n,
+                                                 const double2* __restrict__ x,
+                                                 double2* __restrict__ y, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) y[base + i] = x[base + i];
+  }
+}
+
+// x = 0, r = rh = b, p = v = 0; partial ||b||^2.
+__global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt, int tiles, size_t n, Reduce rd,
+                                                      const double2* __restrict__ b,
+                                                      double2* __restrict__ x, double2* __restrict__ r,
+                                                      double2* __restrict__ rh, double2* __restrict__ p,
+                                                      double2* __restrict__ v, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      const double2 bi = b[base + i];
+      const double2 z = c2(0.0, 0.0);
+      x[base + i] = z;
+      r[base + i] = bi;
+      rh[base + i] = bi;
+      p[base + i] = z;
+      v[base + i] = z;
+      acc[0] += bi.x * bi.x + bi.y * bi.y;
+    }
+  }
+  store_partial<1>(acc, rd, slot, tile);
+}
+
+// p_new = r + beta (p_old - omega v)
+__global__ void __launch_bounds__(kBlock) k_bicg_p(Batch bt, int tiles, size_t n,
+                                                   const double2* __restrict__ r,
+                                                   const double2* __restrict__ p_old,
+                                                   const double2* __restrict__ v,
+                                                   double2* __restrict__ p_new, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const Slot& S = bt.slots[slot];
+  const double2 beta = S.beta, om = S.omega;
+  const size_t base = (size_t)slot * stride;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      const double2 t = csub(p_old[base + i], cmul(om, v[base + i]));
+      p_new[base + i] = cadd(r[base + i], cmul(beta, t));
+    }
+  }
+}
+
+// v = B ph; partial <rh, v>.
+template <bool D2>
+__global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Batch bt, Reduce rd,
+                                                             const double2* __restrict__ ph,
+                                                             const double2* __restrict__ rh,
+                                                             double2* __restrict__ v, size_t stride) {
+  int slot, tile;
+  if (!decode_tile(bt, t.per_slot, slot, tile)) return;
+  int iz, ix;
+  tile_node<D2>(t, tile, iz, ix);
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const size_t base = (size_t)slot * stride;
+  double acc[2] = {0.0, 0.0};
+  if (iz < g.nz && ix < g.nx) {
+    const int p = iz * g.nx + ix;
+    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const double2* xs = ph + base;
+    const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
+    v[base + p] = y;
+    const double2 d = cconjmul(rh[base + p], y);
+    acc[0] = d.x;
+    acc[1] = d.y;
+  }
+  store_partial<2>(acc, rd, slot, tile);
+}
+
+// s = r - alpha v
+__global__ void __launch_bounds__(kBlock) k_bicg_s(Batch bt, int tiles, size_t n,
+                                                   const double2* __restrict__ r,
+                                                   const double2* __restrict__ v,
+                                                   double2* __restrict__ s, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const double2 al = bt.slots[slot].alpha;
+  const size_t base = (size_t)slot * stride;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) s[base + i] = csub(r[base + i], cmul(al, v[base + i]));
+  }
+}
+
+// t = B sh; partials <t, s> and <t, t>.
+template <bool D2>
+__global__ void __launch_bounds__(kBlock) k_bicg_apply_omega(Grid g, Tiles t, Batch bt, Reduce rd,
+                                                             const double2* __restrict__ sh,
+                                                             const double2* __restrict__ s,
+                                                             double2* __restrict__ tv, size_t stride) {
+  int slot, tile;
+  if (!decode_tile(bt, t.per_slot, slot, tile)) return;
+  int iz, ix;
+  tile_node<D2>(t, tile, iz, ix);
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const size_t base = (size_t)slot * stride;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (iz < g.nz && ix < g.nx) {
+    const int p = iz * g.nx + ix;
+    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const double2* xs = sh + base;
+    const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
+    tv[base + p] = y;
+    const double2 ts = cconjmul(y, s[base + p]);
+    acc[0] = ts.x;
+    acc[1] = ts.y;
+    acc[2] = y.x * y.x + y.y * y.y;
+  }
+  store_partial<3>(acc, rd, slot, tile);
+}
+
+// x += alpha ph + omega sh; r = s - omega t; partials <rh, r> and ||r||^2.
+__global__ void __launch_bounds__(kBlock) k_bicg_xr(Batch bt, int tiles, size_t n, Reduce rd,
+                                                    double2* __restrict__ x,
+                                                    const double2* __restrict__ ph,
+                                                    const double2* __restrict__ sh,
+                                                    const double2* __restrict__ s,
+                                                    const double2* __restrict__ t,
+                                                    double2* __restrict__ r,
+                                                    const double2* __restrict__ rh, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const Slot& S0 = bt.slots[slot];
+  const double2 al = S0.alpha, om = S0.omega;
+  const size_t base = (size_t)slot * stride;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      const size_t q = base + i;
+      x[q] = cadd(x[q], cadd(cmul(al, ph[q]), cmul(om, sh[q])));
+      const double2 ri = csub(s[q], cmul(om, t[q]));
+      r[q] = ri;
+      const double2 d = cconjmul(rh[q], ri);
+      acc[0] += d.x;
+      acc[1] += d.y;
+      acc[2] += ri.x * ri.x + ri.y * ri.y;
+    }
+  }
+  store_partial<3>(acc, rd, slot, tile);
+}
+
+// The one restart after a breakdown: rh = r, p = v = 0; partial <r, r>.
+__global__ void __launch_bounds__(kBlock) k_bicg_restart(int tiles, size_t n, Batch bt, Reduce rd,
+                                                         const double2* __restrict__ r,
+                                                         double2* __restrict__ rh,
+                                                         double2* __restrict__ p,
+                                                         double2* __restrict__ v, size_t stride) {
+  const int slot = blockIdx.x / tiles;
+  const int tile = blockIdx.x - slot * tiles;
+  if (bt.slots[slot].status != kRestart) return;
+  const size_t base = (size_t)slot * stride;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      const double2 ri = r[base + i];
+      rh[base + i] = ri;
+      p[base + i] = c2(0.0, 0.0);
+      v[base + i] = c2(0.0, 0.0);
+      const double2 d = cconjmul(ri, ri);
+      acc[0] += d.x;
+      acc[1] += d.y;
+    }
+  }
+  store_partial<2>(acc, rd, slot, tile);
+}
+
+// ---------------------------------------------------------------- BiCGSTAB scalars
+// One block per slot: fixed-order sum of the producer's partials, then the
+// scalar step of the method (van der Vorst's BiCGSTAB, right-preconditioned):
+//   init:    bnorm2, rho' = ||b||^2, beta = rho' (rho = alpha = omega = 1)
+//   sigma:   alpha = rho / <rh, v>
+//   omega:   omega = <t, s> / <t, t>
+//   step:    ||r|| test, breakdown / maxit checks, rho' = <rh, r>,
+//            beta = (rho'/rho)(alpha/omega)
+//   restart: rho = beta = <r, r>, rh = r done by the producer
+__global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch bt, Reduce rd,
+                                                     double tol, int maxit) {
+  int slot;
+  if (which == kFinRestart) {
+    slot = blockIdx.x;
+    if (bt.slots[slot].status != kRestart) return;
+  } else if (!decode_slot_block(bt, slot)) {
+    return;
+  }
+  double acc[3];
+  sum_partials<3>(acc, rd, slot, tiles);
+  if (threadIdx.x != 0) return;
+  Slot& S = bt.slots[slot];
+  switch (which) {
+    case kFinInit: {
+      const double b2 = acc[0];
+      S.t0 = wall_clock64();
+      S.t1 = S.t0;
+      S.bnorm2 = b2;
+      S.rnorm2 = b2;
+      S.iters = 0;
+      S.restarted = 0;
+      S.alpha = c2(1.0, 0.0);
+      S.omega = c2(1.0, 0.0);
+      if (!isfinite(b2)) {
+        S.status = kNonfinite;
+      } else if (b2 == 0.0) {
+        S.status = kConverged;
+      } else {
+        S.rho = c2(b2, 0.0);
+        S.beta = c2(b2, 0.0);
+      }
+      break;
+    }
+    case kFinSigma: {
+      const double2 sigma = c2(acc[0], acc[1]);
+      if (!cfinite(sigma)) {
+        S.status = kNonfinite;
+      } else if (czero(sigma)) {
+        S.status = S.restarted ? kBreakdown : kRestart;
+      } else {
+        S.alpha = cdiv(S.rho, sigma);
+      }
+      break;
+    }
+    case kFinOmega: {
+      const double tt = acc[2];
+      const double2 om = tt != 0.0 ? c2(acc[0] / tt, acc[1] / tt) : c2(0.0, 0.0);
+      if (!cfinite(S.alpha) || !cfinite(om)) {
+        S.status = kNonfinite;
+      } else {
+        S.omega = om;
+      }
+      break;
+    }
+    case kFinStep: {
+      S.iters += 1;
+      S.t1 = wall_clock64();
+      S.rnorm2 = acc[2];
+      const double rn = sqrt(acc[2]);
+      const double2 rho_new = c2(acc[0], acc[1]);
+      if (!isfinite(rn)) {
+        S.status = kNonfinite;
+      } else if (rn <= tol * sqrt(S.bnorm2)) {
+        S.status = kConverged;
+      } else if (czero(S.omega)) {
+        S.status = S.restarted ? kBreakdown : (S.iters >= maxit ? kMaxit : kRestart);
+      } else if (S.iters >= maxit) {
+        S.status = kMaxit;
+      } else if (!cfinite(rho_new)) {
+        S.status = kNonfinite;
+      } else if (czero(rho_new)) {
+        S.status = S.restarted ? kBreakdown : kRestart;
+      } else {
+        S.beta = cmul(cdiv(rho_new, S.rho), cdiv(S.alpha, S.omega));
+        S.rho = rho_new;
+      }
+      break;
+    }
+    case kFinRestart: {
+      const double2 rho = c2(acc[0], acc[1]);
+      S.restarted = 1;
+      S.alpha = c2(1.0, 0.0);
+      S.omega = c2(1.0, 0.0);
+      if (!cfinite(rho)) {
+        S.status = kNonfinite;
+      } else if (czero(rho)) {
+        S.status = kBreakdown;
+      } else {
+        S.rho = rho;
+        S.beta = rho;
+        S.status = kActive;
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Rebuild the active list (ascending slot ids of active slots in want_phase)
+// and the host summary.
+__global__ void __launch_bounds__(1024) k_compact(int nslots, int nrhs, int nfreq,
+                                                  const Slot* __restrict__ slots,
+                                                  int* __restrict__ active, int* __restrict__ nactive,
+                                                  int* __restrict__ fstart, Summary* sum, int want_phase) {
+  __shared__ int wsum[16];
+  __shared__ int wres[16];
+  __shared__ int woth[16];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  int nres_local = 0, noth_local = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int b0 = 0; b0 < nslots; b0 += blockDim.x) {
+    const int i = b0 + threadIdx.x;
+    const int st = i < nslots ? slots[i].status : kConverged;
+    const int ph = i < nslots ? slots[i].phase : 0;
+    const int a = (st == kActive) && (ph == want_phase);
+    nres_local += (st == kRestart);
+    noth_local += (st == kActive) && (ph != want_phase);
+    int x = a;  // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int before = carry;
+    for (int w = 0; w < wid; ++w) before += wsum[w];
+    if (a) active[before + x - 1] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
+      carry += tot;
+    }
+    __syncthreads();
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nres_local += __shfl_xor(nres_local, off, 64);
+    noth_local += __shfl_xor(noth_local, off, 64);
+  }
+  if (lane == 0) {
+    wres[wid] = nres_local;
+    woth[wid] = noth_local;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nr = 0, no = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      nr += wres[w];
+      no += woth[w];
+    }
+    *nactive = carry;
+    sum->nactive = carry;
+    sum->nrestart = nr;
+    sum->nother = no;
+  }
+  // per-frequency ranges of the (ascending, frequency-major) list
+  const int total = carry;
+  for (int f = threadIdx.x; f <= nfreq; f += blockDim.x) {
+    const int key = f * nrhs;
+    int lo = 0, hi = total;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (active[mid] < key) lo = mid + 1;
+      else hi = mid;
+    }
+    fstart[f] = lo;
+  }
+}
+
+// ---------------------------------------------------------------- true residual
+template <bool D2>
+__global__ void __launch_bounds__(kBlock) k_true_residual(Grid g, Tiles t, Batch bt, Reduce rd,
+                                                          const double2* __restrict__ b,
+                                                          const double2* __restrict__ x, size_t stride) {
+  // every slot of the list, whatever its status (XCD-aware tile order)
+  const int xcd = blockIdx.x % kXcd, k = blockIdx.x / kXcd;
+  const int chunk = xcd_chunk(t.per_slot);
+  const int si = k / chunk;
+  const int tile = xcd * chunk + (k - si * chunk);
+  if (tile >= t.per_slot || si >= *bt.nactive) return;
+  const int slot = bt.active[si];
+  int iz, ix;
+  tile_node<D2>(t, tile, iz, ix);
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const size_t base = (size_t)slot * stride;
+  double acc[2] = {0.0, 0.0};
+  if (iz < g.nz && ix < g.nx) {
+    const int p = iz * g.nx + ix;
+    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const double2* xs = x + base;
+    const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
+    const double2 bp = b[base + p];
+    const double2 rr = csub(bp, y);
+    acc[0] = rr.x * rr.x + rr.y * rr.y;
+    acc[1] = bp.x * bp.x + bp.y * bp.y;
+  }
+  store_partial<2>(acc, rd, slot, tile);
+}
+
+__global__ void __launch_bounds__(kBlock) k_true_residual_fin(int tiles, Batch bt, Reduce rd,
+                                                              double* __restrict__ out) {
+  const int si = blockIdx.x;
+  if (si >= *bt.nactive) return;
+  const int slot = bt.active[si];
+  double acc[2];
+  sum_partials<2>(acc, rd, slot, tiles);
+  if (threadIdx.x == 0) {
+    out[2 * slot] = acc[0];
+    out[2 * slot + 1] = acc[1];
+  }
+}
+
+// ---------------------------------------------------------------- GMRES(m)
+// Right-preconditioned restarted GMRES, one Arnoldi process per slot, all
+// slots of a cycle in lockstep. The basis vector i of slot s lives at
+// V + i * vstride + s * stride. Orthogonalisation is classical Gram-Schmidt
+// applied twice; every per-slot sum is a fixed-order two-kernel reduction.
+
+// r = b - B x (x = 0 on the first cycle, which also zeroes x) into V_0;
+// partial ||r||^2.
+template <bool D2>
+__global__ void __launch_bounds__(kBlock) k_gm_residual(Grid g, Tiles t, Batch bt, Reduce rd,
+                                                        int first, const double2* __restrict__ b,
+                                                        double2* __restrict__ x,
+                                                        double2* __restrict__ v0, size_t stride) {
+  int slot, tile;
+  if (!decode_tile(bt, t.per_slot, slot, tile)) return;
+  int iz, ix;
+  tile_node<D2>(t, tile, iz, ix);
+  const size_t base = (size_t)slot * stride;
+  double acc[1] = {0.0};
+  if (iz < g.nz && ix < g.nx) {
+    const int p = iz * g.nx + ix;
+    double2 r;
+    if (first) {
+      x[base + p] = c2(0.0, 0.0);
+      r = b[base + p];
+    } else {
+      const FreqTab& f = bt.ft[bt.slots[slot].freq];
+      const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+      const double2* xs = x + base;
+      r = csub(b[base + p], apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]));
+    }
+    v0[base + p] = r;
+    acc[0] = r.x * r.x + r.y * r.y;
+  }
+  store_partial<1>(acc, rd, slot, tile);
+}
+
+// Cycle start: beta = ||r||, g = (beta, 0, ...), or a final status.
+__global__ void __launch_bounds__(kBlock) k_gm_residual_fin(int tiles, Batch bt, Reduce rd, Gmres gm,
+                                                            int first, double tol, int maxit) {
+  int slot;
+  if (!decode_slot_block(bt, slot)) return;
+  double acc[1];
+  sum_partials<1>(acc, rd, slot, tiles);
+  if (threadIdx.x != 0) return;
+  Slot& S = bt.slots[slot];
+  if (first) {
+    S.bnorm2 = acc[0];
+    S.t0 = wall_clock64();
+    S.t1 = S.t0;
+    S.iters = 0;
+    S.restarted = 0;
+  }
+  S.rnorm2 = acc[0];
+  const double beta = sqrt(acc[0]);
+  if (!isfinite(beta)) {
+    S.status = kNonfinite;
+  } else if (S.bnorm2 == 0.0 || beta <= tol * sqrt(S.bnorm2)) {
+    S.status = kConverged;
+  } else if (S.iters >= maxit) {
+    S.status = kMaxit;
+  } else {
+    S.phase = 0;
+    S.cyc_k = 0;
+    S.scal = c2(beta, 0.0);
+    double2* gg = gm.g + (size_t)slot * (gm.m + 1);
+    gg[0] = c2(beta, 0.0);
+    for (int i = 1; i <= gm.m; ++i) gg[i] = c2(0.0, 0.0);
+  }
+}
+
+// v *= 1 / scal (the newest basis vector's norm); a zero norm leaves v alone.
+__global__ void __launch_bounds__(kBlock) k_gm_scale(Batch bt, int tiles, size_t n, double2* __restrict__ v,
+                                                     size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const double d = bt.slots[slot].scal.x;
+  if (d == 0.0) return;
+  const double inv = 1.0 / d;
+  const size_t base = (size_t)slot * stride;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) v[base + i] = cscale(inv, v[base + i]);
+  }
+}
+
+// Partials of h_i = <V_i, w>, i = 0..j, in chunks of 8 basis vectors.
+__global__ void __launch_bounds__(kBlock) k_gm_dots(Batch bt, int tiles, size_t n, Gmres gm, int j,
+                                                    const double2* __restrict__ V, size_t vstride,
+                                                    const double2* __restrict__ w, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+  const int nv = j + 1;
+  const int width = 2 * (gm.m + 1);
+  double* part = gm.partials + ((size_t)slot * gm.max_tiles + tile) * width;
+  for (int c0 = 0; c0 < nv; c0 += 8) {
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int e = 0; e < kVecPerThread; ++e) {
+      const size_t i = vec_index(tile, e);
+      if (i < n) {
+        const double2 wi = w[base + i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (c0 + q < nv) {
+            const double2 d = cconjmul(V[(size_t)(c0 + q) * vstride + base + i], wi);
+            acc[2 * q] += d.x;
+            acc[2 * q + 1] += d.y;
+          }
+        }
+      }
+    }
+    block_sum<16>(acc);
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < 8 && c0 + q < nv; ++q) {
+        part[2 * (c0 + q)] = acc[2 * q];
+        part[2 * (c0 + q) + 1] = acc[2 * q + 1];
+      }
+    }
+  }
+}
+
+// Sums of the dots in tile order: hc[pass] and column j of H (pass 0 sets, pass 1 adds).
+__global__ void __launch_bounds__(kBlock) k_gm_dots_fin(int tiles, Batch bt, Gmres gm, int j, int pass) {
+  int slot;
+  if (!decode_slot_block(bt, slot)) return;
+  const int nv = j + 1;
+  const int width = 2 * (gm.m + 1);
+  const double* src = gm.partials + (size_t)slot * gm.max_tiles * width;
+  double2* hc = gm.hc + ((size_t)slot * 2 + pass) * (gm.m + 1);
+  double2* Hc = gm.H + (size_t)slot * (gm.m + 1) * gm.m + (size_t)j * (gm.m + 1);
+  for (int v = threadIdx.x; v < 2 * nv; v += blockDim.x) {
+    double sum = 0.0;
+    for (int tt = 0; tt < tiles; ++tt) sum += src[(size_t)tt * width + v];
+    const int i = v >> 1;
+    if (v & 1) {
+      hc[i].y = sum;
+      Hc[i].y = pass ? Hc[i].y + sum : sum;
+    } else {
+      hc[i].x = sum;
+      Hc[i].x = pass ? Hc[i].x + sum : sum;
+    }
+  }
+}
+
+// w -= sum_i hc[pass]_i V_i; the second pass also stores the partial ||w||^2.
+__global__ void __launch_bounds__(kBlock) k_gm_orth(Batch bt, int tiles, size_t n, Reduce rd, Gmres gm,
+                                                    int j, int pass, const double2* __restrict__ V,
+                                                    size_t vstride, double2* __restrict__ w, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+  const double2* hc = gm.hc + ((size_t)slot * 2 + pass) * (gm.m + 1);
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      double2 wi = w[base + i];
+      for (int q = 0; q <= j; ++q) wi = csub(wi, cmul(hc[q], V[(size_t)q * vstride + base + i]));
+      w[base + i] = wi;
+      acc[0] += wi.x * wi.x + wi.y * wi.y;
+    }
+  }
+  if (pass) store_partial<1>(acc, rd, slot, tile);
+}
+
+__device__ __forceinline__ void givens(double2 a, double2 b, double& c, double2& s) {
+  const double na = sqrt(a.x * a.x + a.y * a.y), nb = sqrt(b.x * b.x + b.y * b.y);
+  if (nb == 0.0) {
+    c = 1.0;
+    s = c2(0.0, 0.0);
+  } else if (na == 0.0) {
+    c = 0.0;
+    s = c2(1.0, 0.0);
+  } else {
+    const double nu = hypot(na, nb);
+    c = na / nu;
+    // s = (a / |a|) conj(b) / nu
+    const double2 ua = c2(a.x / na, a.y / na);
+    s = cscale(1.0 / nu, cmul(ua, c2(b.x, -b.y)));
+  }
+}
+
+// After the second pass: ||w|| becomes H[j+1, j], the earlier rotations are
+// applied to column j, the new rotation annihilates H[j+1, j] and updates g,
+// and the cycle-end test is made.
+__global__ void __launch_bounds__(kBlock) k_gm_orth_fin(int tiles, Batch bt, Reduce rd, Gmres gm, int j,
+                                                        double tol, int maxit) {
+  int slot;
+  if (!decode_slot_block(bt, slot)) return;
+  double acc[1];
+  sum_partials<1>(acc, rd, slot, tiles);
+  if (threadIdx.x != 0) return;
+  Slot& S = bt.slots[slot];
+  const int m1 = gm.m + 1;
+  double2* Hc = gm.H + (size_t)slot * m1 * gm.m + (size_t)j * m1;
+  double* cs = gm.cs + (size_t)slot * gm.m;
+  double2* sn = gm.sn + (size_t)slot * gm.m;
+  double2* gg = gm.g + (size_t)slot * m1;
+  const double nrm = sqrt(acc[0]);
+  Hc[j + 1] = c2(nrm, 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double2 a = Hc[i], bb = Hc[i + 1];
+    Hc[i] = cadd(cscale(cs[i], a), cmul(sn[i], bb));
+    Hc[i + 1] = csub(cscale(cs[i], bb), cmul(c2(sn[i].x, -sn[i].y), a));
+  }
+  double cj;
+  double2 sj;
+  givens(Hc[j], Hc[j + 1], cj, sj);
+  cs[j] = cj;
+  sn[j] = sj;
+  Hc[j] = cadd(cscale(cj, Hc[j]), cmul(sj, Hc[j + 1]));
+  Hc[j + 1] = c2(0.0, 0.0);
+  const double2 gj = gg[j];
+  gg[j + 1] = cmul(c2(-sj.x, sj.y), gj);  // -conj(s) g_j
+  gg[j] = cscale(cj, gj);
+  S.iters += 1;
+  S.cyc_k = j + 1;
+  S.t1 = wall_clock64();
+  S.scal = c2(nrm, 0.0);
+  const double est = sqrt(gg[j + 1].x * gg[j + 1].x + gg[j + 1].y * gg[j + 1].y);
+  if (!isfinite(est) || !isfinite(nrm)) {
+    S.status = kNonfinite;
+  } else if (est <= tol * sqrt(S.bnorm2) || S.iters >= maxit || j + 1 == gm.m) {
+    S.phase = 1;
+  }
+}
+
+// y = H^-1 g (upper triangular, k = cyc_k), one thread per slot of the list.
+__global__ void k_gm_solve(Batch bt, int cap, Gmres gm) {
+  const int si = blockIdx.x * blockDim.x + threadIdx.x;
+  if (si >= cap || si >= *bt.nactive) return;
+  const int slot = bt.active[si];
+  const Slot& S = bt.slots[slot];
+  if (S.status != kActive) return;
+  const int k = S.cyc_k, m1 = gm.m + 1;
+  const double2* H = gm.H + (size_t)slot * m1 * gm.m;
+  const double2* gg = gm.g + (size_t)slot * m1;
+  double2* y = gm.y + (size_t)slot * gm.m;
+  for (int i = k - 1; i >= 0; --i) {
+    double2 acc = gg[i];
+    for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(H[(size_t)l * m1 + i], y[l]));
+    y[i] = cdiv(acc, H[(size_t)i * m1 + i]);
+  }
+}
+
+// t = sum_{i < cyc_k} y_i V_i
+__global__ void __launch_bounds__(kBlock) k_gm_combine(Batch bt, int tiles, size_t n, Gmres gm,
+                                                       const double2* __restrict__ V, size_t vstride,
+                                                       double2* __restrict__ t, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+  const int k = bt.slots[slot].cyc_k;
+  const double2* y = gm.y + (size_t)slot * gm.m;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      double2 acc = c2(0.0, 0.0);
+      for (int q = 0; q < k; ++q) acc = cadd(acc, cmul(y[q], V[(size_t)q * vstride + base + i]));
+      t[base + i] = acc;
+    }
+  }
+}
+
+// x += z
+__global__ void __launch_bounds__(kBlock) k_axpy1(Batch bt, int tiles, size_t n,
+                                                  const double2* __restrict__ z,
+                                                  double2* __restrict__ x, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) x[base + i] = cadd(x[base + i], z[base + i]);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline dim3 grid1(long long blocks) { return dim3((unsigned)blocks); }
+
+hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,
+                       size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_copy, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, x, y, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd, const double2* b,
+                            double2* x, double2* r, double2* rh, double2* p, double2* v,
+                            size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_bicg_init, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, b, x, r, rh, p, v, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_p(size_t n, const Batch& bt, int cap, const double2* r, const double2* p_old,
+                         const double2* v, double2* p_new, size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_bicg_p, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, r, p_old, v, p_new, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int cap,
+                                   const Reduce& rd, const double2* ph, const double2* rh,
+                                   double2* v, size_t stride, hipStream_t st) {
+  const Tiles t = grid_tiles(g.nz, g.nx, dim);
+  if (cap <= 0) return hipSuccess;
+  const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
+  if (dim == 2)
+    hipLaunchKernelGGL(k_bicg_apply_sigma<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, ph, rh, v, stride);
+  else
+    hipLaunchKernelGGL(k_bicg_apply_sigma<false>, gr, dim3(kBlock), 0, st, g, t, bt, rd, ph, rh, v, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_s(size_t n, const Batch& bt, int cap, const double2* r, const double2* v,
+                         double2* s, size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_bicg_s, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, r, v, s, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int cap,
+                                   const Reduce& rd, const double2* sh, const double2* s,
+                                   double2* t, size_t stride, hipStream_t st) {
+  const Tiles tl = grid_tiles(g.nz, g.nx, dim);
+  if (cap <= 0) return hipSuccess;
+  const dim3 gr = grid1(tile_blocks(tl.per_slot, cap));
+  if (dim == 2)
+    hipLaunchKernelGGL(k_bicg_apply_omega<true>, gr, dim3(kBlock), 0, st, g, tl, bt, rd, sh, s, t, stride);
+  else
+    hipLaunchKernelGGL(k_bicg_apply_omega<false>, gr, dim3(kBlock), 0, st, g, tl, bt, rd, sh, s, t, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, double2* x,
+                          const double2* ph, const double2* sh, const double2* s, const double2* t,
+                          double2* r, const double2* rh, size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_bicg_xr, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, x, ph, sh, s, t, r, rh, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
+                               const double2* r, double2* rh, double2* p, double2* v,
+                               size_t stride, hipStream_t st) {
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_bicg_restart, grid1((long long)nslots * tiles), dim3(kBlock), 0, st, tiles, n, bt, rd, r, rh, p, v, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
+                           double tol, int maxit, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bicg_fin, dim3(cap), dim3(kBlock), 0, st, which, tiles, bt, rd, tol, maxit);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* active, int* nactive,
+                          int* fstart, Summary* sum, int want_phase, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, nslots, nrhs, nfreq, slots, active, nactive, fstart, sum, want_phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_true_residual(int dim, const Grid& g, const Batch& bt, int cap, const Reduce& rd,
+                                const double2* b, const double2* x, double* out, size_t stride,
+                                hipStream_t st) {
+  const Tiles t = grid_tiles(g.nz, g.nx, dim);
+  if (cap <= 0) return hipSuccess;
+  const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
+  if (dim == 2)
+    hipLaunchKernelGGL(k_true_residual<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, b, x, stride);
+  else
+    hipLaunchKernelGGL(k_true_residual<false>, gr, dim3(kBlock), 0, st, g, t, bt, rd, b, x, stride);
+  hipLaunchKernelGGL(k_true_residual_fin, dim3(cap), dim3(kBlock), 0, st, t.per_slot, bt, rd, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_residual(int dim, const Grid& g, const Batch& bt, int cap, const Reduce& rd,
+                              const Gmres& gm, int first, double tol, int maxit, const double2* b,
+                              double2* x, double2* v0, size_t stride, hipStream_t st) {
+  const Tiles t = grid_tiles(g.nz, g.nx, dim);
+  if (cap <= 0) return hipSuccess;
+  const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
+  if (dim == 2)
+    hipLaunchKernelGGL(k_gm_residual<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, first, b, x, v0, stride);
+  else
+    hipLaunchKernelGGL(k_gm_residual<false>, gr, dim3(kBlock), 0, st, g, t, bt, rd, first, b, x, v0, stride);
+  hipLaunchKernelGGL(k_gm_residual_fin, dim3(cap), dim3(kBlock), 0, st, t.per_slot, bt, rd, gm, first, tol, maxit);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_scale(size_t n, const Batch& bt, int cap, double2* v, size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_gm_scale, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, v, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, int pass,
+                          const double2* V, size_t vstride, const double2* w, size_t stride,
+                          hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_gm_dots, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, j, V, vstride, w, stride);
+  hipLaunchKernelGGL(k_gm_dots_fin, dim3(cap), dim3(kBlock), 0, st, tiles, bt, gm, j, pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm, int j,
+                          int pass, double tol, int maxit, const double2* V, size_t vstride, double2* w,
+                          size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_gm_orth, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, gm, j, pass, V, vstride, w, stride);
+  if (pass) hipLaunchKernelGGL(k_gm_orth_fin, dim3(cap), dim3(kBlock), 0, st, tiles, bt, rd, gm, j, tol, maxit);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_solve(const Batch& bt, int cap, const Gmres& gm, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gm_solve, dim3((cap + 63) / 64), dim3(64), 0, st, bt, cap, gm);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_combine(size_t n, const Batch& bt, int cap, const Gmres& gm, const double2* V,
+                             size_t vstride, double2* t, size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_gm_combine, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, V, vstride, t, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy1(size_t n, const Batch& bt, int cap, const double2* z, double2* x, size_t stride,
+                        hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_axpy1, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, z, x, stride);
+  return hipGetLastError();
+}
+
+}  // namespace hz
