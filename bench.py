@@ -15,6 +15,10 @@ Prints one JSON line (see the field list at the end of main()).
   python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
   python bench.py --copy-calibration     # a plain copy kernel of known size,
                                          # for scaling rocprofv3 byte counters
+  python bench.py --serving [--requests R] [--slots S]
+      # serving stream: Poisson arrivals of mixed requests (side 129/257/513,
+      # f ~ U(2, 15) Hz, 1-32 shots), rate set to 80 % of the measured
+      # one-request-at-a-time service rate; p50/p99 latency and solves/s
 """
 
 import argparse
@@ -147,6 +151,107 @@ def copy_calibration():
                       "launches": 5}), flush=True)
 
 
+def serving(args):
+    """Serving stream through the continuous-admission server."""
+    import numpy as np
+    import torch
+    import paper_1712_08743_amd as hz
+    import workloads
+
+    reqs = [workloads.serving_request(r) for r in range(args.requests)]
+    dev = []
+    for w in reqs:
+        n = w.shape[0]
+        b = torch.zeros((1, len(w.src), n, n), dtype=torch.complex128)
+        for k, ix in enumerate(w.src):
+            b[0, k, 0, ix] = 1.0 / w.h ** 2
+        dev.append((torch.from_numpy(w.m).cuda(), b.cuda()))
+    nsolve = sum(len(w.src) for w in reqs)
+    tol = 1e-8
+
+    # one request at a time through one context: the service rate, and the
+    # results every served request must reproduce bit for bit
+    ctx = hz.Context(0)
+    for side in sorted({w.shape[0] for w in reqs}):  # warm up each grid size once
+        k = next(i for i, w in enumerate(reqs) if w.shape[0] == side)
+        ctx.set_model(dev[k][0], reqs[k].h)
+        ctx.solve(reqs[k].freqs, reqs[k].alpha, dev[k][1], tol=tol)
+    torch.cuda.synchronize()
+    alone = []
+    t0 = time.perf_counter()
+    for w, (m, b) in zip(reqs, dev):
+        ctx.set_model(m, w.h)
+        u, _ = ctx.solve(w.freqs, w.alpha, b, tol=tol)
+        alone.append(u)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    ctx.close()
+    print(f"# one at a time: {len(reqs)} requests, {nsolve} solves in {t_seq:.2f} s", file=sys.stderr, flush=True)
+
+    rate = 0.8 * len(reqs) / t_seq
+    arrivals = workloads.poisson_arrivals(len(reqs), rate, seed=7)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    srv = hz.Server(0, budget_bytes=budget, slots=args.slots)
+    tickets = []
+    start = time.perf_counter()
+    for w, (m, b), ta in zip(reqs, dev, arrivals):
+        delay = start + ta - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(m, w.h, w.freqs, w.alpha, b, tol=tol))
+    lat, queued, ends, same, conv = [], [], [], 0, 0
+    for w, tk, ta, ref in zip(reqs, tickets, arrivals, alone):
+        u, info, times = srv.wait(tk)
+        lat.append(times[2])
+        queued.append(times[0])
+        ends.append(ta + times[2])
+        same += int(torch.equal(u, ref))
+        conv += sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED)
+    st = srv.stats()
+    srv.close()
+    makespan = max(ends)
+    out = {
+        "metric": "served Helmholtz solves/s (serving stream), p50/p99 request latency",
+        "value": nsolve / makespan,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream: {len(reqs)} requests, sides 129/257/513, f ~ U(2,15) Hz, "
+                               f"1-32 shots each, layered + Gaussian anomaly, Poisson arrivals at 80 % of the "
+                               f"one-at-a-time service rate, BiCGSTAB tol {tol:g}",
+                   "requests": len(reqs), "solves": nsolve, "slots": args.slots, "budget_bytes": budget,
+                   "arrival_rate_per_s": rate},
+        "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "queued_s": {"p50": percentile(queued, 50), "p99": percentile(queued, 99)},
+        "one_at_a_time_solves_per_s": nsolve / t_seq,
+        "makespan_s": makespan,
+        "converged": conv,
+        "identical_to_alone": same,
+        "peak_running": st["peak_running"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def one_rhs_per_launch(ctx, w, b1, tol, shot=31):
+    """The plain path: one right-hand side per solve call (shot ``shot`` at
+    every frequency of the workload); solves/s averaged over the frequencies,
+    as in the batch."""
+    import torch
+    secs = []
+    for f in w.freqs:
+        bb = b1[shot:shot + 1].reshape((1, 1) + tuple(b1.shape[1:])).contiguous()
+        ctx.solve([f], w.alpha, bb, tol=tol)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve([f], w.alpha, bb, tol=tol)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+    return len(secs) / sum(secs)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +259,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--serving", action="store_true")
+    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--no-single-rhs", action="store_true")
     ap.add_argument("--maxit", type=int, default=10000,
                     help="iteration cap (below convergence only for short hardware-counter runs)")
     args = ap.parse_args()
@@ -163,6 +272,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.serving:
+        serving(args)
         return
 
     import numpy as np
@@ -241,6 +353,11 @@ def main():
                 "launches": n_dom, "avg_launch_ms": ms_dom / max(n_dom, 1),
                 "algorithmic_bytes_per_launch": dom_bytes / max(n_dom, 1)}
 
+    single = None
+    if not args.no_single_rhs and args.maxit >= 10000:
+        print("# timing the one-right-hand-side-per-call path", file=sys.stderr, flush=True)
+        single = one_rhs_per_launch(ctx, w, b1, tol)
+
     cpu = None
     if not args.no_cpu_baseline:
         gpath = os.path.join(ROOT, "tests", "golden", "c3_oracle_iterations.json")
@@ -270,6 +387,7 @@ def main():
         "iterations_mean_per_freq": per_freq_iters,
         "hbm_gbps_step_model": step_bytes / sec / 1e9,
         "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "one_rhs_per_call": None if single is None else {"solves_per_s": single, "speedup": (nrhs / sec) / single},
         "roofline": roofline,
         "kernel_breakdown": breakdown,
         "cpu_baseline": cpu,

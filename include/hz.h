@@ -227,6 +227,56 @@ int  hz_prolong(hz_ctx *c, int level, int nrhs, const hz_c128 *e_dev, hz_c128 *u
 int  hz_precond(hz_ctx *c, const hz_solve_opts *o, double freq_hz, int nrhs,
                 const hz_c128 *b_dev, hz_c128 *u_dev);
 
+/* ---- serving ----------------------------------------------------------------
+ * A server runs solve requests of any grid size, model and frequencies on one
+ * device with continuous admission: a request starts as soon as an execution
+ * slot is free and the device memory of all slots, including the request's
+ * footprint (hz_footprint), fits the budget. Every slot owns a context and a
+ * HIP stream, so admitted requests overlap on the device, and keeps its
+ * workspace from one request to the next (it releases it only when its memory
+ * keeps the next request from fitting). Requests start in submission order.
+ * The result of a request does not depend on the others: the kernels reduce
+ * every right-hand side in a fixed order. */
+
+typedef struct hz_server hz_server;
+
+typedef struct {
+    int    device;
+    size_t hbm_budget_bytes;  /* device memory the slots may hold together; 0 = no limit */
+    int    slots;             /* requests that may run at once (1..64) */
+} hz_server_opts;
+
+typedef struct {
+    int           dim, nz, nx;   /* grid, as in hz_set_model */
+    double        h;
+    const double *m_dev;         /* slowness [nz][nx], device; kept alive by the caller until done */
+    int           nfreq;
+    const double *freq_hz;       /* host, copied at submission */
+    double        alpha;
+    int           nrhs;          /* right-hand sides per frequency */
+    const hz_c128 *b_dev;        /* [nfreq][nrhs][nz][nx], device, kept alive until done */
+    hz_c128      *u_dev;         /* same shape, device, written */
+    const hz_solve_opts *opts;   /* host, copied at submission; NULL = defaults */
+} hz_request;
+
+/* Device memory a solve of this shape holds (host computation, no device). */
+size_t hz_footprint(int dim, int nz, int nx, int nfreq, int nrhs, const hz_solve_opts *o);
+
+/* Errors: HZ_ERR_ARG (bad device or slot count), HZ_ERR_DEVICE. */
+int  hz_server_create(hz_server **out, const hz_server_opts *o);
+/* Runs the queued requests to completion, then releases every slot. */
+void hz_server_destroy(hz_server *s);
+/* Queue a request; *ticket identifies it. HZ_ERR_NOMEM if its footprint
+ * exceeds the budget on its own. */
+int  hz_server_submit(hz_server *s, const hz_request *rq, long long *ticket);
+/* Block until the request is done; info (host, optional) receives
+ * nfreq*nrhs records, times (host, optional) three doubles: seconds queued,
+ * seconds running, latency (submission to completion). Returns the request's
+ * hz_solve status. A ticket can be waited for once. */
+int  hz_server_wait(hz_server *s, long long ticket, hz_rhs_info *info, double *times);
+int  hz_server_stats(hz_server *s, int *queued, int *running, int *peak_running,
+                     size_t *bytes_in_use);
+
 /* ---- measurement --------------------------------------------------------- */
 
 /* kernel classes that can be timed */

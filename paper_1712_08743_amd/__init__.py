@@ -52,6 +52,17 @@ class RhsInfo(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nz", ctypes.c_int), ("nx", ctypes.c_int), ("h", ctypes.c_double),
+                ("m_dev", ctypes.c_void_p), ("nfreq", ctypes.c_int), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
+                ("alpha", ctypes.c_double), ("nrhs", ctypes.c_int), ("b_dev", ctypes.c_void_p),
+                ("u_dev", ctypes.c_void_p), ("opts", ctypes.POINTER(SolveOpts))]
+
+
 _vp, _ip, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
 _i, _d = ctypes.c_int, ctypes.c_double
 
@@ -78,6 +89,12 @@ _SIGS = {
     "hz_precond": (_i, [_vp, ctypes.POINTER(SolveOpts), _d, _i, _vp, _vp]),
     "hz_timing_start": (_i, [_vp, ctypes.c_uint]),
     "hz_timing_read": (_i, [_vp, _i, _ip, _dp]),
+    "hz_footprint": (ctypes.c_size_t, [_i, _i, _i, _i, _i, ctypes.POINTER(SolveOpts)]),
+    "hz_server_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(ServerOpts)]),
+    "hz_server_destroy": (None, [_vp]),
+    "hz_server_submit": (_i, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_longlong)]),
+    "hz_server_wait": (_i, [_vp, ctypes.c_longlong, ctypes.POINTER(RhsInfo), _dp]),
+    "hz_server_stats": (_i, [_vp, _ip, _ip, _ip, ctypes.POINTER(ctypes.c_size_t)]),
     "hz_status_str": (ctypes.c_char_p, [_i]),
     "hz_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -406,6 +423,84 @@ def plan_grid(shape, h, m_min, m_max, freq, **opt):
         raise HzError(rc, "hz_plan_grid failed")
     del keep
     return L.value, [w[i] for i in range(L.value - 1)]
+
+
+def footprint(shape, nfreq, nrhs, **opt):
+    """Device bytes a solve of this shape holds (host computation)."""
+    o, keep = make_opts(**opt)
+    dim = len(shape)
+    nz, nx = (1, shape[0]) if dim == 1 else shape
+    return int(_lib.hz_footprint(dim, nz, nx, nfreq, nrhs, ctypes.byref(o)))
+
+
+class Server:
+    """Continuous-admission solve server (see hz_server_* in include/hz.h).
+
+    submit() queues a request and returns a ticket; wait() returns
+    (u, info, times) with times = (queued s, running s, latency s). Tensors
+    of a request are kept referenced until it is waited for."""
+
+    def __init__(self, device=0, budget_bytes=0, slots=4):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = _lib.hz_server_create(ctypes.byref(h), ctypes.byref(ServerOpts(device, budget_bytes, slots)))
+        if rc != HZ_OK:
+            raise HzError(rc, "hz_server_create failed")
+        self._h = h
+        self._live = {}
+
+    def submit(self, m, h, freqs, alpha, b, **opt):
+        """m: slowness (n,) or (nz, nx); b: complex128 [nfreq, nrhs, *m.shape]."""
+        t = self.torch
+        m = m.to(self.device, t.float64).contiguous()
+        b = b.to(self.device, t.complex128).contiguous()
+        freqs = [float(f) for f in freqs]
+        if b.dim() != m.dim() + 2 or b.shape[0] != len(freqs) or tuple(b.shape[2:]) != tuple(m.shape):
+            raise ValueError("b must be [nfreq, nrhs, *m.shape]")
+        u = t.empty_like(b)
+        o, keep = make_opts(**opt)
+        fa = (ctypes.c_double * len(freqs))(*freqs)
+        dim = m.dim()
+        nz, nx = (1, m.shape[0]) if dim == 1 else (m.shape[0], m.shape[1])
+        rq = Request(dim, nz, nx, float(h), ctypes.c_void_p(m.data_ptr()), len(freqs),
+                     ctypes.cast(fa, ctypes.POINTER(ctypes.c_double)), float(alpha), b.shape[1],
+                     ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(u.data_ptr()), ctypes.pointer(o))
+        tk = ctypes.c_longlong()
+        torch_stream = t.cuda.current_stream(self.device)
+        torch_stream.synchronize()  # inputs written on torch's stream are complete before a slot reads them
+        rc = _lib.hz_server_submit(self._h, ctypes.byref(rq), ctypes.byref(tk))
+        if rc != HZ_OK:
+            raise HzError(rc, "hz_server_submit failed")
+        self._live[tk.value] = (m, b, u, len(freqs) * b.shape[1], keep)
+        return tk.value
+
+    def wait(self, ticket):
+        m, b, u, nrec, keep = self._live.pop(ticket)
+        info = (RhsInfo * nrec)()
+        times = (ctypes.c_double * 3)()
+        rc = _lib.hz_server_wait(self._h, ctypes.c_longlong(ticket), info, times)
+        if rc < 0:
+            raise HzError(rc, "request failed")
+        return u, [(i.status, i.iters, i.relres) for i in info], tuple(times)
+
+    def stats(self):
+        q, r, pk = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        by = ctypes.c_size_t()
+        _lib.hz_server_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(pk), ctypes.byref(by))
+        return {"queued": q.value, "running": r.value, "peak_running": pk.value, "bytes": by.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hz_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Misfit:

@@ -267,7 +267,7 @@ int ensure_workspace(hz_ctx* c, int nslots, int levels) {
       HZ_ALLOC(c, c->lev[l][k], (size_t)nslots * c->lv[l].n() * sizeof(double2));
   // reduction scratch: enough tiles for any kernel on the fine grid
   const Tiles t = grid_tiles(c->lv[0].nz, c->lv[0].nx, c->dim);
-  const int tiles = std::max(t.per_slot, vec_tiles(n0));
+  const int tiles = std::max({t.per_slot, reduce_tiles(c->lv[0].nz, c->lv[0].nx, c->dim), vec_tiles(n0)});
   if (nslots > c->slot_cap || tiles > c->partial_tiles) {
     const int cap = std::max(nslots, c->slot_cap);
     HZ_ALLOC(c, c->partials, (size_t)cap * tiles * kPartialWidth * sizeof(double));
@@ -579,7 +579,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   };
 
   const int vt = vec_tiles(n0);
-  const int gt = grid_tiles(c->lv[0].nz, c->lv[0].nx, c->dim).per_slot;
+  const int gt = reduce_tiles(c->lv[0].nz, c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
   int rc;
   HZ_HIP(c, launch_bicg_init(n0, bt, nslots, rd, b, x, r, rh, p, v, n0, st));
   HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, st));

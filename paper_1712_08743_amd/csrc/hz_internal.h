@@ -101,6 +101,9 @@ struct Tiles {
 Tiles grid_tiles(int nz, int nx, int dim);
 int vec_tiles(size_t n);
 long long tile_blocks(int per_slot, int cap);  // XCD-aware grid size of a 2D-tiled kernel
+int lds_tiles(int nz, int nx);                 // tiles per slot of the LDS-staged 2D kernels
+// tiles per slot of the kernels that store reduction partials over a grid
+int reduce_tiles(int nz, int nx, int dim);
 
 // ---- kernel launchers (hz_kernels.hip) ----------------------------------------
 // All take the stream last and return the launch status.

@@ -42,6 +42,12 @@ Tiles grid_tiles(int nz, int nx, int dim) {
 
 long long tile_blocks(int per_slot, int cap) { return (long long)kXcd * xcd_chunk(per_slot) * cap; }
 
+int lds_tiles(int nz, int nx) { return ((nx + kTX - 1) / kTX) * ((nz + kTZ - 1) / kTZ); }
+
+int reduce_tiles(int nz, int nx, int dim) {
+  return dim == 2 ? lds_tiles(nz, nx) : grid_tiles(nz, nx, dim).per_slot;
+}
+
 int vec_tiles(size_t n) {
   const size_t per = (size_t)kBlock * kVecPerThread;
   return (int)((n + per - 1) / per);
@@ -495,7 +501,10 @@ __global__ void __launch_bounds__(kCoarseWaves * 64) k_coarse(int nc, Batch bt,
       Bs[js][kk] = (sl >= 0 && kk < kend) ? bc[(size_t)sl * stride + k0 + kk] : c2(0.0, 0.0);
     }
     __syncthreads();
-    for (int kk = 0; kk < kend; ++kk) {
+    // columns past nc are zero in both staged blocks, so the fixed trip
+    // count (fully unrolled: LDS reads issue ahead of the FMAs) is exact
+#pragma unroll 8
+    for (int kk = 0; kk < kCoarseK; ++kk) {
       const double2 a = As[kk][lane];
 #pragma unroll
       for (int j = 0; j < kCoarseSlots; ++j) {

@@ -101,6 +101,49 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
   store_partial<2>(acc, rd, slot, tile);
 }
 
+// LDS-tiled forms (2D): x staged on the tile and its halo, two nodes per thread.
+// WHICH 0: v = B ph, partial <rh, v>; WHICH 1: t = B sh, partials <t, s>, <t, t>.
+template <int WHICH>
+__global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int per_slot, Batch bt, Reduce rd,
+                                                         const double2* __restrict__ xin,
+                                                         const double2* __restrict__ other,
+                                                         double2* __restrict__ y, size_t stride) {
+  __shared__ double2 X[kHZ][kHX];
+  int slot, tile;
+  if (!decode_tile(bt, per_slot, slot, tile)) return;
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const TileOrg t = tile_org(tile, ntx);
+  const size_t base = (size_t)slot * stride;
+  const double2* xs = xin + base;
+  fill_halo(X, g, t, [&](int q, int, int) { return xs[q]; });
+  __syncthreads();
+  const double ih = 1.0 / g.h, ih2 = ih * ih;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) {
+    const int lz = threadIdx.x / kTX + (kBlock / kTX) * r, lx = threadIdx.x % kTX;
+    const int iz = t.z0 + lz, ix = t.x0 + lx;
+    if (iz >= g.nz || ix >= g.nx) continue;
+    const int p = iz * g.nx + ix;
+    const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, g.m[p], f.omega, f.sB_re, f.sB_im);
+    double2 sx, sz;
+    halo_sums(X, lz, lx, sx, sz);
+    const double2 yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
+    y[base + p] = yp;
+    if (WHICH == 0) {
+      const double2 d = cconjmul(other[base + p], yp);
+      acc[0] += d.x;
+      acc[1] += d.y;
+    } else {
+      const double2 d = cconjmul(yp, other[base + p]);
+      acc[0] += d.x;
+      acc[1] += d.y;
+      acc[2] += yp.x * yp.x + yp.y * yp.y;
+    }
+  }
+  store_partial<3>(acc, rd, slot, tile);
+}
+
 // s = r - alpha v
 __global__ void __launch_bounds__(kBlock) k_bicg_s(Batch bt, int tiles, size_t n,
                                                    const double2* __restrict__ r,
@@ -748,9 +791,11 @@ hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int 
   const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
-  if (dim == 2)
-    hipLaunchKernelGGL(k_bicg_apply_sigma<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, ph, rh, v, stride);
-  else
+  if (dim == 2) {
+    const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
+    hipLaunchKernelGGL(k_bicg_apply_t<0>, grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per, bt, rd,
+                       ph, rh, v, stride);
+  } else
     hipLaunchKernelGGL(k_bicg_apply_sigma<false>, gr, dim3(kBlock), 0, st, g, t, bt, rd, ph, rh, v, stride);
   return hipGetLastError();
 }
@@ -769,9 +814,11 @@ hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int 
   const Tiles tl = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
   const dim3 gr = grid1(tile_blocks(tl.per_slot, cap));
-  if (dim == 2)
-    hipLaunchKernelGGL(k_bicg_apply_omega<true>, gr, dim3(kBlock), 0, st, g, tl, bt, rd, sh, s, t, stride);
-  else
+  if (dim == 2) {
+    const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
+    hipLaunchKernelGGL(k_bicg_apply_t<1>, grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per, bt, rd,
+                       sh, s, t, stride);
+  } else
     hipLaunchKernelGGL(k_bicg_apply_omega<false>, gr, dim3(kBlock), 0, st, g, tl, bt, rd, sh, s, t, stride);
   return hipGetLastError();
 }

@@ -17,7 +17,7 @@ LIB = os.path.join(ROOT, "paper_1712_08743_amd", "libhz.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const\s+char)\s*\*?\s*(hz_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|size_t|const\s+char)\s*\*?\s*(hz_\w+)\s*\(", text, flags=re.M)))
 
 
 def test_header_declares_the_path():
@@ -80,3 +80,15 @@ def test_host_plan_rejects_bad_input():
         hz.plan_grid((201, 201), 10.0, 1e-3, 5e-4, 5.0)  # m_max < m_min
     with pytest.raises(hz.HzError):
         hz.plan_grid((201, 201), 10.0, 1 / 3000, 1 / 1500, 5.0, levels=9)
+
+
+def test_footprint_grows_with_the_work():
+    import paper_1712_08743_amd as hz
+    f1 = hz.footprint((257, 257), 1, 1)
+    f8 = hz.footprint((257, 257), 1, 8)
+    f8x2 = hz.footprint((257, 257), 2, 8)
+    big = hz.footprint((513, 513), 1, 8)
+    assert 0 < f1 < f8 < f8x2 < big
+    # about 11 fine complex vectors per right-hand side dominate
+    assert 11 * 16 * 257 * 257 * 8 <= f8 <= 20 * 16 * 257 * 257 * 8
+    assert hz.footprint((257, 257), 1, 8, krylov="gmres", gmres_m=30) > f8 + 30 * 16 * 257 * 257 * 8

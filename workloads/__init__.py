@@ -15,7 +15,12 @@ stand in for them:
 * ``model_2d_layered``   2D 401 x 801, h = 10 m, eight horizontal layers
                          1500-4500 m/s with a smooth seeded random
                          perturbation (5 % rms, 200 m correlation), 64
-                         surface shots, frequencies 3/5/8/12 Hz.
+                         surface shots, frequencies 3/5/8/12 Hz;
+* ``serving_request``    one request of a serving stream: square grid of
+                         side 129, 257 or 513 (h = 10 m), layered model with
+                         a Gaussian anomaly, one frequency from U(2, 15) Hz,
+                         1-32 surface shots; ``poisson_arrivals`` gives the
+                         arrival times.
 """
 
 import numpy as np
@@ -97,3 +102,32 @@ def smooth_random_vectors(nvec, shape, seed, sigma=3.0):
         im = gaussian_filter(rng.standard_normal(shape), sigma)
         out.append((re + 1j * im).ravel())
     return np.array(out)
+
+
+def serving_request(rid, sides=(129, 257, 513), h=10.0):
+    """Request ``rid`` of a serving stream (seeded by rid): side from
+    ``sides``, four layers from 1500 m/s down to 1500-3500 m/s, plus a
+    Gaussian anomaly (+-20 %, radius 5-15 % of the side) at a random point;
+    frequency U(2, 15) Hz (at least 10 nodes per wavelength, c >= 1500 m/s
+    and h = 10 m); nrhs U{1..32} shots on the surface row."""
+    rng = np.random.default_rng(1000 + rid)
+    n = int(sides[rng.integers(0, len(sides))])
+    iz = np.arange(n)
+    bottom = rng.uniform(2500.0, 3500.0)
+    layer_v = np.linspace(1500.0, bottom, 4)
+    c = np.repeat(layer_v[np.minimum(iz * 4 // n, 3)][:, None], n, axis=1)
+    z0, x0 = rng.uniform(0.3, 0.8) * (n - 1), rng.uniform(0.2, 0.8) * (n - 1)
+    rad = rng.uniform(0.05, 0.15) * (n - 1)
+    Z, X = np.meshgrid(iz, iz, indexing="ij")
+    c = c * (1.0 + rng.uniform(-0.2, 0.2) * np.exp(-((Z - z0) ** 2 + (X - x0) ** 2) / (2 * rad ** 2)))
+    c = np.maximum(c, 1500.0)
+    nrhs = int(rng.integers(1, 33))
+    src = sorted(int(i) for i in rng.choice(np.arange(2, n - 2), size=nrhs, replace=False))
+    return Workload(name=f"serve-{rid}-{n}", m=1 / c, c=c, h=h, shape=(n, n),
+                    freqs=[float(rng.uniform(2.0, 15.0))], alpha=0.01, src=src, beta=(1.0, 0.5), tol=1e-8)
+
+
+def poisson_arrivals(count, rate, seed=0):
+    """Arrival times (s) of ``count`` requests at ``rate`` per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
