@@ -54,22 +54,23 @@ def level_sizes(shape, levels):
 def bytes_per_iteration(sizes):
     """Algorithmic HBM bytes of one BiCGSTAB iteration of one right-hand side
     with two V(2,2) cycles, as the kernels run it: each complex vector a
-    kernel touches is read or written once (16 B per node), the shared
-    slowness not counted, the dense coarse inverse read once per cycle."""
+    kernel touches is read or written once (16 B per node); the shared
+    slowness and the per-frequency tables are not counted, nor the dense
+    coarse inverse (one copy per frequency, shared by all its right-hand
+    sides and read from cache)."""
     z = 16
     n0 = sizes[0]
-    total = n0 * z * (5 + 4)        # fused p and s updates with their two sweeps
+    total = n0 * z * (5 + 4)        # p and s updates fused with their two pre-sweeps
     total += n0 * z * (3 + 3 + 8)   # B p^, B s^ (with dots), x/r update
     for l, n in enumerate(sizes[:-1]):
         nc = sizes[l + 1]
-        per_cycle = n * z * 2 + nc * z          # residual + restriction
-        per_cycle += n * z * 3 + nc * z         # prolongation + first post-sweep
-        per_cycle += n * z * 3                  # second post-sweep
+        per_cycle = nc * z                      # restricted residual (fused into the pre-sweeps)
+        per_cycle += n * z * 3 + nc * z         # prolongation + both post-sweeps
         if l > 0:
             per_cycle += n * z * 2              # two pre-sweeps from zero (given b)
         total += 2 * per_cycle
     nc = sizes[-1]
-    total += 2 * (2 * nc * z + nc * nc * z)
+    total += 2 * (2 * nc * z)                   # coarse right-hand side in, solution out
     return total
 
 
@@ -79,10 +80,9 @@ def class_bytes_per_iteration(sizes):
     z = 16
     n0, n1 = sizes[0], sizes[1]
     return {
-        "presmooth": n0 * z * (5 + 4),          # reads r, p_old, v / r, v; writes p / s and u2
-        "restrict": 2 * (n0 * z * 2 + n1 * z),  # reads b, u; writes the coarse rhs
+        # reads r, p_old, v / r, v; writes p / s, u2 and the coarse right-hand side
+        "presmooth": n0 * z * (5 + 4) + 2 * n1 * z,
         "prolong": 2 * (n0 * z * 3 + n1 * z),   # reads u2, b, coarse e; writes u
-        "smooth": 2 * n0 * z * 3,               # reads b, u; writes u
         "apply": 2 * n0 * z * 3,                # reads x, shadow/s; writes B x
         "update": n0 * z * 8,                   # reads x, p^, s^, s, t, r^; writes x, r
     }
@@ -337,7 +337,7 @@ def main():
         if k == "coarse" and ms > 0:
             entry["TFLOP/s"] = slot_iters * 2 * 8 * sizes[-1] ** 2 / (ms * 1e-3) / 1e12
         breakdown[k] = entry
-    dom = max((k for k in classes if k in cb), key=lambda k: timing[k][1])
+    dom = max((k for k in classes if k in cb and timing[k][0] > 0), key=lambda k: timing[k][1])
     n_dom, ms_dom = timing[dom]
     dom_bytes = slot_iters * cb[dom]
     achieved = dom_bytes / (ms_dom * 1e-3) / 1e9 if ms_dom > 0 else None

@@ -93,6 +93,12 @@ typedef struct {
     double jacobi_w;        /* largest damped-Jacobi weight the plan may use (default 0.8) */
     const double *jacobi_w_level; /* host, optional: fixed weight per smoothing level
                                      (levels-1 values, every frequency); NULL = plan by LFA */
+    int    autotune;        /* 1 (default): the first launch of a fused V-cycle kernel for a
+                               (kernel, level grid, batch-size octave) times the candidate
+                               launch shapes and keeps the fastest for the context; 0: a
+                               fixed shape. Results do not depend on the shape. */
+    int    chunk_rows;      /* 0 (default): shape from the tuner (or fixed); > 0, even: grid
+                               rows per wavefront for every fused V-cycle kernel */
 } hz_solve_opts;
 
 typedef struct {

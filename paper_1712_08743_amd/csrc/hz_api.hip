@@ -17,6 +17,8 @@
 #include <deque>
 #include <string>
 #include <vector>
+#include <map>
+#include <array>
 
 using namespace hz;
 
@@ -110,6 +112,11 @@ struct hz_ctx {
   std::vector<Pair> tpairs;        // recorded, not yet folded
   long long t_launches[HZ_KERNEL_CLASSES] = {};
   double t_ms[HZ_KERNEL_CLASSES] = {};
+  // launch-shape tuning: rows per wavefront of the fused V-cycle kernels,
+  // keyed by (kernel, nz, nx, batch-size octave)
+  std::map<std::array<int, 4>, int> tuned_chunk;
+  int tune_mode = 1;   // opts.autotune of the running solve
+  int fixed_chunk = 0; // opts.chunk_rows of the running solve
 };
 
 namespace {
@@ -243,6 +250,9 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
           return fail(c, HZ_ERR_ARG, "jacobi_w_level[%d] must be in (0, 1]", l);
     }
   }
+  if (o->chunk_rows < 0 || (o->chunk_rows & 1) || o->chunk_rows > (1 << 16))
+    return fail(c, HZ_ERR_ARG, "chunk_rows must be 0 or an even number up to 65536");
+  if (o->autotune != 0 && o->autotune != 1) return fail(c, HZ_ERR_ARG, "autotune must be 0 or 1");
   if (o->precond == HZ_PRECOND_EXACT) {
     if (c->dim != 1) return fail(c, HZ_ERR_ARG, "the exact preconditioner is the 1D tridiagonal solve");
     const size_t lds = (size_t)4 * c->nx * sizeof(double2);
@@ -434,7 +444,61 @@ void fold_timing(hz_ctx* c) {
 // ---------------------------------------------------------------- V-cycle
 struct Cycle {
   int levels, nu1, nu2, precond;
+  int autotune, chunk_rows;  // launch shape of the fused kernels (opts.autotune, opts.chunk_rows)
 };
+
+// ---------------------------------------------------------------- launch-shape tuning
+// The wave-streaming fused kernels take the number of grid rows each
+// wavefront marches over. Short chunks give more wavefronts (better for small
+// levels and small batches), long ones re-read fewer halo rows. The tuner
+// times every candidate once per (kernel, level grid, batch-size octave) on
+// the real operands, at the first launch with that key, and keeps the
+// fastest. The kernels are pure (they never write what they read), so the
+// trial launches leave the same result as one launch.
+constexpr int kChunkCandidates[] = {8, 16, 32, 64, 128};
+constexpr int kChunkDefault = 32;
+
+int octave(int cap) {
+  int b = 0;
+  while (b < 30 && (2 << b) <= cap) ++b;
+  return b;
+}
+
+template <class F>
+hipError_t tuned_launch(hz_ctx* c, const Cycle& cy, int kind, const Grid& g, int cap, F launch) {
+  if (cy.chunk_rows > 0) return launch(cy.chunk_rows);
+  const std::array<int, 4> key{kind, g.nz, g.nx, octave(cap)};
+  auto it = c->tuned_chunk.find(key);
+  if (it != c->tuned_chunk.end()) return launch(it->second);
+  if (!cy.autotune) return launch(kChunkDefault);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int pick = kChunkDefault;
+  float best = 0.0f;
+  bool have = false;
+  for (int ch : kChunkCandidates) {
+    if (e != hipSuccess) break;
+    if (ch / 2 >= g.nz && ch != kChunkCandidates[0]) break;  // one chunk already covers the grid
+    if ((e = launch(ch)) != hipSuccess) break;               // warm-up
+    if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+    if ((e = launch(ch)) != hipSuccess) break;
+    if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+    if (!have || ms < best) {
+      best = ms;
+      pick = ch;
+      have = true;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  c->tuned_chunk[key] = pick;
+  return launch(pick);
+}
 
 // How the finest level's right-hand side is formed: read (mode 0), or the
 // BiCGSTAB vector p = a + beta (b - omega c) (mode 1) or s = a - alpha b
@@ -472,6 +536,23 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
     double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
     double2* u = nullptr;
+    double2* bc = c->lev[l + 1][kLb].as<double2>();
+    if (cy.nu1 == 2 && dim == 2) {
+      // both pre-sweeps, the residual and its restriction in one pass
+      const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
+      const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
+      const Grid gc = grid_of(c, l + 1);
+      const size_t nc = c->lv[l + 1].n();
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : -2, [&] {
+             return tuned_launch(c, cy, fr.mode, g, cap, [&](int ch) {
+               return launch_pre2r(g, gc, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, X, bc, nl, nc, ch, st);
+             });
+           })) != hipSuccess)
+        return e;
+      cur[l] = X;
+      bl = bc;
+      continue;
+    }
     if (cy.nu1 == 2) {
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
@@ -491,7 +572,6 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       }
     }
     cur[l] = u;
-    double2* bc = c->lev[l + 1][kLb].as<double2>();
     if ((e = timed(c, l == 0 ? HZ_KERNEL_RESTRICT : -2, [&] {
            return launch_restrict(dim, g, grid_of(c, l + 1), bt, cap, bl, u, bc, nl, c->lv[l + 1].n(), st);
          })) != hipSuccess)
@@ -525,14 +605,19 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
         return e;
       continue;
     }
-    // prolongation fused with the first post-sweep
-    double2* dst = (cy.nu2 == 1) ? R : ((u == X) ? Y : X);
+    // prolongation fused with the first post-sweep (2D: with the first two)
+    const int fused = (dim == 2 && cy.nu2 >= 2) ? 2 : 1;
+    double2* dst = (cy.nu2 == fused) ? R : ((u == X) ? Y : X);
     if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
+           if (fused == 2)
+             return tuned_launch(c, cy, 3, g, cap, [&](int ch) {
+               return launch_post2(g, gc, l, bt, cap, ec, bll, u, dst, nl, c->lv[l + 1].n(), ch, st);
+             });
            return launch_prolong_smooth(dim, g, gc, l, bt, cap, ec, bll, u, dst, nl, c->lv[l + 1].n(), st);
          })) != hipSuccess)
       return e;
     u = dst;
-    for (int k = 1; k < cy.nu2; ++k) {
+    for (int k = fused; k < cy.nu2; ++k) {
       double2* d2 = (k == cy.nu2 - 1) ? R : ((u == X) ? Y : X);
       if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : -2, [&] {
              return launch_smooth(dim, g, l, 0.0, bt, cap, bll, u, d2, nl, st);
@@ -849,6 +934,8 @@ void hz_default_opts(hz_solve_opts* o) {
   o->nu2 = 2;
   o->jacobi_w = 0.8;
   o->jacobi_w_level = nullptr;
+  o->autotune = 1;
+  o->chunk_rows = 0;
 }
 
 int hz_create(hz_ctx** out, const hz_ctx_opts* o) {
@@ -1053,7 +1140,7 @@ int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz
   if ((rc = ensure_workspace(c, nslots, levels)) != HZ_OK) return rc;
   if ((rc = setup_freqs(c, o, nfreq, freq_hz, alpha, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nslots, nrhs)) != HZ_OK) return rc;
-  const Cycle cy{levels, o->nu1, o->nu2, o->precond};
+  const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows};
   const double2* b = reinterpret_cast<const double2*>(b_dev);
   double2* x = reinterpret_cast<double2*>(u_dev);
   if (o->krylov == HZ_BICGSTAB) {
@@ -1427,7 +1514,7 @@ int hz_precond(hz_ctx* c, const hz_solve_opts* o, double freq_hz, int nrhs, cons
   if ((rc = ensure_workspace(c, nrhs, levels)) != HZ_OK) return rc;
   if ((rc = setup_freqs(c, o, 1, &freq_hz, 0.0, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nrhs, nrhs)) != HZ_OK) return rc;
-  const Cycle cy{levels, o->nu1, o->nu2, o->precond};
+  const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows};
   HZ_HIP(c, precond_apply(c, cy, nrhs, reinterpret_cast<const double2*>(b_dev), reinterpret_cast<double2*>(u_dev)));
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   return HZ_OK;

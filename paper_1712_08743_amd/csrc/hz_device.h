@@ -220,6 +220,22 @@ __device__ __forceinline__ size_t vec_index(int tile, int e) {
 namespace hz {
 
 // ---------------------------------------------------------------- LDS tiles (2D)
+// The right-hand side b of a V-cycle level, formed on the fly (MODE 0: read,
+// MODE 1: BiCGSTAB p = r + beta (p_old - omega v), MODE 2: s = r - alpha v).
+struct RhsIn {
+  const double2* a;  // b (MODE 0) or r
+  const double2* b;  // p_old (MODE 1) or v (MODE 2)
+  const double2* c;  // v (MODE 1)
+};
+
+template <int MODE>
+__device__ __forceinline__ double2 rhs_at(const RhsIn& in, size_t q, double2 beta, double2 om,
+                                          double2 al) {
+  if (MODE == 0) return in.a[q];
+  if (MODE == 1) return cadd(in.a[q], cmul(beta, csub(in.b[q], cmul(om, in.c[q]))));
+  return csub(in.a[q], cmul(al, in.b[q]));
+}
+
 // A 256-thread block owns a kTX x kTZ tile of nodes; a radius-one stencil
 // stage reads its input from an LDS copy of the tile plus a one-node halo
 // (kHZ x kHX), filled once with coalesced row loads. Halo entries outside

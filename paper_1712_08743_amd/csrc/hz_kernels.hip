@@ -185,22 +185,6 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid gf, Grid gc, Tiles t, B
 }
 
 // ---------------------------------------------------------------- fused multigrid kernels
-// The right-hand side b of a V-cycle level, formed on the fly (MODE 0: read,
-// MODE 1: BiCGSTAB p = r + beta (p_old - omega v), MODE 2: s = r - alpha v).
-struct RhsIn {
-  const double2* a;  // b (MODE 0) or r
-  const double2* b;  // p_old (MODE 1) or v (MODE 2)
-  const double2* c;  // v (MODE 1)
-};
-
-template <int MODE>
-__device__ __forceinline__ double2 rhs_at(const RhsIn& in, size_t q, double2 beta, double2 om,
-                                          double2 al) {
-  if (MODE == 0) return in.a[q];
-  if (MODE == 1) return cadd(in.a[q], cmul(beta, csub(in.b[q], cmul(om, in.c[q]))));
-  return csub(in.a[q], cmul(al, in.b[q]));
-}
-
 // Two damped-Jacobi sweeps from u = 0 in one pass: u1 = w b / D is formed at
 // the node and its neighbours, then u2 = u1 + w (b - M u1) / D. MODE 1/2 also
 // store the Krylov vector they form (into a buffer other than its inputs).

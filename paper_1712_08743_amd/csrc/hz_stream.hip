@@ -1,0 +1,336 @@
+// Wave-streaming forms of the two fused V-cycle kernels on 2D grids.
+//
+// One wavefront owns a strip of 64 consecutive columns (lane = column) and a
+// chunk of rows of one right-hand side, and marches down the rows. Each
+// stage of a kernel runs a fixed number of rows behind the stage it reads,
+// so the z-neighbours of a node are values the lane computed in the last
+// few rows and keeps in registers; x-neighbours come from the adjacent lanes
+// through cross-lane moves. There is no LDS staging and no barrier; the
+// waves of a block are independent. A strip overlaps its neighbours by the
+// stages' combined x-radius (lanes near the strip edge compute values that
+// only the neighbouring strip stores), and a chunk starts and ends the same
+// number of rows early and late. Every load is a contiguous 64-node row.
+//
+// The arithmetic of every node is written exactly as in the LDS-tiled
+// kernels (same operands, same order), so results do not depend on which
+// form runs.
+
+#include "hz_device.h"
+
+namespace hz {
+
+namespace {
+
+constexpr int kLanes = 64;
+
+__device__ __forceinline__ double2 from_left(double2 v) {  // value of lane - 1
+  return make_double2(__shfl_up(v.x, 1, kLanes), __shfl_up(v.y, 1, kLanes));
+}
+__device__ __forceinline__ double2 from_right(double2 v) {  // value of lane + 1
+  return make_double2(__shfl_down(v.x, 1, kLanes), __shfl_down(v.y, 1, kLanes));
+}
+// v where c holds, else zero (selected per component, so no stack copy is made)
+__device__ __forceinline__ double2 keep(bool c, double2 v) {
+  return make_double2(c ? v.x : 0.0, c ? v.y : 0.0);
+}
+
+// One wave of a block: which (slot, strip, chunk) it owns. Blocks are mapped
+// to XCDs as in decode_tile, over groups of four waves.
+struct WaveTile {
+  int slot, z0, z1, xs;
+};
+
+// chunk: rows per wave (even, so that coarse rows split evenly between waves)
+__device__ __forceinline__ bool wave_tile(const Batch& bt, int nstrip, int nchunk, int chunk_rows, int groups,
+                                          int width, int nz, WaveTile& w) {
+  int slot, grp;
+  if (!decode_tile(bt, groups, slot, grp)) return false;
+  const int tile = grp * (kBlock / kLanes) + (int)(threadIdx.x / kLanes);
+  if (tile >= nstrip * nchunk) return false;
+  const int chunk = tile / nstrip, strip = tile - chunk * nstrip;
+  w.slot = slot;
+  w.z0 = chunk * chunk_rows;
+  w.z1 = min(nz, w.z0 + chunk_rows);
+  w.xs = strip * width;  // first column the strip stores
+  return true;
+}
+
+}  // namespace
+
+// The march is unrolled by two rows, and the loads of the next pair of rows
+// are issued before the current pair is computed (software pipelining), so
+// a wave keeps two pairs of rows in flight. Loads are unconditional, from
+// row and column indices clamped into the grid; a value outside the grid is
+// replaced by zero where it is used.
+
+// Pre-smoothing and restriction (see launch_pre2r): per row j of the march,
+// b_j and u1_j = (w/D) b_j are formed, u2 on row j-1 (one damped-Jacobi
+// sweep from u1), the residual r = b - M u2 on row j-2, and, when row j-2 is
+// odd, the full-weighting restriction to coarse row (j-3)/2 from r on rows
+// j-4 .. j-2. x-radius 3 (u2, r, weights), z from z0-3 to z1+2. Lanes
+// 3 .. 60 store: fine columns xs .. xs+57, coarse columns at even x.
+constexpr int kPreWidth = kLanes - 6;
+
+template <int MODE>
+struct PreRow {  // loads of one row: the right-hand side's inputs, w/D and m
+  double2 a, b, c, wd;
+  double m;
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
+                                                    Batch bt, RhsIn in, double2* __restrict__ bout,
+                                                    double2* __restrict__ u2, double2* __restrict__ bc,
+                                                    size_t stride, size_t sc) {
+  WaveTile w;
+  if (!wave_tile(bt, nstrip, nchunk, chunk_rows, groups, kPreWidth, g.nz, w)) return;
+  const int lane = threadIdx.x % kLanes;
+  const Slot& S = bt.slots[w.slot];
+  const FreqTab& f = bt.ft[S.freq];
+  double2 beta = c2(0.0, 0.0), om = c2(0.0, 0.0), al = c2(0.0, 0.0);
+  if (MODE == 1) {
+    beta = S.beta;
+    om = S.omega;
+  }
+  if (MODE == 2) al = S.alpha;
+  const int x = w.xs - 3 + lane;
+  const bool xin = x >= 0 && x < g.nx;
+  const int xx = min(max(x, 0), g.nx - 1);
+  const bool own = lane >= 3 && lane < 3 + kPreWidth && xin;
+  const bool cown = own && !(x & 1);
+  const size_t base = (size_t)w.slot * stride;
+  const double2* wd = f.winv[lvl];
+  const double ih = 1.0 / g.h, ih2 = ih * ih;
+  const double2 zero = c2(0.0, 0.0);
+  auto load_row = [&](int j) {
+    PreRow<MODE> r;
+    const size_t q = (size_t)min(max(j, 0), g.nz - 1) * g.nx + xx;
+    r.a = in.a[base + q];
+    if (MODE != 0) r.b = in.b[base + q];
+    if (MODE == 1) r.c = in.c[base + q];
+    r.wd = wd[q];
+    r.m = g.m[q];
+    return r;
+  };
+  // rolling rows: u1 on j-2, j-1; b, m on j-1, j-2; w/D on j-1; u2 on j-3, j-2; r on j-4, j-3
+  double2 u1a = zero, u1b = zero, b1 = zero, b2 = zero, wd1 = zero, u2a = zero, u2b = zero, ra = zero, rb = zero;
+  double m1 = 0.0, m2 = 0.0;
+  auto step = [&](int j, const PreRow<MODE>& L, bool odd) {
+    const bool jin = xin && j >= 0 && j < g.nz;
+    double2 bj = zero;
+    if (MODE == 0) bj = L.a;
+    if (MODE == 1) bj = cadd(L.a, cmul(beta, csub(L.b, cmul(om, L.c))));
+    if (MODE == 2) bj = csub(L.a, cmul(al, L.b));
+    bj = keep(jin, bj);
+    const double2 wdj = keep(jin, L.wd);
+    const double mj = jin ? L.m : 0.0;
+    const double2 u1c = cmul(bj, wdj);
+    // u2 on row j-1
+    const int i2 = j - 1;
+    double2 u2c = zero;
+    {
+      const double2 sx = cadd(from_left(u1b), from_right(u1b));
+      const NodeC c = node_coef<true>(i2, x, g.nz, g.nx, ih, m1, f.omega, f.sM_re, f.sM_im);
+      const double2 sz = cadd(u1a, u1c);
+      const double2 v = cadd(u1b, cmul(csub(b1, stencil(c, ih2, u1b, sx, sz)), wd1));
+      u2c = keep(xin && i2 >= 0 && i2 < g.nz, v);
+    }
+    if (own && i2 >= w.z0 && i2 < w.z1) {
+      const size_t q = base + (size_t)i2 * g.nx + x;
+      u2[q] = u2c;
+      if (MODE != 0) bout[q] = b1;
+    }
+    // residual on row j-2
+    const int ir = j - 2;
+    double2 rc = zero;
+    {
+      const double2 sx = cadd(from_left(u2b), from_right(u2b));
+      const NodeC c = node_coef<true>(ir, x, g.nz, g.nx, ih, m2, f.omega, f.sM_re, f.sM_im);
+      const double2 sz = cadd(u2a, u2c);
+      const double2 v = csub(b2, stencil(c, ih2, u2b, sx, sz));
+      rc = keep(xin && ir >= 0 && ir < g.nz, v);
+    }
+    // full weighting to coarse row (ir - 1) / 2 once rows ir-2 .. ir are known
+    if (odd) {
+      const int Iz = (ir - 1) / 2;
+      const double2 la = from_left(ra), ga = from_right(ra);
+      const double2 lb = from_left(rb), gb = from_right(rb);
+      const double2 lc = from_left(rc), gc2 = from_right(rc);
+      if (cown && 2 * Iz >= w.z0 && 2 * Iz < w.z1 && Iz < gc.nz) {
+        double2 acc = c2(0.0, 0.0);
+        acc = cadd(acc, cscale(0.5, cadd(ra, cscale(0.5, cadd(la, ga)))));
+        acc = cadd(acc, cscale(1.0, cadd(rb, cscale(0.5, cadd(lb, gb)))));
+        acc = cadd(acc, cscale(0.5, cadd(rc, cscale(0.5, cadd(lc, gc2)))));
+        bc[(size_t)w.slot * sc + (size_t)Iz * gc.nx + (x >> 1)] = cscale(0.25, acc);
+      }
+    }
+    u1a = u1b;
+    u1b = u1c;
+    b2 = b1;
+    b1 = bj;
+    m2 = m1;
+    m1 = mj;
+    wd1 = wdj;
+    u2a = u2b;
+    u2b = u2c;
+    ra = rb;
+    rb = rc;
+  };
+  // rows z0-3 .. z1+2; the first row is odd (z0 even), so pairs are (odd, even)
+  for (int j = w.z0 - 3; j <= w.z1 + 2; j += 2) {
+    const PreRow<MODE> c0 = load_row(j), c1 = load_row(j + 1);
+    step(j, c0, true);
+    step(j + 1, c1, false);
+  }
+}
+
+// Prolongation, correction and two post-sweeps (see launch_post2): per row j,
+// u3 = u2 + P e on row j, the first sweep u4 on row j-1, the second on row
+// j-2, stored. x-radius 2, z from z0-2 to z1+1. Lanes 2 .. 61 store.
+constexpr int kPostWidth = kLanes - 4;
+
+struct PostRow {  // loads of one row j: u2 on j; b, w/D and m on j-1
+  double2 u2, b, wd;
+  double m;
+};
+
+__global__ void __launch_bounds__(kBlock, 4) k_post2_s(Grid gf, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
+                                                    Batch bt, const double2* __restrict__ e,
+                                                    const double2* __restrict__ b,
+                                                    const double2* __restrict__ u2,
+                                                    double2* __restrict__ u_out, size_t sf, size_t sc) {
+  WaveTile w;
+  if (!wave_tile(bt, nstrip, nchunk, chunk_rows, groups, kPostWidth, gf.nz, w)) return;
+  const int lane = threadIdx.x % kLanes;
+  const FreqTab& f = bt.ft[bt.slots[w.slot].freq];
+  const int x = w.xs - 2 + lane;
+  const bool xin = x >= 0 && x < gf.nx;
+  const int xx = min(max(x, 0), gf.nx - 1);
+  const bool own = lane >= 2 && lane < 2 + kPostWidth && xin;
+  const size_t base = (size_t)w.slot * sf;
+  const double2* es = e + (size_t)w.slot * sc;
+  const double2* us = u2 + base;
+  const double2* bs = b + base;
+  const double2* wd = f.winv[lvl];
+  const double ih = 1.0 / gf.h, ih2 = ih * ih;
+  const double2 zero = c2(0.0, 0.0);
+  const int ox = x & 1;
+  const int Jx = xx >> 1, Jx1 = min(Jx + 1, gc.nx - 1);
+  auto load_row = [&](int j) {
+    PostRow r;
+    const int jj = min(max(j, 0), gf.nz - 1), jm = min(max(j - 1, 0), gf.nz - 1);
+    r.u2 = us[(size_t)jj * gf.nx + xx];
+    const size_t q = (size_t)jm * gf.nx + xx;
+    r.b = bs[q];
+    r.wd = wd[q];
+    r.m = gf.m[q];
+    return r;
+  };
+  auto load_coarse = [&](int cr, double2& ea, double2& eb) {
+    const double2* row = es + (size_t)min(max(cr, 0), gc.nz - 1) * gc.nx;
+    ea = row[Jx];
+    eb = row[Jx1];
+  };
+  // rolling rows: u3 on j-2, j-1; u4 on j-3, j-2; b, m, w/D on j-2
+  double2 u3a = zero, u3b = zero, u4a = zero, u4b = zero, b2 = zero, wd2 = zero;
+  double m2 = 0.0;
+  // lo: coarse row j >> 1; hi: the row below it (odd j)
+  auto step = [&](int j, const PostRow& L, double2 loa, double2 lob, double2 hia, double2 hib, bool odd) {
+    double2 u3c;
+    {
+      double2 a = ox ? cscale(0.5, cadd(loa, lob)) : loa;
+      if (odd) {
+        const double2 a2 = ox ? cscale(0.5, cadd(hia, hib)) : hia;
+        a = cscale(0.5, cadd(a, a2));
+      }
+      u3c = keep(xin && j >= 0 && j < gf.nz, cadd(L.u2, a));
+    }
+    // first sweep on row j-1
+    const int i4 = j - 1;
+    const bool in4 = xin && i4 >= 0 && i4 < gf.nz;
+    double2 u4c;
+    {
+      const double2 sx = cadd(from_left(u3b), from_right(u3b));
+      const NodeC c = node_coef<true>(i4, x, gf.nz, gf.nx, ih, L.m, f.omega, f.sM_re, f.sM_im);
+      const double2 sz = cadd(u3a, u3c);
+      const double2 v = cadd(u3b, cmul(csub(L.b, stencil(c, ih2, u3b, sx, sz)), L.wd));
+      u4c = keep(in4, v);
+    }
+    // second sweep on row j-2
+    const int i5 = j - 2;
+    {
+      const double2 sx = cadd(from_left(u4b), from_right(u4b));
+      if (own && i5 >= w.z0 && i5 < w.z1) {
+        const NodeC c = node_coef<true>(i5, x, gf.nz, gf.nx, ih, m2, f.omega, f.sM_re, f.sM_im);
+        const double2 sz = cadd(u4a, u4c);
+        const double2 res = csub(b2, stencil(c, ih2, u4b, sx, sz));
+        u_out[base + (size_t)i5 * gf.nx + x] = cadd(u4b, cmul(res, wd2));
+      }
+    }
+    u3a = u3b;
+    u3b = u3c;
+    u4a = u4b;
+    u4b = u4c;
+    b2 = L.b;
+    wd2 = L.wd;
+    m2 = L.m;
+  };
+  // rows z0-2 .. z1+1 in pairs (even j, odd j+1); the pair uses coarse rows
+  // j/2 (carried from the previous pair) and j/2 + 1 (loaded with the pair)
+  double2 loa, lob;
+  load_coarse((w.z0 - 2) >> 1, loa, lob);
+  for (int j = w.z0 - 2; j <= w.z1 + 1; j += 2) {
+    double2 hia, hib;
+    load_coarse((j >> 1) + 1, hia, hib);
+    const PostRow c0 = load_row(j), c1 = load_row(j + 1);
+    step(j, c0, loa, lob, hia, hib, false);
+    step(j + 1, c1, loa, lob, hia, hib, true);
+    loa = hia;
+    lob = hib;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+namespace {
+struct StreamShape {
+  int nstrip, nchunk, groups;
+};
+StreamShape stream_shape(const Grid& g, int width, int chunk_rows) {
+  StreamShape s;
+  s.nstrip = (g.nx + width - 1) / width;
+  s.nchunk = (g.nz + chunk_rows - 1) / chunk_rows;
+  s.groups = (s.nstrip * s.nchunk + (kBlock / kLanes) - 1) / (kBlock / kLanes);
+  return s;
+}
+}  // namespace
+
+hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const Batch& bt, int cap,
+                        const double2* a, const double2* b, const double2* c, double2* bout, double2* u2,
+                        double2* bcoarse, size_t stride, size_t sc, int chunk_rows, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
+  const StreamShape sh = stream_shape(g, kPreWidth, chunk_rows);
+  const RhsIn in{a, b, c};
+  const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
+#define HZ_PRE2R(M)                                                                                        \
+  hipLaunchKernelGGL((k_pre2r_s<M>), gr, dim3(kBlock), 0, st, g, gc, sh.nstrip, sh.nchunk, chunk_rows,     \
+                     sh.groups, lvl, bt, in, bout, u2, bcoarse, stride, sc)
+  if (mode == 0) HZ_PRE2R(0);
+  else if (mode == 1) HZ_PRE2R(1);
+  else HZ_PRE2R(2);
+#undef HZ_PRE2R
+  return hipGetLastError();
+}
+
+hipError_t launch_post2(const Grid& gf, const Grid& gc, int lvl, const Batch& bt, int cap, const double2* e,
+                        const double2* b, const double2* u2, double2* u_out, size_t sf, size_t sc, int chunk_rows,
+                        hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
+  const StreamShape sh = stream_shape(gf, kPostWidth, chunk_rows);
+  hipLaunchKernelGGL(k_post2_s, dim3((unsigned)tile_blocks(sh.groups, cap)), dim3(kBlock), 0, st, gf, gc,
+                     sh.nstrip, sh.nchunk, chunk_rows, sh.groups, lvl, bt, e, b, u2, u_out, sf, sc);
+  return hipGetLastError();
+}
+
+}  // namespace hz

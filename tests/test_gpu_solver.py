@@ -130,6 +130,24 @@ def test_batch_invariance_bitwise(hz):
     assert torch.equal(u_all[0, 4], u_one4[0, 0])
 
 
+@pytest.mark.parametrize("shape", [(129, 129), (65, 257)])
+def test_launch_shape_invariance_bitwise(hz, shape):
+    """The fused V-cycle kernels give the same bits for every launch shape
+    (rows per wavefront), so the tuner's choice never changes a result."""
+    import torch
+    nz, nx = shape
+    w = workloads.model_2d_layered(nz=nz, nx=nx, h=15.0, nshots=5, freqs=(4.0,))
+    c = make_ctx(hz, w.m, w.h)
+    b = c.point_rhs([0] * 5, w.src)[None]
+    ref, info_ref = c.solve([4.0], 0.01, b, tol=1e-9, autotune=False)
+    for ch in (2, 8, 64, 512):
+        u, info = c.solve([4.0], 0.01, b, tol=1e-9, chunk_rows=ch)
+        assert torch.equal(u, ref), ch
+        assert [i[1] for i in info] == [i[1] for i in info_ref]
+    u, _ = c.solve([4.0], 0.01, b, tol=1e-9, autotune=True)
+    assert torch.equal(u, ref)
+
+
 def test_unpreconditioned_path(hz):
     """No preconditioner: a small, heavily damped problem still converges."""
     w = workloads.model_2d_lens(n=33, h=60.0)
