@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6  # dense FP64 matrix-core (and vector) peak
 METRIC = "Helmholtz solves/s (2D 401x801, 64 RHS), HBM GB/s, p50/p99 solve latency"
 
 
@@ -336,6 +337,7 @@ def main():
             entry["GB/s"] = slot_iters * cb[k] / (ms * 1e-3) / 1e9
         if k == "coarse" and ms > 0:
             entry["TFLOP/s"] = slot_iters * 2 * 8 * sizes[-1] ** 2 / (ms * 1e-3) / 1e12
+            entry["frac_fp64_peak"] = entry["TFLOP/s"] / PEAK_FP64_TFLOPS
         breakdown[k] = entry
     dom = max((k for k in classes if k in cb and timing[k][0] > 0), key=lambda k: timing[k][1])
     n_dom, ms_dom = timing[dom]

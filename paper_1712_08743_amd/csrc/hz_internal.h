@@ -11,10 +11,7 @@ namespace hz {
 constexpr int kMaxLevels = 12;
 constexpr int kBlock = 256;        // threads per block of the grid kernels
 constexpr int kVecPerThread = 4;   // nodes per thread in the pointwise Krylov kernels
-constexpr int kCoarseRows = 64;    // rows of the coarse inverse per block (one per lane)
-constexpr int kCoarseSlots = 4;    // right-hand sides per wave of the coarse solve
-constexpr int kCoarseWaves = 4;    // waves per block (each its own right-hand sides)
-constexpr int kCoarseK = 32;       // columns of the inverse staged in LDS at a time
+constexpr int kCoarseWaves = 4;    // waves per block of the coarse solve (each its own 16-row tile)
 constexpr int kPcrMax = 2048;      // longest 1D grid for the exact tridiagonal solve
 constexpr int kCoarseMax = 16384;  // most unknowns on the coarsest level (dense inverse)
 

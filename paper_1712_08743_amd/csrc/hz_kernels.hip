@@ -444,67 +444,76 @@ __global__ void __launch_bounds__(kRtx * kRtz) k_restrict_tiled(Grid gf, Grid gc
 }
 
 // ---------------------------------------------------------------- coarse solve
-// uc[slot] = Cinv_f bc[slot] for every active slot, one frequency per block
-// (grid z). Cinv is symmetric (M is complex symmetric), so row `row` of it is
-// read as column `row`: Cinv[k][row], coalesced across the 64 lanes. Per step
-// of kCoarseK columns a block (kCoarseWaves waves) stages its 64 rows of Cinv
-// and the matching entries of its right-hand sides in LDS; each wave then
-// multiplies the shared Cinv block into its own kCoarseSlots right-hand sides
-// (LDS broadcasts). Complex FMA work: nc^2 per right-hand side.
+// uc[slot] = Cinv_f bc[slot] for every active slot: per frequency a dense
+// (nc x nc) by (nc x slots) complex product, on the matrix cores. A wave
+// owns a 16-row by 16-slot tile and steps through K four columns at a time
+// with v_mfma_f64_16x16x4f64, forming the complex product from four real
+// ones: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br. Cinv is symmetric (M is
+// complex symmetric), so the A operand (row r, column k) is read as
+// Cinv[k][r]: 16 consecutive entries per k. Operand layout of the
+// instruction: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, and
+// D[i][j] in lane j + 16 (i % 4), register i / 4. Grid: x = groups of
+// kCoarseWaves row tiles, y = tiles of 16 active slots, z = frequency.
+// Each output is a fixed-order sum over K for its own slot, so results do
+// not depend on which other slots share the tile.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(kCoarseWaves * 64) k_coarse(int nc, Batch bt,
                                                               const double2* __restrict__ bc,
                                                               double2* __restrict__ uc, size_t stride) {
-  constexpr int kPer = kCoarseSlots * kCoarseWaves;
-  __shared__ double2 As[kCoarseK][kCoarseRows];
-  __shared__ double2 Bs[kPer][kCoarseK];
-  __shared__ int sslot[kPer];
   const int f = blockIdx.z;
   const int lo = bt.fstart[f], hi = bt.fstart[f + 1];
-  const int gbase = lo + blockIdx.y * kPer;
-  if (gbase >= hi) return;  // uniform over the block
-  const int ntot = min(kPer, hi - gbase);
-  if (threadIdx.x < kPer) sslot[threadIdx.x] = threadIdx.x < ntot ? bt.active[gbase + threadIdx.x] : -1;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int row = blockIdx.x * kCoarseRows + lane;
-  const int j0 = wv * kCoarseSlots;
+  const int s0 = lo + blockIdx.y * 16;
+  if (s0 >= hi) return;  // uniform over the block
+  const int lane = threadIdx.x & 63;
+  const int r0 = (blockIdx.x * kCoarseWaves + (int)(threadIdx.x >> 6)) * 16;
+  if (r0 >= nc) return;  // uniform over the wave
+  const int i = lane & 15, kq = lane >> 4;
+  const int row = min(r0 + i, nc - 1);  // rows past nc give outputs that are not stored
+  const int slot = s0 + i < hi ? bt.active[s0 + i] : -1;
   const double2* Ci = bt.ft[f].cinv;
-  double2 acc[kCoarseSlots];
+  const double2* bs = bc + (size_t)(slot < 0 ? 0 : slot) * stride;
+  v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+  // columns of a slot past the active list read slot 0's data: MFMA columns
+  // are independent and those outputs are never stored
+  auto step = [&](double2 a, double2 b) {
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+  };
+  const int kfull = nc & ~3;
+  constexpr int kU = 8;  // K steps whose operands are loaded together
+  int k0 = 0;
+  for (; k0 + 4 * kU <= kfull; k0 += 4 * kU) {
+    double2 a[kU], b[kU];
 #pragma unroll
-  for (int j = 0; j < kCoarseSlots; ++j) acc[j] = c2(0.0, 0.0);
-  for (int k0 = 0; k0 < nc; k0 += kCoarseK) {
-    const int kend = min(kCoarseK, nc - k0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < kCoarseK * kCoarseRows; e += blockDim.x) {
-      const int kk = e / kCoarseRows, rr = e - kk * kCoarseRows;
-      const int r = blockIdx.x * kCoarseRows + rr;
-      As[kk][rr] = (kk < kend && r < nc) ? Ci[(size_t)(k0 + kk) * nc + r] : c2(0.0, 0.0);
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + 4 * u + kq;
+      a[u] = Ci[(size_t)k * nc + row];
+      b[u] = bs[k];
     }
-    for (int e = threadIdx.x; e < kPer * kCoarseK; e += blockDim.x) {
-      const int js = e / kCoarseK, kk = e - js * kCoarseK;
-      const int sl = sslot[js];
-      Bs[js][kk] = (sl >= 0 && kk < kend) ? bc[(size_t)sl * stride + k0 + kk] : c2(0.0, 0.0);
-    }
-    __syncthreads();
-    // columns past nc are zero in both staged blocks, so the fixed trip
-    // count (fully unrolled: LDS reads issue ahead of the FMAs) is exact
-#pragma unroll 8
-    for (int kk = 0; kk < kCoarseK; ++kk) {
-      const double2 a = As[kk][lane];
 #pragma unroll
-      for (int j = 0; j < kCoarseSlots; ++j) {
-        const double2 bv = Bs[j0 + j][kk];
-        acc[j].x += a.x * bv.x - a.y * bv.y;
-        acc[j].y += a.x * bv.y + a.y * bv.x;
-      }
-    }
+    for (int u = 0; u < kU; ++u) step(a[u], b[u]);
   }
-  if (row < nc) {
-#pragma unroll
-    for (int j = 0; j < kCoarseSlots; ++j) {
-      const int sl = sslot[j0 + j];
-      if (sl >= 0) uc[(size_t)sl * stride + row] = acc[j];
-    }
+  for (; k0 < kfull; k0 += 4) {
+    const int k = k0 + kq;
+    step(Ci[(size_t)k * nc + row], bs[k]);
   }
+  if (kfull < nc) {  // last partial step: columns past nc contribute zero
+    const int k = kfull + kq;
+    const bool ok = k < nc;
+    const int kk = ok ? k : nc - 1;
+    const double2 a = Ci[(size_t)kk * nc + row], b = bs[kk];
+    step(c2(ok ? a.x : 0.0, ok ? a.y : 0.0), c2(ok ? b.x : 0.0, ok ? b.y : 0.0));
+  }
+  const int j = lane & 15, i0 = lane >> 4;
+  if (s0 + j >= hi) return;
+  const int sl = bt.active[s0 + j];
+  double2* us = uc + (size_t)sl * stride;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r0 + i0 + 4 * r < nc) us[r0 + i0 + 4 * r] = c2(cr[r], ci[r]);
 }
 
 // Dense M on the coarsest grid for every frequency: A[f][i][j].
@@ -846,8 +855,8 @@ hipError_t launch_prolong_smooth(int dim, const Grid& gf, const Grid& gc, int lv
 
 hipError_t launch_coarse_solve(int nc, int nfreq, int nrhs, const Batch& bt, const double2* bc,
                                double2* uc, size_t stride, hipStream_t st) {
-  const int per = kCoarseSlots * kCoarseWaves;
-  const dim3 gr((nc + kCoarseRows - 1) / kCoarseRows, (nrhs + per - 1) / per, nfreq);
+  const int row_tiles = (nc + 15) / 16;
+  const dim3 gr((row_tiles + kCoarseWaves - 1) / kCoarseWaves, (nrhs + 15) / 16, nfreq);
   hipLaunchKernelGGL(k_coarse, gr, dim3(kCoarseWaves * 64), 0, st, nc, bt, bc, uc, stride);
   return hipGetLastError();
 }
