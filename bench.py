@@ -22,7 +22,6 @@ Prints one JSON line (see the field list at the end of main()).
 """
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,14 +33,6 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6  # dense FP64 matrix-core (and vector) peak
 METRIC = "Helmholtz solves/s (2D 401x801, 64 RHS), HBM GB/s, p50/p99 solve latency"
-
-
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("hz_kernels.hip", "hz_krylov.hip", "hz_device.h", "hz_internal.h"):
-        with open(os.path.join(ROOT, "paper_1712_08743_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def level_sizes(shape, levels):
@@ -81,10 +72,11 @@ def class_bytes_per_iteration(sizes):
     z = 16
     n0, n1 = sizes[0], sizes[1]
     return {
-        # reads r, p_old, v / r, v; writes p / s, u2 and the coarse right-hand side
-        "presmooth": n0 * z * (5 + 4) + 2 * n1 * z,
-        "prolong": 2 * (n0 * z * 3 + n1 * z),   # reads u2, b, coarse e; writes u
-        "apply": 2 * n0 * z * 3,                # reads x, shadow/s; writes B x
+        "presmooth": n0 * z * 5 + n1 * z,       # reads r, p_old, v; writes p, u2; coarse right-hand side
+        "presmooth_s": n0 * z * 4 + n1 * z,     # reads r, v; writes s, u2; coarse right-hand side
+        "prolong": 2 * (n0 * z * 3 + n1 * z),   # reads u2, b, coarse e; writes u (two V-cycles)
+        "apply": n0 * z * 3,                    # reads p^, r^; writes v
+        "apply_s": n0 * z * 3,                  # reads s^, s; writes t
         "update": n0 * z * 8,                   # reads x, p^, s^, s, t, r^; writes x, r
     }
 
@@ -256,7 +248,7 @@ def one_rhs_per_launch(ctx, w, b1, tol, shot=31):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -303,7 +295,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    classes = ["presmooth", "restrict", "prolong", "smooth", "apply", "update", "coarse"]
+    classes = ["presmooth", "presmooth_s", "restrict", "prolong", "smooth", "apply", "apply_s", "update", "coarse"]
     ctx.timing_start(classes)
     infos, lat = [], []
     torch.cuda.synchronize()
@@ -343,17 +335,25 @@ def main():
     n_dom, ms_dom = timing[dom]
     dom_bytes = slot_iters * cb[dom]
     achieved = dom_bytes / (ms_dom * 1e-3) / 1e9 if ms_dom > 0 else None
+    # measured HBM bytes per launch: counters per right-hand side (from a
+    # committed rocprofv3 --pmc summary of the same kernel sources) times the
+    # right-hand sides an average launch carries here
+    from paper_1712_08743_amd import profiling
+    launches_per_iter = 2 if dom == "prolong" else 1
+    rhs_per_launch = slot_iters * launches_per_iter / max(n_dom, 1)
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "dominant_kernel_traffic.json")
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("kernel_class") == dom:
-            traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        ent = tr.get("classes", {}).get(dom)
+        if tr.get("kernel_source_hash") == profiling.kernel_source_hash() and ent:
+            traffic = (ent["fetch_bytes_per_rhs"] + ent["write_bytes_per_rhs"]) * rhs_per_launch
+    roofline = {"bound": "hbm", "kernel": dom, "symbol": profiling.CLASS_SYMBOL.get(dom),
+                "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": (achieved / PEAK_HBM_GBS) if achieved else None, "traffic": traffic,
                 "launches": n_dom, "avg_launch_ms": ms_dom / max(n_dom, 1),
-                "algorithmic_bytes_per_launch": dom_bytes / max(n_dom, 1)}
+                "algorithmic_bytes_per_launch": dom_bytes / max(n_dom, 1), "rhs_per_launch": rhs_per_launch}
 
     single = None
     if not args.no_single_rhs and args.maxit >= 10000:

@@ -285,16 +285,22 @@ int  hz_server_stats(hz_server *s, int *queued, int *running, int *peak_running,
 
 /* ---- measurement --------------------------------------------------------- */
 
-/* kernel classes that can be timed */
-#define HZ_KERNEL_SMOOTH   0   /* single damped-Jacobi sweep from a nonzero start, finest level */
-#define HZ_KERNEL_APPLY    1   /* operator application with fused dot products, finest level */
-#define HZ_KERNEL_RESTRICT 2   /* residual and restriction, finest level */
-#define HZ_KERNEL_PROLONG  3   /* prolongation and correction (with the first post-sweep), finest level */
+/* kernel classes that can be timed (launches on the finest level) */
+#define HZ_KERNEL_SMOOTH   0   /* one damped-Jacobi sweep from a nonzero start (V-cycles whose
+                                  smoothing is not fused) */
+#define HZ_KERNEL_APPLY    1   /* operator application with fused dot products: B p^ and <r^, v>
+                                  (BiCGSTAB), B z (GMRES) */
+#define HZ_KERNEL_RESTRICT 2   /* residual and restriction (when not fused into the pre-smoothing) */
+#define HZ_KERNEL_PROLONG  3   /* prolongation and correction with the post-sweeps (2D: both) */
 #define HZ_KERNEL_UPDATE   4   /* Krylov iterate and residual update */
 #define HZ_KERNEL_COARSE   5   /* dense coarse solve */
-#define HZ_KERNEL_PRESMOOTH 6  /* right-hand side update and two Jacobi sweeps from zero, finest level */
+#define HZ_KERNEL_PRESMOOTH 6  /* right-hand side (BiCGSTAB: p = r + beta (p - omega v)) and two
+                                  Jacobi sweeps from zero; on 2D grids also the residual and
+                                  its restriction */
+#define HZ_KERNEL_PRESMOOTH_S 7 /* the same for the BiCGSTAB vector s = r - alpha v */
+#define HZ_KERNEL_APPLY_S  8   /* B s^ with <t, s> and <t, t> (BiCGSTAB) */
 
-#define HZ_KERNEL_CLASSES  7
+#define HZ_KERNEL_CLASSES  9
 
 /* Start timing the kernel classes whose bit (1 << HZ_KERNEL_*) is set in
  * mask, resetting all totals (mask 0 stops): every later launch of such a

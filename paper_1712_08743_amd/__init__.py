@@ -28,7 +28,8 @@ HZ_BICGSTAB, HZ_GMRES = 0, 1
 HZ_PRECOND_MG, HZ_PRECOND_EXACT, HZ_PRECOND_NONE = 0, 1, 2
 HZ_RHS_CONVERGED, HZ_RHS_MAXIT, HZ_RHS_BREAKDOWN, HZ_RHS_NONFINITE = 0, 1, 2, 3
 HZ_MAX_LEVELS = 12
-HZ_KERNEL = {"smooth": 0, "apply": 1, "restrict": 2, "prolong": 3, "update": 4, "coarse": 5, "presmooth": 6}
+HZ_KERNEL = {"smooth": 0, "apply": 1, "restrict": 2, "prolong": 3, "update": 4, "coarse": 5, "presmooth": 6,
+             "presmooth_s": 7, "apply_s": 8}
 
 PRECOND = {"mg": HZ_PRECOND_MG, "exact": HZ_PRECOND_EXACT, "none": HZ_PRECOND_NONE}
 KRYLOV = {"bicgstab": HZ_BICGSTAB, "gmres": HZ_GMRES}

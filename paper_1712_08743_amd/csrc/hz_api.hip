@@ -543,7 +543,8 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
       const Grid gc = grid_of(c, l + 1);
       const size_t nc = c->lv[l + 1].n();
-      if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : -2, [&] {
+      const int cls = l > 0 ? -2 : (fr.mode == 2 ? HZ_KERNEL_PRESMOOTH_S : HZ_KERNEL_PRESMOOTH);
+      if ((e = timed(c, cls, [&] {
              return tuned_launch(c, cy, fr.mode, g, cap, [&](int ch) {
                return launch_pre2r(g, gc, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, X, bc, nl, nc, ch, st);
              });
@@ -723,7 +724,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       HZ_HIP(c, launch_bicg_s(n0, bt, cap, r, v, s, n0, st));
       if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, s, sh));
     }
-    HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] {
+    HZ_HIP(c, timed(c, HZ_KERNEL_APPLY_S, [&] {
              return launch_bicg_apply_omega(c->dim, g0, bt, cap, rd, sh, s, t, n0, st);
            }));
     HZ_HIP(c, launch_bicg_fin(kFinOmega, gt, bt, cap, rd, o->tol, o->maxit, st));

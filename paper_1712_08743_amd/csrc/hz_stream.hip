@@ -77,7 +77,9 @@ struct PreRow {  // loads of one row: the right-hand side's inputs, w/D and m
   double m;
 };
 
-template <int MODE>
+// FINE: launched on the finest level (the same code; a separate symbol lets a
+// profiler tell the finest level's launches from the coarser ones)
+template <int MODE, bool FINE>
 __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
                                                     Batch bt, RhsIn in, double2* __restrict__ bout,
                                                     double2* __restrict__ u2, double2* __restrict__ bc,
@@ -194,6 +196,7 @@ struct PostRow {  // loads of one row j: u2 on j; b, w/D and m on j-1
   double m;
 };
 
+template <bool FINE>
 __global__ void __launch_bounds__(kBlock, 4) k_post2_s(Grid gf, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
                                                     Batch bt, const double2* __restrict__ e,
                                                     const double2* __restrict__ b,
@@ -312,12 +315,13 @@ hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const 
   const StreamShape sh = stream_shape(g, kPreWidth, chunk_rows);
   const RhsIn in{a, b, c};
   const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
-#define HZ_PRE2R(M)                                                                                        \
-  hipLaunchKernelGGL((k_pre2r_s<M>), gr, dim3(kBlock), 0, st, g, gc, sh.nstrip, sh.nchunk, chunk_rows,     \
+#define HZ_PRE2R(M, F)                                                                                     \
+  hipLaunchKernelGGL((k_pre2r_s<M, F>), gr, dim3(kBlock), 0, st, g, gc, sh.nstrip, sh.nchunk, chunk_rows,  \
                      sh.groups, lvl, bt, in, bout, u2, bcoarse, stride, sc)
-  if (mode == 0) HZ_PRE2R(0);
-  else if (mode == 1) HZ_PRE2R(1);
-  else HZ_PRE2R(2);
+  if (mode == 1) HZ_PRE2R(1, true);
+  else if (mode == 2) HZ_PRE2R(2, true);
+  else if (lvl == 0) HZ_PRE2R(0, true);
+  else HZ_PRE2R(0, false);
 #undef HZ_PRE2R
   return hipGetLastError();
 }
@@ -328,8 +332,13 @@ hipError_t launch_post2(const Grid& gf, const Grid& gc, int lvl, const Batch& bt
   if (cap <= 0) return hipSuccess;
   if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
   const StreamShape sh = stream_shape(gf, kPostWidth, chunk_rows);
-  hipLaunchKernelGGL(k_post2_s, dim3((unsigned)tile_blocks(sh.groups, cap)), dim3(kBlock), 0, st, gf, gc,
-                     sh.nstrip, sh.nchunk, chunk_rows, sh.groups, lvl, bt, e, b, u2, u_out, sf, sc);
+  const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
+  if (lvl == 0)
+    hipLaunchKernelGGL(k_post2_s<true>, gr, dim3(kBlock), 0, st, gf, gc, sh.nstrip, sh.nchunk, chunk_rows,
+                       sh.groups, lvl, bt, e, b, u2, u_out, sf, sc);
+  else
+    hipLaunchKernelGGL(k_post2_s<false>, gr, dim3(kBlock), 0, st, gf, gc, sh.nstrip, sh.nchunk, chunk_rows,
+                       sh.groups, lvl, bt, e, b, u2, u_out, sf, sc);
   return hipGetLastError();
 }
 

@@ -1,0 +1,204 @@
+"""Summaries of rocprofv3 output for the library's kernels.
+
+    python -m paper_1712_08743_amd.profiling stats TRACE_CSV --command CMD [--out FILE.md]
+    python -m paper_1712_08743_amd.profiling traffic --fetch CSV --write CSV \\
+        --copy-fetch CSV --copy-write CSV --copy-bytes N --rhs R --command CMD \\
+        [--out FILE.md] [--json FILE.json]
+
+``stats`` reads a ``--kernel-trace`` CSV and tabulates, per kernel symbol,
+the launches, total and average duration; the finest-level kernels are named
+by their timing class (``hz_timing_*``). ``traffic`` reads two ``--pmc``
+counter-collection CSVs (FETCH_SIZE, WRITE_SIZE, in KiB per dispatch) of a
+solve whose every launch carries ``R`` right-hand sides, scales each counter
+by what it reads for the library's plain copy kernel of ``N`` bytes read and
+``N`` written, and reports bytes per dispatch and per right-hand side.
+"""
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# timing class -> kernel symbol (finest level)
+CLASS_SYMBOL = {
+    "presmooth": "hz::k_pre2r_s<1, true>",
+    "presmooth_s": "hz::k_pre2r_s<2, true>",
+    "prolong": "hz::k_post2_s<true>",
+    "apply": "hz::k_bicg_apply_t<0>",
+    "apply_s": "hz::k_bicg_apply_t<1>",
+    "update": "hz::k_bicg_xr",
+    "coarse": "hz::k_coarse",
+}
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources; a traffic measurement is valid for it only."""
+    h = hashlib.sha256()
+    for f in ("hz_kernels.hip", "hz_stream.hip", "hz_krylov.hip", "hz_device.h", "hz_internal.h"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def symbol(name):
+    """Kernel symbol without the parameter list and the leading 'void '."""
+    s = name.split("(")[0].strip()
+    return s[5:] if s.startswith("void ") else s
+
+
+def class_of(sym):
+    for k, v in CLASS_SYMBOL.items():
+        if sym == v:
+            return k
+    return ""
+
+
+def window(rows, marker, first, last):
+    """Rows that start at or after the first-th launch of kernel `marker` and
+    before its last-th (1-based), e.g. the timed steps of a benchmark whose
+    every step launches the marker once."""
+    starts = sorted(int(r["Start_Timestamp"]) for r in rows if symbol(r["Kernel_Name"]) == marker)
+    lo = starts[first - 1] if first - 1 < len(starts) else None
+    hi = starts[last - 1] if last - 1 < len(starts) else None
+    return [r for r in rows if (lo is None or int(r["Start_Timestamp"]) >= lo)
+            and (hi is None or int(r["Start_Timestamp"]) < hi)]
+
+
+def stats(trace_csv, between=None):
+    agg = collections.OrderedDict()
+    rows = list(csv.DictReader(open(trace_csv)))
+    if between:
+        rows = window(rows, *between)
+    for r in rows:
+        s = symbol(r["Kernel_Name"])
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6  # ms
+        a = agg.setdefault(s, [0, 0.0])
+        a[0] += 1
+        a[1] += d
+    return sorted(agg.items(), key=lambda kv: -kv[1][1])
+
+
+def counters(csv_path):
+    """kernel symbol -> list of counter values (KiB per dispatch), over the
+    dispatches with the symbol's most frequent grid size (a launch-shape
+    tuner's trial launches of other shapes are left out)."""
+    by = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(csv_path)):
+        by[symbol(r["Kernel_Name"])][int(r["Grid_Size"])].append(float(r["Counter_Value"]))
+    out = {}
+    for sym, grids in by.items():
+        out[sym] = max(grids.values(), key=len)
+    return out
+
+
+def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, rhs):
+    F, W = counters(fetch_csv), counters(write_csv)
+    cF, cW = counters(copy_fetch_csv), counters(copy_write_csv)
+    cf = cF["hz::k_copy"]
+    cw = cW["hz::k_copy"]
+    ffac = copy_bytes / (1024.0 * sum(cf) / len(cf))
+    wfac = copy_bytes / (1024.0 * sum(cw) / len(cw))
+    rows = {}
+    for sym, vals in F.items():
+        wv = W.get(sym, [])
+        if not wv:
+            continue
+        fb = 1024.0 * ffac * sum(vals) / len(vals)
+        wb = 1024.0 * wfac * sum(wv) / len(wv)
+        rows[sym] = {"dispatches": len(vals), "fetch_bytes": fb, "write_bytes": wb,
+                     "fetch_bytes_per_rhs": fb / rhs, "write_bytes_per_rhs": wb / rhs}
+    return {"fetch_factor": ffac, "write_factor": wfac, "kernels": rows}
+
+
+def _whole_run_md(stats_csv, top=15):
+    lines = ["", "Whole run (the `--stats` summary: warm-up, launch-shape trials and every other launch "
+             "included):", "", "| kernel | calls | total ms | average us |", "|---|---:|---:|---:|"]
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows[:top]:
+        lines.append(f"| `{symbol(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) * 1e-6:.1f} | "
+                     f"{float(r['AverageNs']) * 1e-3:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
+def _stats_md(trace_csv, command, between=None):
+    lines = ["# Kernel durations (rocprofv3 --kernel-trace)", "", "Command:", "", "```", command, "```", ""]
+    if between:
+        lines += [f"Launches from the {between[1]}-th launch of `{between[0]}` up to (not including) its "
+                  f"{between[2]}-th.", ""]
+    lines += ["| kernel | timing class | launches | total ms | average us |", "|---|---|---:|---:|---:|"]
+    for s, (n, ms) in stats(trace_csv, between):
+        lines.append(f"| `{s}` | {class_of(s)} | {n} | {ms:.1f} | {1e3 * ms / n:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
+def _traffic_md(t, command, rhs):
+    lines = ["# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)", "",
+             "Commands:", "", "```", command, "```", "",
+             f"Counters are scaled by the library's copy kernel: FETCH_SIZE x {t['fetch_factor']:.4f}, "
+             f"WRITE_SIZE x {t['write_factor']:.4f} (bytes it moves / KiB the counter reads). "
+             f"Every dispatch carries {rhs} right-hand sides. Writes are counted when the L2 writes "
+             "them back, which can be during a later kernel.", "",
+             "| kernel | timing class | dispatches | read MB | write MB | read B/RHS/node | write B/RHS/node |",
+             "|---|---|---:|---:|---:|---:|---:|"]
+    n0 = t.get("nodes", 0)
+    for s, r in sorted(t["kernels"].items(), key=lambda kv: -(kv[1]["fetch_bytes"] + kv[1]["write_bytes"])):
+        per_node = (f"{r['fetch_bytes_per_rhs'] / n0:.1f} | {r['write_bytes_per_rhs'] / n0:.1f}" if n0 else " | ")
+        lines.append(f"| `{s}` | {class_of(s)} | {r['dispatches']} | {r['fetch_bytes'] / 1e6:.1f} | "
+                     f"{r['write_bytes'] / 1e6:.1f} | {per_node} |")
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("trace")
+    a.add_argument("--command", required=True)
+    a.add_argument("--out")
+    a.add_argument("--between", nargs=3, metavar=("KERNEL", "FIRST", "LAST"),
+                   help="only launches between the FIRST-th and LAST-th launch of KERNEL")
+    a.add_argument("--stats-csv", help="the run's --stats kernel summary, appended as a second table")
+    b = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        b.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    b.add_argument("--copy-bytes", type=float, required=True)
+    b.add_argument("--rhs", type=int, required=True)
+    b.add_argument("--nodes", type=int, default=0)
+    b.add_argument("--command", required=True)
+    b.add_argument("--out")
+    b.add_argument("--json")
+    args = ap.parse_args()
+    if args.what == "stats":
+        between = (args.between[0], int(args.between[1]), int(args.between[2])) if args.between else None
+        text = _stats_md(args.trace, args.command, between)
+        if args.stats_csv:
+            text += _whole_run_md(args.stats_csv)
+    else:
+        t = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes, args.rhs)
+        t["nodes"] = args.nodes
+        text = _traffic_md(t, args.command, args.rhs)
+        if args.json:
+            per_class = {}
+            for k, s in CLASS_SYMBOL.items():
+                if s in t["kernels"]:
+                    r = t["kernels"][s]
+                    per_class[k] = {"symbol": s, "fetch_bytes_per_rhs": r["fetch_bytes_per_rhs"],
+                                    "write_bytes_per_rhs": r["write_bytes_per_rhs"]}
+            with open(args.json, "w") as fh:
+                json.dump({"kernel_source_hash": kernel_source_hash(), "fetch_factor": t["fetch_factor"],
+                           "write_factor": t["write_factor"], "rhs_per_dispatch": args.rhs,
+                           "classes": per_class}, fh, indent=1)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text)
+    else:
+        print(text)
+
+
+if __name__ == "__main__":
+    main()
