@@ -15,6 +15,8 @@ Prints one JSON line (see the field list at the end of main()).
   python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
   python bench.py --copy-calibration     # a plain copy kernel of known size,
                                          # for scaling rocprofv3 byte counters
+  python bench.py --compare       # preconditioned vs not, shifts, GMRES vs BiCGSTAB,
+                                  # Gauss-Newton schedules (a report, not a throughput line)
   python bench.py --serving [--requests R] [--slots S]
       # serving stream: Poisson arrivals of mixed requests (side 129/257/513,
       # f ~ U(2, 15) Hz, 1-32 shots), rate set to 80 % of the measured
@@ -228,6 +230,90 @@ def serving(args):
     print(json.dumps(out), flush=True)
 
 
+def compare(args):
+    """The paper's comparisons on synthetic inputs: Krylov iterations and time
+    with and without the shifted-Laplace preconditioner, shift (1, 0.5)
+    against the paper's 1 + j, GMRES(30) against BiCGSTAB (layered
+    401 x 801 model, 4 shots x 4 frequencies); Gauss-Newton convergence with
+    all frequencies inverted together and with low-to-high frequency groups
+    (reduced inversion model), and the Krylov work of one Gauss-Newton
+    iteration with and without the preconditioner."""
+    import numpy as np
+    import torch
+    import paper_1712_08743_amd as hz
+    from paper_1712_08743_amd import fwi
+    import workloads
+
+    out = {"metric": "comparisons (not a throughput line)", "data": "synthetic"}
+    w = workloads.model_2d_layered()
+    ctx = hz.Context(0)
+    ctx.set_model(torch.from_numpy(w.m).cuda(), w.h)
+    shots = [0, 21, 42, 63]
+    b1 = ctx.point_rhs([0] * len(shots), [w.src[s] for s in shots])
+    b = torch.stack([b1] * len(w.freqs)).contiguous()
+    cases = [("bicgstab", "mg", (1.0, 0.5)), ("bicgstab", "mg", (1.0, 1.0)), ("gmres", "mg", (1.0, 0.5)),
+             ("gmres", "mg", (1.0, 1.0)), ("bicgstab", "none", (1.0, 0.5)), ("gmres", "none", (1.0, 0.5))]
+    krylov = []
+    for kr, pre, beta in cases:
+        opt = dict(krylov=kr, precond=pre, beta=beta, tol=1e-8, maxit=args.compare_maxit if pre == "none" else 10000)
+        ctx.solve(w.freqs[:1], w.alpha, b[:1, :1].contiguous(), **dict(opt, maxit=2))  # launch-shape trials
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = ctx.solve(w.freqs, w.alpha, b, **opt)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ns = len(shots)
+        per = {}
+        for k, f in enumerate(w.freqs):
+            blk = info[k * ns:(k + 1) * ns]
+            per[str(f)] = {"iterations_mean": float(np.mean([i[1] for i in blk])),
+                           "converged": sum(1 for i in blk if i[0] == hz.HZ_RHS_CONVERGED)}
+        krylov.append({"krylov": kr, "precond": pre, "shift": list(beta) if pre != "none" else None,
+                       "seconds": sec, "per_freq": per,
+                       "operator_applications_per_rhs": float(np.mean([i[1] for i in info])) *
+                       (2 if kr == "bicgstab" else 1)})
+        print(f"# {kr} {pre} {beta}: {sec:.2f} s", file=sys.stderr, flush=True)
+    out["krylov"] = {"workload": f"2d-layered-401x801, shots {shots} x {w.freqs} Hz, tol 1e-8", "cases": krylov}
+    ctx.close()
+
+    # Gauss-Newton on a reduced inversion model; observed data from the
+    # library's own solves on the true model at tolerance 1e-12
+    g = workloads.model_fwi(nz=151, nx=301)
+    src = [(0, ix) for ix in g.src]
+    rec = [(0, ix) for ix in g.rec]
+    ctx = hz.Context(0)
+    ctx.set_model(torch.from_numpy(g.m), g.h)
+    _, d_obs, _ = ctx.misfit(g.freqs, g.alpha, src, rec,
+                             torch.zeros((len(g.freqs), len(src), len(rec)), dtype=torch.complex128), 0.0,
+                             tol=1e-12)
+    d_obs = d_obs.cpu()
+    gn = {}
+    for name, kw in (("simultaneous", dict(schedule="simultaneous", gn_iters=4)),
+                     ("sequential", dict(schedule="sequential", groups=[[0, 1], [2, 3], [4, 5]], gn_iters=2))):
+        t0 = time.perf_counter()
+        _, hist = fwi.invert(ctx, g.m_start, g.h, g.freqs, g.alpha, src, rec, d_obs, g.lam, cg_iters=5,
+                             m_true=g.m, tol=1e-8, **kw)
+        gn[name] = {"seconds": time.perf_counter() - t0, "history": hist}
+        print(f"# gauss-newton {name}: {gn[name]['seconds']:.1f} s", file=sys.stderr, flush=True)
+    work = {}
+    for pre in ("mg", "none"):
+        ctx.set_model(torch.from_numpy(g.m_start), g.h)
+        t0 = time.perf_counter()
+        dm, J, it, info = ctx.gn_step(g.freqs, g.alpha, src, rec, d_obs, g.lam, 1, precond=pre, tol=1e-8,
+                                      maxit=args.compare_maxit)
+        torch.cuda.synchronize()
+        work[pre] = {"seconds": time.perf_counter() - t0,
+                     "forward_krylov_iterations_mean": float(np.mean([i[1] for i in info])),
+                     "forward_converged": sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED),
+                     "forward_solves": len(info)}
+    ctx.close()
+    out["gauss_newton"] = {"workload": f"fwi-151x301, {len(src)} shots, {len(rec)} receivers, {g.freqs} Hz, "
+                                       f"lambda {g.lam}, 5 CG iterations per step (1 in the "
+                                       f"with/without-preconditioner step)",
+                           "schedules": gn, "one_step_with_and_without_preconditioner": work}
+    print(json.dumps(out), flush=True)
+
+
 def one_rhs_per_launch(ctx, w, b1, tol, shot=31):
     """The plain path: one right-hand side per solve call (shot ``shot`` at
     every frequency of the workload); solves/s averaged over the frequencies,
@@ -256,6 +342,8 @@ def main():
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-single-rhs", action="store_true")
+    ap.add_argument("--compare", action="store_true")
+    ap.add_argument("--compare-maxit", type=int, default=20000)
     ap.add_argument("--maxit", type=int, default=10000,
                     help="iteration cap (below convergence only for short hardware-counter runs)")
     args = ap.parse_args()
@@ -268,6 +356,9 @@ def main():
         return
     if args.serving:
         serving(args)
+        return
+    if args.compare:
+        compare(args)
         return
 
     import numpy as np

@@ -16,6 +16,11 @@ stand in for them:
                          1500-4500 m/s with a smooth seeded random
                          perturbation (5 % rms, 200 m correlation), 64
                          surface shots, frequencies 3/5/8/12 Hz;
+* ``model_fwi``          2D 301 x 601, h = 10 m, three units 1800/2600/3500 m/s
+                         split by two dipping interfaces plus a seeded
+                         elliptical low-velocity lens; starting model = the
+                         true slowness smoothed with a 400 m Gaussian; 32
+                         surface shots, 151 surface receivers, 3-12 Hz;
 * ``serving_request``    one request of a serving stream: square grid of
                          side 129, 257 or 513 (h = 10 m), layered model with
                          a Gaussian anomaly, one frequency from U(2, 15) Hz,
@@ -85,6 +90,38 @@ def model_2d_layered(nz=401, nx=801, h=10.0, seed=0, nshots=64,
     src = [int(i) for i in ix]  # surface row iz = 0: flat index = ix
     return Workload(name=f"2d-layered-{nz}x{nx}", m=1 / c, c=c, h=h, shape=(nz, nx),
                     freqs=list(freqs), alpha=0.01, src=src, beta=(1.0, 0.5), tol=1e-8)
+
+
+def model_fwi(nz=301, nx=601, h=10.0, seed=0):
+    """True and starting models of a Gauss-Newton FWI test. Interfaces: depth
+    800 m -> 1200 m and 2000 m -> 1600 m linearly across x; units 1800, 2600
+    and 3500 m/s; a lens (-300 m/s, semi-axes 600 m in x and 150 m in z,
+    centre drawn from the seed inside the middle unit). Shots at
+    ix = 21 + 18 k (k < 32), receivers at ix = 4 r (r < 151), all on the
+    surface row, for the full grid; spread evenly on smaller grids."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx) * h
+    z = np.arange(nz) * h
+    Z, X = np.meshgrid(z, x, indexing="ij")
+    L = (nx - 1) * h
+    d1 = (800.0 + 400.0 * X / L) * (nz - 1) * h / 3000.0
+    d2 = (2000.0 - 400.0 * X / L) * (nz - 1) * h / 3000.0
+    c = np.where(Z < d1, 1800.0, np.where(Z < d2, 2600.0, 3500.0))
+    xc = rng.uniform(0.35, 0.65) * L
+    zc = 0.5 * (d1 + d2)[0, int(round(xc / h))] + rng.uniform(-0.05, 0.05) * (nz - 1) * h
+    ax, az = 600.0 * L / 6000.0, 150.0 * (nz - 1) * h / 3000.0
+    c = np.where(((X - xc) / ax) ** 2 + ((Z - zc) / az) ** 2 <= 1.0, c - 300.0, c)
+    m_true = 1.0 / c
+    m_start = gaussian_filter(m_true, sigma=400.0 / h, mode="nearest")
+    if nx == 601:
+        src = [21 + 18 * k for k in range(32)]
+        rec = [4 * r for r in range(151)]
+    else:
+        src = [int(i) for i in np.round(np.linspace(0.035 * (nx - 1), 0.965 * (nx - 1), 32))]
+        rec = [int(i) for i in np.round(np.linspace(0, nx - 1, min(151, nx)))]
+    return Workload(name=f"fwi-{nz}x{nx}", m=m_true, m_start=m_start, c=c, h=h, shape=(nz, nx),
+                    freqs=[3.0, 4.0, 6.0, 8.0, 10.0, 12.0], alpha=0.01, src=src, rec=rec, lam=1e-3,
+                    beta=(1.0, 0.5), tol=1e-8)
 
 
 def random_vectors(nvec, size, seed):
