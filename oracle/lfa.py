@@ -53,12 +53,32 @@ def smoothing_factor_sampled(kh, beta1, beta2, w, dim=2, n=129):
     return float(a[hi].max())
 
 
+COARSE_TARGET = 2048  # unknowns on the coarsest level a default plan aims below
+
+
 def max_levels(shape):
-    """Largest level count the grid allows (coarsest axis at least 3 nodes)."""
+    """Largest level count the grid allows: halve (n -> ceil(n / 2)) while
+    every axis keeps at least 3 nodes."""
     L = 1
     cur = list(shape)
-    while all((n - 1) % 2 == 0 and (n - 1) // 2 + 1 >= 3 for n in cur):
-        cur = [(n - 1) // 2 + 1 for n in cur]
+    while all(n >= 5 for n in cur):
+        cur = [(n + 1) // 2 for n in cur]
+        L += 1
+    return L
+
+
+def default_levels(shape):
+    """Levels of a default plan: halve while every axis has an odd node count
+    (fine and coarse grids share both ends); then, while the coarsest level
+    has more than COARSE_TARGET unknowns, keep halving with the even-count
+    rule (see multigrid.coarse_size)."""
+    L = 1
+    cur = list(shape)
+    while all(n >= 5 and n % 2 == 1 for n in cur):
+        cur = [(n + 1) // 2 for n in cur]
+        L += 1
+    while int(np.prod(cur)) > COARSE_TARGET and all(n >= 5 for n in cur):
+        cur = [(n + 1) // 2 for n in cur]
         L += 1
     return L
 
@@ -66,7 +86,7 @@ def max_levels(shape):
 def plan(shape, h, omega, m_min, m_max, beta1, beta2, w_default=0.8, levels=0):
     """Return (levels, [w_0, ..., w_{L-2}]) for one frequency."""
     dim = len(shape)
-    L = levels if levels > 0 else max_levels(shape)
+    L = levels if levels > 0 else default_levels(shape)
     weights = []
     for l in range(L - 1):
         hl = h * 2.0 ** l

@@ -26,13 +26,23 @@ from .operator import operator_M
 from .direct import factor_superlu
 
 
+def coarse_size(n):
+    """Nodes of the next coarser grid along an axis: coarse node J sits on
+    fine node 2J. With an odd node count the two grids share both ends; with
+    an even count the last fine node has no coarse partner and is
+    interpolated from the last coarse node alone (the coarse grid then ends
+    one fine spacing short of the fine boundary)."""
+    return (n + 1) // 2
+
+
 def coarse_shape(shape):
-    """Shape of the next coarser grid; raises if an axis cannot be halved."""
+    """Shape of the next coarser grid; raises if an axis would drop below
+    three nodes."""
     out = []
     for n in shape:
-        if (n - 1) % 2 or (n - 1) // 2 + 1 < 3:
+        if n < 5:
             raise ValueError(f"grid axis {n} cannot be coarsened")
-        out.append((n - 1) // 2 + 1)
+        out.append(coarse_size(n))
     return tuple(out)
 
 
@@ -42,33 +52,43 @@ def inject(m):
     return m[::2] if m.ndim == 1 else m[::2, ::2]
 
 
-def linear_interp_1d(nc):
-    """(2 nc - 1) x nc linear interpolation: copy at even, average at odd."""
-    nf = 2 * (nc - 1) + 1
+def linear_interp_1d(nc, nf=None):
+    """nf x nc linear interpolation: copy at even fine nodes, average of the
+    two neighbours at odd ones; an odd fine node with no right coarse
+    neighbour (the last node of an even count) copies the last coarse value."""
+    if nf is None:
+        nf = 2 * (nc - 1) + 1
+    if nf not in (2 * nc - 1, 2 * nc):
+        raise ValueError("fine axis must have 2 nc - 1 or 2 nc nodes")
     rows, cols, vals = [], [], []
-    for I in range(nc):
-        rows.append(2 * I)
-        cols.append(I)
-        vals.append(1.0)
-    for I in range(nc - 1):
-        rows += [2 * I + 1, 2 * I + 1]
-        cols += [I, I + 1]
-        vals += [0.5, 0.5]
+    for i in range(nf):
+        I = i // 2
+        if i % 2 == 0:
+            rows.append(i), cols.append(I), vals.append(1.0)
+        elif I + 1 < nc:
+            rows += [i, i]
+            cols += [I, I + 1]
+            vals += [0.5, 0.5]
+        else:
+            rows.append(i), cols.append(I), vals.append(1.0)
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
 
 
-def prolongation(coarse):
-    """Bilinear (2D) or linear (1D) prolongation from a coarse grid shape."""
+def prolongation(coarse, fine=None):
+    """Bilinear (2D) or linear (1D) prolongation from a coarse grid shape to
+    the fine shape (default: the odd-count fine grid 2 nc - 1)."""
+    if fine is None:
+        fine = tuple(2 * (n - 1) + 1 for n in coarse)
     if len(coarse) == 1:
-        return linear_interp_1d(coarse[0])
+        return linear_interp_1d(coarse[0], fine[0])
     nzc, nxc = coarse
     # flat order iz * nx + ix: z is the slow (outer) factor of the Kronecker product
-    return sp.kron(linear_interp_1d(nzc), linear_interp_1d(nxc)).tocsr()
+    return sp.kron(linear_interp_1d(nzc, fine[0]), linear_interp_1d(nxc, fine[1])).tocsr()
 
 
-def restriction(coarse):
+def restriction(coarse, fine=None):
     """R = 2^-dim P^T (full weighting in the interior)."""
-    return (prolongation(coarse).T * (0.5 ** len(coarse))).tocsr()
+    return (prolongation(coarse, fine).T * (0.5 ** len(coarse))).tocsr()
 
 
 class VCycle:
@@ -97,8 +117,8 @@ class VCycle:
             self.D.append(Ml.diagonal())
             if l < levels - 1:
                 cs = coarse_shape(ml.shape)
-                self.P.append(prolongation(cs))
-                self.R.append(restriction(cs))
+                self.P.append(prolongation(cs, ml.shape))
+                self.R.append(restriction(cs, ml.shape))
                 ml, hl = inject(ml), 2 * hl
         self.coarse_lu = factor_superlu(self.M[-1])
         self.levels = levels

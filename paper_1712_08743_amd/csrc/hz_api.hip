@@ -172,24 +172,53 @@ double smoothing_factor(double kh, double b1, double b2, double w, int dim) {
 const double kWeights[] = {0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2};
 constexpr int kKhSamples = 65;
 
-// Largest level count a grid allows: halve while every axis has n - 1 even
-// and at least 3 nodes after halving.
+}  // namespace
+
+namespace hz {
+
+// Level hierarchy. An axis of n nodes halves to ceil(n / 2): coarse node J
+// sits on fine node 2J; with an even n the last fine node has no coarse
+// partner and is interpolated from the last coarse node alone.
+int coarse_n(int n) { return (n + 1) / 2; }
+
+// Largest level count a grid allows: halve while every axis keeps >= 3 nodes.
 int grid_max_levels(int dim, int nz, int nx) {
   int L = 1;
-  while (L < kMaxLevels) {
-    const bool okx = (nx - 1) % 2 == 0 && (nx - 1) / 2 + 1 >= 3;
-    const bool okz = dim == 1 || ((nz - 1) % 2 == 0 && (nz - 1) / 2 + 1 >= 3);
-    if (!okx || !okz) break;
-    nx = (nx - 1) / 2 + 1;
-    if (dim == 2) nz = (nz - 1) / 2 + 1;
+  while (L < kMaxLevels && nx >= 5 && (dim == 1 || nz >= 5)) {
+    nx = coarse_n(nx);
+    if (dim == 2) nz = coarse_n(nz);
     ++L;
   }
   return L;
 }
 
-int plan_grid(int dim, int maxlev, double h, double mmin, double mmax, const hz_solve_opts* o,
+constexpr long kCoarseTarget = 2048;
+
+// Levels of a default plan: halve while every axis has an odd node count,
+// then keep halving while the coarsest level has more than kCoarseTarget
+// unknowns (its dense inverse grows as the square of that).
+int grid_default_levels(int dim, int nz, int nx) {
+  int L = 1;
+  while (L < kMaxLevels && nx >= 5 && nx % 2 == 1 && (dim == 1 || (nz >= 5 && nz % 2 == 1))) {
+    nx = coarse_n(nx);
+    if (dim == 2) nz = coarse_n(nz);
+    ++L;
+  }
+  while (L < kMaxLevels && (long)nx * nz > kCoarseTarget && nx >= 5 && (dim == 1 || nz >= 5)) {
+    nx = coarse_n(nx);
+    if (dim == 2) nz = coarse_n(nz);
+    ++L;
+  }
+  return L;
+}
+
+}  // namespace hz
+
+namespace {
+
+int plan_grid(int dim, int maxlev, int deflev, double h, double mmin, double mmax, const hz_solve_opts* o,
               double omega, int* levels, double* w) {
-  int L = o->levels > 0 ? o->levels : maxlev;
+  int L = o->levels > 0 ? o->levels : deflev;
   if (L > maxlev) return HZ_ERR_SHAPE;
   *levels = L;
   for (int l = 0; l < L - 1; ++l) {
@@ -222,7 +251,8 @@ int plan_grid(int dim, int maxlev, double h, double mmin, double mmax, const hz_
 }
 
 int make_plan(const hz_ctx* c, const hz_solve_opts* o, double omega, int* levels, double* w) {
-  return plan_grid(c->dim, c->maxlev, c->h, c->mmin, c->mmax, o, omega, levels, w);
+  return plan_grid(c->dim, c->maxlev, grid_default_levels(c->dim, c->nz, c->nx), c->h, c->mmin, c->mmax, o, omega,
+                   levels, w);
 }
 
 int check_opts(hz_ctx* c, const hz_solve_opts* o) {
@@ -244,7 +274,7 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
     if (o->levels > c->maxlev)
       return fail(c, HZ_ERR_SHAPE, "grid %dx%d allows at most %d levels", c->nz, c->nx, c->maxlev);
     if (o->jacobi_w_level) {
-      const int L = o->levels > 0 ? o->levels : c->maxlev;
+      const int L = o->levels > 0 ? o->levels : grid_default_levels(c->dim, c->nz, c->nx);
       for (int l = 0; l < L - 1; ++l)
         if (!(o->jacobi_w_level[l] > 0.0 && o->jacobi_w_level[l] <= 1.0))
           return fail(c, HZ_ERR_ARG, "jacobi_w_level[%d] must be in (0, 1]", l);
@@ -1030,12 +1060,10 @@ int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_d
   int L = 1;
   while (L < kMaxLevels) {
     const LevelInfo& f = c->lv[L - 1];
-    const bool okx = (f.nx - 1) % 2 == 0 && (f.nx - 1) / 2 + 1 >= 3;
-    const bool okz = dim == 1 || ((f.nz - 1) % 2 == 0 && (f.nz - 1) / 2 + 1 >= 3);
-    if (!okx || !okz) break;
+    if (f.nx < 5 || (dim == 2 && f.nz < 5)) break;
     LevelInfo& cl = c->lv[L];
-    cl.nx = (f.nx - 1) / 2 + 1;
-    cl.nz = dim == 1 ? 1 : (f.nz - 1) / 2 + 1;
+    cl.nx = coarse_n(f.nx);
+    cl.nz = dim == 1 ? 1 : coarse_n(f.nz);
     cl.h = 2.0 * f.h;
     HZ_ALLOC(c, cl.m, cl.n() * sizeof(double));
     HZ_HIP(c, launch_inject(grid_of(c, L - 1), dim, cl.m.as<double>(), c->stream));
@@ -1100,7 +1128,8 @@ int hz_plan_grid(int dim, int nz, int nx, double h, double m_min, double m_max,
     o = &d;
   }
   for (int l = 0; l < HZ_MAX_LEVELS; ++l) w[l] = 0.0;
-  return plan_grid(dim, grid_max_levels(dim, nz, nx), h, m_min, m_max, o, 2.0 * M_PI * freq_hz, levels, w);
+  return plan_grid(dim, grid_max_levels(dim, nz, nx), grid_default_levels(dim, nz, nx), h, m_min, m_max, o,
+                   2.0 * M_PI * freq_hz, levels, w);
 }
 
 int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,

@@ -97,6 +97,10 @@ struct Tiles {
 
 Tiles grid_tiles(int nz, int nx, int dim);
 int vec_tiles(size_t n);
+// Level hierarchy (hz_api.hip): an axis of n nodes halves to ceil(n / 2).
+int coarse_n(int n);
+int grid_max_levels(int dim, int nz, int nx);      // most levels the grid allows
+int grid_default_levels(int dim, int nz, int nx);  // levels of a default plan
 long long tile_blocks(int per_slot, int cap);  // XCD-aware grid size of a 2D-tiled kernel
 int lds_tiles(int nz, int nx);                 // tiles per slot of the LDS-staged 2D kernels
 // tiles per slot of the kernels that store reduction partials over a grid

@@ -115,7 +115,10 @@ __global__ void k_winv(Grid g, double omega, double s_re, double s_im, double w,
   winv[p] = cscale(w, cinv(diag_of<D2>(c, 1.0 / (g.h * g.h))));
 }
 
-// bc = 2^-dim P^T (b - M u), one thread per coarse node.
+// bc = 2^-dim P^T (b - M u), one thread per coarse node. P^T gives the two
+// fine neighbours of a coarse node weight 1/2, except the last fine node of
+// an axis with an even node count, which is interpolated from the last coarse
+// node alone and so carries weight 1 (coarse node J with 2J + 2 == n).
 template <bool D2>
 __global__ void __launch_bounds__(kBlock) k_restrict(Grid gf, Grid gc, Tiles t, Batch bt,
                                                      const double2* __restrict__ b,
@@ -136,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid gf, Grid gc, Tiles t, 
   for (int dz = dz_lo; dz <= dz_hi; ++dz) {
     const int iz = D2 ? 2 * Iz + dz : 0;
     if (iz < 0 || iz >= gf.nz) continue;
-    const double wzt = (dz == 0) ? 1.0 : 0.5;
+    const double wzt = (dz == 0 || (dz == 1 && 2 * Iz + 2 == gf.nz)) ? 1.0 : 0.5;
     double2 row = c2(0.0, 0.0);
     for (int dx = -1; dx <= 1; ++dx) {
       const int ix = 2 * Ix + dx;
@@ -144,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid gf, Grid gc, Tiles t, 
       const int p = iz * gf.nx + ix;
       const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
       const double2 r = csub(bs[p], apply_node<D2>(us, p, iz, ix, gf.nz, gf.nx, ih2, c, us[p]));
-      const double wxt = (dx == 0) ? 1.0 : 0.5;
+      const double wxt = (dx == 0 || (dx == 1 && 2 * Ix + 2 == gf.nx)) ? 1.0 : 0.5;
       row = cadd(row, cscale(wxt, r));
     }
     acc = cadd(acc, cscale(wzt, row));
@@ -152,19 +155,21 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid gf, Grid gc, Tiles t, 
   bc[(size_t)slot * sc + Iz * gc.nx + Ix] = cscale(D2 ? 0.25 : 0.5, acc);
 }
 
-// Bilinear (1D: linear) interpolation of coarse e at fine node (iz, ix).
+// Bilinear (1D: linear) interpolation of coarse e at fine node (iz, ix). The
+// last node of an even-count axis has no right coarse neighbour: the clamped
+// index makes it (e_J + e_J) / 2 = e_J exactly.
 template <bool D2>
-__device__ __forceinline__ double2 interp(const double2* __restrict__ e, int iz, int ix, int ncx) {
-  const int Jx = ix >> 1, ox = ix & 1;
+__device__ __forceinline__ double2 interp(const double2* __restrict__ e, int iz, int ix, int ncx, int ncz) {
+  const int Jx = ix >> 1, ox = ix & 1, Jx1 = min(Jx + 1, ncx - 1);
   if (!D2) {
-    return ox ? cscale(0.5, cadd(e[Jx], e[Jx + 1])) : e[Jx];
+    return ox ? cscale(0.5, cadd(e[Jx], e[Jx1])) : e[Jx];
   }
   const int Jz = iz >> 1, oz = iz & 1;
   const double2* r0 = e + Jz * ncx;
-  double2 a = ox ? cscale(0.5, cadd(r0[Jx], r0[Jx + 1])) : r0[Jx];
+  double2 a = ox ? cscale(0.5, cadd(r0[Jx], r0[Jx1])) : r0[Jx];
   if (!oz) return a;
-  const double2* r1 = r0 + ncx;
-  const double2 bb = ox ? cscale(0.5, cadd(r1[Jx], r1[Jx + 1])) : r1[Jx];
+  const double2* r1 = Jz + 1 < ncz ? r0 + ncx : r0;
+  const double2 bb = ox ? cscale(0.5, cadd(r1[Jx], r1[Jx1])) : r1[Jx];
   return cscale(0.5, cadd(a, bb));
 }
 
@@ -180,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid gf, Grid gc, Tiles t, B
   tile_node<D2>(t, tile, iz, ix);
   if (iz >= gf.nz || ix >= gf.nx) return;
   const size_t q = (size_t)slot * sf + iz * gf.nx + ix;
-  const double2 ef = interp<D2>(e + (size_t)slot * sc, iz, ix, gc.nx);
+  const double2 ef = interp<D2>(e + (size_t)slot * sc, iz, ix, gc.nx, gc.nz);
   u_out[q] = cadd(u_in[q], ef);
 }
 
@@ -248,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth(Grid gf, Grid gc, Til
   const double2* es = e + (size_t)slot * sc;
   const double2* us = u2 + base;
   auto u3_at = [&](int qz, int qx) -> double2 {
-    return cadd(us[qz * gf.nx + qx], interp<D2>(es, qz, qx, gc.nx));
+    return cadd(us[qz * gf.nx + qx], interp<D2>(es, qz, qx, gc.nx, gc.nz));
   };
   const int p = iz * gf.nx + ix;
   const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
@@ -359,7 +364,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth_t(Grid gf, Grid gc, i
   const double2* es = e + (size_t)slot * sc;
   fill_halo(U, gf, t, [&](int q, int hz, int hx) {
     const int qz = t.z0 - 1 + hz, qx = t.x0 - 1 + hx;
-    return cadd(us[q], interp<true>(es, qz, qx, gc.nx));
+    return cadd(us[q], interp<true>(es, qz, qx, gc.nx, gc.nz));
   });
   __syncthreads();
   const double ih = 1.0 / gf.h, ih2 = ih * ih;
@@ -434,10 +439,14 @@ __global__ void __launch_bounds__(kRtx * kRtz) k_restrict_tiled(Grid gf, Grid gc
   if (Iz >= gc.nz || Ix >= gc.nx) return;
   // residual-region index of fine node 2I + d is 2 * local + 1 + d
   const int rz = 2 * lcz + 1, rx = 2 * lcx + 1;
+  // the last fine node of an even-count axis carries weight 1 (see k_restrict)
+  const bool xe = 2 * Ix + 2 == gf.nx, ze = 2 * Iz + 2 == gf.nz;
   double2 acc = c2(0.0, 0.0);
   for (int dz = -1; dz <= 1; ++dz) {
-    const double wzt = dz == 0 ? 1.0 : 0.5;
-    const double2 row = cadd(Rr[rz + dz][rx], cscale(0.5, cadd(Rr[rz + dz][rx - 1], Rr[rz + dz][rx + 1])));
+    const double wzt = (dz == 0 || (dz == 1 && ze)) ? 1.0 : 0.5;
+    const double2* R = Rr[rz + dz];
+    const double2 row = xe ? cadd(cadd(R[rx], cscale(0.5, R[rx - 1])), R[rx + 1])
+                           : cadd(R[rx], cscale(0.5, cadd(R[rx - 1], R[rx + 1])));
     acc = cadd(acc, cscale(wzt, row));
   }
   bc[(size_t)slot * sc + Iz * gc.nx + Ix] = cscale(0.25, acc);
@@ -697,8 +706,8 @@ __global__ void __launch_bounds__(1024) k_misfit(size_t nd, const double2* __res
 }
 
 __global__ void k_inject(Grid gf, int dim, double* __restrict__ mc) {
-  const int ncx = (gf.nx - 1) / 2 + 1;
-  const int ncz = dim == 2 ? (gf.nz - 1) / 2 + 1 : 1;
+  const int ncx = (gf.nx + 1) / 2;
+  const int ncz = dim == 2 ? (gf.nz + 1) / 2 : 1;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ncx * ncz) return;
   const int Iz = i / ncx, Ix = i - Iz * ncx;
@@ -928,8 +937,8 @@ hipError_t launch_misfit(size_t nd, const double2* d_obs, const double2* d_cal, 
 }
 
 hipError_t launch_inject(const Grid& gf, int dim, double* mc, hipStream_t st) {
-  const int ncx = (gf.nx - 1) / 2 + 1;
-  const int ncz = dim == 2 ? (gf.nz - 1) / 2 + 1 : 1;
+  const int ncx = (gf.nx + 1) / 2;
+  const int ncz = dim == 2 ? (gf.nz + 1) / 2 : 1;
   const int tot = ncx * ncz;
   hipLaunchKernelGGL(k_inject, dim3((tot + 255) / 256), dim3(256), 0, st, gf, dim, mc);
   return hipGetLastError();

@@ -38,16 +38,9 @@ struct Request {
 };
 
 int levels_of(int dim, int nz, int nx, int requested) {
-  int L = 1;
-  while (L < HZ_MAX_LEVELS) {
-    const bool okx = (nx - 1) % 2 == 0 && (nx - 1) / 2 + 1 >= 3;
-    const bool okz = dim == 1 || ((nz - 1) % 2 == 0 && (nz - 1) / 2 + 1 >= 3);
-    if (!okx || !okz) break;
-    nx = (nx - 1) / 2 + 1;
-    if (dim == 2) nz = (nz - 1) / 2 + 1;
-    ++L;
-  }
-  return requested > 0 ? std::min(requested, L) : L;
+  if (dim == 1) nz = 1;
+  const int L = hz::grid_max_levels(dim, nz, nx);
+  return requested > 0 ? std::min(requested, L) : hz::grid_default_levels(dim, nz, nx);
 }
 
 }  // namespace
@@ -156,8 +149,8 @@ size_t hz_footprint(int dim, int nz, int nx, int nfreq, int nrhs, const hz_solve
   int cz = nz, cx = nx;
   for (int l = 0; l < L; ++l) {
     n[l] = (size_t)cz * cx;
-    cx = (cx - 1) / 2 + 1;
-    if (dim == 2) cz = (cz - 1) / 2 + 1;
+    cx = hz::coarse_n(cx);
+    if (dim == 2) cz = hz::coarse_n(cz);
   }
   size_t bytes = 0;
   for (int l = 0; l < L; ++l) bytes += n[l] * sizeof(double);  // slowness per level

@@ -159,10 +159,16 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
       const double2 lb = from_left(rb), gb = from_right(rb);
       const double2 lc = from_left(rc), gc2 = from_right(rc);
       if (cown && 2 * Iz >= w.z0 && 2 * Iz < w.z1 && Iz < gc.nz) {
+        // the last fine node of an even-count axis carries weight 1 (P^T of
+        // the clamped interpolation)
+        const bool xe = x + 2 == g.nx, ze = 2 * Iz + 2 == g.nz;
+        auto row = [&](double2 cen, double2 l, double2 r) {
+          return xe ? cadd(cadd(cen, cscale(0.5, l)), r) : cadd(cen, cscale(0.5, cadd(l, r)));
+        };
         double2 acc = c2(0.0, 0.0);
-        acc = cadd(acc, cscale(0.5, cadd(ra, cscale(0.5, cadd(la, ga)))));
-        acc = cadd(acc, cscale(1.0, cadd(rb, cscale(0.5, cadd(lb, gb)))));
-        acc = cadd(acc, cscale(0.5, cadd(rc, cscale(0.5, cadd(lc, gc2)))));
+        acc = cadd(acc, cscale(0.5, row(ra, la, ga)));
+        acc = cadd(acc, cscale(1.0, row(rb, lb, gb)));
+        acc = cadd(acc, cscale(ze ? 1.0 : 0.5, row(rc, lc, gc2)));
         bc[(size_t)w.slot * sc + (size_t)Iz * gc.nx + (x >> 1)] = cscale(0.25, acc);
       }
     }

@@ -44,7 +44,10 @@ def level_models(m, levels):
     return out
 
 
-SHAPES = [((33, 65), 25.0), ((65, 33), 25.0), ((17, 129), 20.0), ((257,), 10.0)]
+# odd node counts (grids share both ends) and even ones (the last fine node
+# of an even axis is interpolated from the last coarse node)
+SHAPES = [((33, 65), 25.0), ((65, 33), 25.0), ((17, 129), 20.0), ((257,), 10.0),
+          ((34, 66), 25.0), ((21, 40), 30.0), ((256,), 10.0)]
 
 
 @pytest.mark.parametrize("shape,h", SHAPES)
@@ -104,8 +107,8 @@ def test_restriction_and_prolongation(hz, shape, h):
     u = workloads.random_vectors(2, n, seed=7)
     e = workloads.random_vectors(2, int(np.prod(cs)), seed=8)
     M = op.operator_M(m, h, om, *beta)
-    R = mg.restriction(cs)
-    P = mg.prolongation(cs)
+    R = mg.restriction(cs, shape)
+    P = mg.prolongation(cs, shape)
     bc = to_np(c.restrict(0, f, torch.from_numpy(b.reshape((2,) + shape)).cuda(),
                           torch.from_numpy(u.reshape((2,) + shape)).cuda(), beta=beta)).reshape(2, -1)
     up = to_np(c.prolong(0, torch.from_numpy(e.reshape((2,) + cs)).cuda(),
@@ -117,7 +120,9 @@ def test_restriction_and_prolongation(hz, shape, h):
 
 @pytest.mark.parametrize("shape,h,levels,nu", [
     ((33, 65), 25.0, 5, (2, 2)), ((33, 65), 25.0, 3, (1, 1)), ((65, 33), 25.0, 4, (2, 0)),
-    ((17, 129), 20.0, 3, (3, 2)), ((257,), 10.0, 6, (2, 2)), ((101, 201), 10.0, 3, (2, 2))])
+    ((17, 129), 20.0, 3, (3, 2)), ((257,), 10.0, 6, (2, 2)), ((101, 201), 10.0, 3, (2, 2)),
+    ((34, 66), 25.0, 4, (2, 2)), ((60, 100), 20.0, 4, (2, 2)), ((34, 66), 25.0, 3, (1, 1)),
+    ((256,), 10.0, 6, (2, 2))])
 def test_vcycle(hz, shape, h, levels, nu):
     import torch
     m = random_model(shape, 9)

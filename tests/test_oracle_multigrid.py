@@ -28,6 +28,45 @@ def test_prolongation_reproduces_bilinear_functions():
         assert np.allclose(P @ fc.ravel(), ff.ravel(), rtol=0, atol=1e-12)
 
 
+def test_prolongation_on_even_count_axes():
+    """An axis with an even node count: linear functions are reproduced at
+    every fine node but the last, which takes the last coarse value."""
+    for coarse, fine in [((5,), (10,)), ((5, 9), (10, 17)), ((5, 9), (9, 18)), ((4, 4), (8, 7))]:
+        P = mg.prolongation(coarse, fine)
+        Zc, Xc = np.meshgrid(np.arange(coarse[0]) * 2.0, np.arange(coarse[-1]) * 2.0, indexing="ij")
+        Zf, Xf = np.meshgrid(np.arange(fine[0]) * 1.0, np.arange(fine[-1]) * 1.0, indexing="ij")
+        if len(coarse) == 1:
+            Zc, Zf = np.zeros_like(Xc[:1]), np.zeros_like(Xf[:1])
+            Xc, Xf = Xc[:1], Xf[:1]
+        fc = 1 + 0.3 * Xc - 0.7 * Zc + 0.1 * Xc * Zc
+        ff = 1 + 0.3 * Xf - 0.7 * Zf + 0.1 * Xf * Zf
+        # the fine coordinate of the extra node moves onto the last coarse node
+        Xe = np.minimum(Xf, 2.0 * (coarse[-1] - 1))
+        Ze = np.minimum(Zf, 2.0 * (coarse[0] - 1)) if len(coarse) == 2 else Zf
+        fe = 1 + 0.3 * Xe - 0.7 * Ze + 0.1 * Xe * Ze
+        got = (P @ fc.ravel()).reshape(ff.shape)
+        assert np.allclose(got, fe, rtol=0, atol=1e-12)
+        inner = (Xf <= 2.0 * (coarse[-1] - 1)) & (Zf <= 2.0 * (coarse[0] - 1))
+        assert np.allclose(got[inner], ff[inner], rtol=0, atol=1e-12)
+
+
+def test_restriction_weighted_constants_on_even_count_axes():
+    """With an even node count the last coarse node collects the whole last
+    fine cell: R (W_fine 1) equals the coarse weights except on that node,
+    where the axis weight is 1 instead of 1/2."""
+    for coarse, fine in [((5,), (10,)), ((5, 9), (10, 17)), ((5, 9), (9, 18))]:
+        _, _, wf = op.stencil_parts(fine)
+        _, _, wc = op.stencil_parts(coarse)
+        got = (mg.restriction(coarse, fine) @ wf).reshape(coarse)
+        exp = wc.reshape(coarse).copy()
+        axes = [(a, n) for a, (n, nf) in enumerate(zip(coarse, fine)) if nf % 2 == 0]
+        for a, n in axes:
+            idx = [slice(None)] * len(coarse)
+            idx[a] = n - 1
+            exp[tuple(idx)] *= 2.0
+        assert np.allclose(got, exp, rtol=0, atol=1e-14)
+
+
 def test_restriction_preserves_weighted_constants():
     """R (W_fine 1) = W_coarse 1: the weighted residual keeps its meaning."""
     for coarse in [(5,), (5, 9), (9, 5), (3, 3)]:
@@ -63,7 +102,8 @@ def test_coarse_operator_approximates_galerkin_on_smooth_vectors():
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
 
 
-@pytest.mark.parametrize("shape,levels,nu", [((17,), 3, (2, 2)), ((17, 17), 3, (2, 2)),
+@pytest.mark.parametrize("shape,levels,nu", [((16,), 3, (2, 2)), ((10, 18), 3, (1, 1)),
+                                             ((17,), 3, (2, 2)), ((17, 17), 3, (2, 2)),
                                             ((9, 17), 3, (1, 1)), ((17, 9), 2, (2, 1))])
 def test_vcycle_equals_explicit_error_propagation(shape, levels, nu):
     rng = np.random.default_rng(5)
@@ -155,11 +195,16 @@ def test_smoother_growth_matches_lfa(kh, grows):
 
 
 def test_plan_levels_and_weights():
-    assert lfa.max_levels((201, 201)) == 4
-    assert lfa.max_levels((401, 801)) == 5
-    assert lfa.max_levels((301, 601)) == 3
-    assert lfa.max_levels((129, 129)) == 7
-    assert lfa.max_levels((1001,)) == 4
+    # default plans: odd-count halving, then even-count halving while the
+    # coarsest level has more than 2048 unknowns
+    assert lfa.default_levels((201, 201)) == 4
+    assert lfa.default_levels((401, 801)) == 5
+    assert lfa.default_levels((301, 601)) == 5   # 76 x 151 -> 38 x 76 -> 19 x 38
+    assert lfa.default_levels((129, 129)) == 7
+    assert lfa.default_levels((1001,)) == 4
+    assert lfa.max_levels((301, 601)) == 8       # ... 10 x 19 -> 5 x 10 -> 3 x 5
+    assert lfa.max_levels((1001,)) == 9
+    assert mg.coarse_shape((76, 151)) == (38, 76)
     # low kh everywhere: the default weight is kept
     L, w = lfa.plan((201, 201), 10.0, 2 * np.pi * 5, 1 / 2800, 1 / 1200, 1, 0.5)
     assert L == 4 and w == [0.8, 0.8, 0.8]
