@@ -99,6 +99,10 @@ typedef struct {
                                fixed shape. Results do not depend on the shape. */
     int    chunk_rows;      /* 0 (default): shape from the tuner (or fixed); > 0, even: grid
                                rows per wavefront for every fused V-cycle kernel */
+    int    graphs;          /* 1: BiCGSTAB iterations are captured in HIP graphs (two
+                               iterations per graph, one graph per batch-size bucket) and
+                               replayed; 0 (default): every launch issued one by one. Ignored
+                               while kernel timing is on. Results do not depend on it. */
 } hz_solve_opts;
 
 typedef struct {

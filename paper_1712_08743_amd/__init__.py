@@ -46,7 +46,7 @@ class SolveOpts(ctypes.Structure):
                 ("beta2", ctypes.c_double), ("levels", ctypes.c_int), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("jacobi_w", ctypes.c_double),
                 ("jacobi_w_level", ctypes.POINTER(ctypes.c_double)), ("autotune", ctypes.c_int),
-                ("chunk_rows", ctypes.c_int)]
+                ("chunk_rows", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -119,7 +119,8 @@ def default_opts():
 
 
 def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg", beta=(1.0, 0.5),
-              levels=0, nu=(2, 2), jacobi_w=0.8, jacobi_w_level=None, autotune=True, chunk_rows=0):
+              levels=0, nu=(2, 2), jacobi_w=0.8, jacobi_w_level=None, autotune=True, chunk_rows=0,
+              graphs=False):
     """Build an hz_solve_opts; returns (opts, keepalive)."""
     o = default_opts()
     o.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
@@ -133,6 +134,7 @@ def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg"
     o.jacobi_w = float(jacobi_w)
     o.autotune = 1 if autotune else 0
     o.chunk_rows = int(chunk_rows)
+    o.graphs = 1 if graphs else 0
     keep = None
     if jacobi_w_level is not None:
         keep = (ctypes.c_double * max(1, len(jacobi_w_level)))(*[float(w) for w in jacobi_w_level])

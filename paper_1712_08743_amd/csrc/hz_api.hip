@@ -115,6 +115,7 @@ struct hz_ctx {
   // launch-shape tuning: rows per wavefront of the fused V-cycle kernels,
   // keyed by (kernel, nz, nx, batch-size octave)
   std::map<std::array<int, 4>, int> tuned_chunk;
+  hipStream_t graph_stream = nullptr;  // the library's own stream, used only to capture graphs
   int tune_mode = 1;   // opts.autotune of the running solve
   int fixed_chunk = 0; // opts.chunk_rows of the running solve
 };
@@ -283,6 +284,7 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
   if (o->chunk_rows < 0 || (o->chunk_rows & 1) || o->chunk_rows > (1 << 16))
     return fail(c, HZ_ERR_ARG, "chunk_rows must be 0 or an even number up to 65536");
   if (o->autotune != 0 && o->autotune != 1) return fail(c, HZ_ERR_ARG, "autotune must be 0 or 1");
+  if (o->graphs != 0 && o->graphs != 1) return fail(c, HZ_ERR_ARG, "graphs must be 0 or 1");
   if (o->precond == HZ_PRECOND_EXACT) {
     if (c->dim != 1) return fail(c, HZ_ERR_ARG, "the exact preconditioner is the 1D tridiagonal solve");
     const size_t lds = (size_t)4 * c->nx * sizeof(double2);
@@ -705,6 +707,104 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   long long iters_issued = 0;
   const long long guard = 2LL * (o->maxit + 2) + 16;
   bool done = false;
+
+  // One BiCGSTAB iteration for the first `capx` entries of the active list,
+  // issued on stream `sx` (every launch of the path reads c->stream).
+  auto issue_iteration = [&](int capx, hipStream_t sx) -> hipError_t {
+    const hipStream_t saved = c->stream;
+    c->stream = sx;
+    hipError_t e = hipSuccess;
+    // p_new = r + beta (p_old - omega v) into the other p buffer, then ph = V p_new
+    double2* pn = (p == pbuf[0]) ? pbuf[1] : pbuf[0];
+    do {
+      if (fused) {
+        const FineRhs fr{1, r, p, v, pn};
+        if ((e = precond_apply(c, cy, capx, nullptr, ph, &fr)) != hipSuccess) break;
+      } else {
+        if ((e = launch_bicg_p(n0, bt, capx, r, p, v, pn, n0, sx)) != hipSuccess) break;
+        if (!identity && (e = precond_apply(c, cy, capx, pn, ph)) != hipSuccess) break;
+      }
+      p = pn;
+      if (identity) ph = p;
+      if ((e = timed(c, HZ_KERNEL_APPLY, [&] {
+             return launch_bicg_apply_sigma(c->dim, g0, bt, capx, rd, ph, rh, v, n0, sx);
+           })) != hipSuccess)
+        break;
+      if ((e = launch_bicg_fin(kFinSigma, gt, bt, capx, rd, o->tol, o->maxit, sx)) != hipSuccess) break;
+      if (fused) {
+        const FineRhs fr{2, r, v, nullptr, s};
+        if ((e = precond_apply(c, cy, capx, nullptr, sh, &fr)) != hipSuccess) break;
+      } else {
+        if ((e = launch_bicg_s(n0, bt, capx, r, v, s, n0, sx)) != hipSuccess) break;
+        if (!identity && (e = precond_apply(c, cy, capx, s, sh)) != hipSuccess) break;
+      }
+      if ((e = timed(c, HZ_KERNEL_APPLY_S, [&] {
+             return launch_bicg_apply_omega(c->dim, g0, bt, capx, rd, sh, s, t, n0, sx);
+           })) != hipSuccess)
+        break;
+      if ((e = launch_bicg_fin(kFinOmega, gt, bt, capx, rd, o->tol, o->maxit, sx)) != hipSuccess) break;
+      if ((e = timed(c, HZ_KERNEL_UPDATE, [&] {
+             return launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx);
+           })) != hipSuccess)
+        break;
+      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, sx);
+    } while (false);
+    c->stream = saved;
+    return e;
+  };
+
+  // HIP graphs: two iterations (the p buffers swap twice, so a pair starts
+  // and ends on the same buffer) captured once per batch-size bucket (the
+  // active count rounded up to a power of two; launches past the active
+  // list exit at once) and replayed. The first pair of a bucket runs
+  // eagerly, which also runs the launch-shape trials, so nothing that
+  // synchronises is captured. Kernel timing needs per-launch events, so
+  // timed solves run eagerly.
+  const bool use_graphs = o->graphs && c->timing_mask == 0;
+  struct GraphSet {  // instantiated graphs of this solve, destroyed once the stream is idle
+    hipStream_t st;
+    std::map<int, hipGraphExec_t> m;
+    ~GraphSet() {
+      if (m.empty()) return;
+      (void)hipStreamSynchronize(st);
+      for (auto& kv : m) (void)hipGraphExecDestroy(kv.second);
+    }
+  } gset{st, {}};
+  std::map<int, hipGraphExec_t>& graphs = gset.m;
+  std::map<int, int> eager_pairs;
+  auto bucket = [&](int n) {
+    int b = 1;
+    while (b < n) b <<= 1;
+    return std::min(b, nslots);
+  };
+  auto issue_pair_graph = [&](int capx) -> int {
+    const int cb = bucket(capx);
+    auto it = graphs.find(cb);
+    if (it == graphs.end() && eager_pairs[cb] == 0) {
+      eager_pairs[cb] = 1;
+      HZ_HIP(c, issue_iteration(cb, st));
+      HZ_HIP(c, issue_iteration(cb, st));
+      return HZ_OK;
+    }
+    if (it == graphs.end()) {
+      if (!c->graph_stream) HZ_HIP(c, hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking));
+      hipGraph_t gr = nullptr;
+      HZ_HIP(c, hipStreamBeginCapture(c->graph_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = issue_iteration(cb, c->graph_stream);
+      if (e == hipSuccess) e = issue_iteration(cb, c->graph_stream);
+      const hipError_t e2 = hipStreamEndCapture(c->graph_stream, &gr);
+      if (e == hipSuccess) e = e2;
+      hipGraphExec_t ex = nullptr;
+      if (e == hipSuccess) e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      if (gr) (void)hipGraphDestroy(gr);
+      if (e != hipSuccess)
+        return fail(c, HZ_ERR_DEVICE, "capturing the iteration graph failed: %s", hipGetErrorString(e));
+      it = graphs.emplace(cb, ex).first;
+    }
+    HZ_HIP(c, hipGraphLaunch(it->second, st));
+    return HZ_OK;
+  };
+
   while (!done) {
     while (!pending.empty() && ((int)pending.size() > kLag || cap == 0)) {
       const auto [useq, k] = pending.front();
@@ -732,37 +832,13 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       continue;
     }
     if (iters_issued >= guard) break;
-    // p_new = r + beta (p_old - omega v) into the other p buffer, then ph = V p_new
-    double2* pn = (p == pbuf[0]) ? pbuf[1] : pbuf[0];
-    if (fused) {
-      const FineRhs fr{1, r, p, v, pn};
-      HZ_HIP(c, precond_apply(c, cy, cap, nullptr, ph, &fr));
+    if (use_graphs) {
+      if ((rc = issue_pair_graph(cap)) != HZ_OK) return rc;
+      iters_issued += 2;
     } else {
-      HZ_HIP(c, launch_bicg_p(n0, bt, cap, r, p, v, pn, n0, st));
-      if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, pn, ph));
+      HZ_HIP(c, issue_iteration(cap, st));
+      ++iters_issued;
     }
-    p = pn;
-    if (identity) ph = p;
-    HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] {
-             return launch_bicg_apply_sigma(c->dim, g0, bt, cap, rd, ph, rh, v, n0, st);
-           }));
-    HZ_HIP(c, launch_bicg_fin(kFinSigma, gt, bt, cap, rd, o->tol, o->maxit, st));
-    if (fused) {
-      const FineRhs fr{2, r, v, nullptr, s};
-      HZ_HIP(c, precond_apply(c, cy, cap, nullptr, sh, &fr));
-    } else {
-      HZ_HIP(c, launch_bicg_s(n0, bt, cap, r, v, s, n0, st));
-      if (!identity) HZ_HIP(c, precond_apply(c, cy, cap, s, sh));
-    }
-    HZ_HIP(c, timed(c, HZ_KERNEL_APPLY_S, [&] {
-             return launch_bicg_apply_omega(c->dim, g0, bt, cap, rd, sh, s, t, n0, st);
-           }));
-    HZ_HIP(c, launch_bicg_fin(kFinOmega, gt, bt, cap, rd, o->tol, o->maxit, st));
-    HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
-             return launch_bicg_xr(n0, bt, cap, rd, x, ph, sh, s, t, r, rh, n0, st);
-           }));
-    HZ_HIP(c, launch_bicg_fin(kFinStep, vt, bt, cap, rd, o->tol, o->maxit, st));
-    ++iters_issued;
     if ((rc = close_unit()) != HZ_OK) return rc;
   }
   HZ_HIP(c, hipStreamSynchronize(st));
@@ -967,6 +1043,7 @@ void hz_default_opts(hz_solve_opts* o) {
   o->jacobi_w_level = nullptr;
   o->autotune = 1;
   o->chunk_rows = 0;
+  o->graphs = 0;
 }
 
 int hz_create(hz_ctx** out, const hz_ctx_opts* o) {
@@ -1023,6 +1100,7 @@ void hz_destroy(hz_ctx* c) {
   fold_timing(c);
   for (hipEvent_t e : c->tpool) (void)hipEventDestroy(e);
   if (c->ring_host) (void)hipHostFree(c->ring_host);
+  if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
   delete c;
 }
 

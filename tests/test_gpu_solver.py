@@ -148,6 +148,24 @@ def test_launch_shape_invariance_bitwise(hz, shape):
     assert torch.equal(u, ref)
 
 
+@pytest.mark.parametrize("nrhs,freqs", [(1, (5.0,)), (7, (3.0, 6.0, 9.0))])
+def test_graph_replay_bitwise(hz, nrhs, freqs):
+    """Iterations replayed from captured HIP graphs give the same bits and
+    iteration counts as iterations issued one by one (several batch-size
+    buckets as right-hand sides converge, and a second solve that captures
+    its graphs again)."""
+    import torch
+    w = workloads.model_2d_layered(nz=97, nx=193, h=20.0, nshots=nrhs, freqs=freqs)
+    c = make_ctx(hz, w.m, w.h)
+    b1 = c.point_rhs([0] * nrhs, w.src)
+    b = torch.stack([b1] * len(freqs)).contiguous()
+    ref, info_ref = c.solve(freqs, 0.01, b, tol=1e-10, graphs=False)
+    for _ in range(2):
+        u, info = c.solve(freqs, 0.01, b, tol=1e-10, graphs=True)
+        assert torch.equal(u, ref)
+        assert [i[:2] for i in info] == [i[:2] for i in info_ref]
+
+
 def test_unpreconditioned_path(hz):
     """No preconditioner: a small, heavily damped problem still converges."""
     w = workloads.model_2d_lens(n=33, h=60.0)
