@@ -53,7 +53,7 @@ def smoothing_factor_sampled(kh, beta1, beta2, w, dim=2, n=129):
     return float(a[hi].max())
 
 
-COARSE_TARGET = 2048  # unknowns on the coarsest level a default plan aims below
+COARSE_TARGET = 512  # unknowns on the coarsest level a default plan aims at or below
 
 
 def max_levels(shape):
@@ -68,15 +68,10 @@ def max_levels(shape):
 
 
 def default_levels(shape):
-    """Levels of a default plan: halve while every axis has an odd node count
-    (fine and coarse grids share both ends); then, while the coarsest level
-    has more than COARSE_TARGET unknowns, keep halving with the even-count
-    rule (see multigrid.coarse_size)."""
+    """Levels of a default plan: halve while the coarsest level has more than
+    COARSE_TARGET unknowns and every axis keeps at least 3 nodes."""
     L = 1
     cur = list(shape)
-    while all(n >= 5 and n % 2 == 1 for n in cur):
-        cur = [(n + 1) // 2 for n in cur]
-        L += 1
     while int(np.prod(cur)) > COARSE_TARGET and all(n >= 5 for n in cur):
         cur = [(n + 1) // 2 for n in cur]
         L += 1

@@ -195,22 +195,22 @@ def test_smoother_growth_matches_lfa(kh, grows):
 
 
 def test_plan_levels_and_weights():
-    # default plans: odd-count halving, then even-count halving while the
-    # coarsest level has more than 2048 unknowns
-    assert lfa.default_levels((201, 201)) == 4
-    assert lfa.default_levels((401, 801)) == 5
-    assert lfa.default_levels((301, 601)) == 5   # 76 x 151 -> 38 x 76 -> 19 x 38
-    assert lfa.default_levels((129, 129)) == 7
-    assert lfa.default_levels((1001,)) == 4
+    # default plans: halve while the coarsest level has more than 512 unknowns
+    assert lfa.default_levels((201, 201)) == 5   # ... 26 x 26 -> 13 x 13
+    assert lfa.default_levels((401, 801)) == 6   # ... 26 x 51 -> 13 x 26
+    assert lfa.default_levels((301, 601)) == 6   # 76 x 151 -> 38 x 76 -> 19 x 38 -> 10 x 19
+    assert lfa.default_levels((129, 129)) == 4   # 17 x 17
+    assert lfa.default_levels((1001,)) == 2
+    assert lfa.default_levels((17, 17)) == 1
     assert lfa.max_levels((301, 601)) == 8       # ... 10 x 19 -> 5 x 10 -> 3 x 5
     assert lfa.max_levels((1001,)) == 9
     assert mg.coarse_shape((76, 151)) == (38, 76)
     # low kh everywhere: the default weight is kept
-    L, w = lfa.plan((201, 201), 10.0, 2 * np.pi * 5, 1 / 2800, 1 / 1200, 1, 0.5)
+    L, w = lfa.plan((201, 201), 10.0, 2 * np.pi * 5, 1 / 2800, 1 / 1200, 1, 0.5, levels=4)
     assert L == 4 and w == [0.8, 0.8, 0.8]
     # a level in the band gets a smaller weight with mu <= 1 over its kh range
     L, w = lfa.plan((401, 801), 10.0, 2 * np.pi * 12, 1 / 5175, 1 / 1275, 1, 0.5)
-    assert L == 5 and w[0] == 0.8 and w[2] < 0.8
+    assert L == 6 and w[0] == 0.8 and w[2] < 0.8
     for l, wl in enumerate(w):
         hl = 10.0 * 2 ** l
         for kh in np.linspace(2 * np.pi * 12 * hl / 5175, 2 * np.pi * 12 * hl / 1275, 200):
