@@ -54,14 +54,14 @@ def bytes_per_iteration(sizes):
     sides and read from cache)."""
     z = 16
     n0 = sizes[0]
-    total = n0 * z * (5 + 4)        # p and s updates fused with their two pre-sweeps
+    total = n0 * z * (4 + 3)        # p and s updates fused with the pre-sweeps and restriction
     total += n0 * z * (3 + 3 + 8)   # B p^, B s^ (with dots), x/r update
     for l, n in enumerate(sizes[:-1]):
         nc = sizes[l + 1]
-        per_cycle = nc * z                      # restricted residual (fused into the pre-sweeps)
-        per_cycle += n * z * 3 + nc * z         # prolongation + both post-sweeps
+        per_cycle = nc * z                      # restricted residual
+        per_cycle += n * z * 2 + nc * z         # post-smoothing: reads b, coarse e; writes u
         if l > 0:
-            per_cycle += n * z * 2              # two pre-sweeps from zero (given b)
+            per_cycle += n * z                  # pre-sweeps from zero and restriction: read b
         total += 2 * per_cycle
     nc = sizes[-1]
     total += 2 * (2 * nc * z)                   # coarse right-hand side in, solution out
@@ -74,9 +74,9 @@ def class_bytes_per_iteration(sizes):
     z = 16
     n0, n1 = sizes[0], sizes[1]
     return {
-        "presmooth": n0 * z * 5 + n1 * z,       # reads r, p_old, v; writes p, u2; coarse right-hand side
-        "presmooth_s": n0 * z * 4 + n1 * z,     # reads r, v; writes s, u2; coarse right-hand side
-        "prolong": 2 * (n0 * z * 3 + n1 * z),   # reads u2, b, coarse e; writes u (two V-cycles)
+        "presmooth": n0 * z * 4 + n1 * z,       # reads r, p_old, v; writes p; coarse right-hand side
+        "presmooth_s": n0 * z * 3 + n1 * z,     # reads r, v; writes s; coarse right-hand side
+        "prolong": 2 * (n0 * z * 2 + n1 * z),   # reads b, coarse e; writes u (two V-cycles)
         "apply": n0 * z * 3,                    # reads p^, r^; writes v
         "apply_s": n0 * z * 3,                  # reads s^, s; writes t
         "update": n0 * z * 8,                   # reads x, p^, s^, s, t, r^; writes x, r

@@ -142,7 +142,8 @@ int  hz_point_rhs(hz_ctx *c, int nsrc, const int *iz, const int *ix,
  * right-hand sides each, all in one batch. b_dev and u_dev are
  * [nfreq][nrhs][nz][nx] and must not overlap. info (host, optional) receives
  * nfreq*nrhs records. Returns HZ_WARN_NOCONV if some record's status is not
- * HZ_RHS_CONVERGED (its u is the last iterate).
+ * HZ_RHS_CONVERGED (its u is the last iterate). nrhs = 0 is an empty batch:
+ * nothing is read or written and HZ_OK is returned.
  * Errors: HZ_ERR_ARG, HZ_ERR_SHAPE, HZ_ERR_NOMEM, HZ_ERR_STATE, HZ_ERR_DEVICE. */
 int  hz_solve(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
               double alpha, int nrhs, const hz_c128 *b_dev, hz_c128 *u_dev,

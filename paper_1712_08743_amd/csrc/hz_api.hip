@@ -565,6 +565,8 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
     double2* u = nullptr;
     double2* bc = c->lev[l + 1][kLb].as<double2>();
+    // the fused post-smoothing kernel forms the pre-smoothed iterate again
+    const bool post_fused = dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2;
     if (cy.nu1 == 2 && dim == 2) {
       // both pre-sweeps, the residual and its restriction in one pass
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
@@ -574,7 +576,8 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       const int cls = l > 0 ? -2 : (fr.mode == 2 ? HZ_KERNEL_PRESMOOTH_S : HZ_KERNEL_PRESMOOTH);
       if ((e = timed(c, cls, [&] {
              return tuned_launch(c, cy, fr.mode, g, cap, [&](int ch) {
-               return launch_pre2r(g, gc, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, X, bc, nl, nc, ch, st);
+               return launch_pre2r(g, gc, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, post_fused ? nullptr : X,
+                                   bc, nl, nc, ch, st);
              });
            })) != hipSuccess)
         return e;
@@ -635,12 +638,12 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       continue;
     }
     // prolongation fused with the first post-sweep (2D: with the first two)
-    const int fused = (dim == 2 && cy.nu2 >= 2) ? 2 : 1;
+    const int fused = (dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2) ? 2 : 1;
     double2* dst = (cy.nu2 == fused) ? R : ((u == X) ? Y : X);
     if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
            if (fused == 2)
              return tuned_launch(c, cy, 3, g, cap, [&](int ch) {
-               return launch_post2(g, gc, l, bt, cap, ec, bll, u, dst, nl, c->lv[l + 1].n(), ch, st);
+               return launch_post2(g, gc, l, bt, cap, ec, bll, dst, nl, c->lv[l + 1].n(), ch, st);
              });
            return launch_prolong_smooth(dim, g, gc, l, bt, cap, ec, bll, u, dst, nl, c->lv[l + 1].n(), st);
          })) != hipSuccess)
@@ -1215,12 +1218,13 @@ int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz
     hz_default_opts(&d);
     o = &d;
   }
-  if (nfreq < 1 || nrhs < 1 || !freq_hz || !b_dev || !u_dev)
-    return fail(c, HZ_ERR_ARG, "bad solve arguments");
+  if (nfreq < 1 || nrhs < 0 || !freq_hz) return fail(c, HZ_ERR_ARG, "bad solve arguments");
   if (!(alpha >= 0.0) || !isfinite(alpha)) return fail(c, HZ_ERR_ARG, "alpha must be >= 0");
   for (int f = 0; f < nfreq; ++f)
     if (!(freq_hz[f] > 0.0) || !isfinite(freq_hz[f])) return fail(c, HZ_ERR_ARG, "frequency %d must be positive", f);
   if ((rc = check_opts(c, o)) != HZ_OK) return rc;
+  if (nrhs == 0) return HZ_OK;  // an empty batch: nothing to solve
+  if (!b_dev || !u_dev) return fail(c, HZ_ERR_ARG, "bad solve arguments");
   if ((long long)nfreq * nrhs > (1 << 20)) return fail(c, HZ_ERR_ARG, "too many right-hand sides");
   const int nslots = nfreq * nrhs;
   const size_t n0 = c->lv[0].n();

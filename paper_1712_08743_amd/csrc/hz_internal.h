@@ -130,19 +130,19 @@ hipError_t launch_pre2(int dim, const Grid& g, int lvl, int mode, const Batch& b
 hipError_t launch_prolong_smooth(int dim, const Grid& gf, const Grid& gc, int lvl, const Batch& bt,
                                  int cap, const double2* e, const double2* b, const double2* u2,
                                  double2* u_out, size_t sf, size_t sc, hipStream_t st);
-// 2D only: two damped-Jacobi sweeps from zero on the right-hand side formed
-// as in launch_pre2 (stored to bout in modes 1/2), u2 stored, and the
-// full-weighting restriction of the residual b - M u2 stored to bcoarse
+// 2D only: two damped-Jacobi sweeps from zero (u2) on the right-hand side
+// formed as in launch_pre2 (stored to bout in modes 1/2), and the
+// full-weighting restriction of the residual b - M u2 stored to bcoarse; u2
+// itself is stored only when u2 is not null
 // chunk_rows: grid rows per wavefront (even); any even value gives the same
 // result, the fastest one depends on the level and the batch size.
 hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const Batch& bt, int cap,
                         const double2* a, const double2* b, const double2* c, double2* bout, double2* u2,
                         double2* bcoarse, size_t stride, size_t sc, int chunk_rows, hipStream_t st);
-// 2D only: u_out = two damped-Jacobi sweeps on M from u2 + P e (prolongation,
-// correction and both post-sweeps in one pass)
+// 2D only: u_out = two damped-Jacobi sweeps on M from u2 + P e, with u2 the
+// two pre-sweeps from zero on b formed again (as launch_pre2r forms them)
 hipError_t launch_post2(const Grid& gf, const Grid& gc, int lvl, const Batch& bt, int cap, const double2* e,
-                        const double2* b, const double2* u2, double2* u_out, size_t sf, size_t sc, int chunk_rows,
-                        hipStream_t st);
+                        const double2* b, double2* u_out, size_t sf, size_t sc, int chunk_rows, hipStream_t st);
 hipError_t launch_coarse_solve(int nc, int nfreq, int nrhs, const Batch& bt, const double2* bc,
                                double2* uc, size_t stride, hipStream_t st);
 hipError_t launch_pcr(const Grid& g, const Batch& bt, int cap, const double2* b, double2* u,

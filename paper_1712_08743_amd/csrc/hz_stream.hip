@@ -68,7 +68,10 @@ __device__ __forceinline__ bool wave_tile(const Batch& bt, int nstrip, int nchun
 // sweep from u1), the residual r = b - M u2 on row j-2, and, when row j-2 is
 // odd, the full-weighting restriction to coarse row (j-3)/2 from r on rows
 // j-4 .. j-2. x-radius 3 (u2, r, weights), z from z0-3 to z1+2. Lanes
-// 3 .. 60 store: fine columns xs .. xs+57, coarse columns at even x.
+// 3 .. 60 store: fine columns xs .. xs+57, coarse columns at even x. The
+// pre-smoothed u2 is stored only when u2 is not null: the fused
+// post-smoothing kernel forms it again from b (cheaper than writing and
+// reading it back).
 constexpr int kPreWidth = kLanes - 6;
 
 template <int MODE>
@@ -139,8 +142,8 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
     }
     if (own && i2 >= w.z0 && i2 < w.z1) {
       const size_t q = base + (size_t)i2 * g.nx + x;
-      u2[q] = u2c;
       if (MODE != 0) bout[q] = b1;
+      if (u2) u2[q] = u2c;
     }
     // residual on row j-2
     const int ir = j - 2;
@@ -192,33 +195,34 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
   }
 }
 
-// Prolongation, correction and two post-sweeps (see launch_post2): per row j,
-// u3 = u2 + P e on row j, the first sweep u4 on row j-1, the second on row
-// j-2, stored. x-radius 2, z from z0-2 to z1+1. Lanes 2 .. 61 store.
-constexpr int kPostWidth = kLanes - 4;
+// Prolongation, correction and two post-sweeps (see launch_post2), with the
+// pre-smoothed iterate formed again from b: per row j of the march,
+// u1 = (w/D) b on row j, u2 (one sweep from u1, as in k_pre2r_s) and
+// u3 = u2 + P e on row j-1, the first post-sweep u4 on row j-2, the second
+// on row j-3, stored. x-radius 3, z from z0-3 to z1+2. Lanes 3 .. 60 store.
+// HBM traffic per node: b and u_out, plus e on the coarse grid.
+constexpr int kPostWidth = kLanes - 6;
 
-struct PostRow {  // loads of one row j: u2 on j; b, w/D and m on j-1
-  double2 u2, b, wd;
+struct PostRow {  // loads of one row j: b, w/D and m
+  double2 b, wd;
   double m;
 };
 
 template <bool FINE>
-__global__ void __launch_bounds__(kBlock, 4) k_post2_s(Grid gf, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
+__global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
                                                     Batch bt, const double2* __restrict__ e,
                                                     const double2* __restrict__ b,
-                                                    const double2* __restrict__ u2,
                                                     double2* __restrict__ u_out, size_t sf, size_t sc) {
   WaveTile w;
   if (!wave_tile(bt, nstrip, nchunk, chunk_rows, groups, kPostWidth, gf.nz, w)) return;
   const int lane = threadIdx.x % kLanes;
   const FreqTab& f = bt.ft[bt.slots[w.slot].freq];
-  const int x = w.xs - 2 + lane;
+  const int x = w.xs - 3 + lane;
   const bool xin = x >= 0 && x < gf.nx;
   const int xx = min(max(x, 0), gf.nx - 1);
-  const bool own = lane >= 2 && lane < 2 + kPostWidth && xin;
+  const bool own = lane >= 3 && lane < 3 + kPostWidth && xin;
   const size_t base = (size_t)w.slot * sf;
   const double2* es = e + (size_t)w.slot * sc;
-  const double2* us = u2 + base;
   const double2* bs = b + base;
   const double2* wd = f.winv[lvl];
   const double ih = 1.0 / gf.h, ih2 = ih * ih;
@@ -227,9 +231,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_post2_s(Grid gf, Grid gc, int nst
   const int Jx = xx >> 1, Jx1 = min(Jx + 1, gc.nx - 1);
   auto load_row = [&](int j) {
     PostRow r;
-    const int jj = min(max(j, 0), gf.nz - 1), jm = min(max(j - 1, 0), gf.nz - 1);
-    r.u2 = us[(size_t)jj * gf.nx + xx];
-    const size_t q = (size_t)jm * gf.nx + xx;
+    const size_t q = (size_t)min(max(j, 0), gf.nz - 1) * gf.nx + xx;
     r.b = bs[q];
     r.wd = wd[q];
     r.m = gf.m[q];
@@ -240,59 +242,80 @@ __global__ void __launch_bounds__(kBlock, 4) k_post2_s(Grid gf, Grid gc, int nst
     ea = row[Jx];
     eb = row[Jx1];
   };
-  // rolling rows: u3 on j-2, j-1; u4 on j-3, j-2; b, m, w/D on j-2
-  double2 u3a = zero, u3b = zero, u4a = zero, u4b = zero, b2 = zero, wd2 = zero;
-  double m2 = 0.0;
-  // lo: coarse row j >> 1; hi: the row below it (odd j)
-  auto step = [&](int j, const PostRow& L, double2 loa, double2 lob, double2 hia, double2 hib, bool odd) {
+  auto inside = [&](int j) { return xin && j >= 0 && j < gf.nz; };
+  // rolling rows: u1 on j-2, j-1; u3 on j-3, j-2; u4 on j-4, j-3;
+  // b, w/D, m on j-1, j-2, j-3
+  double2 u1a = zero, u1b = zero, u3a = zero, u3b = zero, u4a = zero, u4b = zero;
+  double2 b1 = zero, b2 = zero, b3 = zero, w1 = zero, w2 = zero, w3 = zero;
+  double m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  // lo, hi: coarse rows (j-1) >> 1 and the one below it
+  auto step = [&](int j, const PostRow& L, double2 loa, double2 lob, double2 hia, double2 hib, bool odd_prev) {
+    const bool jin = inside(j);
+    const double2 bj = keep(jin, L.b), wdj = keep(jin, L.wd);
+    const double mj = jin ? L.m : 0.0;
+    const double2 u1c = cmul(bj, wdj);
+    // u2 and u3 on row j-1
+    const int i2 = j - 1;
     double2 u3c;
     {
+      const double2 sx = cadd(from_left(u1b), from_right(u1b));
+      const NodeC c = node_coef<true>(i2, x, gf.nz, gf.nx, ih, m1, f.omega, f.sM_re, f.sM_im);
+      const double2 sz = cadd(u1a, u1c);
+      const double2 u2 = cadd(u1b, cmul(csub(b1, stencil(c, ih2, u1b, sx, sz)), w1));
       double2 a = ox ? cscale(0.5, cadd(loa, lob)) : loa;
-      if (odd) {
+      if (odd_prev) {
         const double2 a2 = ox ? cscale(0.5, cadd(hia, hib)) : hia;
         a = cscale(0.5, cadd(a, a2));
       }
-      u3c = keep(xin && j >= 0 && j < gf.nz, cadd(L.u2, a));
+      u3c = keep(inside(i2), cadd(u2, a));
     }
-    // first sweep on row j-1
-    const int i4 = j - 1;
-    const bool in4 = xin && i4 >= 0 && i4 < gf.nz;
+    // first post-sweep on row j-2
+    const int i4 = j - 2;
     double2 u4c;
     {
       const double2 sx = cadd(from_left(u3b), from_right(u3b));
-      const NodeC c = node_coef<true>(i4, x, gf.nz, gf.nx, ih, L.m, f.omega, f.sM_re, f.sM_im);
+      const NodeC c = node_coef<true>(i4, x, gf.nz, gf.nx, ih, m2, f.omega, f.sM_re, f.sM_im);
       const double2 sz = cadd(u3a, u3c);
-      const double2 v = cadd(u3b, cmul(csub(L.b, stencil(c, ih2, u3b, sx, sz)), L.wd));
-      u4c = keep(in4, v);
+      u4c = keep(inside(i4), cadd(u3b, cmul(csub(b2, stencil(c, ih2, u3b, sx, sz)), w2)));
     }
-    // second sweep on row j-2
-    const int i5 = j - 2;
+    // second post-sweep on row j-3
+    const int i5 = j - 3;
     {
       const double2 sx = cadd(from_left(u4b), from_right(u4b));
       if (own && i5 >= w.z0 && i5 < w.z1) {
-        const NodeC c = node_coef<true>(i5, x, gf.nz, gf.nx, ih, m2, f.omega, f.sM_re, f.sM_im);
+        const NodeC c = node_coef<true>(i5, x, gf.nz, gf.nx, ih, m3, f.omega, f.sM_re, f.sM_im);
         const double2 sz = cadd(u4a, u4c);
-        const double2 res = csub(b2, stencil(c, ih2, u4b, sx, sz));
-        u_out[base + (size_t)i5 * gf.nx + x] = cadd(u4b, cmul(res, wd2));
+        const double2 res = csub(b3, stencil(c, ih2, u4b, sx, sz));
+        u_out[base + (size_t)i5 * gf.nx + x] = cadd(u4b, cmul(res, w3));
       }
     }
+    u1a = u1b;
+    u1b = u1c;
     u3a = u3b;
     u3b = u3c;
     u4a = u4b;
     u4b = u4c;
-    b2 = L.b;
-    wd2 = L.wd;
-    m2 = L.m;
+    b3 = b2;
+    b2 = b1;
+    b1 = bj;
+    w3 = w2;
+    w2 = w1;
+    w1 = wdj;
+    m3 = m2;
+    m2 = m1;
+    m1 = mj;
   };
-  // rows z0-2 .. z1+1 in pairs (even j, odd j+1); the pair uses coarse rows
-  // j/2 (carried from the previous pair) and j/2 + 1 (loaded with the pair)
+  // rows z0-3 .. z1+2 in pairs (odd j, even j+1): the step of row j forms u3
+  // on row j-1 (even, coarse row (j-1)/2 only) and the step of j+1 on row j
+  // (odd, coarse rows (j-1)/2 and (j+1)/2)
   double2 loa, lob;
-  load_coarse((w.z0 - 2) >> 1, loa, lob);
-  for (int j = w.z0 - 2; j <= w.z1 + 1; j += 2) {
+  load_coarse((w.z0 - 4) >> 1, loa, lob);
+  for (int j = w.z0 - 3; j <= w.z1 + 2; j += 2) {
     double2 hia, hib;
-    load_coarse((j >> 1) + 1, hia, hib);
+    load_coarse((j + 1) >> 1, hia, hib);
     const PostRow c0 = load_row(j), c1 = load_row(j + 1);
-    step(j, c0, loa, lob, hia, hib, false);
+    // row j-1 is even: its coarse row is (j-1)/2, held in lo
+    step(j, c0, loa, lob, loa, lob, false);
     step(j + 1, c1, loa, lob, hia, hib, true);
     loa = hia;
     lob = hib;
@@ -333,18 +356,17 @@ hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const 
 }
 
 hipError_t launch_post2(const Grid& gf, const Grid& gc, int lvl, const Batch& bt, int cap, const double2* e,
-                        const double2* b, const double2* u2, double2* u_out, size_t sf, size_t sc, int chunk_rows,
-                        hipStream_t st) {
+                        const double2* b, double2* u_out, size_t sf, size_t sc, int chunk_rows, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
   const StreamShape sh = stream_shape(gf, kPostWidth, chunk_rows);
   const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
   if (lvl == 0)
     hipLaunchKernelGGL(k_post2_s<true>, gr, dim3(kBlock), 0, st, gf, gc, sh.nstrip, sh.nchunk, chunk_rows,
-                       sh.groups, lvl, bt, e, b, u2, u_out, sf, sc);
+                       sh.groups, lvl, bt, e, b, u_out, sf, sc);
   else
     hipLaunchKernelGGL(k_post2_s<false>, gr, dim3(kBlock), 0, st, gf, gc, sh.nstrip, sh.nchunk, chunk_rows,
-                       sh.groups, lvl, bt, e, b, u2, u_out, sf, sc);
+                       sh.groups, lvl, bt, e, b, u_out, sf, sc);
   return hipGetLastError();
 }
 

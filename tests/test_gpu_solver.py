@@ -177,6 +177,33 @@ def test_unpreconditioned_path(hz):
     assert rel(to_np(u)[0, 0].ravel(), direct.solve_superlu(B, op.point_source(w.shape, w.h, [16]))) < 1e-8
 
 
+@pytest.mark.parametrize("shape", [(3, 3), (5, 5), (4, 7), (3,), (6,)])
+def test_tiny_grids(hz, shape):
+    """The smallest grids: one level (the dense exact inverse of M), and an
+    even-count grid that can be halved once."""
+    import torch
+    rng = np.random.default_rng(4)
+    m = 1.0 / rng.uniform(1500, 3000, size=shape)
+    h, f = 50.0, 6.0
+    c = make_ctx(hz, m, h)
+    n = int(np.prod(shape))
+    b = workloads.random_vectors(2, n, seed=2)
+    ref = direct.solve_dense(op.operator_B(m, h, 2 * np.pi * f, 0.01), b.T).T
+    for levels in sorted({1, lfa.max_levels(shape)}):
+        u, info = c.solve([f], 0.01, torch.from_numpy(b.reshape((1, 2) + shape)), tol=1e-12, levels=levels)
+        assert all(i[0] == hz.HZ_RHS_CONVERGED for i in info)
+        assert rel(to_np(u).reshape(2, -1), ref) <= 1e-9
+
+
+def test_empty_batch(hz):
+    import torch
+    w = workloads.model_2d_lens(n=33, h=40.0)
+    c = make_ctx(hz, w.m, w.h)
+    b = torch.empty((1, 0) + w.shape, dtype=torch.complex128, device="cuda")
+    u, info = c.solve([5.0], 0.01, b)
+    assert u.shape == b.shape and info == []
+
+
 def test_failure_paths(hz):
     import torch
     w = workloads.model_2d_lens(n=65, h=30.0)
