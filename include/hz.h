@@ -88,7 +88,8 @@ typedef struct {
     int    maxit;           /* iteration cap per right-hand side (default 10000) */
     int    precond;         /* HZ_PRECOND_* (default HZ_PRECOND_MG) */
     double beta1, beta2;    /* shift of M (default 1, 0.5); beta2 must be > 0 */
-    int    levels;          /* V-cycle levels incl. the finest; 0 = as many as the grid allows */
+    int    levels;          /* V-cycle levels incl. the finest; 0 = halve (an axis of n nodes to
+                               ceil(n/2)) until the coarsest level has at most 512 unknowns */
     int    nu1, nu2;        /* pre- and post-smoothing sweeps (default 2, 2) */
     double jacobi_w;        /* largest damped-Jacobi weight the plan may use (default 0.8) */
     const double *jacobi_w_level; /* host, optional: fixed weight per smoothing level
@@ -198,10 +199,14 @@ int  hz_gn_step(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq
 
 /* The level count and damped-Jacobi weights the solver will use for one
  * frequency (host computation, no device work): *levels and w[0..levels-2].
- * w must hold HZ_MAX_LEVELS doubles. The plan: coarsen while every axis has
- * n-1 even and a coarse size >= 3 (or o->levels if set); per smoothing
- * level, the largest weight in {0.8,...,0.2} not above o->jacobi_w whose
- * local-Fourier smoothing factor stays <= 1 over the level's kh range. */
+ * w must hold HZ_MAX_LEVELS doubles. The plan: o->levels if set, else halve
+ * (n -> ceil(n/2) per axis; with n even the last fine node is interpolated
+ * from the last coarse node) until the coarsest level has at most 512
+ * unknowns or an axis would drop below 3 nodes; per smoothing level, the
+ * largest weight in {0.8,...,0.2} not above o->jacobi_w whose local-Fourier
+ * smoothing factor stays <= 1 over the level's kh range.
+ * Errors: HZ_ERR_STATE (no model), HZ_ERR_SHAPE (o->levels above what the
+ * grid allows: halving while every axis keeps >= 3 nodes). */
 int  hz_plan(const hz_ctx *c, const hz_solve_opts *o, double freq_hz,
              int *levels, double *w);
 
