@@ -483,7 +483,7 @@ struct Cycle {
 // the real operands, at the first launch with that key, and keeps the
 // fastest. The kernels are pure (they never write what they read), so the
 // trial launches leave the same result as one launch.
-constexpr int kChunkCandidates[] = {8, 16, 32, 64, 128};
+constexpr int kChunkCandidates[] = {2, 4, 8, 16, 32, 64, 128};
 constexpr int kChunkDefault = 32;
 
 int octave(int cap) {
