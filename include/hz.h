@@ -67,6 +67,13 @@ typedef struct hz_ctx hz_ctx;
 #define HZ_PRECOND_EXACT 1   /* exact M^-1 (1D only: tridiagonal solve) */
 #define HZ_PRECOND_NONE  2
 
+/* solve on the coarsest multigrid level */
+#define HZ_COARSE_AUTO   0   /* exact, unless the level's smallest kh = omega h_c m_min is >= 2.5,
+                                where damped Jacobi converges for every mode (local Fourier
+                                analysis): then coarse_sweeps sweeps */
+#define HZ_COARSE_EXACT  1   /* dense inverse of M on that level, per frequency */
+#define HZ_COARSE_JACOBI 2   /* coarse_sweeps damped-Jacobi sweeps (weight 0.8) from zero */
+
 /* per right-hand-side status */
 #define HZ_RHS_CONVERGED 0
 #define HZ_RHS_MAXIT     1
@@ -100,6 +107,8 @@ typedef struct {
                                fixed shape. Results do not depend on the shape. */
     int    chunk_rows;      /* 0 (default): shape from the tuner (or fixed); > 0, even: grid
                                rows per wavefront for every fused V-cycle kernel */
+    int    coarse;          /* HZ_COARSE_* (default HZ_COARSE_AUTO) */
+    int    coarse_sweeps;   /* sweeps where the coarsest level is smoothed (default 2, 1..64) */
     int    graphs;          /* 1: BiCGSTAB iterations are captured in HIP graphs (two
                                iterations per graph, one graph per batch-size bucket) and
                                replayed; 0 (default): every launch issued one by one. Ignored

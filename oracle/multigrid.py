@@ -95,9 +95,15 @@ class VCycle:
     """One V-cycle V(nu1, nu2) as a fixed linear map b -> u ~ M^-1 b.
 
     wj: one damped-Jacobi weight per smoothing level (levels 0..L-2).
+    coarse: "exact" (sparse LU of M on the coarsest level), "jacobi"
+    (coarse_sweeps damped-Jacobi sweeps with weight coarse_w from zero) or
+    "auto" (jacobi where the coarsest level's smallest kh, omega times its
+    spacing times the smallest slowness of the model, is at least 2.5 --
+    there damped Jacobi contracts every mode -- else exact).
     """
 
-    def __init__(self, m, h, omega, beta1, beta2, levels, nu1=2, nu2=2, wj=None):
+    def __init__(self, m, h, omega, beta1, beta2, levels, nu1=2, nu2=2, wj=None, coarse="exact",
+                 coarse_sweeps=2, coarse_w=0.8):
         m = np.asarray(m, dtype=np.float64)
         if levels < 1:
             raise ValueError("levels must be >= 1")
@@ -120,7 +126,12 @@ class VCycle:
                 self.P.append(prolongation(cs, ml.shape))
                 self.R.append(restriction(cs, ml.shape))
                 ml, hl = inject(ml), 2 * hl
-        self.coarse_lu = factor_superlu(self.M[-1])
+        if coarse == "auto":
+            kh_min = omega * h * 2.0 ** (levels - 1) * float(np.min(m))
+            coarse = "jacobi" if levels > 1 and kh_min >= 2.5 else "exact"
+        self.coarse = coarse
+        self.coarse_sweeps, self.coarse_w = coarse_sweeps, coarse_w
+        self.coarse_lu = factor_superlu(self.M[-1]) if coarse == "exact" else None
         self.levels = levels
 
     def smooth(self, l, u, b, sweeps):
@@ -130,7 +141,12 @@ class VCycle:
 
     def cycle(self, l, b):
         if l == self.levels - 1:
-            return self.coarse_lu.solve(b)
+            if self.coarse == "exact":
+                return self.coarse_lu.solve(b)
+            u = np.zeros_like(b)
+            for _ in range(self.coarse_sweeps):
+                u = u + self.coarse_w * (b - self.M[l] @ u) / self.D[l]
+            return u
         u = np.zeros_like(b)
         u = self.smooth(l, u, b, self.nu1)
         rc = self.R[l] @ (b - self.M[l] @ u)
@@ -150,7 +166,13 @@ def vcycle_matrix(vc):
     else the coarser V-cycle's matrix). The V-cycle's matrix is then
     C_l = (I - E_l) M_l^-1. Dense; for tiny grids only.
     """
-    C = np.linalg.inv(vc.M[-1].toarray())
+    Mc = vc.M[-1].toarray()
+    if vc.coarse == "exact":
+        C = np.linalg.inv(Mc)
+    else:
+        # k sweeps from zero: u = (I - S^k) M^-1 b with S = I - w D^-1 M
+        S = np.eye(Mc.shape[0]) - vc.coarse_w * (Mc / vc.D[-1][:, None])
+        C = (np.eye(Mc.shape[0]) - np.linalg.matrix_power(S, vc.coarse_sweeps)) @ np.linalg.inv(Mc)
     for l in range(vc.levels - 2, -1, -1):
         M = vc.M[l].toarray()
         n = M.shape[0]

@@ -28,6 +28,8 @@ HZ_BICGSTAB, HZ_GMRES = 0, 1
 HZ_PRECOND_MG, HZ_PRECOND_EXACT, HZ_PRECOND_NONE = 0, 1, 2
 HZ_RHS_CONVERGED, HZ_RHS_MAXIT, HZ_RHS_BREAKDOWN, HZ_RHS_NONFINITE = 0, 1, 2, 3
 HZ_MAX_LEVELS = 12
+HZ_COARSE_AUTO, HZ_COARSE_EXACT, HZ_COARSE_JACOBI = 0, 1, 2
+COARSE = {"auto": HZ_COARSE_AUTO, "exact": HZ_COARSE_EXACT, "jacobi": HZ_COARSE_JACOBI}
 HZ_KERNEL = {"smooth": 0, "apply": 1, "restrict": 2, "prolong": 3, "update": 4, "coarse": 5, "presmooth": 6,
              "presmooth_s": 7, "apply_s": 8}
 
@@ -46,7 +48,8 @@ class SolveOpts(ctypes.Structure):
                 ("beta2", ctypes.c_double), ("levels", ctypes.c_int), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("jacobi_w", ctypes.c_double),
                 ("jacobi_w_level", ctypes.POINTER(ctypes.c_double)), ("autotune", ctypes.c_int),
-                ("chunk_rows", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("chunk_rows", ctypes.c_int), ("coarse", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
+                ("graphs", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -120,7 +123,7 @@ def default_opts():
 
 def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg", beta=(1.0, 0.5),
               levels=0, nu=(2, 2), jacobi_w=0.8, jacobi_w_level=None, autotune=True, chunk_rows=0,
-              graphs=False):
+              graphs=False, coarse="auto", coarse_sweeps=2):
     """Build an hz_solve_opts; returns (opts, keepalive)."""
     o = default_opts()
     o.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
@@ -135,6 +138,8 @@ def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg"
     o.autotune = 1 if autotune else 0
     o.chunk_rows = int(chunk_rows)
     o.graphs = 1 if graphs else 0
+    o.coarse = COARSE[coarse] if isinstance(coarse, str) else int(coarse)
+    o.coarse_sweeps = int(coarse_sweeps)
     keep = None
     if jacobi_w_level is not None:
         keep = (ctypes.c_double * max(1, len(jacobi_w_level)))(*[float(w) for w in jacobi_w_level])

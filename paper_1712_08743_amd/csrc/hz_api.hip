@@ -116,6 +116,7 @@ struct hz_ctx {
   // keyed by (kernel, nz, nx, batch-size octave)
   std::map<std::array<int, 4>, int> tuned_chunk;
   hipStream_t graph_stream = nullptr;  // the library's own stream, used only to capture graphs
+  bool any_coarse_jacobi = false;      // set by setup_freqs for the running solve
   int tune_mode = 1;   // opts.autotune of the running solve
   int fixed_chunk = 0; // opts.chunk_rows of the running solve
 };
@@ -281,6 +282,8 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
     return fail(c, HZ_ERR_ARG, "chunk_rows must be 0 or an even number up to 65536");
   if (o->autotune != 0 && o->autotune != 1) return fail(c, HZ_ERR_ARG, "autotune must be 0 or 1");
   if (o->graphs != 0 && o->graphs != 1) return fail(c, HZ_ERR_ARG, "graphs must be 0 or 1");
+  if (o->coarse < HZ_COARSE_AUTO || o->coarse > HZ_COARSE_JACOBI) return fail(c, HZ_ERR_ARG, "unknown coarse solve");
+  if (o->coarse_sweeps < 1 || o->coarse_sweeps > 64) return fail(c, HZ_ERR_ARG, "coarse_sweeps must be in [1, 64]");
   if (o->precond == HZ_PRECOND_EXACT) {
     if (c->dim != 1) return fail(c, HZ_ERR_ARG, "the exact preconditioner is the 1D tridiagonal solve");
     const size_t lds = (size_t)4 * c->nx * sizeof(double2);
@@ -395,6 +398,18 @@ int setup_freqs(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq
     }
   }
   const bool need_coarse = o->precond == HZ_PRECOND_MG;
+  c->any_coarse_jacobi = false;
+  if (need_coarse && levels > 1) {
+    // damped Jacobi on the coarsest level converges for every mode once its
+    // smallest kh reaches 2.5 (local Fourier analysis of the shifted Laplacian)
+    const double hc = c->lv[levels - 1].h;
+    for (int f = 0; f < nfreq; ++f) {
+      const bool jac = o->coarse == HZ_COARSE_JACOBI ||
+                       (o->coarse == HZ_COARSE_AUTO && ft[f].omega * hc * c->mmin >= 2.5);
+      ft[f].coarse_jacobi = jac ? 1 : 0;
+      c->any_coarse_jacobi = c->any_coarse_jacobi || jac;
+    }
+  }
   if (need_coarse) {
     const int cl = levels - 1;
     const size_t nc = c->lv[cl].n();
@@ -473,6 +488,7 @@ void fold_timing(hz_ctx* c) {
 struct Cycle {
   int levels, nu1, nu2, precond;
   int autotune, chunk_rows;  // launch shape of the fused kernels (opts.autotune, opts.chunk_rows)
+  int coarse_sweeps;         // > 0: some frequency smooths its coarsest level with this many sweeps
 };
 
 // ---------------------------------------------------------------- launch-shape tuning
@@ -484,6 +500,7 @@ struct Cycle {
 // fastest. The kernels are pure (they never write what they read), so the
 // trial launches leave the same result as one launch.
 constexpr int kChunkCandidates[] = {2, 4, 8, 16, 32, 64, 128};
+constexpr double kCoarseJacobiW = 0.8;  // weight of the coarsest-level sweeps (HZ_COARSE_JACOBI)
 constexpr int kChunkDefault = 32;
 
 int octave(int cap) {
@@ -617,6 +634,12 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
            return launch_coarse_solve((int)c->lv[cl].n(), c->cur_nfreq, c->cur_nrhs, bt, c->lev[cl][kLb].as<double2>(),
                                       c->lev[cl][kLu].as<double2>(), c->lv[cl].n(), st);
          })) != hipSuccess)
+      return e;
+    // frequencies whose coarsest level is smoothed (the exact solve skipped them)
+    if (cy.coarse_sweeps > 0 &&
+        (e = launch_coarse_jacobi(dim, grid_of(c, cl), cl, kCoarseJacobiW, cy.coarse_sweeps, bt, cap,
+                                  c->lev[cl][kLb].as<double2>(), c->lev[cl][kLx].as<double2>(),
+                                  c->lev[cl][kLu].as<double2>(), c->lv[cl].n(), st)) != hipSuccess)
       return e;
   }
   // ascend
@@ -1042,6 +1065,8 @@ void hz_default_opts(hz_solve_opts* o) {
   o->jacobi_w_level = nullptr;
   o->autotune = 1;
   o->chunk_rows = 0;
+  o->coarse = HZ_COARSE_AUTO;
+  o->coarse_sweeps = 2;
   o->graphs = 0;
 }
 
@@ -1248,7 +1273,8 @@ int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz
   if ((rc = ensure_workspace(c, nslots, levels)) != HZ_OK) return rc;
   if ((rc = setup_freqs(c, o, nfreq, freq_hz, alpha, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nslots, nrhs)) != HZ_OK) return rc;
-  const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows};
+  const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0};
   const double2* b = reinterpret_cast<const double2*>(b_dev);
   double2* x = reinterpret_cast<double2*>(u_dev);
   if (o->krylov == HZ_BICGSTAB) {
@@ -1622,7 +1648,8 @@ int hz_precond(hz_ctx* c, const hz_solve_opts* o, double freq_hz, int nrhs, cons
   if ((rc = ensure_workspace(c, nrhs, levels)) != HZ_OK) return rc;
   if ((rc = setup_freqs(c, o, 1, &freq_hz, 0.0, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nrhs, nrhs)) != HZ_OK) return rc;
-  const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows};
+  const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0};
   HZ_HIP(c, precond_apply(c, cy, nrhs, reinterpret_cast<const double2*>(b_dev), reinterpret_cast<double2*>(u_dev)));
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   return HZ_OK;

@@ -39,6 +39,7 @@ struct FreqTab {
   double sM_re, sM_im;  // mass shift of M: beta1 - j beta2
   double wj[kMaxLevels];
   const double2* cinv;               // inverse of M on the coarsest level, [nc][nc]
+  int coarse_jacobi;                 // 1: the coarsest level is smoothed, not solved exactly
   const double2* winv[kMaxLevels];   // w_l / diag(M_l) on each smoothing level, [n_l]
 };
 
@@ -143,6 +144,10 @@ hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const 
 // two pre-sweeps from zero on b formed again (as launch_pre2r forms them)
 hipError_t launch_post2(const Grid& gf, const Grid& gc, int lvl, const Batch& bt, int cap, const double2* e,
                         const double2* b, double2* u_out, size_t sf, size_t sc, int chunk_rows, hipStream_t st);
+// u_out = `sweeps` damped-Jacobi sweeps (weight w) from zero on level lvl, for
+// the slots whose frequency has coarse_jacobi set; tmp is a work vector
+hipError_t launch_coarse_jacobi(int dim, const Grid& g, int lvl, double w, int sweeps, const Batch& bt, int cap,
+                                const double2* b, double2* tmp, double2* u_out, size_t stride, hipStream_t st);
 hipError_t launch_coarse_solve(int nc, int nfreq, int nrhs, const Batch& bt, const double2* bc,
                                double2* uc, size_t stride, hipStream_t st);
 hipError_t launch_pcr(const Grid& g, const Batch& bt, int cap, const double2* b, double2* u,

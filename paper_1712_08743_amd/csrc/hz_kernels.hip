@@ -73,17 +73,19 @@ __global__ void __launch_bounds__(kBlock) k_apply(Grid g, Tiles t, int lvl, int 
 }
 
 // u_out = u_in + w (b - M u_in) / diag(M); ZERO: u_in = 0.
+// coarse_only: only slots whose frequency smooths its coarsest level
 template <bool D2, bool ZERO>
 __global__ void __launch_bounds__(kBlock) k_smooth(Grid g, Tiles t, int lvl, double w_override,
                                                    Batch bt, const double2* __restrict__ b,
                                                    const double2* __restrict__ u_in,
-                                                   double2* __restrict__ u_out, size_t stride) {
+                                                   double2* __restrict__ u_out, size_t stride, int coarse_only) {
   int slot, tile;
   if (!decode_tile(bt, t.per_slot, slot, tile)) return;
   int iz, ix;
   tile_node<D2>(t, tile, iz, ix);
   if (iz >= g.nz || ix >= g.nx) return;
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  if (coarse_only && !f.coarse_jacobi) return;
   const int p = iz * g.nx + ix;
   const double ih2 = 1.0 / (g.h * g.h);
   const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
@@ -471,6 +473,7 @@ __global__ void __launch_bounds__(kCoarseWaves * 64) k_coarse(int nc, Batch bt,
                                                               const double2* __restrict__ bc,
                                                               double2* __restrict__ uc, size_t stride) {
   const int f = blockIdx.z;
+  if (bt.ft[f].coarse_jacobi) return;  // that frequency's coarsest level is smoothed instead
   const int lo = bt.fstart[f], hi = bt.fstart[f + 1];
   const int s0 = lo + blockIdx.y * 16;
   if (s0 >= hi) return;  // uniform over the block
@@ -781,14 +784,14 @@ hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, con
   }
   if (dim == 2) {
     if (u_in)
-      hipLaunchKernelGGL((k_smooth<true, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride);
+      hipLaunchKernelGGL((k_smooth<true, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride, 0);
     else
-      hipLaunchKernelGGL((k_smooth<true, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride);
+      hipLaunchKernelGGL((k_smooth<true, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride, 0);
   } else {
     if (u_in)
-      hipLaunchKernelGGL((k_smooth<false, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride);
+      hipLaunchKernelGGL((k_smooth<false, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride, 0);
     else
-      hipLaunchKernelGGL((k_smooth<false, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride);
+      hipLaunchKernelGGL((k_smooth<false, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride, 0);
   }
   return hipGetLastError();
 }
@@ -859,6 +862,28 @@ hipError_t launch_prolong_smooth(int dim, const Grid& gf, const Grid& gc, int lv
                        ntx * ntz, lvl, bt, e, b, u2, u_out, sf, sc);
   } else
     hipLaunchKernelGGL(k_prolong_smooth<false>, gr, dim3(kBlock), 0, st, gf, gc, t, lvl, bt, e, b, u2, u_out, sf, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_jacobi(int dim, const Grid& g, int lvl, double w, int sweeps, const Batch& bt, int cap,
+                                const double2* b, double2* tmp, double2* u_out, size_t stride, hipStream_t st) {
+  if (cap <= 0 || sweeps < 1) return hipSuccess;
+  const Tiles t = grid_tiles(g.nz, g.nx, dim);
+  const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
+  // ping-pong so that the last sweep lands in u_out
+  double2* cur = (sweeps % 2 == 1) ? u_out : tmp;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_smooth<true, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, nullptr, cur, stride, 1);
+  else
+    hipLaunchKernelGGL((k_smooth<false, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, nullptr, cur, stride, 1);
+  for (int k = 1; k < sweeps; ++k) {
+    double2* nxt = (cur == u_out) ? tmp : u_out;
+    if (dim == 2)
+      hipLaunchKernelGGL((k_smooth<true, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, cur, nxt, stride, 1);
+    else
+      hipLaunchKernelGGL((k_smooth<false, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, cur, nxt, stride, 1);
+    cur = nxt;
+  }
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ def test_status_strings_and_defaults():
     assert o.krylov == hz.HZ_BICGSTAB and o.tol == 1e-8 and o.nu1 == 2 and o.nu2 == 2
     assert (o.beta1, o.beta2) == (1.0, 0.5) and o.jacobi_w == 0.8 and o.gmres_m == 30
     assert o.autotune == 1 and o.chunk_rows == 0 and o.graphs == 0
+    assert o.coarse == hz.HZ_COARSE_AUTO and o.coarse_sweeps == 2
 
 
 @pytest.mark.parametrize("shape,h,f,cmin,cmax", [

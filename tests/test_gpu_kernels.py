@@ -134,8 +134,31 @@ def test_vcycle(hz, shape, h, levels, nu):
     n = int(np.prod(shape))
     b = workloads.random_vectors(3, n, seed=11)
     out = to_np(c.precond(f, torch.from_numpy(b.reshape((3,) + shape)).cuda(), levels=levels,
-                          nu=nu, beta=beta, jacobi_w_level=wj)).reshape(3, -1)
+                          nu=nu, beta=beta, jacobi_w_level=wj, coarse="exact")).reshape(3, -1)
     for k in range(3):
+        assert rel(out[k], vc(b[k])) < TOL_CYCLE
+
+
+@pytest.mark.parametrize("mode,f", [("jacobi", 3.0), ("auto", 12.0), ("auto", 1.0)])
+def test_vcycle_coarse_smoothing(hz, mode, f):
+    """The coarsest level smoothed by damped-Jacobi sweeps instead of solved;
+    "auto" smooths it only where its smallest kh is >= 2.5 (12 Hz here,
+    not 1 Hz)."""
+    import torch
+    shape, h = (65, 129), 40.0
+    m = random_model(shape, 13)
+    c = ctx_for(hz, m, h)
+    L = c.plan(f)[0]
+    wj = [0.8, 0.7, 0.5, 0.3, 0.3][:L - 1]
+    hc = h * 2 ** (L - 1)
+    kh_min = 2 * np.pi * f * hc * m.min()
+    jac = mode == "jacobi" or kh_min >= 2.5
+    assert jac == (mode == "jacobi" or f == 12.0)
+    vc = mg.VCycle(m, h, 2 * np.pi * f, 1.0, 0.5, L, 2, 2, wj, coarse="jacobi" if jac else "exact", coarse_sweeps=5)
+    b = workloads.random_vectors(2, m.size, seed=14)
+    out = to_np(c.precond(f, torch.from_numpy(b.reshape((2,) + shape)).cuda(), jacobi_w_level=wj,
+                          coarse=mode, coarse_sweeps=5)).reshape(2, -1)
+    for k in range(2):
         assert rel(out[k], vc(b[k])) < TOL_CYCLE
 
 
@@ -149,7 +172,7 @@ def test_vcycle_uses_the_lfa_plan(hz):
     f = 4.0
     L, wj = lfa.plan(w.shape, w.h, 2 * np.pi * f, w.m.min(), w.m.max(), 1.0, 0.5)
     assert c.plan(f) == (L, wj)
-    vc = mg.VCycle(w.m, w.h, 2 * np.pi * f, 1.0, 0.5, L, 2, 2, wj)
+    vc = mg.VCycle(w.m, w.h, 2 * np.pi * f, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
     b = workloads.random_vectors(2, w.m.size, seed=12)
     out = to_np(c.precond(f, torch.from_numpy(b.reshape((2,) + w.shape)).cuda())).reshape(2, -1)
     for k in range(2):

@@ -82,7 +82,7 @@ def test_c2_lens_vcycle(hz, sign, tol):
     err = rel(ug, ulu)
     assert err < (1e-6 if tol == 1e-8 else 1e-9), err
     assert np.linalg.norm(bn - B @ ug) / np.linalg.norm(bn) <= 2 * tol
-    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 4, 2, 2, [0.8] * 3)
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 4, 2, 2, [0.8] * 3, coarse="auto")
     _, it_o, _, _ = krylov.bicgstab(B, bn, vc, tol=tol, maxit=500)
     assert iters_close(it, it_o), (it, it_o)
 
@@ -103,7 +103,7 @@ def test_multi_frequency_multi_shot_batch(hz):
         B = op.operator_B(w.m, w.h, om, w.alpha)
         lu = direct.factor_superlu(B)
         L, wj = lfa.plan(w.shape, w.h, om, w.m.min(), w.m.max(), 1.0, 0.5)
-        vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj)
+        vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
         for s in range(ns):
             st, it, rr = info[fi * ns + s]
             assert st == hz.HZ_RHS_CONVERGED and rr <= 1e-8
@@ -193,6 +193,23 @@ def test_tiny_grids(hz, shape):
         u, info = c.solve([f], 0.01, torch.from_numpy(b.reshape((1, 2) + shape)), tol=1e-12, levels=levels)
         assert all(i[0] == hz.HZ_RHS_CONVERGED for i in info)
         assert rel(to_np(u).reshape(2, -1), ref) <= 1e-9
+
+
+def test_coarse_smoothing_solve_matches_direct(hz):
+    """A batch mixing frequencies whose coarsest level is solved exactly and
+    smoothed (coarse="auto") still converges to the direct solution."""
+    import torch
+    w = workloads.model_2d_layered(nz=65, nx=129, h=40.0, nshots=3, freqs=(1.0, 12.0))
+    c = make_ctx(hz, w.m, w.h)
+    b1 = c.point_rhs([0] * 3, w.src)
+    b = torch.stack([b1, b1]).contiguous()
+    u, info = c.solve(w.freqs, 0.01, b, tol=1e-10, coarse="auto", coarse_sweeps=8)
+    assert all(i[0] == hz.HZ_RHS_CONVERGED for i in info)
+    bn = to_np(b1).reshape(3, -1)
+    for k, f in enumerate(w.freqs):
+        lu = direct.factor_superlu(op.operator_B(w.m, w.h, 2 * np.pi * f, 0.01))
+        ref = np.array([lu.solve(x) for x in bn])
+        assert rel(to_np(u[k]).reshape(3, -1), ref) <= 1e-7
 
 
 def test_empty_batch(hz):
@@ -302,7 +319,7 @@ def test_gmres_matches_oracle(hz, m, tol):
     u, info = c.solve([f], w.alpha, b[None], krylov="gmres", gmres_m=m, levels=4, nu=(2, 2),
                       jacobi_w_level=[0.8] * 3, tol=tol, maxit=3000)
     B = op.operator_B(w.m, w.h, om, w.alpha)
-    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 4, 2, 2, [0.8] * 3)
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 4, 2, 2, [0.8] * 3, coarse="auto")
     for s, ix in enumerate((100, 37)):
         st, it, rr = info[s]
         assert st == hz.HZ_RHS_CONVERGED and rr <= tol

@@ -119,6 +119,32 @@ def test_vcycle_equals_explicit_error_propagation(shape, levels, nu):
     assert np.linalg.norm(C - Minv) > 1e-6 * np.linalg.norm(Minv)
 
 
+@pytest.mark.parametrize("shape", [(17, 17), (10, 18)])
+def test_vcycle_with_jacobi_coarse_level(shape):
+    """Coarsest level smoothed (k sweeps from zero) instead of solved: the
+    cycle equals the error-propagation matrix with (I - S^k) M_c^-1 there."""
+    rng = np.random.default_rng(8)
+    m = 1.0 / rng.uniform(1500, 3000, size=shape)
+    vc = mg.VCycle(m, 40.0, 2 * np.pi * 6.0, 1.0, 0.5, 3, 2, 2, [0.8, 0.7], coarse="jacobi", coarse_sweeps=5)
+    C = mg.vcycle_matrix(vc)
+    b = rng.standard_normal(m.size) + 1j * rng.standard_normal(m.size)
+    assert np.allclose(vc(b), C @ b, rtol=1e-11, atol=1e-14 * np.abs(C @ b).max())
+
+
+def test_jacobi_converges_on_coarse_level_at_large_kh():
+    """Damped Jacobi (w = 0.8) on the shifted Laplacian (1, 0.5) contracts
+    every mode when the level's smallest kh is >= 2.5 (brute-force spectral
+    radius of the iteration matrix), but not at small kh."""
+    for n, h, f, contracts in [(9, 320.0, 12.0, True), (9, 320.0, 8.0, True), (9, 320.0, 1.0, False)]:
+        m = np.full((n, n), 1 / 3000.0)
+        kh_min = 2 * np.pi * f * h * m.min()
+        M = op.operator_M(m, h, 2 * np.pi * f, 1.0, 0.5).toarray()
+        S = np.eye(n * n) - 0.8 * M / np.diag(M)[:, None]
+        rho = np.abs(np.linalg.eigvals(S)).max()
+        assert (kh_min >= 2.5) == contracts
+        assert (rho < 1.0) == contracts, (f, kh_min, rho)
+
+
 def test_one_level_is_exact_inverse_of_M():
     rng = np.random.default_rng(6)
     m = 1 / rng.uniform(1500, 3000, size=(201,))
