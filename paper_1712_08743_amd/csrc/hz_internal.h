@@ -122,8 +122,9 @@ hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch&
 hipError_t launch_prolong(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                           const double2* e, const double2* u_in, double2* u_out, size_t sf,
                           size_t sc, hipStream_t st);
-// mode 0: b given (in_a); 1: b = p = in_a + beta (in_b - omega in_c) stored to bout;
-// 2: b = s = in_a - alpha in_b stored to bout. u2 = two Jacobi sweeps from zero.
+// 1D grids: mode 0: b given (in_a); 1: b = p = in_a + beta (in_b - omega in_c)
+// stored to bout; 2: b = s = in_a - alpha in_b stored to bout. u2 = two
+// Jacobi sweeps from zero. (2D grids use launch_pre2r.)
 hipError_t launch_pre2(int dim, const Grid& g, int lvl, int mode, const Batch& bt, int cap,
                        const double2* in_a, const double2* in_b, const double2* in_c, double2* bout,
                        double2* u2, size_t stride, hipStream_t st);

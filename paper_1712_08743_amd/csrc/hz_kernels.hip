@@ -273,51 +273,6 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth(Grid gf, Grid gc, Til
 
 // ---- LDS-tiled forms of the three smoothing kernels (2D grids)
 
-// Two sweeps from zero (see k_pre2) with u1 = (w/D) b staged in LDS on the
-// tile and its halo; b of the tile's own nodes is kept for the residual.
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_pre2_t(Grid g, int ntx, int per_slot, int lvl, Batch bt,
-                                                   RhsIn in, double2* __restrict__ bout,
-                                                   double2* __restrict__ u2, size_t stride) {
-  __shared__ double2 U1[kHZ][kHX];
-  __shared__ double2 Bt[kTZ][kTX];
-  int slot, tile;
-  if (!decode_tile(bt, per_slot, slot, tile)) return;
-  const Slot& S = bt.slots[slot];
-  const FreqTab& f = bt.ft[S.freq];
-  double2 beta = c2(0.0, 0.0), om = c2(0.0, 0.0), al = c2(0.0, 0.0);
-  if (MODE == 1) {
-    beta = S.beta;
-    om = S.omega;
-  }
-  if (MODE == 2) al = S.alpha;
-  const TileOrg t = tile_org(tile, ntx);
-  const size_t base = (size_t)slot * stride;
-  const double2* wd = f.winv[lvl];
-  fill_halo(U1, g, t, [&](int q, int hz, int hx) {
-    const double2 b = rhs_at<MODE>(in, base + q, beta, om, al);
-    if (hz >= 1 && hz <= kTZ && hx >= 1 && hx <= kTX) Bt[hz - 1][hx - 1] = b;
-    return cmul(b, wd[q]);
-  });
-  __syncthreads();
-  const double ih = 1.0 / g.h, ih2 = ih * ih;
-#pragma unroll
-  for (int r = 0; r < kRowsPerThread; ++r) {
-    const int lz = threadIdx.x / kTX + (kBlock / kTX) * r, lx = threadIdx.x % kTX;
-    const int iz = t.z0 + lz, ix = t.x0 + lx;
-    if (iz >= g.nz || ix >= g.nx) continue;
-    const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, g.m[p], f.omega, f.sM_re, f.sM_im);
-    double2 sx, sz;
-    halo_sums(U1, lz, lx, sx, sz);
-    const double2 u1p = U1[lz + 1][lx + 1];
-    const double2 b = Bt[lz][lx];
-    const double2 res = csub(b, stencil(c, ih2, u1p, sx, sz));
-    u2[base + p] = cadd(u1p, cmul(res, wd[p]));
-    if (MODE != 0) bout[base + p] = b;
-  }
-}
-
 // One sweep from a nonzero start, u staged in LDS.
 __global__ void __launch_bounds__(kBlock) k_smooth_t(Grid g, int ntx, int per_slot, int lvl, Batch bt,
                                                      const double2* __restrict__ b,
@@ -828,24 +783,16 @@ hipError_t launch_prolong(int dim, const Grid& gf, const Grid& gc, const Batch& 
 hipError_t launch_pre2(int dim, const Grid& g, int lvl, int mode, const Batch& bt, int cap,
                        const double2* in_a, const double2* in_b, const double2* in_c, double2* bout,
                        double2* u2, size_t stride, hipStream_t st) {
+  // 2D grids take the fused pre-smoothing and restriction kernel (launch_pre2r)
+  if (dim != 1) return hipErrorInvalidValue;
   const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
   const RhsIn in{in_a, in_b, in_c};
-#define HZ_PRE2(D2, M) hipLaunchKernelGGL((k_pre2<D2, M>), gr, dim3(kBlock), 0, st, g, t, lvl, bt, in, bout, u2, stride)
-  if (dim == 2) {
-    const int ntx = (g.nx + kTX - 1) / kTX, ntz = (g.nz + kTZ - 1) / kTZ;
-    const dim3 gt = grid1(tile_blocks(ntx * ntz, cap));
-#define HZ_PRE2T(M) hipLaunchKernelGGL((k_pre2_t<M>), gt, dim3(kBlock), 0, st, g, ntx, ntx * ntz, lvl, bt, in, bout, u2, stride)
-    if (mode == 0) HZ_PRE2T(0);
-    else if (mode == 1) HZ_PRE2T(1);
-    else HZ_PRE2T(2);
-#undef HZ_PRE2T
-  } else {
-    if (mode == 0) HZ_PRE2(false, 0);
-    else if (mode == 1) HZ_PRE2(false, 1);
-    else HZ_PRE2(false, 2);
-  }
+#define HZ_PRE2(M) hipLaunchKernelGGL((k_pre2<false, M>), gr, dim3(kBlock), 0, st, g, t, lvl, bt, in, bout, u2, stride)
+  if (mode == 0) HZ_PRE2(0);
+  else if (mode == 1) HZ_PRE2(1);
+  else HZ_PRE2(2);
 #undef HZ_PRE2
   return hipGetLastError();
 }
