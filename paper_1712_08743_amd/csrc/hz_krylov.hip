@@ -188,7 +188,10 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_omega(Grid g, Tiles t, Ba
 }
 
 // x += alpha ph + omega sh; r = s - omega t; partials <rh, r> and ||r||^2.
-__global__ void __launch_bounds__(kBlock) k_bicg_xr(Batch bt, int tiles, size_t n, Reduce rd,
+// Eight streams per node and little arithmetic: on whole tiles the loads of
+// all kVecPerThread nodes are issued at once, which needs about 110 VGPRs,
+// so the occupancy target is lowered to four waves per SIMD to allow it.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) k_bicg_xr(Batch bt, int tiles, size_t n, Reduce rd,
                                                     double2* __restrict__ x,
                                                     const double2* __restrict__ ph,
                                                     const double2* __restrict__ sh,
@@ -202,18 +205,39 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr(Batch bt, int tiles, size_t 
   const double2 al = S0.alpha, om = S0.omega;
   const size_t base = (size_t)slot * stride;
   double acc[3] = {0.0, 0.0, 0.0};
+  auto node = [&](size_t q, double2 xq, double2 phq, double2 shq, double2 sq, double2 tq, double2 rhq) {
+    x[q] = cadd(xq, cadd(cmul(al, phq), cmul(om, shq)));
+    const double2 ri = csub(sq, cmul(om, tq));
+    r[q] = ri;
+    const double2 d = cconjmul(rhq, ri);
+    acc[0] += d.x;
+    acc[1] += d.y;
+    acc[2] += ri.x * ri.x + ri.y * ri.y;
+  };
+  if ((size_t)(tile + 1) * kVecPerThread * kBlock <= n) {
+    // whole tile inside the vector: every load of the thread issued before the first use
+    double2 X[kVecPerThread], PH[kVecPerThread], SH[kVecPerThread], S[kVecPerThread], T[kVecPerThread],
+        RH[kVecPerThread];
 #pragma unroll
-  for (int e = 0; e < kVecPerThread; ++e) {
-    const size_t i = vec_index(tile, e);
-    if (i < n) {
-      const size_t q = base + i;
-      x[q] = cadd(x[q], cadd(cmul(al, ph[q]), cmul(om, sh[q])));
-      const double2 ri = csub(s[q], cmul(om, t[q]));
-      r[q] = ri;
-      const double2 d = cconjmul(rh[q], ri);
-      acc[0] += d.x;
-      acc[1] += d.y;
-      acc[2] += ri.x * ri.x + ri.y * ri.y;
+    for (int e = 0; e < kVecPerThread; ++e) {
+      const size_t q = base + vec_index(tile, e);
+      X[e] = x[q];
+      PH[e] = ph[q];
+      SH[e] = sh[q];
+      S[e] = s[q];
+      T[e] = t[q];
+      RH[e] = rh[q];
+    }
+#pragma unroll
+    for (int e = 0; e < kVecPerThread; ++e) node(base + vec_index(tile, e), X[e], PH[e], SH[e], S[e], T[e], RH[e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < kVecPerThread; ++e) {
+      const size_t i = vec_index(tile, e);
+      if (i < n) {
+        const size_t q = base + i;
+        node(q, x[q], ph[q], sh[q], s[q], t[q], rh[q]);
+      }
     }
   }
   store_partial<3>(acc, rd, slot, tile);
