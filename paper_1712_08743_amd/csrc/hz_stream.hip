@@ -11,9 +11,9 @@
 // only the neighbouring strip stores), and a chunk starts and ends the same
 // number of rows early and late. Every load is a contiguous 64-node row.
 //
-// The arithmetic of every node is written exactly as in the LDS-tiled
-// kernels (same operands, same order), so results do not depend on which
-// form runs.
+// A smoothing sweep is written in the Jacobi form (see jacobi()), which
+// needs only w/D and the real couplings, so its result can differ from the
+// LDS-tiled kernels' residual form in the last bits.
 
 #include "hz_device.h"
 
@@ -29,6 +29,45 @@ __device__ __forceinline__ double2 from_left(double2 v) {  // value of lane - 1
 __device__ __forceinline__ double2 from_right(double2 v) {  // value of lane + 1
   return make_double2(__shfl_down(v.x, 1, kLanes), __shfl_down(v.y, 1, kLanes));
 }
+// Coefficients of the stencil of node_coef / stencil split by what they
+// depend on: the column (fixed per lane) and the row (the same over the
+// wavefront); only the shifted/absorbing term kap needs the node's slowness.
+struct AxisC {
+  double w, e, l;  // weight (1/2 at an end node), end nodes at the index (0..2), 2 - e
+};
+__device__ __forceinline__ AxisC axis_coef(int i, int n) {
+  const int e = (i == 0) + (i == n - 1);
+  AxisC a;
+  a.w = e ? 0.5 : 1.0;
+  a.e = (double)e;
+  a.l = (double)(2 - e);
+  return a;
+}
+// (M x)_p = (lsum x_p - wz sx - wx sz) / h^2 + kap x_p with lsum = wz lx + wx lz,
+// kap = -omega^2 s wx wz m^2 + i omega g m / h and g = wz ex + wx ez;
+// ka = -omega^2 Re s, kb = -omega^2 Im s, kc = omega / h
+__device__ __forceinline__ double2 apply_m(const AxisC& cx, const AxisC& rz, double m, double ka, double kb,
+                                           double kc, double ih2, double2 xp, double2 sx, double2 sz) {
+  const double g = rz.w * cx.e + cx.w * rz.e;
+  const double mw = (cx.w * rz.w) * (m * m);
+  const double kre = ka * mw, kim = kb * mw + kc * g * m;
+  const double lsum = rz.w * cx.l + cx.w * rz.l;
+  const double lre = lsum * xp.x - rz.w * sx.x - cx.w * sz.x;
+  const double lim = lsum * xp.y - rz.w * sx.y - cx.w * sz.y;
+  return c2(ih2 * lre + (kre * xp.x - kim * xp.y), ih2 * lim + (kre * xp.y + kim * xp.x));
+}
+// One damped-Jacobi update u + (w/D)(b - M u) at a node, written as
+// (1 - w) u + (w/D)(b + (wz sx + wx sz) / h^2): the couplings of M to the
+// neighbours are real and its diagonal D (which holds the complex shift and
+// the absorbing term) enters only through wd = w/D, so the slowness is not
+// needed. cz = wz / h^2, cx = wx / h^2, omw = 1 - w.
+__device__ __forceinline__ double2 jacobi(double2 u, double2 b, double2 wd, double2 sx, double2 sz, double cz,
+                                          double cx, double omw) {
+  const double tx = cz * sx.x + (cx * sz.x + b.x);
+  const double ty = cz * sx.y + (cx * sz.y + b.y);
+  return c2(omw * u.x + (wd.x * tx - wd.y * ty), omw * u.y + (wd.x * ty + wd.y * tx));
+}
+
 // v where c holds, else zero (selected per component, so no stack copy is made)
 __device__ __forceinline__ double2 keep(bool c, double2 v) {
   return make_double2(c ? v.x : 0.0, c ? v.y : 0.0);
@@ -106,6 +145,11 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
   const size_t base = (size_t)w.slot * stride;
   const double2* wd = f.winv[lvl];
   const double ih = 1.0 / g.h, ih2 = ih * ih;
+  const double om2 = f.omega * f.omega;
+  const double ka = -om2 * f.sM_re, kb = -om2 * f.sM_im, kc = f.omega * ih;
+  const double omw = 1.0 - f.wj[lvl];
+  const AxisC cx = axis_coef(x, g.nx);
+  const double cwx = ih2 * cx.w;
   const double2 zero = c2(0.0, 0.0);
   auto load_row = [&](int j) {
     PreRow<MODE> r;
@@ -135,9 +179,8 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
     double2 u2c = zero;
     {
       const double2 sx = cadd(from_left(u1b), from_right(u1b));
-      const NodeC c = node_coef<true>(i2, x, g.nz, g.nx, ih, m1, f.omega, f.sM_re, f.sM_im);
       const double2 sz = cadd(u1a, u1c);
-      const double2 v = cadd(u1b, cmul(csub(b1, stencil(c, ih2, u1b, sx, sz)), wd1));
+      const double2 v = jacobi(u1b, b1, wd1, sx, sz, ih2 * axis_coef(i2, g.nz).w, cwx, omw);
       u2c = keep(xin && i2 >= 0 && i2 < g.nz, v);
     }
     if (own && i2 >= w.z0 && i2 < w.z1) {
@@ -150,9 +193,8 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
     double2 rc = zero;
     {
       const double2 sx = cadd(from_left(u2b), from_right(u2b));
-      const NodeC c = node_coef<true>(ir, x, g.nz, g.nx, ih, m2, f.omega, f.sM_re, f.sM_im);
       const double2 sz = cadd(u2a, u2c);
-      const double2 v = csub(b2, stencil(c, ih2, u2b, sx, sz));
+      const double2 v = csub(b2, apply_m(cx, axis_coef(ir, g.nz), m2, ka, kb, kc, ih2, u2b, sx, sz));
       rc = keep(xin && ir >= 0 && ir < g.nz, v);
     }
     // full weighting to coarse row (ir - 1) / 2 once rows ir-2 .. ir are known
@@ -203,9 +245,8 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
 // HBM traffic per node: b and u_out, plus e on the coarse grid.
 constexpr int kPostWidth = kLanes - 6;
 
-struct PostRow {  // loads of one row j: b, w/D and m
+struct PostRow {  // loads of one row j: b and w/D
   double2 b, wd;
-  double m;
 };
 
 template <bool FINE>
@@ -226,6 +267,8 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
   const double2* bs = b + base;
   const double2* wd = f.winv[lvl];
   const double ih = 1.0 / gf.h, ih2 = ih * ih;
+  const double omw = 1.0 - f.wj[lvl];
+  const double cwx = ih2 * axis_coef(x, gf.nx).w;
   const double2 zero = c2(0.0, 0.0);
   const int ox = x & 1;
   const int Jx = xx >> 1, Jx1 = min(Jx + 1, gc.nx - 1);
@@ -234,7 +277,6 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
     const size_t q = (size_t)min(max(j, 0), gf.nz - 1) * gf.nx + xx;
     r.b = bs[q];
     r.wd = wd[q];
-    r.m = gf.m[q];
     return r;
   };
   auto load_coarse = [&](int cr, double2& ea, double2& eb) {
@@ -244,24 +286,21 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
   };
   auto inside = [&](int j) { return xin && j >= 0 && j < gf.nz; };
   // rolling rows: u1 on j-2, j-1; u3 on j-3, j-2; u4 on j-4, j-3;
-  // b, w/D, m on j-1, j-2, j-3
+  // b, w/D on j-1, j-2, j-3
   double2 u1a = zero, u1b = zero, u3a = zero, u3b = zero, u4a = zero, u4b = zero;
   double2 b1 = zero, b2 = zero, b3 = zero, w1 = zero, w2 = zero, w3 = zero;
-  double m1 = 0.0, m2 = 0.0, m3 = 0.0;
   // lo, hi: coarse rows (j-1) >> 1 and the one below it
   auto step = [&](int j, const PostRow& L, double2 loa, double2 lob, double2 hia, double2 hib, bool odd_prev) {
     const bool jin = inside(j);
     const double2 bj = keep(jin, L.b), wdj = keep(jin, L.wd);
-    const double mj = jin ? L.m : 0.0;
     const double2 u1c = cmul(bj, wdj);
     // u2 and u3 on row j-1
     const int i2 = j - 1;
     double2 u3c;
     {
       const double2 sx = cadd(from_left(u1b), from_right(u1b));
-      const NodeC c = node_coef<true>(i2, x, gf.nz, gf.nx, ih, m1, f.omega, f.sM_re, f.sM_im);
       const double2 sz = cadd(u1a, u1c);
-      const double2 u2 = cadd(u1b, cmul(csub(b1, stencil(c, ih2, u1b, sx, sz)), w1));
+      const double2 u2 = jacobi(u1b, b1, w1, sx, sz, ih2 * axis_coef(i2, gf.nz).w, cwx, omw);
       double2 a = ox ? cscale(0.5, cadd(loa, lob)) : loa;
       if (odd_prev) {
         const double2 a2 = ox ? cscale(0.5, cadd(hia, hib)) : hia;
@@ -274,19 +313,16 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
     double2 u4c;
     {
       const double2 sx = cadd(from_left(u3b), from_right(u3b));
-      const NodeC c = node_coef<true>(i4, x, gf.nz, gf.nx, ih, m2, f.omega, f.sM_re, f.sM_im);
       const double2 sz = cadd(u3a, u3c);
-      u4c = keep(inside(i4), cadd(u3b, cmul(csub(b2, stencil(c, ih2, u3b, sx, sz)), w2)));
+      u4c = keep(inside(i4), jacobi(u3b, b2, w2, sx, sz, ih2 * axis_coef(i4, gf.nz).w, cwx, omw));
     }
     // second post-sweep on row j-3
     const int i5 = j - 3;
     {
       const double2 sx = cadd(from_left(u4b), from_right(u4b));
       if (own && i5 >= w.z0 && i5 < w.z1) {
-        const NodeC c = node_coef<true>(i5, x, gf.nz, gf.nx, ih, m3, f.omega, f.sM_re, f.sM_im);
         const double2 sz = cadd(u4a, u4c);
-        const double2 res = csub(b3, stencil(c, ih2, u4b, sx, sz));
-        u_out[base + (size_t)i5 * gf.nx + x] = cadd(u4b, cmul(res, w3));
+        u_out[base + (size_t)i5 * gf.nx + x] = jacobi(u4b, b3, w3, sx, sz, ih2 * axis_coef(i5, gf.nz).w, cwx, omw);
       }
     }
     u1a = u1b;
@@ -301,9 +337,6 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
     w3 = w2;
     w2 = w1;
     w1 = wdj;
-    m3 = m2;
-    m2 = m1;
-    m1 = mj;
   };
   // rows z0-3 .. z1+2 in pairs (odd j, even j+1): the step of row j forms u3
   // on row j-1 (even, coarse row (j-1)/2 only) and the step of j+1 on row j
