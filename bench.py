@@ -93,7 +93,7 @@ def percentile(vals, q):
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
 
 
-def cpu_baseline(w, iters_per_freq, sample_iters=8, shot=31):
+def cpu_baseline(w, iters_per_freq, sample_iters=48, shot=31):
     """Time the oracle (plain FP64 CPU: SciPy sparse matrices, BiCGSTAB, V-cycle)
     on a bounded sample: one shot per frequency, capped at sample_iters
     BiCGSTAB iterations after its setup. Scaled to the full 256-right-hand-side
