@@ -21,6 +21,19 @@ namespace hz {
 
 // ---------------------------------------------------------------- complex helpers
 __device__ __forceinline__ double2 c2(double a, double b) { return make_double2(a, b); }
+
+// Streaming (non-temporal) 16-byte accesses for vectors a kernel touches once.
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(double2* p, double2 a) {
+  d2v v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<d2v*>(p));
+}
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return c2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return c2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double s, double2 a) { return c2(s * a.x, s * a.y); }

@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     double2 sx, sz;
     halo_sums(X, lz, lx, sx, sz);
     const double2 yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
-    y[base + p] = yp;
+    st_nt(y + base + p, yp);
     if (WHICH == 0) {
       const double2 d = cconjmul(other[base + p], yp);
       acc[0] += d.x;
@@ -206,9 +206,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
   const size_t base = (size_t)slot * stride;
   double acc[3] = {0.0, 0.0, 0.0};
   auto node = [&](size_t q, double2 xq, double2 phq, double2 shq, double2 sq, double2 tq, double2 rhq) {
-    x[q] = cadd(xq, cadd(cmul(al, phq), cmul(om, shq)));
+    st_nt(x + q, cadd(xq, cadd(cmul(al, phq), cmul(om, shq))));
     const double2 ri = csub(sq, cmul(om, tq));
-    r[q] = ri;
+    st_nt(r + q, ri);
     const double2 d = cconjmul(rhq, ri);
     acc[0] += d.x;
     acc[1] += d.y;
@@ -221,12 +221,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
     for (int e = 0; e < kVecPerThread; ++e) {
       const size_t q = base + vec_index(tile, e);
-      X[e] = x[q];
-      PH[e] = ph[q];
-      SH[e] = sh[q];
-      S[e] = s[q];
-      T[e] = t[q];
-      RH[e] = rh[q];
+      X[e] = ld_nt(x + q);
+      PH[e] = ld_nt(ph + q);
+      SH[e] = ld_nt(sh + q);
+      S[e] = ld_nt(s + q);
+      T[e] = ld_nt(t + q);
+      RH[e] = ld_nt(rh + q);
     }
 #pragma unroll
     for (int e = 0; e < kVecPerThread; ++e) node(base + vec_index(tile, e), X[e], PH[e], SH[e], S[e], T[e], RH[e]);

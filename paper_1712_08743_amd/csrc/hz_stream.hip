@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
     }
     if (own && i2 >= w.z0 && i2 < w.z1) {
       const size_t q = base + (size_t)i2 * g.nx + x;
-      if (MODE != 0) bout[q] = b1;
+      if (MODE != 0) st_nt(bout + q, b1);
       if (u2) u2[q] = u2c;
     }
     // residual on row j-2
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
       const double2 sx = cadd(from_left(u4b), from_right(u4b));
       if (own && i5 >= w.z0 && i5 < w.z1) {
         const double2 sz = cadd(u4a, u4c);
-        u_out[base + (size_t)i5 * gf.nx + x] = jacobi(u4b, b3, w3, sx, sz, ih2 * axis_coef(i5, gf.nz).w, cwx, omw);
+        st_nt(u_out + base + (size_t)i5 * gf.nx + x, jacobi(u4b, b3, w3, sx, sz, ih2 * axis_coef(i5, gf.nz).w, cwx, omw));
       }
     }
     u1a = u1b;
