@@ -82,6 +82,7 @@ struct hz_ctx {
   DevBuf lev[kMaxLevels][kNumLevelVec];
   int ws_slots = 0, ws_levels = 0;
   DevBuf slots, active, nactive, freqtab, partials, resid, fstart;
+  DevBuf rh_idx, rh_val;  // sparse shadow residuals, [slot_cap][kShadowMax]
   int cur_nfreq = 1, cur_nrhs = 1;  // layout of the slots of the current batch
   int partial_tiles = 0;
   int slot_cap = 0;
@@ -313,6 +314,8 @@ int ensure_workspace(hz_ctx* c, int nslots, int levels) {
     const int cap = std::max(nslots, c->slot_cap);
     HZ_ALLOC(c, c->partials, (size_t)cap * tiles * kPartialWidth * sizeof(double));
     HZ_ALLOC(c, c->slots, (size_t)cap * sizeof(Slot));
+    HZ_ALLOC(c, c->rh_idx, (size_t)cap * kShadowMax * sizeof(int));
+    HZ_ALLOC(c, c->rh_val, (size_t)cap * kShadowMax * sizeof(double2));
     HZ_ALLOC(c, c->active, (size_t)cap * sizeof(int));
     HZ_ALLOC(c, c->nactive, sizeof(int) * 4);
     HZ_ALLOC(c, c->resid, (size_t)cap * 2 * sizeof(double));
@@ -338,6 +341,8 @@ Batch batch_of(const hz_ctx* c) {
   b.slots = c->slots.as<Slot>();
   b.ft = c->freqtab.as<FreqTab>();
   b.fstart = c->fstart.as<int>();
+  b.rh_idx = c->rh_idx.as<int>();
+  b.rh_val = c->rh_val.as<double2>();
   return b;
 }
 
@@ -364,6 +369,7 @@ int reset_slots(hz_ctx* c, int nslots, int nrhs) {
     memset(&s[i], 0, sizeof(Slot));
     s[i].status = kActive;
     s[i].freq = i / nrhs;
+    s[i].rh_nnz = -1;
   }
   HZ_HIP(c, hipMemcpyAsync(c->slots.p, s.data(), nslots * sizeof(Slot), hipMemcpyHostToDevice, c->stream));
   return reset_list(c, nslots, nrhs);
@@ -722,7 +728,8 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   const int gt = reduce_tiles(c->lv[0].nz, c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
   int rc;
   HZ_HIP(c, launch_bicg_init(n0, bt, nslots, rd, b, x, r, rh, p, v, n0, st));
-  HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, st));
+  HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
+  HZ_HIP(c, launch_rh_sparse(n0, nslots, bt, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st));
   if ((rc = close_unit()) != HZ_OK) return rc;
 
   int cap = nslots;
@@ -752,7 +759,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
              return launch_bicg_apply_sigma(c->dim, g0, bt, capx, rd, ph, rh, v, n0, sx);
            })) != hipSuccess)
         break;
-      if ((e = launch_bicg_fin(kFinSigma, gt, bt, capx, rd, o->tol, o->maxit, sx)) != hipSuccess) break;
+      if ((e = launch_bicg_fin(kFinSigma, gt, bt, capx, rd, o->tol, o->maxit, v, n0, sx)) != hipSuccess) break;
       if (fused) {
         const FineRhs fr{2, r, v, nullptr, s};
         if ((e = precond_apply(c, cy, capx, nullptr, sh, &fr)) != hipSuccess) break;
@@ -764,12 +771,13 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
              return launch_bicg_apply_omega(c->dim, g0, bt, capx, rd, sh, s, t, n0, sx);
            })) != hipSuccess)
         break;
-      if ((e = launch_bicg_fin(kFinOmega, gt, bt, capx, rd, o->tol, o->maxit, sx)) != hipSuccess) break;
+      if ((e = launch_bicg_fin(kFinOmega, gt, bt, capx, rd, o->tol, o->maxit, nullptr, n0, sx)) != hipSuccess)
+        break;
       if ((e = timed(c, HZ_KERNEL_UPDATE, [&] {
              return launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx);
            })) != hipSuccess)
         break;
-      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, sx);
+      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx);
     } while (false);
     c->stream = saved;
     return e;
@@ -838,7 +846,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
         cap = std::min(cap, sm.nactive);
         if (sm.nrestart > 0) {
           HZ_HIP(c, launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st));  // current p buffer
-          HZ_HIP(c, launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, st));
+          HZ_HIP(c, launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
           restart_seq = seq;
           if ((rc = close_unit()) != HZ_OK) return rc;
           cap = nslots;

@@ -52,7 +52,14 @@ struct Slot {
   int phase;                  // GMRES: 0 = Arnoldi steps, 1 = cycle end pending
   int cyc_k;                  // GMRES: Arnoldi steps taken in the current cycle
   double2 scal;               // GMRES: divisor of the newest basis vector (real part)
+  int rh_nnz;                 // BiCGSTAB: nonzeros of the shadow residual r^ held in the sparse
+                              // list (Batch::rh_idx/rh_val), -1: r^ is used as a dense vector
 };
+
+// A shadow residual r^ = b with at most this many nonzeros (point sources,
+// receiver sets) is also kept as a list, and the inner products with it are
+// formed from the list instead of streaming r^.
+constexpr int kShadowMax = 256;
 
 // GMRES(m) per-slot small arrays (device): Hessenberg matrix column-major
 // H[slot][j*(m+1) + i], right-hand side g, rotations (cs, sn), solution y and the
@@ -76,6 +83,8 @@ struct Batch {
   Slot* slots;
   const FreqTab* ft;
   const int* fstart;   // [nfreq + 1]: the list's entries of frequency f are fstart[f]..fstart[f+1]-1
+  const int* rh_idx;      // [capacity][kShadowMax] node indices of r^'s nonzeros, ascending
+  const double2* rh_val;  // [capacity][kShadowMax] their values
 };
 
 // Scratch for deterministic per-slot reductions: block partial sums.
@@ -185,10 +194,17 @@ hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, 
 hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
                                const double2* r, double2* rh, double2* p, double2* v,
                                size_t stride, hipStream_t st);
+// The sparse list of r^ = b for every one of the nslots slots (rh_nnz = -1
+// where b has more than kShadowMax nonzeros). idx/val: the arrays Batch
+// points to, writable.
+hipError_t launch_rh_sparse(size_t n, int nslots, const Batch& bt, const double2* b, int* idx, double2* val,
+                            size_t stride, hipStream_t st);
 enum : int { kFinInit = 0, kFinSigma = 1, kFinOmega = 2, kFinStep = 3, kFinRestart = 4 };
 // tiles: the producer's tiles per slot; restart runs over all nslots slots.
+// vec: for sigma v, for step r (the inner products with a sparse r^ are
+// formed here from it); unused otherwise.
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
-                           double tol, int maxit, hipStream_t st);
+                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st);
 hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* active, int* nactive,
                           int* fstart, Summary* sum, int want_phase, hipStream_t st);
 hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,

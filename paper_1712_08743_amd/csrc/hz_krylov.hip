@@ -88,15 +88,18 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const size_t base = (size_t)slot * stride;
   double acc[2] = {0.0, 0.0};
+  const bool dense_rh = bt.slots[slot].rh_nnz < 0;  // else <rh, v> is formed from the sparse list
   if (iz < g.nz && ix < g.nx) {
     const int p = iz * g.nx + ix;
     const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
     const double2* xs = ph + base;
     const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
     v[base + p] = y;
-    const double2 d = cconjmul(rh[base + p], y);
-    acc[0] = d.x;
-    acc[1] = d.y;
+    if (dense_rh) {
+      const double2 d = cconjmul(rh[base + p], y);
+      acc[0] = d.x;
+      acc[1] = d.y;
+    }
   }
   store_partial<2>(acc, rd, slot, tile);
 }
@@ -118,6 +121,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
   fill_halo(X, g, t, [&](int q, int, int) { return xs[q]; });
   __syncthreads();
   const double ih = 1.0 / g.h, ih2 = ih * ih;
+  // WHICH 0 with a sparse r^: <rh, v> is formed from the list by the reduction kernel
+  const bool dots = WHICH == 1 || bt.slots[slot].rh_nnz < 0;
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < kRowsPerThread; ++r) {
@@ -131,9 +136,11 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     const double2 yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
     st_nt(y + base + p, yp);
     if (WHICH == 0) {
-      const double2 d = cconjmul(other[base + p], yp);
-      acc[0] += d.x;
-      acc[1] += d.y;
+      if (dots) {
+        const double2 d = cconjmul(other[base + p], yp);
+        acc[0] += d.x;
+        acc[1] += d.y;
+      }
     } else {
       const double2 d = cconjmul(yp, other[base + p]);
       acc[0] += d.x;
@@ -203,6 +210,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
   if (!decode_vec(bt, tiles, slot, tile)) return;
   const Slot& S0 = bt.slots[slot];
   const double2 al = S0.alpha, om = S0.omega;
+  const bool dense_rh = S0.rh_nnz < 0;  // else <rh, r> is formed from the sparse list
   const size_t base = (size_t)slot * stride;
   double acc[3] = {0.0, 0.0, 0.0};
   auto node = [&](size_t q, double2 xq, double2 phq, double2 shq, double2 sq, double2 tq, double2 rhq) {
@@ -226,7 +234,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
       SH[e] = ld_nt(sh + q);
       S[e] = ld_nt(s + q);
       T[e] = ld_nt(t + q);
-      RH[e] = ld_nt(rh + q);
+      RH[e] = dense_rh ? ld_nt(rh + q) : c2(0.0, 0.0);
     }
 #pragma unroll
     for (int e = 0; e < kVecPerThread; ++e) node(base + vec_index(tile, e), X[e], PH[e], SH[e], S[e], T[e], RH[e]);
@@ -236,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
       const size_t i = vec_index(tile, e);
       if (i < n) {
         const size_t q = base + i;
-        node(q, x[q], ph[q], sh[q], s[q], t[q], rh[q]);
+        node(q, x[q], ph[q], sh[q], s[q], t[q], dense_rh ? rh[q] : c2(0.0, 0.0));
       }
     }
   }
@@ -270,6 +278,44 @@ __global__ void __launch_bounds__(kBlock) k_bicg_restart(int tiles, size_t n, Ba
   store_partial<2>(acc, rd, slot, tile);
 }
 
+// The sparse list of r^ = b (one block per slot): the nonzeros are found in
+// one coalesced pass and appended to an LDS list in any order, then each is
+// written at its rank by node index, so the list is in ascending order
+// whatever order the appends took. More than kShadowMax nonzeros:
+// rh_nnz = -1 (r^ stays a dense vector).
+__global__ void __launch_bounds__(kBlock) k_rh_sparse(size_t n, Batch bt, const double2* __restrict__ b,
+                                                      int* __restrict__ idx, double2* __restrict__ val,
+                                                      size_t stride) {
+  __shared__ int count;
+  __shared__ int sidx[kShadowMax];
+  __shared__ double2 sval[kShadowMax];
+  const int slot = blockIdx.x;
+  const double2* bs = b + (size_t)slot * stride;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  for (size_t i = threadIdx.x; i < n; i += kBlock) {
+    const double2 bi = bs[i];
+    if (bi.x != 0.0 || bi.y != 0.0) {
+      const int k = atomicAdd(&count, 1);
+      if (k < kShadowMax) {
+        sidx[k] = (int)i;
+        sval[k] = bi;
+      }
+    }
+  }
+  __syncthreads();
+  const int total = count;
+  if (threadIdx.x == 0) bt.slots[slot].rh_nnz = total <= kShadowMax ? total : -1;
+  if (total > kShadowMax) return;
+  for (int k = threadIdx.x; k < total; k += kBlock) {
+    const int ik = sidx[k];
+    int rank = 0;
+    for (int j = 0; j < total; ++j) rank += sidx[j] < ik;
+    idx[(size_t)slot * kShadowMax + rank] = ik;
+    val[(size_t)slot * kShadowMax + rank] = sval[k];
+  }
+}
+
 // ---------------------------------------------------------------- BiCGSTAB scalars
 // One block per slot: fixed-order sum of the producer's partials, then the
 // scalar step of the method (van der Vorst's BiCGSTAB, right-preconditioned):
@@ -280,7 +326,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_restart(int tiles, size_t n, Ba
 //            beta = (rho'/rho)(alpha/omega)
 //   restart: rho = beta = <r, r>, rh = r done by the producer
 __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch bt, Reduce rd,
-                                                     double tol, int maxit) {
+                                                     double tol, int maxit, const double2* __restrict__ vec,
+                                                     size_t stride) {
   int slot;
   if (which == kFinRestart) {
     slot = blockIdx.x;
@@ -288,8 +335,27 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
   } else if (!decode_slot_block(bt, slot)) {
     return;
   }
-  double acc[3];
-  sum_partials<3>(acc, rd, slot, tiles);
+  // <rh, v> (sigma) or <rh, r> (step) from r^'s sparse list, in list order,
+  // in place of the producer's partials (which hold zeros there)
+  const int nnz = bt.slots[slot].rh_nnz;
+  const bool sparse = (which == kFinSigma || which == kFinStep) && nnz >= 0;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const double* src = rd.partials + (size_t)slot * rd.max_tiles * kPartialWidth;
+  for (int k = threadIdx.x; k < tiles; k += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] += src[(size_t)k * kPartialWidth + q];
+  }
+  if (sparse) {
+    const int* idx = bt.rh_idx + (size_t)slot * kShadowMax;
+    const double2* val = bt.rh_val + (size_t)slot * kShadowMax;
+    const double2* vs = vec + (size_t)slot * stride;
+    for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
+      const double2 d = cconjmul(val[k], vs[idx[k]]);
+      acc[0] += d.x;
+      acc[1] += d.y;
+    }
+  }
+  block_sum<3>(acc);
   if (threadIdx.x != 0) return;
   Slot& S = bt.slots[slot];
   switch (which) {
@@ -361,6 +427,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
     case kFinRestart: {
       const double2 rho = c2(acc[0], acc[1]);
       S.restarted = 1;
+      S.rh_nnz = -1;  // r^ = r from here on, dense
       S.alpha = c2(1.0, 0.0);
       S.omega = c2(1.0, 0.0);
       if (!cfinite(rho)) {
@@ -865,9 +932,17 @@ hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Redu
 }
 
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
-                           double tol, int maxit, hipStream_t st) {
+                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bicg_fin, dim3(cap), dim3(kBlock), 0, st, which, tiles, bt, rd, tol, maxit);
+  if ((which == kFinSigma || which == kFinStep) && !vec) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bicg_fin, dim3(cap), dim3(kBlock), 0, st, which, tiles, bt, rd, tol, maxit, vec, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_rh_sparse(size_t n, int nslots, const Batch& bt, const double2* b, int* idx, double2* val,
+                            size_t stride, hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rh_sparse, dim3(nslots), dim3(kBlock), 0, st, n, bt, b, idx, val, stride);
   return hipGetLastError();
 }
 

@@ -212,6 +212,43 @@ def test_coarse_smoothing_solve_matches_direct(hz):
         assert rel(to_np(u[k]).reshape(3, -1), ref) <= 1e-7
 
 
+def test_sparse_and_dense_shadow_residuals(hz):
+    """r^ = b is kept as a list when b has at most 256 nonzeros (inner
+    products with r^ formed from the list) and streamed as a vector
+    otherwise. Point sources, 256 and 257 nonzeros, a dense b and b = 0 in one
+    batch: every slot converges to the direct solution, the point source in
+    the oracle's iteration count, and a slot gives the same bits alone."""
+    import torch
+    w = workloads.model_2d_lens(n=65, h=30.0)
+    c = make_ctx(hz, w.m, w.h)
+    rng = np.random.default_rng(11)
+    n = w.shape[0] * w.shape[1]
+    bs = np.zeros((5, n), dtype=np.complex128)
+    bs[0] = op.point_source(w.shape, w.h, [20])
+    for k, nnz in ((1, 256), (2, 257)):
+        pos = rng.choice(n, size=nnz, replace=False)
+        bs[k, pos] = rng.standard_normal(nnz) + 1j * rng.standard_normal(nnz)
+    bs[3] = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    b = torch.from_numpy(bs.reshape((1, 5) + w.shape)).cuda()
+    f = 5.0
+    u, info = c.solve([f], 0.01, b, tol=1e-10)
+    om = 2 * np.pi * f
+    B = op.operator_B(w.m, w.h, om, 0.01)
+    lu = direct.factor_superlu(B)
+    for k in range(4):
+        assert info[k][0] == hz.HZ_RHS_CONVERGED, (k, info[k])
+        assert rel(to_np(u[0, k]).ravel(), lu.solve(bs[k])) <= 1e-7, k
+    assert info[4] == (hz.HZ_RHS_CONVERGED, 0, 0.0)
+    L, wj = lfa.plan(w.shape, w.h, om, w.m.min(), w.m.max(), 1.0, 0.5)
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
+    _, it_o, _, _ = krylov.bicgstab(B, bs[0], vc, tol=1e-10, maxit=2000)
+    assert iters_close(info[0][1], it_o), (info[0][1], it_o)
+    for k in (0, 1, 2):
+        u1, info1 = c.solve([f], 0.01, b[:, k:k + 1].contiguous(), tol=1e-10)
+        assert torch.equal(u1[0, 0], u[0, k]), k
+        assert info1[0][1] == info[k][1]
+
+
 def test_empty_batch(hz):
     import torch
     w = workloads.model_2d_lens(n=33, h=40.0)
