@@ -57,7 +57,8 @@ struct LevelInfo {
 };
 
 // Fine-level vectors of the solvers (x is the caller's output buffer).
-enum FineVec { kR, kRh, kP, kP2, kV, kPh, kS, kSh, kT, kT1, kT2, kNumFine };
+enum FineVec { kR, kRh, kP, kP2, kV, kPh, kPh2, kS, kSh, kSh2, kT, kT1, kT2, kNumFine };
+static_assert(kNumFine == kFineVectors, "the footprint counts kFineVectors fine vectors");
 // Per coarse level: right-hand side, result, two smoothing buffers.
 enum LevelVec { kLb, kLu, kLx, kLy, kNumLevelVec };
 
@@ -707,8 +708,16 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   double2* t = c->fine[kT].as<double2>();
   const bool identity = cy.precond == HZ_PRECOND_NONE;
   const bool fused = fused_pre(cy);
-  double2* ph = c->fine[kPh].as<double2>();
-  double2* sh = identity ? s : c->fine[kSh].as<double2>();
+  // The iterate is advanced every second iteration: p^ and s^ of iteration
+  // 2k (ring 0) stay in their buffers while 2k+1 (ring 1) writes the others,
+  // and ring 1's update adds both terms (one read and write of x instead of
+  // two). Without a preconditioner s^ = s is overwritten at once, so x is
+  // advanced every iteration.
+  const bool defer = !identity;
+  double2* const phr[2] = {c->fine[kPh].as<double2>(), c->fine[kPh2].as<double2>()};
+  double2* const shr[2] = {identity ? s : c->fine[kSh].as<double2>(), identity ? s : c->fine[kSh2].as<double2>()};
+  double2* ph = phr[0];
+  double2* sh = shr[0];
 
   long long seq = 0;                 // units issued
   long long restart_seq = -1;        // last unit that was a restart
@@ -739,10 +748,15 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
 
   // One BiCGSTAB iteration for the first `capx` entries of the active list,
   // issued on stream `sx` (every launch of the path reads c->stream).
-  auto issue_iteration = [&](int capx, hipStream_t sx) -> hipError_t {
+  auto issue_iteration = [&](int capx, hipStream_t sx, int ring) -> hipError_t {
     const hipStream_t saved = c->stream;
     c->stream = sx;
     hipError_t e = hipSuccess;
+    const int rg = defer ? ring : -1;
+    if (!identity) {
+      ph = phr[ring];
+      sh = shr[ring];
+    }
     // p_new = r + beta (p_old - omega v) into the other p buffer, then ph = V p_new
     double2* pn = (p == pbuf[0]) ? pbuf[1] : pbuf[0];
     do {
@@ -774,10 +788,10 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       if ((e = launch_bicg_fin(kFinOmega, gt, bt, capx, rd, o->tol, o->maxit, nullptr, n0, sx)) != hipSuccess)
         break;
       if ((e = timed(c, HZ_KERNEL_UPDATE, [&] {
-             return launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx);
+             return launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx, rg, phr[0], shr[0]);
            })) != hipSuccess)
         break;
-      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx);
+      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx, rg);
     } while (false);
     c->stream = saved;
     return e;
@@ -812,16 +826,16 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
     auto it = graphs.find(cb);
     if (it == graphs.end() && eager_pairs[cb] == 0) {
       eager_pairs[cb] = 1;
-      HZ_HIP(c, issue_iteration(cb, st));
-      HZ_HIP(c, issue_iteration(cb, st));
+      HZ_HIP(c, issue_iteration(cb, st, 0));
+      HZ_HIP(c, issue_iteration(cb, st, 1));
       return HZ_OK;
     }
     if (it == graphs.end()) {
       if (!c->graph_stream) HZ_HIP(c, hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking));
       hipGraph_t gr = nullptr;
       HZ_HIP(c, hipStreamBeginCapture(c->graph_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e = issue_iteration(cb, c->graph_stream);
-      if (e == hipSuccess) e = issue_iteration(cb, c->graph_stream);
+      hipError_t e = issue_iteration(cb, c->graph_stream, 0);
+      if (e == hipSuccess) e = issue_iteration(cb, c->graph_stream, 1);
       const hipError_t e2 = hipStreamEndCapture(c->graph_stream, &gr);
       if (e == hipSuccess) e = e2;
       hipGraphExec_t ex = nullptr;
@@ -845,6 +859,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       if (!stale) {
         cap = std::min(cap, sm.nactive);
         if (sm.nrestart > 0) {
+          if (defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 1, x, phr[0], shr[0], n0, st));
           HZ_HIP(c, launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st));  // current p buffer
           HZ_HIP(c, launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
           restart_seq = seq;
@@ -866,11 +881,13 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       if ((rc = issue_pair_graph(cap)) != HZ_OK) return rc;
       iters_issued += 2;
     } else {
-      HZ_HIP(c, issue_iteration(cap, st));
+      HZ_HIP(c, issue_iteration(cap, st, (int)(iters_issued & 1)));
       ++iters_issued;
     }
     if ((rc = close_unit()) != HZ_OK) return rc;
   }
+  // terms of slots that stopped after a ring-0 update
+  if (defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 0, x, phr[0], shr[0], n0, st));
   HZ_HIP(c, hipStreamSynchronize(st));
   fold_timing(c);
   return HZ_OK;

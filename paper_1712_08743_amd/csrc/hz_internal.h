@@ -54,12 +54,18 @@ struct Slot {
   double2 scal;               // GMRES: divisor of the newest basis vector (real part)
   int rh_nnz;                 // BiCGSTAB: nonzeros of the shadow residual r^ held in the sparse
                               // list (Batch::rh_idx/rh_val), -1: r^ is used as a dense vector
+  int pending;                // BiCGSTAB: pend_alpha ph0 + pend_omega sh0 not yet added to x
+  double2 pend_alpha, pend_omega;
 };
 
 // A shadow residual r^ = b with at most this many nonzeros (point sources,
 // receiver sets) is also kept as a list, and the inner products with it are
 // formed from the list instead of streaming r^.
 constexpr int kShadowMax = 256;
+
+// Complex vectors per right-hand side on the finest grid (r, r^, two p
+// buffers, v, two p^ buffers, s, two s^ buffers, t and two smoothing buffers).
+constexpr int kFineVectors = 13;
 
 // GMRES(m) per-slot small arrays (device): Hessenberg matrix column-major
 // H[slot][j*(m+1) + i], right-hand side g, rotations (cs, sn), solution y and the
@@ -188,9 +194,16 @@ hipError_t launch_bicg_s(size_t n, const Batch& bt, int cap, const double2* r, c
 hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int cap,
                                    const Reduce& rd, const double2* sh, const double2* s,
                                    double2* t, size_t stride, hipStream_t st);
+// ring -1: x += alpha ph + omega sh; ring 0: x unchanged, the term left
+// pending (recorded by the step reduction); ring 1: x += pending term (ph0,
+// sh0: ring 0's buffers) + alpha ph + omega sh.
 hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, double2* x,
                           const double2* ph, const double2* sh, const double2* s, const double2* t,
-                          double2* r, const double2* rh, size_t stride, hipStream_t st);
+                          double2* r, const double2* rh, size_t stride, hipStream_t st, int ring = -1,
+                          const double2* ph0 = nullptr, const double2* sh0 = nullptr);
+// Adds the pending term to x (all nslots slots, or only those about to restart).
+hipError_t launch_bicg_flush(size_t n, int nslots, const Batch& bt, int only_restart, double2* x,
+                             const double2* ph0, const double2* sh0, size_t stride, hipStream_t st);
 hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
                                const double2* r, double2* rh, double2* p, double2* v,
                                size_t stride, hipStream_t st);
@@ -203,8 +216,10 @@ enum : int { kFinInit = 0, kFinSigma = 1, kFinOmega = 2, kFinStep = 3, kFinResta
 // tiles: the producer's tiles per slot; restart runs over all nslots slots.
 // vec: for sigma v, for step r (the inner products with a sparse r^ are
 // formed here from it); unused otherwise.
+// ring (step only): 0 records the update's term as pending, 1 clears it.
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
-                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st);
+                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st,
+                           int ring = -1);
 hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* active, int* nactive,
                           int* fstart, Summary* sum, int want_phase, hipStream_t st);
 hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,

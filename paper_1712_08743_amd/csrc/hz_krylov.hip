@@ -194,27 +194,40 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_omega(Grid g, Tiles t, Ba
   store_partial<3>(acc, rd, slot, tile);
 }
 
-// x += alpha ph + omega sh; r = s - omega t; partials <rh, r> and ||r||^2.
-// Eight streams per node and little arithmetic: on whole tiles the loads of
-// all kVecPerThread nodes are issued at once, which needs about 110 VGPRs,
-// so the occupancy target is lowered to four waves per SIMD to allow it.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) k_bicg_xr(Batch bt, int tiles, size_t n, Reduce rd,
-                                                    double2* __restrict__ x,
-                                                    const double2* __restrict__ ph,
-                                                    const double2* __restrict__ sh,
-                                                    const double2* __restrict__ s,
-                                                    const double2* __restrict__ t,
-                                                    double2* __restrict__ r,
-                                                    const double2* __restrict__ rh, size_t stride) {
+// r = s - omega t with the partials <rh, r> and ||r||^2, and the iterate.
+// XMODE -1: x += alpha ph + omega sh (every iteration). The iterate may also
+// be advanced every second iteration (ph and sh of two iterations are kept
+// in two buffers each, "rings" 0 and 1): XMODE 0 (ring 0) leaves x alone and
+// the reduction kernel records alpha, omega as the slot's pending term;
+// XMODE 1 (ring 1) adds the pending term (when there is one) and the
+// current one, x += (alpha0 ph0 + omega0 sh0) + (alpha ph + omega sh).
+// Streams per node: 4 (s, t / r and, for a dense r^, rh), 9 with x in ring
+// 1, 7 every iteration without the rings; on whole tiles the loads of all
+// kVecPerThread nodes are issued at once (about 110 VGPRs), so the occupancy
+// target is four waves per SIMD.
+template <int XMODE>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_bicg_xr(Batch bt, int tiles, size_t n, Reduce rd, double2* __restrict__ x, const double2* __restrict__ ph,
+          const double2* __restrict__ sh, const double2* __restrict__ ph0, const double2* __restrict__ sh0,
+          const double2* __restrict__ s, const double2* __restrict__ t, double2* __restrict__ r,
+          const double2* __restrict__ rh, size_t stride) {
   int slot, tile;
   if (!decode_vec(bt, tiles, slot, tile)) return;
   const Slot& S0 = bt.slots[slot];
   const double2 al = S0.alpha, om = S0.omega;
+  const double2 al0 = S0.pend_alpha, om0 = S0.pend_omega;
+  const bool pend = XMODE == 1 && S0.pending;
   const bool dense_rh = S0.rh_nnz < 0;  // else <rh, r> is formed from the sparse list
   const size_t base = (size_t)slot * stride;
   double acc[3] = {0.0, 0.0, 0.0};
-  auto node = [&](size_t q, double2 xq, double2 phq, double2 shq, double2 sq, double2 tq, double2 rhq) {
-    st_nt(x + q, cadd(xq, cadd(cmul(al, phq), cmul(om, shq))));
+  const double2 zero = c2(0.0, 0.0);
+  auto node = [&](size_t q, double2 xq, double2 phq, double2 shq, double2 ph0q, double2 sh0q, double2 sq,
+                  double2 tq, double2 rhq) {
+    if (XMODE != 0) {
+      double2 dx = cadd(cmul(al, phq), cmul(om, shq));
+      if (pend) dx = cadd(cadd(cmul(al0, ph0q), cmul(om0, sh0q)), dx);
+      st_nt(x + q, cadd(xq, dx));
+    }
     const double2 ri = csub(sq, cmul(om, tq));
     st_nt(r + q, ri);
     const double2 d = cconjmul(rhq, ri);
@@ -224,31 +237,56 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
   };
   if ((size_t)(tile + 1) * kVecPerThread * kBlock <= n) {
     // whole tile inside the vector: every load of the thread issued before the first use
-    double2 X[kVecPerThread], PH[kVecPerThread], SH[kVecPerThread], S[kVecPerThread], T[kVecPerThread],
-        RH[kVecPerThread];
+    double2 X[kVecPerThread], PH[kVecPerThread], SH[kVecPerThread], P0[kVecPerThread], S0v[kVecPerThread],
+        S[kVecPerThread], T[kVecPerThread], RH[kVecPerThread];
 #pragma unroll
     for (int e = 0; e < kVecPerThread; ++e) {
       const size_t q = base + vec_index(tile, e);
-      X[e] = ld_nt(x + q);
-      PH[e] = ld_nt(ph + q);
-      SH[e] = ld_nt(sh + q);
+      X[e] = XMODE != 0 ? ld_nt(x + q) : zero;
+      PH[e] = XMODE != 0 ? ld_nt(ph + q) : zero;
+      SH[e] = XMODE != 0 ? ld_nt(sh + q) : zero;
+      P0[e] = pend ? ld_nt(ph0 + q) : zero;
+      S0v[e] = pend ? ld_nt(sh0 + q) : zero;
       S[e] = ld_nt(s + q);
       T[e] = ld_nt(t + q);
-      RH[e] = dense_rh ? ld_nt(rh + q) : c2(0.0, 0.0);
+      RH[e] = dense_rh ? ld_nt(rh + q) : zero;
     }
 #pragma unroll
-    for (int e = 0; e < kVecPerThread; ++e) node(base + vec_index(tile, e), X[e], PH[e], SH[e], S[e], T[e], RH[e]);
+    for (int e = 0; e < kVecPerThread; ++e)
+      node(base + vec_index(tile, e), X[e], PH[e], SH[e], P0[e], S0v[e], S[e], T[e], RH[e]);
   } else {
 #pragma unroll
     for (int e = 0; e < kVecPerThread; ++e) {
       const size_t i = vec_index(tile, e);
       if (i < n) {
         const size_t q = base + i;
-        node(q, x[q], ph[q], sh[q], s[q], t[q], dense_rh ? rh[q] : c2(0.0, 0.0));
+        node(q, XMODE != 0 ? x[q] : zero, XMODE != 0 ? ph[q] : zero, XMODE != 0 ? sh[q] : zero,
+             pend ? ph0[q] : zero, pend ? sh0[q] : zero, s[q], t[q], dense_rh ? rh[q] : zero);
       }
     }
   }
   store_partial<3>(acc, rd, slot, tile);
+}
+
+// x += alpha0 ph0 + omega0 sh0 for the slots with a pending term (all slots
+// at the end of a solve; the restarting ones before a restart).
+__global__ void __launch_bounds__(kBlock) k_bicg_flush(Batch bt, int tiles, size_t n, int only_restart,
+                                                       double2* __restrict__ x, const double2* __restrict__ ph0,
+                                                       const double2* __restrict__ sh0, size_t stride) {
+  const int slot = blockIdx.x / tiles;
+  const int tile = blockIdx.x - slot * tiles;
+  const Slot& S = bt.slots[slot];
+  if (!S.pending || (only_restart && S.status != kRestart)) return;
+  const double2 al0 = S.pend_alpha, om0 = S.pend_omega;
+  const size_t base = (size_t)slot * stride;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      const size_t q = base + i;
+      x[q] = cadd(x[q], cadd(cmul(al0, ph0[q]), cmul(om0, sh0[q])));
+    }
+  }
 }
 
 // The one restart after a breakdown: rh = r, p = v = 0; partial <r, r>.
@@ -327,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_rh_sparse(size_t n, Batch bt, const 
 //   restart: rho = beta = <r, r>, rh = r done by the producer
 __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch bt, Reduce rd,
                                                      double tol, int maxit, const double2* __restrict__ vec,
-                                                     size_t stride) {
+                                                     size_t stride, int ring) {
   int slot;
   if (which == kFinRestart) {
     slot = blockIdx.x;
@@ -401,6 +439,14 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
       break;
     }
     case kFinStep: {
+      // the update just done in ring 0 left alpha ph + omega sh pending; ring 1 added it
+      if (ring == 0) {
+        S.pend_alpha = S.alpha;
+        S.pend_omega = S.omega;
+        S.pending = 1;
+      } else if (ring == 1) {
+        S.pending = 0;
+      }
       S.iters += 1;
       S.t1 = wall_clock64();
       S.rnorm2 = acc[2];
@@ -428,6 +474,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
       const double2 rho = c2(acc[0], acc[1]);
       S.restarted = 1;
       S.rh_nnz = -1;  // r^ = r from here on, dense
+      S.pending = 0;  // added to x by the flush before the restart
       S.alpha = c2(1.0, 0.0);
       S.omega = c2(1.0, 0.0);
       if (!cfinite(rho)) {
@@ -916,10 +963,30 @@ hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int 
 
 hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, double2* x,
                           const double2* ph, const double2* sh, const double2* s, const double2* t,
-                          double2* r, const double2* rh, size_t stride, hipStream_t st) {
+                          double2* r, const double2* rh, size_t stride, hipStream_t st, int ring,
+                          const double2* ph0, const double2* sh0) {
   if (cap <= 0) return hipSuccess;
+  if (ring == 1 && (!ph0 || !sh0)) return hipErrorInvalidValue;
   const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_bicg_xr, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, x, ph, sh, s, t, r, rh, stride);
+  const dim3 gr = grid1((long long)cap * tiles);
+  if (ring < 0)
+    hipLaunchKernelGGL(k_bicg_xr<-1>, gr, dim3(kBlock), 0, st, bt, tiles, n, rd, x, ph, sh, ph0, sh0, s, t, r, rh,
+                       stride);
+  else if (ring == 0)
+    hipLaunchKernelGGL(k_bicg_xr<0>, gr, dim3(kBlock), 0, st, bt, tiles, n, rd, x, ph, sh, ph0, sh0, s, t, r, rh,
+                       stride);
+  else
+    hipLaunchKernelGGL(k_bicg_xr<1>, gr, dim3(kBlock), 0, st, bt, tiles, n, rd, x, ph, sh, ph0, sh0, s, t, r, rh,
+                       stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_flush(size_t n, int nslots, const Batch& bt, int only_restart, double2* x,
+                             const double2* ph0, const double2* sh0, size_t stride, hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_bicg_flush, grid1((long long)nslots * tiles), dim3(kBlock), 0, st, bt, tiles, n, only_restart,
+                     x, ph0, sh0, stride);
   return hipGetLastError();
 }
 
@@ -932,10 +999,11 @@ hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Redu
 }
 
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
-                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st) {
+                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st, int ring) {
   if (cap <= 0) return hipSuccess;
   if ((which == kFinSigma || which == kFinStep) && !vec) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bicg_fin, dim3(cap), dim3(kBlock), 0, st, which, tiles, bt, rd, tol, maxit, vec, stride);
+  hipLaunchKernelGGL(k_bicg_fin, dim3(cap), dim3(kBlock), 0, st, which, tiles, bt, rd, tol, maxit, vec, stride,
+                     ring);
   return hipGetLastError();
 }
 

@@ -23,14 +23,15 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# timing class -> kernel symbol (finest level)
+# timing class -> kernel symbol(s) (finest level); a class with two symbols
+# launches each of them every second iteration
 CLASS_SYMBOL = {
     "presmooth": "hz::k_pre2r_s<1, true>",
     "presmooth_s": "hz::k_pre2r_s<2, true>",
     "prolong": "hz::k_post2_s<true>",
     "apply": "hz::k_bicg_apply_t<0>",
     "apply_s": "hz::k_bicg_apply_t<1>",
-    "update": "hz::k_bicg_xr",
+    "update": ("hz::k_bicg_xr<0>", "hz::k_bicg_xr<1>"),
     "coarse": "hz::k_coarse",
 }
 
@@ -50,9 +51,14 @@ def symbol(name):
     return s[5:] if s.startswith("void ") else s
 
 
+def symbols_of(cls):
+    v = CLASS_SYMBOL[cls]
+    return v if isinstance(v, tuple) else (v,)
+
+
 def class_of(sym):
-    for k, v in CLASS_SYMBOL.items():
-        if sym == v:
+    for k in CLASS_SYMBOL:
+        if sym in symbols_of(k):
             return k
     return ""
 
@@ -184,11 +190,14 @@ def main():
         text = _traffic_md(t, args.command, args.rhs)
         if args.json:
             per_class = {}
-            for k, s in CLASS_SYMBOL.items():
-                if s in t["kernels"]:
-                    r = t["kernels"][s]
-                    per_class[k] = {"symbol": s, "fetch_bytes_per_rhs": r["fetch_bytes_per_rhs"],
-                                    "write_bytes_per_rhs": r["write_bytes_per_rhs"]}
+            for k in CLASS_SYMBOL:
+                syms = [s for s in symbols_of(k) if s in t["kernels"]]
+                if len(syms) == len(symbols_of(k)):  # mean over the class's symbols (equal launch counts)
+                    per_class[k] = {"symbol": " + ".join(syms),
+                                    "fetch_bytes_per_rhs": sum(t["kernels"][s]["fetch_bytes_per_rhs"]
+                                                               for s in syms) / len(syms),
+                                    "write_bytes_per_rhs": sum(t["kernels"][s]["write_bytes_per_rhs"]
+                                                               for s in syms) / len(syms)}
             with open(args.json, "w") as fh:
                 json.dump({"kernel_source_hash": kernel_source_hash(), "fetch_factor": t["fetch_factor"],
                            "write_factor": t["write_factor"], "rhs_per_dispatch": args.rhs,
