@@ -122,7 +122,7 @@ struct PreRow {  // loads of one row: the right-hand side's inputs, w/D and m
 // FINE: launched on the finest level (the same code; a separate symbol lets a
 // profiler tell the finest level's launches from the coarser ones)
 template <int MODE, bool FINE>
-__global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
                                                     Batch bt, RhsIn in, double2* __restrict__ bout,
                                                     double2* __restrict__ u2, double2* __restrict__ bc,
                                                     size_t stride, size_t sc) {
@@ -161,8 +161,13 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
     r.m = g.m[q];
     return r;
   };
-  // rolling rows: u1 on j-2, j-1; b, m on j-1, j-2; w/D on j-1; u2 on j-3, j-2; r on j-4, j-3
-  double2 u1a = zero, u1b = zero, b1 = zero, b2 = zero, wd1 = zero, u2a = zero, u2b = zero, ra = zero, rb = zero;
+  // weight of the right neighbour in the horizontal restriction stencil: 1
+  // for the last fine node of an even-count axis (P^T of the clamped
+  // interpolation), else 1/2
+  const double wgx = x + 2 == g.nx ? 1.0 : 0.5;
+  // rolling rows: u1 on j-2, j-1; b, m on j-1, j-2; w/D on j-1; u2 on j-3, j-2;
+  // the horizontally restricted residual on j-4, j-3
+  double2 u1a = zero, u1b = zero, b1 = zero, b2 = zero, wd1 = zero, u2a = zero, u2b = zero, ha = zero, hb = zero;
   double m1 = 0.0, m2 = 0.0;
   auto step = [&](int j, const PreRow<MODE>& L, bool odd) {
     const bool jin = xin && j >= 0 && j < g.nz;
@@ -170,9 +175,9 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
     if (MODE == 0) bj = L.a;
     if (MODE == 1) bj = cadd(L.a, cmul(beta, csub(L.b, cmul(om, L.c))));
     if (MODE == 2) bj = csub(L.a, cmul(al, L.b));
-    bj = keep(jin, bj);
+    // outside the grid u1 = 0 through w/D; b and m there only enter values that are zeroed
     const double2 wdj = keep(jin, L.wd);
-    const double mj = jin ? L.m : 0.0;
+    const double mj = L.m;
     const double2 u1c = cmul(bj, wdj);
     // u2 on row j-1
     const int i2 = j - 1;
@@ -197,23 +202,16 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
       const double2 v = csub(b2, apply_m(cx, axis_coef(ir, g.nz), m2, ka, kb, kc, ih2, u2b, sx, sz));
       rc = keep(xin && ir >= 0 && ir < g.nz, v);
     }
-    // full weighting to coarse row (ir - 1) / 2 once rows ir-2 .. ir are known
+    // full weighting: each residual row restricted horizontally once, then
+    // coarse row (ir - 1) / 2 from rows ir-2 .. ir (the last fine row of an
+    // even-count axis again with weight 1)
+    const double2 lc = from_left(rc), gc2 = from_right(rc);
+    const double2 hc = c2(rc.x + 0.5 * lc.x + wgx * gc2.x, rc.y + 0.5 * lc.y + wgx * gc2.y);
     if (odd) {
       const int Iz = (ir - 1) / 2;
-      const double2 la = from_left(ra), ga = from_right(ra);
-      const double2 lb = from_left(rb), gb = from_right(rb);
-      const double2 lc = from_left(rc), gc2 = from_right(rc);
       if (cown && 2 * Iz >= w.z0 && 2 * Iz < w.z1 && Iz < gc.nz) {
-        // the last fine node of an even-count axis carries weight 1 (P^T of
-        // the clamped interpolation)
-        const bool xe = x + 2 == g.nx, ze = 2 * Iz + 2 == g.nz;
-        auto row = [&](double2 cen, double2 l, double2 r) {
-          return xe ? cadd(cadd(cen, cscale(0.5, l)), r) : cadd(cen, cscale(0.5, cadd(l, r)));
-        };
-        double2 acc = c2(0.0, 0.0);
-        acc = cadd(acc, cscale(0.5, row(ra, la, ga)));
-        acc = cadd(acc, cscale(1.0, row(rb, lb, gb)));
-        acc = cadd(acc, cscale(ze ? 1.0 : 0.5, row(rc, lc, gc2)));
+        const double wz3 = 2 * Iz + 2 == g.nz ? 1.0 : 0.5;
+        const double2 acc = c2(0.5 * ha.x + hb.x + wz3 * hc.x, 0.5 * ha.y + hb.y + wz3 * hc.y);
         bc[(size_t)w.slot * sc + (size_t)Iz * gc.nx + (x >> 1)] = cscale(0.25, acc);
       }
     }
@@ -226,8 +224,8 @@ __global__ void __launch_bounds__(kBlock) k_pre2r_s(Grid g, Grid gc, int nstrip,
     wd1 = wdj;
     u2a = u2b;
     u2b = u2c;
-    ra = rb;
-    rb = rc;
+    ha = hb;
+    hb = hc;
   };
   // rows z0-3 .. z1+2; the first row is odd (z0 even), so pairs are (odd, even)
   for (int j = w.z0 - 3; j <= w.z1 + 2; j += 2) {
@@ -291,8 +289,8 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
   double2 b1 = zero, b2 = zero, b3 = zero, w1 = zero, w2 = zero, w3 = zero;
   // lo, hi: coarse rows (j-1) >> 1 and the one below it
   auto step = [&](int j, const PostRow& L, double2 loa, double2 lob, double2 hia, double2 hib, bool odd_prev) {
-    const bool jin = inside(j);
-    const double2 bj = keep(jin, L.b), wdj = keep(jin, L.wd);
+    // outside the grid u1 = 0 through w/D; b there only enters values that are zeroed
+    const double2 bj = L.b, wdj = keep(inside(j), L.wd);
     const double2 u1c = cmul(bj, wdj);
     // u2 and u3 on row j-1
     const int i2 = j - 1;
