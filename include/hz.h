@@ -113,6 +113,9 @@ typedef struct {
                                iterations per graph, one graph per batch-size bucket) and
                                replayed; 0 (default): every launch issued one by one. Ignored
                                while kernel timing is on. Results do not depend on it. */
+    int    restart_at;      /* for tests of the breakdown path: > 0 makes every BiCGSTAB
+                               right-hand side take the one restart (r^ = r, p = v = 0) after
+                               this many iterations, as after a breakdown; 0 (default): off */
 } hz_solve_opts;
 
 typedef struct {

@@ -49,7 +49,7 @@ class SolveOpts(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("jacobi_w", ctypes.c_double),
                 ("jacobi_w_level", ctypes.POINTER(ctypes.c_double)), ("autotune", ctypes.c_int),
                 ("chunk_rows", ctypes.c_int), ("coarse", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("restart_at", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -123,7 +123,7 @@ def default_opts():
 
 def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg", beta=(1.0, 0.5),
               levels=0, nu=(2, 2), jacobi_w=0.8, jacobi_w_level=None, autotune=True, chunk_rows=0,
-              graphs=False, coarse="auto", coarse_sweeps=2):
+              graphs=False, coarse="auto", coarse_sweeps=2, restart_at=0):
     """Build an hz_solve_opts; returns (opts, keepalive)."""
     o = default_opts()
     o.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
@@ -138,6 +138,7 @@ def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg"
     o.autotune = 1 if autotune else 0
     o.chunk_rows = int(chunk_rows)
     o.graphs = 1 if graphs else 0
+    o.restart_at = int(restart_at)
     o.coarse = COARSE[coarse] if isinstance(coarse, str) else int(coarse)
     o.coarse_sweeps = int(coarse_sweeps)
     keep = None

@@ -284,6 +284,7 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
     return fail(c, HZ_ERR_ARG, "chunk_rows must be 0 or an even number up to 65536");
   if (o->autotune != 0 && o->autotune != 1) return fail(c, HZ_ERR_ARG, "autotune must be 0 or 1");
   if (o->graphs != 0 && o->graphs != 1) return fail(c, HZ_ERR_ARG, "graphs must be 0 or 1");
+  if (o->restart_at < 0) return fail(c, HZ_ERR_ARG, "restart_at must be >= 0");
   if (o->coarse < HZ_COARSE_AUTO || o->coarse > HZ_COARSE_JACOBI) return fail(c, HZ_ERR_ARG, "unknown coarse solve");
   if (o->coarse_sweeps < 1 || o->coarse_sweeps > 64) return fail(c, HZ_ERR_ARG, "coarse_sweeps must be in [1, 64]");
   if (o->precond == HZ_PRECOND_EXACT) {
@@ -791,7 +792,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
              return launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx, rg, phr[0], shr[0]);
            })) != hipSuccess)
         break;
-      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx, rg);
+      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx, rg, o->restart_at);
     } while (false);
     c->stream = saved;
     return e;
@@ -1093,6 +1094,7 @@ void hz_default_opts(hz_solve_opts* o) {
   o->coarse = HZ_COARSE_AUTO;
   o->coarse_sweeps = 2;
   o->graphs = 0;
+  o->restart_at = 0;
 }
 
 int hz_create(hz_ctx** out, const hz_ctx_opts* o) {

@@ -217,9 +217,10 @@ enum : int { kFinInit = 0, kFinSigma = 1, kFinOmega = 2, kFinStep = 3, kFinResta
 // vec: for sigma v, for step r (the inner products with a sparse r^ are
 // formed here from it); unused otherwise.
 // ring (step only): 0 records the update's term as pending, 1 clears it.
+// restart_at (step only, > 0): take the restart after that many iterations.
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
                            double tol, int maxit, const double2* vec, size_t stride, hipStream_t st,
-                           int ring = -1);
+                           int ring = -1, int restart_at = 0);
 hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* active, int* nactive,
                           int* fstart, Summary* sum, int want_phase, hipStream_t st);
 hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,

@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_rh_sparse(size_t n, Batch bt, const 
 //   restart: rho = beta = <r, r>, rh = r done by the producer
 __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch bt, Reduce rd,
                                                      double tol, int maxit, const double2* __restrict__ vec,
-                                                     size_t stride, int ring) {
+                                                     size_t stride, int ring, int restart_at) {
   int slot;
   if (which == kFinRestart) {
     slot = blockIdx.x;
@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
         S.status = kMaxit;
       } else if (!cfinite(rho_new)) {
         S.status = kNonfinite;
-      } else if (czero(rho_new)) {
+      } else if (czero(rho_new) || (restart_at > 0 && S.iters == restart_at && !S.restarted)) {
         S.status = S.restarted ? kBreakdown : kRestart;
       } else {
         S.beta = cmul(cdiv(rho_new, S.rho), cdiv(S.alpha, S.omega));
@@ -999,11 +999,12 @@ hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Redu
 }
 
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
-                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st, int ring) {
+                           double tol, int maxit, const double2* vec, size_t stride, hipStream_t st, int ring,
+                           int restart_at) {
   if (cap <= 0) return hipSuccess;
   if ((which == kFinSigma || which == kFinStep) && !vec) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_bicg_fin, dim3(cap), dim3(kBlock), 0, st, which, tiles, bt, rd, tol, maxit, vec, stride,
-                     ring);
+                     ring, restart_at);
   return hipGetLastError();
 }
 

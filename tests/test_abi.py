@@ -49,7 +49,7 @@ def test_status_strings_and_defaults():
     o = hz.default_opts()
     assert o.krylov == hz.HZ_BICGSTAB and o.tol == 1e-8 and o.nu1 == 2 and o.nu2 == 2
     assert (o.beta1, o.beta2) == (1.0, 0.5) and o.jacobi_w == 0.8 and o.gmres_m == 30
-    assert o.autotune == 1 and o.chunk_rows == 0 and o.graphs == 0
+    assert o.autotune == 1 and o.chunk_rows == 0 and o.graphs == 0 and o.restart_at == 0
     assert o.coarse == hz.HZ_COARSE_AUTO and o.coarse_sweeps == 2
 
 

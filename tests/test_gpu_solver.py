@@ -249,6 +249,38 @@ def test_sparse_and_dense_shadow_residuals(hz):
         assert info1[0][1] == info[k][1]
 
 
+@pytest.mark.parametrize("restart_at,graphs", [(5, False), (6, False), (6, True)])
+def test_forced_restart_converges(hz, restart_at, graphs):
+    """BiCGSTAB's breakdown restart (r^ = r, p = v = 0), forced after
+    iteration 5 (which leaves its term of the iterate pending: it is added
+    before the restart) and 6: r^ becomes a dense vector; point sources
+    (sparse r^ before the restart) and a dense b still converge to the
+    direct solution."""
+    import torch
+    w = workloads.model_2d_lens(n=65, h=30.0)
+    c = make_ctx(hz, w.m, w.h)
+    rng = np.random.default_rng(5)
+    n = w.shape[0] * w.shape[1]
+    bs = np.zeros((3, n), dtype=np.complex128)
+    bs[0] = op.point_source(w.shape, w.h, [20])
+    bs[1] = op.point_source(w.shape, w.h, [33 * 65 + 40])
+    bs[2] = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    b = torch.from_numpy(bs.reshape((1, 3) + w.shape)).cuda()
+    f = 5.0
+    u, info = c.solve([f], 0.01, b, tol=1e-10, restart_at=restart_at, graphs=graphs)
+    lu = direct.factor_superlu(op.operator_B(w.m, w.h, 2 * np.pi * f, 0.01))
+    u_ref, info_ref = c.solve([f], 0.01, b, tol=1e-10)
+    for k in range(3):
+        assert info[k][0] == hz.HZ_RHS_CONVERGED, (k, info[k])
+        assert info[k][1] > restart_at
+        assert info[k][2] <= 1e-10
+        assert rel(to_np(u[0, k]).ravel(), lu.solve(bs[k])) <= 1e-7, k
+        # the restart costs iterations but the result is the same solution
+        assert rel(to_np(u[0, k]), to_np(u_ref[0, k])) <= 1e-7
+    # the restarted recurrences differ from the unforced ones
+    assert any(info[k][1] != info_ref[k][1] for k in range(3))
+
+
 def test_empty_batch(hz):
     import torch
     w = workloads.model_2d_lens(n=33, h=40.0)
