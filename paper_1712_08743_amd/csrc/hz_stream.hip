@@ -26,14 +26,15 @@ constexpr int kLanes = 64;
 // Neighbouring lanes' values by whole-wavefront DPP shifts (wave_shr:1,
 // wave_shl:1 on the two 32-bit halves): VALU moves with a few cycles of
 // latency, where a general shuffle goes through the LDS crossbar. The lane
-// with no neighbour (0 from the left, 63 from the right) receives 0.
+// with no neighbour (0 from the left, 63 from the right) receives 0 (the
+// bound control of the move).
 constexpr int kDppWaveShr1 = 0x138;  // lane i takes lane i - 1
 constexpr int kDppWaveShl1 = 0x130;  // lane i takes lane i + 1
 template <int CTRL>
 __device__ __forceinline__ double dpp_shift(double v) {
   const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffLL), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double2 from_left(double2 v) {  // value of lane - 1
@@ -97,7 +98,10 @@ __device__ __forceinline__ bool wave_tile(const Batch& bt, int nstrip, int nchun
                                           int width, int nz, WaveTile& w) {
   int slot, grp;
   if (!decode_tile(bt, groups, slot, grp)) return false;
-  const int tile = grp * (kBlock / kLanes) + (int)(threadIdx.x / kLanes);
+  // the wavefront's index in the block, read from lane 0 so that the compiler
+  // sees it (and every row index and row condition derived from it) as uniform
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kLanes));
+  const int tile = grp * (kBlock / kLanes) + wv;
   if (tile >= nstrip * nchunk) return false;
   const int chunk = tile / nstrip, strip = tile - chunk * nstrip;
   w.slot = slot;
