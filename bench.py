@@ -405,6 +405,13 @@ def main():
     ctx.timing_start([])
     sec = (t1 - t0) / args.steps
     print(f"# timed {args.steps} step(s): {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    # the V-cycle's coarser levels, timed in one more step after the timed region: events around
+    # their many short launches would lengthen the timed steps (by about 4 %)
+    ctx.timing_start(["levels"])
+    step()
+    torch.cuda.synchronize()
+    levels = ctx.timing_read("levels")
+    ctx.timing_start([])
 
     info = infos[-1]
     conv = sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED and i[2] <= tol)
@@ -427,6 +434,8 @@ def main():
             entry["TFLOP/s"] = slot_iters * 2 * 8 * sizes[-1] ** 2 / (ms * 1e-3) / 1e12
             entry["frac_fp64_peak"] = entry["TFLOP/s"] / PEAK_FP64_TFLOPS
         breakdown[k] = entry
+    breakdown["levels"] = {"launches": levels[0], "ms": levels[1], "steps": 1,
+                           "note": "coarser V-cycle levels, timed in one extra step after the timed ones"}
     dom = max((k for k in classes if k in cb and timing[k][0] > 0), key=lambda k: timing[k][1])
     n_dom, ms_dom = timing[dom]
     dom_bytes = slot_iters * cb[dom]

@@ -321,8 +321,11 @@ int  hz_server_stats(hz_server *s, int *queued, int *running, int *peak_running,
                                   its restriction */
 #define HZ_KERNEL_PRESMOOTH_S 7 /* the same for the BiCGSTAB vector s = r - alpha v */
 #define HZ_KERNEL_APPLY_S  8   /* B s^ with <t, s> and <t, t> (BiCGSTAB) */
+#define HZ_KERNEL_LEVELS   9   /* every V-cycle launch below the finest level except the dense
+                                  coarse solve: smoothing, residual, transfers, and the sweeps
+                                  that smooth the coarsest level */
 
-#define HZ_KERNEL_CLASSES  9
+#define HZ_KERNEL_CLASSES  10
 
 /* Start timing the kernel classes whose bit (1 << HZ_KERNEL_*) is set in
  * mask, resetting all totals (mask 0 stops): every later launch of such a

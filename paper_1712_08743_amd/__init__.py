@@ -31,7 +31,7 @@ HZ_MAX_LEVELS = 12
 HZ_COARSE_AUTO, HZ_COARSE_EXACT, HZ_COARSE_JACOBI = 0, 1, 2
 COARSE = {"auto": HZ_COARSE_AUTO, "exact": HZ_COARSE_EXACT, "jacobi": HZ_COARSE_JACOBI}
 HZ_KERNEL = {"smooth": 0, "apply": 1, "restrict": 2, "prolong": 3, "update": 4, "coarse": 5, "presmooth": 6,
-             "presmooth_s": 7, "apply_s": 8}
+             "presmooth_s": 7, "apply_s": 8, "levels": 9}
 
 PRECOND = {"mg": HZ_PRECOND_MG, "exact": HZ_PRECOND_EXACT, "none": HZ_PRECOND_NONE}
 KRYLOV = {"bicgstab": HZ_BICGSTAB, "gmres": HZ_GMRES}

@@ -598,7 +598,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
       const Grid gc = grid_of(c, l + 1);
       const size_t nc = c->lv[l + 1].n();
-      const int cls = l > 0 ? -2 : (fr.mode == 2 ? HZ_KERNEL_PRESMOOTH_S : HZ_KERNEL_PRESMOOTH);
+      const int cls = l > 0 ? HZ_KERNEL_LEVELS : (fr.mode == 2 ? HZ_KERNEL_PRESMOOTH_S : HZ_KERNEL_PRESMOOTH);
       if ((e = timed(c, cls, [&] {
              return tuned_launch(c, cy, fr.mode, g, cap, [&](int ch) {
                return launch_pre2r(g, gc, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, post_fused ? nullptr : X,
@@ -613,7 +613,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     if (cy.nu1 == 2) {
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
-      if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : -2, [&] {
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : HZ_KERNEL_LEVELS, [&] {
              return launch_pre2(dim, g, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, X, nl, st);
            })) != hipSuccess)
         return e;
@@ -621,7 +621,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     } else {
       for (int k = 0; k < cy.nu1; ++k) {
         double2* dst = (u == X) ? Y : X;
-        const int cls = (l == 0 && u) ? HZ_KERNEL_SMOOTH : -2;
+        const int cls = l > 0 ? HZ_KERNEL_LEVELS : (u ? HZ_KERNEL_SMOOTH : -2);
         if ((e = timed(c, cls, [&] { return launch_smooth(dim, g, l, 0.0, bt, cap, bl, u, dst, nl, st); })) !=
             hipSuccess)
           return e;
@@ -629,7 +629,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       }
     }
     cur[l] = u;
-    if ((e = timed(c, l == 0 ? HZ_KERNEL_RESTRICT : -2, [&] {
+    if ((e = timed(c, l == 0 ? HZ_KERNEL_RESTRICT : HZ_KERNEL_LEVELS, [&] {
            return launch_restrict(dim, g, grid_of(c, l + 1), bt, cap, bl, u, bc, nl, c->lv[l + 1].n(), st);
          })) != hipSuccess)
       return e;
@@ -644,10 +644,12 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
          })) != hipSuccess)
       return e;
     // frequencies whose coarsest level is smoothed (the exact solve skipped them)
-    if (cy.coarse_sweeps > 0 &&
-        (e = launch_coarse_jacobi(dim, grid_of(c, cl), cl, kCoarseJacobiW, cy.coarse_sweeps, bt, cap,
-                                  c->lev[cl][kLb].as<double2>(), c->lev[cl][kLx].as<double2>(),
-                                  c->lev[cl][kLu].as<double2>(), c->lv[cl].n(), st)) != hipSuccess)
+    if (cy.coarse_sweeps > 0 && (e = timed(c, HZ_KERNEL_LEVELS, [&] {
+                                   return launch_coarse_jacobi(dim, grid_of(c, cl), cl, kCoarseJacobiW,
+                                                               cy.coarse_sweeps, bt, cap, c->lev[cl][kLb].as<double2>(),
+                                                               c->lev[cl][kLx].as<double2>(),
+                                                               c->lev[cl][kLu].as<double2>(), c->lv[cl].n(), st);
+                                 })) != hipSuccess)
       return e;
   }
   // ascend
@@ -662,7 +664,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     const double2* ec = c->lev[l + 1][kLu].as<double2>();
     double2* u = cur[l];
     if (cy.nu2 == 0) {
-      if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : HZ_KERNEL_LEVELS, [&] {
              return launch_prolong(dim, g, gc, bt, cap, ec, u, R, nl, c->lv[l + 1].n(), st);
            })) != hipSuccess)
         return e;
@@ -671,7 +673,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     // prolongation fused with the first post-sweep (2D: with the first two)
     const int fused = (dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2) ? 2 : 1;
     double2* dst = (cy.nu2 == fused) ? R : ((u == X) ? Y : X);
-    if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : -2, [&] {
+    if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : HZ_KERNEL_LEVELS, [&] {
            if (fused == 2)
              return tuned_launch(c, cy, 3, g, cap, [&](int ch) {
                return launch_post2(g, gc, l, bt, cap, ec, bll, dst, nl, c->lv[l + 1].n(), ch, st);
@@ -682,7 +684,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     u = dst;
     for (int k = fused; k < cy.nu2; ++k) {
       double2* d2 = (k == cy.nu2 - 1) ? R : ((u == X) ? Y : X);
-      if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : -2, [&] {
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : HZ_KERNEL_LEVELS, [&] {
              return launch_smooth(dim, g, l, 0.0, bt, cap, bll, u, d2, nl, st);
            })) != hipSuccess)
         return e;
