@@ -281,6 +281,34 @@ def test_forced_restart_converges(hz, restart_at, graphs):
     assert any(info[k][1] != info_ref[k][1] for k in range(3))
 
 
+def test_kernel_timing_classes(hz):
+    """hz_timing_start/read: every launch of a timed class is counted (one
+    operator apply of each kind and one update per BiCGSTAB iteration, two
+    post-smoothing launches per iteration, the coarser levels' launches), the
+    times are positive, untimed classes stay at zero, timing does not change
+    the result, and a class past the last one is refused."""
+    import torch
+    w = workloads.model_2d_layered(nz=97, nx=193, h=20.0, nshots=3, freqs=(4.0,))
+    c = make_ctx(hz, w.m, w.h)
+    b = c.point_rhs([0] * 3, w.src)[None]
+    ref, info_ref = c.solve([4.0], 0.01, b, tol=1e-9)
+    c.timing_start(["apply", "apply_s", "update", "prolong", "levels"])
+    u, info = c.solve([4.0], 0.01, b, tol=1e-9)
+    t = {k: c.timing_read(k) for k in hz.HZ_KERNEL}
+    c.timing_start([])
+    assert torch.equal(u, ref)
+    slot_iters = sum(i[1] for i in info)
+    for k in ("apply", "apply_s", "update"):
+        assert t[k][0] >= max(i[1] for i in info) and t[k][1] > 0.0, (k, t[k])
+    assert t["prolong"][0] == 2 * t["apply"][0]
+    assert t["levels"][0] > t["prolong"][0] and t["levels"][1] > 0.0
+    assert t["presmooth"] == (0, 0.0) and t["coarse"] == (0, 0.0)
+    assert slot_iters >= t["update"][0]
+    with pytest.raises(hz.HzError) as e:
+        c.timing_start([len(hz.HZ_KERNEL)])
+    assert e.value.code == hz.HZ_ERR_ARG
+
+
 def test_empty_batch(hz):
     import torch
     w = workloads.model_2d_lens(n=33, h=40.0)
