@@ -53,12 +53,13 @@ def bytes_per_iteration(sizes):
     coarse inverse (one copy per frequency, shared by all its right-hand
     sides and read from cache). The benchmark's right-hand sides are point
     sources, so the shadow residual r^ = b is held as a one-entry list and
-    the inner products with it stream no vector. The iterate x is advanced
-    every second iteration (with both iterations' p^ and s^)."""
+    the inner products with it stream no vector; v = B p^ is then never
+    stored (the pre-smoothing kernels form it from p^). The iterate x is
+    advanced every second iteration (with both iterations' p^ and s^)."""
     z = 16
     n0 = sizes[0]
-    total = n0 * z * (4 + 3)        # p and s updates fused with the pre-sweeps and restriction
-    total += n0 * z * (2 + 3 + 6)   # B p^, B s^ (with dots), r update (+ x every second iteration)
+    total = n0 * z * (4 + 3)        # p and s updates (B p^ formed in the kernel) fused with the pre-sweeps
+    total += n0 * z * (3 + 6)       # B s^ (with dots), r update (+ x every second iteration)
     for l, n in enumerate(sizes[:-1]):
         nc = sizes[l + 1]
         per_cycle = nc * z                      # restricted residual
@@ -77,10 +78,10 @@ def class_bytes_per_iteration(sizes):
     z = 16
     n0, n1 = sizes[0], sizes[1]
     return {
-        "presmooth": n0 * z * 4 + n1 * z,       # reads r, p_old, v; writes p; coarse right-hand side
-        "presmooth_s": n0 * z * 3 + n1 * z,     # reads r, v; writes s; coarse right-hand side
+        "presmooth": n0 * z * 4 + n1 * z,       # reads r, p_old, p^_old; writes p; coarse right-hand side
+        "presmooth_s": n0 * z * 3 + n1 * z,     # reads r, p^; writes s; coarse right-hand side
         "prolong": 2 * (n0 * z * 2 + n1 * z),   # reads b, coarse e; writes u (two V-cycles)
-        "apply": n0 * z * 2,                    # reads p^; writes v (r^ is a sparse list)
+        "apply": n0 * z * 2,                    # reads p^, r^ (only while some r^ is dense)
         "apply_s": n0 * z * 3,                  # reads s^, s; writes t
         # r = s - omega t every iteration (reads s, t; writes r), x every second one
         # (reads x, two p^, two s^; writes x): 6 vectors per iteration on average

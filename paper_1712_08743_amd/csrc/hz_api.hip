@@ -555,7 +555,9 @@ hipError_t tuned_launch(hz_ctx* c, const Cycle& cy, int kind, const Grid& g, int
 
 // How the finest level's right-hand side is formed: read (mode 0), or the
 // BiCGSTAB vector p = a + beta (b - omega c) (mode 1) or s = a - alpha b
-// (mode 2), stored to `out` by the kernel that forms it.
+// (mode 2), stored to `out` by the kernel that forms it. 2D only: modes 4
+// and 5 take p^ in c and form its product with B themselves, p = a + beta
+// (b - omega B c) (a where beta = 0) and s = a - alpha B c.
 struct FineRhs {
   int mode;
   const double2* a;
@@ -598,7 +600,8 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
       const Grid gc = grid_of(c, l + 1);
       const size_t nc = c->lv[l + 1].n();
-      const int cls = l > 0 ? HZ_KERNEL_LEVELS : (fr.mode == 2 ? HZ_KERNEL_PRESMOOTH_S : HZ_KERNEL_PRESMOOTH);
+      const int cls =
+          l > 0 ? HZ_KERNEL_LEVELS : (fr.mode == 2 || fr.mode == 5 ? HZ_KERNEL_PRESMOOTH_S : HZ_KERNEL_PRESMOOTH);
       if ((e = timed(c, cls, [&] {
              return tuned_launch(c, cy, fr.mode, g, cap, [&](int ch) {
                return launch_pre2r(g, gc, l, fr.mode, bt, cap, fr.a, fr.b, fr.c, fr.out, post_fused ? nullptr : X,
@@ -711,6 +714,14 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   double2* t = c->fine[kT].as<double2>();
   const bool identity = cy.precond == HZ_PRECOND_NONE;
   const bool fused = fused_pre(cy);
+  // 2D with the fused pre-smoothing kernel: v = B p^ is never stored. The
+  // pre-smoothing kernels form it from p^ (the last iteration's p^ for the p
+  // update, the current one for s), and sigma = <r^, B p^> is formed at the
+  // nodes of r^'s sparse list. Slots whose r^ is dense (a right-hand side
+  // with many nonzeros, or after a restart) take sigma from an operator pass
+  // that stores nothing, launched while any active slot needs it.
+  const bool vfree = fused && c->dim == 2;
+  bool dense_rh = false;
   // The iterate is advanced every second iteration: p^ and s^ of iteration
   // 2k (ring 0) stay in their buffers while 2k+1 (ring 1) writes the others,
   // and ring 1's update adds both terms (one read and write of x instead of
@@ -743,6 +754,11 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
   HZ_HIP(c, launch_rh_sparse(n0, nslots, bt, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st));
   if ((rc = close_unit()) != HZ_OK) return rc;
+  if (vfree) {  // whether the first iterations need the dense sigma pass
+    const int k = pending.back().second;
+    HZ_HIP(c, hipEventSynchronize(c->ev[k]));
+    dense_rh = c->ring_host[k].ndense > 0;
+  }
 
   int cap = nslots;
   long long iters_issued = 0;
@@ -763,7 +779,10 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
     // p_new = r + beta (p_old - omega v) into the other p buffer, then ph = V p_new
     double2* pn = (p == pbuf[0]) ? pbuf[1] : pbuf[0];
     do {
-      if (fused) {
+      if (vfree) {  // the last iteration's p^ is in the other ring buffer
+        const FineRhs fr{4, r, p, phr[ring ^ 1], pn};
+        if ((e = precond_apply(c, cy, capx, nullptr, ph, &fr)) != hipSuccess) break;
+      } else if (fused) {
         const FineRhs fr{1, r, p, v, pn};
         if ((e = precond_apply(c, cy, capx, nullptr, ph, &fr)) != hipSuccess) break;
       } else {
@@ -772,12 +791,25 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       }
       p = pn;
       if (identity) ph = p;
-      if ((e = timed(c, HZ_KERNEL_APPLY, [&] {
-             return launch_bicg_apply_sigma(c->dim, g0, bt, capx, rd, ph, rh, v, n0, sx);
-           })) != hipSuccess)
-        break;
-      if ((e = launch_bicg_fin(kFinSigma, gt, bt, capx, rd, o->tol, o->maxit, v, n0, sx)) != hipSuccess) break;
-      if (fused) {
+      if (vfree) {
+        if (dense_rh && (e = timed(c, HZ_KERNEL_APPLY, [&] {
+                           return launch_bicg_apply_sigma(c->dim, g0, bt, capx, rd, ph, rh, nullptr, n0, sx);
+                         })) != hipSuccess)
+          break;
+        if ((e = launch_bicg_fin(kFinSigmaB, gt, bt, capx, rd, o->tol, o->maxit, ph, n0, sx, -1, 0, &g0)) !=
+            hipSuccess)
+          break;
+      } else {
+        if ((e = timed(c, HZ_KERNEL_APPLY, [&] {
+               return launch_bicg_apply_sigma(c->dim, g0, bt, capx, rd, ph, rh, v, n0, sx);
+             })) != hipSuccess)
+          break;
+        if ((e = launch_bicg_fin(kFinSigma, gt, bt, capx, rd, o->tol, o->maxit, v, n0, sx)) != hipSuccess) break;
+      }
+      if (vfree) {
+        const FineRhs fr{5, r, nullptr, ph, s};
+        if ((e = precond_apply(c, cy, capx, nullptr, sh, &fr)) != hipSuccess) break;
+      } else if (fused) {
         const FineRhs fr{2, r, v, nullptr, s};
         if ((e = precond_apply(c, cy, capx, nullptr, sh, &fr)) != hipSuccess) break;
       } else {
@@ -803,7 +835,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   // HIP graphs: two iterations (the p buffers swap twice, so a pair starts
   // and ends on the same buffer) captured once per batch-size bucket (the
   // active count rounded up to a power of two; launches past the active
-  // list exit at once) and replayed. The first pair of a bucket runs
+  // list exit at once) and whether the dense sigma pass is in, and replayed. The first pair of a bucket runs
   // eagerly, which also runs the launch-shape trials, so nothing that
   // synchronises is captured. Kernel timing needs per-launch events, so
   // timed solves run eagerly.
@@ -826,9 +858,10 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   };
   auto issue_pair_graph = [&](int capx) -> int {
     const int cb = bucket(capx);
-    auto it = graphs.find(cb);
-    if (it == graphs.end() && eager_pairs[cb] == 0) {
-      eager_pairs[cb] = 1;
+    const int key = 2 * cb + (dense_rh ? 1 : 0);
+    auto it = graphs.find(key);
+    if (it == graphs.end() && eager_pairs[key] == 0) {
+      eager_pairs[key] = 1;
       HZ_HIP(c, issue_iteration(cb, st, 0));
       HZ_HIP(c, issue_iteration(cb, st, 1));
       return HZ_OK;
@@ -846,7 +879,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       if (gr) (void)hipGraphDestroy(gr);
       if (e != hipSuccess)
         return fail(c, HZ_ERR_DEVICE, "capturing the iteration graph failed: %s", hipGetErrorString(e));
-      it = graphs.emplace(cb, ex).first;
+      it = graphs.emplace(key, ex).first;
     }
     HZ_HIP(c, hipGraphLaunch(it->second, st));
     return HZ_OK;
@@ -861,11 +894,13 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       const bool stale = restart_seq > useq;
       if (!stale) {
         cap = std::min(cap, sm.nactive);
+        if (sm.nrestart == 0) dense_rh = sm.ndense > 0;
         if (sm.nrestart > 0) {
           if (defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 1, x, phr[0], shr[0], n0, st));
           HZ_HIP(c, launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st));  // current p buffer
           HZ_HIP(c, launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
           restart_seq = seq;
+          dense_rh = true;  // r^ = r for the restarted slots
           if ((rc = close_unit()) != HZ_OK) return rc;
           cap = nslots;
         } else if (sm.nactive == 0) {

@@ -237,8 +237,8 @@ namespace hz {
 // MODE 1: BiCGSTAB p = r + beta (p_old - omega v), MODE 2: s = r - alpha v).
 struct RhsIn {
   const double2* a;  // b (MODE 0) or r
-  const double2* b;  // p_old (MODE 1) or v (MODE 2)
-  const double2* c;  // v (MODE 1)
+  const double2* b;  // p_old (MODE 1, 4) or v (MODE 2)
+  const double2* c;  // v (MODE 1); p^_old (MODE 4) or p^ (MODE 5), whose product with B is formed
 };
 
 template <int MODE>

@@ -102,7 +102,8 @@ struct Reduce {
 
 // Summary the host polls: counts of active and restart-pending slots.
 struct Summary {
-  int nactive, nrestart, nother, pad1;  // nother: active slots in the other GMRES phase
+  int nactive, nrestart, nother;  // nother: active slots in the other GMRES phase
+  int ndense;                     // active slots whose shadow residual r^ is a dense vector
 };
 
 struct Tiles {
@@ -186,6 +187,7 @@ hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd
                             double2* v, size_t stride, hipStream_t st);
 hipError_t launch_bicg_p(size_t n, const Batch& bt, int cap, const double2* r, const double2* p_old,
                          const double2* v, double2* p_new, size_t stride, hipStream_t st);
+// v null (2D only): no store; only the slots whose r^ is dense get a partial.
 hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int cap,
                                    const Reduce& rd, const double2* ph, const double2* rh,
                                    double2* v, size_t stride, hipStream_t st);
@@ -212,15 +214,16 @@ hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Redu
 // points to, writable.
 hipError_t launch_rh_sparse(size_t n, int nslots, const Batch& bt, const double2* b, int* idx, double2* val,
                             size_t stride, hipStream_t st);
-enum : int { kFinInit = 0, kFinSigma = 1, kFinOmega = 2, kFinStep = 3, kFinRestart = 4 };
+enum : int { kFinInit = 0, kFinSigma = 1, kFinOmega = 2, kFinStep = 3, kFinRestart = 4, kFinSigmaB = 5 };
 // tiles: the producer's tiles per slot; restart runs over all nslots slots.
-// vec: for sigma v, for step r (the inner products with a sparse r^ are
-// formed here from it); unused otherwise.
+// vec: for sigma v, for sigma-B p^ (v = B p^ is formed at the nodes of a
+// sparse r^; g: the finest 2D grid), for step r (the inner products with a
+// sparse r^ are formed here from it); unused otherwise.
 // ring (step only): 0 records the update's term as pending, 1 clears it.
 // restart_at (step only, > 0): take the restart after that many iterations.
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
                            double tol, int maxit, const double2* vec, size_t stride, hipStream_t st,
-                           int ring = -1, int restart_at = 0);
+                           int ring = -1, int restart_at = 0, const Grid* g = nullptr);
 hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* active, int* nactive,
                           int* fstart, Summary* sum, int want_phase, hipStream_t st);
 hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,

@@ -106,6 +106,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
 
 // LDS-tiled forms (2D): x staged on the tile and its halo, two nodes per thread.
 // WHICH 0: v = B ph, partial <rh, v>; WHICH 1: t = B sh, partials <t, s>, <t, t>.
+// WHICH 0 with y null stores nothing and serves only the slots whose r^ is
+// dense (the others leave at once): their partial <rh, B ph>.
 template <int WHICH>
 __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int per_slot, Batch bt, Reduce rd,
                                                          const double2* __restrict__ xin,
@@ -114,6 +116,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
   __shared__ double2 X[kHZ][kHX];
   int slot, tile;
   if (!decode_tile(bt, per_slot, slot, tile)) return;
+  if (WHICH == 0 && !y && bt.slots[slot].rh_nnz >= 0) return;
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const TileOrg t = tile_org(tile, ntx);
   const size_t base = (size_t)slot * stride;
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     double2 sx, sz;
     halo_sums(X, lz, lx, sx, sz);
     const double2 yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
-    st_nt(y + base + p, yp);
+    if (WHICH == 1 || y) st_nt(y + base + p, yp);
     if (WHICH == 0) {
       if (dots) {
         const double2 d = cconjmul(other[base + p], yp);
@@ -365,7 +368,7 @@ __global__ void __launch_bounds__(kBlock) k_rh_sparse(size_t n, Batch bt, const 
 //   restart: rho = beta = <r, r>, rh = r done by the producer
 __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch bt, Reduce rd,
                                                      double tol, int maxit, const double2* __restrict__ vec,
-                                                     size_t stride, int ring, int restart_at) {
+                                                     size_t stride, int ring, int restart_at, Grid g) {
   int slot;
   if (which == kFinRestart) {
     slot = blockIdx.x;
@@ -374,12 +377,16 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
     return;
   }
   // <rh, v> (sigma) or <rh, r> (step) from r^'s sparse list, in list order,
-  // in place of the producer's partials (which hold zeros there)
+  // in place of the producer's partials (which hold zeros there). Sigma
+  // with vec = ph (kFinSigmaB) forms v = B ph at the list's nodes, and its
+  // partials are read only where r^ is dense (no producer wrote them
+  // otherwise).
   const int nnz = bt.slots[slot].rh_nnz;
-  const bool sparse = (which == kFinSigma || which == kFinStep) && nnz >= 0;
+  const bool form_b = which == kFinSigmaB;
+  const bool sparse = (which == kFinSigma || form_b || which == kFinStep) && nnz >= 0;
   double acc[3] = {0.0, 0.0, 0.0};
   const double* src = rd.partials + (size_t)slot * rd.max_tiles * kPartialWidth;
-  for (int k = threadIdx.x; k < tiles; k += blockDim.x) {
+  for (int k = threadIdx.x; k < tiles && !(form_b && sparse); k += blockDim.x) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) acc[q] += src[(size_t)k * kPartialWidth + q];
   }
@@ -387,8 +394,18 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
     const int* idx = bt.rh_idx + (size_t)slot * kShadowMax;
     const double2* val = bt.rh_val + (size_t)slot * kShadowMax;
     const double2* vs = vec + (size_t)slot * stride;
+    const FreqTab& f = bt.ft[bt.slots[slot].freq];
     for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
-      const double2 d = cconjmul(val[k], vs[idx[k]]);
+      const int p = idx[k];
+      double2 y;
+      if (form_b) {
+        const int iz = p / g.nx, ix = p - iz * g.nx;
+        const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+        y = apply_node<true>(vs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, vs[p]);
+      } else {
+        y = vs[p];
+      }
+      const double2 d = cconjmul(val[k], y);
       acc[0] += d.x;
       acc[1] += d.y;
     }
@@ -413,11 +430,12 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
         S.status = kConverged;
       } else {
         S.rho = c2(b2, 0.0);
-        S.beta = c2(b2, 0.0);
+        S.beta = c2(0.0, 0.0);  // the first p is r
       }
       break;
     }
-    case kFinSigma: {
+    case kFinSigma:
+    case kFinSigmaB: {
       const double2 sigma = c2(acc[0], acc[1]);
       if (!cfinite(sigma)) {
         S.status = kNonfinite;
@@ -483,7 +501,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
         S.status = kBreakdown;
       } else {
         S.rho = rho;
-        S.beta = rho;
+        S.beta = c2(0.0, 0.0);  // the first p after the restart is r
         S.status = kActive;
       }
       break;
@@ -502,9 +520,10 @@ __global__ void __launch_bounds__(1024) k_compact(int nslots, int nrhs, int nfre
   __shared__ int wsum[16];
   __shared__ int wres[16];
   __shared__ int woth[16];
+  __shared__ int wden[16];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
-  int nres_local = 0, noth_local = 0;
+  int nres_local = 0, noth_local = 0, nden_local = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int b0 = 0; b0 < nslots; b0 += blockDim.x) {
@@ -514,6 +533,7 @@ __global__ void __launch_bounds__(1024) k_compact(int nslots, int nrhs, int nfre
     const int a = (st == kActive) && (ph == want_phase);
     nres_local += (st == kRestart);
     noth_local += (st == kActive) && (ph != want_phase);
+    nden_local += a && slots[i].rh_nnz < 0;
     int x = a;  // inclusive scan over the wave
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -536,22 +556,26 @@ __global__ void __launch_bounds__(1024) k_compact(int nslots, int nrhs, int nfre
   for (int off = 32; off > 0; off >>= 1) {
     nres_local += __shfl_xor(nres_local, off, 64);
     noth_local += __shfl_xor(noth_local, off, 64);
+    nden_local += __shfl_xor(nden_local, off, 64);
   }
   if (lane == 0) {
     wres[wid] = nres_local;
     woth[wid] = noth_local;
+    wden[wid] = nden_local;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int nr = 0, no = 0;
+    int nr = 0, no = 0, nd = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
       nr += wres[w];
       no += woth[w];
+      nd += wden[w];
     }
     *nactive = carry;
     sum->nactive = carry;
     sum->nrestart = nr;
     sum->nother = no;
+    sum->ndense = nd;
   }
   // per-frequency ranges of the (ascending, frequency-major) list
   const int total = carry;
@@ -928,6 +952,7 @@ hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int 
                                    double2* v, size_t stride, hipStream_t st) {
   const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
+  if (!v && dim != 2) return hipErrorInvalidValue;
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
   if (dim == 2) {
     const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
@@ -1000,11 +1025,13 @@ hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Redu
 
 hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const Reduce& rd,
                            double tol, int maxit, const double2* vec, size_t stride, hipStream_t st, int ring,
-                           int restart_at) {
+                           int restart_at, const Grid* g) {
   if (cap <= 0) return hipSuccess;
-  if ((which == kFinSigma || which == kFinStep) && !vec) return hipErrorInvalidValue;
+  if ((which == kFinSigma || which == kFinSigmaB || which == kFinStep) && !vec) return hipErrorInvalidValue;
+  if (which == kFinSigmaB && !g) return hipErrorInvalidValue;
+  const Grid gg = g ? *g : Grid{0, 0, 0.0, nullptr};
   hipLaunchKernelGGL(k_bicg_fin, dim3(cap), dim3(kBlock), 0, st, which, tiles, bt, rd, tol, maxit, vec, stride,
-                     ring, restart_at);
+                     ring, restart_at, gg);
   return hipGetLastError();
 }
 

@@ -128,56 +128,75 @@ __device__ __forceinline__ bool wave_tile(const Batch& bt, int nstrip, int nchun
 // pre-smoothed u2 is stored only when u2 is not null: the fused
 // post-smoothing kernel forms it again from b (cheaper than writing and
 // reading it back).
-constexpr int kPreWidth = kLanes - 6;
+//
+// MODE 4 and 5 form the operator product B p^ themselves instead of reading
+// a stored v = B p^: p = r + beta (p_old - omega B p^_old) (p = r where beta
+// is zero: the first iteration and the one after a restart, where p^_old
+// holds nothing of this solve and its value is not used), and
+// s = r - alpha B p^. B p^ on row j comes from p^ on
+// rows j-1 .. j+1, loaded one row ahead of the other inputs; it widens the
+// x-radius to 4, so those strips store 56 columns.
+constexpr int pre_radius(int mode) { return mode >= 4 ? 4 : 3; }
+constexpr int pre_width(int mode) { return kLanes - 2 * pre_radius(mode); }
+constexpr int kPreWidth = pre_width(0);
 
 template <int MODE>
-struct PreRow {  // loads of one row: the right-hand side's inputs, w/D and m
+struct PreRow {  // loads of one row: the right-hand side's inputs, w/D and m (MODE 4, 5: c is p^ on the next row)
   double2 a, b, c, wd;
   double m;
 };
 
 // FINE: launched on the finest level (the same code; a separate symbol lets a
-// profiler tell the finest level's launches from the coarser ones)
+// profiler tell the finest level's launches from the coarser ones). MODE 4
+// and 5 hold p^ on three rows more: they get up to 168 VGPRs (3 waves per
+// SIMD) rather than spill at 128, which made them far slower.
 template <int MODE, bool FINE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE >= 4 ? 3 : 4, 8))) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
                                                     Batch bt, RhsIn in, double2* __restrict__ bout,
                                                     double2* __restrict__ u2, double2* __restrict__ bc,
                                                     size_t stride, size_t sc) {
+  constexpr int R = pre_radius(MODE), W = pre_width(MODE);
   WaveTile w;
-  if (!wave_tile(bt, nstrip, nchunk, chunk_rows, groups, kPreWidth, g.nz, w)) return;
+  if (!wave_tile(bt, nstrip, nchunk, chunk_rows, groups, W, g.nz, w)) return;
   const int lane = threadIdx.x % kLanes;
   const Slot& S = bt.slots[w.slot];
   const FreqTab& f = bt.ft[S.freq];
   double2 beta = c2(0.0, 0.0), om = c2(0.0, 0.0), al = c2(0.0, 0.0);
-  if (MODE == 1) {
+  if (MODE == 1 || MODE == 4) {
     beta = S.beta;
     om = S.omega;
   }
-  if (MODE == 2) al = S.alpha;
-  const int x = w.xs - 3 + lane;
+  if (MODE == 2 || MODE == 5) al = S.alpha;
+  const bool fresh = MODE == 4 && czero(beta);
+  const int x = w.xs - R + lane;
   const bool xin = x >= 0 && x < g.nx;
   const int xx = min(max(x, 0), g.nx - 1);
-  const bool own = lane >= 3 && lane < 3 + kPreWidth && xin;
+  const bool own = lane >= R && lane < R + W && xin;
   const bool cown = own && !(x & 1);
   const size_t base = (size_t)w.slot * stride;
   const double2* wd = f.winv[lvl];
   const double ih = 1.0 / g.h, ih2 = ih * ih;
   const double om2 = f.omega * f.omega;
   const double ka = -om2 * f.sM_re, kb = -om2 * f.sM_im, kc = f.omega * ih;
+  const double kaB = -om2 * f.sB_re, kbB = -om2 * f.sB_im;
   const double omw = 1.0 - f.wj[lvl];
   const AxisC cx = axis_coef(x, g.nx);
   const double cwx = ih2 * cx.w;
   const double2 zero = c2(0.0, 0.0);
+  auto row_index = [&](int j) { return (size_t)min(max(j, 0), g.nz - 1) * g.nx + xx; };
   auto load_row = [&](int j) {
     PreRow<MODE> r;
-    const size_t q = (size_t)min(max(j, 0), g.nz - 1) * g.nx + xx;
+    const size_t q = row_index(j);
     r.a = in.a[base + q];
-    if (MODE != 0) r.b = in.b[base + q];
+    if (MODE != 0 && MODE != 5) r.b = in.b[base + q];
     if (MODE == 1) r.c = in.c[base + q];
+    if (MODE >= 4) r.c = in.c[base + row_index(j + 1)];
     r.wd = wd[q];
     r.m = g.m[q];
     return r;
   };
+  // p^ on the rows of the grid, zero outside it (the operator's missing neighbours)
+  auto p_hat = [&](int j, double2 v) { return keep(xin && j >= 0 && j < g.nz, v); };
   // weight of the right neighbour in the horizontal restriction stencil: 1
   // for the last fine node of an even-count axis (P^T of the clamped
   // interpolation), else 1/2
@@ -186,12 +205,27 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
   // the horizontally restricted residual on j-4, j-3
   double2 u1a = zero, u1b = zero, b1 = zero, b2 = zero, wd1 = zero, u2a = zero, u2b = zero, ha = zero, hb = zero;
   double m1 = 0.0, m2 = 0.0;
+  // MODE 4, 5: p^ on rows j-1 and j
+  double2 q0 = zero, q1 = zero;
+  if (MODE >= 4) {
+    q0 = p_hat(w.z0 - 4, in.c[base + row_index(w.z0 - 4)]);
+    q1 = p_hat(w.z0 - 3, in.c[base + row_index(w.z0 - 3)]);
+  }
   auto step = [&](int j, const PreRow<MODE>& L, bool odd) {
     const bool jin = xin && j >= 0 && j < g.nz;
     double2 bj = zero;
     if (MODE == 0) bj = L.a;
     if (MODE == 1) bj = cadd(L.a, cmul(beta, csub(L.b, cmul(om, L.c))));
     if (MODE == 2) bj = csub(L.a, cmul(al, L.b));
+    if (MODE >= 4) {
+      const double2 q2 = p_hat(j + 1, L.c);
+      const double2 bp = apply_m(cx, axis_coef(j, g.nz), L.m, kaB, kbB, kc, ih2, q1,
+                                 cadd(from_left(q1), from_right(q1)), cadd(q0, q2));
+      q0 = q1;
+      q1 = q2;
+      if (MODE == 4) bj = fresh ? L.a : cadd(L.a, cmul(beta, csub(L.b, cmul(om, bp))));
+      if (MODE == 5) bj = csub(L.a, cmul(al, bp));
+    }
     // outside the grid u1 = 0 through w/D; b and m there only enter values that are zeroed
     const double2 wdj = keep(jin, L.wd);
     const double mj = L.m;
@@ -389,7 +423,9 @@ hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const 
                         double2* bcoarse, size_t stride, size_t sc, int chunk_rows, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
-  const StreamShape sh = stream_shape(g, kPreWidth, chunk_rows);
+  // modes other than 0 form the finest level's right-hand side
+  if (mode < 0 || mode > 5 || mode == 3 || (lvl != 0 && mode != 0)) return hipErrorInvalidValue;
+  const StreamShape sh = stream_shape(g, pre_width(mode), chunk_rows);
   const RhsIn in{a, b, c};
   const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
 #define HZ_PRE2R(M, F)                                                                                     \
@@ -397,6 +433,8 @@ hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const 
                      sh.groups, lvl, bt, in, bout, u2, bcoarse, stride, sc)
   if (mode == 1) HZ_PRE2R(1, true);
   else if (mode == 2) HZ_PRE2R(2, true);
+  else if (mode == 4) HZ_PRE2R(4, true);
+  else if (mode == 5) HZ_PRE2R(5, true);
   else if (lvl == 0) HZ_PRE2R(0, true);
   else HZ_PRE2R(0, false);
 #undef HZ_PRE2R

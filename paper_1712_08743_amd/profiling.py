@@ -26,8 +26,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # timing class -> kernel symbol(s) (finest level); a class with two symbols
 # launches each of them every second iteration
 CLASS_SYMBOL = {
-    "presmooth": "hz::k_pre2r_s<1, true>",
-    "presmooth_s": "hz::k_pre2r_s<2, true>",
+    "presmooth": "hz::k_pre2r_s<4, true>",
+    "presmooth_s": "hz::k_pre2r_s<5, true>",
     "prolong": "hz::k_post2_s<true>",
     "apply": "hz::k_bicg_apply_t<0>",
     "apply_s": "hz::k_bicg_apply_t<1>",

@@ -283,27 +283,40 @@ def test_forced_restart_converges(hz, restart_at, graphs):
 
 def test_kernel_timing_classes(hz):
     """hz_timing_start/read: every launch of a timed class is counted (one
-    operator apply of each kind and one update per BiCGSTAB iteration, two
-    post-smoothing launches per iteration, the coarser levels' launches), the
-    times are positive, untimed classes stay at zero, timing does not change
-    the result, and a class past the last one is refused."""
+    pre-smoothing launch of each kind, one operator apply on s^ and one update
+    per BiCGSTAB iteration, two post-smoothing launches per iteration, the
+    coarser levels' launches), the times are positive, untimed classes stay at
+    zero, timing does not change the result, and a class past the last one is
+    refused. With point sources r^ is a sparse list and no operator pass on p^
+    is made (the pre-smoothing kernels form B p^); a dense right-hand side
+    takes one per iteration for <r^, B p^>."""
     import torch
     w = workloads.model_2d_layered(nz=97, nx=193, h=20.0, nshots=3, freqs=(4.0,))
     c = make_ctx(hz, w.m, w.h)
     b = c.point_rhs([0] * 3, w.src)[None]
     ref, info_ref = c.solve([4.0], 0.01, b, tol=1e-9)
-    c.timing_start(["apply", "apply_s", "update", "prolong", "levels"])
+    c.timing_start(["apply", "apply_s", "update", "prolong", "presmooth_s", "levels"])
     u, info = c.solve([4.0], 0.01, b, tol=1e-9)
     t = {k: c.timing_read(k) for k in hz.HZ_KERNEL}
     c.timing_start([])
     assert torch.equal(u, ref)
     slot_iters = sum(i[1] for i in info)
-    for k in ("apply", "apply_s", "update"):
+    for k in ("presmooth_s", "apply_s", "update"):
         assert t[k][0] >= max(i[1] for i in info) and t[k][1] > 0.0, (k, t[k])
-    assert t["prolong"][0] == 2 * t["apply"][0]
+    assert t["apply"] == (0, 0.0)
+    assert t["prolong"][0] == 2 * t["presmooth_s"][0]
     assert t["levels"][0] > t["prolong"][0] and t["levels"][1] > 0.0
     assert t["presmooth"] == (0, 0.0) and t["coarse"] == (0, 0.0)
     assert slot_iters >= t["update"][0]
+    g = torch.Generator().manual_seed(5)
+    bd = torch.complex(torch.randn((1, 2) + w.shape, generator=g, dtype=torch.float64),
+                       torch.randn((1, 2) + w.shape, generator=g, dtype=torch.float64)).cuda()
+    c.timing_start(["apply", "presmooth_s"])
+    _, info_d = c.solve([4.0], 0.01, bd, tol=1e-9)
+    td = {k: c.timing_read(k) for k in ("apply", "presmooth_s")}
+    c.timing_start([])
+    assert all(i[0] == hz.HZ_RHS_CONVERGED for i in info_d)
+    assert td["apply"][0] == td["presmooth_s"][0] >= max(i[1] for i in info_d) and td["apply"][1] > 0.0, td
     with pytest.raises(hz.HzError) as e:
         c.timing_start([len(hz.HZ_KERNEL)])
     assert e.value.code == hz.HZ_ERR_ARG
