@@ -360,12 +360,12 @@ __global__ void __launch_bounds__(kBlock) k_rh_sparse(size_t n, Batch bt, const 
 // ---------------------------------------------------------------- BiCGSTAB scalars
 // One block per slot: fixed-order sum of the producer's partials, then the
 // scalar step of the method (van der Vorst's BiCGSTAB, right-preconditioned):
-//   init:    bnorm2, rho' = ||b||^2, beta = rho' (rho = alpha = omega = 1)
-//   sigma:   alpha = rho / <rh, v>
+//   init:    bnorm2, rho = ||b||^2, beta = 0 (alpha = omega = 1; the first p is r)
+//   sigma:   alpha = rho / <rh, v> (sigma-B: v = B ph)
 //   omega:   omega = <t, s> / <t, t>
 //   step:    ||r|| test, breakdown / maxit checks, rho' = <rh, r>,
 //            beta = (rho'/rho)(alpha/omega)
-//   restart: rho = beta = <r, r>, rh = r done by the producer
+//   restart: rho = <r, r>, beta = 0; rh = r done by the producer
 __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch bt, Reduce rd,
                                                      double tol, int maxit, const double2* __restrict__ vec,
                                                      size_t stride, int ring, int restart_at, Grid g) {
@@ -384,9 +384,10 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
   const int nnz = bt.slots[slot].rh_nnz;
   const bool form_b = which == kFinSigmaB;
   const bool sparse = (which == kFinSigma || form_b || which == kFinStep) && nnz >= 0;
+  const bool use_partials = !(form_b && sparse);
   double acc[3] = {0.0, 0.0, 0.0};
   const double* src = rd.partials + (size_t)slot * rd.max_tiles * kPartialWidth;
-  for (int k = threadIdx.x; k < tiles && !(form_b && sparse); k += blockDim.x) {
+  for (int k = threadIdx.x; k < tiles && use_partials; k += blockDim.x) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) acc[q] += src[(size_t)k * kPartialWidth + q];
   }
