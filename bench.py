@@ -17,6 +17,8 @@ Prints one JSON line (see the field list at the end of main()).
                                          # for scaling rocprofv3 byte counters
   python bench.py --compare       # preconditioned vs not, shifts, GMRES vs BiCGSTAB,
                                   # Gauss-Newton schedules (a report, not a throughput line)
+  python bench.py --fwi           # gradient and Gauss-Newton step on the full inversion survey
+                                  # (301 x 601, 32 shots x 6 frequencies; a report line)
   python bench.py --serving [--requests R] [--slots S]
       # serving stream: Poisson arrivals of mixed requests (side 129/257/513,
       # f ~ U(2, 15) Hz, 1-32 shots), rate set to 80 % of the measured
@@ -320,6 +322,69 @@ def compare(args):
     print(json.dumps(out), flush=True)
 
 
+def fwi_report(args):
+    """The FWI pieces on the full inversion survey (301 x 601, 32 surface shots,
+    151 receivers, six frequencies, lambda 1e-3): the adjoint-state gradient of
+    Eq. (7) (a forward and an adjoint solve per shot and frequency) and one
+    Gauss-Newton step of Eq. (9) (each CG iteration a Born and an adjoint
+    batch), BiCGSTAB to 1e-8. Observed data come from the library's own solves
+    on the true model at tolerance 1e-12. One JSON line (a report, not the
+    throughput line)."""
+    import torch
+    import numpy as np
+    import paper_1712_08743_amd as hz
+    import workloads
+    g = workloads.model_fwi()
+    src = [(0, ix) for ix in g.src]
+    rec = [(0, ix) for ix in g.rec]
+    ctx = hz.Context(0)
+    ctx.set_model(torch.from_numpy(g.m), g.h)
+    _, d_obs, _ = ctx.misfit(g.freqs, g.alpha, src, rec,
+                             torch.zeros((len(g.freqs), len(src), len(rec)), dtype=torch.complex128), 0.0,
+                             tol=1e-12)
+    d_obs = d_obs.cpu()
+    ctx.set_model(torch.from_numpy(g.m_start), g.h)
+    print("# fwi: warm-up gradient (also runs the launch-shape trials)", file=sys.stderr, flush=True)
+    ctx.gradient(g.freqs, g.alpha, src, rec, d_obs, g.lam, tol=1e-8)
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 3))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        J, grad, info = ctx.gradient(g.freqs, g.alpha, src, rec, d_obs, g.lam, tol=1e-8)
+    torch.cuda.synchronize()
+    t_grad = (time.perf_counter() - t0) / reps
+    nsol = len(info)
+    print(f"# fwi: gradient {t_grad:.3f} s ({nsol} solves)", file=sys.stderr, flush=True)
+    cg = 2
+    t0 = time.perf_counter()
+    dm, J_gn, cg_it, info_gn = ctx.gn_step(g.freqs, g.alpha, src, rec, d_obs, g.lam, cg, tol=1e-8)
+    torch.cuda.synchronize()
+    t_gn = time.perf_counter() - t0
+    # solves of one step: the forward and adjoint batches of the gradient (nsol together), then a
+    # Born and an adjoint batch per CG iteration (nsol again)
+    gn_solves = nsol * (1 + int(cg_it))
+    print(f"# fwi: Gauss-Newton step {t_gn:.3f} s ({cg_it} CG iterations)", file=sys.stderr, flush=True)
+    ctx.close()
+    nodes = g.shape[0] * g.shape[1]
+    out = {
+        "metric": "FWI gradient and Gauss-Newton step time",
+        "unit": "s",
+        "higher_is_better": False,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"fwi-{g.shape[0]}x{g.shape[1]}, {len(src)} shots, {len(rec)} receivers, "
+                               f"{list(g.freqs)} Hz, lambda {g.lam}, BiCGSTAB tol 1e-8, V(2,2) shifted-Laplace "
+                               f"(1,0.5)", "grid": list(g.shape), "nodes": nodes},
+        "gradient": {"seconds": t_grad, "repeats": reps, "solves": nsol, "solves_per_s": nsol / t_grad,
+                     "iterations_mean": float(np.mean([i[1] for i in info])),
+                     "converged": sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED), "J": J},
+        "gauss_newton_step": {"seconds": t_gn, "cg_iterations": int(cg_it), "solves": gn_solves,
+                              "solves_per_s": gn_solves / t_gn, "J": J_gn,
+                              "dm_norm": float(torch.linalg.norm(dm).item())},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def one_rhs_per_launch(ctx, w, b1, tol, shot=31):
     """The plain path: one right-hand side per solve call (shot ``shot`` at
     every frequency of the workload); solves/s averaged over the frequencies,
@@ -349,6 +414,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-single-rhs", action="store_true")
     ap.add_argument("--compare", action="store_true")
+    ap.add_argument("--fwi", action="store_true")
     ap.add_argument("--compare-maxit", type=int, default=20000)
     ap.add_argument("--maxit", type=int, default=10000,
                     help="iteration cap (below convergence only for short hardware-counter runs)")
@@ -365,6 +431,9 @@ def main():
         return
     if args.compare:
         compare(args)
+        return
+    if args.fwi:
+        fwi_report(args)
         return
 
     import numpy as np
