@@ -42,13 +42,12 @@ def smoothing_factor_sampled(kh, beta1, beta2, w, dim=2, n=129):
     s = complex(beta1, -beta2)
     q = float(kh) ** 2
     t = np.linspace(-np.pi, np.pi, n)
-    if dim == 1:
-        hi = np.abs(t) >= np.pi / 2
-        lsym = 2 - 2 * np.cos(t)
-    else:
-        tz, tx = np.meshgrid(t, t, indexing="ij")
-        hi = (np.abs(tz) >= np.pi / 2) | (np.abs(tx) >= np.pi / 2)
-        lsym = 4 - 2 * np.cos(tz) - 2 * np.cos(tx)
+    th = np.meshgrid(*([t] * dim), indexing="ij")
+    hi = np.zeros(th[0].shape, dtype=bool)
+    lsym = np.zeros(th[0].shape)
+    for ta in th:
+        hi |= np.abs(ta) >= np.pi / 2
+        lsym += 2 - 2 * np.cos(ta)
     a = np.abs(1 - w * (lsym - s * q) / (2 * dim - s * q))
     return float(a[hi].max())
 

@@ -12,7 +12,7 @@ geometric multigrid V-cycle, written out plainly:
 * damped Jacobi smoothing u <- u + w_l (b - M_l u) / diag(M_l), nu1 sweeps
   before and nu2 after the coarse correction, starting from u = 0;
 * restriction R = 2^-dim P^T of the weighted residual (full weighting in the
-  interior), bilinear prolongation P (linear in 1D);
+  interior), bilinear prolongation P (linear in 1D, trilinear in 3D);
 * exact solve on the coarsest level (SuperLU here; any exact method is the
   same operator).
 
@@ -49,7 +49,7 @@ def coarse_shape(shape):
 def inject(m):
     """Slowness on the next coarser grid: values at the coincident nodes."""
     m = np.asarray(m)
-    return m[::2] if m.ndim == 1 else m[::2, ::2]
+    return m[(slice(None, None, 2),) * m.ndim]
 
 
 def linear_interp_1d(nc, nf=None):
@@ -75,15 +75,16 @@ def linear_interp_1d(nc, nf=None):
 
 
 def prolongation(coarse, fine=None):
-    """Bilinear (2D) or linear (1D) prolongation from a coarse grid shape to
-    the fine shape (default: the odd-count fine grid 2 nc - 1)."""
+    """Linear (1D), bilinear (2D) or trilinear (3D) prolongation from a coarse
+    grid shape to the fine shape (default: the odd-count fine grid 2 nc - 1):
+    the tensor product of the axes' linear interpolations."""
     if fine is None:
         fine = tuple(2 * (n - 1) + 1 for n in coarse)
-    if len(coarse) == 1:
-        return linear_interp_1d(coarse[0], fine[0])
-    nzc, nxc = coarse
-    # flat order iz * nx + ix: z is the slow (outer) factor of the Kronecker product
-    return sp.kron(linear_interp_1d(nzc, fine[0]), linear_interp_1d(nxc, fine[1])).tocsr()
+    P = linear_interp_1d(coarse[0], fine[0])
+    # flat order: the first axis is the slow (outer) factor of the Kronecker product
+    for a in range(1, len(coarse)):
+        P = sp.kron(P, linear_interp_1d(coarse[a], fine[a]))
+    return P.tocsr()
 
 
 def restriction(coarse, fine=None):

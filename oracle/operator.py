@@ -10,17 +10,20 @@ the discretised problem as B u = f.
 Readings of what the paper leaves open (each listed in the design doc):
 
 * Grid: nodes (iz, ix) at z = iz h, x = ix h, flat index iz*nx + ix; every
-  edge of the rectangle absorbs. In 1D the single axis is x.
+  edge of the rectangle absorbs. In 1D the single axis is x. Eq. (1) allows
+  d = 3 as well: nodes (iz, iy, ix), flat index (iz*ny + iy)*nx + ix, every
+  face of the box absorbing.
 * Absorbing condition: du/dn + j omega m u = 0 on the boundary (n the outward
   normal, undamped wavenumber). Second-order centred differences; the ghost
   node beyond an edge is eliminated with the centred form of the condition.
-* Each row is then multiplied by its control-volume weight w = w_x w_z, with
-  w_axis = 1/2 on the two end nodes of an axis and 1 elsewhere. The result is
+* Each row is then multiplied by its control-volume weight w (the product of
+  the axes' weights), with w_axis = 1/2 on the two end nodes of an axis and 1
+  elsewhere. The result is
   the complex-symmetric matrix
       A = L / h^2 + (j omega / h) diag(g m) - omega^2 s diag(w m^2),
   where L is the real symmetric Neumann Laplacian whose coupling between two
-  neighbours along one axis is the weight of the other axis, and g sums, over
-  the axes on which a node is an end node, the weight of the other axis.
+  neighbours along one axis is the product of the other axes' weights, and g
+  sums that product over the axis ends a node lies on.
   s = 1 - j alpha gives B; s = beta1 - j beta2 gives the shifted Laplacian M
   (same boundary term).
 * A unit point source at node p is b = e_p / h^dim in this weighted system.
@@ -39,56 +42,55 @@ def end_weights(n):
 
 
 def stencil_parts(shape):
-    """Return (L, g, w) for a grid of the given shape (n,) or (nz, nx).
+    """Return (L, g, w) for a grid of the given shape (n,), (nz, nx) or
+    (nz, ny, nx), axes in that order, the last one fastest in the flat order.
 
     L is the weighted Neumann Laplacian without the 1/h^2 factor (sparse,
-    real, symmetric), g the boundary-term weight and w the mass weight, both
-    flattened in the grid's flat order.
+    real, symmetric): two neighbours along an axis are coupled by the product
+    of the other axes' weights (the face between their control volumes).
+    g is the boundary-term weight: a node on an end of an axis gets that same
+    product for each such end. w is the mass weight, the product of all the
+    axes' weights. g and w are flattened in the grid's flat order.
     """
-    if len(shape) == 1:
-        (n,) = shape
-        p = np.arange(n - 1)
-        q = p + 1
-        c = np.ones(n - 1)
-        g = np.zeros(n)
-        g[0] = 1.0
-        g[-1] = 1.0
-        w = end_weights(n)
-        size = n
-    else:
-        nz, nx = shape
-        wz, wx = end_weights(nz), end_weights(nx)
-        idx = np.arange(nz * nx).reshape(nz, nx)
-        # neighbours along x share the row's z-weight
-        px, qx = idx[:, :-1].ravel(), idx[:, 1:].ravel()
-        cx = np.repeat(wz, nx - 1)
-        # neighbours along z share the column's x-weight
-        pz, qz = idx[:-1, :].ravel(), idx[1:, :].ravel()
-        cz = np.tile(wx, nz - 1)
-        p = np.concatenate([px, pz])
-        q = np.concatenate([qx, qz])
-        c = np.concatenate([cx, cz])
-        g2 = np.zeros((nz, nx))
-        g2[:, 0] += wz
-        g2[:, -1] += wz
-        g2[0, :] += wx
-        g2[-1, :] += wx
-        g = g2.ravel()
-        w = np.outer(wz, wx).ravel()
-        size = nz * nx
+    shape = tuple(int(n) for n in shape)
+    dim = len(shape)
+    size = int(np.prod(shape))
+    ws = [end_weights(n) for n in shape]
+    idx = np.arange(size).reshape(shape)
+    ps, qs, cs = [], [], []
+    g = np.zeros(shape)
+    for a in range(dim):
+        face = np.ones(shape)
+        for b in range(dim):
+            if b != a:
+                face = face * ws[b].reshape([-1 if i == b else 1 for i in range(dim)])
+        lo = [slice(None)] * dim
+        hi = [slice(None)] * dim
+        lo[a], hi[a] = slice(0, -1), slice(1, None)
+        ps.append(idx[tuple(lo)].ravel())
+        qs.append(idx[tuple(hi)].ravel())
+        cs.append(face[tuple(lo)].ravel())
+        for end in (0, -1):
+            sel = [slice(None)] * dim
+            sel[a] = end
+            g[tuple(sel)] += face[tuple(sel)]
+    p, q, c = np.concatenate(ps), np.concatenate(qs), np.concatenate(cs)
+    w = ws[0]
+    for b in range(1, dim):
+        w = np.multiply.outer(w, ws[b])
     off = sp.coo_matrix((np.concatenate([-c, -c]),
                          (np.concatenate([p, q]), np.concatenate([q, p]))),
                         shape=(size, size))
     deg = np.bincount(p, weights=c, minlength=size) + \
         np.bincount(q, weights=c, minlength=size)
     L = (off + sp.diags(deg)).tocsr()
-    return L, g, w
+    return L, g.ravel(), np.asarray(w).ravel()
 
 
 def helmholtz_matrix(m, h, omega, s):
     """A = L/h^2 + (j omega/h) diag(g m) - omega^2 s diag(w m^2), CSR complex128.
 
-    m: slowness, shape (n,) for 1D or (nz, nx) for 2D. s: complex mass shift;
+    m: slowness, shape (n,), (nz, nx) or (nz, ny, nx). s: complex mass shift;
     s = 1 - j alpha is the operator B of Eq. (2)-(3), s = beta1 - j beta2 the
     shifted Laplacian M.
     """
