@@ -151,6 +151,26 @@ int  hz_set_model(hz_ctx *c, int dim, int nz, int nx, double h, const double *m_
 int  hz_point_rhs(hz_ctx *c, int nsrc, const int *iz, const int *ix,
                   const hz_c128 *amp, hz_c128 *b_dev);
 
+/* A 3D slowness model (Eq. (1) poses the problem in d = 1, 2, 3 dimensions;
+ * constant density as in Eq. (2)): nodes (iz, iy, ix) at spacing h, every
+ * face of the box absorbing, the same control-volume discretisation as in 1D
+ * and 2D (7-point stencil; a node's face weights are the products of the
+ * other axes' end weights). m_dev: device, [nz][ny][nx] doubles, copied.
+ * Every axis halves on each coarser level. A 3D model is solved by hz_solve
+ * with BiCGSTAB and the multigrid or no preconditioner (u_dev and b_dev
+ * [nfreq][nrhs][nz][ny][nx]); GMRES, the exact 1D preconditioner, the
+ * misfit, gradient and Gauss-Newton calls return HZ_ERR_ARG for it.
+ * Errors: HZ_ERR_ARG (nz, ny or nx < 3, h <= 0, non-finite or non-positive m,
+ * more than 2^30 nodes). */
+int  hz_set_model_3d(hz_ctx *c, int nz, int ny, int nx, double h, const double *m_dev);
+
+/* Point sources on a 3D model: b_dev[s] = amp[s] / h^3 at node
+ * (iz[s], iy[s], ix[s]), zero elsewhere; b_dev is [nsrc][nz][ny][nx].
+ * Errors: HZ_ERR_STATE, HZ_ERR_ARG (node outside the grid, model not 3D;
+ * hz_point_rhs refuses a 3D model). */
+int  hz_point_rhs_3d(hz_ctx *c, int nsrc, const int *iz, const int *iy, const int *ix,
+                     const hz_c128 *amp, hz_c128 *b_dev);
+
 /* Solve B(omega_f) u = b for nfreq frequencies (Hz, > 0) times nrhs
  * right-hand sides each, all in one batch. b_dev and u_dev are
  * [nfreq][nrhs][nz][nx] and must not overlap. info (host, optional) receives

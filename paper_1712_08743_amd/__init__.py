@@ -77,6 +77,8 @@ _SIGS = {
     "hz_destroy": (None, [_vp]),
     "hz_set_model": (_i, [_vp, _i, _i, _i, _d, _vp]),
     "hz_point_rhs": (_i, [_vp, _i, _ip, _ip, _vp, _vp]),
+    "hz_set_model_3d": (_i, [_vp, _i, _i, _i, _d, _vp]),
+    "hz_point_rhs_3d": (_i, [_vp, _i, _ip, _ip, _ip, _vp, _vp]),
     "hz_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _vp, _vp,
                       ctypes.POINTER(RhsInfo)]),
     "hz_misfit": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
@@ -193,16 +195,21 @@ class Context:
 
     # -- model and sources -------------------------------------------------
     def set_model(self, m, h):
-        """m: float64 tensor (n,) for 1D or (nz, nx) for 2D, slowness in s/m."""
+        """m: float64 tensor (n,) for 1D, (nz, nx) for 2D or (nz, ny, nx) for 3D, slowness in s/m."""
         t = self.torch
         m = m.to(device=self.device, dtype=t.float64).contiguous()
         if m.dim() == 1:
             dim, nz, nx = 1, 1, m.shape[0]
         elif m.dim() == 2:
             dim, nz, nx = 2, m.shape[0], m.shape[1]
+        elif m.dim() == 3:
+            dim = 3
         else:
-            raise ValueError("m must be 1D or 2D")
-        self._check(_lib.hz_set_model(self._h, dim, nz, nx, float(h), _ptr(m)))
+            raise ValueError("m must be 1D, 2D or 3D")
+        if dim == 3:
+            self._check(_lib.hz_set_model_3d(self._h, m.shape[0], m.shape[1], m.shape[2], float(h), _ptr(m)))
+        else:
+            self._check(_lib.hz_set_model(self._h, dim, nz, nx, float(h), _ptr(m)))
         self.shape = tuple(m.shape)
         self.dim = dim
         self.h = float(h)
@@ -229,6 +236,21 @@ class Context:
         self._check(_lib.hz_point_rhs(self._h, nsrc, _int_array(iz), _int_array(ix),
                                       ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
                                       _ptr(b)))
+        return b
+
+    def point_rhs_3d(self, iz, iy, ix, amp=None):
+        """Weighted point sources on a 3D model, complex128 tensor [nsrc, nz, ny, nx]."""
+        t = self.torch
+        nsrc = len(ix)
+        b = t.empty((nsrc,) + self.shape, dtype=t.complex128, device=self.device)
+        ampbuf = None
+        if amp is not None:
+            ampbuf = (ctypes.c_double * (2 * nsrc))()
+            for k, a in enumerate(amp):
+                ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
+        self._check(_lib.hz_point_rhs_3d(self._h, nsrc, _int_array(iz), _int_array(iy), _int_array(ix),
+                                         ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
+                                         _ptr(b)))
         return b
 
     # -- solves ------------------------------------------------------------

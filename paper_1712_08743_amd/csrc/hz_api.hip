@@ -50,10 +50,11 @@ struct DevBuf {
 };
 
 struct LevelInfo {
-  int nz = 0, nx = 0;
+  int nz = 0, nx = 0, ny = 1;  // ny > 1 on 3D grids only
   double h = 0.0;
   DevBuf m;
-  size_t n() const { return (size_t)nz * nx; }
+  size_t n() const { return (size_t)nz * ny * nx; }
+  int rows() const { return nz * ny; }  // rows of the 2D tiling of the grid
 };
 
 // Fine-level vectors of the solvers (x is the caller's output buffer).
@@ -73,7 +74,7 @@ struct hz_ctx {
   size_t budget = 0;
   std::string err;
   // model
-  int dim = 0, nz = 0, nx = 0;
+  int dim = 0, nz = 0, nx = 0, ny = 1;
   double h = 0.0, mmin = 0.0, mmax = 0.0;
   int maxlev = 0;
   LevelInfo lv[kMaxLevels];
@@ -156,6 +157,7 @@ Grid grid_of(const hz_ctx* c, int l) {
   Grid g;
   g.nz = c->lv[l].nz;
   g.nx = c->lv[l].nx;
+  g.ny = c->lv[l].ny;
   g.h = c->lv[l].h;
   g.m = c->lv[l].m.as<double>();
   return g;
@@ -212,6 +214,29 @@ int grid_default_levels(int dim, int nz, int nx) {
   return L;
 }
 
+// The same two counts on a 3D grid (every axis halves).
+int grid_max_levels3(int nz, int ny, int nx) {
+  int L = 1;
+  while (L < kMaxLevels && nz >= 5 && ny >= 5 && nx >= 5) {
+    nz = coarse_n(nz);
+    ny = coarse_n(ny);
+    nx = coarse_n(nx);
+    ++L;
+  }
+  return L;
+}
+
+int grid_default_levels3(int nz, int ny, int nx) {
+  int L = 1;
+  while (L < kMaxLevels && (long)nz * ny * nx > kCoarseTarget && nz >= 5 && ny >= 5 && nx >= 5) {
+    nz = coarse_n(nz);
+    ny = coarse_n(ny);
+    nx = coarse_n(nx);
+    ++L;
+  }
+  return L;
+}
+
 }  // namespace hz
 
 namespace {
@@ -250,9 +275,12 @@ int plan_grid(int dim, int maxlev, int deflev, double h, double mmin, double mma
   return HZ_OK;
 }
 
+int default_levels_of(const hz_ctx* c) {
+  return c->dim == 3 ? grid_default_levels3(c->nz, c->ny, c->nx) : grid_default_levels(c->dim, c->nz, c->nx);
+}
+
 int make_plan(const hz_ctx* c, const hz_solve_opts* o, double omega, int* levels, double* w) {
-  return plan_grid(c->dim, c->maxlev, grid_default_levels(c->dim, c->nz, c->nx), c->h, c->mmin, c->mmax, o, omega,
-                   levels, w);
+  return plan_grid(c->dim, c->maxlev, default_levels_of(c), c->h, c->mmin, c->mmax, o, omega, levels, w);
 }
 
 int check_opts(hz_ctx* c, const hz_solve_opts* o) {
@@ -261,6 +289,7 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
   if (o->krylov != HZ_BICGSTAB && o->krylov != HZ_GMRES) return fail(c, HZ_ERR_ARG, "unknown krylov method");
   if (o->krylov == HZ_GMRES && (o->gmres_m < 1 || o->gmres_m > 200))
     return fail(c, HZ_ERR_ARG, "gmres_m must be in [1, 200]");
+  if (o->krylov == HZ_GMRES && c->dim == 3) return fail(c, HZ_ERR_ARG, "3D grids are solved by BiCGSTAB only");
   if (o->precond < HZ_PRECOND_MG || o->precond > HZ_PRECOND_NONE) return fail(c, HZ_ERR_ARG, "unknown preconditioner");
   if (o->precond != HZ_PRECOND_NONE) {
     if (!(o->beta2 > 0.0) || !isfinite(o->beta1) || !isfinite(o->beta2))
@@ -272,9 +301,9 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
     if (!(o->jacobi_w > 0.0 && o->jacobi_w <= 1.0)) return fail(c, HZ_ERR_ARG, "jacobi_w must be in (0, 1]");
     if (o->levels < 0) return fail(c, HZ_ERR_ARG, "levels must be >= 0");
     if (o->levels > c->maxlev)
-      return fail(c, HZ_ERR_SHAPE, "grid %dx%d allows at most %d levels", c->nz, c->nx, c->maxlev);
+      return fail(c, HZ_ERR_SHAPE, "the grid allows at most %d levels", c->maxlev);
     if (o->jacobi_w_level) {
-      const int L = o->levels > 0 ? o->levels : grid_default_levels(c->dim, c->nz, c->nx);
+      const int L = o->levels > 0 ? o->levels : default_levels_of(c);
       for (int l = 0; l < L - 1; ++l)
         if (!(o->jacobi_w_level[l] > 0.0 && o->jacobi_w_level[l] <= 1.0))
           return fail(c, HZ_ERR_ARG, "jacobi_w_level[%d] must be in (0, 1]", l);
@@ -310,8 +339,8 @@ int ensure_workspace(hz_ctx* c, int nslots, int levels) {
     for (int k = 0; k < kNumLevelVec; ++k)
       HZ_ALLOC(c, c->lev[l][k], (size_t)nslots * c->lv[l].n() * sizeof(double2));
   // reduction scratch: enough tiles for any kernel on the fine grid
-  const Tiles t = grid_tiles(c->lv[0].nz, c->lv[0].nx, c->dim);
-  const int tiles = std::max({t.per_slot, reduce_tiles(c->lv[0].nz, c->lv[0].nx, c->dim), vec_tiles(n0)});
+  const Tiles t = grid_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);
+  const int tiles = std::max({t.per_slot, reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim), vec_tiles(n0)});
   if (nslots > c->slot_cap || tiles > c->partial_tiles) {
     const int cap = std::max(nslots, c->slot_cap);
     HZ_ALLOC(c, c->partials, (size_t)cap * tiles * kPartialWidth * sizeof(double));
@@ -613,7 +642,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       bl = bc;
       continue;
     }
-    if (cy.nu1 == 2) {
+    if (cy.nu1 == 2 && dim == 1) {
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
       if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : HZ_KERNEL_LEVELS, [&] {
@@ -713,7 +742,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   double2* s = c->fine[kS].as<double2>();
   double2* t = c->fine[kT].as<double2>();
   const bool identity = cy.precond == HZ_PRECOND_NONE;
-  const bool fused = fused_pre(cy);
+  const bool fused = fused_pre(cy) && c->dim != 3;
   // 2D with the fused pre-smoothing kernel: v = B p^ is never stored. The
   // pre-smoothing kernels form it from p^ (the last iteration's p^ for the p
   // update, the current one for s), and sigma = <r^, B p^> is formed at the
@@ -748,7 +777,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   };
 
   const int vt = vec_tiles(n0);
-  const int gt = reduce_tiles(c->lv[0].nz, c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
+  const int gt = reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
   int rc;
   HZ_HIP(c, launch_bicg_init(n0, bt, nslots, rd, b, x, r, rh, p, v, n0, st));
   HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
@@ -1192,16 +1221,11 @@ void hz_destroy(hz_ctx* c) {
   delete c;
 }
 
-int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_dev) {
-  if (!c) return HZ_ERR_ARG;
-  if (!m_dev) return fail(c, HZ_ERR_ARG, "m_dev is NULL");
-  if (dim != 1 && dim != 2) return fail(c, HZ_ERR_ARG, "dim must be 1 or 2");
-  if (dim == 1 && (nz != 1 || nx < 3)) return fail(c, HZ_ERR_ARG, "1D needs nz = 1 and nx >= 3");
-  if (dim == 2 && (nz < 3 || nx < 3)) return fail(c, HZ_ERR_ARG, "2D needs nz, nx >= 3");
-  if ((size_t)nz * nx > (size_t)1 << 30) return fail(c, HZ_ERR_ARG, "grid too large");
-  if (!(h > 0.0) || !isfinite(h)) return fail(c, HZ_ERR_ARG, "h must be positive");
+namespace {
+// The model of any dimension (ny = 1 below 3D); arguments checked by the callers.
+int set_model_impl(hz_ctx* c, int dim, int nz, int ny, int nx, double h, const double* m_dev) {
   HZ_HIP(c, hipSetDevice(c->device));
-  const size_t n = (size_t)nz * nx;
+  const size_t n = (size_t)nz * ny * nx;
   HZ_ALLOC(c, c->lv[0].m, n * sizeof(double));
   HZ_HIP(c, hipMemcpyAsync(c->lv[0].m.p, m_dev, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   DevBuf chk;
@@ -1216,20 +1240,23 @@ int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_d
   }
   c->dim = dim;
   c->nz = nz;
+  c->ny = ny;
   c->nx = nx;
   c->h = h;
   c->mmin = out3[0];
   c->mmax = out3[1];
   c->lv[0].nz = nz;
+  c->lv[0].ny = ny;
   c->lv[0].nx = nx;
   c->lv[0].h = h;
   int L = 1;
   while (L < kMaxLevels) {
     const LevelInfo& f = c->lv[L - 1];
-    if (f.nx < 5 || (dim == 2 && f.nz < 5)) break;
+    if (f.nx < 5 || (dim >= 2 && f.nz < 5) || (dim == 3 && f.ny < 5)) break;
     LevelInfo& cl = c->lv[L];
     cl.nx = coarse_n(f.nx);
     cl.nz = dim == 1 ? 1 : coarse_n(f.nz);
+    cl.ny = dim == 3 ? coarse_n(f.ny) : 1;
     cl.h = 2.0 * f.h;
     HZ_ALLOC(c, cl.m, cl.n() * sizeof(double));
     HZ_HIP(c, launch_inject(grid_of(c, L - 1), dim, cl.m.as<double>(), c->stream));
@@ -1243,17 +1270,32 @@ int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_d
   return HZ_OK;
 }
 
-int hz_point_rhs(hz_ctx* c, int nsrc, const int* iz, const int* ix, const hz_c128* amp,
-                 hz_c128* b_dev) {
-  int rc = require_model(c);
-  if (rc) return rc;
-  if (nsrc < 1 || !iz || !ix || !b_dev) return fail(c, HZ_ERR_ARG, "bad point-source arguments");
-  std::vector<int> nodes(nsrc);
-  for (int s = 0; s < nsrc; ++s) {
-    if (iz[s] < 0 || iz[s] >= c->nz || ix[s] < 0 || ix[s] >= c->nx)
-      return fail(c, HZ_ERR_ARG, "source %d at (%d, %d) is outside the grid", s, iz[s], ix[s]);
-    nodes[s] = iz[s] * c->nx + ix[s];
-  }
+}  // namespace
+
+int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_dev) {
+  if (!c) return HZ_ERR_ARG;
+  if (!m_dev) return fail(c, HZ_ERR_ARG, "m_dev is NULL");
+  if (dim != 1 && dim != 2) return fail(c, HZ_ERR_ARG, "dim must be 1 or 2 (3D grids: hz_set_model_3d)");
+  if (dim == 1 && (nz != 1 || nx < 3)) return fail(c, HZ_ERR_ARG, "1D needs nz = 1 and nx >= 3");
+  if (dim == 2 && (nz < 3 || nx < 3)) return fail(c, HZ_ERR_ARG, "2D needs nz, nx >= 3");
+  if ((size_t)nz * nx > (size_t)1 << 30) return fail(c, HZ_ERR_ARG, "grid too large");
+  if (!(h > 0.0) || !isfinite(h)) return fail(c, HZ_ERR_ARG, "h must be positive");
+  return set_model_impl(c, dim, nz, 1, nx, h, m_dev);
+}
+
+int hz_set_model_3d(hz_ctx* c, int nz, int ny, int nx, double h, const double* m_dev) {
+  if (!c) return HZ_ERR_ARG;
+  if (!m_dev) return fail(c, HZ_ERR_ARG, "m_dev is NULL");
+  if (nz < 3 || ny < 3 || nx < 3) return fail(c, HZ_ERR_ARG, "3D needs nz, ny, nx >= 3");
+  if ((size_t)nz * ny * nx > (size_t)1 << 30) return fail(c, HZ_ERR_ARG, "grid too large");
+  if (!(h > 0.0) || !isfinite(h)) return fail(c, HZ_ERR_ARG, "h must be positive");
+  return set_model_impl(c, 3, nz, ny, nx, h, m_dev);
+}
+
+namespace {
+// b_dev[s] = amp_s / h^dim at node nodes[s] (flat index), zero elsewhere
+int set_points(hz_ctx* c, const std::vector<int>& nodes, const hz_c128* amp, hz_c128* b_dev) {
+  const int nsrc = (int)nodes.size();
   HZ_HIP(c, hipSetDevice(c->device));
   HZ_ALLOC(c, c->scratch_int, (size_t)nsrc * sizeof(int));
   HZ_HIP(c, hipMemcpyAsync(c->scratch_int.p, nodes.data(), nsrc * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -1263,11 +1305,42 @@ int hz_point_rhs(hz_ctx* c, int nsrc, const int* iz, const int* ix, const hz_c12
     HZ_HIP(c, hipMemcpyAsync(c->scratch_c.p, amp, nsrc * sizeof(double2), hipMemcpyHostToDevice, c->stream));
     ampd = c->scratch_c.as<double2>();
   }
-  const double scale = c->dim == 2 ? 1.0 / (c->h * c->h) : 1.0 / c->h;
+  const double scale = c->dim == 1 ? 1.0 / c->h : (c->dim == 2 ? 1.0 / (c->h * c->h) : 1.0 / std::pow(c->h, 3.0));
   HZ_HIP(c, launch_point_rhs(c->lv[0].n(), nsrc, c->scratch_int.as<int>(), ampd, scale,
                              reinterpret_cast<double2*>(b_dev), c->stream));
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   return HZ_OK;
+}
+}  // namespace
+
+int hz_point_rhs(hz_ctx* c, int nsrc, const int* iz, const int* ix, const hz_c128* amp,
+                 hz_c128* b_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (c->dim == 3) return fail(c, HZ_ERR_ARG, "the model is 3D: use hz_point_rhs_3d");
+  if (nsrc < 1 || !iz || !ix || !b_dev) return fail(c, HZ_ERR_ARG, "bad point-source arguments");
+  std::vector<int> nodes(nsrc);
+  for (int s = 0; s < nsrc; ++s) {
+    if (iz[s] < 0 || iz[s] >= c->nz || ix[s] < 0 || ix[s] >= c->nx)
+      return fail(c, HZ_ERR_ARG, "source %d at (%d, %d) is outside the grid", s, iz[s], ix[s]);
+    nodes[s] = iz[s] * c->nx + ix[s];
+  }
+  return set_points(c, nodes, amp, b_dev);
+}
+
+int hz_point_rhs_3d(hz_ctx* c, int nsrc, const int* iz, const int* iy, const int* ix, const hz_c128* amp,
+                    hz_c128* b_dev) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (c->dim != 3) return fail(c, HZ_ERR_ARG, "the model is not 3D: use hz_point_rhs");
+  if (nsrc < 1 || !iz || !iy || !ix || !b_dev) return fail(c, HZ_ERR_ARG, "bad point-source arguments");
+  std::vector<int> nodes(nsrc);
+  for (int s = 0; s < nsrc; ++s) {
+    if (iz[s] < 0 || iz[s] >= c->nz || iy[s] < 0 || iy[s] >= c->ny || ix[s] < 0 || ix[s] >= c->nx)
+      return fail(c, HZ_ERR_ARG, "source %d at (%d, %d, %d) is outside the grid", s, iz[s], iy[s], ix[s]);
+    nodes[s] = (iz[s] * c->ny + iy[s]) * c->nx + ix[s];
+  }
+  return set_points(c, nodes, amp, b_dev);
 }
 
 int hz_plan(const hz_ctx* c, const hz_solve_opts* o, double freq_hz, int* levels, double* w) {
@@ -1358,6 +1431,7 @@ int hz_misfit(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_h
               double* J, hz_c128* d_cal_dev, hz_rhs_info* info) {
   int rc = require_model(c);
   if (rc) return rc;
+  if (c->dim == 3) return fail(c, HZ_ERR_ARG, "the misfit, gradient and Gauss-Newton calls take 1D and 2D models");
   if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
       !d_obs_dev || !J)
     return fail(c, HZ_ERR_ARG, "bad misfit arguments");
@@ -1407,6 +1481,7 @@ int hz_gradient(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq
                 double* grad_dev, hz_rhs_info* info) {
   int rc = require_model(c);
   if (rc) return rc;
+  if (c->dim == 3) return fail(c, HZ_ERR_ARG, "the misfit, gradient and Gauss-Newton calls take 1D and 2D models");
   if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
       !d_obs_dev || !J || !grad_dev)
     return fail(c, HZ_ERR_ARG, "bad gradient arguments");
@@ -1509,6 +1584,7 @@ int hz_gn_step(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_
                double cg_tol, double* J, double* dm_dev, int* cg_done, hz_rhs_info* info) {
   int rc = require_model(c);
   if (rc) return rc;
+  if (c->dim == 3) return fail(c, HZ_ERR_ARG, "the misfit, gradient and Gauss-Newton calls take 1D and 2D models");
   if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
       !d_obs_dev || !J || !dm_dev || !cg_done || cg_iters < 0)
     return fail(c, HZ_ERR_ARG, "bad Gauss-Newton arguments");

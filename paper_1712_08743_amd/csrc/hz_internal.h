@@ -29,7 +29,8 @@ enum : int {
 struct Grid {
   int nz, nx;
   double h;
-  const double* m;  // device, [nz][nx]
+  const double* m;  // device, [nz][nx] ([nz][ny][nx] on 3D grids)
+  int ny = 1;       // 3D grids only
 };
 
 // Per-frequency constants (device table).

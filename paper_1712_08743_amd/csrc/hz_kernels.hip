@@ -19,6 +19,7 @@
 // the device so that converged right-hand sides cost no launch slots.
 
 #include "hz_device.h"
+#include "hz_node3.h"
 
 #include <math.h>
 
@@ -711,13 +712,192 @@ __global__ void __launch_bounds__(1024) k_check_model(size_t n, const double* __
   }
 }
 
+// ---------------------------------------------------------------- 3D grids
+// One node per thread on (nz, ny, nx) grids (hz_node3.h): neighbours are
+// read from memory, the 2D tiling runs over the nz * ny rows.
+
+__global__ void __launch_bounds__(kBlock) k_apply3(Grid g, Tiles t, int which, Batch bt,
+                                                   const double2* __restrict__ x, double2* __restrict__ y,
+                                                   size_t stride) {
+  int slot, tile, iz, iy, ix;
+  size_t p;
+  if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, g, iz, iy, ix, p)) return;
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const double sre = which ? f.sM_re : f.sB_re, sim = which ? f.sM_im : f.sB_im;
+  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, sre, sim);
+  const double2* xs = x + (size_t)slot * stride;
+  y[(size_t)slot * stride + p] = apply_node3(xs, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
+}
+
+// u_out = u_in + w (b - M u_in) / diag(M); ZERO: u_in = 0 (as k_smooth)
+template <bool ZERO>
+__global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, double w_override, Batch bt,
+                                                    const double2* __restrict__ b,
+                                                    const double2* __restrict__ u_in,
+                                                    double2* __restrict__ u_out, size_t stride, int coarse_only) {
+  int slot, tile, iz, iy, ix;
+  size_t p;
+  if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, g, iz, iy, ix, p)) return;
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  if (coarse_only && !f.coarse_jacobi) return;
+  const double ih2 = 1.0 / (g.h * g.h);
+  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
+  const double2 wdinv = w_override > 0.0 ? cscale(w_override, cinv(diag3(c, ih2))) : f.winv[lvl][p];
+  const size_t base = (size_t)slot * stride;
+  const double2 bp = b[base + p];
+  double2 out;
+  if (ZERO) {
+    out = cmul(bp, wdinv);
+  } else {
+    const double2* us = u_in + base;
+    const double2 res = csub(bp, apply_node3(us, p, iz, iy, ix, g, ih2, c));
+    out = cadd(us[p], cmul(res, wdinv));
+  }
+  u_out[base + p] = out;
+}
+
+__global__ void k_winv3(Grid g, double omega, double s_re, double s_im, double w, double2* __restrict__ winv) {
+  const size_t n = (size_t)g.nz * g.ny * g.nx;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int ix = (int)(p % g.nx);
+  const int r = (int)(p / g.nx);
+  const int iz = r / g.ny, iy = r - iz * g.ny;
+  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], omega, s_re, s_im);
+  winv[p] = cscale(w, cinv(diag3(c, 1.0 / (g.h * g.h))));
+}
+
+// weight of fine offset d in {-1, 0, 1} around coarse node J in P^T (see k_restrict)
+__device__ __forceinline__ double pt_weight(int d, int J, int nf) {
+  return (d == 0 || (d == 1 && 2 * J + 2 == nf)) ? 1.0 : 0.5;
+}
+
+// bc = 2^-3 P^T (b - M u), one thread per coarse node, the residual formed
+// at each of the (up to) 27 fine nodes it gathers
+__global__ void __launch_bounds__(kBlock) k_restrict3(Grid gf, Grid gc, Tiles t, Batch bt,
+                                                      const double2* __restrict__ b,
+                                                      const double2* __restrict__ u,
+                                                      double2* __restrict__ bc, size_t sf, size_t sc) {
+  int slot, tile, Iz, Iy, Ix;
+  size_t P;
+  if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, gc, Iz, Iy, Ix, P)) return;
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const double ih2 = 1.0 / (gf.h * gf.h);
+  const double2* bs = b + (size_t)slot * sf;
+  const double2* us = u + (size_t)slot * sf;
+  double2 acc = c2(0.0, 0.0);
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int iz = 2 * Iz + dz;
+    if (iz < 0 || iz >= gf.nz) continue;
+    const double wz = pt_weight(dz, Iz, gf.nz);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int iy = 2 * Iy + dy;
+      if (iy < 0 || iy >= gf.ny) continue;
+      const double wzy = wz * pt_weight(dy, Iy, gf.ny);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ix = 2 * Ix + dx;
+        if (ix < 0 || ix >= gf.nx) continue;
+        const size_t p = ((size_t)iz * gf.ny + iy) * gf.nx + ix;
+        const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
+        const double2 r = csub(bs[p], apply_node3(us, p, iz, iy, ix, gf, ih2, c));
+        acc = cadd(acc, cscale(wzy * pt_weight(dx, Ix, gf.nx), r));
+      }
+    }
+  }
+  bc[(size_t)slot * sc + P] = cscale(0.125, acc);
+}
+
+// u_out = u_in + P e (u_out may be u_in)
+__global__ void __launch_bounds__(kBlock) k_prolong3(Grid gf, Grid gc, Tiles t, Batch bt,
+                                                     const double2* __restrict__ e, const double2* u_in,
+                                                     double2* u_out, size_t sf, size_t sc) {
+  int slot, tile, iz, iy, ix;
+  size_t p;
+  if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, gf, iz, iy, ix, p)) return;
+  const size_t q = (size_t)slot * sf + p;
+  u_out[q] = cadd(u_in[q], interp3(e + (size_t)slot * sc, iz, iy, ix, gc.nz, gc.ny, gc.nx));
+}
+
+// Prolongation, correction and one damped-Jacobi sweep in one pass (as
+// k_prolong_smooth): u3 = u2 + P e at the node and its six neighbours.
+__global__ void __launch_bounds__(kBlock) k_prolong_smooth3(Grid gf, Grid gc, Tiles t, int lvl, Batch bt,
+                                                            const double2* __restrict__ e,
+                                                            const double2* __restrict__ b,
+                                                            const double2* __restrict__ u2,
+                                                            double2* __restrict__ u_out, size_t sf, size_t sc) {
+  int slot, tile, iz, iy, ix;
+  size_t p;
+  if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, gf, iz, iy, ix, p)) return;
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const double ih2 = 1.0 / (gf.h * gf.h);
+  const size_t base = (size_t)slot * sf;
+  const double2* es = e + (size_t)slot * sc;
+  const double2* us = u2 + base;
+  auto u3_at = [&](int qz, int qy, int qx) -> double2 {
+    return cadd(us[((size_t)qz * gf.ny + qy) * gf.nx + qx], interp3(es, qz, qy, qx, gc.nz, gc.ny, gc.nx));
+  };
+  const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
+  const double2 u3p = u3_at(iz, iy, ix);
+  double2 sz = c2(0.0, 0.0), sy = c2(0.0, 0.0), sx = c2(0.0, 0.0);
+  if (ix > 0) sx = cadd(sx, u3_at(iz, iy, ix - 1));
+  if (ix < gf.nx - 1) sx = cadd(sx, u3_at(iz, iy, ix + 1));
+  if (iy > 0) sy = cadd(sy, u3_at(iz, iy - 1, ix));
+  if (iy < gf.ny - 1) sy = cadd(sy, u3_at(iz, iy + 1, ix));
+  if (iz > 0) sz = cadd(sz, u3_at(iz - 1, iy, ix));
+  if (iz < gf.nz - 1) sz = cadd(sz, u3_at(iz + 1, iy, ix));
+  const double2 res = csub(b[base + p], stencil3(c, ih2, u3p, sz, sy, sx));
+  u_out[base + p] = cadd(u3p, cmul(res, f.winv[lvl][p]));
+}
+
+// Dense M on the coarsest 3D grid for every frequency: A[f][i][j].
+__global__ void k_assemble_dense3(Grid g, int nfreq, const FreqTab* __restrict__ ft, double2* __restrict__ A) {
+  const size_t nc = (size_t)g.nz * g.ny * g.nx;
+  const size_t total = nc * nc * nfreq;
+  const double ih2 = 1.0 / (g.h * g.h);
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int f = (int)(e / (nc * nc));
+    const size_t rem = e - (size_t)f * nc * nc;
+    const int i = (int)(rem / nc), j = (int)(rem - (size_t)i * nc);
+    const int ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
+    const int jx = j % g.nx, jy = (j / g.nx) % g.ny, jz = j / (g.nx * g.ny);
+    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[i], ft[f].omega, ft[f].sM_re, ft[f].sM_im);
+    double2 val = c2(0.0, 0.0);
+    if (i == j) {
+      val = diag3(c, ih2);
+    } else if (jz == iz && jy == iy && (jx == ix - 1 || jx == ix + 1)) {
+      val = c2(-c.fx * ih2, 0.0);
+    } else if (jz == iz && jx == ix && (jy == iy - 1 || jy == iy + 1)) {
+      val = c2(-c.fy * ih2, 0.0);
+    } else if (jy == iy && jx == ix && (jz == iz - 1 || jz == iz + 1)) {
+      val = c2(-c.fz * ih2, 0.0);
+    }
+    A[e] = val;
+  }
+}
+
+__global__ void k_inject3(Grid gf, double* __restrict__ mc) {
+  const int ncx = (gf.nx + 1) / 2, ncy = (gf.ny + 1) / 2, ncz = (gf.nz + 1) / 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncx * ncy * ncz) return;
+  const int Ix = i % ncx, Iy = (i / ncx) % ncy, Iz = i / (ncx * ncy);
+  mc[i] = gf.m[((size_t)2 * Iz * gf.ny + 2 * Iy) * gf.nx + 2 * Ix];
+}
+
 // ---------------------------------------------------------------- launchers
 static inline dim3 grid1(long long blocks) { return dim3((unsigned)blocks); }
 
+// the row tiling of a 3D grid
+static inline Tiles tiles3(const Grid& g) { return grid_tiles(g.nz * g.ny, g.nx, 3); }
+
 hipError_t launch_apply(int dim, const Grid& g, int lvl, int which, const Batch& bt, int cap,
                         const double2* x, double2* y, size_t stride, hipStream_t st) {
-  const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
+  if (dim == 3) {
+    const Tiles t = tiles3(g);
+    hipLaunchKernelGGL(k_apply3, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, g, t, which, bt, x, y, stride);
+    return hipGetLastError();
+  }
+  const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (dim == 2)
     hipLaunchKernelGGL(k_apply<true>, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, g, t, lvl, which, bt, x, y, stride);
   else
@@ -728,8 +908,17 @@ hipError_t launch_apply(int dim, const Grid& g, int lvl, int which, const Batch&
 hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, const Batch& bt,
                          int cap, const double2* b, const double2* u_in, double2* u_out,
                          size_t stride, hipStream_t st) {
-  const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
+  if (dim == 3) {
+    const Tiles t = tiles3(g);
+    const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
+    if (u_in)
+      hipLaunchKernelGGL(k_smooth3<false>, gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride, 0);
+    else
+      hipLaunchKernelGGL(k_smooth3<true>, gr, dim3(kBlock), 0, st, g, t, lvl, w_override, bt, b, u_in, u_out, stride, 0);
+    return hipGetLastError();
+  }
+  const Tiles t = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
   if (dim == 2 && u_in && w_override <= 0.0) {
     const int ntx = (g.nx + kTX - 1) / kTX, ntz = (g.nz + kTZ - 1) / kTZ;
@@ -754,8 +943,14 @@ hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, con
 hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                            const double2* b, const double2* u, double2* bc, size_t sf, size_t sc,
                            hipStream_t st) {
-  const Tiles t = grid_tiles(gc.nz, gc.nx, dim);
   if (cap <= 0) return hipSuccess;
+  if (dim == 3) {
+    const Tiles t = tiles3(gc);
+    hipLaunchKernelGGL(k_restrict3, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, gf, gc, t, bt, b, u,
+                       bc, sf, sc);
+    return hipGetLastError();
+  }
+  const Tiles t = grid_tiles(gc.nz, gc.nx, dim);
   if (dim == 2) {
     const int ntx = (gc.nx + kRtx - 1) / kRtx, ntz = (gc.nz + kRtz - 1) / kRtz;
     hipLaunchKernelGGL(k_restrict_tiled, grid1(tile_blocks(ntx * ntz, cap)), dim3(kRtx * kRtz), 0, st, gf, gc,
@@ -770,8 +965,14 @@ hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch&
 hipError_t launch_prolong(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                           const double2* e, const double2* u_in, double2* u_out, size_t sf,
                           size_t sc, hipStream_t st) {
-  const Tiles t = grid_tiles(gf.nz, gf.nx, dim);
   if (cap <= 0) return hipSuccess;
+  if (dim == 3) {
+    const Tiles t = tiles3(gf);
+    hipLaunchKernelGGL(k_prolong3, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, gf, gc, t, bt, e, u_in,
+                       u_out, sf, sc);
+    return hipGetLastError();
+  }
+  const Tiles t = grid_tiles(gf.nz, gf.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
   if (dim == 2)
     hipLaunchKernelGGL(k_prolong<true>, gr, dim3(kBlock), 0, st, gf, gc, t, bt, e, u_in, u_out, sf, sc);
@@ -800,8 +1001,14 @@ hipError_t launch_pre2(int dim, const Grid& g, int lvl, int mode, const Batch& b
 hipError_t launch_prolong_smooth(int dim, const Grid& gf, const Grid& gc, int lvl, const Batch& bt,
                                  int cap, const double2* e, const double2* b, const double2* u2,
                                  double2* u_out, size_t sf, size_t sc, hipStream_t st) {
-  const Tiles t = grid_tiles(gf.nz, gf.nx, dim);
   if (cap <= 0) return hipSuccess;
+  if (dim == 3) {
+    const Tiles t = tiles3(gf);
+    hipLaunchKernelGGL(k_prolong_smooth3, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, gf, gc, t, lvl,
+                       bt, e, b, u2, u_out, sf, sc);
+    return hipGetLastError();
+  }
+  const Tiles t = grid_tiles(gf.nz, gf.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
   if (dim == 2) {
     const int ntx = (gf.nx + kTX - 1) / kTX, ntz = (gf.nz + kTZ - 1) / kTZ;
@@ -815,17 +1022,21 @@ hipError_t launch_prolong_smooth(int dim, const Grid& gf, const Grid& gc, int lv
 hipError_t launch_coarse_jacobi(int dim, const Grid& g, int lvl, double w, int sweeps, const Batch& bt, int cap,
                                 const double2* b, double2* tmp, double2* u_out, size_t stride, hipStream_t st) {
   if (cap <= 0 || sweeps < 1) return hipSuccess;
-  const Tiles t = grid_tiles(g.nz, g.nx, dim);
+  const Tiles t = dim == 3 ? tiles3(g) : grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
   // ping-pong so that the last sweep lands in u_out
   double2* cur = (sweeps % 2 == 1) ? u_out : tmp;
-  if (dim == 2)
+  if (dim == 3)
+    hipLaunchKernelGGL(k_smooth3<true>, gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, nullptr, cur, stride, 1);
+  else if (dim == 2)
     hipLaunchKernelGGL((k_smooth<true, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, nullptr, cur, stride, 1);
   else
     hipLaunchKernelGGL((k_smooth<false, true>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, nullptr, cur, stride, 1);
   for (int k = 1; k < sweeps; ++k) {
     double2* nxt = (cur == u_out) ? tmp : u_out;
-    if (dim == 2)
+    if (dim == 3)
+      hipLaunchKernelGGL(k_smooth3<false>, gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, cur, nxt, stride, 1);
+    else if (dim == 2)
       hipLaunchKernelGGL((k_smooth<true, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, cur, nxt, stride, 1);
     else
       hipLaunchKernelGGL((k_smooth<false, false>), gr, dim3(kBlock), 0, st, g, t, lvl, w, bt, b, cur, nxt, stride, 1);
@@ -860,9 +1071,11 @@ static inline unsigned flat_blocks(size_t total) {
 
 hipError_t launch_winv(int dim, const Grid& g, double omega, double s_re, double s_im, double w,
                        double2* winv, hipStream_t st) {
-  const size_t n = (size_t)g.nz * g.nx;
+  const size_t n = (size_t)g.nz * g.ny * g.nx;
   const unsigned nb = (unsigned)((n + 255) / 256);
-  if (dim == 2)
+  if (dim == 3)
+    hipLaunchKernelGGL(k_winv3, dim3(nb), dim3(256), 0, st, g, omega, s_re, s_im, w, winv);
+  else if (dim == 2)
     hipLaunchKernelGGL(k_winv<true>, dim3(nb), dim3(256), 0, st, g, omega, s_re, s_im, w, winv);
   else
     hipLaunchKernelGGL(k_winv<false>, dim3(nb), dim3(256), 0, st, g, omega, s_re, s_im, w, winv);
@@ -871,9 +1084,11 @@ hipError_t launch_winv(int dim, const Grid& g, double omega, double s_re, double
 
 hipError_t launch_assemble_dense(int dim, const Grid& g, int nfreq, const FreqTab* ft, double2* A,
                                  hipStream_t st) {
-  const size_t nc = (size_t)g.nz * g.nx;
+  const size_t nc = (size_t)g.nz * g.ny * g.nx;
   const unsigned nb = flat_blocks(nc * nc * nfreq);
-  if (dim == 2)
+  if (dim == 3)
+    hipLaunchKernelGGL(k_assemble_dense3, dim3(nb), dim3(256), 0, st, g, nfreq, ft, A);
+  else if (dim == 2)
     hipLaunchKernelGGL(k_assemble_dense<true>, dim3(nb), dim3(256), 0, st, g, nfreq, ft, A);
   else
     hipLaunchKernelGGL(k_assemble_dense<false>, dim3(nb), dim3(256), 0, st, g, nfreq, ft, A);
@@ -909,6 +1124,11 @@ hipError_t launch_misfit(size_t nd, const double2* d_obs, const double2* d_cal, 
 }
 
 hipError_t launch_inject(const Grid& gf, int dim, double* mc, hipStream_t st) {
+  if (dim == 3) {
+    const int tot = ((gf.nx + 1) / 2) * ((gf.ny + 1) / 2) * ((gf.nz + 1) / 2);
+    hipLaunchKernelGGL(k_inject3, dim3((tot + 255) / 256), dim3(256), 0, st, gf, mc);
+    return hipGetLastError();
+  }
   const int ncx = (gf.nx + 1) / 2;
   const int ncz = dim == 2 ? (gf.nz + 1) / 2 : 1;
   const int tot = ncx * ncz;

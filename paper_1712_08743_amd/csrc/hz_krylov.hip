@@ -6,6 +6,7 @@
 // a fixed order (see store_partial / sum_partials).
 
 #include "hz_device.h"
+#include "hz_node3.h"
 
 namespace hz {
 
@@ -149,6 +150,42 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
       acc[0] += d.x;
       acc[1] += d.y;
       acc[2] += yp.x * yp.x + yp.y * yp.y;
+    }
+  }
+  store_partial<3>(acc, rd, slot, tile);
+}
+
+// 3D grids (hz_node3.h), one node per thread over the row tiling: v = B ph
+// with the partial <rh, v> (dense r^ only), t = B sh with <t, s> and <t, t>.
+// Every tile stores its partials, zero past the grid.
+template <int WHICH>
+__global__ void __launch_bounds__(kBlock) k_bicg_apply3(Grid g, Tiles t, Batch bt, Reduce rd,
+                                                        const double2* __restrict__ xin,
+                                                        const double2* __restrict__ other,
+                                                        double2* __restrict__ y, size_t stride) {
+  int slot, tile;
+  if (!decode_tile(bt, t.per_slot, slot, tile)) return;
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const size_t base = (size_t)slot * stride;
+  const bool dots = WHICH == 1 || bt.slots[slot].rh_nnz < 0;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int iz, iy, ix;
+  size_t p;
+  if (node3_of(t, tile, g, iz, iy, ix, p)) {
+    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const double2 yp = apply_node3(xin + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
+    y[base + p] = yp;
+    if (WHICH == 0) {
+      if (dots) {
+        const double2 d = cconjmul(other[base + p], yp);
+        acc[0] = d.x;
+        acc[1] = d.y;
+      }
+    } else {
+      const double2 d = cconjmul(yp, other[base + p]);
+      acc[0] = d.x;
+      acc[1] = d.y;
+      acc[2] = yp.x * yp.x + yp.y * yp.y;
     }
   }
   store_partial<3>(acc, rd, slot, tile);
@@ -622,6 +659,32 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(Grid g, Tiles t, Batch
   store_partial<2>(acc, rd, slot, tile);
 }
 
+// ||b - B x||^2 and ||b||^2 on a 3D grid (as k_true_residual)
+__global__ void __launch_bounds__(kBlock) k_true_residual3(Grid g, Tiles t, Batch bt, Reduce rd,
+                                                           const double2* __restrict__ b,
+                                                           const double2* __restrict__ x, size_t stride) {
+  const int xcd = blockIdx.x % kXcd, k = blockIdx.x / kXcd;
+  const int chunk = xcd_chunk(t.per_slot);
+  const int si = k / chunk;
+  const int tile = xcd * chunk + (k - si * chunk);
+  if (tile >= t.per_slot || si >= *bt.nactive) return;
+  const int slot = bt.active[si];
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const size_t base = (size_t)slot * stride;
+  double acc[2] = {0.0, 0.0};
+  int iz, iy, ix;
+  size_t p;
+  if (node3_of(t, tile, g, iz, iy, ix, p)) {
+    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const double2 y = apply_node3(x + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
+    const double2 bp = b[base + p];
+    const double2 rr = csub(bp, y);
+    acc[0] = rr.x * rr.x + rr.y * rr.y;
+    acc[1] = bp.x * bp.x + bp.y * bp.y;
+  }
+  store_partial<2>(acc, rd, slot, tile);
+}
+
 __global__ void __launch_bounds__(kBlock) k_true_residual_fin(int tiles, Batch bt, Reduce rd,
                                                               double* __restrict__ out) {
   const int si = blockIdx.x;
@@ -951,9 +1014,15 @@ hipError_t launch_bicg_p(size_t n, const Batch& bt, int cap, const double2* r, c
 hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int cap,
                                    const Reduce& rd, const double2* ph, const double2* rh,
                                    double2* v, size_t stride, hipStream_t st) {
-  const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
   if (!v && dim != 2) return hipErrorInvalidValue;
+  if (dim == 3) {
+    const Tiles t3 = grid_tiles(g.nz * g.ny, g.nx, 3);
+    hipLaunchKernelGGL(k_bicg_apply3<0>, grid1(tile_blocks(t3.per_slot, cap)), dim3(kBlock), 0, st, g, t3, bt, rd,
+                       ph, rh, v, stride);
+    return hipGetLastError();
+  }
+  const Tiles t = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
   if (dim == 2) {
     const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
@@ -975,8 +1044,14 @@ hipError_t launch_bicg_s(size_t n, const Batch& bt, int cap, const double2* r, c
 hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int cap,
                                    const Reduce& rd, const double2* sh, const double2* s,
                                    double2* t, size_t stride, hipStream_t st) {
-  const Tiles tl = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
+  if (dim == 3) {
+    const Tiles t3 = grid_tiles(g.nz * g.ny, g.nx, 3);
+    hipLaunchKernelGGL(k_bicg_apply3<1>, grid1(tile_blocks(t3.per_slot, cap)), dim3(kBlock), 0, st, g, t3, bt, rd,
+                       sh, s, t, stride);
+    return hipGetLastError();
+  }
+  const Tiles tl = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(tl.per_slot, cap));
   if (dim == 2) {
     const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
@@ -1052,10 +1127,12 @@ hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* act
 hipError_t launch_true_residual(int dim, const Grid& g, const Batch& bt, int cap, const Reduce& rd,
                                 const double2* b, const double2* x, double* out, size_t stride,
                                 hipStream_t st) {
-  const Tiles t = grid_tiles(g.nz, g.nx, dim);
+  const Tiles t = dim == 3 ? grid_tiles(g.nz * g.ny, g.nx, 3) : grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
-  if (dim == 2)
+  if (dim == 3)
+    hipLaunchKernelGGL(k_true_residual3, gr, dim3(kBlock), 0, st, g, t, bt, rd, b, x, stride);
+  else if (dim == 2)
     hipLaunchKernelGGL(k_true_residual<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, b, x, stride);
   else
     hipLaunchKernelGGL(k_true_residual<false>, gr, dim3(kBlock), 0, st, g, t, bt, rd, b, x, stride);

@@ -21,6 +21,10 @@ stand in for them:
                          elliptical low-velocity lens; starting model = the
                          true slowness smoothed with a 400 m Gaussian; 32
                          surface shots, 151 surface receivers, 3-12 Hz;
+* ``model_3d_layered``   3D (nz, ny, nx) box, h = 20 m, horizontal layers
+                         1500-4500 m/s with a smooth seeded random
+                         perturbation (5 % rms, 200 m correlation), shots on
+                         the surface plane (Eq. (1) with d = 3);
 * ``serving_request``    one request of a serving stream: square grid of
                          side 129, 257 or 513 (h = 10 m), layered model with
                          a Gaussian anomaly, one frequency from U(2, 15) Hz,
@@ -89,6 +93,28 @@ def model_2d_layered(nz=401, nx=801, h=10.0, seed=0, nshots=64,
         ix = np.round(np.linspace(0.03 * (nx - 1), 0.97 * (nx - 1), nshots)).astype(int)
     src = [int(i) for i in ix]  # surface row iz = 0: flat index = ix
     return Workload(name=f"2d-layered-{nz}x{nx}", m=1 / c, c=c, h=h, shape=(nz, nx),
+                    freqs=list(freqs), alpha=0.01, src=src, beta=(1.0, 0.5), tol=1e-8)
+
+
+def model_3d_layered(nz=65, ny=65, nx=65, h=20.0, seed=0, nshots=8, freqs=(2.0, 4.0), nlayers=6):
+    """Horizontal layers 1500-4500 m/s (nlayers of equal thickness in z)
+    times (1 + p), p a Gaussian-filtered white-noise field (covariance length
+    200 m), scaled to 5 % rms and clipped to +-15 %. Shots on the surface
+    plane iz = 0 at (iy, ix) spread over the central 60 % of each axis."""
+    layer_v = np.linspace(1500.0, 4500.0, nlayers)
+    iz = np.arange(nz)
+    lz = np.minimum(iz * nlayers // nz, nlayers - 1)
+    c = np.broadcast_to(layer_v[lz][:, None, None], (nz, ny, nx)).copy()
+    rng = np.random.default_rng(seed)
+    p = gaussian_filter(rng.standard_normal((nz, ny, nx)), sigma=200.0 / (h * np.sqrt(2.0)))
+    p *= 0.05 / np.sqrt(np.mean(p ** 2))
+    p = np.clip(p, -0.15, 0.15)
+    c = c * (1.0 + p)
+    k = int(np.ceil(np.sqrt(nshots)))
+    ys = np.round(np.linspace(0.2 * (ny - 1), 0.8 * (ny - 1), k)).astype(int)
+    xs = np.round(np.linspace(0.2 * (nx - 1), 0.8 * (nx - 1), k)).astype(int)
+    src = [(0, int(ys[i // k]), int(xs[i % k])) for i in range(nshots)]
+    return Workload(name=f"3d-layered-{nz}x{ny}x{nx}", m=1 / c, c=c, h=h, shape=(nz, ny, nx),
                     freqs=list(freqs), alpha=0.01, src=src, beta=(1.0, 0.5), tol=1e-8)
 
 
