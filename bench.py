@@ -17,6 +17,7 @@ Prints one JSON line (see the field list at the end of main()).
                                          # for scaling rocprofv3 byte counters
   python bench.py --compare       # preconditioned vs not, shifts, GMRES vs BiCGSTAB,
                                   # Gauss-Newton schedules (a report, not a throughput line)
+  python bench.py --3d            # batched solves on a 3D box (129^3, 16 right-hand sides; a report line)
   python bench.py --fwi           # gradient and Gauss-Newton step on the full inversion survey
                                   # (301 x 601, 32 shots x 6 frequencies; a report line)
   python bench.py --serving [--requests R] [--slots S]
@@ -385,6 +386,136 @@ def fwi_report(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_3d(args):
+    """Batched solves on a 3D box (Eq. (1) with d = 3, constant density): the
+    layered 129 x 129 x 129 model (h = 20 m), 8 surface shots x 3 and 5 Hz =
+    16 right-hand sides, BiCGSTAB to 1e-8 with the planned V(2,2)
+    shifted-Laplace (1, 0.5) preconditioner. A step = set the model + solve
+    the 16 right-hand sides, inputs resident in HBM. Kernel classes are timed
+    with HIP events; the dominant one gives the roofline line. The CPU
+    oracle is timed on a bounded sample (set-up plus a few BiCGSTAB
+    iterations of one shot per frequency) and scaled to the batch with the
+    GPU's iteration counts (which the parity tests hold within 5 % of the
+    oracle's). One JSON line, a report beside the 2D throughput line."""
+    import torch
+    import numpy as np
+    import paper_1712_08743_amd as hz
+    import workloads
+    w = workloads.model_3d_layered(129, 129, 129, h=20.0, nshots=8, freqs=(3.0, 5.0))
+    tol = 1e-8
+    ctx = hz.Context(0)
+    m = torch.from_numpy(w.m).cuda()
+    ctx.set_model(m, w.h)
+    iz, iy, ix = ([s[a] for s in w.src] for a in range(3))
+    b1 = ctx.point_rhs_3d(iz, iy, ix)
+    b = torch.stack([b1] * len(w.freqs)).contiguous()
+    u = torch.empty_like(b)
+    nrhs = b.shape[0] * b.shape[1]
+
+    def step():
+        ctx.set_model(m, w.h)
+        _, info = ctx.solve(w.freqs, w.alpha, b, out=u, tol=tol)
+        return info
+
+    print(f"# 3d: warm-up step on {w.name}, {nrhs} right-hand sides", file=sys.stderr, flush=True)
+    step()
+    torch.cuda.synchronize()
+    classes = ["smooth", "restrict", "prolong", "apply", "apply_s", "update", "coarse"]
+    ctx.timing_start(classes)
+    steps = max(1, min(args.steps, 3))
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    timing = {k: ctx.timing_read(k) for k in classes}
+    ctx.timing_start([])
+    print(f"# 3d: {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    info = infos[-1]
+    iters = [i[1] for i in info]
+    slot_iters = sum(sum(i[1] for i in inf) for inf in infos)
+    n0 = int(np.prod(w.shape))
+    n1 = int(np.prod(ctx.level_shape(1)))
+    z = 16
+    # algorithmic bytes per right-hand side and iteration of the finest-level classes (two V-cycles;
+    # the first pre-sweep, from zero, and the p and s updates are not timed)
+    cb = {"smooth": 2 * 2 * 3 * n0 * z,              # the second pre-sweep and the last post-sweep: b, u / u
+          "restrict": 2 * (2 * n0 * z + n1 * z),     # b, u / coarse b
+          "prolong": 2 * (3 * n0 * z + n1 * z),      # coarse e, b, u / u (with one post-sweep)
+          "apply": 2 * n0 * z,                       # p^ / v
+          "apply_s": 3 * n0 * z,                     # s^, s / t
+          "update": 6 * n0 * z}                      # s, t / r; x every second iteration
+    breakdown = {}
+    for k in classes:
+        n, ms = timing[k]
+        e = {"launches": n, "ms": ms / steps}
+        if k in cb and ms > 0:
+            e["GB/s"] = slot_iters * cb[k] / (ms * 1e-3) / 1e9
+        breakdown[k] = e
+    dom = max((k for k in cb if timing[k][0] > 0), key=lambda k: timing[k][1])
+    achieved = slot_iters * cb[dom] / (timing[dom][1] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "launches": timing[dom][0], "avg_launch_ms": timing[dom][1] / max(timing[dom][0], 1)}
+    levels = [ctx.plan(f)[0] for f in w.freqs]
+    ctx.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# 3d: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_3d(w, iters, len(w.src))
+    out = {
+        "metric": "Helmholtz solves/s (3D 129^3, 16 RHS)",
+        "value": nrhs / sec, "unit": "solves/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"{w.name}, h {w.h} m, 8 surface shots x {w.freqs} Hz = 16 RHS, BiCGSTAB tol 1e-8, "
+                               "V(2,2) shifted-Laplace (1,0.5), LFA-planned weights",
+                   "grid": list(w.shape), "levels": levels},
+        "converged": sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED and i[2] <= tol),
+        "iterations_mean_per_freq": {str(f): float(np.mean(iters[k * len(w.src):(k + 1) * len(w.src)]))
+                                     for k, f in enumerate(w.freqs)},
+        "kernel_breakdown": breakdown,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_3d(w, iters, nshot, sample_iters=3):
+    """The oracle on one shot per frequency: its V-cycle set-up plus
+    sample_iters BiCGSTAB iterations, scaled to the batch (nshot shots per
+    frequency, the GPU's iteration counts)."""
+    import numpy as np
+    from oracle import operator as op
+    from oracle import multigrid as mg
+    from oracle import krylov
+    from oracle import lfa
+    total = 0.0
+    per_freq = {}
+    t_all = time.perf_counter()
+    for k, f in enumerate(w.freqs):
+        om = 2 * np.pi * f
+        t0 = time.perf_counter()
+        B = op.operator_B(w.m, w.h, om, w.alpha)
+        L, wj = lfa.plan(w.shape, w.h, om, float(w.m.min()), float(w.m.max()), 1.0, 0.5)
+        vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
+        t_setup = time.perf_counter() - t0
+        iz, iy, ix = w.src[0]
+        bn = op.point_source(w.shape, w.h, [(iz * w.shape[1] + iy) * w.shape[2] + ix])
+        t0 = time.perf_counter()
+        krylov.bicgstab(B, bn, vc, tol=1e-30, maxit=sample_iters)
+        t_it = (time.perf_counter() - t0) / sample_iters
+        n_it = float(np.mean(iters[k * nshot:(k + 1) * nshot]))
+        total += t_setup + nshot * n_it * t_it
+        per_freq[str(f)] = {"setup_s": t_setup, "s_per_iteration": t_it, "iterations": n_it}
+    sample_s = time.perf_counter() - t_all
+    return {"value": nshot * len(w.freqs) / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one shot per frequency: the oracle's V-cycle set-up plus {sample_iters} BiCGSTAB "
+                      f"iterations ({sample_s:.1f} s of CPU), scaled to {nshot} shots x the GPU's mean "
+                      "iterations per frequency",
+            "host_cpus": os.cpu_count(), "per_freq": per_freq}
+
+
 def one_rhs_per_launch(ctx, w, b1, tol, shot=31):
     """The plain path: one right-hand side per solve call (shot ``shot`` at
     every frequency of the workload); solves/s averaged over the frequencies,
@@ -415,6 +546,7 @@ def main():
     ap.add_argument("--no-single-rhs", action="store_true")
     ap.add_argument("--compare", action="store_true")
     ap.add_argument("--fwi", action="store_true")
+    ap.add_argument("--3d", dest="three_d", action="store_true")
     ap.add_argument("--compare-maxit", type=int, default=20000)
     ap.add_argument("--maxit", type=int, default=10000,
                     help="iteration cap (below convergence only for short hardware-counter runs)")
@@ -434,6 +566,9 @@ def main():
         return
     if args.fwi:
         fwi_report(args)
+        return
+    if args.three_d:
+        bench_3d(args)
         return
 
     import numpy as np

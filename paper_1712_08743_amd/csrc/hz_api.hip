@@ -661,8 +661,11 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       }
     }
     cur[l] = u;
+    // the level's other smoothing buffer holds the residual where the restriction stores it first
+    double2* spare = (u == X) ? Y : X;
     if ((e = timed(c, l == 0 ? HZ_KERNEL_RESTRICT : HZ_KERNEL_LEVELS, [&] {
-           return launch_restrict(dim, g, grid_of(c, l + 1), bt, cap, bl, u, bc, nl, c->lv[l + 1].n(), st);
+           return launch_restrict_via(dim, g, grid_of(c, l + 1), bt, cap, bl, u, spare, bc, nl, c->lv[l + 1].n(),
+                                      st);
          })) != hipSuccess)
       return e;
     bl = bc;
@@ -710,6 +713,13 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
              return tuned_launch(c, cy, 3, g, cap, [&](int ch) {
                return launch_post2(g, gc, l, bt, cap, ec, bll, dst, nl, c->lv[l + 1].n(), ch, st);
              });
+           if (dim == 3) {
+             // 3D: u += P e in place (the pre-smoothed iterate is not needed after), then a plain
+             // sweep; the fused form interpolates at all seven stencil nodes of every node
+             hipError_t e3 = launch_prolong(dim, g, gc, bt, cap, ec, u, u, nl, c->lv[l + 1].n(), st);
+             if (e3 == hipSuccess) e3 = launch_smooth(dim, g, l, 0.0, bt, cap, bll, u, dst, nl, st);
+             return e3;
+           }
            return launch_prolong_smooth(dim, g, gc, l, bt, cap, ec, bll, u, dst, nl, c->lv[l + 1].n(), st);
          })) != hipSuccess)
       return e;

@@ -136,6 +136,11 @@ hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, con
 hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                            const double2* b, const double2* u, double2* bc, size_t sf,
                            size_t sc, hipStream_t st);
+// The same restriction with the fine residual b - M u first stored in
+// scratch (a fine-level vector, 3D grids; other dimensions ignore it).
+hipError_t launch_restrict_via(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
+                               const double2* b, const double2* u, double2* scratch, double2* bc, size_t sf,
+                               size_t sc, hipStream_t st);
 hipError_t launch_prolong(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                           const double2* e, const double2* u_in, double2* u_out, size_t sf,
                           size_t sc, hipStream_t st);

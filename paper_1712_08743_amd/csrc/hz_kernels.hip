@@ -807,6 +807,46 @@ __global__ void __launch_bounds__(kBlock) k_restrict3(Grid gf, Grid gc, Tiles t,
   bc[(size_t)slot * sc + P] = cscale(0.125, acc);
 }
 
+// r = b - M u on a 3D level, for the restriction below
+__global__ void __launch_bounds__(kBlock) k_residual3(Grid g, Tiles t, Batch bt, const double2* __restrict__ b,
+                                                      const double2* __restrict__ u, double2* __restrict__ r,
+                                                      size_t stride) {
+  int slot, tile, iz, iy, ix;
+  size_t p;
+  if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, g, iz, iy, ix, p)) return;
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const size_t base = (size_t)slot * stride;
+  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
+  r[base + p] = csub(b[base + p], apply_node3(u + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c));
+}
+
+// bc = 2^-3 P^T r from a stored fine residual (the weights of k_restrict3)
+__global__ void __launch_bounds__(kBlock) k_restrict_r3(Grid gf, Grid gc, Tiles t, Batch bt,
+                                                        const double2* __restrict__ r, double2* __restrict__ bc,
+                                                        size_t sf, size_t sc) {
+  int slot, tile, Iz, Iy, Ix;
+  size_t P;
+  if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, gc, Iz, Iy, Ix, P)) return;
+  const double2* rs = r + (size_t)slot * sf;
+  double2 acc = c2(0.0, 0.0);
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int iz = 2 * Iz + dz;
+    if (iz < 0 || iz >= gf.nz) continue;
+    const double wz = pt_weight(dz, Iz, gf.nz);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int iy = 2 * Iy + dy;
+      if (iy < 0 || iy >= gf.ny) continue;
+      const double wzy = wz * pt_weight(dy, Iy, gf.ny);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ix = 2 * Ix + dx;
+        if (ix < 0 || ix >= gf.nx) continue;
+        acc = cadd(acc, cscale(wzy * pt_weight(dx, Ix, gf.nx), rs[((size_t)iz * gf.ny + iy) * gf.nx + ix]));
+      }
+    }
+  }
+  bc[(size_t)slot * sc + P] = cscale(0.125, acc);
+}
+
 // u_out = u_in + P e (u_out may be u_in)
 __global__ void __launch_bounds__(kBlock) k_prolong3(Grid gf, Grid gc, Tiles t, Batch bt,
                                                      const double2* __restrict__ e, const double2* u_in,
@@ -959,6 +999,19 @@ hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch&
     hipLaunchKernelGGL(k_restrict<false>, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, gf, gc, t, bt,
                        b, u, bc, sf, sc);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_via(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
+                               const double2* b, const double2* u, double2* scratch, double2* bc, size_t sf,
+                               size_t sc, hipStream_t st) {
+  if (dim != 3) return launch_restrict(dim, gf, gc, bt, cap, b, u, bc, sf, sc, st);
+  if (cap <= 0) return hipSuccess;
+  const Tiles tf = tiles3(gf), tc = tiles3(gc);
+  hipLaunchKernelGGL(k_residual3, grid1(tile_blocks(tf.per_slot, cap)), dim3(kBlock), 0, st, gf, tf, bt, b, u,
+                     scratch, sf);
+  hipLaunchKernelGGL(k_restrict_r3, grid1(tile_blocks(tc.per_slot, cap)), dim3(kBlock), 0, st, gf, gc, tc, bt,
+                     scratch, bc, sf, sc);
   return hipGetLastError();
 }
 
