@@ -200,3 +200,32 @@ def test_3d_refusals(hz):
     with pytest.raises(hz.HzError) as e:
         c2.point_rhs_3d([0], [1], [1])
     assert e.value.code == hz.HZ_ERR_ARG
+
+
+def test_3d_vcycle_with_smoothed_coarsest_level(hz):
+    """The coarsest level smoothed by damped-Jacobi sweeps instead of solved
+    (the form taken where its smallest kh is large), against the oracle."""
+    import torch
+    shape, h, levels, f = (17, 17, 17), 60.0, 3, 12.0
+    m = random_model(shape, 21)
+    c = ctx_for(hz, m, h)
+    wj = [0.6, 0.4]
+    vc = mg.VCycle(m, h, 2 * np.pi * f, 1.0, 0.5, levels, 2, 2, wj, coarse="jacobi", coarse_sweeps=3)
+    b = workloads.random_vectors(2, int(np.prod(shape)), seed=23)
+    out = to_np(c.precond(f, torch.from_numpy(b.reshape((2,) + shape)).cuda(), levels=levels, nu=(2, 2),
+                          jacobi_w_level=wj, coarse="jacobi", coarse_sweeps=3)).reshape(2, -1)
+    for k in range(2):
+        assert rel(out[k], vc(b[k])) < TOL_CYCLE
+
+
+def test_3d_unpreconditioned_solve(hz):
+    """No preconditioner on a small, damped 3D box: converges to the LU solution."""
+    w = workloads.model_3d_layered(9, 11, 13, h=40.0, nshots=1, freqs=(2.0,))
+    c = ctx_for(hz, w.m, w.h)
+    (iz, iy, ix), = w.src
+    b = c.point_rhs_3d([iz], [iy], [ix])
+    u, info = c.solve([2.0], 0.2, b[None].contiguous(), precond="none", tol=1e-10, maxit=5000)
+    assert info[0][0] == hz.HZ_RHS_CONVERGED
+    B = op.operator_B(w.m, w.h, 2 * np.pi * 2.0, 0.2)
+    bn = op.point_source(w.shape, w.h, [(iz * w.shape[1] + iy) * w.shape[2] + ix])
+    assert rel(to_np(u)[0, 0].ravel(), direct.solve_superlu(B, bn)) < 1e-8
