@@ -287,4 +287,31 @@ __device__ __forceinline__ void halo_sums(const double2 (*S)[kHX], int lz, int l
   sz = cadd(S[lz][lx + 1], S[lz + 2][lx + 1]);
 }
 
+// ---- lane exchange of the wavefront-marching kernels (lane = grid column)
+
+// Neighbouring lanes' values by whole-wavefront DPP shifts (wave_shr:1,
+// wave_shl:1 on the two 32-bit halves): VALU moves with a few cycles of
+// latency, where a general shuffle goes through the LDS crossbar. The lane
+// with no neighbour (0 from the left, 63 from the right) receives 0 (the
+// bound control of the move).
+constexpr int kDppWaveShr1 = 0x138;  // lane i takes lane i - 1
+constexpr int kDppWaveShl1 = 0x130;  // lane i takes lane i + 1
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 from_left(double2 v) {  // value of lane - 1
+  return make_double2(dpp_shift<kDppWaveShr1>(v.x), dpp_shift<kDppWaveShr1>(v.y));
+}
+__device__ __forceinline__ double2 from_right(double2 v) {  // value of lane + 1
+  return make_double2(dpp_shift<kDppWaveShl1>(v.x), dpp_shift<kDppWaveShl1>(v.y));
+}
+// v where c holds, else zero (selected per component, so no stack copy is made)
+__device__ __forceinline__ double2 keep(bool c, double2 v) {
+  return make_double2(c ? v.x : 0.0, c ? v.y : 0.0);
+}
+
 }  // namespace hz

@@ -756,6 +756,84 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
   u_out[base + p] = out;
 }
 
+// One damped-Jacobi sweep on a 3D level from a given iterate with the
+// level's tabulated w/D, marching along z: a wavefront owns kMarchW columns of
+// one y-row (lane = column, from xs - 1; lanes 1 .. kMarchW store) and
+// kMarchZ z-planes. z-neighbours stay in registers, x-neighbours come from
+// the adjacent lanes, y-neighbours are the rows of the block's other
+// wavefronts (tile order puts neighbouring rows in one block), read from
+// cache. Written in the Jacobi form (1 - w) u + (w/D)(b + (fz sz + fy sy +
+// fx sx) / h^2), so the slowness is not read.
+constexpr int kMarchW = 62;
+constexpr int kMarchZ = 16;  // even: the march takes two planes per step
+
+__global__ void __launch_bounds__(kBlock) k_smooth3m(Grid g, int nstrip, int nchunk, int groups, int lvl, Batch bt,
+                                                     const double2* __restrict__ b,
+                                                     const double2* __restrict__ u_in,
+                                                     double2* __restrict__ u_out, size_t stride) {
+  int slot, grp;
+  if (!decode_tile(bt, groups, slot, grp)) return;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+  const int tile = grp * (kBlock / 64) + wv;
+  if (tile >= g.ny * nstrip * nchunk) return;
+  const int iy = tile % g.ny;  // y fastest: a block's wavefronts are neighbouring rows
+  const int rest = tile / g.ny;
+  const int strip = rest % nstrip, chunk = rest / nstrip;
+  const int lane = threadIdx.x % 64;
+  const int x = strip * kMarchW - 1 + lane;
+  const bool xin = x >= 0 && x < g.nx;
+  const int xx = min(max(x, 0), g.nx - 1);
+  const bool own = lane >= 1 && lane <= kMarchW && xin;
+  const int z0 = chunk * kMarchZ, z1 = min(g.nz, z0 + kMarchZ);
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const double2* wd = f.winv[lvl];
+  const double omw = 1.0 - f.wj[lvl];
+  const double ih2 = 1.0 / (g.h * g.h);
+  const size_t base = (size_t)slot * stride;
+  const double2* us = u_in + base;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const double wy = (iy == 0 || iy == g.ny - 1) ? 0.5 : 1.0, wx = (x == 0 || x == g.nx - 1) ? 0.5 : 1.0;
+  const double2 zero = c2(0.0, 0.0);
+  // node (z, iy, xx); z inside the grid
+  auto at = [&](int z) { return (size_t)z * sz + (size_t)iy * sy + xx; };
+  // u on plane z of the wavefront's row, zero outside the grid
+  auto plane = [&](int z) { return (z >= 0 && z < g.nz) ? keep(xin, us[at(z)]) : zero; };
+  struct Row {  // loads for output plane z: u on z + 1, the y-neighbours on z, b, w/D
+    double2 uc, ul, ur, bz, wdz;
+  };
+  auto load = [&](int z) {
+    Row r;
+    r.uc = plane(z + 1);
+    const int zc = min(z, g.nz - 1);  // the second plane of a step may be past the grid (not stored)
+    const size_t q = at(zc);
+    r.ul = iy > 0 ? us[q - sy] : zero;
+    r.ur = iy < g.ny - 1 ? us[q + sy] : zero;
+    r.bz = b[base + q];
+    r.wdz = wd[q];
+    return r;
+  };
+  auto step = [&](int z, const Row& r, double2 ua, double2 ub) {
+    const double wz = (z == 0 || z == g.nz - 1) ? 0.5 : 1.0;
+    const double fz = wy * wx, fy = wz * wx, fx = wz * wy;
+    const double2 sxv = cadd(from_left(ub), from_right(ub));
+    const double2 syv = cadd(r.ul, r.ur);
+    const double2 szv = cadd(ua, r.uc);
+    const double tx = ih2 * (fz * szv.x + fy * syv.x + fx * sxv.x) + r.bz.x;
+    const double ty = ih2 * (fz * szv.y + fy * syv.y + fx * sxv.y) + r.bz.y;
+    const double2 out =
+        c2(omw * ub.x + (r.wdz.x * tx - r.wdz.y * ty), omw * ub.y + (r.wdz.x * ty + r.wdz.y * tx));
+    if (own && z < z1) u_out[base + at(z)] = out;
+  };
+  double2 ua = plane(z0 - 1), ub = plane(z0);
+  for (int z = z0; z < z1; z += 2) {
+    const Row r0 = load(z), r1 = load(z + 1);
+    step(z, r0, ua, ub);
+    step(z + 1, r1, ub, r0.uc);
+    ua = r0.uc;
+    ub = r1.uc;
+  }
+}
+
 __global__ void k_winv3(Grid g, double omega, double s_re, double s_im, double w, double2* __restrict__ winv) {
   const size_t n = (size_t)g.nz * g.ny * g.nx;
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -949,6 +1027,13 @@ hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, con
                          int cap, const double2* b, const double2* u_in, double2* u_out,
                          size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  if (dim == 3 && u_in && w_override <= 0.0) {
+    const int nstrip = (g.nx + kMarchW - 1) / kMarchW, nchunk = (g.nz + kMarchZ - 1) / kMarchZ;
+    const int groups = (g.ny * nstrip * nchunk + 3) / 4;
+    hipLaunchKernelGGL(k_smooth3m, grid1(tile_blocks(groups, cap)), dim3(kBlock), 0, st, g, nstrip, nchunk, groups,
+                       lvl, bt, b, u_in, u_out, stride);
+    return hipGetLastError();
+  }
   if (dim == 3) {
     const Tiles t = tiles3(g);
     const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
