@@ -136,6 +136,40 @@ def cpu_baseline(w, iters_per_freq, sample_iters=48, shot=31):
             "host_cpus": os.cpu_count(), "per_freq": per_freq}
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_direct_baseline(w, shots=4):
+    """The paper's own way of solving (its observed data come from an LU
+    factorisation): SuperLU of B at the first frequency plus `shots`
+    triangular solves, on one core, scaled to the step (one factorisation per
+    frequency, one solve per right-hand side)."""
+    import numpy as np
+    from oracle import operator as op, direct
+    om = 2 * np.pi * w.freqs[0]
+    t0 = time.perf_counter()
+    lu = direct.factor_superlu(op.operator_B(w.m, w.h, om, w.alpha))
+    t_factor = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k in range(shots):
+        lu.solve(op.point_source(w.shape, w.h, [w.src[k]]))
+    t_solve = (time.perf_counter() - t0) / shots
+    nrhs = len(w.src) * len(w.freqs)
+    total = len(w.freqs) * t_factor + nrhs * t_solve
+    return {"value": nrhs / total, "unit": "solves/s", "cores": 1, "kind": "oracle, direct (SuperLU)",
+            "sample": f"SuperLU factorisation of B at {w.freqs[0]} Hz ({t_factor:.1f} s) plus {shots} triangular "
+                      f"solves ({t_solve:.2f} s each), scaled to {len(w.freqs)} factorisations and {nrhs} solves"}
+
+
 def copy_calibration():
     """A plain copy of a known size through the library's copy kernel (the
     identity preconditioner): 64 vectors of 401 x 801 complex128 read and
@@ -681,7 +715,7 @@ def main():
         print("# timing the one-right-hand-side-per-call path", file=sys.stderr, flush=True)
         single = one_rhs_per_launch(ctx, w, b1, tol)
 
-    cpu = None
+    cpu = cpu_lu = None
     if not args.no_cpu_baseline:
         gpath = os.path.join(ROOT, "tests", "golden", "c3_oracle_iterations.json")
         with open(gpath) as fh:
@@ -689,6 +723,9 @@ def main():
         its = {k: v["mean_iterations"] for k, v in gold["freqs"].items()}
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, its)
+        cpu["cpu_model"] = cpu_model()
+        print("# timing the direct (LU) solve on the CPU", file=sys.stderr, flush=True)
+        cpu_lu = cpu_direct_baseline(w)
 
     out = {
         "metric": METRIC,
@@ -718,6 +755,7 @@ def main():
         "roofline": roofline,
         "kernel_breakdown": breakdown,
         "cpu_baseline": cpu,
+        "cpu_direct_lu": cpu_lu,
     }
     print(json.dumps(out), flush=True)
 
