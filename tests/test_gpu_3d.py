@@ -229,3 +229,31 @@ def test_3d_unpreconditioned_solve(hz):
     B = op.operator_B(w.m, w.h, 2 * np.pi * 2.0, 0.2)
     bn = op.point_source(w.shape, w.h, [(iz * w.shape[1] + iy) * w.shape[2] + ix])
     assert rel(to_np(u)[0, 0].ravel(), direct.solve_superlu(B, bn)) < 1e-8
+
+
+@pytest.mark.parametrize("f", [2.0, 6.0, 12.0])
+def test_3d_plan_matches_oracle_plan(hz, f):
+    """The library's level count and damped-Jacobi weights on a 3D grid are
+    the oracle's plan (local Fourier analysis with dim = 3)."""
+    from oracle import lfa
+    w = workloads.model_3d_layered(65, 33, 49, h=20.0, nshots=1)
+    c = ctx_for(hz, w.m, w.h)
+    L, wj = c.plan(f)
+    Lo, wo = lfa.plan(w.shape, w.h, 2 * np.pi * f, float(w.m.min()), float(w.m.max()), 1.0, 0.5)
+    assert L == Lo and np.allclose(wj, wo, rtol=0, atol=1e-15), (L, wj, Lo, wo)
+
+
+def test_3d_graph_replay_bitwise(hz):
+    """Iterations replayed from captured HIP graphs on a 3D model give the
+    same bits and iteration counts as iterations issued one by one."""
+    import torch
+    w = workloads.model_3d_layered(17, 21, 19, h=25.0, nshots=3, freqs=(3.0, 5.0))
+    c = ctx_for(hz, w.m, w.h)
+    iz, iy, ix = ([s[a] for s in w.src] for a in range(3))
+    b1 = c.point_rhs_3d(iz, iy, ix)
+    b = torch.stack([b1] * len(w.freqs)).contiguous()
+    ref, info_ref = c.solve(w.freqs, w.alpha, b, tol=1e-10, graphs=False)
+    for _ in range(2):
+        u, info = c.solve(w.freqs, w.alpha, b, tol=1e-10, graphs=True)
+        assert torch.equal(u, ref)
+        assert [i[:2] for i in info] == [i[:2] for i in info_ref]
