@@ -3,8 +3,10 @@ oracle, element by element on seeded inputs: the operators B and M on every
 level, one damped-Jacobi sweep, the weighted restriction, the trilinear
 prolongation, the V-cycle, point sources; then whole solves against the
 oracle's direct (LU) solution and its own preconditioned BiCGSTAB iteration
-counts, batch invariance, and the calls a 3D model refuses. Shapes mix odd
-and even node counts and span several 64-wide tiles with ragged tails.
+counts, batch invariance, graph replay, the level plan, the calls a 3D model
+refuses, and the benchmark's own 129^3 workload checked through the oracle's
+operator. Shapes mix odd and even node counts and span several 64-wide tiles
+with ragged tails.
 
 Tolerances as for 2D: one stencil evaluation 1e-13 relative, a V-cycle
 1e-11, a solve to relative residual 1e-8 within 1e-6 of the LU solution and
@@ -257,3 +259,25 @@ def test_3d_graph_replay_bitwise(hz):
         u, info = c.solve(w.freqs, w.alpha, b, tol=1e-10, graphs=True)
         assert torch.equal(u, ref)
         assert [i[:2] for i in info] == [i[:2] for i in info_ref]
+
+
+def test_3d_benchmark_workload_residuals(hz):
+    """The 3D benchmark's own workload (129^3, h = 20 m, 8 shots x 3/5 Hz, in
+    the launch configuration the benchmark times): every right-hand side
+    converges, and the oracle's operator confirms ||b - B u|| / ||b|| <= 2 tol
+    for each of them (a property that holds at any size)."""
+    import torch
+    w = workloads.model_3d_layered(129, 129, 129, h=20.0, nshots=8, freqs=(3.0, 5.0))
+    c = ctx_for(hz, w.m, w.h)
+    iz, iy, ix = ([s[a] for s in w.src] for a in range(3))
+    b1 = c.point_rhs_3d(iz, iy, ix)
+    b = torch.stack([b1] * len(w.freqs)).contiguous()
+    print(f"[3d-bench-workload] solving {b.shape[0] * b.shape[1]} right-hand sides on {w.shape}", flush=True)
+    u, info = c.solve(w.freqs, w.alpha, b, tol=1e-8)
+    assert all(i[0] == hz.HZ_RHS_CONVERGED for i in info)
+    u, bh = to_np(u), to_np(b)
+    for fi, f in enumerate(w.freqs):
+        B = op.operator_B(w.m, w.h, 2 * np.pi * f, w.alpha)
+        for s in range(len(w.src)):
+            r = bh[fi, s].ravel() - B @ u[fi, s].ravel()
+            assert np.linalg.norm(r) <= 2e-8 * np.linalg.norm(bh[fi, s]), (f, s)
