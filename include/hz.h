@@ -157,9 +157,9 @@ int  hz_point_rhs(hz_ctx *c, int nsrc, const int *iz, const int *ix,
  * and 2D (7-point stencil; a node's face weights are the products of the
  * other axes' end weights). m_dev: device, [nz][ny][nx] doubles, copied.
  * Every axis halves on each coarser level. A 3D model is solved by hz_solve
- * with BiCGSTAB and the multigrid or no preconditioner (u_dev and b_dev
- * [nfreq][nrhs][nz][ny][nx]); GMRES, the exact 1D preconditioner, the
- * misfit, gradient and Gauss-Newton calls return HZ_ERR_ARG for it.
+ * with BiCGSTAB or GMRES and the multigrid or no preconditioner (u_dev and
+ * b_dev [nfreq][nrhs][nz][ny][nx]); the exact 1D preconditioner, the misfit,
+ * gradient and Gauss-Newton calls return HZ_ERR_ARG for it.
  * Errors: HZ_ERR_ARG (nz, ny or nx < 3, h <= 0, non-finite or non-positive m,
  * more than 2^30 nodes). */
 int  hz_set_model_3d(hz_ctx *c, int nz, int ny, int nx, double h, const double *m_dev);

@@ -289,7 +289,6 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
   if (o->krylov != HZ_BICGSTAB && o->krylov != HZ_GMRES) return fail(c, HZ_ERR_ARG, "unknown krylov method");
   if (o->krylov == HZ_GMRES && (o->gmres_m < 1 || o->gmres_m > 200))
     return fail(c, HZ_ERR_ARG, "gmres_m must be in [1, 200]");
-  if (o->krylov == HZ_GMRES && c->dim == 3) return fail(c, HZ_ERR_ARG, "3D grids are solved by BiCGSTAB only");
   if (o->precond < HZ_PRECOND_MG || o->precond > HZ_PRECOND_NONE) return fail(c, HZ_ERR_ARG, "unknown preconditioner");
   if (o->precond != HZ_PRECOND_NONE) {
     if (!(o->beta2 > 0.0) || !isfinite(o->beta1) || !isfinite(o->beta2))

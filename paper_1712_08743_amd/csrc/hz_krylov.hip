@@ -735,6 +735,32 @@ __global__ void __launch_bounds__(kBlock) k_gm_residual(Grid g, Tiles t, Batch b
   store_partial<1>(acc, rd, slot, tile);
 }
 
+// The same on a 3D grid (row tiling, hz_node3.h).
+__global__ void __launch_bounds__(kBlock) k_gm_residual3(Grid g, Tiles t, Batch bt, Reduce rd, int first,
+                                                         const double2* __restrict__ b, double2* __restrict__ x,
+                                                         double2* __restrict__ v0, size_t stride) {
+  int slot, tile;
+  if (!decode_tile(bt, t.per_slot, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+  double acc[1] = {0.0};
+  int iz, iy, ix;
+  size_t p;
+  if (node3_of(t, tile, g, iz, iy, ix, p)) {
+    double2 r;
+    if (first) {
+      x[base + p] = c2(0.0, 0.0);
+      r = b[base + p];
+    } else {
+      const FreqTab& f = bt.ft[bt.slots[slot].freq];
+      const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+      r = csub(b[base + p], apply_node3(x + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c));
+    }
+    v0[base + p] = r;
+    acc[0] = r.x * r.x + r.y * r.y;
+  }
+  store_partial<1>(acc, rd, slot, tile);
+}
+
 // Cycle start: beta = ||r||, g = (beta, 0, ...), or a final status.
 __global__ void __launch_bounds__(kBlock) k_gm_residual_fin(int tiles, Batch bt, Reduce rd, Gmres gm,
                                                             int first, double tol, int maxit) {
@@ -1143,10 +1169,12 @@ hipError_t launch_true_residual(int dim, const Grid& g, const Batch& bt, int cap
 hipError_t launch_gm_residual(int dim, const Grid& g, const Batch& bt, int cap, const Reduce& rd,
                               const Gmres& gm, int first, double tol, int maxit, const double2* b,
                               double2* x, double2* v0, size_t stride, hipStream_t st) {
-  const Tiles t = grid_tiles(g.nz, g.nx, dim);
+  const Tiles t = dim == 3 ? grid_tiles(g.nz * g.ny, g.nx, 3) : grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
-  if (dim == 2)
+  if (dim == 3)
+    hipLaunchKernelGGL(k_gm_residual3, gr, dim3(kBlock), 0, st, g, t, bt, rd, first, b, x, v0, stride);
+  else if (dim == 2)
     hipLaunchKernelGGL(k_gm_residual<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, first, b, x, v0, stride);
   else
     hipLaunchKernelGGL(k_gm_residual<false>, gr, dim3(kBlock), 0, st, g, t, bt, rd, first, b, x, v0, stride);

@@ -179,14 +179,15 @@ def test_3d_batch_invariance_bitwise(hz):
 
 
 def test_3d_refusals(hz):
-    """What a 3D model does not take: GMRES, the 2D source and receiver
-    calls, an axis below three nodes; a 2D model refuses the 3D sources."""
+    """What a 3D model does not take: the 2D source and receiver calls, the
+    exact 1D preconditioner, an axis below three nodes; a 2D model refuses
+    the 3D sources."""
     import torch
     w = workloads.model_3d_layered(9, 9, 9, h=30.0, nshots=1, freqs=(3.0,))
     c = ctx_for(hz, w.m, w.h)
     b = c.point_rhs_3d([0], [4], [4])[None].contiguous()
     with pytest.raises(hz.HzError) as e:
-        c.solve(w.freqs, w.alpha, b, krylov="gmres")
+        c.solve(w.freqs, w.alpha, b, precond="exact")
     assert e.value.code == hz.HZ_ERR_ARG
     with pytest.raises(hz.HzError) as e:
         c.point_rhs([0], [4])
@@ -281,3 +282,28 @@ def test_3d_benchmark_workload_residuals(hz):
         for s in range(len(w.src)):
             r = bh[fi, s].ravel() - B @ u[fi, s].ravel()
             assert np.linalg.norm(r) <= 2e-8 * np.linalg.norm(bh[fi, s]), (f, s)
+
+
+@pytest.mark.parametrize("m", [30, 5])
+def test_3d_gmres_matches_direct_and_oracle(hz, m):
+    """GMRES(m) with the V-cycle on a 3D box: the wavefields against LU and
+    the iteration count against the oracle's GMRES(m) with the same V-cycle."""
+    import torch
+    w = workloads.model_3d_layered(17, 21, 25, h=25.0, nshots=2, freqs=(4.0,))
+    c = ctx_for(hz, w.m, w.h)
+    iz, iy, ix = ([s[a] for s in w.src] for a in range(3))
+    b = c.point_rhs_3d(iz, iy, ix)[None].contiguous()
+    u, info = c.solve(w.freqs, w.alpha, b, krylov="gmres", gmres_m=m, tol=1e-8)
+    u = to_np(u)
+    om = 2 * np.pi * w.freqs[0]
+    B = op.operator_B(w.m, w.h, om, w.alpha)
+    L, wj = c.plan(w.freqs[0])
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
+    for s in range(len(w.src)):
+        st, it, rr = info[s]
+        assert st == hz.HZ_RHS_CONVERGED and rr <= 1e-8
+        bn = op.point_source(w.shape, w.h, [(iz[s] * w.shape[1] + iy[s]) * w.shape[2] + ix[s]])
+        assert rel(u[0, s].ravel(), direct.solve_superlu(B, bn)) < 1e-6
+        if s == 0:
+            _, it_o, _, st_o = krylov.gmres(B, bn, vc, m=m, tol=1e-8, maxit=2000)
+            assert st_o == krylov.CONVERGED and iters_close(it, it_o), (it, it_o)
