@@ -429,8 +429,9 @@ def bench_3d(args):
     with HIP events; the dominant one gives the roofline line. The CPU
     oracle is timed on a bounded sample (set-up plus a few BiCGSTAB
     iterations of one shot per frequency) and scaled to the batch with the
-    GPU's iteration counts (which the parity tests hold within 5 % of the
-    oracle's). One JSON line, a report beside the 2D throughput line."""
+    oracle's own iteration counts to convergence
+    (tests/golden/l3d_oracle_iterations.json). One JSON line, a report beside
+    the 2D throughput line."""
     import torch
     import numpy as np
     import paper_1712_08743_amd as hz
@@ -497,7 +498,9 @@ def bench_3d(args):
     cpu = None
     if not args.no_cpu_baseline:
         print("# 3d: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline_3d(w, iters, len(w.src))
+        with open(os.path.join(ROOT, "tests", "golden", "l3d_oracle_iterations.json")) as fh:
+            gold = json.load(fh)
+        cpu = cpu_baseline_3d(w, {k: v["mean_iterations"] for k, v in gold["freqs"].items()}, len(w.src))
     out = {
         "metric": "Helmholtz solves/s (3D 129^3, 16 RHS)",
         "value": nrhs / sec, "unit": "solves/s", "n_gpus": 1, "steps": steps, "warmup": 1,
@@ -515,10 +518,10 @@ def bench_3d(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_3d(w, iters, nshot, sample_iters=3):
+def cpu_baseline_3d(w, iters_per_freq, nshot, sample_iters=3):
     """The oracle on one shot per frequency: its V-cycle set-up plus
     sample_iters BiCGSTAB iterations, scaled to the batch (nshot shots per
-    frequency, the GPU's iteration counts)."""
+    frequency, the oracle's mean iterations to convergence per frequency)."""
     import numpy as np
     from oracle import operator as op
     from oracle import multigrid as mg
@@ -539,14 +542,14 @@ def cpu_baseline_3d(w, iters, nshot, sample_iters=3):
         t0 = time.perf_counter()
         krylov.bicgstab(B, bn, vc, tol=1e-30, maxit=sample_iters)
         t_it = (time.perf_counter() - t0) / sample_iters
-        n_it = float(np.mean(iters[k * nshot:(k + 1) * nshot]))
+        n_it = iters_per_freq[str(f)]
         total += t_setup + nshot * n_it * t_it
         per_freq[str(f)] = {"setup_s": t_setup, "s_per_iteration": t_it, "iterations": n_it}
     sample_s = time.perf_counter() - t_all
     return {"value": nshot * len(w.freqs) / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"one shot per frequency: the oracle's V-cycle set-up plus {sample_iters} BiCGSTAB "
-                      f"iterations ({sample_s:.1f} s of CPU), scaled to {nshot} shots x the GPU's mean "
-                      "iterations per frequency",
+                      f"iterations ({sample_s:.1f} s of CPU), scaled to {nshot} shots x the oracle's mean "
+                      "iterations to 1e-8 per frequency (tests/golden/l3d_oracle_iterations.json)",
             "host_cpus": os.cpu_count(), "per_freq": per_freq}
 
 

@@ -265,7 +265,9 @@ def test_3d_graph_replay_bitwise(hz):
 def test_3d_benchmark_workload_residuals(hz):
     """The 3D benchmark's own workload (129^3, h = 20 m, 8 shots x 3/5 Hz, in
     the launch configuration the benchmark times): every right-hand side
-    converges, and the oracle's operator confirms ||b - B u|| / ||b|| <= 2 tol
+    converges, the iteration counts of two shots per frequency are the
+    oracle's (stored by tests/golden/make_3d_oracle_iterations.py) within
+    max(2, 5 %), and the oracle's operator confirms ||b - B u|| / ||b|| <= 2 tol
     for each of them (a property that holds at any size)."""
     import torch
     w = workloads.model_3d_layered(129, 129, 129, h=20.0, nshots=8, freqs=(3.0, 5.0))
@@ -276,6 +278,15 @@ def test_3d_benchmark_workload_residuals(hz):
     print(f"[3d-bench-workload] solving {b.shape[0] * b.shape[1]} right-hand sides on {w.shape}", flush=True)
     u, info = c.solve(w.freqs, w.alpha, b, tol=1e-8)
     assert all(i[0] == hz.HZ_RHS_CONVERGED for i in info)
+    # iteration counts of the shots the oracle ran to convergence (tests/golden)
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "l3d_oracle_iterations.json")) as fh:
+        gold = json.load(fh)
+    for fi, f in enumerate(w.freqs):
+        for s, it_o in zip(gold["shots"], gold["freqs"][str(f)]["iterations"]):
+            it = info[fi * len(w.src) + s][1]
+            assert iters_close(it, it_o), (f, s, it, it_o)
     u, bh = to_np(u), to_np(b)
     for fi, f in enumerate(w.freqs):
         B = op.operator_B(w.m, w.h, 2 * np.pi * f, w.alpha)
