@@ -158,8 +158,9 @@ int  hz_point_rhs(hz_ctx *c, int nsrc, const int *iz, const int *ix,
  * other axes' end weights). m_dev: device, [nz][ny][nx] doubles, copied.
  * Every axis halves on each coarser level. A 3D model is solved by hz_solve
  * with BiCGSTAB or GMRES and the multigrid or no preconditioner (u_dev and
- * b_dev [nfreq][nrhs][nz][ny][nx]); the exact 1D preconditioner, the misfit,
- * gradient and Gauss-Newton calls return HZ_ERR_ARG for it.
+ * b_dev [nfreq][nrhs][nz][ny][nx]); the exact 1D preconditioner returns
+ * HZ_ERR_ARG for it. Its misfit, gradient and Gauss-Newton step are the _3d
+ * calls below (the 2D calls return HZ_ERR_ARG for a 3D model).
  * Errors: HZ_ERR_ARG (nz, ny or nx < 3, h <= 0, non-finite or non-positive m,
  * more than 2^30 nodes). */
 int  hz_set_model_3d(hz_ctx *c, int nz, int ny, int nx, double h, const double *m_dev);
@@ -228,6 +229,30 @@ int  hz_gn_step(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq
                 const hz_c128 *src_amp, int nrec, const int *rec_iz, const int *rec_ix,
                 const hz_c128 *d_obs_dev, double lambda, int cg_iters, double cg_tol,
                 double *J, double *dm_dev, int *cg_done, hz_rhs_info *info);
+
+/* hz_misfit, hz_gradient and hz_gn_step on a 3D model (set by
+ * hz_set_model_3d): sources and receivers are nodes (iz, iy, ix), host
+ * arrays; the source amplitude is amp / h^3. In delta_i, g_i is the node's
+ * exposed boundary face area and w_i its control volume, both in cell units
+ * (products of the axes' end weights). grad_dev and dm_dev are device
+ * [nz][ny][nx] doubles. Everything else, results and errors as in the 2D
+ * calls; each returns HZ_ERR_ARG for a model that is not 3D. */
+int  hz_misfit_3d(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+                  double alpha, int nsrc, const int *src_iz, const int *src_iy,
+                  const int *src_ix, const hz_c128 *src_amp, int nrec, const int *rec_iz,
+                  const int *rec_iy, const int *rec_ix, const hz_c128 *d_obs_dev,
+                  double lambda, double *J, hz_c128 *d_cal_dev, hz_rhs_info *info);
+int  hz_gradient_3d(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+                    double alpha, int nsrc, const int *src_iz, const int *src_iy,
+                    const int *src_ix, const hz_c128 *src_amp, int nrec, const int *rec_iz,
+                    const int *rec_iy, const int *rec_ix, const hz_c128 *d_obs_dev,
+                    double lambda, double *J, double *grad_dev, hz_rhs_info *info);
+int  hz_gn_step_3d(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+                   double alpha, int nsrc, const int *src_iz, const int *src_iy,
+                   const int *src_ix, const hz_c128 *src_amp, int nrec, const int *rec_iz,
+                   const int *rec_iy, const int *rec_ix, const hz_c128 *d_obs_dev,
+                   double lambda, int cg_iters, double cg_tol, double *J, double *dm_dev,
+                   int *cg_done, hz_rhs_info *info);
 
 /* The level count and damped-Jacobi weights the solver will use for one
  * frequency (host computation, no device work): *levels and w[0..levels-2].

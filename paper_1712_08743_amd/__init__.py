@@ -87,6 +87,12 @@ _SIGS = {
                          _ip, _vp, _d, _dp, _vp, ctypes.POINTER(RhsInfo)]),
     "hz_gn_step": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
                         _ip, _vp, _d, _i, _d, _dp, _vp, _ip, ctypes.POINTER(RhsInfo)]),
+    "hz_misfit_3d": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _ip, _vp, _i, _ip,
+                          _ip, _ip, _vp, _d, _dp, _vp, ctypes.POINTER(RhsInfo)]),
+    "hz_gradient_3d": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _ip, _vp, _i, _ip,
+                            _ip, _ip, _vp, _d, _dp, _vp, ctypes.POINTER(RhsInfo)]),
+    "hz_gn_step_3d": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _ip, _vp, _i, _ip,
+                           _ip, _ip, _vp, _d, _i, _d, _dp, _vp, _ip, ctypes.POINTER(RhsInfo)]),
     "hz_plan": (_i, [_vp, ctypes.POINTER(SolveOpts), _d, _ip, _dp]),
     "hz_plan_grid": (_i, [_i, _i, _i, _d, _d, _d, ctypes.POINTER(SolveOpts), _d, _ip, _dp]),
     "hz_apply": (_i, [_vp, _i, _i, _d, _d, _d, _d, _i, _vp, _vp]),
@@ -281,85 +287,94 @@ class Context:
         self.last_seconds = [i.seconds for i in info]
         return u, [(i.status, i.iters, i.relres) for i in info]
 
-    def misfit(self, freqs, alpha, src, rec, d_obs, lam, src_amp=None, **opt):
-        """J(m) of Eq. (4); src, rec: lists of (iz, ix). Returns (J, d_cal, info)."""
+    def _fwi_call(self, name, three_d, freqs, src, rec, d_obs, src_amp, nrec_info):
+        """Marshal the arguments shared by the misfit, gradient and
+        Gauss-Newton calls: (function, leading args, trailing arg builder)."""
         t = self.torch
         freqs = [float(f) for f in freqs]
         nf, ns, nr = len(freqs), len(src), len(rec)
         d_obs = d_obs.to(self.device, t.complex128).contiguous()
         assert tuple(d_obs.shape) == (nf, ns, nr)
-        d_cal = t.empty_like(d_obs)
-        o, keep = make_opts(**opt)
-        info = (RhsInfo * (nf * ns))()
-        J = ctypes.c_double()
         ampbuf = None
         if src_amp is not None:
             ampbuf = (ctypes.c_double * (2 * ns))()
             for k, a in enumerate(src_amp):
                 ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
-        rc = _lib.hz_misfit(self._h, ctypes.byref(o), nf, (ctypes.c_double * nf)(*freqs), float(alpha), ns,
-                            _int_array([s[0] for s in src]), _int_array([s[1] for s in src]),
-                            ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
-                            nr, _int_array([r[0] for r in rec]), _int_array([r[1] for r in rec]),
-                            _ptr(d_obs), float(lam), ctypes.byref(J), _ptr(d_cal), info)
+        naxes = 3 if three_d else 2
+        for q in list(src) + list(rec):
+            if len(q) != naxes:
+                raise ValueError(f"sources and receivers are {naxes}-tuples of node indices, got {q}")
+        src_axes = [_int_array([q[a] for q in src]) for a in range(naxes)]
+        rec_axes = [_int_array([q[a] for q in rec]) for a in range(naxes)]
+        amp = ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None
+        fa = (ctypes.c_double * nf)(*freqs)
+        fn = getattr(_lib, name + ("_3d" if three_d else ""))
+        head = [nf, fa]
+        pts = [ns] + src_axes + [amp, nr] + rec_axes + [_ptr(d_obs)]
+        info = (RhsInfo * (nrec_info * nf * ns))()
+        return fn, head, pts, info, d_obs, (ampbuf, src_axes, rec_axes, fa)
+
+    def _misfit(self, three_d, freqs, alpha, src, rec, d_obs, lam, src_amp, opt):
+        fn, head, pts, info, d_obs, keep_args = self._fwi_call("hz_misfit", three_d, freqs, src, rec, d_obs,
+                                                               src_amp, 1)
+        d_cal = self.torch.empty_like(d_obs)
+        o, keep = make_opts(**opt)
+        J = ctypes.c_double()
+        rc = fn(self._h, ctypes.byref(o), *head, float(alpha), *pts, float(lam), ctypes.byref(J), _ptr(d_cal), info)
         self._check(rc, allow_warn=True)
-        del keep
+        del keep, keep_args
         return J.value, d_cal, [(i.status, i.iters, i.relres) for i in info]
+
+    def _gradient(self, three_d, freqs, alpha, src, rec, d_obs, lam, src_amp, opt):
+        fn, head, pts, info, d_obs, keep_args = self._fwi_call("hz_gradient", three_d, freqs, src, rec, d_obs,
+                                                               src_amp, 2)
+        grad = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        o, keep = make_opts(**opt)
+        J = ctypes.c_double()
+        rc = fn(self._h, ctypes.byref(o), *head, float(alpha), *pts, float(lam), ctypes.byref(J), _ptr(grad), info)
+        self._check(rc, allow_warn=True)
+        del keep, keep_args
+        return J.value, grad, [(i.status, i.iters, i.relres) for i in info]
+
+    def _gn_step(self, three_d, freqs, alpha, src, rec, d_obs, lam, cg_iters, cg_tol, src_amp, opt):
+        fn, head, pts, info, d_obs, keep_args = self._fwi_call("hz_gn_step", three_d, freqs, src, rec, d_obs,
+                                                               src_amp, 1)
+        dm = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        o, keep = make_opts(**opt)
+        J = ctypes.c_double()
+        done = ctypes.c_int()
+        rc = fn(self._h, ctypes.byref(o), *head, float(alpha), *pts, float(lam), int(cg_iters), float(cg_tol),
+                ctypes.byref(J), _ptr(dm), ctypes.byref(done), info)
+        self._check(rc, allow_warn=True)
+        del keep, keep_args
+        return dm, J.value, done.value, [(i.status, i.iters, i.relres) for i in info]
+
+    def misfit(self, freqs, alpha, src, rec, d_obs, lam, src_amp=None, **opt):
+        """J(m) of Eq. (4); src, rec: lists of (iz, ix). Returns (J, d_cal, info)."""
+        return self._misfit(False, freqs, alpha, src, rec, d_obs, lam, src_amp, opt)
+
+    def misfit_3d(self, freqs, alpha, src, rec, d_obs, lam, src_amp=None, **opt):
+        """misfit on a 3D model; src, rec: lists of (iz, iy, ix)."""
+        return self._misfit(True, freqs, alpha, src, rec, d_obs, lam, src_amp, opt)
 
     def gradient(self, freqs, alpha, src, rec, d_obs, lam, src_amp=None, **opt):
         """J(m) and dJ/dm (float64 tensor shaped like m) by the adjoint-state
         method. Returns (J, grad, info) with 2 * nfreq * nsrc info records
         (forward solves, then adjoint solves)."""
-        t = self.torch
-        freqs = [float(f) for f in freqs]
-        nf, ns, nr = len(freqs), len(src), len(rec)
-        d_obs = d_obs.to(self.device, t.complex128).contiguous()
-        assert tuple(d_obs.shape) == (nf, ns, nr)
-        grad = t.empty(self.shape, dtype=t.float64, device=self.device)
-        o, keep = make_opts(**opt)
-        info = (RhsInfo * (2 * nf * ns))()
-        J = ctypes.c_double()
-        ampbuf = None
-        if src_amp is not None:
-            ampbuf = (ctypes.c_double * (2 * ns))()
-            for k, a in enumerate(src_amp):
-                ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
-        rc = _lib.hz_gradient(self._h, ctypes.byref(o), nf, (ctypes.c_double * nf)(*freqs), float(alpha), ns,
-                              _int_array([q[0] for q in src]), _int_array([q[1] for q in src]),
-                              ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
-                              nr, _int_array([r[0] for r in rec]), _int_array([r[1] for r in rec]),
-                              _ptr(d_obs), float(lam), ctypes.byref(J), _ptr(grad), info)
-        self._check(rc, allow_warn=True)
-        del keep
-        return J.value, grad, [(i.status, i.iters, i.relres) for i in info]
+        return self._gradient(False, freqs, alpha, src, rec, d_obs, lam, src_amp, opt)
+
+    def gradient_3d(self, freqs, alpha, src, rec, d_obs, lam, src_amp=None, **opt):
+        """gradient on a 3D model; src, rec: lists of (iz, iy, ix)."""
+        return self._gradient(True, freqs, alpha, src, rec, d_obs, lam, src_amp, opt)
 
     def gn_step(self, freqs, alpha, src, rec, d_obs, lam, cg_iters, cg_tol=0.0, src_amp=None, **opt):
         """One Gauss-Newton update (Eq. (9)) of the current model by CG on the
         Gauss-Newton system. Returns (dm, J, cg_iterations, info)."""
-        t = self.torch
-        freqs = [float(f) for f in freqs]
-        nf, ns, nr = len(freqs), len(src), len(rec)
-        d_obs = d_obs.to(self.device, t.complex128).contiguous()
-        assert tuple(d_obs.shape) == (nf, ns, nr)
-        dm = t.empty(self.shape, dtype=t.float64, device=self.device)
-        o, keep = make_opts(**opt)
-        info = (RhsInfo * (nf * ns))()
-        J = ctypes.c_double()
-        done = ctypes.c_int()
-        ampbuf = None
-        if src_amp is not None:
-            ampbuf = (ctypes.c_double * (2 * ns))()
-            for k, a in enumerate(src_amp):
-                ampbuf[2 * k], ampbuf[2 * k + 1] = complex(a).real, complex(a).imag
-        rc = _lib.hz_gn_step(self._h, ctypes.byref(o), nf, (ctypes.c_double * nf)(*freqs), float(alpha), ns,
-                             _int_array([q[0] for q in src]), _int_array([q[1] for q in src]),
-                             ctypes.cast(ampbuf, ctypes.c_void_p) if ampbuf is not None else None,
-                             nr, _int_array([r[0] for r in rec]), _int_array([r[1] for r in rec]),
-                             _ptr(d_obs), float(lam), int(cg_iters), float(cg_tol), ctypes.byref(J), _ptr(dm),
-                             ctypes.byref(done), info)
-        self._check(rc, allow_warn=True)
-        del keep
-        return dm, J.value, done.value, [(i.status, i.iters, i.relres) for i in info]
+        return self._gn_step(False, freqs, alpha, src, rec, d_obs, lam, cg_iters, cg_tol, src_amp, opt)
+
+    def gn_step_3d(self, freqs, alpha, src, rec, d_obs, lam, cg_iters, cg_tol=0.0, src_amp=None, **opt):
+        """gn_step on a 3D model; src, rec: lists of (iz, iy, ix)."""
+        return self._gn_step(True, freqs, alpha, src, rec, d_obs, lam, cg_iters, cg_tol, src_amp, opt)
 
     def plan(self, freq, **opt):
         o, keep = make_opts(**opt)

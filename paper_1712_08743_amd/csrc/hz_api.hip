@@ -1434,31 +1434,23 @@ int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz
   return any_fail ? HZ_WARN_NOCONV : HZ_OK;
 }
 
-int hz_misfit(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
-              int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
-              const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda,
-              double* J, hz_c128* d_cal_dev, hz_rhs_info* info) {
-  int rc = require_model(c);
-  if (rc) return rc;
-  if (c->dim == 3) return fail(c, HZ_ERR_ARG, "the misfit, gradient and Gauss-Newton calls take 1D and 2D models");
-  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
-      !d_obs_dev || !J)
+namespace {
+// The misfit, gradient and Gauss-Newton step for sources and receivers given
+// as flat node indices (checked by the public calls below).
+int misfit_nodes(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha, int nsrc,
+                 const std::vector<int>& snodes, const hz_c128* src_amp, int nrec, const std::vector<int>& rnodes,
+                 const hz_c128* d_obs_dev, double lambda, double* J, hz_c128* d_cal_dev, hz_rhs_info* info) {
+  int rc;
+  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !d_obs_dev || !J)
     return fail(c, HZ_ERR_ARG, "bad misfit arguments");
   if (!(lambda >= 0.0) || !isfinite(lambda)) return fail(c, HZ_ERR_ARG, "lambda must be >= 0");
-  std::vector<int> rnodes(nrec);
-  for (int r = 0; r < nrec; ++r) {
-    if (rec_iz[r] < 0 || rec_iz[r] >= c->nz || rec_ix[r] < 0 || rec_ix[r] >= c->nx)
-      return fail(c, HZ_ERR_ARG, "receiver %d is outside the grid", r);
-    rnodes[r] = rec_iz[r] * c->nx + rec_ix[r];
-  }
   HZ_HIP(c, hipSetDevice(c->device));
   const size_t n0 = c->lv[0].n();
   const size_t nb = (size_t)nfreq * nsrc * n0;
   HZ_ALLOC(c, c->misfit_b, nb * sizeof(double2));
   HZ_ALLOC(c, c->misfit_u, nb * sizeof(double2));
   for (int f = 0; f < nfreq; ++f) {
-    rc = hz_point_rhs(c, nsrc, src_iz, src_ix, src_amp,
-                      reinterpret_cast<hz_c128*>(c->misfit_b.as<double2>() + (size_t)f * nsrc * n0));
+    rc = set_points(c, snodes, src_amp, reinterpret_cast<hz_c128*>(c->misfit_b.as<double2>() + (size_t)f * nsrc * n0));
     if (rc) return rc;
   }
   rc = hz_solve(c, o, nfreq, freq_hz, alpha, nsrc, reinterpret_cast<const hz_c128*>(c->misfit_b.p),
@@ -1484,26 +1476,16 @@ int hz_misfit(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_h
   return solve_rc;
 }
 
-int hz_gradient(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
-                int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
-                const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda, double* J,
-                double* grad_dev, hz_rhs_info* info) {
-  int rc = require_model(c);
-  if (rc) return rc;
-  if (c->dim == 3) return fail(c, HZ_ERR_ARG, "the misfit, gradient and Gauss-Newton calls take 1D and 2D models");
-  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
-      !d_obs_dev || !J || !grad_dev)
+int gradient_nodes(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha, int nsrc,
+                   const std::vector<int>& snodes, const hz_c128* src_amp, int nrec, const std::vector<int>& rnode,
+                   const hz_c128* d_obs_dev, double lambda, double* J, double* grad_dev, hz_rhs_info* info) {
+  int rc;
+  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !d_obs_dev || !J || !grad_dev)
     return fail(c, HZ_ERR_ARG, "bad gradient arguments");
   if (!(lambda >= 0.0) || !isfinite(lambda)) return fail(c, HZ_ERR_ARG, "lambda must be >= 0");
   for (int f = 0; f < nfreq; ++f)
     if (!(freq_hz[f] > 0.0) || !isfinite(freq_hz[f])) return fail(c, HZ_ERR_ARG, "frequency %d must be positive", f);
   // distinct receiver nodes and, for each, its receivers (in receiver order)
-  std::vector<int> rnode(nrec);
-  for (int r = 0; r < nrec; ++r) {
-    if (rec_iz[r] < 0 || rec_iz[r] >= c->nz || rec_ix[r] < 0 || rec_ix[r] >= c->nx)
-      return fail(c, HZ_ERR_ARG, "receiver %d is outside the grid", r);
-    rnode[r] = rec_iz[r] * c->nx + rec_ix[r];
-  }
   std::vector<int> order(nrec);
   for (int r = 0; r < nrec; ++r) order[r] = r;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rnode[a] < rnode[b]; });
@@ -1548,8 +1530,7 @@ int hz_gradient(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq
   for (int f0 = 0; f0 < nfreq; f0 += chunk) {
     const int nf = std::min(chunk, nfreq - f0);
     for (int f = 0; f < nf; ++f) {
-      rc = hz_point_rhs(c, nsrc, src_iz, src_ix, src_amp,
-                        reinterpret_cast<hz_c128*>(c->fwi_b.as<double2>() + (size_t)f * nsrc * n0));
+      rc = set_points(c, snodes, src_amp, reinterpret_cast<hz_c128*>(c->fwi_b.as<double2>() + (size_t)f * nsrc * n0));
       if (rc) return rc;
     }
     hz_rhs_info* inf_fwd = info ? info + (size_t)f0 * nsrc : nullptr;
@@ -1587,25 +1568,16 @@ int hz_gradient(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq
   return worst;
 }
 
-int hz_gn_step(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
-               int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
-               const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda, int cg_iters,
-               double cg_tol, double* J, double* dm_dev, int* cg_done, hz_rhs_info* info) {
-  int rc = require_model(c);
-  if (rc) return rc;
-  if (c->dim == 3) return fail(c, HZ_ERR_ARG, "the misfit, gradient and Gauss-Newton calls take 1D and 2D models");
-  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !src_iz || !src_ix || !rec_iz || !rec_ix ||
-      !d_obs_dev || !J || !dm_dev || !cg_done || cg_iters < 0)
+int gn_step_nodes(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha, int nsrc,
+                  const std::vector<int>& snodes, const hz_c128* src_amp, int nrec, const std::vector<int>& rnode,
+                  const hz_c128* d_obs_dev, double lambda, int cg_iters, double cg_tol, double* J, double* dm_dev,
+                  int* cg_done, hz_rhs_info* info) {
+  int rc;
+  if (nfreq < 1 || nsrc < 1 || nrec < 1 || !freq_hz || !d_obs_dev || !J || !dm_dev || !cg_done || cg_iters < 0)
     return fail(c, HZ_ERR_ARG, "bad Gauss-Newton arguments");
   if (!(lambda >= 0.0) || !isfinite(lambda) || !(cg_tol >= 0.0)) return fail(c, HZ_ERR_ARG, "bad lambda or cg_tol");
   for (int f = 0; f < nfreq; ++f)
     if (!(freq_hz[f] > 0.0) || !isfinite(freq_hz[f])) return fail(c, HZ_ERR_ARG, "frequency %d must be positive", f);
-  std::vector<int> rnode(nrec);
-  for (int r = 0; r < nrec; ++r) {
-    if (rec_iz[r] < 0 || rec_iz[r] >= c->nz || rec_ix[r] < 0 || rec_ix[r] >= c->nx)
-      return fail(c, HZ_ERR_ARG, "receiver %d is outside the grid", r);
-    rnode[r] = rec_iz[r] * c->nx + rec_ix[r];
-  }
   std::vector<int> order(nrec);
   for (int r = 0; r < nrec; ++r) order[r] = r;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rnode[a] < rnode[b]; });
@@ -1654,7 +1626,7 @@ int hz_gn_step(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_
   int worst = HZ_OK;
   // forward fields, kept for every Born product
   for (int f = 0; f < nfreq; ++f) {
-    rc = hz_point_rhs(c, nsrc, src_iz, src_ix, src_amp, reinterpret_cast<hz_c128*>(B + (size_t)f * nsrc * n0));
+    rc = set_points(c, snodes, src_amp, reinterpret_cast<hz_c128*>(B + (size_t)f * nsrc * n0));
     if (rc) return rc;
   }
   rc = hz_solve(c, o, nfreq, freq_hz, alpha, nsrc, reinterpret_cast<const hz_c128*>(B), reinterpret_cast<hz_c128*>(U),
@@ -1710,6 +1682,102 @@ int hz_gn_step(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   *cg_done = it;
   return worst;
+}
+
+// flat node indices of n points given per axis (iy null for a 1D or 2D
+// grid); what names the points in the error message
+int node_list(hz_ctx* c, int n, const int* iz, const int* iy, const int* ix, const char* what,
+              std::vector<int>& nodes) {
+  if (n < 1 || !iz || !ix || (c->dim == 3 && !iy)) return fail(c, HZ_ERR_ARG, "bad %s arguments", what);
+  nodes.resize(n);
+  for (int k = 0; k < n; ++k) {
+    const int y = c->dim == 3 ? iy[k] : 0;
+    if (iz[k] < 0 || iz[k] >= c->nz || y < 0 || y >= c->ny || ix[k] < 0 || ix[k] >= c->nx)
+      return fail(c, HZ_ERR_ARG, "%s %d is outside the grid", what, k);
+    nodes[k] = (iz[k] * c->ny + y) * c->nx + ix[k];
+  }
+  return HZ_OK;
+}
+
+// the model, its dimension and the source and receiver lists of a public call
+int fwi_points(hz_ctx* c, bool three_d, int nsrc, const int* src_iz, const int* src_iy, const int* src_ix,
+               int nrec, const int* rec_iz, const int* rec_iy, const int* rec_ix, std::vector<int>& snodes,
+               std::vector<int>& rnodes) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  if (three_d && c->dim != 3) return fail(c, HZ_ERR_ARG, "the model is not 3D: use the call without _3d");
+  if (!three_d && c->dim == 3) return fail(c, HZ_ERR_ARG, "the model is 3D: use the _3d call");
+  rc = node_list(c, nsrc, src_iz, src_iy, src_ix, "source", snodes);
+  if (rc) return rc;
+  return node_list(c, nrec, rec_iz, rec_iy, rec_ix, "receiver", rnodes);
+}
+}  // namespace
+
+int hz_misfit(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+              int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
+              const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda,
+              double* J, hz_c128* d_cal_dev, hz_rhs_info* info) {
+  std::vector<int> sn, rn;
+  int rc = fwi_points(c, false, nsrc, src_iz, nullptr, src_ix, nrec, rec_iz, nullptr, rec_ix, sn, rn);
+  if (rc) return rc;
+  return misfit_nodes(c, o, nfreq, freq_hz, alpha, nsrc, sn, src_amp, nrec, rn, d_obs_dev, lambda, J, d_cal_dev,
+                      info);
+}
+
+int hz_misfit_3d(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha, int nsrc,
+                 const int* src_iz, const int* src_iy, const int* src_ix, const hz_c128* src_amp, int nrec,
+                 const int* rec_iz, const int* rec_iy, const int* rec_ix, const hz_c128* d_obs_dev, double lambda,
+                 double* J, hz_c128* d_cal_dev, hz_rhs_info* info) {
+  std::vector<int> sn, rn;
+  int rc = fwi_points(c, true, nsrc, src_iz, src_iy, src_ix, nrec, rec_iz, rec_iy, rec_ix, sn, rn);
+  if (rc) return rc;
+  return misfit_nodes(c, o, nfreq, freq_hz, alpha, nsrc, sn, src_amp, nrec, rn, d_obs_dev, lambda, J, d_cal_dev,
+                      info);
+}
+
+int hz_gradient(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+                int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
+                const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda, double* J,
+                double* grad_dev, hz_rhs_info* info) {
+  std::vector<int> sn, rn;
+  int rc = fwi_points(c, false, nsrc, src_iz, nullptr, src_ix, nrec, rec_iz, nullptr, rec_ix, sn, rn);
+  if (rc) return rc;
+  return gradient_nodes(c, o, nfreq, freq_hz, alpha, nsrc, sn, src_amp, nrec, rn, d_obs_dev, lambda, J, grad_dev,
+                        info);
+}
+
+int hz_gradient_3d(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha, int nsrc,
+                   const int* src_iz, const int* src_iy, const int* src_ix, const hz_c128* src_amp, int nrec,
+                   const int* rec_iz, const int* rec_iy, const int* rec_ix, const hz_c128* d_obs_dev,
+                   double lambda, double* J, double* grad_dev, hz_rhs_info* info) {
+  std::vector<int> sn, rn;
+  int rc = fwi_points(c, true, nsrc, src_iz, src_iy, src_ix, nrec, rec_iz, rec_iy, rec_ix, sn, rn);
+  if (rc) return rc;
+  return gradient_nodes(c, o, nfreq, freq_hz, alpha, nsrc, sn, src_amp, nrec, rn, d_obs_dev, lambda, J, grad_dev,
+                        info);
+}
+
+int hz_gn_step(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+               int nsrc, const int* src_iz, const int* src_ix, const hz_c128* src_amp, int nrec,
+               const int* rec_iz, const int* rec_ix, const hz_c128* d_obs_dev, double lambda, int cg_iters,
+               double cg_tol, double* J, double* dm_dev, int* cg_done, hz_rhs_info* info) {
+  std::vector<int> sn, rn;
+  int rc = fwi_points(c, false, nsrc, src_iz, nullptr, src_ix, nrec, rec_iz, nullptr, rec_ix, sn, rn);
+  if (rc) return rc;
+  return gn_step_nodes(c, o, nfreq, freq_hz, alpha, nsrc, sn, src_amp, nrec, rn, d_obs_dev, lambda, cg_iters,
+                       cg_tol, J, dm_dev, cg_done, info);
+}
+
+int hz_gn_step_3d(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha, int nsrc,
+                  const int* src_iz, const int* src_iy, const int* src_ix, const hz_c128* src_amp, int nrec,
+                  const int* rec_iz, const int* rec_iy, const int* rec_ix, const hz_c128* d_obs_dev,
+                  double lambda, int cg_iters, double cg_tol, double* J, double* dm_dev, int* cg_done,
+                  hz_rhs_info* info) {
+  std::vector<int> sn, rn;
+  int rc = fwi_points(c, true, nsrc, src_iz, src_iy, src_ix, nrec, rec_iz, rec_iy, rec_ix, sn, rn);
+  if (rc) return rc;
+  return gn_step_nodes(c, o, nfreq, freq_hz, alpha, nsrc, sn, src_amp, nrec, rn, d_obs_dev, lambda, cg_iters,
+                       cg_tol, J, dm_dev, cg_done, info);
 }
 
 int hz_apply(hz_ctx* c, int op, int level, double freq_hz, double alpha, double beta1, double beta2,

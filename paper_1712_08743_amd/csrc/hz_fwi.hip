@@ -7,9 +7,11 @@
 // (B is complex symmetric, so the transpose system is B itself),
 //   dJ/dm_i = -2 Re[ sum_{f,s} delta_i(f) u_i mu_i ] + 2 lambda m_i,
 //   delta_i(f) = dB_ii/dm_i = j omega g_i / h - 2 omega^2 (1 - j alpha) w_i m_i,
-// the absorbing boundary term included.
+// the absorbing boundary term included; on 1D, 2D and 3D grids (g_i the
+// node's exposed boundary length or face area, w_i its control volume).
 
 #include "hz_device.h"
+#include "hz_node3.h"
 
 namespace hz {
 
@@ -40,29 +42,47 @@ __global__ void k_adjoint_set(int nslots, int nuniq, const int* __restrict__ uni
   out[(size_t)s * stride + node] = acc;
 }
 
+// The geometry of dB_ii/dm_i at node p: gh = g_i / h (the boundary term's
+// weight over h) and w = w_i (the control-volume weight), on a 1D, 2D or 3D
+// grid (flat index p).
+template <int DIM>
+__device__ __forceinline__ void sens_geom(const Grid& g, size_t p, double& gh, double& w) {
+  if constexpr (DIM == 3) {
+    const size_t r = p / g.nx;
+    const int ix = (int)(p - r * g.nx), iz = (int)(r / g.ny), iy = (int)(r - (size_t)iz * g.ny);
+    // with omega = m = 1 and no mass shift, kap.y is the boundary weight over h
+    gh = node_coef3(iz, iy, ix, g, 1.0 / g.h, 1.0, 1.0, 0.0, 0.0).kap.y;
+    w = (iz == 0 || iz == g.nz - 1 ? 0.5 : 1.0) * (iy == 0 || iy == g.ny - 1 ? 0.5 : 1.0) *
+        (ix == 0 || ix == g.nx - 1 ? 0.5 : 1.0);
+  } else {
+    const int iz = DIM == 2 ? (int)(p / g.nx) : 0;
+    const int ix = (int)(p - (size_t)iz * g.nx);
+    // geometry weights: d(kap)/dm with s = 1 - j alpha and omega = 1 gives the per-frequency pieces
+    const NodeC c1 = node_coef<DIM == 2>(iz, ix, g.nz, g.nx, 1.0 / g.h, 1.0, 1.0, 0.0, 0.0);  // kap.y = g / h
+    gh = c1.kap.y;
+    w = c1.wx * c1.wz;
+  }
+}
+
 // grad_i = -2 Re sum_{f, s} delta_i(f) u_i mu_i + 2 lambda m_i, one thread per
 // node, slots summed in order (deterministic). u and mu are [nfreq*nsrc][n].
 // accumulate != 0 adds to grad (frequency chunks).
 // The same sum serves the Gauss-Newton product H v = 2 Re[G^H G v] + 2 lambda v
 // when mu is the adjoint field of the Born data of v: reg is m (gradient) or
 // v (Gauss-Newton product).
-template <bool D2>
+template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_grad_accum(Grid g, int nfreq, int nsrc,
                                                        const double* __restrict__ omega, double alpha,
                                                        const double2* __restrict__ u,
                                                        const double2* __restrict__ mu, size_t stride,
                                                        double lambda, const double* __restrict__ reg,
                                                        int accumulate, double* __restrict__ grad) {
-  const size_t n = (size_t)g.nz * g.nx;
+  const size_t n = (size_t)g.nz * g.ny * g.nx;
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const int iz = D2 ? (int)(p / g.nx) : 0;
-  const int ix = (int)(p - (size_t)iz * g.nx);
   const double m = g.m[p];
-  // geometry weights: d(kap)/dm with s = 1 - j alpha and omega = 1 gives the per-frequency pieces
-  const NodeC c1 = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, 1.0, 1.0, 0.0, 0.0);  // kap.y = g / h
-  const double gh = c1.kap.y;
-  const double w = c1.wx * c1.wz;
+  double gh, w;
+  sens_geom<DIM>(g, p, gh, w);
   double acc = 0.0;
   for (int f = 0; f < nfreq; ++f) {
     const double om = omega[f];
@@ -81,20 +101,18 @@ __global__ void __launch_bounds__(kBlock) k_grad_accum(Grid g, int nfreq, int ns
 }
 
 // Born right-hand sides: rhs[slot] = -delta(f) * u[slot] * v (v real).
-template <bool D2>
+template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_born_src(Grid g, int nslots, int nsrc,
                                                      const double* __restrict__ omega, double alpha,
                                                      const double2* __restrict__ u,
                                                      const double* __restrict__ v,
                                                      double2* __restrict__ rhs, size_t stride) {
-  const size_t n = (size_t)g.nz * g.nx;
+  const size_t n = (size_t)g.nz * g.ny * g.nx;
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const int iz = D2 ? (int)(p / g.nx) : 0;
-  const int ix = (int)(p - (size_t)iz * g.nx);
   const double m = g.m[p];
-  const NodeC c1 = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, 1.0, 1.0, 0.0, 0.0);
-  const double gh = c1.kap.y, w = c1.wx * c1.wz;
+  double gh, w;
+  sens_geom<DIM>(g, p, gh, w);
   const double vp = v[p];
   for (int s = 0; s < nslots; ++s) {
     const double om = omega[s / nsrc];
@@ -201,25 +219,30 @@ hipError_t launch_adjoint_src(int nslots, size_t n, int nuniq, const int* uniq_n
 hipError_t launch_grad_accum(int dim, const Grid& g, int nfreq, int nsrc, const double* omega, double alpha,
                              const double2* u, const double2* mu, double lambda, const double* reg,
                              int accumulate, double* grad, hipStream_t st) {
-  const size_t n = (size_t)g.nz * g.nx;
+  const size_t n = (size_t)g.nz * g.ny * g.nx;
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-  if (dim == 2)
-    hipLaunchKernelGGL(k_grad_accum<true>, dim3(nb), dim3(kBlock), 0, st, g, nfreq, nsrc, omega, alpha, u, mu, n,
+  if (dim == 3)
+    hipLaunchKernelGGL(k_grad_accum<3>, dim3(nb), dim3(kBlock), 0, st, g, nfreq, nsrc, omega, alpha, u, mu, n,
+                       lambda, reg, accumulate, grad);
+  else if (dim == 2)
+    hipLaunchKernelGGL(k_grad_accum<2>, dim3(nb), dim3(kBlock), 0, st, g, nfreq, nsrc, omega, alpha, u, mu, n,
                        lambda, reg, accumulate, grad);
   else
-    hipLaunchKernelGGL(k_grad_accum<false>, dim3(nb), dim3(kBlock), 0, st, g, nfreq, nsrc, omega, alpha, u, mu, n,
+    hipLaunchKernelGGL(k_grad_accum<1>, dim3(nb), dim3(kBlock), 0, st, g, nfreq, nsrc, omega, alpha, u, mu, n,
                        lambda, reg, accumulate, grad);
   return hipGetLastError();
 }
 
 hipError_t launch_born_src(int dim, const Grid& g, int nslots, int nsrc, const double* omega, double alpha,
                            const double2* u, const double* v, double2* rhs, hipStream_t st) {
-  const size_t n = (size_t)g.nz * g.nx;
+  const size_t n = (size_t)g.nz * g.ny * g.nx;
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-  if (dim == 2)
-    hipLaunchKernelGGL(k_born_src<true>, dim3(nb), dim3(kBlock), 0, st, g, nslots, nsrc, omega, alpha, u, v, rhs, n);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_born_src<3>, dim3(nb), dim3(kBlock), 0, st, g, nslots, nsrc, omega, alpha, u, v, rhs, n);
+  else if (dim == 2)
+    hipLaunchKernelGGL(k_born_src<2>, dim3(nb), dim3(kBlock), 0, st, g, nslots, nsrc, omega, alpha, u, v, rhs, n);
   else
-    hipLaunchKernelGGL(k_born_src<false>, dim3(nb), dim3(kBlock), 0, st, g, nslots, nsrc, omega, alpha, u, v, rhs, n);
+    hipLaunchKernelGGL(k_born_src<1>, dim3(nb), dim3(kBlock), 0, st, g, nslots, nsrc, omega, alpha, u, v, rhs, n);
   return hipGetLastError();
 }
 

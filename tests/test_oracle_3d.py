@@ -169,3 +169,60 @@ def test_3d_lfa_closed_form_matches_brute_force():
             a = lfa.smoothing_factor(kh, b1, b2, w, 3)
             bf = lfa.smoothing_factor_sampled(kh, b1, b2, w, 3, n=65)
             assert abs(a - bf) < 1e-12, (kh, b1, b2, w, a, bf)
+
+
+def _survey_3d(shape=(7, 8, 9), h=40.0):
+    """A small 3D survey: true and starting layered models, surface shots,
+    receivers on the surface plane, the far corner and an edge node."""
+    from oracle import gradient as og
+    import workloads
+    nz, ny, nx = shape
+    true = workloads.model_3d_layered(nz, ny, nx, h=h, nshots=2, freqs=(2.0, 3.5), nlayers=3)
+    start = workloads.model_3d_layered(nz, ny, nx, h=h, nshots=2, freqs=(2.0, 3.5), nlayers=3, seed=5)
+    flat = lambda z, y, x: (z * ny + y) * nx + x
+    src = [flat(*s) for s in true.src]
+    rec = [flat(0, y, x) for y in range(0, ny, 3) for x in range(0, nx, 3)]
+    rec += [flat(nz - 1, ny - 1, nx - 1), flat(3, 0, nx - 1)]
+    sv = og.Survey(shape, h, true.freqs, 0.05, src, rec)
+    return og, start.m, sv, og.data(true.m, sv)
+
+
+def _smooth_3d(shape, k):
+    Z, Y, X = np.meshgrid(*(np.linspace(0, 1, n) for n in shape), indexing="ij")
+    return np.cos(k * np.pi * X + 0.3) * np.cos((k + 1) * np.pi * Y) * (1 + Z)
+
+
+def test_3d_gradient_matches_central_differences():
+    """Eq. (7) on a 3D grid: the directional derivative of J along smooth
+    directions, and along single face, edge and corner nodes (whose boundary
+    term's dependence on m is the exposed face area 1, 1 and 3/4)."""
+    og, m, sv, d_obs = _survey_3d()
+    lam = 1e3
+    J, g = og.gradient(m, sv, d_obs, lam)
+    assert np.isclose(J, og.misfit(m, sv, d_obs, lam), rtol=1e-12)
+    for k in (1, 2):
+        v = _smooth_3d(m.shape, k) * np.abs(m).max()
+        eps = 1e-4
+        fd = (og.misfit(m + eps * v, sv, d_obs, lam) - og.misfit(m - eps * v, sv, d_obs, lam)) / (2 * eps)
+        an = float(np.sum(g * v))
+        assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    J0, g0 = og.gradient(m, sv, d_obs, 0.0)
+    nz, ny, nx = m.shape
+    for node in ((0, 3, 4), (nz - 1, 0, 5), (0, 0, 0), (nz - 1, ny - 1, nx - 1), (3, 4, 0)):
+        v = np.zeros_like(m)
+        v[node] = m[node]
+        eps = 1e-5
+        fd = (og.misfit(m + eps * v, sv, d_obs, 0.0) - og.misfit(m - eps * v, sv, d_obs, 0.0)) / (2 * eps)
+        assert abs(fd - g0[node] * v[node]) <= 1e-5 * abs(fd) + 1e-12 * J0, node
+
+
+def test_3d_taylor_remainder_and_born_data():
+    og, m, sv, d_obs = _survey_3d()
+    J, g = og.gradient(m, sv, d_obs, 0.0)
+    v = _smooth_3d(m.shape, 1) * np.abs(m).max()
+    rems = [abs(og.misfit(m + e * v, sv, d_obs, 0.0) - J - e * float(np.sum(g * v))) for e in (4e-3, 2e-3, 1e-3)]
+    assert 3.5 < rems[0] / rems[1] < 4.5 and 3.5 < rems[1] / rems[2] < 4.5, rems
+    eps = 1e-5
+    fd = (og.data(m + eps * v, sv) - og.data(m - eps * v, sv)) / (2 * eps)
+    gb = og.born(m, sv, v)
+    assert np.linalg.norm(fd - gb) <= 1e-6 * np.linalg.norm(gb)
