@@ -94,3 +94,27 @@ def test_footprint_grows_with_the_work():
     # about 11 fine complex vectors per right-hand side dominate
     assert 11 * 16 * 257 * 257 * 8 <= f8 <= 20 * 16 * 257 * 257 * 8
     assert hz.footprint((257, 257), 1, 8, krylov="gmres", gmres_m=30) > f8 + 30 * 16 * 257 * 257 * 8
+
+
+def test_every_context_call_refuses_a_null_context():
+    """Each call that takes a context returns HZ_ERR_ARG for NULL (host-side
+    check; zero sizes and NULL pointers everywhere else, no device work)."""
+    import paper_1712_08743_amd as hz
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    lib = ctypes.CDLL(LIB)
+    calls = re.findall(r"^\s*int\s+(hz_\w+)\s*\(\s*(?:const\s+)?hz_ctx\s*\*\s*\w+([^;]*)\);", text, flags=re.M | re.S)
+    assert len(calls) >= 19
+    for name, rest in calls:
+        argtypes, args = [ctypes.c_void_p], [None]
+        for p in (q.strip() for q in rest.split(",") if q.strip()):
+            if "*" in p:
+                argtypes.append(ctypes.c_void_p); args.append(None)
+            elif p.startswith("double"):
+                argtypes.append(ctypes.c_double); args.append(0.0)
+            elif p.startswith("unsigned"):
+                argtypes.append(ctypes.c_uint); args.append(0)
+            else:
+                argtypes.append(ctypes.c_int); args.append(0)
+        f = getattr(lib, name)
+        f.argtypes, f.restype = argtypes, ctypes.c_int
+        assert f(*args) == hz.HZ_ERR_ARG, name
