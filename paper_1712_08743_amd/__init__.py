@@ -560,6 +560,7 @@ class Misfit:
     gradient (Eq. (7)) computed by the library (forward and adjoint solves on
     the GPU). The gradient is formed together with J in the forward call,
     where the forward wavefields are at hand, and kept for the backward pass.
+    A 3D slowness tensor takes (iz, iy, ix) sources and receivers.
     """
 
     def __init__(self, ctx, freqs, alpha, src, rec, d_obs, lam, **opt):
@@ -573,8 +574,9 @@ class Misfit:
             @staticmethod
             def forward(fctx, m):
                 outer.ctx.set_model(m.detach(), outer.ctx.h)
-                J, grad, info = outer.ctx.gradient(outer.freqs, outer.alpha, outer.src, outer.rec,
-                                                   outer.d_obs, outer.lam, **outer.opt)
+                grad_call = outer.ctx.gradient_3d if m.dim() == 3 else outer.ctx.gradient
+                J, grad, info = grad_call(outer.freqs, outer.alpha, outer.src, outer.rec,
+                                          outer.d_obs, outer.lam, **outer.opt)
                 outer.last_info = info
                 fctx.save_for_backward(grad)
                 return torch.tensor(J, dtype=torch.float64, device=m.device)
