@@ -474,8 +474,8 @@ def bench_3d(args):
     n1 = int(np.prod(ctx.level_shape(1)))
     z = 16
     # algorithmic bytes per right-hand side and iteration of the finest-level classes (two V-cycles;
-    # the first pre-sweep, from zero, and the p and s updates are not timed)
-    cb = {"smooth": 2 * 2 * 3 * n0 * z,              # the second pre-sweep and the last post-sweep: b, u / u
+    # the p and s updates are not timed)
+    cb = {"smooth": 2 * (2 + 3) * n0 * z,            # both pre-sweeps from zero: b / u; the last post-sweep: b, u / u
           "restrict": 2 * (2 * n0 * z + n1 * z),     # b, u / coarse b
           "prolong": 2 * (3 * n0 * z + n1 * z),      # coarse e, b, u / u (with one post-sweep)
           "apply": 2 * n0 * z,                       # p^ / v

@@ -641,7 +641,14 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       bl = bc;
       continue;
     }
-    if (cy.nu1 == 2 && dim == 1) {
+    if (cy.nu1 == 2 && dim == 3) {
+      // both pre-sweeps from zero in one marching pass
+      if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : HZ_KERNEL_LEVELS, [&] {
+             return launch_march3(g, l, bt, cap, true, bl, nullptr, X, nl, st);
+           })) != hipSuccess)
+        return e;
+      u = X;
+    } else if (cy.nu1 == 2 && dim == 1) {
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
       if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : HZ_KERNEL_LEVELS, [&] {

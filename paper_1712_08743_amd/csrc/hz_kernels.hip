@@ -764,9 +764,13 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
 // wavefronts (tile order puts neighbouring rows in one block), read from
 // cache. Written in the Jacobi form (1 - w) u + (w/D)(b + (fz sz + fy sy +
 // fx sx) / h^2), so the slowness is not read.
+// FROM_ZERO: the two sweeps from u = 0 in one pass. The first gives
+// u1 = (w/D) b, formed wherever the march reads u (u_in is not read), and the
+// pass stores the second sweep from u1.
 constexpr int kMarchW = 62;
 constexpr int kMarchZ = 16;  // even: the march takes two planes per step
 
+template <bool FROM_ZERO>
 __global__ void __launch_bounds__(kBlock) k_smooth3m(Grid g, int nstrip, int nchunk, int groups, int lvl, Batch bt,
                                                      const double2* __restrict__ b,
                                                      const double2* __restrict__ u_in,
@@ -790,14 +794,16 @@ __global__ void __launch_bounds__(kBlock) k_smooth3m(Grid g, int nstrip, int nch
   const double omw = 1.0 - f.wj[lvl];
   const double ih2 = 1.0 / (g.h * g.h);
   const size_t base = (size_t)slot * stride;
-  const double2* us = u_in + base;
+  const double2* us = FROM_ZERO ? nullptr : u_in + base;
   const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
   const double wy = (iy == 0 || iy == g.ny - 1) ? 0.5 : 1.0, wx = (x == 0 || x == g.nx - 1) ? 0.5 : 1.0;
   const double2 zero = c2(0.0, 0.0);
   // node (z, iy, xx); z inside the grid
   auto at = [&](int z) { return (size_t)z * sz + (size_t)iy * sy + xx; };
+  // the iterate the sweep starts from at node q
+  auto uval = [&](size_t q) { return FROM_ZERO ? cmul(b[base + q], wd[q]) : us[q]; };
   // u on plane z of the wavefront's row, zero outside the grid
-  auto plane = [&](int z) { return (z >= 0 && z < g.nz) ? keep(xin, us[at(z)]) : zero; };
+  auto plane = [&](int z) { return (z >= 0 && z < g.nz) ? keep(xin, uval(at(z))) : zero; };
   struct Row {  // loads for output plane z: u on z + 1, the y-neighbours on z, b, w/D
     double2 uc, ul, ur, bz, wdz;
   };
@@ -806,8 +812,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth3m(Grid g, int nstrip, int nch
     r.uc = plane(z + 1);
     const int zc = min(z, g.nz - 1);  // the second plane of a step may be past the grid (not stored)
     const size_t q = at(zc);
-    r.ul = iy > 0 ? us[q - sy] : zero;
-    r.ur = iy < g.ny - 1 ? us[q + sy] : zero;
+    r.ul = iy > 0 ? uval(q - sy) : zero;
+    r.ur = iy < g.ny - 1 ? uval(q + sy) : zero;
     r.bz = b[base + q];
     r.wdz = wd[q];
     return r;
@@ -824,13 +830,48 @@ __global__ void __launch_bounds__(kBlock) k_smooth3m(Grid g, int nstrip, int nch
         c2(omw * ub.x + (r.wdz.x * tx - r.wdz.y * ty), omw * ub.y + (r.wdz.x * ty + r.wdz.y * tx));
     if (own && z < z1) u_out[base + at(z)] = out;
   };
-  double2 ua = plane(z0 - 1), ub = plane(z0);
-  for (int z = z0; z < z1; z += 2) {
-    const Row r0 = load(z), r1 = load(z + 1);
-    step(z, r0, ua, ub);
-    step(z + 1, r1, ub, r0.uc);
-    ua = r0.uc;
-    ub = r1.uc;
+  if constexpr (FROM_ZERO) {
+    // b and w/D of the centre plane were loaded a step earlier, as the plane above
+    auto raw = [&](int z, double2& bq, double2& wq) {
+      const bool in = z >= 0 && z < g.nz;
+      const size_t q = at(in ? z : 0);
+      bq = in ? b[base + q] : zero;
+      wq = in ? wd[q] : zero;
+    };
+    auto yrow = [&](int z, Row& r) {
+      const size_t q = at(min(z, g.nz - 1));
+      r.ul = iy > 0 ? uval(q - sy) : zero;
+      r.ur = iy < g.ny - 1 ? uval(q + sy) : zero;
+    };
+    double2 bq, wq;
+    raw(z0 - 1, bq, wq);
+    double2 ua = keep(xin, cmul(bq, wq));
+    raw(z0, bq, wq);
+    double2 ub = keep(xin, cmul(bq, wq));
+    for (int z = z0; z < z1; z += 2) {
+      Row r0, r1;
+      r0.bz = bq;
+      r0.wdz = wq;
+      raw(z + 1, r1.bz, r1.wdz);
+      raw(z + 2, bq, wq);
+      yrow(z, r0);
+      yrow(z + 1, r1);
+      r0.uc = keep(xin, cmul(r1.bz, r1.wdz));
+      r1.uc = keep(xin, cmul(bq, wq));
+      step(z, r0, ua, ub);
+      step(z + 1, r1, ub, r0.uc);
+      ua = r0.uc;
+      ub = r1.uc;
+    }
+  } else {
+    double2 ua = plane(z0 - 1), ub = plane(z0);
+    for (int z = z0; z < z1; z += 2) {
+      const Row r0 = load(z), r1 = load(z + 1);
+      step(z, r0, ua, ub);
+      step(z + 1, r1, ub, r0.uc);
+      ua = r0.uc;
+      ub = r1.uc;
+    }
   }
 }
 
@@ -1023,17 +1064,26 @@ hipError_t launch_apply(int dim, const Grid& g, int lvl, int which, const Batch&
   return hipGetLastError();
 }
 
+// the marching 3D sweep (from u_in, or both sweeps from zero)
+hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool from_zero, const double2* b,
+                         const double2* u_in, double2* u_out, size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int nstrip = (g.nx + kMarchW - 1) / kMarchW, nchunk = (g.nz + kMarchZ - 1) / kMarchZ;
+  const int groups = (g.ny * nstrip * nchunk + 3) / 4;
+  if (from_zero)
+    hipLaunchKernelGGL(k_smooth3m<true>, grid1(tile_blocks(groups, cap)), dim3(kBlock), 0, st, g, nstrip, nchunk,
+                       groups, lvl, bt, b, u_in, u_out, stride);
+  else
+    hipLaunchKernelGGL(k_smooth3m<false>, grid1(tile_blocks(groups, cap)), dim3(kBlock), 0, st, g, nstrip, nchunk,
+                       groups, lvl, bt, b, u_in, u_out, stride);
+  return hipGetLastError();
+}
+
 hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, const Batch& bt,
                          int cap, const double2* b, const double2* u_in, double2* u_out,
                          size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
-  if (dim == 3 && u_in && w_override <= 0.0) {
-    const int nstrip = (g.nx + kMarchW - 1) / kMarchW, nchunk = (g.nz + kMarchZ - 1) / kMarchZ;
-    const int groups = (g.ny * nstrip * nchunk + 3) / 4;
-    hipLaunchKernelGGL(k_smooth3m, grid1(tile_blocks(groups, cap)), dim3(kBlock), 0, st, g, nstrip, nchunk, groups,
-                       lvl, bt, b, u_in, u_out, stride);
-    return hipGetLastError();
-  }
+  if (dim == 3 && u_in && w_override <= 0.0) return launch_march3(g, lvl, bt, cap, false, b, u_in, u_out, stride, st);
   if (dim == 3) {
     const Tiles t = tiles3(g);
     const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
