@@ -947,22 +947,28 @@ __global__ void __launch_bounds__(kBlock) k_restrict_r3(Grid gf, Grid gc, Tiles 
   size_t P;
   if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, gc, Iz, Iy, Ix, P)) return;
   const double2* rs = r + (size_t)slot * sf;
-  double2 acc = c2(0.0, 0.0);
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int iz = 2 * Iz + dz;
-    if (iz < 0 || iz >= gf.nz) continue;
-    const double wz = pt_weight(dz, Iz, gf.nz);
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int iy = 2 * Iy + dy;
-      if (iy < 0 || iy >= gf.ny) continue;
-      const double wzy = wz * pt_weight(dy, Iy, gf.ny);
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int ix = 2 * Ix + dx;
-        if (ix < 0 || ix >= gf.nx) continue;
-        acc = cadd(acc, cscale(wzy * pt_weight(dx, Ix, gf.nx), rs[((size_t)iz * gf.ny + iy) * gf.nx + ix]));
-      }
-    }
+  // offsets past the grid read the centre fine node (2I, always inside) with weight zero, so
+  // the 27 loads carry no branches and are all issued before the sum
+  int zi[3], yi[3], xi[3];
+  double wz[3], wy[3], wx[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int iz = 2 * Iz + d - 1, iy = 2 * Iy + d - 1, ix = 2 * Ix + d - 1;
+    const bool inz = iz >= 0 && iz < gf.nz, iny = iy >= 0 && iy < gf.ny, inx = ix >= 0 && ix < gf.nx;
+    zi[d] = inz ? iz : 2 * Iz;
+    yi[d] = iny ? iy : 2 * Iy;
+    xi[d] = inx ? ix : 2 * Ix;
+    wz[d] = inz ? pt_weight(d - 1, Iz, gf.nz) : 0.0;
+    wy[d] = iny ? pt_weight(d - 1, Iy, gf.ny) : 0.0;
+    wx[d] = inx ? pt_weight(d - 1, Ix, gf.nx) : 0.0;
   }
+  double2 v[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k)
+    v[k] = rs[((size_t)zi[k / 9] * gf.ny + yi[(k / 3) % 3]) * gf.nx + xi[k % 3]];
+  double2 acc = c2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 27; ++k) acc = cadd(acc, cscale(wz[k / 9] * wy[(k / 3) % 3] * wx[k % 3], v[k]));
   bc[(size_t)slot * sc + P] = cscale(0.125, acc);
 }
 
