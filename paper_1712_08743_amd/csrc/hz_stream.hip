@@ -114,7 +114,6 @@ __device__ __forceinline__ bool wave_tile(const Batch& bt, int nstrip, int nchun
 // x-radius to 4, so those strips store 56 columns.
 constexpr int pre_radius(int mode) { return mode >= 4 ? 4 : 3; }
 constexpr int pre_width(int mode) { return kLanes - 2 * pre_radius(mode); }
-constexpr int kPreWidth = pre_width(0);
 
 template <int MODE>
 struct PreRow {  // loads of one row: the right-hand side's inputs, w/D and m (MODE 4, 5: c is p^ on the next row)
