@@ -494,6 +494,26 @@ def bench_3d(args):
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                 "launches": timing[dom][0], "avg_launch_ms": timing[dom][1] / max(timing[dom][0], 1)}
     levels = [ctx.plan(f)[0] for f in w.freqs]
+    # the adjoint-state gradient (Eq. (7)) on the same box: observed data from the library's own
+    # solves on the layered model at tolerance 1e-12, the gradient at a second seed's model
+    rec = [(0, y, x) for y in range(0, 129, 8) for x in range(0, 129, 8)]
+    _, d_obs, _ = ctx.misfit_3d(w.freqs, w.alpha, w.src, rec,
+                                torch.zeros((len(w.freqs), len(w.src), len(rec)), dtype=torch.complex128), 0.0,
+                                tol=1e-12)
+    start = workloads.model_3d_layered(129, 129, 129, h=20.0, nshots=8, freqs=(3.0, 5.0), seed=3)
+    ctx.set_model(torch.from_numpy(start.m).cuda(), w.h)
+    print("# 3d: warm-up gradient", file=sys.stderr, flush=True)
+    ctx.gradient_3d(w.freqs, w.alpha, w.src, rec, d_obs, 1e-3, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, ginfo = ctx.gradient_3d(w.freqs, w.alpha, w.src, rec, d_obs, 1e-3, tol=tol)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    print(f"# 3d: gradient {t_grad:.3f} s ({len(ginfo)} solves)", file=sys.stderr, flush=True)
+    gradient = {"seconds": t_grad, "solves": len(ginfo), "solves_per_s": len(ginfo) / t_grad,
+                "converged": sum(1 for i in ginfo if i[0] == hz.HZ_RHS_CONVERGED),
+                "receivers": len(rec), "lambda": 1e-3,
+                "note": "forward and adjoint batch of 8 shots x 2 frequencies, data from the library at 1e-12"}
     ctx.close()
     cpu = None
     if not args.no_cpu_baseline:
@@ -514,6 +534,7 @@ def bench_3d(args):
         "kernel_breakdown": breakdown,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "gradient": gradient,
     }
     print(json.dumps(out), flush=True)
 
