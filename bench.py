@@ -17,7 +17,7 @@ Prints one JSON line (see the field list at the end of main()).
                                          # for scaling rocprofv3 byte counters
   python bench.py --compare       # preconditioned vs not, shifts, GMRES vs BiCGSTAB,
                                   # Gauss-Newton schedules (a report, not a throughput line)
-  python bench.py --3d            # batched solves on a 3D box (129^3, 16 right-hand sides; a report line)
+  python bench.py --3d            # batched solves on a 3D box (129^3, 16 right-hand sides) and its gradient; a report line
   python bench.py --fwi           # gradient and Gauss-Newton step on the full inversion survey
                                   # (301 x 601, 32 shots x 6 frequencies; a report line)
   python bench.py --serving [--requests R] [--slots S]
