@@ -102,37 +102,85 @@ def percentile(vals, q):
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
 
 
-def cpu_baseline(w, iters_per_freq, sample_iters=48, shot=31):
-    """Time the oracle (plain FP64 CPU: SciPy sparse matrices, BiCGSTAB, V-cycle)
-    on a bounded sample: one shot per frequency, capped at sample_iters
-    BiCGSTAB iterations after its setup. Scaled to the full 256-right-hand-side
-    step with the oracle's own iteration counts to convergence."""
+def _cpu_sample_worker(args):
+    """One process of the CPU baseline: the oracle's set-up of B and the
+    V-cycle for one frequency (the library's default plan: LFA levels and
+    weights, coarse="auto"), then sample_iters BiCGSTAB iterations on one
+    shot. Returns (freq, setup seconds, seconds per iteration)."""
+    f, shot, sample_iters = args
     import numpy as np
+    import workloads
     from oracle import operator as op, multigrid as mg, krylov, lfa
+    w = workloads.model_2d_layered()
+    om = 2 * np.pi * f
+    t0 = time.perf_counter()
+    B = op.operator_B(w.m, w.h, om, w.alpha)
+    L, wj = lfa.plan(w.shape, w.h, om, w.m.min(), w.m.max(), 1.0, 0.5)
+    V = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
+    t_setup = time.perf_counter() - t0
+    b = op.point_source(w.shape, w.h, [w.src[shot]])
+    t0 = time.perf_counter()
+    _, it, _, _ = krylov.bicgstab(B, b, V, tol=1e-30, maxit=sample_iters)
+    return f, t_setup, (time.perf_counter() - t0) / it
+
+
+def host_cores():
+    """Cores this process may run on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(w, iters_per_freq, sample_iters=24):
+    """Time the oracle (plain FP64 CPU: SciPy sparse matrices, BiCGSTAB, the
+    V-cycle with the GPU's plan and coarse policy) with one process per host
+    core and one BLAS thread each. All processes run at once (so the memory
+    bandwidth they share is part of the measurement): process k takes
+    frequency k mod 4 and a shot of its own, sets up the oracle's operator
+    and V-cycle and runs sample_iters BiCGSTAB iterations. The full step is
+    then P cores sharing 64 shots x the oracle's own iteration counts to
+    convergence per frequency, each core also paying every frequency's
+    set-up: wall = (sum_f 64 its_f t_f + P sum_f setup_f) / P."""
+    import multiprocessing as mp
+    import numpy as np
+    P = host_cores()
+    shots = [(k * 7 + 3) % len(w.src) for k in range(P)]
+    jobs = [(float(w.freqs[k % len(w.freqs)]), shots[k], sample_iters) for k in range(P)]
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(P) as pool:
+            res = pool.map(_cpu_sample_worker, jobs, chunksize=1)
+        sample_s = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     per_freq = {}
-    total = 0.0
-    t_all = time.perf_counter()
+    work = 0.0
+    setup_all = 0.0
     for f in w.freqs:
-        om = 2 * np.pi * f
-        t0 = time.perf_counter()
-        B = op.operator_B(w.m, w.h, om, w.alpha)
-        L, wj = lfa.plan(w.shape, w.h, om, w.m.min(), w.m.max(), 1.0, 0.5)
-        V = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj)
-        t_setup = time.perf_counter() - t0
-        b = op.point_source(w.shape, w.h, [w.src[shot]])
-        t0 = time.perf_counter()
-        _, it, _, _ = krylov.bicgstab(B, b, V, tol=1e-30, maxit=sample_iters)
-        t_it = (time.perf_counter() - t0) / it
+        rs = [r for r in res if r[0] == float(f)]
+        t_setup = float(np.mean([r[1] for r in rs]))
+        t_it = float(np.mean([r[2] for r in rs]))
         n_it = iters_per_freq[str(f)]
-        per_freq[str(f)] = {"setup_s": t_setup, "s_per_iteration": t_it, "iterations": n_it}
-        total += t_setup + len(w.src) * n_it * t_it
-    sample_s = time.perf_counter() - t_all
+        per_freq[str(f)] = {"setup_s": t_setup, "s_per_iteration": t_it, "iterations": n_it, "processes": len(rs)}
+        work += len(w.src) * n_it * t_it
+        setup_all += t_setup
+    wall = (work + P * setup_all) / P
     nrhs = len(w.src) * len(w.freqs)
-    return {"value": nrhs / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"shot {shot} at each of {len(w.freqs)} frequencies, oracle setup plus "
-                       f"{sample_iters} BiCGSTAB iterations each ({sample_s:.1f} s of CPU); scaled to "
-                       f"{len(w.src)} shots x the oracle's mean iterations to 1e-8 "
-                       "(tests/golden/c3_oracle_iterations.json)"),
+    return {"value": nrhs / wall, "unit": "solves/s", "cores": P, "kind": "oracle",
+            "sample": (f"{P} processes at once (one per core, 1 BLAS thread each), each the oracle's set-up for one "
+                       f"of the {len(w.freqs)} frequencies plus {sample_iters} BiCGSTAB iterations on its own shot "
+                       f"({sample_s:.1f} s wall); scaled to {len(w.src)} shots x the oracle's mean iterations to "
+                       "1e-8 per frequency (tests/golden/c3_oracle_iterations.json) shared by the "
+                       f"{P} cores, each paying every frequency's set-up"),
             "host_cpus": os.cpu_count(), "per_freq": per_freq}
 
 
@@ -574,21 +622,24 @@ def cpu_baseline_3d(w, iters_per_freq, nshot, sample_iters=3):
             "host_cpus": os.cpu_count(), "per_freq": per_freq}
 
 
-def one_rhs_per_launch(ctx, w, b1, tol, shot=31):
-    """The plain path: one right-hand side per solve call (shot ``shot`` at
-    every frequency of the workload); solves/s averaged over the frequencies,
-    as in the batch."""
+def one_rhs_per_call(ctx, w, b1, tol, shot=31, plain=False):
+    """One right-hand side per solve call (shot ``shot`` at every frequency of
+    the workload); solves/s over the four solves and their mean iterations.
+    plain=False: the library's batched path called with a batch of one;
+    plain=True: the plain per-launch path (every step of the iteration a
+    kernel of its own, scalars read back by the host every iteration)."""
     import torch
-    secs = []
+    secs, its = [], []
     for f in w.freqs:
         bb = b1[shot:shot + 1].reshape((1, 1) + tuple(b1.shape[1:])).contiguous()
-        ctx.solve([f], w.alpha, bb, tol=tol)  # warm
+        ctx.solve([f], w.alpha, bb, tol=tol, plain=plain)  # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.solve([f], w.alpha, bb, tol=tol)
+        _, info = ctx.solve([f], w.alpha, bb, tol=tol, plain=plain)
         torch.cuda.synchronize()
         secs.append(time.perf_counter() - t0)
-    return len(secs) / sum(secs)
+        its.append(info[0][1])
+    return len(secs) / sum(secs), its
 
 
 def main():
@@ -734,10 +785,18 @@ def main():
                 "launches": n_dom, "avg_launch_ms": ms_dom / max(n_dom, 1),
                 "algorithmic_bytes_per_launch": dom_bytes / max(n_dom, 1), "rhs_per_launch": rhs_per_launch}
 
-    single = None
+    single = plain = None
     if not args.no_single_rhs and args.maxit >= 10000:
-        print("# timing the one-right-hand-side-per-call path", file=sys.stderr, flush=True)
-        single = one_rhs_per_launch(ctx, w, b1, tol)
+        print("# timing one right-hand side per call (batched library, then the plain path)", file=sys.stderr,
+              flush=True)
+        rate, its = one_rhs_per_call(ctx, w, b1, tol)
+        single = {"solves_per_s": rate, "iterations": its, "speedup": (nrhs / sec) / rate}
+        rate, its = one_rhs_per_call(ctx, w, b1, tol, plain=True)
+        plain = {"solves_per_s": rate, "iterations": its, "speedup": (nrhs / sec) / rate,
+                 "what": "one right-hand side per call, every step of the iteration a kernel of its own "
+                         "(single smoothing sweeps, residual and restriction, prolongation, operator apply, "
+                         "vector updates), dense shadow residual, the host reading every iteration's scalars "
+                         "back before it issues the next"}
 
     cpu = cpu_lu = None
     if not args.no_cpu_baseline:
@@ -775,7 +834,8 @@ def main():
                          "frequencies run at the same time, so these rates do not add up to value)",
         "hbm_gbps_step_model": step_bytes / sec / 1e9,
         "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
-        "one_rhs_per_call": None if single is None else {"solves_per_s": single, "speedup": (nrhs / sec) / single},
+        "single_rhs_batched_library": single,
+        "plain_per_launch": plain,
         "roofline": roofline,
         "kernel_breakdown": breakdown,
         "cpu_baseline": cpu,

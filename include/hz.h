@@ -53,7 +53,11 @@ typedef struct hz_ctx hz_ctx;
 #define HZ_OK            0
 #define HZ_WARN_NOCONV   1   /* output written; some right-hand side did not converge */
 #define HZ_ERR_ARG      -1   /* null pointer, bad size or value, non-finite or non-positive slowness */
-#define HZ_ERR_SHAPE    -2   /* grid cannot be coarsened to the requested level count */
+#define HZ_ERR_SHAPE    -2   /* grid cannot be coarsened to the requested level count, or the
+                                coarsest level is solved exactly and has more than
+                                HZ_COARSE_MAX unknowns */
+#define HZ_COARSE_MAX 4096   /* most unknowns of an exactly solved coarsest level (its dense
+                                inverse costs n^3 work and 16 n^2 bytes per frequency) */
 #define HZ_ERR_NOMEM    -3   /* device allocation failed or workspace budget exceeded */
 #define HZ_ERR_DEVICE   -4   /* a HIP runtime error */
 #define HZ_ERR_STATE    -5   /* no model set */
@@ -116,6 +120,14 @@ typedef struct {
     int    restart_at;      /* for tests of the breakdown path: > 0 makes every BiCGSTAB
                                right-hand side take the one restart (r^ = r, p = v = 0) after
                                this many iterations, as after a breakdown; 0 (default): off */
+    int    plain;           /* 1: the plain per-launch path, kept as a point of comparison:
+                               every step of the iteration is a kernel of its own (single
+                               smoothing sweeps, residual and restriction, prolongation, operator
+                               apply and vector updates), the shadow residual is a dense vector,
+                               the iterate is advanced every iteration, and the host reads each
+                               iteration's scalars back before it issues the next. Same
+                               iteration, results agree to rounding. 0 (default): the fused
+                               batched path. */
 } hz_solve_opts;
 
 typedef struct {
@@ -263,7 +275,8 @@ int  hz_gn_step_3d(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *f
  * largest weight in {0.8,...,0.2} not above o->jacobi_w whose local-Fourier
  * smoothing factor stays <= 1 over the level's kh range.
  * Errors: HZ_ERR_STATE (no model), HZ_ERR_SHAPE (o->levels above what the
- * grid allows: halving while every axis keeps >= 3 nodes). */
+ * grid allows: halving while every axis keeps >= 3 nodes; or a coarsest level
+ * solved exactly at this frequency with more than HZ_COARSE_MAX unknowns). */
 int  hz_plan(const hz_ctx *c, const hz_solve_opts *o, double freq_hz,
              int *levels, double *w);
 

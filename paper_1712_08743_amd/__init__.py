@@ -49,7 +49,7 @@ class SolveOpts(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("jacobi_w", ctypes.c_double),
                 ("jacobi_w_level", ctypes.POINTER(ctypes.c_double)), ("autotune", ctypes.c_int),
                 ("chunk_rows", ctypes.c_int), ("coarse", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
-                ("graphs", ctypes.c_int), ("restart_at", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("restart_at", ctypes.c_int), ("plain", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -131,7 +131,7 @@ def default_opts():
 
 def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg", beta=(1.0, 0.5),
               levels=0, nu=(2, 2), jacobi_w=0.8, jacobi_w_level=None, autotune=True, chunk_rows=0,
-              graphs=False, coarse="auto", coarse_sweeps=2, restart_at=0):
+              graphs=False, coarse="auto", coarse_sweeps=2, restart_at=0, plain=False):
     """Build an hz_solve_opts; returns (opts, keepalive)."""
     o = default_opts()
     o.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
@@ -147,6 +147,7 @@ def make_opts(krylov="bicgstab", gmres_m=30, tol=1e-8, maxit=10000, precond="mg"
     o.chunk_rows = int(chunk_rows)
     o.graphs = 1 if graphs else 0
     o.restart_at = int(restart_at)
+    o.plain = 1 if plain else 0
     o.coarse = COARSE[coarse] if isinstance(coarse, str) else int(coarse)
     o.coarse_sweeps = int(coarse_sweeps)
     keep = None
@@ -558,38 +559,69 @@ class Misfit:
     ``Misfit(ctx, freqs, alpha, src, rec, d_obs, lam)(m)`` returns a 0-d
     float64 tensor; its backward pass returns dJ/dm from the adjoint-state
     gradient (Eq. (7)) computed by the library (forward and adjoint solves on
-    the GPU). The gradient is formed together with J in the forward call,
-    where the forward wavefields are at hand, and kept for the backward pass.
-    A 3D slowness tensor takes (iz, iy, ix) sources and receivers.
+    the GPU). When autograd will need the gradient (``m.requires_grad`` under
+    grad mode) the forward call forms it together with J, where the forward
+    wavefields are at hand; otherwise (a line search, ``torch.no_grad()``)
+    the forward call runs the forward solves alone. With ``lazy=True`` the
+    forward call always computes J alone and the backward pass computes the
+    gradient, solving the forward problems again (nothing is kept between
+    the two passes). A 3D slowness tensor takes (iz, iy, ix) sources and
+    receivers.
     """
 
-    def __init__(self, ctx, freqs, alpha, src, rec, d_obs, lam, **opt):
+    def __init__(self, ctx, freqs, alpha, src, rec, d_obs, lam, lazy=False, **opt):
         import torch
         self.ctx, self.freqs, self.alpha = ctx, list(freqs), float(alpha)
         self.src, self.rec, self.d_obs, self.lam, self.opt = src, rec, d_obs, float(lam), opt
+        self.lazy = bool(lazy)
         self.last_info = None
+        self.calls = {"misfit": 0, "gradient": 0}
         outer = self
+
+        def gradient(m):
+            outer.ctx.set_model(m, outer.ctx.h)
+            call = outer.ctx.gradient_3d if m.dim() == 3 else outer.ctx.gradient
+            outer.calls["gradient"] += 1
+            J, grad, info = call(outer.freqs, outer.alpha, outer.src, outer.rec, outer.d_obs, outer.lam, **outer.opt)
+            outer.last_info = info
+            return J, grad
 
         class _Fn(torch.autograd.Function):
             @staticmethod
             def forward(fctx, m):
-                outer.ctx.set_model(m.detach(), outer.ctx.h)
-                grad_call = outer.ctx.gradient_3d if m.dim() == 3 else outer.ctx.gradient
-                J, grad, info = grad_call(outer.freqs, outer.alpha, outer.src, outer.rec,
-                                          outer.d_obs, outer.lam, **outer.opt)
-                outer.last_info = info
-                fctx.save_for_backward(grad)
+                m = m.detach()
+                if outer._need_grad and not outer.lazy:
+                    J, grad = gradient(m)
+                    fctx.save_for_backward(grad)
+                    fctx.grad_ready = True
+                else:
+                    outer.ctx.set_model(m, outer.ctx.h)
+                    call = outer.ctx.misfit_3d if m.dim() == 3 else outer.ctx.misfit
+                    outer.calls["misfit"] += 1
+                    J, _, info = call(outer.freqs, outer.alpha, outer.src, outer.rec, outer.d_obs, outer.lam,
+                                      **outer.opt)
+                    outer.last_info = info
+                    fctx.save_for_backward(m)
+                    fctx.grad_ready = False
                 return torch.tensor(J, dtype=torch.float64, device=m.device)
 
             @staticmethod
             def backward(fctx, gJ):
-                (grad,) = fctx.saved_tensors
+                (saved,) = fctx.saved_tensors
+                grad = saved if fctx.grad_ready else gradient(saved)[1]
                 return gJ * grad
 
         self._fn = _Fn
 
     def __call__(self, m):
+        # forward() runs with grad mode off: decide here whether autograd will ask for dJ/dm
+        self._need_grad = bool(self.torch_grad_enabled() and m.requires_grad)
         return self._fn.apply(m)
+
+    @staticmethod
+    def torch_grad_enabled():
+        import torch
+        return torch.is_grad_enabled()
 
 
 def exported_symbols():

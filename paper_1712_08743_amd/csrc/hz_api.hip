@@ -241,10 +241,33 @@ int grid_default_levels3(int nz, int ny, int nx) {
 
 namespace {
 
-int plan_grid(int dim, int maxlev, int deflev, double h, double mmin, double mmax, const hz_solve_opts* o,
-              double omega, int* levels, double* w) {
+// Whether the V-cycle of L levels solves its coarsest level exactly at this
+// frequency (as setup_freqs decides), and how many unknowns that level has.
+bool coarse_is_exact(const hz_solve_opts* o, int L, double hc, double mmin, double omega) {
+  if (o->precond != HZ_PRECOND_MG) return false;
+  if (L == 1 || o->coarse == HZ_COARSE_EXACT) return true;
+  return o->coarse == HZ_COARSE_AUTO && !(omega * hc * mmin >= 2.5);
+}
+
+size_t coarsest_nodes(int dim, int nz, int ny, int nx, int L) {
+  for (int l = 1; l < L; ++l) {
+    nx = coarse_n(nx);
+    if (dim >= 2) nz = coarse_n(nz);
+    if (dim == 3) ny = coarse_n(ny);
+  }
+  return (size_t)nx * (dim >= 2 ? nz : 1) * (dim == 3 ? ny : 1);
+}
+
+// The level count and per-level Jacobi weights for one frequency; refuses
+// (HZ_ERR_SHAPE) a plan whose coarsest level is solved exactly and holds
+// more than kCoarseMax unknowns.
+int plan_grid(int dim, int nz, int ny, int nx, int maxlev, int deflev, double h, double mmin, double mmax,
+              const hz_solve_opts* o, double omega, int* levels, double* w) {
   int L = o->levels > 0 ? o->levels : deflev;
   if (L > maxlev) return HZ_ERR_SHAPE;
+  if (coarse_is_exact(o, L, h * ldexp(1.0, L - 1), mmin, omega) &&
+      coarsest_nodes(dim, nz, ny, nx, L) > (size_t)kCoarseMax)
+    return HZ_ERR_SHAPE;
   *levels = L;
   for (int l = 0; l < L - 1; ++l) {
     if (o->jacobi_w_level) {
@@ -280,7 +303,8 @@ int default_levels_of(const hz_ctx* c) {
 }
 
 int make_plan(const hz_ctx* c, const hz_solve_opts* o, double omega, int* levels, double* w) {
-  return plan_grid(c->dim, c->maxlev, default_levels_of(c), c->h, c->mmin, c->mmax, o, omega, levels, w);
+  return plan_grid(c->dim, c->nz, c->ny, c->nx, c->maxlev, default_levels_of(c), c->h, c->mmin, c->mmax, o, omega,
+                   levels, w);
 }
 
 int check_opts(hz_ctx* c, const hz_solve_opts* o) {
@@ -313,6 +337,7 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
   if (o->autotune != 0 && o->autotune != 1) return fail(c, HZ_ERR_ARG, "autotune must be 0 or 1");
   if (o->graphs != 0 && o->graphs != 1) return fail(c, HZ_ERR_ARG, "graphs must be 0 or 1");
   if (o->restart_at < 0) return fail(c, HZ_ERR_ARG, "restart_at must be >= 0");
+  if (o->plain != 0 && o->plain != 1) return fail(c, HZ_ERR_ARG, "plain must be 0 or 1");
   if (o->coarse < HZ_COARSE_AUTO || o->coarse > HZ_COARSE_JACOBI) return fail(c, HZ_ERR_ARG, "unknown coarse solve");
   if (o->coarse_sweeps < 1 || o->coarse_sweeps > 64) return fail(c, HZ_ERR_ARG, "coarse_sweeps must be in [1, 64]");
   if (o->precond == HZ_PRECOND_EXACT) {
@@ -446,7 +471,10 @@ int setup_freqs(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq
       c->any_coarse_jacobi = c->any_coarse_jacobi || jac;
     }
   }
-  if (need_coarse) {
+  // the dense inverse is needed unless every frequency smooths its coarsest level
+  bool need_inverse = false;
+  for (int f = 0; f < nfreq; ++f) need_inverse = need_inverse || !(levels > 1 && ft[f].coarse_jacobi);
+  if (need_coarse && need_inverse) {
     const int cl = levels - 1;
     const size_t nc = c->lv[cl].n();
     if (nc > (size_t)kCoarseMax)
@@ -525,6 +553,7 @@ struct Cycle {
   int levels, nu1, nu2, precond;
   int autotune, chunk_rows;  // launch shape of the fused kernels (opts.autotune, opts.chunk_rows)
   int coarse_sweeps;         // > 0: some frequency smooths its coarsest level with this many sweeps
+  int plain;                 // opts.plain: one kernel per step, no fused V-cycle kernels
 };
 
 // ---------------------------------------------------------------- launch-shape tuning
@@ -594,7 +623,9 @@ struct FineRhs {
   double2* out;
 };
 
-bool fused_pre(const Cycle& cy) { return cy.precond == HZ_PRECOND_MG && cy.levels >= 2 && cy.nu1 == 2; }
+bool fused_pre(const Cycle& cy) {
+  return cy.precond == HZ_PRECOND_MG && cy.levels >= 2 && cy.nu1 == 2 && !cy.plain;
+}
 
 // out = V b on the finest grid for the slots of the active list. With rhs
 // (fused path only) the finest right-hand side is formed by the first kernel.
@@ -621,8 +652,8 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     double2* u = nullptr;
     double2* bc = c->lev[l + 1][kLb].as<double2>();
     // the fused post-smoothing kernel forms the pre-smoothed iterate again
-    const bool post_fused = dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2;
-    if (cy.nu1 == 2 && dim == 2) {
+    const bool post_fused = dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.plain;
+    if (cy.nu1 == 2 && dim == 2 && !cy.plain) {
       // both pre-sweeps, the residual and its restriction in one pass
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
@@ -641,14 +672,14 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       bl = bc;
       continue;
     }
-    if (cy.nu1 == 2 && dim == 3) {
+    if (cy.nu1 == 2 && dim == 3 && !cy.plain) {
       // both pre-sweeps from zero in one marching pass
       if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : HZ_KERNEL_LEVELS, [&] {
              return launch_march3(g, l, bt, cap, true, bl, nullptr, X, nl, st);
            })) != hipSuccess)
         return e;
       u = X;
-    } else if (cy.nu1 == 2 && dim == 1) {
+    } else if (cy.nu1 == 2 && dim == 1 && !cy.plain) {
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
       if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : HZ_KERNEL_LEVELS, [&] {
@@ -712,7 +743,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       continue;
     }
     // prolongation fused with the first post-sweep (2D: with the first two)
-    const int fused = (dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2) ? 2 : 1;
+    const int fused = (dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.plain) ? 2 : 1;
     double2* dst = (cy.nu2 == fused) ? R : ((u == X) ? Y : X);
     if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : HZ_KERNEL_LEVELS, [&] {
            if (fused == 2)
@@ -772,7 +803,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   // and ring 1's update adds both terms (one read and write of x instead of
   // two). Without a preconditioner s^ = s is overwritten at once, so x is
   // advanced every iteration.
-  const bool defer = !identity;
+  const bool defer = !identity && !cy.plain;
   double2* const phr[2] = {c->fine[kPh].as<double2>(), c->fine[kPh2].as<double2>()};
   double2* const shr[2] = {identity ? s : c->fine[kSh].as<double2>(), identity ? s : c->fine[kSh2].as<double2>()};
   double2* ph = phr[0];
@@ -797,7 +828,9 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   int rc;
   HZ_HIP(c, launch_bicg_init(n0, bt, nslots, rd, b, x, r, rh, p, v, n0, st));
   HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
-  HZ_HIP(c, launch_rh_sparse(n0, nslots, bt, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st));
+  // the plain path keeps every r^ dense (rh_nnz = -1 from reset_slots)
+  if (!cy.plain)
+    HZ_HIP(c, launch_rh_sparse(n0, nslots, bt, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st));
   if ((rc = close_unit()) != HZ_OK) return rc;
   if (vfree) {  // whether the first iterations need the dense sigma pass
     const int k = pending.back().second;
@@ -884,7 +917,10 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   // eagerly, which also runs the launch-shape trials, so nothing that
   // synchronises is captured. Kernel timing needs per-launch events, so
   // timed solves run eagerly.
-  const bool use_graphs = o->graphs && c->timing_mask == 0;
+  const bool use_graphs = o->graphs && c->timing_mask == 0 && !cy.plain;
+  // summaries in flight before the host waits: the plain path reads every
+  // iteration's back before it issues the next
+  const int lag = cy.plain ? 0 : kLag;
   struct GraphSet {  // instantiated graphs of this solve, destroyed once the stream is idle
     hipStream_t st;
     std::map<int, hipGraphExec_t> m;
@@ -931,7 +967,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   };
 
   while (!done) {
-    while (!pending.empty() && ((int)pending.size() > kLag || cap == 0)) {
+    while (!pending.empty() && ((int)pending.size() > lag || cap == 0)) {
       const auto [useq, k] = pending.front();
       pending.pop_front();
       HZ_HIP(c, hipEventSynchronize(c->ev[k]));
@@ -1067,7 +1103,7 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
              }));
       HZ_HIP(c, launch_gm_scale(n0, bt, cap, w, n0, st));
       if ((rc = close_unit(0)) != HZ_OK) return rc;
-      while ((int)pending.size() > kLag) {
+      while ((int)pending.size() > (cy.plain ? 0 : kLag)) {
         const int k = pending.front().second;
         pending.pop_front();
         HZ_HIP(c, hipEventSynchronize(c->ev[k]));
@@ -1177,6 +1213,7 @@ void hz_default_opts(hz_solve_opts* o) {
   o->coarse_sweeps = 2;
   o->graphs = 0;
   o->restart_at = 0;
+  o->plain = 0;
 }
 
 int hz_create(hz_ctx** out, const hz_ctx_opts* o) {
@@ -1383,12 +1420,13 @@ int hz_plan_grid(int dim, int nz, int nx, double h, double m_min, double m_max,
     o = &d;
   }
   for (int l = 0; l < HZ_MAX_LEVELS; ++l) w[l] = 0.0;
-  return plan_grid(dim, grid_max_levels(dim, nz, nx), grid_default_levels(dim, nz, nx), h, m_min, m_max, o,
-                   2.0 * M_PI * freq_hz, levels, w);
+  return plan_grid(dim, nz, 1, nx, grid_max_levels(dim, nz, nx), grid_default_levels(dim, nz, nx), h, m_min, m_max,
+                   o, 2.0 * M_PI * freq_hz, levels, w);
 }
 
-int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
-             int nrhs, const hz_c128* b_dev, hz_c128* u_dev, hz_rhs_info* info) {
+namespace {
+int solve_impl(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha, int nrhs,
+               const hz_c128* b_dev, hz_c128* u_dev, hz_rhs_info* info) {
   int rc = require_model(c);
   if (rc) return rc;
   hz_solve_opts d;
@@ -1419,7 +1457,10 @@ int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz
     for (int f = 0; f < nfreq; ++f) {
       int L = 0;
       if ((rc = make_plan(c, o, 2.0 * M_PI * freq_hz[f], &L, wj[f].data())) != HZ_OK)
-        return fail(c, rc, "cannot plan the V-cycle");
+        return fail(c, rc,
+                    "cannot plan the V-cycle: more levels than the grid allows, or an exactly solved "
+                    "coarsest level above %d unknowns",
+                    kCoarseMax);
       levels = L;
     }
   }
@@ -1427,7 +1468,7 @@ int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz
   if ((rc = setup_freqs(c, o, nfreq, freq_hz, alpha, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nslots, nrhs)) != HZ_OK) return rc;
   const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
-                 c->any_coarse_jacobi ? o->coarse_sweeps : 0};
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain};
   const double2* b = reinterpret_cast<const double2*>(b_dev);
   double2* x = reinterpret_cast<double2*>(u_dev);
   if (o->krylov == HZ_BICGSTAB) {
@@ -1439,6 +1480,12 @@ int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz
   int any_fail = 0;
   if ((rc = collect_info(c, nslots, b, x, info, &any_fail)) != HZ_OK) return rc;
   return any_fail ? HZ_WARN_NOCONV : HZ_OK;
+}
+}  // namespace
+
+int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+             int nrhs, const hz_c128* b_dev, hz_c128* u_dev, hz_rhs_info* info) {
+  return solve_impl(c, o, nfreq, freq_hz, alpha, nrhs, b_dev, u_dev, info);
 }
 
 namespace {
@@ -1867,13 +1914,14 @@ int hz_precond(hz_ctx* c, const hz_solve_opts* o, double freq_hz, int nrhs, cons
   std::vector<std::vector<double>> wj(1, std::vector<double>(kMaxLevels, 0.0));
   if (o->precond == HZ_PRECOND_MG) {
     if ((rc = make_plan(c, o, 2.0 * M_PI * freq_hz, &levels, wj[0].data())) != HZ_OK)
-      return fail(c, rc, "cannot plan the V-cycle");
+      return fail(c, rc, "cannot plan the V-cycle: more levels than the grid allows, or an exactly solved "
+                         "coarsest level above %d unknowns", kCoarseMax);
   }
   if ((rc = ensure_workspace(c, nrhs, levels)) != HZ_OK) return rc;
   if ((rc = setup_freqs(c, o, 1, &freq_hz, 0.0, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nrhs, nrhs)) != HZ_OK) return rc;
   const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
-                 c->any_coarse_jacobi ? o->coarse_sweeps : 0};
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain};
   HZ_HIP(c, precond_apply(c, cy, nrhs, reinterpret_cast<const double2*>(b_dev), reinterpret_cast<double2*>(u_dev)));
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   return HZ_OK;

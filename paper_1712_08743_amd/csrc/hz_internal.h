@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "hz.h"
+
 namespace hz {
 
 constexpr int kMaxLevels = 12;
@@ -13,7 +15,11 @@ constexpr int kBlock = 256;        // threads per block of the grid kernels
 constexpr int kVecPerThread = 4;   // nodes per thread in the pointwise Krylov kernels
 constexpr int kCoarseWaves = 4;    // waves per block of the coarse solve (each its own 16-row tile)
 constexpr int kPcrMax = 2048;      // longest 1D grid for the exact tridiagonal solve
-constexpr int kCoarseMax = 16384;  // most unknowns on the coarsest level (dense inverse)
+// Most unknowns on a coarsest level that is solved exactly. The dense inverse
+// takes one Gauss-Jordan launch per pivot over an (n x n) complex matrix per
+// frequency, so its set-up grows as n^3: 4096 unknowns is 268 MB per frequency
+// and well under a second; larger coarsest levels are refused.
+constexpr int kCoarseMax = HZ_COARSE_MAX;
 
 // Per right-hand-side solver status. Finished states equal the HZ_RHS_* codes.
 enum : int {

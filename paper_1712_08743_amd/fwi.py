@@ -24,7 +24,10 @@ def invert(ctx, m0, h, freqs, alpha, src, rec, d_obs, lam, gn_iters, cg_iters, s
     update, CG iterations, Krylov iterations of the forward solves and, when
     m_true is given, the relative model error after the update."""
     import torch
-    m = np.array(m0, dtype=np.float64, copy=True)
+    # the model stays on the device: Eq. (9)'s update m + step dm is a device axpy
+    m = torch.as_tensor(np.asarray(m0, dtype=np.float64) if not torch.is_tensor(m0) else m0,
+                        dtype=torch.float64).to(ctx.device).clone()
+    mt = None if m_true is None else torch.as_tensor(np.asarray(m_true, dtype=np.float64)).to(m.device)
     d_obs = torch.as_tensor(np.asarray(d_obs) if not torch.is_tensor(d_obs) else d_obs)
     order = np.argsort(freqs)
     if schedule == "simultaneous":
@@ -36,12 +39,12 @@ def invert(ctx, m0, h, freqs, alpha, src, rec, d_obs, lam, gn_iters, cg_iters, s
         fr = [float(freqs[i]) for i in g]
         dg = d_obs[list(g)].contiguous()
         for _ in range(gn_iters):
-            ctx.set_model(torch.from_numpy(m), h)
+            ctx.set_model(m, h)
             dm, J, it, info = ctx.gn_step(fr, alpha, src, rec, dg, lam, cg_iters, **opt)
-            m = m + step * dm.cpu().numpy()
+            m.add_(dm, alpha=float(step))
             rec_ = {"group": gi, "freqs": fr, "J": J, "cg_iterations": it,
                     "krylov_iterations": int(sum(i[1] for i in info))}
-            if m_true is not None:
-                rec_["model_error"] = float(np.linalg.norm(m - m_true) / np.linalg.norm(m_true))
+            if mt is not None:
+                rec_["model_error"] = float(torch.linalg.vector_norm(m - mt) / torch.linalg.vector_norm(mt))
             history.append(rec_)
-    return m, history
+    return m.cpu().numpy(), history

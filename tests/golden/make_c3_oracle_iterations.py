@@ -1,7 +1,10 @@
 """Write c3_oracle_iterations.json: the oracle's own BiCGSTAB iteration counts
-(tol 1e-8, LFA-planned V(2,2) shifted-Laplace (1, 0.5) preconditioner) on the
-401 x 801 layered model for three of its 64 surface shots at each of the
-frequencies 3, 5, 8 and 12 Hz. Calls only oracle/ (and the input generators).
+(tol 1e-8, V(2,2) shifted-Laplace (1, 0.5) preconditioner with the default
+plan: LFA-planned levels and weights, and the coarsest level solved exactly
+or, where its smallest kh is at least 2.5, smoothed by two damped-Jacobi
+sweeps -- the solver library's default policy) on the 401 x 801 layered
+model for three of its 64 surface shots at each of the frequencies 3, 5, 8
+and 12 Hz. Calls only oracle/ (and the input generators).
 
 Run from the repository root: python tests/golden/make_c3_oracle_iterations.py
 """
@@ -24,13 +27,16 @@ SHOTS = (0, 31, 63)
 
 def main():
     w = workloads.model_2d_layered()
-    out = {"workload": w.name, "tol": 1e-8, "beta": [1.0, 0.5], "nu": [2, 2], "shots": list(SHOTS),
+    out = {"workload": w.name, "tol": 1e-8, "beta": [1.0, 0.5], "nu": [2, 2], "coarse_policy": "auto",
+           "shots": list(SHOTS),
            "freqs": {}}
     for f in w.freqs:
         om = 2 * np.pi * f
         B = op.operator_B(w.m, w.h, om, w.alpha)
         L, wj = lfa.plan(w.shape, w.h, om, w.m.min(), w.m.max(), 1.0, 0.5)
-        V = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj)
+        V = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
+        hc = w.h * 2.0 ** (L - 1)
+        coarse = "jacobi" if om * hc * w.m.min() >= 2.5 else "exact"
         its = []
         t0 = time.perf_counter()
         for s in SHOTS:
@@ -39,7 +45,7 @@ def main():
             assert st == krylov.CONVERGED, (f, s, st)
             its.append(int(it))
         secs = time.perf_counter() - t0
-        out["freqs"][str(f)] = {"levels": L, "jacobi_w": wj, "iterations": its,
+        out["freqs"][str(f)] = {"levels": L, "jacobi_w": wj, "coarse": coarse, "iterations": its,
                                 "mean_iterations": float(np.mean(its))}
         print(f, L, wj, its, f"{secs:.1f}s", flush=True)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_oracle_iterations.json")

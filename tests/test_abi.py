@@ -84,6 +84,28 @@ def test_host_plan_rejects_bad_input():
         hz.plan_grid((201, 201), 10.0, 1 / 3000, 1 / 1500, 5.0, levels=9)
 
 
+def test_host_plan_refuses_a_large_exact_coarsest_level():
+    """An exactly solved coarsest level is inverted densely (one launch per
+    pivot, n^3 work), so more than 4096 unknowns there is refused by the
+    host plan; the same level smoothed instead of solved is accepted."""
+    import paper_1712_08743_amd as hz
+    mmin, mmax = 1 / 3500, 1 / 1500
+    # 301 x 601 with three levels: 76 x 151 = 11 476 unknowns on the coarsest level
+    for coarse in ("exact", "auto"):
+        with pytest.raises(hz.HzError) as ei:
+            hz.plan_grid((301, 601), 10.0, mmin, mmax, 3.0, levels=3, coarse=coarse)
+        assert ei.value.code == hz.HZ_ERR_SHAPE
+    L, w = hz.plan_grid((301, 601), 10.0, mmin, mmax, 3.0, levels=3, coarse="jacobi")
+    assert L == 3 and len(w) == 2
+    # auto smooths that level where its smallest kh reaches 2.5 (12 Hz: 2 pi 12 * 40 / 3500 = 0.86; not here)
+    # 64 x 64 with one level: 4096 unknowns, the largest accepted
+    assert hz.plan_grid((64, 64), 10.0, mmin, mmax, 3.0, levels=1)[0] == 1
+    with pytest.raises(hz.HzError):
+        hz.plan_grid((65, 65), 10.0, mmin, mmax, 3.0, levels=1)
+    # the default plan stays far below the limit
+    assert hz.plan_grid((301, 601), 10.0, mmin, mmax, 3.0)[0] == 6
+
+
 def test_footprint_grows_with_the_work():
     import paper_1712_08743_amd as hz
     f1 = hz.footprint((257, 257), 1, 1)

@@ -84,6 +84,32 @@ def test_autograd_function(hz):
     assert torch.allclose(m.grad, g2 * 4.0, rtol=1e-12, atol=0)
 
 
+def test_misfit_autograd_forward_without_gradient(hz):
+    """Evaluations that need no gradient (no_grad, a tensor that does not
+    require it) run the forward solves alone; lazy=True computes the
+    gradient in the backward pass. J and dJ/dm are the same either way."""
+    import torch
+    true, start, src, rec, sv, d_obs = _survey(nz=21, nx=41, h=40.0, nshots=2, freqs=(2.5,))
+    c = _ctx(hz, start.m, start.h)
+    J2, g2, _ = c.gradient(sv.freqs, sv.alpha, src, rec, torch.from_numpy(d_obs), 1e-3, tol=1e-11)
+    f = hz.Misfit(c, sv.freqs, sv.alpha, src, rec, torch.from_numpy(d_obs), 1e-3, tol=1e-11)
+    m = torch.from_numpy(start.m).cuda()
+    with torch.no_grad():
+        J = f(m.clone().requires_grad_(True))
+    assert f.calls == {"misfit": 1, "gradient": 0}
+    J_plain = f(m)
+    assert f.calls == {"misfit": 2, "gradient": 0}
+    assert abs(J.item() - J2) <= 1e-12 * J2 and abs(J_plain.item() - J2) <= 1e-12 * J2
+    lazy = hz.Misfit(c, sv.freqs, sv.alpha, src, rec, torch.from_numpy(d_obs), 1e-3, lazy=True, tol=1e-11)
+    ml = m.clone().requires_grad_(True)
+    Jl = lazy(ml)
+    assert lazy.calls == {"misfit": 1, "gradient": 0}
+    Jl.backward()
+    assert lazy.calls == {"misfit": 1, "gradient": 1}
+    assert abs(Jl.item() - J2) <= 1e-12 * J2
+    assert torch.equal(ml.grad, g2)
+
+
 def test_chunked_gradient_matches_full(hz):
     """A workspace budget that admits one frequency at a time gives the same
     gradient (forward fields recomputed per chunk instead of kept)."""

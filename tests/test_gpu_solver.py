@@ -87,6 +87,36 @@ def test_c2_lens_vcycle(hz, sign, tol):
     assert iters_close(it, it_o), (it, it_o)
 
 
+@pytest.mark.parametrize("krylov_name", ["bicgstab", "gmres"])
+def test_plain_per_launch_path(hz, krylov_name):
+    """The plain per-launch path (single kernels for every step, dense
+    shadow residual, host readback every iteration) runs the same
+    iteration as the fused batched path: the same wavefield to rounding
+    (both against LU), the oracle's iteration count, and GMRES too."""
+    w = workloads.model_2d_lens(sign=-1.0)
+    c = make_ctx(hz, w.m, w.h)
+    f = w.freqs[0]
+    om = 2 * np.pi * f
+    b = c.point_rhs([0, 0], [100, 37])
+    kw = dict(levels=4, nu=(2, 2), jacobi_w_level=[0.8] * 3, tol=1e-10, krylov=krylov_name)
+    u0, i0 = c.solve([f], w.alpha, b[None], **kw)
+    u1, i1 = c.solve([f], w.alpha, b[None], plain=True, **kw)
+    B = op.operator_B(w.m, w.h, om, w.alpha)
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, 4, 2, 2, [0.8] * 3, coarse="auto")
+    for s, ix in enumerate((100, 37)):
+        assert i0[s][0] == hz.HZ_RHS_CONVERGED and i1[s][0] == hz.HZ_RHS_CONVERGED
+        bn = op.point_source(w.shape, w.h, [ix])
+        ulu = direct.solve_superlu(B, bn)
+        assert rel(to_np(u1)[0, s].ravel(), ulu) < 1e-8
+        assert rel(to_np(u1)[0, s].ravel(), to_np(u0)[0, s].ravel()) < 1e-8
+        assert iters_close(i1[s][1], i0[s][1])
+        if krylov_name == "bicgstab":
+            _, it_o, _, _ = krylov.bicgstab(B, bn, vc, tol=1e-10, maxit=500)
+        else:
+            _, it_o, _, _ = krylov.gmres(B, bn, vc, m=30, tol=1e-10, maxit=500)
+        assert iters_close(i1[s][1], it_o), (i1[s][1], it_o)
+
+
 def test_multi_frequency_multi_shot_batch(hz):
     """Several frequencies and shots in one batch, planned weights, each
     right-hand side against its own LU solution."""
@@ -395,25 +425,46 @@ def test_misfit_matches_oracle(hz):
     assert abs(J - J_o) <= 1e-7 * J_o
 
 
-def test_full_size_batched_configuration_sampled(hz):
+def test_full_size_batched_configuration(hz):
     """401 x 801 grid, 64 surface shots x {3, 5, 8, 12} Hz = 256 right-hand
-    sides in one batch (the benchmark's launch configuration); two shots per
-    frequency are checked against LU, and every right-hand side's true
-    residual against the tolerance."""
+    sides in one batch (the benchmark's launch configuration, default plan
+    and coarse policy). Every one of the 256 returned wavefields has its
+    true residual recomputed with the oracle's sparse B; shots 0, 31 and 63
+    of every frequency are checked against LU and their iteration counts
+    against the oracle's own BiCGSTAB with the same V-cycle
+    (tests/golden/c3_oracle_iterations.json, written by the oracle alone)."""
+    import json
+    import os
     import torch
     w = workloads.model_2d_layered()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_oracle_iterations.json")))
+    assert gold["coarse_policy"] == "auto" and gold["tol"] == 1e-8
     c = make_ctx(hz, w.m, w.h)
     ns = len(w.src)
     b1 = c.point_rhs([0] * ns, w.src)
     b = torch.stack([b1] * len(w.freqs))
     u, info = c.solve(w.freqs, w.alpha, b, tol=1e-8)
     assert all(i[0] == hz.HZ_RHS_CONVERGED and i[2] <= 1e-8 for i in info), info
+    U = to_np(u).reshape(len(w.freqs), ns, -1)
+    bn = to_np(b1).reshape(ns, -1)
     for fi, f in enumerate(w.freqs):
         om = 2 * np.pi * f
-        lu = direct.factor_superlu(op.operator_B(w.m, w.h, om, w.alpha))
-        for s in (0, 41):
-            bn = op.point_source(w.shape, w.h, [w.src[s]])
-            assert rel(to_np(u[fi, s]).ravel(), lu.solve(bn)) < 1e-6
+        g = gold["freqs"][str(f)]
+        L, wj = c.plan(f)
+        assert L == g["levels"] and np.allclose(wj, g["jacobi_w"], rtol=0, atol=1e-15)
+        B = op.operator_B(w.m, w.h, om, w.alpha)
+        # true residual of all 64 wavefields from the oracle's operator
+        R = (bn - (B @ U[fi].T).T)
+        rr = np.linalg.norm(R, axis=1) / np.linalg.norm(bn, axis=1)
+        gpu_rr = np.array([info[fi * ns + s][2] for s in range(ns)])
+        assert rr.max() <= 1.01e-8, (f, rr.max())
+        assert np.allclose(rr, gpu_rr, rtol=1e-3, atol=0), (f, rr, gpu_rr)
+        lu = direct.factor_superlu(B)
+        for k, s in enumerate(gold["shots"]):
+            ref = lu.solve(op.point_source(w.shape, w.h, [w.src[s]]))
+            assert rel(U[fi, s], ref) < 1e-6, (f, s)
+            it = info[fi * ns + s][1]
+            assert iters_close(it, g["iterations"][k]), (f, s, it, g["iterations"][k])
 
 
 @pytest.mark.parametrize("m,tol", [(30, 1e-8), (5, 1e-10)])
