@@ -195,6 +195,29 @@ int  hz_solve(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_h
               double alpha, int nrhs, const hz_c128 *b_dev, hz_c128 *u_dev,
               hz_rhs_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hz_solve
+ * with the same arguments, results and errors, whose whole solver workspace
+ * (Krylov and multigrid vectors, the per-frequency tables and coarse
+ * inverses, the slot records and reduction partials) is taken from a static
+ * device array of HZ_NOALLOC_BYTES that the library holds on every device it
+ * runs on until the process ends. The call itself allocates nothing: no
+ * hipMalloc or hipFree, no launch-shape trials (launch shapes the context
+ * has already tuned are reused, others take the default shape), no kernel
+ * timing and no graphs. The model must have been set by hz_set_model (which
+ * allocates the level hierarchy once); the context's own workspace is left
+ * as it was. The coarse inverses are formed again on every call.
+ * Every call on a device shares that device's array and overwrites it:
+ * calls that overlap in time on one device (several contexts, streams or
+ * threads) race and must be serialised by the caller.
+ * Errors: those of hz_solve, and HZ_ERR_NOMEM (with a message giving the
+ * bytes needed) when the workspace exceeds HZ_NOALLOC_BYTES; hz_footprint
+ * estimates it. */
+#define HZ_NOALLOC_BYTES (64u << 20)
+int  hz_solve_noalloc(hz_ctx *c, const hz_solve_opts *o, int nfreq, const double *freq_hz,
+                      double alpha, int nrhs, const hz_c128 *b_dev, hz_c128 *u_dev,
+                      hz_rhs_info *info);
+
 /* Misfit of Eq. (4): J = sum over frequencies, shots and receivers of
  * |d_obs - u(receiver)|^2 + lambda * sum m^2, where u solves B u = b for
  * each shot (point source at (src_iz, src_ix) with amplitude src_amp,

@@ -81,6 +81,8 @@ _SIGS = {
     "hz_point_rhs_3d": (_i, [_vp, _i, _ip, _ip, _ip, _vp, _vp]),
     "hz_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _vp, _vp,
                       ctypes.POINTER(RhsInfo)]),
+    "hz_solve_noalloc": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _vp, _vp,
+                              ctypes.POINTER(RhsInfo)]),
     "hz_misfit": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
                        _ip, _vp, _d, _dp, _vp, ctypes.POINTER(RhsInfo)]),
     "hz_gradient": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _dp, _d, _i, _ip, _ip, _vp, _i, _ip,
@@ -261,11 +263,13 @@ class Context:
         return b
 
     # -- solves ------------------------------------------------------------
-    def solve(self, freqs, alpha, b, out=None, **opt):
+    def solve(self, freqs, alpha, b, out=None, noalloc=False, **opt):
         """Solve for every frequency and every right-hand side.
 
         b: complex128 tensor [nfreq, nrhs, *shape] (or [nrhs, *shape] for one
         frequency). Returns (u, info) with info a list of (status, iters, relres).
+        noalloc=True calls hz_solve_noalloc (the workspace from the library's
+        static device array; pass ``out`` to allocate nothing on this side either).
         """
         t = self.torch
         freqs = [float(f) for f in freqs]
@@ -282,7 +286,8 @@ class Context:
         o, keep = make_opts(**opt)
         info = (RhsInfo * (nf * nrhs))()
         fa = (ctypes.c_double * nf)(*freqs)
-        rc = _lib.hz_solve(self._h, ctypes.byref(o), nf, fa, float(alpha), nrhs, _ptr(b), _ptr(u), info)
+        call = _lib.hz_solve_noalloc if noalloc else _lib.hz_solve
+        rc = call(self._h, ctypes.byref(o), nf, fa, float(alpha), nrhs, _ptr(b), _ptr(u), info)
         self._check(rc, allow_warn=True)
         del keep
         self.last_seconds = [i.seconds for i in info]

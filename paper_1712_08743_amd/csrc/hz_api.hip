@@ -18,28 +18,55 @@
 #include <string>
 #include <vector>
 #include <map>
+#include <mutex>
 #include <array>
 
 using namespace hz;
 
 namespace {
 
+// The allocation-free solve (hz_solve_noalloc) takes its workspace from a
+// static device array: while an arena is installed on the calling thread,
+// DevBuf::ensure hands out 256-byte aligned regions of it (a bump pointer)
+// instead of calling hipMalloc, and such regions are never freed.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  size_t wanted = 0;  // end of the furthest region asked for (above cap: refused)
+};
+thread_local Arena* t_arena = nullptr;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;  // a region of the arena, not ours to free
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
   }
   hipError_t ensure(size_t nb) {
     if (nb <= bytes && p) return hipSuccess;
-    release();
     if (nb == 0) nb = 256;
+    if (t_arena) {
+      // an owned buffer here would have to be freed: the caller stashes them all first
+      if (p && !borrowed) return hipErrorInvalidValue;
+      const size_t off = (t_arena->used + 255) & ~(size_t)255;
+      t_arena->wanted = std::max(t_arena->wanted, off + nb);
+      if (off + nb > t_arena->cap) return hipErrorOutOfMemory;
+      p = t_arena->base + off;
+      bytes = nb;
+      borrowed = true;
+      t_arena->used = off + nb;
+      return hipSuccess;
+    }
+    release();
     hipError_t e = hipMalloc(&p, nb);
     if (e == hipSuccess) bytes = nb;
     else p = nullptr;
@@ -48,6 +75,33 @@ struct DevBuf {
   template <class T>
   T* as() const { return static_cast<T*>(p); }
 };
+
+// Workspace of the allocation-free solve: one array per device, found by
+// hipGetSymbolAddress at context creation (the name is only a host-side
+// stand-in for it). Every call on a device shares that device's array.
+__device__ __align__(256) unsigned char scratch[HZ_NOALLOC_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// With the device current: the address of this device's scratch array (looked up once).
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 struct LevelInfo {
   int nz = 0, nx = 0, ny = 1;  // ny > 1 on 3D grids only
@@ -122,6 +176,9 @@ struct hz_ctx {
   bool any_coarse_jacobi = false;      // set by setup_freqs for the running solve
   int tune_mode = 1;   // opts.autotune of the running solve
   int fixed_chunk = 0; // opts.chunk_rows of the running solve
+  // inside hz_solve_noalloc: no launch-shape trials, no timing events, no graphs
+  bool noalloc = false;
+  hipError_t scratch_status = hipSuccess;  // lookup of the device's scratch array at creation
 };
 
 namespace {
@@ -524,7 +581,7 @@ hipEvent_t take_event(hz_ctx* c) {
 
 template <class F>
 hipError_t timed(hz_ctx* c, int cls, F&& launch) {
-  if (cls < 0 || !(c->timing_mask & (1u << cls))) return launch();
+  if (cls < 0 || !(c->timing_mask & (1u << cls)) || c->noalloc) return launch();
   hipEvent_t a = take_event(c), b = take_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, c->stream);
@@ -580,7 +637,7 @@ hipError_t tuned_launch(hz_ctx* c, const Cycle& cy, int kind, const Grid& g, int
   const std::array<int, 4> key{kind, g.nz, g.nx, octave(cap)};
   auto it = c->tuned_chunk.find(key);
   if (it != c->tuned_chunk.end()) return launch(it->second);
-  if (!cy.autotune) return launch(kChunkDefault);
+  if (!cy.autotune || c->noalloc) return launch(kChunkDefault);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -917,7 +974,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   // eagerly, which also runs the launch-shape trials, so nothing that
   // synchronises is captured. Kernel timing needs per-launch events, so
   // timed solves run eagerly.
-  const bool use_graphs = o->graphs && c->timing_mask == 0 && !cy.plain;
+  const bool use_graphs = o->graphs && c->timing_mask == 0 && !cy.plain && !c->noalloc;
   // summaries in flight before the host waits: the plain path reads every
   // iteration's back before it issues the next
   const int lag = cy.plain ? 0 : kLag;
@@ -1251,6 +1308,9 @@ int hz_create(hz_ctx** out, const hz_ctx_opts* o) {
     return HZ_ERR_DEVICE;
   }
   c->ring_dev = static_cast<Summary*>(dptr);
+  // the allocation-free solve's array on this device (device current); a
+  // failed lookup is reported by hz_solve_noalloc, the other calls do not need it
+  c->scratch_status = scratch_setup(c->device);
   for (int k = 0; k < kRing; ++k) {
     if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) {
       hz_destroy(c);
@@ -1486,6 +1546,93 @@ int solve_impl(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_
 int hz_solve(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
              int nrhs, const hz_c128* b_dev, hz_c128* u_dev, hz_rhs_info* info) {
   return solve_impl(c, o, nfreq, freq_hz, alpha, nrhs, b_dev, u_dev, info);
+}
+
+namespace {
+
+// Moves the context's solver workspace aside (and its cached coarse
+// inverses, workspace sizes and slot capacity) so that the solve finds
+// every buffer empty and takes it from the arena; puts everything back on
+// destruction, after the stream has drained.
+struct WorkspaceStash {
+  hz_ctx* c;
+  std::vector<DevBuf*> bufs;
+  struct Saved {
+    void* p;
+    size_t bytes;
+    bool borrowed;
+  };
+  std::vector<Saved> saved;
+  int ws_slots, ws_levels, slot_cap, partial_tiles;
+  std::vector<double> cinv_key;
+  const double2* cinv_base;
+  explicit WorkspaceStash(hz_ctx* cc) : c(cc) {
+    for (auto& b : c->fine) bufs.push_back(&b);
+    for (auto& lvb : c->lev)
+      for (auto& b : lvb) bufs.push_back(&b);
+    for (DevBuf* b : {&c->slots, &c->active, &c->nactive, &c->freqtab, &c->partials, &c->resid, &c->fstart,
+                      &c->rh_idx, &c->rh_val, &c->cinv_a, &c->cinv_b, &c->winv, &c->gm_V, &c->gm_small,
+                      &c->gm_part})
+      bufs.push_back(b);
+    for (DevBuf* b : bufs) {
+      saved.push_back({b->p, b->bytes, b->borrowed});
+      b->p = nullptr;
+      b->bytes = 0;
+      b->borrowed = false;
+    }
+    ws_slots = c->ws_slots;
+    ws_levels = c->ws_levels;
+    slot_cap = c->slot_cap;
+    partial_tiles = c->partial_tiles;
+    cinv_key = c->cinv_key;
+    cinv_base = c->cinv_base;
+    c->ws_slots = c->ws_levels = c->slot_cap = c->partial_tiles = 0;
+    c->cinv_key.clear();
+    c->cinv_base = nullptr;
+  }
+  ~WorkspaceStash() {
+    (void)hipStreamSynchronize(c->stream);  // nothing may still use the arena's regions
+    for (size_t i = 0; i < bufs.size(); ++i) {
+      bufs[i]->p = saved[i].p;
+      bufs[i]->bytes = saved[i].bytes;
+      bufs[i]->borrowed = saved[i].borrowed;
+    }
+    c->ws_slots = ws_slots;
+    c->ws_levels = ws_levels;
+    c->slot_cap = slot_cap;
+    c->partial_tiles = partial_tiles;
+    c->cinv_key = cinv_key;
+    c->cinv_base = cinv_base;
+  }
+};
+
+}  // namespace
+
+int hz_solve_noalloc(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_hz, double alpha,
+                     int nrhs, const hz_c128* b_dev, hz_c128* u_dev, hz_rhs_info* info) {
+  int rc = require_model(c);
+  if (rc) return rc;
+  HZ_HIP(c, hipSetDevice(c->device));
+  void* base = scratch_of(c->device);
+  if (c->scratch_status != hipSuccess || !base)
+    return fail(c, HZ_ERR_DEVICE, "the scratch array of device %d was not found: %s", c->device,
+                hipGetErrorString(c->scratch_status));
+  Arena arena;
+  arena.base = static_cast<char*>(base);
+  arena.cap = HZ_NOALLOC_BYTES;
+  {
+    WorkspaceStash stash(c);
+    c->noalloc = true;
+    t_arena = &arena;
+    rc = solve_impl(c, o, nfreq, freq_hz, alpha, nrhs, b_dev, u_dev, info);
+    t_arena = nullptr;
+    c->noalloc = false;
+  }
+  if (rc == HZ_ERR_NOMEM && arena.wanted > arena.cap)
+    return fail(c, HZ_ERR_NOMEM,
+                "the solve's workspace exceeds the %zu bytes of the allocation-free call (at least %zu needed)",
+                (size_t)HZ_NOALLOC_BYTES, arena.wanted);
+  return rc;
 }
 
 namespace {
