@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/hz_kernels.hip", "csrc/hz_stream.hip", "csrc/hz_krylov.hip", "csrc/hz_fwi.hip", "csrc/hz_api.hip",
+SOURCES = ["csrc/hz_kernels.hip", "csrc/hz_stream.hip", "csrc/hz_vsmall.hip", "csrc/hz_krylov.hip", "csrc/hz_fwi.hip", "csrc/hz_api.hip",
            "csrc/hz_server.hip"]
 LIB = os.path.join(HERE, "libhz.so")
 

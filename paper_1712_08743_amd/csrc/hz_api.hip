@@ -698,10 +698,35 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   if (L == 1) return launch_coarse_solve((int)n0, c->cur_nfreq, c->cur_nrhs, bt, b0, out, n0, st);
   hipError_t e;
   if (rhs) b0 = rhs->out;
+  // 2D V(2,2): the levels from the first one with at most kSmallNodes nodes
+  // down to the coarsest are walked by two kernels (one workgroup per
+  // right-hand side) instead of a launch per level and step
+  // (the first level small enough whose vectors also fit the workgroup's LDS)
+  int l0 = L;
+  SmallLevels sl;
+  memset(&sl, 0, sizeof sl);
+  if (dim == 2 && cy.nu1 == 2 && cy.nu2 == 2 && !cy.plain && L >= 3)
+    for (int lf = 1; lf < L - 1 && l0 == L; ++lf) {
+      if (c->lv[lf].n() > (size_t)kSmallNodes) continue;
+      sl.l0 = lf;
+      sl.L = L;
+      sl.coarse_sweeps = cy.coarse_sweeps;
+      sl.coarse_w = kCoarseJacobiW;
+      for (int l = lf; l < L; ++l) {
+        sl.g[l] = grid_of(c, l);
+        sl.b[l] = c->lev[l][kLb].as<double2>();
+        sl.u[l] = c->lev[l][kLu].as<double2>();
+        sl.x[l] = c->lev[l][kLx].as<double2>();
+        sl.y[l] = c->lev[l][kLy].as<double2>();
+        sl.n[l] = c->lv[l].n();
+      }
+      if (small_levels_lds(sl) <= c->max_lds) l0 = lf;
+    }
+  const int ldesc = std::min(L - 1, l0);  // levels with per-level launches
   // descend
   const double2* bl = b0;
   double2* cur[kMaxLevels];
-  for (int l = 0; l < L - 1; ++l) {
+  for (int l = 0; l < ldesc; ++l) {
     const Grid g = grid_of(c, l);
     const size_t nl = c->lv[l].n();
     double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
@@ -764,8 +789,18 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       return e;
     bl = bc;
   }
-  // coarsest
-  {
+  if (l0 < L - 1) {
+    const int cl = L - 1;
+    if ((e = timed(c, HZ_KERNEL_LEVELS, [&] { return launch_vdown(sl, bt, cap, st); })) != hipSuccess) return e;
+    // the exact coarse solve (frequencies that smooth their coarsest level were done in the descent)
+    if ((e = timed(c, HZ_KERNEL_COARSE, [&] {
+           return launch_coarse_solve((int)c->lv[cl].n(), c->cur_nfreq, c->cur_nrhs, bt, c->lev[cl][kLb].as<double2>(),
+                                      c->lev[cl][kLu].as<double2>(), c->lv[cl].n(), st);
+         })) != hipSuccess)
+      return e;
+    if ((e = timed(c, HZ_KERNEL_LEVELS, [&] { return launch_vup(sl, bt, cap, st); })) != hipSuccess) return e;
+  } else {
+    // coarsest
     const int cl = L - 1;
     if ((e = timed(c, HZ_KERNEL_COARSE, [&] {
            return launch_coarse_solve((int)c->lv[cl].n(), c->cur_nfreq, c->cur_nrhs, bt, c->lev[cl][kLb].as<double2>(),
@@ -782,7 +817,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       return e;
   }
   // ascend
-  for (int l = L - 2; l >= 0; --l) {
+  for (int l = ldesc - 1; l >= 0; --l) {
     const Grid g = grid_of(c, l);
     const Grid gc = grid_of(c, l + 1);
     const size_t nl = c->lv[l].n();

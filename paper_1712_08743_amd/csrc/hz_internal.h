@@ -130,6 +130,30 @@ int lds_tiles(int nz, int nx);                 // tiles per slot of the LDS-stag
 // tiles per slot of the kernels that store reduction partials over a grid
 int reduce_tiles(int nz, int nx, int dim);
 
+// The small levels of a 2D V-cycle, walked by one workgroup per right-hand
+// side (hz_vsmall.hip): smoothing levels l0 .. L-2 and the coarsest level
+// L-1. Arrays are indexed by level; n is each level's slot stride.
+// Most nodes of a level the fused kernels take: one complex vector of the
+// largest such level is held in LDS (96 KB).
+constexpr int kSmallNodes = 6144;
+struct SmallLevels {
+  int l0, L;
+  int coarse_sweeps;  // sweeps on the coarsest level of frequencies that smooth it (0: none)
+  double coarse_w;    // their damped-Jacobi weight
+  Grid g[kMaxLevels];
+  double2* b[kMaxLevels];  // right-hand sides (b[l0] is the input)
+  double2* u[kMaxLevels];  // V-cycle results (u[l0] is the output; u[L-1] the coarse solution)
+  double2* x[kMaxLevels];  // pre-smoothed iterate, kept for the ascent; work vector on the coarsest level
+  double2* y[kMaxLevels];  // residual, then u2 + P e
+  size_t n[kMaxLevels];
+};
+// Descent (to the coarse right-hand side, and the coarsest level's sweeps for
+// frequencies that smooth it) and ascent, one workgroup per entry of the
+// active list (cap entries at most).
+size_t small_levels_lds(const SmallLevels& s);  // LDS bytes per workgroup of the two kernels
+hipError_t launch_vdown(const SmallLevels& s, const Batch& bt, int cap, hipStream_t st);
+hipError_t launch_vup(const SmallLevels& s, const Batch& bt, int cap, hipStream_t st);
+
 // ---- kernel launchers (hz_kernels.hip) ----------------------------------------
 // All take the stream last and return the launch status.
 // `which` selects the mass shift: 0 = B (1 - j alpha), 1 = M (beta1 - j beta2).
