@@ -338,21 +338,28 @@ int  hz_precond(hz_ctx *c, const hz_solve_opts *o, double freq_hz, int nrhs,
 
 /* ---- serving ----------------------------------------------------------------
  * A server runs solve requests of any grid size, model and frequencies on one
- * device with continuous admission: a request starts as soon as an execution
- * slot is free and the device memory of all slots, including the request's
- * footprint (hz_footprint), fits the budget. Every slot owns a context and a
- * HIP stream, so admitted requests overlap on the device, and keeps its
- * workspace from one request to the next (it releases it only when its memory
- * keeps the next request from fitting). Requests start in submission order.
- * The result of a request does not depend on the others: the kernels reduce
- * every right-hand side in a fixed order. */
+ * device with continuous batching. Requests the batched BiCGSTAB path takes
+ * (2D grids, the multigrid preconditioner, no fixed per-level weights) are
+ * grouped by grid and solver options; each group runs in one engine whose
+ * slots are lanes of 8 right-hand sides: every (request, frequency) takes
+ * ceil(nrhs / 8) lanes and keeps the request's own slowness model. A request
+ * that arrives while its group's engine runs joins the running batch between
+ * two iterations as soon as enough lanes are free, and leaves it when all its
+ * right-hand sides have stopped; the engine stops once idle. Engines of
+ * different groups, and requests no engine takes (1D, GMRES, other
+ * preconditioners), run on workers of their own, each on its own HIP stream,
+ * so their work overlaps on the device. Device memory is admitted against the
+ * budget by hz_server_footprint. The result of a request does not depend on
+ * the others, bit for bit: every reduction is in a fixed order per right-hand
+ * side, and a request joins a batch after an even number of its iterations,
+ * so its iterate is advanced in the same order as in hz_solve. */
 
 typedef struct hz_server hz_server;
 
 typedef struct {
     int    device;
     size_t hbm_budget_bytes;  /* device memory the slots may hold together; 0 = no limit */
-    int    slots;             /* requests that may run at once (1..64) */
+    int    slots;             /* workers (1..64): engines and single requests running at once */
 } hz_server_opts;
 
 typedef struct {
@@ -371,18 +378,28 @@ typedef struct {
 /* Device memory a solve of this shape holds (host computation, no device). */
 size_t hz_footprint(int dim, int nz, int nx, int nfreq, int nrhs, const hz_solve_opts *o);
 
-/* Errors: HZ_ERR_ARG (bad device or slot count), HZ_ERR_DEVICE. */
+/* Device memory the server reserves to run such a request: an engine of its
+ * lanes (nfreq * ceil(nrhs / 8)) for a request an engine takes, else its
+ * hz_footprint (host computation). A request above the budget is refused. */
+size_t hz_server_footprint(int dim, int nz, int nx, int nfreq, int nrhs, const hz_solve_opts *o);
+
+/* Errors: HZ_ERR_ARG (bad device or slot count), HZ_ERR_DEVICE.
+ * hbm_budget_bytes = 0: nine tenths of the device memory free at creation. */
 int  hz_server_create(hz_server **out, const hz_server_opts *o);
 /* Runs the queued requests to completion, then releases every slot. */
 void hz_server_destroy(hz_server *s);
-/* Queue a request; *ticket identifies it. HZ_ERR_NOMEM if its footprint
- * exceeds the budget on its own. */
+/* Queue a request; *ticket identifies it. HZ_ERR_NOMEM if its server
+ * footprint exceeds the budget on its own. */
 int  hz_server_submit(hz_server *s, const hz_request *rq, long long *ticket);
 /* Block until the request is done; info (host, optional) receives
  * nfreq*nrhs records, times (host, optional) three doubles: seconds queued,
  * seconds running, latency (submission to completion). Returns the request's
- * hz_solve status. A ticket can be waited for once. */
+ * hz_solve status. A ticket can be waited for once: a second wait on it,
+ * also one from another thread while the first waits, returns HZ_ERR_ARG. */
 int  hz_server_wait(hz_server *s, long long ticket, hz_rhs_info *info, double *times);
+/* queued: requests waiting; running: requests on the device (an engine runs
+ * many); peak_running: most at once so far; bytes_in_use: device memory the
+ * running engines and requests hold. */
 int  hz_server_stats(hz_server *s, int *queued, int *running, int *peak_running,
                      size_t *bytes_in_use);
 

@@ -105,6 +105,7 @@ _SIGS = {
     "hz_timing_start": (_i, [_vp, ctypes.c_uint]),
     "hz_timing_read": (_i, [_vp, _i, _ip, _dp]),
     "hz_footprint": (ctypes.c_size_t, [_i, _i, _i, _i, _i, ctypes.POINTER(SolveOpts)]),
+    "hz_server_footprint": (ctypes.c_size_t, [_i, _i, _i, _i, _i, ctypes.POINTER(SolveOpts)]),
     "hz_server_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(ServerOpts)]),
     "hz_server_destroy": (None, [_vp]),
     "hz_server_submit": (_i, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_longlong)]),
@@ -488,8 +489,16 @@ def footprint(shape, nfreq, nrhs, **opt):
     return int(_lib.hz_footprint(dim, nz, nx, nfreq, nrhs, ctypes.byref(o)))
 
 
+def server_footprint(shape, nfreq, nrhs, **opt):
+    """Device bytes the server reserves to run a request of this shape (host computation)."""
+    o, keep = make_opts(**opt)
+    dim = len(shape)
+    nz, nx = (1, shape[0]) if dim == 1 else shape
+    return int(_lib.hz_server_footprint(dim, nz, nx, nfreq, nrhs, ctypes.byref(o)))
+
+
 class Server:
-    """Continuous-admission solve server (see hz_server_* in include/hz.h).
+    """Continuous-batching solve server (see hz_server_* in include/hz.h).
 
     submit() queues a request and returns a ticket; wait() returns
     (u, info, times) with times = (queued s, running s, latency s). Tensors

@@ -5,6 +5,7 @@
 // that the device writes into mapped host memory.
 
 #include "hz.h"
+#include "hz_engine.h"
 #include "hz_internal.h"
 
 #include <math.h>
@@ -107,6 +108,7 @@ struct LevelInfo {
   int nz = 0, nx = 0, ny = 1;  // ny > 1 on 3D grids only
   double h = 0.0;
   DevBuf m;
+  size_t mstride = 0;  // engines: one model per lane, mstride apart (see Grid::mstride)
   size_t n() const { return (size_t)nz * ny * nx; }
   int rows() const { return nz * ny; }  // rows of the 2D tiling of the grid
 };
@@ -217,6 +219,7 @@ Grid grid_of(const hz_ctx* c, int l) {
   g.ny = c->lv[l].ny;
   g.h = c->lv[l].h;
   g.m = c->lv[l].m.as<double>();
+  g.mstride = c->lv[l].mstride;
   return g;
 }
 
@@ -631,12 +634,26 @@ int octave(int cap) {
   return b;
 }
 
+// Shapes tuned by any context of the process, per device (contexts created
+// later, such as the server's engines, start from them).
+std::mutex g_tuned_mu;
+std::map<std::array<int, 5>, int> g_tuned;
+
 template <class F>
 hipError_t tuned_launch(hz_ctx* c, const Cycle& cy, int kind, const Grid& g, int cap, F launch) {
   if (cy.chunk_rows > 0) return launch(cy.chunk_rows);
   const std::array<int, 4> key{kind, g.nz, g.nx, octave(cap)};
   auto it = c->tuned_chunk.find(key);
   if (it != c->tuned_chunk.end()) return launch(it->second);
+  const std::array<int, 5> gkey{c->device, kind, g.nz, g.nx, octave(cap)};
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto gt = g_tuned.find(gkey);
+    if (gt != g_tuned.end()) {
+      c->tuned_chunk[key] = gt->second;
+      return launch(gt->second);
+    }
+  }
   if (!cy.autotune || c->noalloc) return launch(kChunkDefault);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
@@ -664,6 +681,10 @@ hipError_t tuned_launch(hz_ctx* c, const Cycle& cy, int kind, const Grid& g, int
   if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) return e;
   c->tuned_chunk[key] = pick;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned.emplace(gkey, pick);
+  }
   return launch(pick);
 }
 
@@ -866,78 +887,76 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
 }
 
 // ---------------------------------------------------------------- BiCGSTAB driver
-int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
-                 const double2* b, double2* x) {
-  const size_t n0 = c->lv[0].n();
-  const Batch bt = batch_of(c);
-  const Reduce rd = reducer(c);
-  const Grid g0 = grid_of(c, 0);
-  hipStream_t st = c->stream;
-  double2* r = c->fine[kR].as<double2>();
-  double2* rh = c->fine[kRh].as<double2>();
-  double2* pbuf[2] = {c->fine[kP].as<double2>(), c->fine[kP2].as<double2>()};
-  double2* p = pbuf[0];
-  double2* v = c->fine[kV].as<double2>();
-  double2* s = c->fine[kS].as<double2>();
-  double2* t = c->fine[kT].as<double2>();
-  const bool identity = cy.precond == HZ_PRECOND_NONE;
-  const bool fused = fused_pre(cy) && c->dim != 3;
-  // 2D with the fused pre-smoothing kernel: v = B p^ is never stored. The
-  // pre-smoothing kernels form it from p^ (the last iteration's p^ for the p
-  // update, the current one for s), and sigma = <r^, B p^> is formed at the
-  // nodes of r^'s sparse list. Slots whose r^ is dense (a right-hand side
-  // with many nonzeros, or after a restart) take sigma from an operator pass
-  // that stores nothing, launched while any active slot needs it.
-  const bool vfree = fused && c->dim == 2;
-  bool dense_rh = false;
-  // The iterate is advanced every second iteration: p^ and s^ of iteration
-  // 2k (ring 0) stay in their buffers while 2k+1 (ring 1) writes the others,
-  // and ring 1's update adds both terms (one read and write of x instead of
-  // two). Without a preconditioner s^ = s is overwritten at once, so x is
-  // advanced every iteration.
-  const bool defer = !identity && !cy.plain;
-  double2* const phr[2] = {c->fine[kPh].as<double2>(), c->fine[kPh2].as<double2>()};
-  double2* const shr[2] = {identity ? s : c->fine[kSh].as<double2>(), identity ? s : c->fine[kSh2].as<double2>()};
-  double2* ph = phr[0];
-  double2* sh = shr[0];
+// The vectors and flags of a BiCGSTAB run over the context's slots, and one
+// iteration of it for the first entries of the active list.
+struct BicgIter {
+  hz_ctx* c;
+  const hz_solve_opts* o;
+  Cycle cy;
+  size_t n0;
+  Batch bt;
+  Reduce rd;
+  Grid g0;
+  double2 *r, *rh, *pbuf[2], *p, *v, *s, *t, *x;
+  double2 *phr[2], *shr[2], *ph, *sh;
+  bool identity, fused, vfree, defer;
+  bool dense_rh = false;  // some active slot's r^ is a dense vector
+  int vt, gt;
 
-  long long seq = 0;                 // units issued
-  long long restart_seq = -1;        // last unit that was a restart
-  std::deque<std::pair<long long, int>> pending;  // (unit, ring slot)
-  int ring_next = 0;
-  auto close_unit = [&]() -> int {
-    const int k = ring_next;
-    ring_next = (ring_next + 1) % kRing;
-    HZ_HIP(c, launch_compact(nslots, c->cur_nrhs, c->cur_nfreq, bt.slots, c->active.as<int>(),
-                             c->nactive.as<int>(), c->fstart.as<int>(), c->ring_dev + k, 0, st));
-    HZ_HIP(c, hipEventRecord(c->ev[k], st));
-    pending.emplace_back(seq++, k);
-    return HZ_OK;
-  };
-
-  const int vt = vec_tiles(n0);
-  const int gt = reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
-  int rc;
-  HZ_HIP(c, launch_bicg_init(n0, bt, nslots, rd, b, x, r, rh, p, v, n0, st));
-  HZ_HIP(c, launch_bicg_fin(kFinInit, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
-  // the plain path keeps every r^ dense (rh_nnz = -1 from reset_slots)
-  if (!cy.plain)
-    HZ_HIP(c, launch_rh_sparse(n0, nslots, bt, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st));
-  if ((rc = close_unit()) != HZ_OK) return rc;
-  if (vfree) {  // whether the first iterations need the dense sigma pass
-    const int k = pending.back().second;
-    HZ_HIP(c, hipEventSynchronize(c->ev[k]));
-    dense_rh = c->ring_host[k].ndense > 0;
+  BicgIter(hz_ctx* cc, const hz_solve_opts* oo, const Cycle& cyy, double2* xx) : c(cc), o(oo), cy(cyy), x(xx) {
+    n0 = c->lv[0].n();
+    bt = batch_of(c);
+    rd = reducer(c);
+    g0 = grid_of(c, 0);
+    r = c->fine[kR].as<double2>();
+    rh = c->fine[kRh].as<double2>();
+    pbuf[0] = c->fine[kP].as<double2>();
+    pbuf[1] = c->fine[kP2].as<double2>();
+    p = pbuf[0];
+    v = c->fine[kV].as<double2>();
+    s = c->fine[kS].as<double2>();
+    t = c->fine[kT].as<double2>();
+    identity = cy.precond == HZ_PRECOND_NONE;
+    fused = fused_pre(cy) && c->dim != 3;
+    // 2D with the fused pre-smoothing kernel: v = B p^ is never stored. The
+    // pre-smoothing kernels form it from p^ (the last iteration's p^ for the p
+    // update, the current one for s), and sigma = <r^, B p^> is formed at the
+    // nodes of r^'s sparse list. Slots whose r^ is dense (a right-hand side
+    // with many nonzeros, or after a restart) take sigma from an operator pass
+    // that stores nothing, launched while any active slot needs it.
+    vfree = fused && c->dim == 2;
+    // The iterate is advanced every second iteration: p^ and s^ of iteration
+    // 2k (ring 0) stay in their buffers while 2k+1 (ring 1) writes the others,
+    // and ring 1's update adds both terms (one read and write of x instead of
+    // two). Without a preconditioner s^ = s is overwritten at once, so x is
+    // advanced every iteration.
+    defer = !identity && !cy.plain;
+    phr[0] = c->fine[kPh].as<double2>();
+    phr[1] = c->fine[kPh2].as<double2>();
+    shr[0] = identity ? s : c->fine[kSh].as<double2>();
+    shr[1] = identity ? s : c->fine[kSh2].as<double2>();
+    ph = phr[0];
+    sh = shr[0];
+    vt = vec_tiles(n0);
+    gt = reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
   }
 
-  int cap = nslots;
-  long long iters_issued = 0;
-  const long long guard = 2LL * (o->maxit + 2) + 16;
-  bool done = false;
+  // Start the slots of the list `lb` (cap entries): x = 0, r = r^ = b, the
+  // initial scalars and (unless plain) the sparse lists of r^ for the slots
+  // slot0 .. slot0 + nlist - 1.
+  hipError_t start(const Batch& lb, int cap, const double2* b, int slot0, int nlist) {
+    hipStream_t st = c->stream;
+    hipError_t e = launch_bicg_init(n0, lb, cap, rd, b, x, r, rh, p, v, n0, st);
+    if (e == hipSuccess) e = launch_bicg_fin(kFinInit, vt, lb, cap, rd, o->tol, o->maxit, nullptr, n0, st);
+    // the plain path keeps every r^ dense (rh_nnz = -1 in the slot records)
+    if (e == hipSuccess && !cy.plain)
+      e = launch_rh_sparse(n0, nlist, lb, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st, slot0);
+    return e;
+  }
 
   // One BiCGSTAB iteration for the first `capx` entries of the active list,
   // issued on stream `sx` (every launch of the path reads c->stream).
-  auto issue_iteration = [&](int capx, hipStream_t sx, int ring) -> hipError_t {
+  hipError_t issue(int capx, hipStream_t sx, int ring) {
     const hipStream_t saved = c->stream;
     c->stream = sx;
     hipError_t e = hipSuccess;
@@ -1000,7 +1019,56 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
     } while (false);
     c->stream = saved;
     return e;
+  }
+
+  // The one restart after a breakdown for the slots waiting for it (their
+  // pending iterate terms added first).
+  hipError_t restart(int nslots) {
+    hipStream_t st = c->stream;
+    hipError_t e = hipSuccess;
+    if (defer) e = launch_bicg_flush(n0, nslots, bt, 1, x, phr[0], shr[0], n0, st);
+    if (e == hipSuccess) e = launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st);  // current p buffer
+    if (e == hipSuccess) e = launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st);
+    dense_rh = true;  // r^ = r for the restarted slots
+    return e;
+  }
+};
+
+int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
+                 const double2* b, double2* x) {
+  BicgIter it(c, o, cy, x);
+  const Batch bt = it.bt;
+  const size_t n0 = it.n0;
+  hipStream_t st = c->stream;
+
+  long long seq = 0;                 // units issued
+  long long restart_seq = -1;        // last unit that was a restart
+  std::deque<std::pair<long long, int>> pending;  // (unit, ring slot)
+  int ring_next = 0;
+  auto close_unit = [&]() -> int {
+    const int k = ring_next;
+    ring_next = (ring_next + 1) % kRing;
+    HZ_HIP(c, launch_compact(nslots, c->cur_nrhs, c->cur_nfreq, bt.slots, c->active.as<int>(),
+                             c->nactive.as<int>(), c->fstart.as<int>(), c->ring_dev + k, 0, st));
+    HZ_HIP(c, hipEventRecord(c->ev[k], st));
+    pending.emplace_back(seq++, k);
+    return HZ_OK;
   };
+
+  int rc;
+  HZ_HIP(c, it.start(bt, nslots, b, 0, nslots));
+  if ((rc = close_unit()) != HZ_OK) return rc;
+  if (it.vfree) {  // whether the first iterations need the dense sigma pass
+    const int k = pending.back().second;
+    HZ_HIP(c, hipEventSynchronize(c->ev[k]));
+    it.dense_rh = c->ring_host[k].ndense > 0;
+  }
+
+  int cap = nslots;
+  long long iters_issued = 0;
+  const long long guard = 2LL * (o->maxit + 2) + 16;
+  bool done = false;
+  auto issue_iteration = [&](int capx, hipStream_t sx, int ring) { return it.issue(capx, sx, ring); };
 
   // HIP graphs: two iterations (the p buffers swap twice, so a pair starts
   // and ends on the same buffer) captured once per batch-size bucket (the
@@ -1031,7 +1099,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
   };
   auto issue_pair_graph = [&](int capx) -> int {
     const int cb = bucket(capx);
-    const int key = 2 * cb + (dense_rh ? 1 : 0);
+    const int key = 2 * cb + (it.dense_rh ? 1 : 0);
     auto it = graphs.find(key);
     if (it == graphs.end() && eager_pairs[key] == 0) {
       eager_pairs[key] = 1;
@@ -1067,13 +1135,10 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
       const bool stale = restart_seq > useq;
       if (!stale) {
         cap = std::min(cap, sm.nactive);
-        if (sm.nrestart == 0) dense_rh = sm.ndense > 0;
+        if (sm.nrestart == 0) it.dense_rh = sm.ndense > 0;
         if (sm.nrestart > 0) {
-          if (defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 1, x, phr[0], shr[0], n0, st));
-          HZ_HIP(c, launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st));  // current p buffer
-          HZ_HIP(c, launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st));
+          HZ_HIP(c, it.restart(nslots));
           restart_seq = seq;
-          dense_rh = true;  // r^ = r for the restarted slots
           if ((rc = close_unit()) != HZ_OK) return rc;
           cap = nslots;
         } else if (sm.nactive == 0) {
@@ -1098,7 +1163,7 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
     if ((rc = close_unit()) != HZ_OK) return rc;
   }
   // terms of slots that stopped after a ring-0 update
-  if (defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 0, x, phr[0], shr[0], n0, st));
+  if (it.defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 0, x, it.phr[0], it.shr[0], n0, st));
   HZ_HIP(c, hipStreamSynchronize(st));
   fold_timing(c);
   return HZ_OK;
@@ -2148,3 +2213,470 @@ const char* hz_status_str(int status) {
 const char* hz_last_error(const hz_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- continuous-batching engine
+struct hz_engine {
+  hz_ctx* c = nullptr;
+  int lanes = 0, width = 0, L = 0;
+  hz_solve_opts o{};
+  Cycle cy{};
+  DevBuf B, X;      // right-hand sides and iterates of every slot, [lanes * width][n]
+  DevBuf cwork;     // Gauss-Jordan work matrix of one lane
+  DevBuf list, count;  // a short active list (slots being started or finished)
+  DevBuf chk;       // model check output
+  int* fst_host = nullptr;  // pinned, [kRing][lanes + 1]: per-lane ranges of each summary's list
+  std::vector<FreqTab> ft;  // host copy of the lane table
+  size_t winv_per_lane = 0, nc = 0;
+  struct Part {
+    int lane, fi, off, cnt;  // right-hand sides off .. off + cnt - 1 of frequency fi
+  };
+  struct Running {
+    hz::EngineJob job;
+    std::vector<Part> parts;
+  };
+  std::vector<Running> running;
+  std::vector<int> free_lanes;
+  std::string err;
+};
+
+namespace {
+
+size_t level_nodes(int nz, int nx, int l) {
+  for (int k = 0; k < l; ++k) {
+    nz = coarse_n(nz);
+    nx = coarse_n(nx);
+  }
+  return (size_t)nz * nx;
+}
+
+int engine_levels(int nz, int nx, const hz_solve_opts* o) {
+  const int L = grid_default_levels(2, nz, nx);
+  return o->levels > 0 ? std::min(o->levels, grid_max_levels(2, nz, nx)) : L;
+}
+
+// Copies a request's model into a lane's model rows (every level), and its
+// smallest and largest slowness.
+int engine_model(hz_engine* e, int lane, const double* m_dev, double* mmin, double* mmax) {
+  hz_ctx* c = e->c;
+  const size_t n0 = c->lv[0].n();
+  double* m0 = c->lv[0].m.as<double>() + (size_t)lane * c->lv[0].mstride;
+  HZ_HIP(c, hipMemcpyAsync(m0, m_dev, n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  for (int l = 1; l < e->L; ++l) {
+    Grid gf = grid_of(c, l - 1);
+    gf.m += (size_t)lane * gf.mstride;
+    gf.mstride = 0;
+    HZ_HIP(c, launch_inject(gf, 2, c->lv[l].m.as<double>() + (size_t)lane * c->lv[l].mstride, c->stream));
+  }
+  HZ_HIP(c, launch_check_model(n0, m0, e->chk.as<double>(), c->stream));
+  double out3[3];
+  HZ_HIP(c, hipMemcpyAsync(out3, e->chk.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  if (out3[2] > 0.0) return fail(c, HZ_ERR_ARG, "slowness has %.0f entries that are not finite and positive", out3[2]);
+  *mmin = out3[0];
+  *mmax = out3[1];
+  return HZ_OK;
+}
+
+// The lane table entry of one (request, frequency): plan weights, w / D
+// tables, coarse inverse or coarse smoothing, the model it reads.
+int engine_lane_setup(hz_engine* e, int lane, int model, double mmin, double mmax, double freq_hz, double alpha) {
+  hz_ctx* c = e->c;
+  FreqTab& f = e->ft[lane];
+  memset(&f, 0, sizeof f);
+  f.omega = 2.0 * M_PI * freq_hz;
+  f.sB_re = 1.0;
+  f.sB_im = -alpha;
+  f.sM_re = e->o.beta1;
+  f.sM_im = -e->o.beta2;
+  f.model = model;
+  int L = 0;
+  double w[kMaxLevels] = {};
+  hz_solve_opts po = e->o;
+  po.levels = e->L;
+  int rc = plan_grid(2, c->nz, 1, c->nx, c->maxlev, e->L, c->h, mmin, mmax, &po, f.omega, &L, w);
+  if (rc != HZ_OK || L != e->L) return fail(c, HZ_ERR_SHAPE, "cannot plan the V-cycle of a lane");
+  for (int l = 0; l < L - 1; ++l) f.wj[l] = w[l];
+  double2* wp = c->winv.as<double2>() + (size_t)lane * e->winv_per_lane;
+  for (int l = 0; l < L - 1; ++l) {
+    Grid g = grid_of(c, l);
+    g.m += (size_t)model * g.mstride;
+    g.mstride = 0;
+    HZ_HIP(c, launch_winv(2, g, f.omega, f.sM_re, f.sM_im, f.wj[l], wp, c->stream));
+    f.winv[l] = wp;
+    wp += c->lv[l].n();
+  }
+  const int cl = L - 1;
+  f.coarse_jacobi = !coarse_is_exact(&e->o, L, c->lv[cl].h, mmin, f.omega) ? 1 : 0;
+  double2* cinv = c->cinv_a.as<double2>() + (size_t)lane * e->nc * e->nc;
+  f.cinv = cinv;
+  HZ_HIP(c, hipMemcpyAsync(c->freqtab.as<FreqTab>() + lane, &f, sizeof f, hipMemcpyHostToDevice, c->stream));
+  if (!f.coarse_jacobi) {
+    Grid g = grid_of(c, cl);
+    g.m += (size_t)model * g.mstride;
+    g.mstride = 0;
+    double2* work = e->cwork.as<double2>();
+    HZ_HIP(c, launch_assemble_dense(2, g, 1, c->freqtab.as<FreqTab>() + lane, work, c->stream));
+    double2* src = work;
+    double2* dst = cinv;
+    for (size_t k = 0; k < e->nc; ++k) {
+      HZ_HIP(c, launch_gj_step((int)e->nc, 1, (int)k, src, dst, c->stream));
+      std::swap(src, dst);
+    }
+    if (src != cinv)
+      HZ_HIP(c, hipMemcpyAsync(cinv, src, e->nc * e->nc * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+  }
+  return HZ_OK;
+}
+
+// The slots k0 .. k0 + cnt - 1 as a short active list (a batch over them).
+int engine_list(hz_engine* e, const std::vector<int>& slots, Batch* lb) {
+  hz_ctx* c = e->c;
+  const int n = (int)slots.size();
+  HZ_HIP(c, hipMemcpyAsync(e->list.p, slots.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipMemcpyAsync(e->count.p, &n, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  *lb = batch_of(c);
+  lb->active = e->list.as<int>();
+  lb->nactive = e->count.as<int>();
+  return HZ_OK;
+}
+
+}  // namespace
+
+namespace hz {
+
+size_t engine_bytes(int nz, int nx, int lanes, int width, const hz_solve_opts* o) {
+  const int L = engine_levels(nz, nx, o);
+  const size_t slots = (size_t)lanes * width;
+  const size_t z = sizeof(double2);
+  size_t bytes = 0;
+  const size_t n0 = (size_t)nz * nx;
+  for (int l = 0; l < L; ++l) bytes += lanes * level_nodes(nz, nx, l) * sizeof(double);  // models
+  bytes += (size_t)(kNumFine + 2) * slots * n0 * z;  // Krylov vectors, right-hand sides, iterates
+  for (int l = 1; l < L; ++l) bytes += (size_t)kNumLevelVec * slots * level_nodes(nz, nx, l) * z;
+  for (int l = 0; l + 1 < L; ++l) bytes += lanes * level_nodes(nz, nx, l) * z;  // w / D tables
+  const size_t nc = level_nodes(nz, nx, L - 1);
+  bytes += (lanes + 1) * nc * nc * z;  // coarse inverses and the work matrix
+  const Tiles t = grid_tiles(nz, nx, 2);
+  const int tiles = std::max({t.per_slot, reduce_tiles(nz, nx, 2), vec_tiles(n0)});
+  bytes += slots * ((size_t)tiles * kPartialWidth * sizeof(double) + sizeof(Slot) + kShadowMax * (sizeof(int) + z) +
+                    2 * sizeof(double) + 2 * sizeof(int));
+  bytes += lanes * sizeof(FreqTab) + (lanes + 1) * sizeof(int) + 4096;
+  return bytes;
+}
+
+int engine_create(hz_engine** out, int device, void* stream, int nz, int nx, double h, int lanes, int width,
+                  const hz_solve_opts* o) {
+  if (!out || !o || nz < 5 || nx < 5 || !(h > 0.0) || lanes < 1 || width < 1) return HZ_ERR_ARG;
+  *out = nullptr;
+  if (o->krylov != HZ_BICGSTAB || o->precond != HZ_PRECOND_MG || o->plain) return HZ_ERR_ARG;
+  hz_engine* e = new hz_engine();
+  const hz_ctx_opts co{device, stream, 0};
+  int rc = hz_create(&e->c, &co);
+  if (rc != HZ_OK) {
+    delete e;
+    return rc;
+  }
+  hz_ctx* c = e->c;
+  e->lanes = lanes;
+  e->width = width;
+  e->o = *o;
+  e->o.jacobi_w_level = nullptr;
+  e->L = engine_levels(nz, nx, o);
+  auto bail = [&](int code) {
+    e->err = c->err;
+    engine_destroy(e);
+    return code;
+  };
+  // the grid of every level, one model row per lane
+  c->dim = 2;
+  c->nz = nz;
+  c->ny = 1;
+  c->nx = nx;
+  c->h = h;
+  c->maxlev = grid_max_levels(2, nz, nx);
+  if ((rc = check_opts(c, &e->o)) != HZ_OK) return bail(rc);
+  if (e->L < 2) return bail(fail(c, HZ_ERR_SHAPE, "the engine needs at least two levels"));
+  for (int l = 0; l < e->L; ++l) {
+    LevelInfo& lv = c->lv[l];
+    lv.nz = l == 0 ? nz : coarse_n(c->lv[l - 1].nz);
+    lv.nx = l == 0 ? nx : coarse_n(c->lv[l - 1].nx);
+    lv.ny = 1;
+    lv.h = l == 0 ? h : 2.0 * c->lv[l - 1].h;
+    lv.mstride = lv.n();
+    if (lv.m.ensure((size_t)lanes * lv.n() * sizeof(double)) != hipSuccess) return bail(HZ_ERR_NOMEM);
+  }
+  e->nc = c->lv[e->L - 1].n();
+  if (coarse_is_exact(&e->o, e->L, c->lv[e->L - 1].h, 0.0, 1.0) && e->nc > (size_t)kCoarseMax)
+    return bail(fail(c, HZ_ERR_SHAPE, "coarsest level above %d unknowns", kCoarseMax));
+  const int nslots = lanes * width;
+  if ((rc = ensure_workspace(c, nslots, e->L)) != HZ_OK) return bail(rc);
+  const size_t n0 = c->lv[0].n();
+  for (int l = 0; l + 1 < e->L; ++l) e->winv_per_lane += c->lv[l].n();
+  if (c->winv.ensure((size_t)lanes * e->winv_per_lane * sizeof(double2)) != hipSuccess ||
+      c->cinv_a.ensure((size_t)lanes * e->nc * e->nc * sizeof(double2)) != hipSuccess ||
+      e->cwork.ensure(e->nc * e->nc * sizeof(double2)) != hipSuccess ||
+      c->freqtab.ensure((size_t)lanes * sizeof(FreqTab)) != hipSuccess ||
+      c->fstart.ensure((size_t)(lanes + 1) * sizeof(int)) != hipSuccess ||
+      e->B.ensure((size_t)nslots * n0 * sizeof(double2)) != hipSuccess ||
+      e->X.ensure((size_t)nslots * n0 * sizeof(double2)) != hipSuccess ||
+      e->list.ensure((size_t)nslots * sizeof(int)) != hipSuccess || e->count.ensure(sizeof(int)) != hipSuccess ||
+      e->chk.ensure(4 * sizeof(double)) != hipSuccess)
+    return bail(fail(c, HZ_ERR_NOMEM, "engine buffers"));
+  void* fh = nullptr;
+  if (hipHostMalloc(&fh, (size_t)kRing * (lanes + 1) * sizeof(int)) != hipSuccess) return bail(HZ_ERR_NOMEM);
+  e->fst_host = static_cast<int*>(fh);
+  e->ft.assign(lanes, FreqTab{});
+  for (int k = 0; k < lanes; ++k) {
+    e->ft[k].model = k;
+    e->free_lanes.push_back(lanes - 1 - k);  // handed out from the back: lane 0 first
+  }
+  HZ_HIP(c, hipMemcpyAsync(c->freqtab.p, e->ft.data(), lanes * sizeof(FreqTab), hipMemcpyHostToDevice, c->stream));
+  // every slot idle (not in any list) until a lane is given to a request
+  std::vector<Slot> sl(nslots);
+  for (int i = 0; i < nslots; ++i) {
+    memset(&sl[i], 0, sizeof(Slot));
+    sl[i].status = kConverged;
+    sl[i].freq = i / width;
+    sl[i].rh_nnz = -1;
+  }
+  HZ_HIP(c, hipMemcpyAsync(c->slots.p, sl.data(), nslots * sizeof(Slot), hipMemcpyHostToDevice, c->stream));
+  const int zero = 0;
+  HZ_HIP(c, hipMemcpyAsync(c->nactive.p, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  c->cur_nfreq = lanes;
+  c->cur_nrhs = width;
+  e->cy = Cycle{e->L, e->o.nu1, e->o.nu2, HZ_PRECOND_MG, e->o.autotune, e->o.chunk_rows, e->o.coarse_sweeps, 0};
+  *out = e;
+  return HZ_OK;
+}
+
+void engine_destroy(hz_engine* e) {
+  if (!e) return;
+  if (e->c) {
+    (void)hipSetDevice(e->c->device);
+    (void)hipStreamSynchronize(e->c->stream);
+  }
+  if (e->fst_host) (void)hipHostFree(e->fst_host);
+  e->B.release();
+  e->X.release();
+  e->cwork.release();
+  e->list.release();
+  e->count.release();
+  e->chk.release();
+  hz_destroy(e->c);
+  delete e;
+}
+
+size_t engine_allocated(const hz_engine* e) {
+  const hz_ctx* c = e->c;
+  size_t b = e->B.bytes + e->X.bytes + e->cwork.bytes + e->list.bytes + e->count.bytes + e->chk.bytes;
+  for (const auto& v : c->fine) b += v.bytes;
+  for (const auto& lv : c->lev)
+    for (const auto& v : lv) b += v.bytes;
+  for (const auto& lv : c->lv) b += lv.m.bytes;
+  for (const DevBuf* v : {&c->slots, &c->active, &c->nactive, &c->freqtab, &c->partials, &c->resid, &c->fstart,
+                          &c->rh_idx, &c->rh_val, &c->cinv_a, &c->cinv_b, &c->winv})
+    b += v->bytes;
+  return b;
+}
+
+const char* engine_error(const hz_engine* e) { return e ? (e->err.empty() ? e->c->err.c_str() : e->err.c_str()) : ""; }
+
+int engine_run(hz_engine* e, EngineHooks& hooks) {
+  hz_ctx* c = e->c;
+  HZ_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const int nslots = e->lanes * e->width;
+  const int W = e->width;
+  const size_t n0 = c->lv[0].n();
+  BicgIter it(c, &e->o, e->cy, e->X.as<double2>());
+  const Batch bt = it.bt;
+  double2* Bv = e->B.as<double2>();
+  double2* Xv = e->X.as<double2>();
+
+  long long seq = 0, restart_seq = -1, admit_seq = -1;
+  std::deque<std::pair<long long, int>> pending;
+  int ring_next = 0;
+  auto close_unit = [&]() -> int {
+    const int k = ring_next;
+    ring_next = (ring_next + 1) % kRing;
+    HZ_HIP(c, launch_compact(nslots, W, e->lanes, bt.slots, c->active.as<int>(), c->nactive.as<int>(),
+                             c->fstart.as<int>(), c->ring_dev + k, 0, st));
+    HZ_HIP(c, hipMemcpyAsync(e->fst_host + (size_t)k * (e->lanes + 1), c->fstart.p, (e->lanes + 1) * sizeof(int),
+                             hipMemcpyDeviceToHost, st));
+    HZ_HIP(c, hipEventRecord(c->ev[k], st));
+    pending.emplace_back(seq++, k);
+    return HZ_OK;
+  };
+  // A finished job: pending iterate terms, true residuals, the result.
+  auto finish = [&](hz_engine::Running& run) -> int {
+    const EngineJob& jb = run.job;
+    std::vector<int> sl;
+    std::vector<int> at;  // info index of each listed slot
+    for (const auto& pt : run.parts) {
+      HZ_HIP(c, launch_bicg_flush(n0, pt.cnt, bt, 0, Xv, it.phr[0], it.shr[0], n0, st, pt.lane * W));
+      HZ_HIP(c, hipMemcpyAsync(jb.u_dev + ((size_t)pt.fi * jb.nrhs + pt.off) * n0, Xv + (size_t)pt.lane * W * n0,
+                               (size_t)pt.cnt * n0 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      for (int k = 0; k < pt.cnt; ++k) {
+        sl.push_back(pt.lane * W + k);
+        at.push_back(pt.fi * jb.nrhs + pt.off + k);
+      }
+    }
+    Batch lb;
+    int rc = engine_list(e, sl, &lb);
+    if (rc) return rc;
+    HZ_HIP(c, launch_true_residual(2, grid_of(c, 0), lb, (int)sl.size(), it.rd, Bv, Xv, c->resid.as<double>(), n0, st));
+    std::vector<Slot> rec(nslots);
+    std::vector<double> res(2 * (size_t)nslots);
+    HZ_HIP(c, hipMemcpyAsync(rec.data(), c->slots.p, nslots * sizeof(Slot), hipMemcpyDeviceToHost, st));
+    HZ_HIP(c, hipMemcpyAsync(res.data(), c->resid.p, 2 * nslots * sizeof(double), hipMemcpyDeviceToHost, st));
+    HZ_HIP(c, hipStreamSynchronize(st));
+    std::vector<hz_rhs_info> info(sl.size());
+    int any_fail = 0;
+    for (size_t i = 0; i < sl.size(); ++i) {
+      const Slot& sr = rec[sl[i]];
+      int stt = sr.status;
+      if (stt == kActive) stt = kMaxit;
+      if (stt == kRestart) stt = kBreakdown;
+      if (stt != kConverged) any_fail = 1;
+      hz_rhs_info& in = info[at[i]];
+      in.status = stt;
+      in.iters = sr.iters;
+      const double r2 = res[2 * (size_t)sl[i]], b2 = res[2 * (size_t)sl[i] + 1];
+      in.relres = b2 > 0.0 ? sqrt(r2) / sqrt(b2) : 0.0;
+      in.seconds = c->wall_khz > 0.0 ? (double)(sr.t1 - sr.t0) / (c->wall_khz * 1e3) : 0.0;
+    }
+    for (const auto& pt : run.parts) e->free_lanes.push_back(pt.lane);
+    hooks.done(jb.tag, any_fail ? HZ_WARN_NOCONV : HZ_OK, info);
+    return HZ_OK;
+  };
+  // A new job: its model, ceil(nrhs / width) lanes per frequency (the lanes
+  // of one frequency share the first one's tables), its right-hand sides started.
+  auto admit = [&](EngineJob& jb) -> int {
+    hz_engine::Running run;
+    run.job = jb;
+    const int per = (jb.nrhs + W - 1) / W;
+    for (int fi = 0; fi < jb.nfreq; ++fi)
+      for (int q = 0; q < per; ++q) {
+        run.parts.push_back({e->free_lanes.back(), fi, q * W, std::min(W, jb.nrhs - q * W)});
+        e->free_lanes.pop_back();
+      }
+    const int model = run.parts[0].lane;
+    double mmin = 0.0, mmax = 0.0;
+    int rc = engine_model(e, model, jb.m_dev, &mmin, &mmax);
+    std::vector<int> sl;
+    int first = -1;
+    for (const auto& pt : run.parts) {
+      if (rc) break;
+      if (pt.off == 0) {
+        first = pt.lane;
+        rc = engine_lane_setup(e, pt.lane, model, mmin, mmax, jb.freq_hz[pt.fi], jb.alpha);
+        if (rc) break;
+      } else {
+        e->ft[pt.lane] = e->ft[first];
+        HZ_HIP(c, hipMemcpyAsync(c->freqtab.as<FreqTab>() + pt.lane, &e->ft[pt.lane], sizeof(FreqTab),
+                                 hipMemcpyHostToDevice, st));
+      }
+      std::vector<Slot> srec(pt.cnt);
+      for (int k = 0; k < pt.cnt; ++k) {
+        memset(&srec[k], 0, sizeof(Slot));
+        srec[k].status = kActive;
+        srec[k].freq = pt.lane;
+        srec[k].rh_nnz = -1;
+        sl.push_back(pt.lane * W + k);
+      }
+      HZ_HIP(c, hipMemcpyAsync(bt.slots + pt.lane * W, srec.data(), pt.cnt * sizeof(Slot), hipMemcpyHostToDevice, st));
+      HZ_HIP(c, hipMemcpyAsync(Bv + (size_t)pt.lane * W * n0, jb.b_dev + ((size_t)pt.fi * jb.nrhs + pt.off) * n0,
+                               (size_t)pt.cnt * n0 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      HZ_HIP(c, hipStreamSynchronize(st));  // srec is read before it goes out of scope
+    }
+    if (rc != HZ_OK) {
+      for (const auto& pt : run.parts) e->free_lanes.push_back(pt.lane);
+      std::vector<hz_rhs_info> none;
+      hooks.done(jb.tag, rc, none);
+      return HZ_OK;  // the job is refused; the engine goes on
+    }
+    Batch lb;
+    if ((rc = engine_list(e, sl, &lb)) != HZ_OK) return rc;
+    HZ_HIP(c, it.start(lb, (int)sl.size(), Bv, 0, 0));
+    for (const auto& pt : run.parts)
+      HZ_HIP(c, launch_rh_sparse(n0, pt.cnt, bt, Bv, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st,
+                                 pt.lane * W));
+    e->running.push_back(std::move(run));
+    return HZ_OK;
+  };
+
+  int cap = 0;
+  long long iters_issued = 0;
+  int rc = HZ_OK;
+  for (;;) {
+    // summaries of finished units
+    while (!pending.empty() && ((int)pending.size() > kLag || cap == 0)) {
+      const auto [useq, k] = pending.front();
+      pending.pop_front();
+      HZ_HIP(c, hipEventSynchronize(c->ev[k]));
+      const Summary sm = c->ring_host[k];
+      if (restart_seq > useq) continue;
+      const bool fresh = admit_seq < useq;  // every running job's slots were in this unit's list
+      if (sm.nrestart > 0) {
+        HZ_HIP(c, it.restart(nslots));
+        restart_seq = seq;
+        if ((rc = close_unit()) != HZ_OK) return rc;
+        cap = nslots;
+        continue;
+      }
+      if (!fresh) continue;
+      cap = std::min(cap, sm.nactive);
+      it.dense_rh = sm.ndense > 0;
+      const int* fs = e->fst_host + (size_t)k * (e->lanes + 1);
+      for (size_t j = 0; j < e->running.size();) {
+        bool all_done = true;
+        for (const auto& pt : e->running[j].parts) all_done = all_done && fs[pt.lane + 1] == fs[pt.lane];
+        if (!all_done) {
+          ++j;
+          continue;
+        }
+        if ((rc = finish(e->running[j])) != HZ_OK) return rc;
+        e->running.erase(e->running.begin() + j);
+      }
+    }
+    // New jobs between iterations, after an even number of them: a slot's
+    // first iteration is then a ring-0 one, as in hz_solve, so its iterate
+    // is advanced in the same order and comes out bitwise the same. With no
+    // job left every pending term has been flushed and the count restarts.
+    if (e->running.empty()) iters_issued = 0;
+    const bool idle = e->running.empty() && pending.empty();
+    std::vector<EngineJob> jobs;
+    bool go = true;
+    if ((iters_issued & 1) == 0) go = hooks.next((int)e->free_lanes.size(), idle, jobs);
+    int added = 0;
+    for (EngineJob& jb : jobs) {
+      if (jb.nrhs < 1 || jb.nfreq < 1 || (long long)jb.nfreq * ((jb.nrhs + W - 1) / W) > (long long)e->free_lanes.size()) {
+        std::vector<hz_rhs_info> none;
+        hooks.done(jb.tag, HZ_ERR_ARG, none);
+        continue;
+      }
+      if ((rc = admit(jb)) != HZ_OK) return rc;
+      added += jb.nfreq * jb.nrhs;
+    }
+    if (added > 0) {
+      admit_seq = seq;
+      it.dense_rh = true;  // until a summary has seen the new slots' lists
+      cap = std::min(nslots, cap + added);
+      if ((rc = close_unit()) != HZ_OK) return rc;
+    }
+    if (!go && e->running.empty() && pending.empty()) break;
+    if (cap == 0) {
+      // nothing to iterate: take a summary so that finished jobs are seen
+      if (pending.empty() && !e->running.empty() && (rc = close_unit()) != HZ_OK) return rc;
+      continue;
+    }
+    HZ_HIP(c, it.issue(cap, st, (int)(iters_issued & 1)));
+    ++iters_issued;
+    if ((rc = close_unit()) != HZ_OK) return rc;
+  }
+  HZ_HIP(c, hipStreamSynchronize(st));
+  return HZ_OK;
+}
+
+}  // namespace hz

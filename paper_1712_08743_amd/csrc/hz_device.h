@@ -60,6 +60,11 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 __device__ __forceinline__ bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 __device__ __forceinline__ bool czero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
 
+// The slowness on grid g of the model that frequency entry f solves with.
+__device__ __forceinline__ const double* model_m(const Grid& g, const FreqTab& f) {
+  return g.m + (size_t)f.model * g.mstride;
+}
+
 struct NodeC {
   double wz, wx, lsum;
   double2 kap;

@@ -37,6 +37,9 @@ struct Grid {
   double h;
   const double* m;  // device, [nz][nx] ([nz][ny][nx] on 3D grids)
   int ny = 1;       // 3D grids only
+  // models of several requests in one batch: frequency entry f reads its
+  // slowness at m + FreqTab::model * mstride (0: one model for every entry)
+  size_t mstride = 0;
 };
 
 // Per-frequency constants (device table).
@@ -48,6 +51,7 @@ struct FreqTab {
   const double2* cinv;               // inverse of M on the coarsest level, [nc][nc]
   int coarse_jacobi;                 // 1: the coarsest level is smoothed, not solved exactly
   const double2* winv[kMaxLevels];   // w_l / diag(M_l) on each smoothing level, [n_l]
+  int model;                         // which model of the batch (see Grid::mstride)
 };
 
 // Per right-hand-side Krylov scalars (device array, one per slot).
@@ -243,8 +247,9 @@ hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, 
                           double2* r, const double2* rh, size_t stride, hipStream_t st, int ring = -1,
                           const double2* ph0 = nullptr, const double2* sh0 = nullptr);
 // Adds the pending term to x (all nslots slots, or only those about to restart).
+// (slots slot0 .. slot0 + nslots - 1)
 hipError_t launch_bicg_flush(size_t n, int nslots, const Batch& bt, int only_restart, double2* x,
-                             const double2* ph0, const double2* sh0, size_t stride, hipStream_t st);
+                             const double2* ph0, const double2* sh0, size_t stride, hipStream_t st, int slot0 = 0);
 hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
                                const double2* r, double2* rh, double2* p, double2* v,
                                size_t stride, hipStream_t st);
@@ -252,7 +257,7 @@ hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Redu
 // where b has more than kShadowMax nonzeros). idx/val: the arrays Batch
 // points to, writable.
 hipError_t launch_rh_sparse(size_t n, int nslots, const Batch& bt, const double2* b, int* idx, double2* val,
-                            size_t stride, hipStream_t st);
+                            size_t stride, hipStream_t st, int slot0 = 0);
 enum : int { kFinInit = 0, kFinSigma = 1, kFinOmega = 2, kFinStep = 3, kFinRestart = 4, kFinSigmaB = 5 };
 // tiles: the producer's tiles per slot; restart runs over all nslots slots.
 // vec: for sigma v, for sigma-B p^ (v = B p^ is formed at the nodes of a

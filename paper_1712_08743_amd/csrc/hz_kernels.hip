@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(kBlock) k_apply(Grid g, Tiles t, int lvl, int 
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const double sre = which ? f.sM_re : f.sB_re, sim = which ? f.sM_im : f.sB_im;
   const int p = iz * g.nx + ix;
-  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, sre, sim);
+  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, sre, sim);
   const double2* xs = x + (size_t)slot * stride;
   y[(size_t)slot * stride + p] = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
   (void)lvl;
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth(Grid g, Tiles t, int lvl, dou
   if (coarse_only && !f.coarse_jacobi) return;
   const int p = iz * g.nx + ix;
   const double ih2 = 1.0 / (g.h * g.h);
-  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
+  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
   // w / diag(M): tabulated per frequency and level, or formed here for an explicit weight
   const double2 wdinv = w_override > 0.0 ? cscale(w_override, cinv(diag_of<D2>(c, ih2))) : f.winv[lvl][p];
   const size_t base = (size_t)slot * stride;
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid gf, Grid gc, Tiles t, 
       const int ix = 2 * Ix + dx;
       if (ix < 0 || ix >= gf.nx) continue;
       const int p = iz * gf.nx + ix;
-      const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
+      const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
       const double2 r = csub(bs[p], apply_node<D2>(us, p, iz, ix, gf.nz, gf.nx, ih2, c, us[p]));
       const double wxt = (dx == 0 || (dx == 1 && 2 * Ix + 2 == gf.nx)) ? 1.0 : 0.5;
       row = cadd(row, cscale(wxt, r));
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_pre2(Grid g, Tiles t, int lvl, Batch
   const double2* wd = f.winv[lvl];
   // u1 at a node q: (w / D_q) b_q
   auto u1_at = [&](int q) -> double2 { return cmul(rhs_at<MODE>(in, base + q, beta, om, al), wd[q]); };
-  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
+  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
   const double2 wdp = wd[p];
   const double2 bp = rhs_at<MODE>(in, base + p, beta, om, al);
   const double2 u1p = cmul(bp, wdp);
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth(Grid gf, Grid gc, Til
     return cadd(us[qz * gf.nx + qx], interp<D2>(es, qz, qx, gc.nx, gc.nz));
   };
   const int p = iz * gf.nx + ix;
-  const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
+  const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
   const double2 u3p = u3_at(iz, ix);
   double2 sx = c2(0.0, 0.0), sz = c2(0.0, 0.0);
   if (ix > 0) sx = cadd(sx, u3_at(iz, ix - 1));
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_t(Grid g, int ntx, int per_sl
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= g.nz || ix >= g.nx) continue;
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, g.m[p], f.omega, f.sM_re, f.sM_im);
+    const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
     double2 sx, sz;
     halo_sums(U, lz, lx, sx, sz);
     const double2 up = U[lz + 1][lx + 1];
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth_t(Grid gf, Grid gc, i
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= gf.nz || ix >= gf.nx) continue;
     const int p = iz * gf.nx + ix;
-    const NodeC c = node_coef<true>(iz, ix, gf.nz, gf.nx, ih, gf.m[p], f.omega, f.sM_re, f.sM_im);
+    const NodeC c = node_coef<true>(iz, ix, gf.nz, gf.nx, ih, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
     double2 sx, sz;
     halo_sums(U, lz, lx, sx, sz);
     const double2 u3p = U[lz + 1][lx + 1];
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(kRtx * kRtz) k_restrict_tiled(Grid gf, Grid gc
     double2 r = c2(0.0, 0.0);
     if (iz >= 0 && iz < gf.nz && ix >= 0 && ix < gf.nx) {
       const int p = iz * gf.nx + ix;
-      const NodeC c = node_coef<true>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
+      const NodeC c = node_coef<true>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
       const int uz = lz + 1, ux = lx + 1;
       double2 sx = c2(0.0, 0.0), sz = c2(0.0, 0.0);
       if (ix > 0) sx = cadd(sx, U[uz][ux - 1]);
@@ -498,7 +498,8 @@ __global__ void k_assemble_dense(Grid g, int nfreq, const FreqTab* __restrict__ 
     const int i = (int)(rem / nc), j = (int)(rem - (size_t)i * nc);
     const int iz = i / g.nx, ix = i - iz * g.nx;
     const int jz = j / g.nx, jx = j - jz * g.nx;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[i], ft[f].omega, ft[f].sM_re, ft[f].sM_im);
+    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, ft[f])[i], ft[f].omega, ft[f].sM_re,
+                                  ft[f].sM_im);
     double2 val = c2(0.0, 0.0);
     if (i == j) {
       val = diag_of<D2>(c, ih2);
@@ -557,7 +558,7 @@ __global__ void __launch_bounds__(1024) k_pcr(Grid g, Batch bt, const double2* _
   const double ih2 = 1.0 / (g.h * g.h);
   const double2* bs = b + (size_t)slot * stride;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const NodeC c = node_coef<false>(0, i, 1, n, 1.0 / g.h, g.m[i], f.omega, f.sM_re, f.sM_im);
+    const NodeC c = node_coef<false>(0, i, 1, n, 1.0 / g.h, model_m(g, f)[i], f.omega, f.sM_re, f.sM_im);
     A[i] = c2(i > 0 ? -ih2 : 0.0, 0.0);
     Cu[i] = c2(i < n - 1 ? -ih2 : 0.0, 0.0);
     Bd[i] = diag_of<false>(c, ih2);
@@ -724,7 +725,7 @@ __global__ void __launch_bounds__(kBlock) k_apply3(Grid g, Tiles t, int which, B
   if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, g, iz, iy, ix, p)) return;
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const double sre = which ? f.sM_re : f.sB_re, sim = which ? f.sM_im : f.sB_im;
-  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, sre, sim);
+  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, sre, sim);
   const double2* xs = x + (size_t)slot * stride;
   y[(size_t)slot * stride + p] = apply_node3(xs, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
 }
@@ -741,7 +742,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   if (coarse_only && !f.coarse_jacobi) return;
   const double ih2 = 1.0 / (g.h * g.h);
-  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
+  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
   const double2 wdinv = w_override > 0.0 ? cscale(w_override, cinv(diag3(c, ih2))) : f.winv[lvl][p];
   const size_t base = (size_t)slot * stride;
   const double2 bp = b[base + p];
@@ -917,7 +918,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict3(Grid gf, Grid gc, Tiles t,
         const int ix = 2 * Ix + dx;
         if (ix < 0 || ix >= gf.nx) continue;
         const size_t p = ((size_t)iz * gf.ny + iy) * gf.nx + ix;
-        const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
+        const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
         const double2 r = csub(bs[p], apply_node3(us, p, iz, iy, ix, gf, ih2, c));
         acc = cadd(acc, cscale(wzy * pt_weight(dx, Ix, gf.nx), r));
       }
@@ -935,7 +936,7 @@ __global__ void __launch_bounds__(kBlock) k_residual3(Grid g, Tiles t, Batch bt,
   if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, g, iz, iy, ix, p)) return;
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const size_t base = (size_t)slot * stride;
-  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
+  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
   r[base + p] = csub(b[base + p], apply_node3(u + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c));
 }
 
@@ -1001,7 +1002,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth3(Grid gf, Grid gc, Ti
   auto u3_at = [&](int qz, int qy, int qx) -> double2 {
     return cadd(us[((size_t)qz * gf.ny + qy) * gf.nx + qx], interp3(es, qz, qy, qx, gc.nz, gc.ny, gc.nx));
   };
-  const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, gf.m[p], f.omega, f.sM_re, f.sM_im);
+  const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
   const double2 u3p = u3_at(iz, iy, ix);
   double2 sz = c2(0.0, 0.0), sy = c2(0.0, 0.0), sx = c2(0.0, 0.0);
   if (ix > 0) sx = cadd(sx, u3_at(iz, iy, ix - 1));
@@ -1025,7 +1026,8 @@ __global__ void k_assemble_dense3(Grid g, int nfreq, const FreqTab* __restrict__
     const int i = (int)(rem / nc), j = (int)(rem - (size_t)i * nc);
     const int ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
     const int jx = j % g.nx, jy = (j / g.nx) % g.ny, jz = j / (g.nx * g.ny);
-    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[i], ft[f].omega, ft[f].sM_re, ft[f].sM_im);
+    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, ft[f])[i], ft[f].omega, ft[f].sM_re,
+                                ft[f].sM_im);
     double2 val = c2(0.0, 0.0);
     if (i == j) {
       val = diag3(c, ih2);

@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
   const bool dense_rh = bt.slots[slot].rh_nnz < 0;  // else <rh, v> is formed from the sparse list
   if (iz < g.nz && ix < g.nx) {
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2* xs = ph + base;
     const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
     v[base + p] = y;
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= g.nz || ix >= g.nx) continue;
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     double2 sx, sz;
     halo_sums(X, lz, lx, sx, sz);
     const double2 yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply3(Grid g, Tiles t, Batch b
   int iz, iy, ix;
   size_t p;
   if (node3_of(t, tile, g, iz, iy, ix, p)) {
-    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2 yp = apply_node3(xin + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
     y[base + p] = yp;
     if (WHICH == 0) {
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_omega(Grid g, Tiles t, Ba
   double acc[3] = {0.0, 0.0, 0.0};
   if (iz < g.nz && ix < g.nx) {
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2* xs = sh + base;
     const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
     tv[base + p] = y;
@@ -312,9 +312,9 @@ k_bicg_xr(Batch bt, int tiles, size_t n, Reduce rd, double2* __restrict__ x, con
 // at the end of a solve; the restarting ones before a restart).
 __global__ void __launch_bounds__(kBlock) k_bicg_flush(Batch bt, int tiles, size_t n, int only_restart,
                                                        double2* __restrict__ x, const double2* __restrict__ ph0,
-                                                       const double2* __restrict__ sh0, size_t stride) {
-  const int slot = blockIdx.x / tiles;
-  const int tile = blockIdx.x - slot * tiles;
+                                                       const double2* __restrict__ sh0, size_t stride, int slot0) {
+  const int slot = slot0 + (int)(blockIdx.x / tiles);
+  const int tile = blockIdx.x - (slot - slot0) * tiles;
   const Slot& S = bt.slots[slot];
   if (!S.pending || (only_restart && S.status != kRestart)) return;
   const double2 al0 = S.pend_alpha, om0 = S.pend_omega;
@@ -363,11 +363,11 @@ __global__ void __launch_bounds__(kBlock) k_bicg_restart(int tiles, size_t n, Ba
 // rh_nnz = -1 (r^ stays a dense vector).
 __global__ void __launch_bounds__(kBlock) k_rh_sparse(size_t n, Batch bt, const double2* __restrict__ b,
                                                       int* __restrict__ idx, double2* __restrict__ val,
-                                                      size_t stride) {
+                                                      size_t stride, int slot0) {
   __shared__ int count;
   __shared__ int sidx[kShadowMax];
   __shared__ double2 sval[kShadowMax];
-  const int slot = blockIdx.x;
+  const int slot = slot0 + (int)blockIdx.x;
   const double2* bs = b + (size_t)slot * stride;
   if (threadIdx.x == 0) count = 0;
   __syncthreads();
@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
       double2 y;
       if (form_b) {
         const int iz = p / g.nx, ix = p - iz * g.nx;
-        const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+        const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
         y = apply_node<true>(vs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, vs[p]);
       } else {
         y = vs[p];
@@ -648,7 +648,7 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(Grid g, Tiles t, Batch
   double acc[2] = {0.0, 0.0};
   if (iz < g.nz && ix < g.nx) {
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2* xs = x + base;
     const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
     const double2 bp = b[base + p];
@@ -675,7 +675,7 @@ __global__ void __launch_bounds__(kBlock) k_true_residual3(Grid g, Tiles t, Batc
   int iz, iy, ix;
   size_t p;
   if (node3_of(t, tile, g, iz, iy, ix, p)) {
-    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2 y = apply_node3(x + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
     const double2 bp = b[base + p];
     const double2 rr = csub(bp, y);
@@ -725,7 +725,7 @@ __global__ void __launch_bounds__(kBlock) k_gm_residual(Grid g, Tiles t, Batch b
       r = b[base + p];
     } else {
       const FreqTab& f = bt.ft[bt.slots[slot].freq];
-      const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+      const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
       const double2* xs = x + base;
       r = csub(b[base + p], apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]));
     }
@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(kBlock) k_gm_residual3(Grid g, Tiles t, Batch 
       r = b[base + p];
     } else {
       const FreqTab& f = bt.ft[bt.slots[slot].freq];
-      const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], f.omega, f.sB_re, f.sB_im);
+      const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
       r = csub(b[base + p], apply_node3(x + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c));
     }
     v0[base + p] = r;
@@ -1109,11 +1109,11 @@ hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, 
 }
 
 hipError_t launch_bicg_flush(size_t n, int nslots, const Batch& bt, int only_restart, double2* x,
-                             const double2* ph0, const double2* sh0, size_t stride, hipStream_t st) {
+                             const double2* ph0, const double2* sh0, size_t stride, hipStream_t st, int slot0) {
   if (nslots <= 0) return hipSuccess;
   const int tiles = vec_tiles(n);
   hipLaunchKernelGGL(k_bicg_flush, grid1((long long)nslots * tiles), dim3(kBlock), 0, st, bt, tiles, n, only_restart,
-                     x, ph0, sh0, stride);
+                     x, ph0, sh0, stride, slot0);
   return hipGetLastError();
 }
 
@@ -1138,9 +1138,9 @@ hipError_t launch_bicg_fin(int which, int tiles, const Batch& bt, int cap, const
 }
 
 hipError_t launch_rh_sparse(size_t n, int nslots, const Batch& bt, const double2* b, int* idx, double2* val,
-                            size_t stride, hipStream_t st) {
+                            size_t stride, hipStream_t st, int slot0) {
   if (nslots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rh_sparse, dim3(nslots), dim3(kBlock), 0, st, n, bt, b, idx, val, stride);
+  hipLaunchKernelGGL(k_rh_sparse, dim3(nslots), dim3(kBlock), 0, st, n, bt, b, idx, val, stride, slot0);
   return hipGetLastError();
 }
 

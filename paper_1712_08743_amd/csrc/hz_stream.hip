@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
     if (MODE == 1) r.c = in.c[base + q];
     if (MODE >= 4) r.c = in.c[base + row_index(j + 1)];
     r.wd = wd[q];
-    r.m = g.m[q];
+    r.m = model_m(g, f)[q];
     return r;
   };
   // p^ on the rows of the grid, zero outside it (the operator's missing neighbours)

@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_vdown(SmallLevels s, Batch bt) 
     __syncthreads();
     // the slowness for the residual (w / D is no longer needed)
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) mk[k] = g.m[min(t + k * kSmallBlock, n - 1)];
+    for (int k = 0; k < kPer; ++k) mk[k] = model_m(g, f)[min(t + k * kSmallBlock, n - 1)];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int p = t + k * kSmallBlock;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_vdown(SmallLevels s, Batch bt) 
     double2* dst = sw + 1 == s.coarse_sweeps ? u : nxt;
     for (int p = t; p < n; p += kSmallBlock) {
       const int iz = p / g.nx, ix = p - iz * g.nx;
-      const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], f.omega, f.sM_re, f.sM_im);
+      const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
       const double2 wdinv = cscale(s.coarse_w, cinv(diag_of<true>(c, ih2)));
       if (sw == 0) {
         dst[p] = cmul(b[p], wdinv);

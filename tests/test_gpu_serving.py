@@ -1,9 +1,12 @@
-"""GPU tests of the continuous-admission solve server: requests of different
-grids, dimensions, frequencies and right-hand-side counts run at the same time
-on separate streams and give, bit for bit, what a standalone context gives for
-the same request (every reduction has a fixed order per right-hand side);
-admission keeps the summed resident footprint within the memory budget; a
-request larger than the budget is refused at submission."""
+"""GPU tests of the continuous-batching solve server: requests of different
+grids, dimensions, frequencies and right-hand-side counts run at the same
+time (requests on one grid in one engine's batch, each with its own model;
+others on workers of their own) and give, bit for bit, what a standalone
+context gives for the same request (every reduction has a fixed order per
+right-hand side, and a request joins a batch after an even number of
+iterations); requests that arrive while an engine runs join its batch; the
+memory the server holds stays within the budget; a request larger than the
+budget is refused at submission."""
 
 import numpy as np
 import pytest
@@ -33,6 +36,17 @@ def _requests():
     return out
 
 
+def _drained(srv, timeout=5.0):
+    """stats() once the engines have gone idle and given their memory back."""
+    import time
+    t0 = time.perf_counter()
+    st = srv.stats()
+    while st["bytes"] and time.perf_counter() - t0 < timeout:
+        time.sleep(0.01)
+        st = srv.stats()
+    return st
+
+
 def _standalone(hz, reqs, **opt):
     import torch
     res = []
@@ -59,9 +73,9 @@ def test_concurrent_requests_match_standalone_bitwise(hz, slots):
             assert [i[1] for i in info] == [i[1] for i in info_ref]
             assert torch.equal(u, u_ref)
             assert times[0] >= 0.0 and times[1] > 0.0 and times[2] >= times[1]
-        st = srv.stats()
-        assert st["queued"] == 0 and st["running"] == 0
-        assert 1 <= st["peak_running"] <= slots
+        st = _drained(srv)
+        assert st["queued"] == 0 and st["running"] == 0 and st["bytes"] == 0
+        assert st["peak_running"] >= 1
     finally:
         srv.close()
 
@@ -74,8 +88,8 @@ def test_budget_admission_and_refusal(hz):
     big = workloads.model_2d_layered(nz=65, nx=129, h=20.0, nshots=4, freqs=(3.0,))
     small = workloads.model_2d_lens(n=33, h=40.0)
     n_big = big.m.size
-    fp_big = hz.footprint(big.shape, 1, 4)
-    fp_small = hz.footprint(small.shape, 1, 2)
+    fp_big = hz.server_footprint(big.shape, 1, 4, tol=1e-8)
+    fp_small = hz.server_footprint(small.shape, 1, 2, tol=1e-8)
     assert fp_small < fp_big
     budget = fp_big + 2 * fp_small
     rng = np.random.default_rng(5)
@@ -97,7 +111,9 @@ def test_budget_admission_and_refusal(hz):
     srv = hz.Server(0, budget_bytes=budget, slots=3)
     try:
         with pytest.raises(hz.HzError) as e:
-            srv.submit(torch.from_numpy(big.m), big.h, (3.0,), 0.02, rhs(big.shape, 8, big.h), tol=1e-8)
+            # 24 right-hand sides: three lanes of the big grid
+            assert hz.server_footprint(big.shape, 1, 24, tol=1e-8) > budget
+            srv.submit(torch.from_numpy(big.m), big.h, (3.0,), 0.02, rhs(big.shape, 24, big.h), tol=1e-8)
         assert e.value.code == hz.HZ_ERR_NOMEM
         tickets = [srv.submit(torch.from_numpy(m), h, f, 0.02, b, tol=1e-8) for m, h, f, b in reqs]
         peak_bytes = 0
@@ -107,5 +123,63 @@ def test_budget_admission_and_refusal(hz):
             assert torch.equal(u, u_ref)
         assert peak_bytes <= budget
         assert n_big > small.m.size
+    finally:
+        srv.close()
+
+
+def test_late_requests_join_the_running_batch(hz):
+    """One worker: requests on one grid, each with its own model (a lens of
+    each sign and two layered models), submitted while the first ones run,
+    are taken into the same engine's batch (more requests on the device at
+    once than there are workers), and every result equals the standalone
+    solve bit for bit."""
+    import time
+    import torch
+    lay = [workloads.model_2d_layered(nz=65, nx=65, h=20.0, seed=k, nshots=4, freqs=(3.0 + k,)) for k in range(2)]
+    lens = [workloads.model_2d_lens(n=65, h=20.0, sign=sg) for sg in (-1.0, 1.0)]
+    rng = np.random.default_rng(3)
+    reqs = []
+    for k in range(8):
+        mdl = (lay + lens)[k % 4]
+        nrhs = [3, 9, 1, 17][k % 4]
+        freqs = (2.5 + 0.5 * k,) if k % 2 == 0 else (2.0 + 0.25 * k, 4.5)
+        b = np.zeros((len(freqs), nrhs, mdl.m.size), dtype=np.complex128)
+        for f in range(len(freqs)):
+            for r in range(nrhs):
+                b[f, r, rng.integers(0, 65)] = 1.0 / mdl.h ** 2  # surface row
+        reqs.append((mdl.m, mdl.h, freqs, torch.from_numpy(b.reshape((len(freqs), nrhs, 65, 65)))))
+    ref = _standalone(hz, reqs, tol=1e-9)
+    srv = hz.Server(0, slots=1)
+    try:
+        tickets = [srv.submit(torch.from_numpy(m), h, f, 0.02, b, tol=1e-9) for m, h, f, b in reqs[:3]]
+        time.sleep(0.02)
+        tickets += [srv.submit(torch.from_numpy(m), h, f, 0.02, b, tol=1e-9) for m, h, f, b in reqs[3:]]
+        for (u_ref, info_ref), tk in zip(ref, tickets):
+            u, info, times = srv.wait(tk)
+            assert [i[0] for i in info] == [hz.HZ_RHS_CONVERGED] * len(info)
+            assert [i[1] for i in info] == [i[1] for i in info_ref]
+            assert torch.equal(u, u_ref)
+        st = _drained(srv)
+        assert st["peak_running"] >= 4, st  # one worker, several requests in its batch
+        assert st["bytes"] == 0
+    finally:
+        srv.close()
+
+
+def test_second_wait_on_a_ticket_is_refused(hz):
+    import torch
+    mdl = workloads.model_2d_lens(n=33, h=40.0)
+    b = torch.zeros((1, 1) + mdl.shape, dtype=torch.complex128)
+    b[0, 0, 0, 16] = 1.0 / mdl.h ** 2
+    srv = hz.Server(0, slots=1)
+    try:
+        tk = srv.submit(torch.from_numpy(mdl.m), mdl.h, (3.0,), 0.02, b)
+        u, info, _ = srv.wait(tk)
+        assert info[0][0] == hz.HZ_RHS_CONVERGED
+        with pytest.raises(KeyError):
+            srv.wait(tk)
+        import ctypes
+        from paper_1712_08743_amd import _lib
+        assert _lib.hz_server_wait(srv._h, ctypes.c_longlong(tk), None, None) == hz.HZ_ERR_ARG
     finally:
         srv.close()
