@@ -12,7 +12,8 @@ derivative of J as written (readings listed in the design doc):
 
 * u = B^-1 b per (shot, frequency); only the diagonal of B depends on m:
   dB_ii/dm_i = delta_i = j omega g_i / h - 2 omega^2 (1 - j alpha) w_i m_i
-  (the absorbing boundary term included);
+  (the absorbing boundary term included; with a fixed density rho of Eq. (1)
+  that term carries sqrt(rho_i));
 * du/dm_i = -B^-1 e_i delta_i u_i, so the Born data of a perturbation dm are
   G dm = -P B^-1 (delta * u * dm);
 * with the data residual res = P u - d_obs and the adjoint field
@@ -29,18 +30,21 @@ from .operator import operator_B, stencil_parts, point_source
 from .direct import factor_superlu
 
 
-def diag_derivative(m, h, omega, alpha):
+def diag_derivative(m, h, omega, alpha, rho=None):
     """delta_i = d(B_ii)/d(m_i) for every node (flattened)."""
     m = np.asarray(m, dtype=np.float64)
     _, g, w = stencil_parts(m.shape)
     mf = m.ravel()
+    if rho is not None:
+        g = g * np.sqrt(np.asarray(rho, dtype=np.float64).ravel())
     return 1j * omega * g / h - 2.0 * omega ** 2 * (1.0 - 1j * alpha) * w * mf
 
 
 class Survey:
     """Shots (point sources), receivers (nodes) and frequencies on a grid."""
 
-    def __init__(self, shape, h, freqs, alpha, src_nodes, rec_nodes, src_amps=None):
+    def __init__(self, shape, h, freqs, alpha, src_nodes, rec_nodes, src_amps=None, rho=None):
+        self.rho = None if rho is None else np.asarray(rho, dtype=np.float64)  # density of Eq. (1), fixed
         self.shape = tuple(shape)
         self.h = float(h)
         self.freqs = [float(f) for f in freqs]
@@ -60,7 +64,7 @@ def forward(m, sv):
     b = sv.rhs()
     us, lus = [], []
     for f in sv.freqs:
-        lu = factor_superlu(operator_B(m, sv.h, 2 * np.pi * f, sv.alpha))
+        lu = factor_superlu(operator_B(m, sv.h, 2 * np.pi * f, sv.alpha, sv.rho))
         lus.append(lu)
         us.append(np.array([lu.solve(bs) for bs in b]))
     return us, lus
@@ -86,7 +90,7 @@ def gradient(m, sv, d_obs, lam):
     J = lam * float(np.sum(m ** 2))
     g = np.zeros(n)
     for fi, f in enumerate(sv.freqs):
-        delta = diag_derivative(m, sv.h, 2 * np.pi * f, sv.alpha)
+        delta = diag_derivative(m, sv.h, 2 * np.pi * f, sv.alpha, sv.rho)
         for s in range(len(sv.src)):
             u = us[fi][s]
             res = u[sv.rec] - d_obs[fi, s]
@@ -105,7 +109,7 @@ def born(m, sv, dm):
     us, lus = forward(m, sv)
     out = []
     for fi, f in enumerate(sv.freqs):
-        delta = diag_derivative(m, sv.h, 2 * np.pi * f, sv.alpha)
+        delta = diag_derivative(m, sv.h, 2 * np.pi * f, sv.alpha, sv.rho)
         rows = []
         for s in range(len(sv.src)):
             w = lus[fi].solve(-delta * us[fi][s] * np.asarray(dm).ravel())
@@ -123,7 +127,7 @@ def born_adjoint(m, sv, dd):
     n = m.size
     acc = np.zeros(n, dtype=np.complex128)
     for fi, f in enumerate(sv.freqs):
-        delta = diag_derivative(m, sv.h, 2 * np.pi * f, sv.alpha)
+        delta = diag_derivative(m, sv.h, 2 * np.pi * f, sv.alpha, sv.rho)
         for s in range(len(sv.src)):
             src = np.zeros(n, dtype=np.complex128)
             np.add.at(src, sv.rec, dd[fi, s])

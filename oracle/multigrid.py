@@ -101,11 +101,14 @@ class VCycle:
     "auto" (jacobi where the coarsest level's smallest kh, omega times its
     spacing times the smallest slowness of the model, is at least 2.5 --
     there damped Jacobi contracts every mode -- else exact).
+    rho: density of Eq. (1) (None: constant density), injected to the coarse
+    levels like the slowness; kh then uses the slowness m / sqrt(rho).
     """
 
     def __init__(self, m, h, omega, beta1, beta2, levels, nu1=2, nu2=2, wj=None, coarse="exact",
-                 coarse_sweeps=2, coarse_w=0.8):
+                 coarse_sweeps=2, coarse_w=0.8, rho=None):
         m = np.asarray(m, dtype=np.float64)
+        rl = None if rho is None else np.asarray(rho, dtype=np.float64)
         if levels < 1:
             raise ValueError("levels must be >= 1")
         if wj is None:
@@ -119,7 +122,7 @@ class VCycle:
         ml, hl = m, h
         for l in range(levels):
             self.shapes.append(ml.shape)
-            Ml = operator_M(ml, hl, omega, beta1, beta2)
+            Ml = operator_M(ml, hl, omega, beta1, beta2, rl)
             self.M.append(Ml)
             self.D.append(Ml.diagonal())
             if l < levels - 1:
@@ -127,8 +130,10 @@ class VCycle:
                 self.P.append(prolongation(cs, ml.shape))
                 self.R.append(restriction(cs, ml.shape))
                 ml, hl = inject(ml), 2 * hl
+                rl = None if rl is None else inject(rl)
         if coarse == "auto":
-            kh_min = omega * h * 2.0 ** (levels - 1) * float(np.min(m))
+            me = m if rho is None else m / np.sqrt(np.asarray(rho, dtype=np.float64))
+            kh_min = omega * h * 2.0 ** (levels - 1) * float(np.min(me))
             coarse = "jacobi" if levels > 1 and kh_min >= 2.5 else "exact"
         self.coarse = coarse
         self.coarse_sweeps, self.coarse_w = coarse_sweeps, coarse_w

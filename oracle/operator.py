@@ -27,6 +27,20 @@ Readings of what the paper leaves open (each listed in the design doc):
   s = 1 - j alpha gives B; s = beta1 - j beta2 gives the shifted Laplacian M
   (same boundary term).
 * A unit point source at node p is b = e_p / h^dim in this weighted system.
+
+Variable density, Eq. (1) as printed: -div(rho grad u) - k^2 (1 - j alpha) u
+= f with rho > 0 multiplying the flux and not the mass term (Eq. (2) is the
+case rho = 1). Readings (listed in DESIGN.md):
+
+* the coupling of two neighbours is multiplied by the density on their
+  common face, the mean (rho_p + rho_q) / 2 of the two nodes' densities;
+* the absorbing condition is written for the flux, rho du/dn + j omega m
+  sqrt(rho) u = 0: outgoing for the local wavenumber omega m / sqrt(rho) of
+  the equation, and du/dn + j omega m u = 0 again at rho = 1. The boundary
+  term of the matrix becomes (j omega / h) diag(g m sqrt(rho)).
+
+With a constant density c this gives exactly c times the constant-density
+matrix of the slowness m / sqrt(c).
 """
 
 import numpy as np
@@ -41,7 +55,7 @@ def end_weights(n):
     return w
 
 
-def stencil_parts(shape):
+def stencil_parts(shape, rho=None):
     """Return (L, g, w) for a grid of the given shape (n,), (nz, nx) or
     (nz, ny, nx), axes in that order, the last one fastest in the flat order.
 
@@ -50,7 +64,9 @@ def stencil_parts(shape):
     of the other axes' weights (the face between their control volumes).
     g is the boundary-term weight: a node on an end of an axis gets that same
     product for each such end. w is the mass weight, the product of all the
-    axes' weights. g and w are flattened in the grid's flat order.
+    axes' weights. g and w are flattened in the grid's flat order. With a
+    density rho (the grid's shape) every coupling is multiplied by the mean
+    density of its two nodes.
     """
     shape = tuple(int(n) for n in shape)
     dim = len(shape)
@@ -75,6 +91,9 @@ def stencil_parts(shape):
             sel[a] = end
             g[tuple(sel)] += face[tuple(sel)]
     p, q, c = np.concatenate(ps), np.concatenate(qs), np.concatenate(cs)
+    if rho is not None:
+        rf = np.asarray(rho, dtype=np.float64).ravel()
+        c = c * 0.5 * (rf[p] + rf[q])
     w = ws[0]
     for b in range(1, dim):
         w = np.multiply.outer(w, ws[b])
@@ -87,28 +106,38 @@ def stencil_parts(shape):
     return L, g.ravel(), np.asarray(w).ravel()
 
 
-def helmholtz_matrix(m, h, omega, s):
+def helmholtz_matrix(m, h, omega, s, rho=None):
     """A = L/h^2 + (j omega/h) diag(g m) - omega^2 s diag(w m^2), CSR complex128.
 
     m: slowness, shape (n,), (nz, nx) or (nz, ny, nx). s: complex mass shift;
     s = 1 - j alpha is the operator B of Eq. (2)-(3), s = beta1 - j beta2 the
-    shifted Laplacian M.
+    shifted Laplacian M. rho: density of Eq. (1) (None: 1), which weights the
+    couplings by face densities and the boundary term by sqrt(rho).
     """
     m = np.asarray(m, dtype=np.float64)
-    L, g, w = stencil_parts(m.shape)
+    L, g, w = stencil_parts(m.shape, rho)
     mf = m.ravel()
-    diag = 1j * omega * g * mf / h - omega ** 2 * complex(s) * w * mf ** 2
+    gm = g * mf if rho is None else g * mf * np.sqrt(np.asarray(rho, dtype=np.float64).ravel())
+    diag = 1j * omega * gm / h - omega ** 2 * complex(s) * w * mf ** 2
     return (L.astype(np.complex128) / h ** 2 + sp.diags(diag)).tocsr()
 
 
-def operator_B(m, h, omega, alpha):
-    """The damped Helmholtz operator B of Eq. (2)-(3)."""
-    return helmholtz_matrix(m, h, omega, 1.0 - 1j * alpha)
+def operator_B(m, h, omega, alpha, rho=None):
+    """The damped Helmholtz operator B of Eq. (2)-(3) (Eq. (1) with a density rho)."""
+    return helmholtz_matrix(m, h, omega, 1.0 - 1j * alpha, rho)
 
 
-def operator_M(m, h, omega, beta1, beta2):
-    """The shifted-Laplace operator M = -Laplace - (beta1 - j beta2) omega^2 m^2."""
-    return helmholtz_matrix(m, h, omega, beta1 - 1j * beta2)
+def operator_M(m, h, omega, beta1, beta2, rho=None):
+    """The shifted-Laplace operator M = -Laplace - (beta1 - j beta2) omega^2 m^2
+    (-div(rho grad) for the flux with a density rho)."""
+    return helmholtz_matrix(m, h, omega, beta1 - 1j * beta2, rho)
+
+
+def effective_slowness(m, rho=None):
+    """m / sqrt(rho): the slowness the density-weighted equation propagates
+    with (its local wavenumber is omega m / sqrt(rho))."""
+    m = np.asarray(m, dtype=np.float64)
+    return m if rho is None else m / np.sqrt(np.asarray(rho, dtype=np.float64))
 
 
 def point_source(shape, h, nodes, amps=None):

@@ -29,7 +29,11 @@ stand in for them:
                          side 129, 257 or 513 (h = 10 m), layered model with
                          a Gaussian anomaly, one frequency from U(2, 15) Hz,
                          1-32 surface shots; ``poisson_arrivals`` gives the
-                         arrival times.
+                         arrival times;
+* ``gardner_density``    a density field for Eq. (1) that follows the
+                         velocity model: Gardner's rule rho ~ c^(1/4),
+                         relative to the density at the slowest velocity
+                         (dimensionless, 1 to about 1.3 over 1500-4500 m/s).
 """
 
 import numpy as np
@@ -148,6 +152,12 @@ def model_fwi(nz=301, nx=601, h=10.0, seed=0):
     return Workload(name=f"fwi-{nz}x{nx}", m=m_true, m_start=m_start, c=c, h=h, shape=(nz, nx),
                     freqs=[3.0, 4.0, 6.0, 8.0, 10.0, 12.0], alpha=0.01, src=src, rec=rec, lam=1e-3,
                     beta=(1.0, 0.5), tol=1e-8)
+
+
+def gardner_density(m):
+    """Density of the same shape as the slowness m, (c / c_min)^(1/4) with c = 1/m."""
+    c = 1.0 / np.asarray(m, dtype=np.float64)
+    return (c / c.min()) ** 0.25
 
 
 def random_vectors(nvec, size, seed):
