@@ -156,6 +156,25 @@ void hz_destroy(hz_ctx *c);
  * Errors: HZ_ERR_ARG (bad sizes, h <= 0, non-finite or non-positive m). */
 int  hz_set_model(hz_ctx *c, int dim, int nz, int nx, double h, const double *m_dev);
 
+/* Variable density (Eq. (1): -div(rho grad u) - k^2 (1 - j alpha) u = f) on
+ * the 1D or 2D model set last. rho_dev: device, [nz][nx] doubles, finite and
+ * positive, copied; NULL returns to constant density (Eq. (2)). A new
+ * hz_set_model also does. Discretisation: the coupling of two neighbouring
+ * nodes is multiplied by the mean (rho_p + rho_q) / 2 of their densities,
+ * and the absorbing boundary is written for the flux, rho du/dn + j omega m
+ * sqrt(rho) u = 0, so its term carries sqrt(rho_p); the shifted Laplacian M
+ * takes the same couplings and boundary term. The density is injected to
+ * the coarse levels like the slowness, and the V-cycle is planned for the
+ * slowness m / sqrt(rho) the equation propagates with. Every call on the
+ * model (hz_solve, hz_solve_noalloc, hz_precond, hz_apply, hz_smooth,
+ * hz_restrict, the misfit, gradient and Gauss-Newton calls, whose dB/dm
+ * carries sqrt(rho) in its boundary part) then uses the density; the solver
+ * takes its one-kernel-per-step V-cycle (the fused kernels have constant
+ * density only). The serving calls are not affected.
+ * Errors: HZ_ERR_ARG (no 1D or 2D model, non-finite or non-positive rho),
+ * HZ_ERR_NOMEM, HZ_ERR_DEVICE. */
+int  hz_set_density(hz_ctx *c, const double *rho_dev);
+
 /* Point sources in weighted form: b_dev[s] = amp[s] / h^dim at node
  * (iz[s], ix[s]) and zero elsewhere, for s < nsrc. iz, ix, amp are host
  * arrays (amp NULL = unit amplitude); b_dev is [nsrc][nz][nx].

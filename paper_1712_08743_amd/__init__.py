@@ -76,6 +76,7 @@ _SIGS = {
     "hz_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(CtxOpts)]),
     "hz_destroy": (None, [_vp]),
     "hz_set_model": (_i, [_vp, _i, _i, _i, _d, _vp]),
+    "hz_set_density": (_i, [_vp, _vp]),
     "hz_point_rhs": (_i, [_vp, _i, _ip, _ip, _vp, _vp]),
     "hz_set_model_3d": (_i, [_vp, _i, _i, _i, _d, _vp]),
     "hz_point_rhs_3d": (_i, [_vp, _i, _ip, _ip, _ip, _vp, _vp]),
@@ -224,6 +225,22 @@ class Context:
         self.dim = dim
         self.h = float(h)
         self._m = m
+        self._rho = None
+        return self
+
+    def set_density(self, rho):
+        """Density of Eq. (1) on the 1D or 2D model (float64 tensor of the
+        model's shape, finite and positive); None returns to constant density."""
+        if rho is None:
+            self._check(_lib.hz_set_density(self._h, None))
+            self._rho = None
+            return self
+        t = self.torch
+        rho = rho.to(device=self.device, dtype=t.float64).contiguous()
+        if tuple(rho.shape) != self.shape:
+            raise ValueError(f"density shape {tuple(rho.shape)} is not the model's {self.shape}")
+        self._check(_lib.hz_set_density(self._h, _ptr(rho)))
+        self._rho = rho
         return self
 
     @property

@@ -108,6 +108,7 @@ struct LevelInfo {
   int nz = 0, nx = 0, ny = 1;  // ny > 1 on 3D grids only
   double h = 0.0;
   DevBuf m;
+  DevBuf rho;          // density of Eq. (1) on this level (when hz_ctx::has_rho)
   size_t mstride = 0;  // engines: one model per lane, mstride apart (see Grid::mstride)
   size_t n() const { return (size_t)nz * ny * nx; }
   int rows() const { return nz * ny; }  // rows of the 2D tiling of the grid
@@ -131,8 +132,11 @@ struct hz_ctx {
   std::string err;
   // model
   int dim = 0, nz = 0, nx = 0, ny = 1;
-  double h = 0.0, mmin = 0.0, mmax = 0.0;
+  // mmin, mmax: the slowness range the V-cycle is planned for (m / sqrt(rho)
+  // under a density); m_lo, m_hi: the range of the model itself
+  double h = 0.0, mmin = 0.0, mmax = 0.0, m_lo = 0.0, m_hi = 0.0;
   int maxlev = 0;
+  int has_rho = 0;  // a density of Eq. (1) is set (1D and 2D grids)
   LevelInfo lv[kMaxLevels];
   int model_version = 0;
   // solver workspace
@@ -220,6 +224,7 @@ Grid grid_of(const hz_ctx* c, int l) {
   g.h = c->lv[l].h;
   g.m = c->lv[l].m.as<double>();
   g.mstride = c->lv[l].mstride;
+  g.rho = c->has_rho ? c->lv[l].rho.as<double>() : nullptr;
   return g;
 }
 
@@ -613,7 +618,8 @@ struct Cycle {
   int levels, nu1, nu2, precond;
   int autotune, chunk_rows;  // launch shape of the fused kernels (opts.autotune, opts.chunk_rows)
   int coarse_sweeps;         // > 0: some frequency smooths its coarsest level with this many sweeps
-  int plain;                 // opts.plain: one kernel per step, no fused V-cycle kernels
+  int plain;                 // opts.plain: one kernel per step, dense r^, host readback every iteration
+  int unfused;               // no fused V-cycle kernels (opts.plain, or a density is set)
 };
 
 // ---------------------------------------------------------------- launch-shape tuning
@@ -702,7 +708,7 @@ struct FineRhs {
 };
 
 bool fused_pre(const Cycle& cy) {
-  return cy.precond == HZ_PRECOND_MG && cy.levels >= 2 && cy.nu1 == 2 && !cy.plain;
+  return cy.precond == HZ_PRECOND_MG && cy.levels >= 2 && cy.nu1 == 2 && !cy.unfused;
 }
 
 // out = V b on the finest grid for the slots of the active list. With rhs
@@ -726,7 +732,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   int l0 = L;
   SmallLevels sl;
   memset(&sl, 0, sizeof sl);
-  if (dim == 2 && cy.nu1 == 2 && cy.nu2 == 2 && !cy.plain && L >= 3)
+  if (dim == 2 && cy.nu1 == 2 && cy.nu2 == 2 && !cy.unfused && L >= 3)
     for (int lf = 1; lf < L - 1 && l0 == L; ++lf) {
       if (c->lv[lf].n() > (size_t)kSmallNodes) continue;
       sl.l0 = lf;
@@ -755,8 +761,8 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
     double2* u = nullptr;
     double2* bc = c->lev[l + 1][kLb].as<double2>();
     // the fused post-smoothing kernel forms the pre-smoothed iterate again
-    const bool post_fused = dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.plain;
-    if (cy.nu1 == 2 && dim == 2 && !cy.plain) {
+    const bool post_fused = dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.unfused;
+    if (cy.nu1 == 2 && dim == 2 && !cy.unfused) {
       // both pre-sweeps, the residual and its restriction in one pass
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
@@ -775,14 +781,14 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       bl = bc;
       continue;
     }
-    if (cy.nu1 == 2 && dim == 3 && !cy.plain) {
+    if (cy.nu1 == 2 && dim == 3 && !cy.unfused) {
       // both pre-sweeps from zero in one marching pass
       if ((e = timed(c, l == 0 ? HZ_KERNEL_SMOOTH : HZ_KERNEL_LEVELS, [&] {
              return launch_march3(g, l, bt, cap, true, bl, nullptr, X, nl, st);
            })) != hipSuccess)
         return e;
       u = X;
-    } else if (cy.nu1 == 2 && dim == 1 && !cy.plain) {
+    } else if (cy.nu1 == 2 && dim == 1 && !cy.unfused) {
       const FineRhs plain{0, bl, nullptr, nullptr, nullptr};
       const FineRhs& fr = (l == 0 && rhs) ? *rhs : plain;
       if ((e = timed(c, l == 0 ? HZ_KERNEL_PRESMOOTH : HZ_KERNEL_LEVELS, [&] {
@@ -856,7 +862,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
       continue;
     }
     // prolongation fused with the first post-sweep (2D: with the first two)
-    const int fused = (dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.plain) ? 2 : 1;
+    const int fused = (dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.unfused) ? 2 : 1;
     double2* dst = (cy.nu2 == fused) ? R : ((u == X) ? Y : X);
     if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : HZ_KERNEL_LEVELS, [&] {
            if (fused == 2)
@@ -938,7 +944,9 @@ struct BicgIter {
     ph = phr[0];
     sh = shr[0];
     vt = vec_tiles(n0);
-    gt = reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
+    // tiles of the operator-apply kernels (a density takes the one-node-per-thread forms)
+    gt = g0.rho ? grid_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim).per_slot
+                : reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);
   }
 
   // Start the slots of the list `lb` (cap entries): x = 0, r = r^ = b, the
@@ -1456,8 +1464,9 @@ int set_model_impl(hz_ctx* c, int dim, int nz, int ny, int nx, double h, const d
   c->ny = ny;
   c->nx = nx;
   c->h = h;
-  c->mmin = out3[0];
-  c->mmax = out3[1];
+  c->mmin = c->m_lo = out3[0];
+  c->mmax = c->m_hi = out3[1];
+  c->has_rho = 0;  // a new model starts at constant density
   c->lv[0].nz = nz;
   c->lv[0].ny = ny;
   c->lv[0].nx = nx;
@@ -1494,6 +1503,50 @@ int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_d
   if ((size_t)nz * nx > (size_t)1 << 30) return fail(c, HZ_ERR_ARG, "grid too large");
   if (!(h > 0.0) || !isfinite(h)) return fail(c, HZ_ERR_ARG, "h must be positive");
   return set_model_impl(c, dim, nz, 1, nx, h, m_dev);
+}
+
+int hz_set_density(hz_ctx* c, const double* rho_dev) {
+  if (!c) return HZ_ERR_ARG;
+  if (c->dim != 1 && c->dim != 2) return fail(c, HZ_ERR_ARG, "a density needs a 1D or 2D model set first");
+  HZ_HIP(c, hipSetDevice(c->device));
+  HZ_HIP(c, hipStreamSynchronize(c->stream));
+  if (!rho_dev) {
+    c->has_rho = 0;
+    c->mmin = c->m_lo;
+    c->mmax = c->m_hi;
+  } else {
+    const size_t n = c->lv[0].n();
+    HZ_ALLOC(c, c->lv[0].rho, n * sizeof(double));
+    HZ_HIP(c, hipMemcpyAsync(c->lv[0].rho.p, rho_dev, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    DevBuf chk;
+    HZ_ALLOC(c, chk, 4 * sizeof(double));
+    HZ_HIP(c, launch_check_density(n, c->lv[0].m.as<double>(), c->lv[0].rho.as<double>(), chk.as<double>(),
+                                   c->stream));
+    double out3[3];
+    HZ_HIP(c, hipMemcpyAsync(out3, chk.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HZ_HIP(c, hipStreamSynchronize(c->stream));
+    if (out3[2] > 0.0) {
+      c->has_rho = 0;
+      c->mmin = c->m_lo;
+      c->mmax = c->m_hi;
+      return fail(c, HZ_ERR_ARG, "density has %.0f entries that are not finite and positive", out3[2]);
+    }
+    // injected to the coarse levels like the slowness
+    for (int l = 1; l < c->maxlev; ++l) {
+      HZ_ALLOC(c, c->lv[l].rho, c->lv[l].n() * sizeof(double));
+      Grid gf = grid_of(c, l - 1);
+      gf.m = c->lv[l - 1].rho.as<double>();
+      HZ_HIP(c, launch_inject(gf, c->dim, c->lv[l].rho.as<double>(), c->stream));
+    }
+    HZ_HIP(c, hipStreamSynchronize(c->stream));
+    c->has_rho = 1;
+    c->mmin = out3[0];
+    c->mmax = out3[1];
+  }
+  c->model_version += 1;
+  c->cinv_key.clear();
+  c->cinv_base = nullptr;
+  return HZ_OK;
 }
 
 int hz_set_model_3d(hz_ctx* c, int nz, int ny, int nx, double h, const double* m_dev) {
@@ -1628,7 +1681,7 @@ int solve_impl(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_
   if ((rc = setup_freqs(c, o, nfreq, freq_hz, alpha, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nslots, nrhs)) != HZ_OK) return rc;
   const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
-                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain};
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain, o->plain || c->has_rho};
   const double2* b = reinterpret_cast<const double2*>(b_dev);
   double2* x = reinterpret_cast<double2*>(u_dev);
   if (o->krylov == HZ_BICGSTAB) {
@@ -2168,7 +2221,7 @@ int hz_precond(hz_ctx* c, const hz_solve_opts* o, double freq_hz, int nrhs, cons
   if ((rc = setup_freqs(c, o, 1, &freq_hz, 0.0, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nrhs, nrhs)) != HZ_OK) return rc;
   const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
-                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain};
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain, o->plain || c->has_rho};
   HZ_HIP(c, precond_apply(c, cy, nrhs, reinterpret_cast<const double2*>(b_dev), reinterpret_cast<double2*>(u_dev)));
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   return HZ_OK;

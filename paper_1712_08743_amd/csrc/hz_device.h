@@ -70,10 +70,11 @@ struct NodeC {
   double2 kap;
 };
 
-// ih = 1 / h of the node's level.
+// ih = 1 / h of the node's level; gs scales the absorbing term (sqrt of the
+// node's density under a variable density, see node_op).
 template <bool D2>
 __device__ __forceinline__ NodeC node_coef(int iz, int ix, int nz, int nx, double ih, double m,
-                                           double omega, double s_re, double s_im) {
+                                           double omega, double s_re, double s_im, double gs = 1.0) {
   NodeC c;
   const int x0 = (ix == 0), x1 = (ix == nx - 1);
   c.wx = (x0 | x1) ? 0.5 : 1.0;
@@ -89,7 +90,7 @@ __device__ __forceinline__ NodeC node_coef(int iz, int ix, int nz, int nx, doubl
     c.lsum = (double)(2 - x0 - x1);
   }
   const double om2wm2 = omega * omega * (c.wx * c.wz) * (m * m);
-  c.kap = c2(-om2wm2 * s_re, omega * g * m * ih - om2wm2 * s_im);
+  c.kap = c2(-om2wm2 * s_re, omega * g * m * ih * gs - om2wm2 * s_im);
   return c;
 }
 
@@ -119,6 +120,71 @@ __device__ __forceinline__ double2 apply_node(const double2* __restrict__ x, int
 template <bool D2>
 __device__ __forceinline__ double2 diag_of(const NodeC& c, double ih2) {
   return c2(c.lsum * ih2 + c.kap.x, c.kap.y);
+}
+
+// ---------------------------------------------------------------- variable density
+// Eq. (1) with a density rho on the grid (Grid::rho): the coupling of node p
+// with a neighbour q is the constant-density one times the density on their
+// common face, (rho_p + rho_q) / 2; the absorbing term is written for the
+// flux, rho du/dn + j omega m sqrt(rho) u = 0, so it carries sqrt(rho_p).
+// With Grid::rho null node_op and apply_op are node_coef and apply_node.
+struct NodeOp {
+  NodeC c;       // lsum: the sum of the couplings in use
+  double cq[4];  // density couplings to the -x, +x, -z, +z neighbours (0 where missing)
+};
+
+template <bool D2>
+__device__ __forceinline__ NodeOp node_op(const Grid& g, int iz, int ix, int p, double m, double omega,
+                                          double s_re, double s_im) {
+  NodeOp o;
+  if (!g.rho) {
+    o.c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, m, omega, s_re, s_im);
+    return o;
+  }
+  const double* r = g.rho;
+  const double rp = r[p];
+  o.c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, m, omega, s_re, s_im, sqrt(rp));
+  o.cq[0] = ix > 0 ? o.c.wz * (0.5 * (rp + r[p - 1])) : 0.0;
+  o.cq[1] = ix < g.nx - 1 ? o.c.wz * (0.5 * (rp + r[p + 1])) : 0.0;
+  o.cq[2] = (D2 && iz > 0) ? o.c.wx * (0.5 * (rp + r[p - g.nx])) : 0.0;
+  o.cq[3] = (D2 && iz < g.nz - 1) ? o.c.wx * (0.5 * (rp + r[p + g.nx])) : 0.0;
+  o.c.lsum = (o.cq[0] + o.cq[1]) + (o.cq[2] + o.cq[3]);
+  return o;
+}
+
+// (A x)_p with the value at p and the neighbours' values from val(dz, dx),
+// which is called for the existing neighbours only.
+template <bool D2, class F>
+__device__ __forceinline__ double2 apply_op_at(const Grid& g, const NodeOp& o, int iz, int ix, double ih2,
+                                               double2 xp, F val) {
+  if (!g.rho) {
+    double2 sx = c2(0.0, 0.0), sz = c2(0.0, 0.0);
+    if (ix > 0) sx = cadd(sx, val(0, -1));
+    if (ix < g.nx - 1) sx = cadd(sx, val(0, 1));
+    if (D2) {
+      if (iz > 0) sz = cadd(sz, val(-1, 0));
+      if (iz < g.nz - 1) sz = cadd(sz, val(1, 0));
+    }
+    return stencil(o.c, ih2, xp, sx, sz);
+  }
+  double2 s = c2(0.0, 0.0);
+  if (ix > 0) s = cadd(s, cscale(o.cq[0], val(0, -1)));
+  if (ix < g.nx - 1) s = cadd(s, cscale(o.cq[1], val(0, 1)));
+  if (D2) {
+    if (iz > 0) s = cadd(s, cscale(o.cq[2], val(-1, 0)));
+    if (iz < g.nz - 1) s = cadd(s, cscale(o.cq[3], val(1, 0)));
+  }
+  const double2 lx = c2(o.c.lsum * xp.x - s.x, o.c.lsum * xp.y - s.y);
+  return cadd(cscale(ih2, lx), cmul(o.c.kap, xp));
+}
+
+// (A x)_p for x given at the slot's base pointer; xp = x[p].
+template <bool D2>
+__device__ __forceinline__ double2 apply_op(const Grid& g, const NodeOp& o, const double2* __restrict__ x, int p,
+                                            int iz, int ix, double ih2, double2 xp) {
+  if (!g.rho) return apply_node<D2>(x, p, iz, ix, g.nz, g.nx, ih2, o.c, xp);
+  const int nx = g.nx;
+  return apply_op_at<D2>(g, o, iz, ix, ih2, xp, [&](int dz, int dx) { return x[p + dz * nx + dx]; });
 }
 
 // Which block of the grid is this: active-list entry and tile.

@@ -59,7 +59,8 @@ __device__ __forceinline__ void sens_geom(const Grid& g, size_t p, double& gh, d
     const int ix = (int)(p - (size_t)iz * g.nx);
     // geometry weights: d(kap)/dm with s = 1 - j alpha and omega = 1 gives the per-frequency pieces
     const NodeC c1 = node_coef<DIM == 2>(iz, ix, g.nz, g.nx, 1.0 / g.h, 1.0, 1.0, 0.0, 0.0);  // kap.y = g / h
-    gh = c1.kap.y;
+    // a density of Eq. (1) scales the absorbing term by sqrt(rho_i)
+    gh = g.rho ? c1.kap.y * sqrt(g.rho[p]) : c1.kap.y;
     w = c1.wx * c1.wz;
   }
 }

@@ -67,9 +67,9 @@ __global__ void __launch_bounds__(kBlock) k_apply(Grid g, Tiles t, int lvl, int 
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const double sre = which ? f.sM_re : f.sB_re, sim = which ? f.sM_im : f.sB_im;
   const int p = iz * g.nx + ix;
-  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, sre, sim);
+  const NodeOp o = node_op<D2>(g, iz, ix, p, model_m(g, f)[p], f.omega, sre, sim);
   const double2* xs = x + (size_t)slot * stride;
-  y[(size_t)slot * stride + p] = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
+  y[(size_t)slot * stride + p] = apply_op<D2>(g, o, xs, p, iz, ix, 1.0 / (g.h * g.h), xs[p]);
   (void)lvl;
 }
 
@@ -89,9 +89,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth(Grid g, Tiles t, int lvl, dou
   if (coarse_only && !f.coarse_jacobi) return;
   const int p = iz * g.nx + ix;
   const double ih2 = 1.0 / (g.h * g.h);
-  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
+  const NodeOp o = node_op<D2>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
   // w / diag(M): tabulated per frequency and level, or formed here for an explicit weight
-  const double2 wdinv = w_override > 0.0 ? cscale(w_override, cinv(diag_of<D2>(c, ih2))) : f.winv[lvl][p];
+  const double2 wdinv = w_override > 0.0 ? cscale(w_override, cinv(diag_of<D2>(o.c, ih2))) : f.winv[lvl][p];
   const size_t base = (size_t)slot * stride;
   const double2 bp = b[base + p];
   double2 out;
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth(Grid g, Tiles t, int lvl, dou
   } else {
     const double2* us = u_in + base;
     const double2 up = us[p];
-    const double2 res = csub(bp, apply_node<D2>(us, p, iz, ix, g.nz, g.nx, ih2, c, up));
+    const double2 res = csub(bp, apply_op<D2>(g, o, us, p, iz, ix, ih2, up));
     out = cadd(up, cmul(res, wdinv));
   }
   u_out[base + p] = out;
@@ -114,8 +114,8 @@ __global__ void k_winv(Grid g, double omega, double s_re, double s_im, double w,
   if (p >= n) return;
   const int iz = D2 ? (int)(p / g.nx) : 0;
   const int ix = (int)(p - (size_t)iz * g.nx);
-  const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, g.m[p], omega, s_re, s_im);
-  winv[p] = cscale(w, cinv(diag_of<D2>(c, 1.0 / (g.h * g.h))));
+  const NodeOp o = node_op<D2>(g, iz, ix, (int)p, g.m[p], omega, s_re, s_im);
+  winv[p] = cscale(w, cinv(diag_of<D2>(o.c, 1.0 / (g.h * g.h))));
 }
 
 // bc = 2^-dim P^T (b - M u), one thread per coarse node. P^T gives the two
@@ -148,8 +148,8 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid gf, Grid gc, Tiles t, 
       const int ix = 2 * Ix + dx;
       if (ix < 0 || ix >= gf.nx) continue;
       const int p = iz * gf.nx + ix;
-      const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
-      const double2 r = csub(bs[p], apply_node<D2>(us, p, iz, ix, gf.nz, gf.nx, ih2, c, us[p]));
+      const NodeOp o = node_op<D2>(gf, iz, ix, p, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
+      const double2 r = csub(bs[p], apply_op<D2>(gf, o, us, p, iz, ix, ih2, us[p]));
       const double wxt = (dx == 0 || (dx == 1 && 2 * Ix + 2 == gf.nx)) ? 1.0 : 0.5;
       row = cadd(row, cscale(wxt, r));
     }
@@ -259,16 +259,11 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth(Grid gf, Grid gc, Til
     return cadd(us[qz * gf.nx + qx], interp<D2>(es, qz, qx, gc.nx, gc.nz));
   };
   const int p = iz * gf.nx + ix;
-  const NodeC c = node_coef<D2>(iz, ix, gf.nz, gf.nx, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
+  const NodeOp o = node_op<D2>(gf, iz, ix, p, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
   const double2 u3p = u3_at(iz, ix);
-  double2 sx = c2(0.0, 0.0), sz = c2(0.0, 0.0);
-  if (ix > 0) sx = cadd(sx, u3_at(iz, ix - 1));
-  if (ix < gf.nx - 1) sx = cadd(sx, u3_at(iz, ix + 1));
-  if (D2) {
-    if (iz > 0) sz = cadd(sz, u3_at(iz - 1, ix));
-    if (iz < gf.nz - 1) sz = cadd(sz, u3_at(iz + 1, ix));
-  }
-  const double2 res = csub(b[base + p], stencil(c, ih2, u3p, sx, sz));
+  const double2 res = csub(b[base + p], apply_op_at<D2>(gf, o, iz, ix, ih2, u3p, [&](int dz, int dx) {
+                             return u3_at(iz + dz, ix + dx);
+                           }));
   u_out[base + p] = cadd(u3p, cmul(res, f.winv[lvl][p]));
 }
 
@@ -498,15 +493,15 @@ __global__ void k_assemble_dense(Grid g, int nfreq, const FreqTab* __restrict__ 
     const int i = (int)(rem / nc), j = (int)(rem - (size_t)i * nc);
     const int iz = i / g.nx, ix = i - iz * g.nx;
     const int jz = j / g.nx, jx = j - jz * g.nx;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, ft[f])[i], ft[f].omega, ft[f].sM_re,
-                                  ft[f].sM_im);
+    const NodeOp o = node_op<D2>(g, iz, ix, i, model_m(g, ft[f])[i], ft[f].omega, ft[f].sM_re, ft[f].sM_im);
+    const NodeC& c = o.c;
     double2 val = c2(0.0, 0.0);
     if (i == j) {
       val = diag_of<D2>(c, ih2);
     } else if (jz == iz && (jx == ix - 1 || jx == ix + 1)) {
-      val = c2(-c.wz * ih2, 0.0);
+      val = c2(-(g.rho ? o.cq[jx == ix - 1 ? 0 : 1] : c.wz) * ih2, 0.0);
     } else if (D2 && jx == ix && (jz == iz - 1 || jz == iz + 1)) {
-      val = c2(-c.wx * ih2, 0.0);
+      val = c2(-(g.rho ? o.cq[jz == iz - 1 ? 2 : 3] : c.wx) * ih2, 0.0);
     }
     A[e] = val;
   }
@@ -558,10 +553,10 @@ __global__ void __launch_bounds__(1024) k_pcr(Grid g, Batch bt, const double2* _
   const double ih2 = 1.0 / (g.h * g.h);
   const double2* bs = b + (size_t)slot * stride;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const NodeC c = node_coef<false>(0, i, 1, n, 1.0 / g.h, model_m(g, f)[i], f.omega, f.sM_re, f.sM_im);
-    A[i] = c2(i > 0 ? -ih2 : 0.0, 0.0);
-    Cu[i] = c2(i < n - 1 ? -ih2 : 0.0, 0.0);
-    Bd[i] = diag_of<false>(c, ih2);
+    const NodeOp o = node_op<false>(g, 0, i, i, model_m(g, f)[i], f.omega, f.sM_re, f.sM_im);
+    A[i] = c2(i > 0 ? -(g.rho ? o.cq[0] : 1.0) * ih2 : 0.0, 0.0);
+    Cu[i] = c2(i < n - 1 ? -(g.rho ? o.cq[1] : 1.0) * ih2 : 0.0, 0.0);
+    Bd[i] = diag_of<false>(o.c, ih2);
     D[i] = bs[i];
   }
   __syncthreads();
@@ -685,6 +680,47 @@ __global__ void __launch_bounds__(1024) k_check_model(size_t n, const double* __
     if (!(isfinite(v) && v > 0.0)) {
       bad += 1.0;
     } else {
+      lo = fmin(lo, v);
+      hi = fmax(hi, v);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+    bad += __shfl_xor(bad, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wid] = lo;
+    sh[1][wid] = hi;
+    sh[2][wid] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      sh[0][0] = fmin(sh[0][0], sh[0][w]);
+      sh[1][0] = fmax(sh[1][0], sh[1][w]);
+      sh[2][0] += sh[2][w];
+    }
+    out3[0] = sh[0][0];
+    out3[1] = sh[1][0];
+    out3[2] = sh[2][0];
+  }
+}
+
+// out3 = {min m / sqrt(rho), max m / sqrt(rho), count of rho entries that are
+// not finite and positive}: the slowness range the density-weighted equation
+// propagates with (its local wavenumber is omega m / sqrt(rho)).
+__global__ void __launch_bounds__(1024) k_check_density(size_t n, const double* __restrict__ m,
+                                                        const double* __restrict__ rho, double* __restrict__ out3) {
+  __shared__ double sh[3][16];
+  double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = rho[i];
+    if (!(isfinite(r) && r > 0.0)) {
+      bad += 1.0;
+    } else {
+      const double v = m[i] / sqrt(r);
       lo = fmin(lo, v);
       hi = fmax(hi, v);
     }
@@ -1076,6 +1112,7 @@ hipError_t launch_apply(int dim, const Grid& g, int lvl, int which, const Batch&
 hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool from_zero, const double2* b,
                          const double2* u_in, double2* u_out, size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  if (g.rho) return hipErrorInvalidValue;  // constant density only
   const int nstrip = (g.nx + kMarchW - 1) / kMarchW, nchunk = (g.nz + kMarchZ - 1) / kMarchZ;
   const int groups = (g.ny * nstrip * nchunk + 3) / 4;
   if (from_zero)
@@ -1103,7 +1140,8 @@ hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, con
   }
   const Tiles t = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
-  if (dim == 2 && u_in && w_override <= 0.0) {
+  // the LDS-tiled form has constant density only
+  if (dim == 2 && u_in && w_override <= 0.0 && !g.rho) {
     const int ntx = (g.nx + kTX - 1) / kTX, ntz = (g.nz + kTZ - 1) / kTZ;
     hipLaunchKernelGGL(k_smooth_t, grid1(tile_blocks(ntx * ntz, cap)), dim3(kBlock), 0, st, g, ntx, ntx * ntz, lvl,
                        bt, b, u_in, u_out, stride);
@@ -1134,10 +1172,13 @@ hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch&
     return hipGetLastError();
   }
   const Tiles t = grid_tiles(gc.nz, gc.nx, dim);
-  if (dim == 2) {
+  if (dim == 2 && !gf.rho) {
     const int ntx = (gc.nx + kRtx - 1) / kRtx, ntz = (gc.nz + kRtz - 1) / kRtz;
     hipLaunchKernelGGL(k_restrict_tiled, grid1(tile_blocks(ntx * ntz, cap)), dim3(kRtx * kRtz), 0, st, gf, gc,
                        ntx, ntx * ntz, bt, b, u, bc, sf, sc);
+  } else if (dim == 2) {
+    hipLaunchKernelGGL(k_restrict<true>, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, gf, gc, t, bt,
+                       b, u, bc, sf, sc);
   } else {
     hipLaunchKernelGGL(k_restrict<false>, grid1(tile_blocks(t.per_slot, cap)), dim3(kBlock), 0, st, gf, gc, t, bt,
                        b, u, bc, sf, sc);
@@ -1180,8 +1221,9 @@ hipError_t launch_prolong(int dim, const Grid& gf, const Grid& gc, const Batch& 
 hipError_t launch_pre2(int dim, const Grid& g, int lvl, int mode, const Batch& bt, int cap,
                        const double2* in_a, const double2* in_b, const double2* in_c, double2* bout,
                        double2* u2, size_t stride, hipStream_t st) {
-  // 2D grids take the fused pre-smoothing and restriction kernel (launch_pre2r)
-  if (dim != 1) return hipErrorInvalidValue;
+  // 2D grids take the fused pre-smoothing and restriction kernel (launch_pre2r);
+  // constant density only
+  if (dim != 1 || g.rho) return hipErrorInvalidValue;
   const Tiles t = grid_tiles(g.nz, g.nx, dim);
   if (cap <= 0) return hipSuccess;
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
@@ -1206,11 +1248,13 @@ hipError_t launch_prolong_smooth(int dim, const Grid& gf, const Grid& gc, int lv
   }
   const Tiles t = grid_tiles(gf.nz, gf.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
-  if (dim == 2) {
+  if (dim == 2 && !gf.rho) {
     const int ntx = (gf.nx + kTX - 1) / kTX, ntz = (gf.nz + kTZ - 1) / kTZ;
     hipLaunchKernelGGL(k_prolong_smooth_t, grid1(tile_blocks(ntx * ntz, cap)), dim3(kBlock), 0, st, gf, gc, ntx,
                        ntx * ntz, lvl, bt, e, b, u2, u_out, sf, sc);
-  } else
+  } else if (dim == 2)
+    hipLaunchKernelGGL(k_prolong_smooth<true>, gr, dim3(kBlock), 0, st, gf, gc, t, lvl, bt, e, b, u2, u_out, sf, sc);
+  else
     hipLaunchKernelGGL(k_prolong_smooth<false>, gr, dim3(kBlock), 0, st, gf, gc, t, lvl, bt, e, b, u2, u_out, sf, sc);
   return hipGetLastError();
 }
@@ -1329,6 +1373,11 @@ hipError_t launch_inject(const Grid& gf, int dim, double* mc, hipStream_t st) {
   const int ncz = dim == 2 ? (gf.nz + 1) / 2 : 1;
   const int tot = ncx * ncz;
   hipLaunchKernelGGL(k_inject, dim3((tot + 255) / 256), dim3(256), 0, st, gf, dim, mc);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_density(size_t n, const double* m, const double* rho, double* out3, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_density, dim3(1), dim3(1024), 0, st, n, m, rho, out3);
   return hipGetLastError();
 }
 

@@ -92,9 +92,9 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
   const bool dense_rh = bt.slots[slot].rh_nnz < 0;  // else <rh, v> is formed from the sparse list
   if (iz < g.nz && ix < g.nx) {
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+    const NodeOp o = node_op<D2>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2* xs = ph + base;
-    const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
+    const double2 y = apply_op<D2>(g, o, xs, p, iz, ix, 1.0 / (g.h * g.h), xs[p]);
     v[base + p] = y;
     if (dense_rh) {
       const double2 d = cconjmul(rh[base + p], y);
@@ -222,9 +222,9 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_omega(Grid g, Tiles t, Ba
   double acc[3] = {0.0, 0.0, 0.0};
   if (iz < g.nz && ix < g.nx) {
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+    const NodeOp o = node_op<D2>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2* xs = sh + base;
-    const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
+    const double2 y = apply_op<D2>(g, o, xs, p, iz, ix, 1.0 / (g.h * g.h), xs[p]);
     tv[base + p] = y;
     const double2 ts = cconjmul(y, s[base + p]);
     acc[0] = ts.x;
@@ -438,8 +438,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
       double2 y;
       if (form_b) {
         const int iz = p / g.nx, ix = p - iz * g.nx;
-        const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
-        y = apply_node<true>(vs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, vs[p]);
+        const NodeOp o = node_op<true>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+        y = apply_op<true>(g, o, vs, p, iz, ix, 1.0 / (g.h * g.h), vs[p]);
       } else {
         y = vs[p];
       }
@@ -648,9 +648,9 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(Grid g, Tiles t, Batch
   double acc[2] = {0.0, 0.0};
   if (iz < g.nz && ix < g.nx) {
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+    const NodeOp o = node_op<D2>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
     const double2* xs = x + base;
-    const double2 y = apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]);
+    const double2 y = apply_op<D2>(g, o, xs, p, iz, ix, 1.0 / (g.h * g.h), xs[p]);
     const double2 bp = b[base + p];
     const double2 rr = csub(bp, y);
     acc[0] = rr.x * rr.x + rr.y * rr.y;
@@ -725,9 +725,9 @@ __global__ void __launch_bounds__(kBlock) k_gm_residual(Grid g, Tiles t, Batch b
       r = b[base + p];
     } else {
       const FreqTab& f = bt.ft[bt.slots[slot].freq];
-      const NodeC c = node_coef<D2>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+      const NodeOp o = node_op<D2>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
       const double2* xs = x + base;
-      r = csub(b[base + p], apply_node<D2>(xs, p, iz, ix, g.nz, g.nx, 1.0 / (g.h * g.h), c, xs[p]));
+      r = csub(b[base + p], apply_op<D2>(g, o, xs, p, iz, ix, 1.0 / (g.h * g.h), xs[p]));
     }
     v0[base + p] = r;
     acc[0] = r.x * r.x + r.y * r.y;
@@ -1050,7 +1050,10 @@ hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int 
   }
   const Tiles t = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
-  if (dim == 2) {
+  if (dim == 2 && g.rho) {  // the LDS-tiled form has constant density only
+    if (!v) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bicg_apply_sigma<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, ph, rh, v, stride);
+  } else if (dim == 2) {
     const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
     hipLaunchKernelGGL(k_bicg_apply_t<0>, grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per, bt, rd,
                        ph, rh, v, stride);
@@ -1079,7 +1082,9 @@ hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int 
   }
   const Tiles tl = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(tl.per_slot, cap));
-  if (dim == 2) {
+  if (dim == 2 && g.rho) {  // the LDS-tiled form has constant density only
+    hipLaunchKernelGGL(k_bicg_apply_omega<true>, gr, dim3(kBlock), 0, st, g, tl, bt, rd, sh, s, t, stride);
+  } else if (dim == 2) {
     const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
     hipLaunchKernelGGL(k_bicg_apply_t<1>, grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per, bt, rd,
                        sh, s, t, stride);

@@ -398,6 +398,7 @@ hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const 
                         double2* bcoarse, size_t stride, size_t sc, int chunk_rows, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
+  if (g.rho) return hipErrorInvalidValue;  // constant density only
   // modes other than 0 form the finest level's right-hand side
   if (mode < 0 || mode > 5 || mode == 3 || (lvl != 0 && mode != 0)) return hipErrorInvalidValue;
   const StreamShape sh = stream_shape(g, pre_width(mode), chunk_rows);
@@ -420,6 +421,7 @@ hipError_t launch_post2(const Grid& gf, const Grid& gc, int lvl, const Batch& bt
                         const double2* b, double2* u_out, size_t sf, size_t sc, int chunk_rows, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
+  if (gf.rho) return hipErrorInvalidValue;  // constant density only
   const StreamShape sh = stream_shape(gf, kPostWidth, chunk_rows);
   const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
   if (lvl == 0)

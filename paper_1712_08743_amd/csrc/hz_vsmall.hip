@@ -279,6 +279,7 @@ std::atomic<size_t> g_allowed_down{0}, g_allowed_up{0};
 
 hipError_t launch_vdown(const SmallLevels& s, const Batch& bt, int cap, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  if (s.g[s.l0].rho) return hipErrorInvalidValue;  // constant density only
   const size_t lds = small_levels_lds(s);
   const hipError_t e = allow_lds(k_vdown, lds, g_allowed_down);
   if (e != hipSuccess) return e;
@@ -288,6 +289,7 @@ hipError_t launch_vdown(const SmallLevels& s, const Batch& bt, int cap, hipStrea
 
 hipError_t launch_vup(const SmallLevels& s, const Batch& bt, int cap, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  if (s.g[s.l0].rho) return hipErrorInvalidValue;  // constant density only
   const size_t lds = small_levels_lds(s);
   const hipError_t e = allow_lds(k_vup, lds, g_allowed_up);
   if (e != hipSuccess) return e;
