@@ -18,6 +18,7 @@ Prints one JSON line (see the field list at the end of main()).
   python bench.py --compare       # preconditioned vs not, shifts, GMRES vs BiCGSTAB,
                                   # Gauss-Newton schedules (a report, not a throughput line)
   python bench.py --3d            # batched solves on a 3D box (129^3, 16 right-hand sides) and its gradient; a report line
+  python bench.py --density       # the same batch with a variable density (Eq. (1)); a report line
   python bench.py --fwi           # gradient and Gauss-Newton step on the full inversion survey
                                   # (301 x 601, 32 shots x 6 frequencies; a report line)
   python bench.py --serving [--requests R] [--slots S]
@@ -653,6 +654,66 @@ def one_rhs_per_call(ctx, w, b1, tol, shot=31, plain=False):
     return len(secs) / sum(secs), its
 
 
+def bench_density(args):
+    """Variable density (Eq. (1)) on the benchmark batch: the layered 401 x 801
+    model with a density that follows it (Gardner's rule, relative to the
+    slowest velocity), 64 surface shots x 3/5/8/12 Hz = 256 right-hand sides,
+    BiCGSTAB to 1e-8 with the planned V(2,2) shifted-Laplace (1, 0.5)
+    preconditioner, which a density solve applies with its per-step kernels.
+    A step = set the model and the density + solve, inputs resident in HBM.
+    The constant-density batch is timed beside it in the same process. One
+    JSON line, a report beside the headline line."""
+    import torch
+    import numpy as np
+    import paper_1712_08743_amd as hz
+    import workloads
+    w = workloads.model_2d_layered()
+    rho = torch.from_numpy(workloads.gardner_density(w.m)).cuda()
+    nshot, nfreq = len(w.src), len(w.freqs)
+    nrhs = nshot * nfreq
+    ctx = hz.Context(0)
+    m = torch.from_numpy(w.m).cuda()
+    ctx.set_model(m, w.h)
+    b1 = ctx.point_rhs([0] * nshot, w.src)
+    b = torch.stack([b1] * nfreq).contiguous()
+    u = torch.empty_like(b)
+    tol = 1e-8
+    out = {"metric": "Helmholtz solves/s (2D 401x801, 256 RHS, variable density of Eq. (1))", "unit": "solves/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "2d-layered-401x801 with a Gardner density (rho ~ c^(1/4), 1 to 1.3), 64 surface "
+                                  "shots x {3,5,8,12} Hz = 256 RHS, BiCGSTAB tol 1e-8, V(2,2) shifted-Laplace "
+                                  "(1,0.5), LFA-planned weights for m / sqrt(rho)"}}
+    for name, dens in (("density", rho), ("constant", None)):
+        def step():
+            ctx.set_model(m, w.h)
+            if dens is not None:
+                ctx.set_density(dens)
+            _, info = ctx.solve(w.freqs, w.alpha, b, out=u, tol=tol)
+            return info
+        print(f"# {name}: warm-up step", file=sys.stderr, flush=True)
+        step()
+        torch.cuda.synchronize()
+        steps = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = step()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        print(f"# {name}: {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+        iters = [i[1] for i in info]
+        res = {"value": nrhs / sec, "ms_per_step": sec * 1e3, "steps": steps, "warmup": 1,
+               "converged": sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED and i[2] <= tol),
+               "iterations_mean_per_freq": {str(f): float(np.mean(iters[k * nshot:(k + 1) * nshot]))
+                                            for k, f in enumerate(w.freqs)},
+               "levels": ctx.plan(w.freqs[0])[0]}
+        if name == "density":
+            out.update(res)
+        else:
+            out["constant_density"] = res
+    out["ratio_to_constant_density"] = out["value"] / out["constant_density"]["value"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -668,6 +729,7 @@ def main():
     ap.add_argument("--compare", action="store_true")
     ap.add_argument("--fwi", action="store_true")
     ap.add_argument("--3d", dest="three_d", action="store_true")
+    ap.add_argument("--density", action="store_true")
     ap.add_argument("--compare-maxit", type=int, default=20000)
     ap.add_argument("--maxit", type=int, default=10000,
                     help="iteration cap (below convergence only for short hardware-counter runs)")
@@ -690,6 +752,9 @@ def main():
         return
     if args.three_d:
         bench_3d(args)
+        return
+    if args.density:
+        bench_density(args)
         return
 
     import numpy as np

@@ -5,13 +5,17 @@
         --copy-fetch CSV --copy-write CSV --copy-bytes N --rhs R --command CMD \\
         [--out FILE.md] [--json FILE.json]
 
+    python -m paper_1712_08743_amd.profiling stalls CSV [CSV ...] --command CMD [--out FILE.md]
+
 ``stats`` reads a ``--kernel-trace`` CSV and tabulates, per kernel symbol,
 the launches, total and average duration; the finest-level kernels are named
 by their timing class (``hz_timing_*``). ``traffic`` reads two ``--pmc``
 counter-collection CSVs (FETCH_SIZE, WRITE_SIZE, in KiB per dispatch) of a
 solve whose every launch carries ``R`` right-hand sides, scales each counter
 by what it reads for the library's plain copy kernel of ``N`` bytes read and
-``N`` written, and reports bytes per dispatch and per right-hand side.
+``N`` written, and reports bytes per dispatch and per right-hand side. ``stalls`` reads
+``--pmc`` runs of the SQ wave counters and tabulates, per kernel, where its
+waves spend their cycles and the instructions each wave issues.
 """
 
 import argparse
@@ -120,6 +124,57 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, rh
     return {"fetch_factor": ffac, "write_factor": wfac, "kernels": rows}
 
 
+def counter_means(csv_paths):
+    """kernel symbol -> (grid size, dispatches, {counter: mean per dispatch}) over
+    the dispatches with the symbol's most frequent grid size, from one or more
+    ``--pmc`` counter-collection CSVs (one row per counter and dispatch)."""
+    by = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(list)))
+    ids = collections.defaultdict(lambda: collections.defaultdict(set))  # dispatches per run
+    for run, path in enumerate(csv_paths):
+        for r in csv.DictReader(open(path)):
+            sym, g = symbol(r["Kernel_Name"]), int(r["Grid_Size"])
+            by[sym][g][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            ids[sym][g].add((run, r["Dispatch_Id"]))
+    out = {}
+    for sym, grids in by.items():
+        g, cnt = max(grids.items(), key=lambda kv: max(len(v) for v in kv[1].values()))
+        runs = collections.Counter(run for run, _ in ids[sym][g])
+        out[sym] = (g, max(runs.values()), {k: sum(v) / len(v) for k, v in cnt.items()})
+    return out
+
+
+def _stalls_md(csv_paths, command, top=12):
+    lines = ["# Wave stall counters (rocprofv3 --pmc)", "", "Commands:", "", "```", command, "```", "",
+             "Per kernel, the dispatches with its most frequent grid size. Fractions are of `SQ_WAVE_CYCLES` "
+             "(the counters count per wave, in the same units): `SQ_WAIT_ANY` = waiting at `s_waitcnt` (for "
+             "loads), `SQ_WAIT_INST_ANY` = waiting for an instruction to issue, `SQ_ACTIVE_INST_ANY` / "
+             "`_VALU` = issuing. Instructions are per wavefront.", "",
+             "| kernel | grid | dispatches | wait (loads) | wait (issue) | active | active VALU | VALU instr. | "
+             "VMEM reads | VMEM writes | SALU instr. |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    rows = counter_means(csv_paths)
+
+    def cyc(item):
+        g, n, c = item[1]
+        return c.get("SQ_WAVE_CYCLES", 0.0) * n
+
+    for sym, (g, n, c) in sorted(rows.items(), key=cyc, reverse=True)[:top]:
+        wc, waves = c.get("SQ_WAVE_CYCLES"), c.get("SQ_WAVES")
+        if not wc or not waves:
+            continue
+
+        def fr(k):
+            return f"{c[k] / wc:.2f}" if k in c else ""
+
+        def per_wave(k):
+            return f"{c[k] / waves:.0f}" if k in c else ""
+
+        lines.append(f"| `{sym}` | {g} | {n} | {fr('SQ_WAIT_ANY')} | {fr('SQ_WAIT_INST_ANY')} | "
+                     f"{fr('SQ_ACTIVE_INST_ANY')} | {fr('SQ_ACTIVE_INST_VALU')} | {per_wave('SQ_INSTS_VALU')} | "
+                     f"{per_wave('SQ_INSTS_VMEM_RD')} | {per_wave('SQ_INSTS_VMEM_WR')} | {per_wave('SQ_INSTS_SALU')} |")
+    return "\n".join(lines) + "\n"
+
+
 def _whole_run_md(stats_csv, top=15):
     lines = ["", "Whole run (the `--stats` summary: warm-up, launch-shape trials and every other launch "
              "included):", "", "| kernel | calls | total ms | average us |", "|---|---:|---:|---:|"]
@@ -169,6 +224,10 @@ def main():
     a.add_argument("--between", nargs=3, metavar=("KERNEL", "FIRST", "LAST"),
                    help="only launches between the FIRST-th and LAST-th launch of KERNEL")
     a.add_argument("--stats-csv", help="the run's --stats kernel summary, appended as a second table")
+    c = sub.add_parser("stalls")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--command", required=True)
+    c.add_argument("--out")
     b = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         b.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -179,7 +238,9 @@ def main():
     b.add_argument("--out")
     b.add_argument("--json")
     args = ap.parse_args()
-    if args.what == "stats":
+    if args.what == "stalls":
+        text = _stalls_md(args.csv, args.command)
+    elif args.what == "stats":
         between = (args.between[0], int(args.between[1]), int(args.between[2])) if args.between else None
         text = _stats_md(args.trace, args.command, between)
         if args.stats_csv:
