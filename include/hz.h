@@ -168,9 +168,12 @@ int  hz_set_model(hz_ctx *c, int dim, int nz, int nx, double h, const double *m_
  * slowness m / sqrt(rho) the equation propagates with. Every call on the
  * model (hz_solve, hz_solve_noalloc, hz_precond, hz_apply, hz_smooth,
  * hz_restrict, the misfit, gradient and Gauss-Newton calls, whose dB/dm
- * carries sqrt(rho) in its boundary part) then uses the density; the solver
- * takes its one-kernel-per-step V-cycle (the fused kernels have constant
- * density only). The serving calls are not affected.
+ * carries sqrt(rho) in its boundary part) then uses the density. On 2D
+ * grids the fused kernels read a per-level table of the couplings (three
+ * doubles per node of every level, built here: about 32 bytes per fine
+ * node in all), and the levels the constant-density solve walks in two
+ * small-level kernels take a launch per level and step; 1D grids take the
+ * one-kernel-per-step V-cycle. The serving calls are not affected.
  * Errors: HZ_ERR_ARG (no 1D or 2D model, non-finite or non-positive rho),
  * HZ_ERR_NOMEM, HZ_ERR_DEVICE. */
 int  hz_set_density(hz_ctx *c, const double *rho_dev);

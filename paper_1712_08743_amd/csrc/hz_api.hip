@@ -109,6 +109,7 @@ struct LevelInfo {
   double h = 0.0;
   DevBuf m;
   DevBuf rho;          // density of Eq. (1) on this level (when hz_ctx::has_rho)
+  DevBuf dc;           // 2D: its coupling table for the fused kernels (Grid::dc)
   size_t mstride = 0;  // engines: one model per lane, mstride apart (see Grid::mstride)
   size_t n() const { return (size_t)nz * ny * nx; }
   int rows() const { return nz * ny; }  // rows of the 2D tiling of the grid
@@ -225,6 +226,7 @@ Grid grid_of(const hz_ctx* c, int l) {
   g.m = c->lv[l].m.as<double>();
   g.mstride = c->lv[l].mstride;
   g.rho = c->has_rho ? c->lv[l].rho.as<double>() : nullptr;
+  g.dc = (c->has_rho && c->dim == 2) ? c->lv[l].dc.as<double>() : nullptr;
   return g;
 }
 
@@ -619,7 +621,7 @@ struct Cycle {
   int autotune, chunk_rows;  // launch shape of the fused kernels (opts.autotune, opts.chunk_rows)
   int coarse_sweeps;         // > 0: some frequency smooths its coarsest level with this many sweeps
   int plain;                 // opts.plain: one kernel per step, dense r^, host readback every iteration
-  int unfused;               // no fused V-cycle kernels (opts.plain, or a density is set)
+  int unfused;               // no fused V-cycle kernels (opts.plain, or a density on a 1D grid)
 };
 
 // ---------------------------------------------------------------- launch-shape tuning
@@ -732,7 +734,8 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   int l0 = L;
   SmallLevels sl;
   memset(&sl, 0, sizeof sl);
-  if (dim == 2 && cy.nu1 == 2 && cy.nu2 == 2 && !cy.unfused && L >= 3)
+  // (constant density only: a density takes a launch per level and step there)
+  if (dim == 2 && cy.nu1 == 2 && cy.nu2 == 2 && !cy.unfused && L >= 3 && !c->has_rho)
     for (int lf = 1; lf < L - 1 && l0 == L; ++lf) {
       if (c->lv[lf].n() > (size_t)kSmallNodes) continue;
       sl.l0 = lf;
@@ -944,9 +947,7 @@ struct BicgIter {
     ph = phr[0];
     sh = shr[0];
     vt = vec_tiles(n0);
-    // tiles of the operator-apply kernels (a density takes the one-node-per-thread forms)
-    gt = g0.rho ? grid_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim).per_slot
-                : reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);
+    gt = reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
   }
 
   // Start the slots of the list `lb` (cap entries): x = 0, r = r^ = b, the
@@ -1538,6 +1539,14 @@ int hz_set_density(hz_ctx* c, const double* rho_dev) {
       gf.m = c->lv[l - 1].rho.as<double>();
       HZ_HIP(c, launch_inject(gf, c->dim, c->lv[l].rho.as<double>(), c->stream));
     }
+    // 2D: every level's coupling table for the fused kernels
+    if (c->dim == 2)
+      for (int l = 0; l < c->maxlev; ++l) {
+        HZ_ALLOC(c, c->lv[l].dc, 3 * c->lv[l].n() * sizeof(double));
+        Grid gl = grid_of(c, l);
+        gl.rho = c->lv[l].rho.as<double>();
+        HZ_HIP(c, launch_density_coef(gl, c->lv[l].dc.as<double>(), c->stream));
+      }
     HZ_HIP(c, hipStreamSynchronize(c->stream));
     c->has_rho = 1;
     c->mmin = out3[0];
@@ -1681,7 +1690,7 @@ int solve_impl(hz_ctx* c, const hz_solve_opts* o, int nfreq, const double* freq_
   if ((rc = setup_freqs(c, o, nfreq, freq_hz, alpha, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nslots, nrhs)) != HZ_OK) return rc;
   const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
-                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain, o->plain || c->has_rho};
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain, o->plain || (c->has_rho && c->dim != 2)};
   const double2* b = reinterpret_cast<const double2*>(b_dev);
   double2* x = reinterpret_cast<double2*>(u_dev);
   if (o->krylov == HZ_BICGSTAB) {
@@ -2221,7 +2230,7 @@ int hz_precond(hz_ctx* c, const hz_solve_opts* o, double freq_hz, int nrhs, cons
   if ((rc = setup_freqs(c, o, 1, &freq_hz, 0.0, levels, wj)) != HZ_OK) return rc;
   if ((rc = reset_slots(c, nrhs, nrhs)) != HZ_OK) return rc;
   const Cycle cy{levels, o->nu1, o->nu2, o->precond, o->autotune, o->chunk_rows,
-                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain, o->plain || c->has_rho};
+                 c->any_coarse_jacobi ? o->coarse_sweeps : 0, o->plain, o->plain || (c->has_rho && c->dim != 2)};
   HZ_HIP(c, precond_apply(c, cy, nrhs, reinterpret_cast<const double2*>(b_dev), reinterpret_cast<double2*>(u_dev)));
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   return HZ_OK;

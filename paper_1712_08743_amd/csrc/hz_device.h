@@ -385,4 +385,38 @@ __device__ __forceinline__ double2 keep(bool c, double2 v) {
   return make_double2(c ? v.x : 0.0, c ? v.y : 0.0);
 }
 
+// ---- variable density in the fused kernels (2D): Grid::dc holds, per level,
+// three arrays of n: the coupling of each node to its right neighbour
+// wz (rho_p + rho_right) / 2, to the neighbour below wx (rho_p + rho_below) / 2
+// (zero where that neighbour is missing), and the absorbing term's weight
+// g sqrt(rho_p) (see node_op). A node's coupling to its left (upper)
+// neighbour is that neighbour's right (lower) one.
+struct RhoC {
+  double l, r, u, d;  // couplings to the left, right, upper and lower neighbour
+};
+
+// (M x)_p = [(l + r + u + d) x_p - (l x_l + r x_r + u x_u + d x_d)] / h^2 + kap x_p,
+// kap = -omega^2 s w m^2 + j omega gb m / h with w = wx wz the mass weight;
+// ka = -omega^2 Re s, kb = -omega^2 Im s, kc = omega / h
+__device__ __forceinline__ double2 apply_m_rho(const RhoC& c, double gb, double w, double m, double ka, double kb,
+                                               double kc, double ih2, double2 xp, double2 xl, double2 xr,
+                                               double2 xu, double2 xd) {
+  const double mw = w * (m * m);
+  const double kre = ka * mw, kim = kb * mw + kc * gb * m;
+  const double lsum = (c.l + c.r) + (c.u + c.d);
+  const double sre = (c.l * xl.x + c.r * xr.x) + (c.u * xu.x + c.d * xd.x);
+  const double sim = (c.l * xl.y + c.r * xr.y) + (c.u * xu.y + c.d * xd.y);
+  return c2(ih2 * (lsum * xp.x - sre) + (kre * xp.x - kim * xp.y),
+            ih2 * (lsum * xp.y - sim) + (kre * xp.y + kim * xp.x));
+}
+
+// One damped-Jacobi update in the form (1 - w) u + (w/D)(b + (sum of the
+// couplings times the neighbours) / h^2), with density couplings.
+__device__ __forceinline__ double2 jacobi_rho(double2 u, double2 b, double2 wd, const RhoC& c, double2 xl,
+                                              double2 xr, double2 xu, double2 xd, double ih2, double omw) {
+  const double tx = ih2 * ((c.l * xl.x + c.r * xr.x) + (c.u * xu.x + c.d * xd.x)) + b.x;
+  const double ty = ih2 * ((c.l * xl.y + c.r * xr.y) + (c.u * xu.y + c.d * xd.y)) + b.y;
+  return c2(omw * u.x + (wd.x * tx - wd.y * ty), omw * u.y + (wd.x * ty + wd.y * tx));
+}
+
 }  // namespace hz

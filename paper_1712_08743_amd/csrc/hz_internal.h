@@ -43,6 +43,9 @@ struct Grid {
   // density of Eq. (1) on this level, [nz][nx] (1D and 2D grids; null:
   // constant density, the operator of Eq. (2))
   const double* rho = nullptr;
+  // 2D grids with a density: the level's coupling table (RhoC in hz_device.h),
+  // [3][nz][nx]; the fused kernels read it instead of rho
+  const double* dc = nullptr;
 };
 
 // Per-frequency constants (device table).
@@ -323,6 +326,8 @@ hipError_t launch_adjoint_data(int nslots, size_t n, int nuniq, const int* uniq_
 hipError_t launch_cg(int mode, size_t n, const double* g, const double* Hp, double* x, double* r, double* p,
                      double* state, double tol, hipStream_t st);
 hipError_t launch_check_model(size_t n, const double* m, double* out3, hipStream_t st);
+// The coupling table of a 2D level with a density (Grid::dc) from g.rho.
+hipError_t launch_density_coef(const Grid& g, double* dc, hipStream_t st);
 // out3 = {min m / sqrt(rho), max m / sqrt(rho), count of rho entries that are
 // not finite and positive} (the extremes over the valid entries)
 hipError_t launch_check_density(size_t n, const double* m, const double* rho, double* out3, hipStream_t st);

@@ -708,6 +708,23 @@ __global__ void __launch_bounds__(1024) k_check_model(size_t n, const double* __
   }
 }
 
+// The coupling table of a 2D level with a density (see RhoC): for node (iz, ix)
+// wz (rho_p + rho_right) / 2 (zero on the last column), wx (rho_p + rho_below)
+// / 2 (zero on the last row) and g sqrt(rho_p), the same values node_op forms.
+__global__ void k_density_coef(Grid g, double* __restrict__ dc) {
+  const size_t n = (size_t)g.nz * g.nx;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int iz = (int)(p / g.nx), ix = (int)(p - (size_t)iz * g.nx);
+  const double* r = g.rho;
+  const double rp = r[p];
+  const int x0 = ix == 0, x1 = ix == g.nx - 1, z0 = iz == 0, z1 = iz == g.nz - 1;
+  const double wx = (x0 | x1) ? 0.5 : 1.0, wz = (z0 | z1) ? 0.5 : 1.0;
+  dc[p] = x1 ? 0.0 : wz * (0.5 * (rp + r[p + 1]));
+  dc[n + p] = z1 ? 0.0 : wx * (0.5 * (rp + r[p + g.nx]));
+  dc[2 * n + p] = (wz * (double)(x0 + x1) + wx * (double)(z0 + z1)) * sqrt(rp);
+}
+
 // out3 = {min m / sqrt(rho), max m / sqrt(rho), count of rho entries that are
 // not finite and positive}: the slowness range the density-weighted equation
 // propagates with (its local wavenumber is omega m / sqrt(rho)).
@@ -1373,6 +1390,13 @@ hipError_t launch_inject(const Grid& gf, int dim, double* mc, hipStream_t st) {
   const int ncz = dim == 2 ? (gf.nz + 1) / 2 : 1;
   const int tot = ncx * ncz;
   hipLaunchKernelGGL(k_inject, dim3((tot + 255) / 256), dim3(256), 0, st, gf, dim, mc);
+  return hipGetLastError();
+}
+
+hipError_t launch_density_coef(const Grid& g, double* dc, hipStream_t st) {
+  const size_t n = (size_t)g.nz * g.nx;
+  if (!g.rho || g.ny != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_density_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, dc);
   return hipGetLastError();
 }
 

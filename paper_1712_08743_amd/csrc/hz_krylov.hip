@@ -108,8 +108,9 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
 // LDS-tiled forms (2D): x staged on the tile and its halo, two nodes per thread.
 // WHICH 0: v = B ph, partial <rh, v>; WHICH 1: t = B sh, partials <t, s>, <t, t>.
 // WHICH 0 with y null stores nothing and serves only the slots whose r^ is
-// dense (the others leave at once): their partial <rh, B ph>.
-template <int WHICH>
+// dense (the others leave at once): their partial <rh, B ph>. RHO: with a
+// density (Eq. (1)), the couplings from the level's table (Grid::dc).
+template <int WHICH, bool RHO>
 __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int per_slot, Batch bt, Reduce rd,
                                                          const double2* __restrict__ xin,
                                                          const double2* __restrict__ other,
@@ -134,10 +135,24 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= g.nz || ix >= g.nx) continue;
     const int p = iz * g.nx + ix;
-    const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
-    double2 sx, sz;
-    halo_sums(X, lz, lx, sx, sz);
-    const double2 yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
+    double2 yp;
+    if (RHO) {
+      const size_t n = (size_t)g.nz * g.nx;
+      RhoC rc;
+      rc.l = ix > 0 ? g.dc[p - 1] : 0.0;
+      rc.r = g.dc[p];
+      rc.u = iz > 0 ? g.dc[n + p - g.nx] : 0.0;
+      rc.d = g.dc[n + p];
+      const double wxz = ((ix == 0 || ix == g.nx - 1) ? 0.5 : 1.0) * ((iz == 0 || iz == g.nz - 1) ? 0.5 : 1.0);
+      const double om2 = f.omega * f.omega;
+      yp = apply_m_rho(rc, g.dc[2 * n + p], wxz, model_m(g, f)[p], -om2 * f.sB_re, -om2 * f.sB_im, f.omega * ih,
+                       ih2, X[lz + 1][lx + 1], X[lz + 1][lx], X[lz + 1][lx + 2], X[lz][lx + 1], X[lz + 2][lx + 1]);
+    } else {
+      const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+      double2 sx, sz;
+      halo_sums(X, lz, lx, sx, sz);
+      yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
+    }
     if (WHICH == 1 || y) st_nt(y + base + p, yp);
     if (WHICH == 0) {
       if (dots) {
@@ -1050,13 +1065,15 @@ hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int 
   }
   const Tiles t = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(t.per_slot, cap));
-  if (dim == 2 && g.rho) {  // the LDS-tiled form has constant density only
-    if (!v) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bicg_apply_sigma<true>, gr, dim3(kBlock), 0, st, g, t, bt, rd, ph, rh, v, stride);
-  } else if (dim == 2) {
+  if (dim == 2) {
+    if (g.rho && !g.dc) return hipErrorInvalidValue;  // a density needs the level's coupling table
     const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
-    hipLaunchKernelGGL(k_bicg_apply_t<0>, grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per, bt, rd,
-                       ph, rh, v, stride);
+    if (g.dc)
+      hipLaunchKernelGGL((k_bicg_apply_t<0, true>), grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per,
+                         bt, rd, ph, rh, v, stride);
+    else
+      hipLaunchKernelGGL((k_bicg_apply_t<0, false>), grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per,
+                         bt, rd, ph, rh, v, stride);
   } else
     hipLaunchKernelGGL(k_bicg_apply_sigma<false>, gr, dim3(kBlock), 0, st, g, t, bt, rd, ph, rh, v, stride);
   return hipGetLastError();
@@ -1082,12 +1099,15 @@ hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int 
   }
   const Tiles tl = grid_tiles(g.nz, g.nx, dim);
   const dim3 gr = grid1(tile_blocks(tl.per_slot, cap));
-  if (dim == 2 && g.rho) {  // the LDS-tiled form has constant density only
-    hipLaunchKernelGGL(k_bicg_apply_omega<true>, gr, dim3(kBlock), 0, st, g, tl, bt, rd, sh, s, t, stride);
-  } else if (dim == 2) {
+  if (dim == 2) {
+    if (g.rho && !g.dc) return hipErrorInvalidValue;  // a density needs the level's coupling table
     const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
-    hipLaunchKernelGGL(k_bicg_apply_t<1>, grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per, bt, rd,
-                       sh, s, t, stride);
+    if (g.dc)
+      hipLaunchKernelGGL((k_bicg_apply_t<1, true>), grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per,
+                         bt, rd, sh, s, t, stride);
+    else
+      hipLaunchKernelGGL((k_bicg_apply_t<1, false>), grid1(tile_blocks(per, cap)), dim3(kBlock), 0, st, g, ntx, per,
+                         bt, rd, sh, s, t, stride);
   } else
     hipLaunchKernelGGL(k_bicg_apply_omega<false>, gr, dim3(kBlock), 0, st, g, tl, bt, rd, sh, s, t, stride);
   return hipGetLastError();

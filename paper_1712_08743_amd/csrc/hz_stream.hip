@@ -119,14 +119,30 @@ template <int MODE>
 struct PreRow {  // loads of one row: the right-hand side's inputs, w/D and m (MODE 4, 5: c is p^ on the next row)
   double2 a, b, c, wd;
   double m;
+  double cr, cd, gb;  // with a density: the row's coupling table (RhoC)
 };
+
+// The couplings at lane x of row i from the row's own table entries (cr, cd)
+// and the lower coupling of the row above (cd_up); every lane takes part in
+// the lane shift.
+__device__ __forceinline__ RhoC rho_row(int x, int i, double cr, double cd, double cd_up) {
+  const double l = dpp_shift<kDppWaveShr1>(cr);
+  RhoC c;
+  c.l = x > 0 ? l : 0.0;
+  c.r = cr;
+  c.u = i > 0 ? cd_up : 0.0;
+  c.d = cd;
+  return c;
+}
 
 // FINE: launched on the finest level (the same code; a separate symbol lets a
 // profiler tell the finest level's launches from the coarser ones). MODE 4
 // and 5 hold p^ on three rows more: they get up to 168 VGPRs (3 waves per
-// SIMD) rather than spill at 128, which made them far slower.
-template <int MODE, bool FINE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE >= 4 ? 3 : 4, 8))) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
+// SIMD) rather than spill at 128, which made them far slower. RHO: with a
+// density (Eq. (1)), the couplings come from the level's table (g.dc), kept
+// for two rows behind the march; 3 waves per SIMD as well.
+template <int MODE, bool FINE, bool RHO>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE >= 4 || RHO ? 3 : 4, 8))) k_pre2r_s(Grid g, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
                                                     Batch bt, RhsIn in, double2* __restrict__ bout,
                                                     double2* __restrict__ u2, double2* __restrict__ bc,
                                                     size_t stride, size_t sc) {
@@ -159,6 +175,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
   const double cwx = ih2 * cx.w;
   const double2 zero = c2(0.0, 0.0);
   auto row_index = [&](int j) { return (size_t)min(max(j, 0), g.nz - 1) * g.nx + xx; };
+  const size_t nn = (size_t)g.nz * g.nx;
   auto load_row = [&](int j) {
     PreRow<MODE> r;
     const size_t q = row_index(j);
@@ -168,6 +185,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
     if (MODE >= 4) r.c = in.c[base + row_index(j + 1)];
     r.wd = wd[q];
     r.m = model_m(g, f)[q];
+    if (RHO) {
+      r.cr = g.dc[q];
+      r.cd = g.dc[nn + q];
+      r.gb = g.dc[2 * nn + q];
+    }
     return r;
   };
   // p^ on the rows of the grid, zero outside it (the operator's missing neighbours)
@@ -180,11 +202,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
   // the horizontally restricted residual on j-4, j-3
   double2 u1a = zero, u1b = zero, b1 = zero, b2 = zero, wd1 = zero, u2a = zero, u2b = zero, ha = zero, hb = zero;
   double m1 = 0.0, m2 = 0.0;
+  // RHO: the coupling table on rows j-1 and j-2, and the lower coupling of row j-3
+  double cr1 = 0.0, cd1 = 0.0, gb1 = 0.0, cr2 = 0.0, cd2 = 0.0, gb2 = 0.0, cd3 = 0.0;
   // MODE 4, 5: p^ on rows j-1 and j
   double2 q0 = zero, q1 = zero;
   if (MODE >= 4) {
     q0 = p_hat(w.z0 - 4, in.c[base + row_index(w.z0 - 4)]);
     q1 = p_hat(w.z0 - 3, in.c[base + row_index(w.z0 - 3)]);
+    // B p^ on the first row of the march couples to the row above it
+    if (RHO) cd1 = g.dc[nn + row_index(w.z0 - 4)];
   }
   auto step = [&](int j, const PreRow<MODE>& L, bool odd) {
     const bool jin = xin && j >= 0 && j < g.nz;
@@ -194,8 +220,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
     if (MODE == 2) bj = csub(L.a, cmul(al, L.b));
     if (MODE >= 4) {
       const double2 q2 = p_hat(j + 1, L.c);
-      const double2 bp = apply_m(cx, axis_coef(j, g.nz), L.m, kaB, kbB, kc, ih2, q1,
-                                 cadd(from_left(q1), from_right(q1)), cadd(q0, q2));
+      double2 bp;
+      if (RHO) {
+        const RhoC cj = rho_row(x, j, L.cr, L.cd, cd1);
+        bp = apply_m_rho(cj, L.gb, cx.w * axis_coef(j, g.nz).w, L.m, kaB, kbB, kc, ih2, q1, from_left(q1),
+                         from_right(q1), q0, q2);
+      } else {
+        bp = apply_m(cx, axis_coef(j, g.nz), L.m, kaB, kbB, kc, ih2, q1, cadd(from_left(q1), from_right(q1)),
+                     cadd(q0, q2));
+      }
       q0 = q1;
       q1 = q2;
       if (MODE == 4) bj = fresh ? L.a : cadd(L.a, cmul(beta, csub(L.b, cmul(om, bp))));
@@ -209,9 +242,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
     const int i2 = j - 1;
     double2 u2c = zero;
     {
-      const double2 sx = cadd(from_left(u1b), from_right(u1b));
-      const double2 sz = cadd(u1a, u1c);
-      const double2 v = jacobi(u1b, b1, wd1, sx, sz, ih2 * axis_coef(i2, g.nz).w, cwx, omw);
+      double2 v;
+      if (RHO) {
+        v = jacobi_rho(u1b, b1, wd1, rho_row(x, i2, cr1, cd1, cd2), from_left(u1b), from_right(u1b), u1a, u1c,
+                       ih2, omw);
+      } else {
+        const double2 sx = cadd(from_left(u1b), from_right(u1b));
+        const double2 sz = cadd(u1a, u1c);
+        v = jacobi(u1b, b1, wd1, sx, sz, ih2 * axis_coef(i2, g.nz).w, cwx, omw);
+      }
       u2c = keep(xin && i2 >= 0 && i2 < g.nz, v);
     }
     if (own && i2 >= w.z0 && i2 < w.z1) {
@@ -223,9 +262,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
     const int ir = j - 2;
     double2 rc = zero;
     {
-      const double2 sx = cadd(from_left(u2b), from_right(u2b));
-      const double2 sz = cadd(u2a, u2c);
-      const double2 v = csub(b2, apply_m(cx, axis_coef(ir, g.nz), m2, ka, kb, kc, ih2, u2b, sx, sz));
+      double2 v;
+      if (RHO) {
+        const RhoC cir = rho_row(x, ir, cr2, cd2, cd3);
+        v = csub(b2, apply_m_rho(cir, gb2, cx.w * axis_coef(ir, g.nz).w, m2, ka, kb, kc, ih2, u2b, from_left(u2b),
+                                 from_right(u2b), u2a, u2c));
+      } else {
+        const double2 sx = cadd(from_left(u2b), from_right(u2b));
+        const double2 sz = cadd(u2a, u2c);
+        v = csub(b2, apply_m(cx, axis_coef(ir, g.nz), m2, ka, kb, kc, ih2, u2b, sx, sz));
+      }
       rc = keep(xin && ir >= 0 && ir < g.nz, v);
     }
     // full weighting: each residual row restricted horizontally once, then
@@ -252,6 +298,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
     u2b = u2c;
     ha = hb;
     hb = hc;
+    if (RHO) {
+      cd3 = cd2;
+      cr2 = cr1;
+      cd2 = cd1;
+      gb2 = gb1;
+      cr1 = L.cr;
+      cd1 = L.cd;
+      gb1 = L.gb;
+    }
   };
   // rows z0-3 .. z1+2; the first row is odd (z0 even), so pairs are (odd, even)
   for (int j = w.z0 - 3; j <= w.z1 + 2; j += 2) {
@@ -269,12 +324,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
 // HBM traffic per node: b and u_out, plus e on the coarse grid.
 constexpr int kPostWidth = kLanes - 6;
 
-struct PostRow {  // loads of one row j: b and w/D
+struct PostRow {  // loads of one row j: b and w/D (with a density also row j-1's coupling table)
   double2 b, wd;
+  double cr, cd;
 };
 
-template <bool FINE>
-__global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
+// RHO: with a density (Eq. (1)), the couplings come from the level's table
+// (g.dc), loaded one row behind b and kept for two rows; 3 waves per SIMD.
+template <bool FINE, bool RHO>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RHO ? 3 : 4, 8))) k_post2_s(Grid gf, Grid gc, int nstrip, int nchunk, int chunk_rows, int groups, int lvl,
                                                     Batch bt, const double2* __restrict__ e,
                                                     const double2* __restrict__ b,
                                                     double2* __restrict__ u_out, size_t sf, size_t sc) {
@@ -296,11 +354,17 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
   const double2 zero = c2(0.0, 0.0);
   const int ox = x & 1;
   const int Jx = xx >> 1, Jx1 = min(Jx + 1, gc.nx - 1);
+  const size_t nn = (size_t)gf.nz * gf.nx;
   auto load_row = [&](int j) {
     PostRow r;
     const size_t q = (size_t)min(max(j, 0), gf.nz - 1) * gf.nx + xx;
     r.b = bs[q];
     r.wd = wd[q];
+    if (RHO) {
+      const size_t q1 = (size_t)min(max(j - 1, 0), gf.nz - 1) * gf.nx + xx;
+      r.cr = gf.dc[q1];
+      r.cd = gf.dc[nn + q1];
+    }
     return r;
   };
   auto load_coarse = [&](int cr, double2& ea, double2& eb) {
@@ -313,6 +377,8 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
   // b, w/D on j-1, j-2, j-3
   double2 u1a = zero, u1b = zero, u3a = zero, u3b = zero, u4a = zero, u4b = zero;
   double2 b1 = zero, b2 = zero, b3 = zero, w1 = zero, w2 = zero, w3 = zero;
+  // RHO: the coupling table on rows j-2 and j-3, and the lower coupling of row j-4
+  double cr2 = 0.0, cd2 = 0.0, cr3 = 0.0, cd3 = 0.0, cd4 = 0.0;
   // lo, hi: coarse rows (j-1) >> 1 and the one below it
   auto step = [&](int j, const PostRow& L, double2 loa, double2 lob, double2 hia, double2 hib, bool odd_prev) {
     // outside the grid u1 = 0 through w/D; b there only enters values that are zeroed
@@ -322,9 +388,15 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
     const int i2 = j - 1;
     double2 u3c;
     {
-      const double2 sx = cadd(from_left(u1b), from_right(u1b));
-      const double2 sz = cadd(u1a, u1c);
-      const double2 u2 = jacobi(u1b, b1, w1, sx, sz, ih2 * axis_coef(i2, gf.nz).w, cwx, omw);
+      double2 u2;
+      if (RHO) {
+        u2 = jacobi_rho(u1b, b1, w1, rho_row(x, i2, L.cr, L.cd, cd2), from_left(u1b), from_right(u1b), u1a, u1c,
+                        ih2, omw);
+      } else {
+        const double2 sx = cadd(from_left(u1b), from_right(u1b));
+        const double2 sz = cadd(u1a, u1c);
+        u2 = jacobi(u1b, b1, w1, sx, sz, ih2 * axis_coef(i2, gf.nz).w, cwx, omw);
+      }
       double2 a = ox ? cscale(0.5, cadd(loa, lob)) : loa;
       if (odd_prev) {
         const double2 a2 = ox ? cscale(0.5, cadd(hia, hib)) : hia;
@@ -335,14 +407,22 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
     // first post-sweep on row j-2
     const int i4 = j - 2;
     double2 u4c;
-    {
+    if (RHO) {
+      u4c = keep(inside(i4), jacobi_rho(u3b, b2, w2, rho_row(x, i4, cr2, cd2, cd3), from_left(u3b), from_right(u3b),
+                                        u3a, u3c, ih2, omw));
+    } else {
       const double2 sx = cadd(from_left(u3b), from_right(u3b));
       const double2 sz = cadd(u3a, u3c);
       u4c = keep(inside(i4), jacobi(u3b, b2, w2, sx, sz, ih2 * axis_coef(i4, gf.nz).w, cwx, omw));
     }
     // second post-sweep on row j-3
     const int i5 = j - 3;
-    {
+    if (RHO) {
+      const RhoC c5 = rho_row(x, i5, cr3, cd3, cd4);
+      const double2 ul = from_left(u4b), ur = from_right(u4b);
+      if (own && i5 >= w.z0 && i5 < w.z1)
+        st_nt(u_out + base + (size_t)i5 * gf.nx + x, jacobi_rho(u4b, b3, w3, c5, ul, ur, u4a, u4c, ih2, omw));
+    } else {
       const double2 sx = cadd(from_left(u4b), from_right(u4b));
       if (own && i5 >= w.z0 && i5 < w.z1) {
         const double2 sz = cadd(u4a, u4c);
@@ -361,6 +441,13 @@ __global__ void __launch_bounds__(kBlock) k_post2_s(Grid gf, Grid gc, int nstrip
     w3 = w2;
     w2 = w1;
     w1 = wdj;
+    if (RHO) {
+      cd4 = cd3;
+      cr3 = cr2;
+      cd3 = cd2;
+      cr2 = L.cr;
+      cd2 = L.cd;
+    }
   };
   // rows z0-3 .. z1+2 in pairs (odd j, even j+1): the step of row j forms u3
   // on row j-1 (even, coarse row (j-1)/2 only) and the step of j+1 on row j
@@ -398,15 +485,21 @@ hipError_t launch_pre2r(const Grid& g, const Grid& gc, int lvl, int mode, const 
                         double2* bcoarse, size_t stride, size_t sc, int chunk_rows, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
-  if (g.rho) return hipErrorInvalidValue;  // constant density only
+  if (g.rho && !g.dc) return hipErrorInvalidValue;  // a density needs the level's coupling table
   // modes other than 0 form the finest level's right-hand side
   if (mode < 0 || mode > 5 || mode == 3 || (lvl != 0 && mode != 0)) return hipErrorInvalidValue;
   const StreamShape sh = stream_shape(g, pre_width(mode), chunk_rows);
   const RhsIn in{a, b, c};
   const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
-#define HZ_PRE2R(M, F)                                                                                     \
-  hipLaunchKernelGGL((k_pre2r_s<M, F>), gr, dim3(kBlock), 0, st, g, gc, sh.nstrip, sh.nchunk, chunk_rows,  \
-                     sh.groups, lvl, bt, in, bout, u2, bcoarse, stride, sc)
+#define HZ_PRE2R(M, F)                                                                                           \
+  do {                                                                                                           \
+    if (g.dc)                                                                                                    \
+      hipLaunchKernelGGL((k_pre2r_s<M, F, true>), gr, dim3(kBlock), 0, st, g, gc, sh.nstrip, sh.nchunk,         \
+                         chunk_rows, sh.groups, lvl, bt, in, bout, u2, bcoarse, stride, sc);                     \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_pre2r_s<M, F, false>), gr, dim3(kBlock), 0, st, g, gc, sh.nstrip, sh.nchunk,        \
+                         chunk_rows, sh.groups, lvl, bt, in, bout, u2, bcoarse, stride, sc);                     \
+  } while (0)
   if (mode == 1) HZ_PRE2R(1, true);
   else if (mode == 2) HZ_PRE2R(2, true);
   else if (mode == 4) HZ_PRE2R(4, true);
@@ -421,15 +514,20 @@ hipError_t launch_post2(const Grid& gf, const Grid& gc, int lvl, const Batch& bt
                         const double2* b, double2* u_out, size_t sf, size_t sc, int chunk_rows, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   if (chunk_rows < 2 || (chunk_rows & 1)) return hipErrorInvalidValue;
-  if (gf.rho) return hipErrorInvalidValue;  // constant density only
+  if (gf.rho && !gf.dc) return hipErrorInvalidValue;  // a density needs the level's coupling table
   const StreamShape sh = stream_shape(gf, kPostWidth, chunk_rows);
   const dim3 gr((unsigned)tile_blocks(sh.groups, cap));
-  if (lvl == 0)
-    hipLaunchKernelGGL(k_post2_s<true>, gr, dim3(kBlock), 0, st, gf, gc, sh.nstrip, sh.nchunk, chunk_rows,
-                       sh.groups, lvl, bt, e, b, u_out, sf, sc);
-  else
-    hipLaunchKernelGGL(k_post2_s<false>, gr, dim3(kBlock), 0, st, gf, gc, sh.nstrip, sh.nchunk, chunk_rows,
-                       sh.groups, lvl, bt, e, b, u_out, sf, sc);
+#define HZ_POST2(F, R)                                                                                          \
+  hipLaunchKernelGGL((k_post2_s<F, R>), gr, dim3(kBlock), 0, st, gf, gc, sh.nstrip, sh.nchunk, chunk_rows,   \
+                     sh.groups, lvl, bt, e, b, u_out, sf, sc)
+  if (gf.dc) {
+    if (lvl == 0) HZ_POST2(true, true);
+    else HZ_POST2(false, true);
+  } else {
+    if (lvl == 0) HZ_POST2(true, false);
+    else HZ_POST2(false, false);
+  }
+#undef HZ_POST2
   return hipGetLastError();
 }
 

