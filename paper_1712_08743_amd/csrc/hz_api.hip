@@ -1262,12 +1262,11 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
       }
       HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] { return launch_apply(c->dim, g0, 0, 0, bt, cap, zin, w, n0, st); }));
       HZ_HIP(c, launch_gm_dots(n0, bt, cap, gm, j, 0, V, vstride, w, n0, st));
-      HZ_HIP(c, launch_gm_orth(n0, bt, cap, rd, gm, j, 0, o->tol, o->maxit, V, vstride, w, n0, st));
+      HZ_HIP(c, launch_gm_orth(n0, bt, cap, rd, gm, j, V, vstride, w, n0, st));
       HZ_HIP(c, launch_gm_dots(n0, bt, cap, gm, j, 1, V, vstride, w, n0, st));
-      HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
-               return launch_gm_orth(n0, bt, cap, rd, gm, j, 1, o->tol, o->maxit, V, vstride, w, n0, st);
-             }));
-      HZ_HIP(c, launch_gm_scale(n0, bt, cap, w, n0, st));
+      HZ_HIP(c, launch_gm_orth_fin(bt, cap, gm, j, o->tol, o->maxit, st));
+      HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE,
+                      [&] { return launch_gm_orth_scale(n0, bt, cap, gm, j, V, vstride, w, n0, st); }));
       if ((rc = close_unit(0)) != HZ_OK) return rc;
       while ((int)pending.size() > (cy.plain ? 0 : kLag)) {
         const int k = pending.front().second;

@@ -293,9 +293,17 @@ hipError_t launch_gm_scale(size_t n, const Batch& bt, int cap, double2* v, size_
 hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, int pass,
                           const double2* V, size_t vstride, const double2* w, size_t stride,
                           hipStream_t st);
-hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm,
-                          int j, int pass, double tol, int maxit, const double2* V,
-                          size_t vstride, double2* w, size_t stride, hipStream_t st);
+// Gram-Schmidt against V_0..V_j (k_gm_* in hz_krylov.hip): launch_gm_dots
+// (pass 0), launch_gm_orth (first update and the reorthogonalisation test),
+// launch_gm_dots (pass 1, only the slots that reorthogonalise),
+// launch_gm_orth_fin (H column j, rotations, cycle-end test), then
+// launch_gm_orth_scale (second update where made, and the normalisation)
+hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm, int j,
+                          const double2* V, size_t vstride, double2* w, size_t stride, hipStream_t st);
+hipError_t launch_gm_orth_fin(const Batch& bt, int cap, const Gmres& gm, int j, double tol, int maxit,
+                              hipStream_t st);
+hipError_t launch_gm_orth_scale(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, const double2* V,
+                                size_t vstride, double2* w, size_t stride, hipStream_t st);
 hipError_t launch_gm_solve(const Batch& bt, int cap, const Gmres& gm, hipStream_t st);
 hipError_t launch_gm_combine(size_t n, const Batch& bt, int cap, const Gmres& gm,
                              const double2* V, size_t vstride, double2* t, size_t stride,

@@ -717,7 +717,15 @@ __global__ void __launch_bounds__(kBlock) k_true_residual_fin(int tiles, Batch b
 // Right-preconditioned restarted GMRES, one Arnoldi process per slot, all
 // slots of a cycle in lockstep. The basis vector i of slot s lives at
 // V + i * vstride + s * stride. Orthogonalisation is classical Gram-Schmidt
-// applied twice; every per-slot sum is a fixed-order two-kernel reduction.
+// with the reorthogonalisation test of Daniel, Gragg, Kaufman and Stewart
+// (1976): w' = w - V (V^H w); a second pass w'' = w' - V (V^H w') is made
+// only for the slots where ||w'|| < ||w|| / sqrt(2) (much of w lay in the
+// basis, so w' carries the rounding of that cancellation). The norm of the
+// result is ||w'||^2 - sum |h'_i|^2 (h' = V^H w', rounding-sized after one
+// pass), and the last update is fused with the normalisation. Per slot the
+// scalars hc[0][m].x = ||w||^2 and hc[1][m] = (||w'||^2, reorthogonalise?)
+// use the entries the coefficients of the first m - 1 steps leave free.
+// Every per-slot sum is a fixed-order two-kernel reduction.
 
 // r = b - B x (x = 0 on the first cycle, which also zeroes x) into V_0;
 // partial ||r||^2.
@@ -826,25 +834,29 @@ __global__ void __launch_bounds__(kBlock) k_gm_scale(Batch bt, int tiles, size_t
   }
 }
 
-// Partials of h_i = <V_i, w>, i = 0..j, in chunks of 8 basis vectors.
-__global__ void __launch_bounds__(kBlock) k_gm_dots(Batch bt, int tiles, size_t n, Gmres gm, int j,
+// Partials of h_i = <V_i, w>, i = 0..j, in chunks of 8 basis vectors; pass 0
+// also ||w||^2 (after the dots, entry 2 (j + 1)). Pass 1 runs only for the
+// slots that reorthogonalise.
+__global__ void __launch_bounds__(kBlock) k_gm_dots(Batch bt, int tiles, size_t n, Gmres gm, int j, int pass,
                                                     const double2* __restrict__ V, size_t vstride,
                                                     const double2* __restrict__ w, size_t stride) {
   int slot, tile;
   if (!decode_vec(bt, tiles, slot, tile)) return;
+  if (pass == 1 && gm.hc[((size_t)slot * 2 + 1) * (gm.m + 1) + gm.m].y == 0.0) return;
   const size_t base = (size_t)slot * stride;
   const int nv = j + 1;
   const int width = 2 * (gm.m + 1);
   double* part = gm.partials + ((size_t)slot * gm.max_tiles + tile) * width;
   for (int c0 = 0; c0 < nv; c0 += 8) {
-    double acc[16];
+    double acc[18];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 18; ++q) acc[q] = 0.0;
 #pragma unroll
     for (int e = 0; e < kVecPerThread; ++e) {
       const size_t i = vec_index(tile, e);
       if (i < n) {
         const double2 wi = w[base + i];
+        if (pass == 0 && c0 == 0) acc[16] += wi.x * wi.x + wi.y * wi.y;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           if (c0 + q < nv) {
@@ -855,17 +867,20 @@ __global__ void __launch_bounds__(kBlock) k_gm_dots(Batch bt, int tiles, size_t 
         }
       }
     }
-    block_sum<16>(acc);
+    block_sum<18>(acc);
     if (threadIdx.x == 0) {
       for (int q = 0; q < 8 && c0 + q < nv; ++q) {
         part[2 * (c0 + q)] = acc[2 * q];
         part[2 * (c0 + q) + 1] = acc[2 * q + 1];
       }
+      if (pass == 0 && c0 == 0) part[2 * nv] = acc[16];
     }
   }
 }
 
-// Sums of the dots in tile order: hc[pass] and column j of H (pass 0 sets, pass 1 adds).
+// Sums of the dots in tile order: hc[pass] and column j of H (pass 0 sets,
+// pass 1 adds; a slot that does not reorthogonalise gets hc[1] = 0); pass 0
+// also ||w||^2 into hc[0][m].x.
 __global__ void __launch_bounds__(kBlock) k_gm_dots_fin(int tiles, Batch bt, Gmres gm, int j, int pass) {
   int slot;
   if (!decode_slot_block(bt, slot)) return;
@@ -874,9 +889,18 @@ __global__ void __launch_bounds__(kBlock) k_gm_dots_fin(int tiles, Batch bt, Gmr
   const double* src = gm.partials + (size_t)slot * gm.max_tiles * width;
   double2* hc = gm.hc + ((size_t)slot * 2 + pass) * (gm.m + 1);
   double2* Hc = gm.H + (size_t)slot * (gm.m + 1) * gm.m + (size_t)j * (gm.m + 1);
-  for (int v = threadIdx.x; v < 2 * nv; v += blockDim.x) {
+  if (pass == 1 && hc[gm.m].y == 0.0) {
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) hc[i] = c2(0.0, 0.0);
+    return;
+  }
+  const int nsum = pass == 0 ? 2 * nv + 1 : 2 * nv;
+  for (int v = threadIdx.x; v < nsum; v += blockDim.x) {
     double sum = 0.0;
     for (int tt = 0; tt < tiles; ++tt) sum += src[(size_t)tt * width + v];
+    if (v == 2 * nv) {  // ||w||^2
+      hc[gm.m].x = sum;
+      continue;
+    }
     const int i = v >> 1;
     if (v & 1) {
       hc[i].y = sum;
@@ -888,14 +912,15 @@ __global__ void __launch_bounds__(kBlock) k_gm_dots_fin(int tiles, Batch bt, Gmr
   }
 }
 
-// w -= sum_i hc[pass]_i V_i; the second pass also stores the partial ||w||^2.
-__global__ void __launch_bounds__(kBlock) k_gm_orth(Batch bt, int tiles, size_t n, Reduce rd, Gmres gm,
-                                                    int j, int pass, const double2* __restrict__ V,
-                                                    size_t vstride, double2* __restrict__ w, size_t stride) {
+// The first update w' = w - sum_i hc[0]_i V_i (stored) and the partials of
+// ||w'||^2.
+__global__ void __launch_bounds__(kBlock) k_gm_orth(Batch bt, int tiles, size_t n, Reduce rd, Gmres gm, int j,
+                                                    const double2* __restrict__ V, size_t vstride,
+                                                    double2* __restrict__ w, size_t stride) {
   int slot, tile;
   if (!decode_vec(bt, tiles, slot, tile)) return;
   const size_t base = (size_t)slot * stride;
-  const double2* hc = gm.hc + ((size_t)slot * 2 + pass) * (gm.m + 1);
+  const double2* hc = gm.hc + (size_t)slot * 2 * (gm.m + 1);
   double acc[1] = {0.0};
 #pragma unroll
   for (int e = 0; e < kVecPerThread; ++e) {
@@ -907,7 +932,46 @@ __global__ void __launch_bounds__(kBlock) k_gm_orth(Batch bt, int tiles, size_t 
       acc[0] += wi.x * wi.x + wi.y * wi.y;
     }
   }
-  if (pass) store_partial<1>(acc, rd, slot, tile);
+  store_partial<1>(acc, rd, slot, tile);
+}
+
+// hc[1][m] = (||w'||^2, 1 where the slot reorthogonalises, else 0): where
+// ||w'||^2 < ||w||^2 / 2, or either is not finite.
+__global__ void __launch_bounds__(kBlock) k_gm_reorth_test(int tiles, Batch bt, Reduce rd, Gmres gm) {
+  int slot;
+  if (!decode_slot_block(bt, slot)) return;
+  double acc[1];
+  sum_partials<1>(acc, rd, slot, tiles);
+  if (threadIdx.x != 0) return;
+  const double2* h0 = gm.hc + (size_t)slot * 2 * (gm.m + 1);
+  double2* h1 = gm.hc + ((size_t)slot * 2 + 1) * (gm.m + 1);
+  const bool keep_one = acc[0] >= 0.5 * h0[gm.m].x;
+  h1[gm.m] = c2(acc[0], keep_one ? 0.0 : 1.0);
+}
+
+// The normalisation, fused with the second update where the slot
+// reorthogonalises: w = (w' - sum_i hc[1]_i V_i) / scal, else w' / scal;
+// scal = H[j+1, j] from k_gm_orth_fin (a zero norm leaves w unscaled).
+__global__ void __launch_bounds__(kBlock) k_gm_orth_scale(Batch bt, int tiles, size_t n, Gmres gm, int j,
+                                                          const double2* __restrict__ V, size_t vstride,
+                                                          double2* __restrict__ w, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const size_t base = (size_t)slot * stride;
+  const double2* hc = gm.hc + ((size_t)slot * 2 + 1) * (gm.m + 1);
+  const bool second = hc[gm.m].y != 0.0;
+  const double d = bt.slots[slot].scal.x;
+  const double inv = d == 0.0 ? 1.0 : 1.0 / d;
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      double2 wi = w[base + i];
+      if (second)
+        for (int q = 0; q <= j; ++q) wi = csub(wi, cmul(hc[q], V[(size_t)q * vstride + base + i]));
+      w[base + i] = cscale(inv, wi);
+    }
+  }
 }
 
 __device__ __forceinline__ void givens(double2 a, double2 b, double& c, double2& s) {
@@ -927,15 +991,13 @@ __device__ __forceinline__ void givens(double2 a, double2 b, double& c, double2&
   }
 }
 
-// After the second pass: ||w|| becomes H[j+1, j], the earlier rotations are
-// applied to column j, the new rotation annihilates H[j+1, j] and updates g,
-// and the cycle-end test is made.
-__global__ void __launch_bounds__(kBlock) k_gm_orth_fin(int tiles, Batch bt, Reduce rd, Gmres gm, int j,
-                                                        double tol, int maxit) {
+// After the second pass's dots: ||w''|| = sqrt(||w'||^2 - sum_i |hc[1]_i|^2)
+// (||w'|| where the slot does not reorthogonalise) becomes H[j+1, j], the
+// earlier rotations are applied to column j, the new rotation annihilates
+// H[j+1, j] and updates g, and the cycle-end test is made.
+__global__ void __launch_bounds__(kBlock) k_gm_orth_fin(Batch bt, Gmres gm, int j, double tol, int maxit) {
   int slot;
   if (!decode_slot_block(bt, slot)) return;
-  double acc[1];
-  sum_partials<1>(acc, rd, slot, tiles);
   if (threadIdx.x != 0) return;
   Slot& S = bt.slots[slot];
   const int m1 = gm.m + 1;
@@ -943,7 +1005,10 @@ __global__ void __launch_bounds__(kBlock) k_gm_orth_fin(int tiles, Batch bt, Red
   double* cs = gm.cs + (size_t)slot * gm.m;
   double2* sn = gm.sn + (size_t)slot * gm.m;
   double2* gg = gm.g + (size_t)slot * m1;
-  const double nrm = sqrt(acc[0]);
+  const double2* h1 = gm.hc + ((size_t)slot * 2 + 1) * m1;
+  double nrm2 = h1[gm.m].x;
+  for (int i = 0; i <= j; ++i) nrm2 -= h1[i].x * h1[i].x + h1[i].y * h1[i].y;
+  const double nrm = sqrt(fmax(nrm2, 0.0));
   Hc[j + 1] = c2(nrm, 0.0);
   for (int i = 0; i < j; ++i) {
     const double2 a = Hc[i], bb = Hc[i + 1];
@@ -1219,18 +1284,35 @@ hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Gmres& gm, i
                           hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_gm_dots, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, j, V, vstride, w, stride);
+  hipLaunchKernelGGL(k_gm_dots, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, j, pass, V,
+                     vstride, w, stride);
   hipLaunchKernelGGL(k_gm_dots_fin, dim3(cap), dim3(kBlock), 0, st, tiles, bt, gm, j, pass);
   return hipGetLastError();
 }
 
 hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm, int j,
-                          int pass, double tol, int maxit, const double2* V, size_t vstride, double2* w,
-                          size_t stride, hipStream_t st) {
+                          const double2* V, size_t vstride, double2* w, size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_gm_orth, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, gm, j, pass, V, vstride, w, stride);
-  if (pass) hipLaunchKernelGGL(k_gm_orth_fin, dim3(cap), dim3(kBlock), 0, st, tiles, bt, rd, gm, j, tol, maxit);
+  hipLaunchKernelGGL(k_gm_orth, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, gm, j, V,
+                     vstride, w, stride);
+  hipLaunchKernelGGL(k_gm_reorth_test, dim3(cap), dim3(kBlock), 0, st, tiles, bt, rd, gm);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_orth_fin(const Batch& bt, int cap, const Gmres& gm, int j, double tol, int maxit,
+                              hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gm_orth_fin, dim3(cap), dim3(kBlock), 0, st, bt, gm, j, tol, maxit);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_orth_scale(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, const double2* V,
+                                size_t vstride, double2* w, size_t stride, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  const int tiles = vec_tiles(n);
+  hipLaunchKernelGGL(k_gm_orth_scale, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, j, V,
+                     vstride, w, stride);
   return hipGetLastError();
 }
 
