@@ -171,9 +171,8 @@ int  hz_set_model(hz_ctx *c, int dim, int nz, int nx, double h, const double *m_
  * carries sqrt(rho) in its boundary part) then uses the density. On 2D
  * grids the fused kernels read a per-level table of the couplings (three
  * doubles per node of every level, built here: about 32 bytes per fine
- * node in all), and the levels the constant-density solve walks in two
- * small-level kernels take a launch per level and step; 1D grids take the
- * one-kernel-per-step V-cycle. The serving calls are not affected.
+ * node in all); 1D grids take the one-kernel-per-step V-cycle. The serving
+ * calls are not affected.
  * Errors: HZ_ERR_ARG (no 1D or 2D model, non-finite or non-positive rho),
  * HZ_ERR_NOMEM, HZ_ERR_DEVICE. */
 int  hz_set_density(hz_ctx *c, const double *rho_dev);

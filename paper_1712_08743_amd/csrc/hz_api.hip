@@ -734,8 +734,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   int l0 = L;
   SmallLevels sl;
   memset(&sl, 0, sizeof sl);
-  // (constant density only: a density takes a launch per level and step there)
-  if (dim == 2 && cy.nu1 == 2 && cy.nu2 == 2 && !cy.unfused && L >= 3 && !c->has_rho)
+  if (dim == 2 && cy.nu1 == 2 && cy.nu2 == 2 && !cy.unfused && L >= 3)
     for (int lf = 1; lf < L - 1 && l0 == L; ++lf) {
       if (c->lv[lf].n() > (size_t)kSmallNodes) continue;
       sl.l0 = lf;

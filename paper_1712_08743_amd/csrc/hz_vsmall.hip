@@ -17,7 +17,9 @@
 // (wz sx + wx sz) / h^2) (w / D tabulated per frequency and level), the
 // residual with the shifted Laplacian M of the level, full weighting 2^-2 P^T
 // of the residual (weight 1 for the last fine node of an even-count axis),
-// and bilinear prolongation.
+// and bilinear prolongation. With a density (Eq. (1), RHO) the couplings of
+// a node come from the level's table (Grid::dc, see RhoC), read where they
+// are used (the table is shared by every right-hand side and stays in cache).
 
 #include "hz_device.h"
 
@@ -53,6 +55,41 @@ __device__ __forceinline__ void nbr_sums(const double2* S, int p, int iz, int ix
   if (iz < nz - 1) sz = cadd(sz, S[p + nx]);
 }
 
+// the density couplings of node p = (iz, ix) from the level's table
+__device__ __forceinline__ RhoC rho_at(const Grid& g, int p, int iz, int ix) {
+  const size_t n = (size_t)g.nz * g.nx;
+  RhoC c;
+  c.l = ix > 0 ? g.dc[p - 1] : 0.0;
+  c.r = g.dc[p];
+  c.u = iz > 0 ? g.dc[n + p - g.nx] : 0.0;
+  c.d = g.dc[n + p];
+  return c;
+}
+
+// the four neighbours of node p in LDS (zero where missing)
+__device__ __forceinline__ void nbrs(const double2* S, int p, int iz, int ix, int nz, int nx, double2& xl, double2& xr,
+                                     double2& xu, double2& xd) {
+  const double2 z = c2(0.0, 0.0);
+  xl = ix > 0 ? S[p - 1] : z;
+  xr = ix < nx - 1 ? S[p + 1] : z;
+  xu = iz > 0 ? S[p - nx] : z;
+  xd = iz < nz - 1 ? S[p + nx] : z;
+}
+
+// one damped-Jacobi update at node p of level g from the values in LDS
+template <bool RHO>
+__device__ __forceinline__ double2 sweep_at(const Grid& g, const double2* S, int p, int iz, int ix, double2 u, double2 b,
+                                            double2 wd, double ih2, double omw) {
+  if (RHO) {
+    double2 xl, xr, xu, xd;
+    nbrs(S, p, iz, ix, g.nz, g.nx, xl, xr, xu, xd);
+    return jacobi_rho(u, b, wd, rho_at(g, p, iz, ix), xl, xr, xu, xd, ih2, omw);
+  }
+  double2 sx, sz;
+  nbr_sums(S, p, iz, ix, g.nz, g.nx, sx, sz);
+  return jacobi_form(u, b, wd, sx, sz, ih2 * end_w(iz, g.nz), ih2 * end_w(ix, g.nx), omw);
+}
+
 // bilinear interpolation of coarse e at fine node (iz, ix); the last node of
 // an even-count axis takes the last coarse node alone (clamped index)
 __device__ __forceinline__ double2 prolong_at(const double2* __restrict__ e, int iz, int ix, int ncx, int ncz) {
@@ -70,6 +107,7 @@ __device__ __forceinline__ double2 prolong_at(const double2* __restrict__ e, int
 }  // namespace
 
 // Descent over levels l0 .. L-2 and the coarsest level's sweeps.
+template <bool RHO>
 __global__ void __launch_bounds__(kSmallBlock) k_vdown(SmallLevels s, Batch bt) {
   extern __shared__ double2 S[];
   int slot;
@@ -106,9 +144,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_vdown(SmallLevels s, Batch bt) 
       const int p = t + k * kSmallBlock;
       if (p >= n) continue;
       const int iz = p / g.nx, ix = p - iz * g.nx;
-      double2 sx, sz;
-      nbr_sums(S, p, iz, ix, g.nz, g.nx, sx, sz);
-      uk[k] = jacobi_form(S[p], bk[k], wk[k], sx, sz, ih2 * end_w(iz, g.nz), ih2 * end_w(ix, g.nx), omw);
+      uk[k] = sweep_at<RHO>(g, S, p, iz, ix, S[p], bk[k], wk[k], ih2, omw);
     }
     __syncthreads();
     // the slowness for the residual (w / D is no longer needed)
@@ -128,10 +164,19 @@ __global__ void __launch_bounds__(kSmallBlock) k_vdown(SmallLevels s, Batch bt) 
       const int p = t + k * kSmallBlock;
       if (p >= n) continue;
       const int iz = p / g.nx, ix = p - iz * g.nx;
-      const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, mk[k], f.omega, f.sM_re, f.sM_im);
-      double2 sx, sz;
-      nbr_sums(S, p, iz, ix, g.nz, g.nx, sx, sz);
-      uk[k] = csub(bk[k], stencil(c, ih2, uk[k], sx, sz));
+      if (RHO) {
+        double2 xl, xr, xu, xd;
+        nbrs(S, p, iz, ix, g.nz, g.nx, xl, xr, xu, xd);
+        const double om2 = f.omega * f.omega;
+        const double gb = g.dc[2 * (size_t)n + p];
+        uk[k] = csub(bk[k], apply_m_rho(rho_at(g, p, iz, ix), gb, end_w(iz, g.nz) * end_w(ix, g.nx), mk[k],
+                                        -om2 * f.sM_re, -om2 * f.sM_im, f.omega / g.h, ih2, uk[k], xl, xr, xu, xd));
+      } else {
+        const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, mk[k], f.omega, f.sM_re, f.sM_im);
+        double2 sx, sz;
+        nbr_sums(S, p, iz, ix, g.nz, g.nx, sx, sz);
+        uk[k] = csub(bk[k], stencil(c, ih2, uk[k], sx, sz));
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -180,14 +225,16 @@ __global__ void __launch_bounds__(kSmallBlock) k_vdown(SmallLevels s, Batch bt) 
     double2* dst = sw + 1 == s.coarse_sweeps ? u : nxt;
     for (int p = t; p < n; p += kSmallBlock) {
       const int iz = p / g.nx, ix = p - iz * g.nx;
-      const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
-      const double2 wdinv = cscale(s.coarse_w, cinv(diag_of<true>(c, ih2)));
+      // (node_op reads the density itself: the per-step kernels' arithmetic)
+      const NodeOp o = node_op<true>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
+      const double2 wdinv = cscale(s.coarse_w, cinv(diag_of<true>(o.c, ih2)));
       if (sw == 0) {
         dst[p] = cmul(b[p], wdinv);
       } else {
-        double2 sx, sz;
-        nbr_sums(cur, p, iz, ix, g.nz, g.nx, sx, sz);
-        const double2 res = csub(b[p], stencil(c, ih2, cur[p], sx, sz));
+        const int nx = g.nx;
+        const double2 res = csub(b[p], apply_op_at<true>(g, o, iz, ix, ih2, cur[p], [&](int dz, int dx) {
+                                   return cur[p + dz * nx + dx];
+                                 }));
         dst[p] = cadd(cur[p], cmul(res, wdinv));
       }
     }
@@ -200,6 +247,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_vdown(SmallLevels s, Batch bt) 
 
 // Ascent over levels L-2 .. l0: u = two sweeps from u2 + P e, with u2 the
 // pre-smoothed iterate the descent left in the level's first buffer.
+template <bool RHO>
 __global__ void __launch_bounds__(kSmallBlock) k_vup(SmallLevels s, Batch bt) {
   extern __shared__ double2 S[];
   int slot;
@@ -238,9 +286,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_vup(SmallLevels s, Batch bt) {
         const int p = t + k * kSmallBlock;
         if (p >= n) continue;
         const int iz = p / g.nx, ix = p - iz * g.nx;
-        double2 sx, sz;
-        nbr_sums(S, p, iz, ix, g.nz, g.nx, sx, sz);
-        uk[k] = jacobi_form(uk[k], bk[k], wk[k], sx, sz, ih2 * end_w(iz, g.nz), ih2 * end_w(ix, g.nx), omw);
+        uk[k] = sweep_at<RHO>(g, S, p, iz, ix, uk[k], bk[k], wk[k], ih2, omw);
       }
       __syncthreads();
     }
@@ -274,27 +320,29 @@ hipError_t allow_lds(K kernel, size_t bytes, std::atomic<size_t>& allowed) {
   }
   return e;
 }
-std::atomic<size_t> g_allowed_down{0}, g_allowed_up{0};
+std::atomic<size_t> g_allowed[4];  // k_vdown<false, true>, k_vup<false, true>
+
+template <bool RHO>
+hipError_t launch_small(bool down, const SmallLevels& s, const Batch& bt, int cap, hipStream_t st) {
+  const size_t lds = small_levels_lds(s);
+  const auto kernel = down ? k_vdown<RHO> : k_vup<RHO>;
+  const hipError_t e = allow_lds(kernel, lds, g_allowed[(down ? 0 : 2) + (RHO ? 1 : 0)]);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)cap), dim3(kSmallBlock), lds, st, s, bt);
+  return hipGetLastError();
+}
 }  // namespace
 
 hipError_t launch_vdown(const SmallLevels& s, const Batch& bt, int cap, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
-  if (s.g[s.l0].rho) return hipErrorInvalidValue;  // constant density only
-  const size_t lds = small_levels_lds(s);
-  const hipError_t e = allow_lds(k_vdown, lds, g_allowed_down);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_vdown, dim3((unsigned)cap), dim3(kSmallBlock), lds, st, s, bt);
-  return hipGetLastError();
+  if (s.g[s.l0].rho && !s.g[s.l0].dc) return hipErrorInvalidValue;  // a density needs the coupling tables
+  return s.g[s.l0].dc ? launch_small<true>(true, s, bt, cap, st) : launch_small<false>(true, s, bt, cap, st);
 }
 
 hipError_t launch_vup(const SmallLevels& s, const Batch& bt, int cap, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
-  if (s.g[s.l0].rho) return hipErrorInvalidValue;  // constant density only
-  const size_t lds = small_levels_lds(s);
-  const hipError_t e = allow_lds(k_vup, lds, g_allowed_up);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_vup, dim3((unsigned)cap), dim3(kSmallBlock), lds, st, s, bt);
-  return hipGetLastError();
+  if (s.g[s.l0].rho && !s.g[s.l0].dc) return hipErrorInvalidValue;  // a density needs the coupling tables
+  return s.g[s.l0].dc ? launch_small<true>(false, s, bt, cap, st) : launch_small<false>(false, s, bt, cap, st);
 }
 
 }  // namespace hz
