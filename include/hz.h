@@ -157,9 +157,10 @@ void hz_destroy(hz_ctx *c);
 int  hz_set_model(hz_ctx *c, int dim, int nz, int nx, double h, const double *m_dev);
 
 /* Variable density (Eq. (1): -div(rho grad u) - k^2 (1 - j alpha) u = f) on
- * the 1D or 2D model set last. rho_dev: device, [nz][nx] doubles, finite and
- * positive, copied; NULL returns to constant density (Eq. (2)). A new
- * hz_set_model also does. Discretisation: the coupling of two neighbouring
+ * the model set last (1D, 2D or 3D). rho_dev: device, [nz][nx] doubles
+ * ([nz][ny][nx] in 3D), finite and positive, copied; NULL returns to
+ * constant density (Eq. (2)). A new hz_set_model or hz_set_model_3d also
+ * does. Discretisation: the coupling of two neighbouring
  * nodes is multiplied by the mean (rho_p + rho_q) / 2 of their densities,
  * and the absorbing boundary is written for the flux, rho du/dn + j omega m
  * sqrt(rho) u = 0, so its term carries sqrt(rho_p); the shifted Laplacian M
@@ -171,9 +172,9 @@ int  hz_set_model(hz_ctx *c, int dim, int nz, int nx, double h, const double *m_
  * carries sqrt(rho) in its boundary part) then uses the density. On 2D
  * grids the fused kernels read a per-level table of the couplings (three
  * doubles per node of every level, built here: about 32 bytes per fine
- * node in all); 1D grids take the one-kernel-per-step V-cycle. The serving
- * calls are not affected.
- * Errors: HZ_ERR_ARG (no 1D or 2D model, non-finite or non-positive rho),
+ * node in all); 1D and 3D grids take the one-kernel-per-step V-cycle. The
+ * serving calls are not affected.
+ * Errors: HZ_ERR_ARG (no model, non-finite or non-positive rho),
  * HZ_ERR_NOMEM, HZ_ERR_DEVICE. */
 int  hz_set_density(hz_ctx *c, const double *rho_dev);
 

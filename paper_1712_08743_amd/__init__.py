@@ -229,8 +229,8 @@ class Context:
         return self
 
     def set_density(self, rho):
-        """Density of Eq. (1) on the 1D or 2D model (float64 tensor of the
-        model's shape, finite and positive); None returns to constant density."""
+        """Density of Eq. (1) on the model (float64 tensor of the model's
+        shape, finite and positive); None returns to constant density."""
         if rho is None:
             self._check(_lib.hz_set_density(self._h, None))
             self._rho = None

@@ -137,7 +137,7 @@ struct hz_ctx {
   // under a density); m_lo, m_hi: the range of the model itself
   double h = 0.0, mmin = 0.0, mmax = 0.0, m_lo = 0.0, m_hi = 0.0;
   int maxlev = 0;
-  int has_rho = 0;  // a density of Eq. (1) is set (1D and 2D grids)
+  int has_rho = 0;  // a density of Eq. (1) is set
   LevelInfo lv[kMaxLevels];
   int model_version = 0;
   // solver workspace
@@ -621,7 +621,7 @@ struct Cycle {
   int autotune, chunk_rows;  // launch shape of the fused kernels (opts.autotune, opts.chunk_rows)
   int coarse_sweeps;         // > 0: some frequency smooths its coarsest level with this many sweeps
   int plain;                 // opts.plain: one kernel per step, dense r^, host readback every iteration
-  int unfused;               // no fused V-cycle kernels (opts.plain, or a density on a 1D grid)
+  int unfused;               // no fused V-cycle kernels (opts.plain, or a density on a 1D or 3D grid)
 };
 
 // ---------------------------------------------------------------- launch-shape tuning
@@ -1506,7 +1506,7 @@ int hz_set_model(hz_ctx* c, int dim, int nz, int nx, double h, const double* m_d
 
 int hz_set_density(hz_ctx* c, const double* rho_dev) {
   if (!c) return HZ_ERR_ARG;
-  if (c->dim != 1 && c->dim != 2) return fail(c, HZ_ERR_ARG, "a density needs a 1D or 2D model set first");
+  if (c->dim < 1 || c->dim > 3) return fail(c, HZ_ERR_ARG, "a density needs a model set first");
   HZ_HIP(c, hipSetDevice(c->device));
   HZ_HIP(c, hipStreamSynchronize(c->stream));
   if (!rho_dev) {

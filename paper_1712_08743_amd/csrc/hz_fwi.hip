@@ -51,7 +51,9 @@ __device__ __forceinline__ void sens_geom(const Grid& g, size_t p, double& gh, d
     const size_t r = p / g.nx;
     const int ix = (int)(p - r * g.nx), iz = (int)(r / g.ny), iy = (int)(r - (size_t)iz * g.ny);
     // with omega = m = 1 and no mass shift, kap.y is the boundary weight over h
+    // (a density of Eq. (1) scales it by sqrt(rho_i))
     gh = node_coef3(iz, iy, ix, g, 1.0 / g.h, 1.0, 1.0, 0.0, 0.0).kap.y;
+    if (g.rho) gh *= sqrt(g.rho[p]);
     w = (iz == 0 || iz == g.nz - 1 ? 0.5 : 1.0) * (iy == 0 || iy == g.ny - 1 ? 0.5 : 1.0) *
         (ix == 0 || ix == g.nx - 1 ? 0.5 : 1.0);
   } else {

@@ -40,8 +40,8 @@ struct Grid {
   // models of several requests in one batch: frequency entry f reads its
   // slowness at m + FreqTab::model * mstride (0: one model for every entry)
   size_t mstride = 0;
-  // density of Eq. (1) on this level, [nz][nx] (1D and 2D grids; null:
-  // constant density, the operator of Eq. (2))
+  // density of Eq. (1) on this level, [nz][nx] ([nz][ny][nx] on 3D grids;
+  // null: constant density, the operator of Eq. (2))
   const double* rho = nullptr;
   // 2D grids with a density: the level's coupling table (RhoC in hz_device.h),
   // [3][nz][nx]; the fused kernels read it instead of rho

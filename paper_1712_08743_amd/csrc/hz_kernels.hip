@@ -778,9 +778,9 @@ __global__ void __launch_bounds__(kBlock) k_apply3(Grid g, Tiles t, int which, B
   if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, g, iz, iy, ix, p)) return;
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const double sre = which ? f.sM_re : f.sB_re, sim = which ? f.sM_im : f.sB_im;
-  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, sre, sim);
+  const NodeOp3 o = node_op3(iz, iy, ix, g, p, model_m(g, f)[p], f.omega, sre, sim);
   const double2* xs = x + (size_t)slot * stride;
-  y[(size_t)slot * stride + p] = apply_node3(xs, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
+  y[(size_t)slot * stride + p] = apply_op3(g, o, xs, p, iz, iy, ix, 1.0 / (g.h * g.h));
 }
 
 // u_out = u_in + w (b - M u_in) / diag(M); ZERO: u_in = 0 (as k_smooth)
@@ -795,8 +795,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   if (coarse_only && !f.coarse_jacobi) return;
   const double ih2 = 1.0 / (g.h * g.h);
-  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
-  const double2 wdinv = w_override > 0.0 ? cscale(w_override, cinv(diag3(c, ih2))) : f.winv[lvl][p];
+  const NodeOp3 o = node_op3(iz, iy, ix, g, p, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
+  const double2 wdinv = w_override > 0.0 ? cscale(w_override, cinv(diag3(o.c, ih2))) : f.winv[lvl][p];
   const size_t base = (size_t)slot * stride;
   const double2 bp = b[base + p];
   double2 out;
@@ -804,7 +804,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
     out = cmul(bp, wdinv);
   } else {
     const double2* us = u_in + base;
-    const double2 res = csub(bp, apply_node3(us, p, iz, iy, ix, g, ih2, c));
+    const double2 res = csub(bp, apply_op3(g, o, us, p, iz, iy, ix, ih2));
     out = cadd(us[p], cmul(res, wdinv));
   }
   u_out[base + p] = out;
@@ -936,8 +936,8 @@ __global__ void k_winv3(Grid g, double omega, double s_re, double s_im, double w
   const int ix = (int)(p % g.nx);
   const int r = (int)(p / g.nx);
   const int iz = r / g.ny, iy = r - iz * g.ny;
-  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, g.m[p], omega, s_re, s_im);
-  winv[p] = cscale(w, cinv(diag3(c, 1.0 / (g.h * g.h))));
+  const NodeOp3 o = node_op3(iz, iy, ix, g, p, g.m[p], omega, s_re, s_im);
+  winv[p] = cscale(w, cinv(diag3(o.c, 1.0 / (g.h * g.h))));
 }
 
 // weight of fine offset d in {-1, 0, 1} around coarse node J in P^T (see k_restrict)
@@ -971,8 +971,8 @@ __global__ void __launch_bounds__(kBlock) k_restrict3(Grid gf, Grid gc, Tiles t,
         const int ix = 2 * Ix + dx;
         if (ix < 0 || ix >= gf.nx) continue;
         const size_t p = ((size_t)iz * gf.ny + iy) * gf.nx + ix;
-        const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
-        const double2 r = csub(bs[p], apply_node3(us, p, iz, iy, ix, gf, ih2, c));
+        const NodeOp3 o = node_op3(iz, iy, ix, gf, p, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
+        const double2 r = csub(bs[p], apply_op3(gf, o, us, p, iz, iy, ix, ih2));
         acc = cadd(acc, cscale(wzy * pt_weight(dx, Ix, gf.nx), r));
       }
     }
@@ -989,8 +989,8 @@ __global__ void __launch_bounds__(kBlock) k_residual3(Grid g, Tiles t, Batch bt,
   if (!decode_tile(bt, t.per_slot, slot, tile) || !node3_of(t, tile, g, iz, iy, ix, p)) return;
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const size_t base = (size_t)slot * stride;
-  const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
-  r[base + p] = csub(b[base + p], apply_node3(u + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c));
+  const NodeOp3 o = node_op3(iz, iy, ix, g, p, model_m(g, f)[p], f.omega, f.sM_re, f.sM_im);
+  r[base + p] = csub(b[base + p], apply_op3(g, o, u + base, p, iz, iy, ix, 1.0 / (g.h * g.h)));
 }
 
 // bc = 2^-3 P^T r from a stored fine residual (the weights of k_restrict3)
@@ -1055,16 +1055,11 @@ __global__ void __launch_bounds__(kBlock) k_prolong_smooth3(Grid gf, Grid gc, Ti
   auto u3_at = [&](int qz, int qy, int qx) -> double2 {
     return cadd(us[((size_t)qz * gf.ny + qy) * gf.nx + qx], interp3(es, qz, qy, qx, gc.nz, gc.ny, gc.nx));
   };
-  const NodeC3 c = node_coef3(iz, iy, ix, gf, 1.0 / gf.h, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
+  const NodeOp3 o = node_op3(iz, iy, ix, gf, p, model_m(gf, f)[p], f.omega, f.sM_re, f.sM_im);
   const double2 u3p = u3_at(iz, iy, ix);
-  double2 sz = c2(0.0, 0.0), sy = c2(0.0, 0.0), sx = c2(0.0, 0.0);
-  if (ix > 0) sx = cadd(sx, u3_at(iz, iy, ix - 1));
-  if (ix < gf.nx - 1) sx = cadd(sx, u3_at(iz, iy, ix + 1));
-  if (iy > 0) sy = cadd(sy, u3_at(iz, iy - 1, ix));
-  if (iy < gf.ny - 1) sy = cadd(sy, u3_at(iz, iy + 1, ix));
-  if (iz > 0) sz = cadd(sz, u3_at(iz - 1, iy, ix));
-  if (iz < gf.nz - 1) sz = cadd(sz, u3_at(iz + 1, iy, ix));
-  const double2 res = csub(b[base + p], stencil3(c, ih2, u3p, sz, sy, sx));
+  const double2 res = csub(b[base + p], apply_op3_at(gf, o, iz, iy, ix, ih2, u3p, [&](int dz, int dy, int dx) {
+                             return u3_at(iz + dz, iy + dy, ix + dx);
+                           }));
   u_out[base + p] = cadd(u3p, cmul(res, f.winv[lvl][p]));
 }
 
@@ -1079,17 +1074,17 @@ __global__ void k_assemble_dense3(Grid g, int nfreq, const FreqTab* __restrict__
     const int i = (int)(rem / nc), j = (int)(rem - (size_t)i * nc);
     const int ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
     const int jx = j % g.nx, jy = (j / g.nx) % g.ny, jz = j / (g.nx * g.ny);
-    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, ft[f])[i], ft[f].omega, ft[f].sM_re,
-                                ft[f].sM_im);
+    const NodeOp3 o = node_op3(iz, iy, ix, g, i, model_m(g, ft[f])[i], ft[f].omega, ft[f].sM_re, ft[f].sM_im);
+    const NodeC3& c = o.c;
     double2 val = c2(0.0, 0.0);
     if (i == j) {
       val = diag3(c, ih2);
     } else if (jz == iz && jy == iy && (jx == ix - 1 || jx == ix + 1)) {
-      val = c2(-c.fx * ih2, 0.0);
+      val = c2(-(g.rho ? o.cq[jx == ix - 1 ? 0 : 1] : c.fx) * ih2, 0.0);
     } else if (jz == iz && jx == ix && (jy == iy - 1 || jy == iy + 1)) {
-      val = c2(-c.fy * ih2, 0.0);
+      val = c2(-(g.rho ? o.cq[jy == iy - 1 ? 2 : 3] : c.fy) * ih2, 0.0);
     } else if (jy == iy && jx == ix && (jz == iz - 1 || jz == iz + 1)) {
-      val = c2(-c.fz * ih2, 0.0);
+      val = c2(-(g.rho ? o.cq[jz == iz - 1 ? 4 : 5] : c.fz) * ih2, 0.0);
     }
     A[e] = val;
   }
@@ -1145,7 +1140,9 @@ hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, con
                          int cap, const double2* b, const double2* u_in, double2* u_out,
                          size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
-  if (dim == 3 && u_in && w_override <= 0.0) return launch_march3(g, lvl, bt, cap, false, b, u_in, u_out, stride, st);
+  // (the marching sweep has constant density only)
+  if (dim == 3 && u_in && w_override <= 0.0 && !g.rho)
+    return launch_march3(g, lvl, bt, cap, false, b, u_in, u_out, stride, st);
   if (dim == 3) {
     const Tiles t = tiles3(g);
     const dim3 gr = grid1(tile_blocks(t.per_slot, cap));

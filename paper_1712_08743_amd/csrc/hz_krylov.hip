@@ -187,8 +187,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply3(Grid g, Tiles t, Batch b
   int iz, iy, ix;
   size_t p;
   if (node3_of(t, tile, g, iz, iy, ix, p)) {
-    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
-    const double2 yp = apply_node3(xin + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
+    const NodeOp3 o = node_op3(iz, iy, ix, g, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+    const double2 yp = apply_op3(g, o, xin + base, p, iz, iy, ix, 1.0 / (g.h * g.h));
     y[base + p] = yp;
     if (WHICH == 0) {
       if (dots) {
@@ -690,8 +690,8 @@ __global__ void __launch_bounds__(kBlock) k_true_residual3(Grid g, Tiles t, Batc
   int iz, iy, ix;
   size_t p;
   if (node3_of(t, tile, g, iz, iy, ix, p)) {
-    const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
-    const double2 y = apply_node3(x + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c);
+    const NodeOp3 o = node_op3(iz, iy, ix, g, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+    const double2 y = apply_op3(g, o, x + base, p, iz, iy, ix, 1.0 / (g.h * g.h));
     const double2 bp = b[base + p];
     const double2 rr = csub(bp, y);
     acc[0] = rr.x * rr.x + rr.y * rr.y;
@@ -775,8 +775,8 @@ __global__ void __launch_bounds__(kBlock) k_gm_residual3(Grid g, Tiles t, Batch 
       r = b[base + p];
     } else {
       const FreqTab& f = bt.ft[bt.slots[slot].freq];
-      const NodeC3 c = node_coef3(iz, iy, ix, g, 1.0 / g.h, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
-      r = csub(b[base + p], apply_node3(x + base, p, iz, iy, ix, g, 1.0 / (g.h * g.h), c));
+      const NodeOp3 o = node_op3(iz, iy, ix, g, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
+      r = csub(b[base + p], apply_op3(g, o, x + base, p, iz, iy, ix, 1.0 / (g.h * g.h)));
     }
     v0[base + p] = r;
     acc[0] = r.x * r.x + r.y * r.y;

@@ -21,8 +21,9 @@ struct NodeC3 {
   double2 kap;        // boundary and mass term (diagonal part without lsum / h^2)
 };
 
+// gs scales the absorbing term (sqrt of the node's density, see node_op3)
 __device__ __forceinline__ NodeC3 node_coef3(int iz, int iy, int ix, const Grid& g, double ih, double m,
-                                             double omega, double s_re, double s_im) {
+                                             double omega, double s_re, double s_im, double gs = 1.0) {
   const int ez = (iz == 0) + (iz == g.nz - 1), ey = (iy == 0) + (iy == g.ny - 1), ex = (ix == 0) + (ix == g.nx - 1);
   const double wz = ez ? 0.5 : 1.0, wy = ey ? 0.5 : 1.0, wx = ex ? 0.5 : 1.0;
   NodeC3 c;
@@ -32,7 +33,7 @@ __device__ __forceinline__ NodeC3 node_coef3(int iz, int iy, int ix, const Grid&
   c.lsum = c.fz * (double)(2 - ez) + c.fy * (double)(2 - ey) + c.fx * (double)(2 - ex);
   const double gb = c.fz * (double)ez + c.fy * (double)ey + c.fx * (double)ex;
   const double om2wm2 = omega * omega * (wz * wy * wx) * (m * m);
-  c.kap = c2(-om2wm2 * s_re, omega * gb * m * ih - om2wm2 * s_im);
+  c.kap = c2(-om2wm2 * s_re, omega * gb * m * ih * gs - om2wm2 * s_im);
   return c;
 }
 
@@ -61,6 +62,72 @@ __device__ __forceinline__ double2 apply_node3(const double2* __restrict__ x, si
   const double2 ay = cadd(cadd(zero, yl ? vyl : zero), yr ? vyr : zero);
   const double2 az = cadd(cadd(zero, zl ? vzl : zero), zr ? vzr : zero);
   return stencil3(c, ih2, x[p], az, ay, ax);
+}
+
+// ---- variable density (Eq. (1) with d = 3): the coupling to a neighbour is
+// the face weight times the mean density of the two nodes, the absorbing
+// term carries sqrt(rho_p) (as node_op in 2D). Grid::rho null: node_op3 and
+// apply_op3 are node_coef3 and apply_node3.
+struct NodeOp3 {
+  NodeC3 c;      // lsum: the sum of the couplings in use
+  double cq[6];  // density couplings to the -x, +x, -y, +y, -z, +z neighbours (0 where missing)
+};
+
+__device__ __forceinline__ NodeOp3 node_op3(int iz, int iy, int ix, const Grid& g, size_t p, double m, double omega,
+                                            double s_re, double s_im) {
+  NodeOp3 o;
+  if (!g.rho) {
+    o.c = node_coef3(iz, iy, ix, g, 1.0 / g.h, m, omega, s_re, s_im);
+    return o;
+  }
+  const double* r = g.rho;
+  const double rp = r[p];
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  o.c = node_coef3(iz, iy, ix, g, 1.0 / g.h, m, omega, s_re, s_im, sqrt(rp));
+  o.cq[0] = ix > 0 ? o.c.fx * (0.5 * (rp + r[p - 1])) : 0.0;
+  o.cq[1] = ix < g.nx - 1 ? o.c.fx * (0.5 * (rp + r[p + 1])) : 0.0;
+  o.cq[2] = iy > 0 ? o.c.fy * (0.5 * (rp + r[p - sy])) : 0.0;
+  o.cq[3] = iy < g.ny - 1 ? o.c.fy * (0.5 * (rp + r[p + sy])) : 0.0;
+  o.cq[4] = iz > 0 ? o.c.fz * (0.5 * (rp + r[p - sz])) : 0.0;
+  o.cq[5] = iz < g.nz - 1 ? o.c.fz * (0.5 * (rp + r[p + sz])) : 0.0;
+  o.c.lsum = ((o.cq[0] + o.cq[1]) + (o.cq[2] + o.cq[3])) + (o.cq[4] + o.cq[5]);
+  return o;
+}
+
+// (A x)_p with the value at p and the neighbours' values from val(dz, dy, dx),
+// called for the existing neighbours only
+template <class F>
+__device__ __forceinline__ double2 apply_op3_at(const Grid& g, const NodeOp3& o, int iz, int iy, int ix, double ih2,
+                                                double2 xp, F val) {
+  if (!g.rho) {
+    double2 sz = c2(0.0, 0.0), sy = c2(0.0, 0.0), sx = c2(0.0, 0.0);
+    if (ix > 0) sx = cadd(sx, val(0, 0, -1));
+    if (ix < g.nx - 1) sx = cadd(sx, val(0, 0, 1));
+    if (iy > 0) sy = cadd(sy, val(0, -1, 0));
+    if (iy < g.ny - 1) sy = cadd(sy, val(0, 1, 0));
+    if (iz > 0) sz = cadd(sz, val(-1, 0, 0));
+    if (iz < g.nz - 1) sz = cadd(sz, val(1, 0, 0));
+    return stencil3(o.c, ih2, xp, sz, sy, sx);
+  }
+  double2 s = c2(0.0, 0.0);
+  if (ix > 0) s = cadd(s, cscale(o.cq[0], val(0, 0, -1)));
+  if (ix < g.nx - 1) s = cadd(s, cscale(o.cq[1], val(0, 0, 1)));
+  if (iy > 0) s = cadd(s, cscale(o.cq[2], val(0, -1, 0)));
+  if (iy < g.ny - 1) s = cadd(s, cscale(o.cq[3], val(0, 1, 0)));
+  if (iz > 0) s = cadd(s, cscale(o.cq[4], val(-1, 0, 0)));
+  if (iz < g.nz - 1) s = cadd(s, cscale(o.cq[5], val(1, 0, 0)));
+  const double2 lx = c2(o.c.lsum * xp.x - s.x, o.c.lsum * xp.y - s.y);
+  return cadd(cscale(ih2, lx), cmul(o.c.kap, xp));
+}
+
+// (A x)_p for x at the slot's base pointer
+__device__ __forceinline__ double2 apply_op3(const Grid& g, const NodeOp3& o, const double2* __restrict__ x, size_t p,
+                                             int iz, int iy, int ix, double ih2) {
+  if (!g.rho) return apply_node3(x, p, iz, iy, ix, g, ih2, o.c);
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  return apply_op3_at(g, o, iz, iy, ix, ih2, x[p], [&](int dz, int dy, int dx) {
+    return x[(size_t)((long long)p + (long long)dz * (long long)sz + (long long)dy * (long long)sy + dx)];
+  });
 }
 
 // The node of a thread in the row-tiled 3D grid: false past the grid.

@@ -5,7 +5,8 @@ for the slowness m / sqrt(rho), the solve in 1D and 2D with BiCGSTAB and
 GMRES against the oracle's LU and its Krylov iteration counts, a batch of
 shots and frequencies, the allocation-free solve, the adjoint-state gradient,
 the constant-density identity B_rho=c(m) = c B(m / sqrt(c)) on the full
-401 x 801 grid, and the return to constant density.
+401 x 801 grid, the return to constant density, and on 3D boxes the
+operators, a sweep, the restriction, the V-cycle, a solve and the gradient.
 
 Tolerances as for constant density: one stencil evaluation 1e-13, a V-cycle
 1e-11 (relative 2-norm); wavefields 1e-6 against LU at tol = 1e-8; iteration
@@ -320,6 +321,110 @@ def test_density_cleared_and_refused(hz):
         c.set_density(torch.from_numpy(rho[:, :-1].copy()))
     c3 = hz.Context(0)
     c3.set_model(torch.full((9, 9, 9), 1 / 2000.0, dtype=torch.float64), 20.0)
+    bad = np.ones((9, 9, 9))
+    bad[4, 4, 4] = -2.0
     with pytest.raises(hz.HzError) as ei:
-        c3.set_density(torch.ones(9, 9, 9, dtype=torch.float64))
+        c3.set_density(torch.from_numpy(bad))
     assert ei.value.code == hz.HZ_ERR_ARG
+
+
+# ---------------------------------------------------------------- 3D grids (Eq. (1) with d = 3)
+
+SHAPES3 = [((9, 11, 17), 40.0), ((10, 12, 16), 40.0)]
+
+
+@pytest.mark.parametrize("shape,h", SHAPES3)
+def test_3d_density_operator_and_sweep(hz, shape, h):
+    import torch
+    m, rho = random_model(shape, 21)
+    c = ctx(hz, m, h, rho)
+    f, alpha, beta, w = 5.0, 0.03, (1.0, 0.5), 0.7
+    om = 2 * np.pi * f
+    L = c.plan(f)[0]
+    ms, rs = injected(m, L), injected(rho, L)
+    for l in range(L):
+        shp = ms[l].shape
+        x = workloads.random_vectors(2, int(np.prod(shp)), seed=30 + l)
+        xt = torch.from_numpy(x.reshape((2,) + shp)).cuda()
+        hl = h * 2 ** l
+        yB = to_np(c.apply("B", l, f, xt, alpha=alpha, beta=beta)).reshape(2, -1)
+        yM = to_np(c.apply("M", l, f, xt, alpha=alpha, beta=beta)).reshape(2, -1)
+        B = op.operator_B(ms[l], hl, om, alpha, rs[l])
+        M = op.operator_M(ms[l], hl, om, *beta, rho=rs[l])
+        for k in range(2):
+            assert rel(yB[k], B @ x[k]) < TOL_STEP
+            assert rel(yM[k], M @ x[k]) < TOL_STEP
+    n = m.size
+    b = workloads.random_vectors(2, n, seed=3)
+    u = workloads.random_vectors(2, n, seed=4)
+    M = op.operator_M(m, h, om, *beta, rho=rho)
+    D = M.diagonal()
+    bt = torch.from_numpy(b.reshape((2,) + shape)).cuda()
+    ut = torch.from_numpy(u.reshape((2,) + shape)).cuda()
+    sw = to_np(c.smooth(0, f, bt, ut, w=w, beta=beta)).reshape(2, -1)
+    cs = mg.coarse_shape(shape)
+    bc = to_np(c.restrict(0, f, bt, ut, beta=beta)).reshape(2, -1)
+    R = mg.restriction(cs, shape)
+    for k in range(2):
+        assert rel(sw[k], u[k] + w * (b[k] - M @ u[k]) / D) < TOL_STEP
+        assert rel(bc[k], R @ (b[k] - M @ u[k])) < TOL_STEP
+
+
+@pytest.mark.parametrize("levels,nu", [(2, (2, 2)), (3, (2, 2)), (3, (1, 1))])
+def test_3d_density_vcycle(hz, levels, nu):
+    import torch
+    shape, h = (17, 21, 33), 25.0
+    m, rho = random_model(shape, 22)
+    c = ctx(hz, m, h, rho)
+    f, beta = 6.0, (1.0, 0.5)
+    wj = [0.8, 0.6][:levels - 1]
+    vc = mg.VCycle(m, h, 2 * np.pi * f, beta[0], beta[1], levels, nu[0], nu[1], wj, rho=rho)
+    b = workloads.random_vectors(2, m.size, seed=11)
+    out = to_np(c.precond(f, torch.from_numpy(b.reshape((2,) + shape)).cuda(), levels=levels, nu=nu, beta=beta,
+                          jacobi_w_level=wj, coarse="exact")).reshape(2, -1)
+    for k in range(2):
+        assert rel(out[k], vc(b[k])) < TOL_CYCLE
+
+
+def test_3d_density_solve_and_gradient(hz):
+    """A layered 17 x 21 x 25 box with a Gardner density: 2 shots x 2
+    frequencies against LU and the oracle's BiCGSTAB iteration count, then
+    the adjoint-state gradient against the oracle's."""
+    import torch
+    w = workloads.model_3d_layered(17, 21, 25, h=25.0, nshots=2, freqs=(2.0, 3.5))
+    rho = workloads.gardner_density(w.m)
+    c = ctx(hz, w.m, w.h, rho)
+    iz, iy, ix = ([s[a] for s in w.src] for a in range(3))
+    b1 = c.point_rhs_3d(iz, iy, ix)
+    b = torch.stack([b1] * len(w.freqs)).contiguous()
+    u, info = c.solve(w.freqs, w.alpha, b, tol=1e-8)
+    u = to_np(u)
+    ns = len(w.src)
+    nodes = [(iz[s] * w.shape[1] + iy[s]) * w.shape[2] + ix[s] for s in range(ns)]
+    for fi, f in enumerate(w.freqs):
+        om = 2 * np.pi * f
+        B = op.operator_B(w.m, w.h, om, w.alpha, rho)
+        lu = direct.factor_superlu(B)
+        L, wj = c.plan(f)
+        vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto", rho=rho)
+        for s in range(ns):
+            st, it, rr = info[fi * ns + s]
+            assert st == hz.HZ_RHS_CONVERGED and rr <= 1e-8
+            bn = op.point_source(w.shape, w.h, [nodes[s]])
+            assert rel(u[fi, s].ravel(), lu.solve(bn)) < 1e-6
+            if s == 0:
+                _, it_o, _, _ = krylov.bicgstab(B, bn, vc, tol=1e-8, maxit=2000)
+                assert iters_close(it, it_o), (f, it, it_o)
+    start = workloads.model_3d_layered(17, 21, 25, h=25.0, nshots=2, freqs=(2.0, 3.5), seed=3)
+    rec = [(0, y, x) for y in range(0, 21, 4) for x in range(0, 25, 4)]
+    rec_nodes = [(a * w.shape[1] + b_) * w.shape[2] + c_ for a, b_, c_ in rec]
+    sv = og.Survey(w.shape, w.h, w.freqs, w.alpha, nodes, rec_nodes, rho=rho)
+    d_obs = og.data(w.m, sv)
+    lam = 1e-3
+    J_o, g_o = og.gradient(start.m, sv, d_obs, lam)
+    c.set_model(torch.from_numpy(start.m), w.h)
+    c.set_density(torch.from_numpy(rho))
+    J, g, ginfo = c.gradient_3d(sv.freqs, sv.alpha, w.src, rec, torch.from_numpy(d_obs), lam, tol=1e-11)
+    assert all(i[0] == hz.HZ_RHS_CONVERGED for i in ginfo)
+    assert abs(J - J_o) <= 1e-8 * J_o
+    assert np.linalg.norm(g.cpu().numpy() - g_o) <= 1e-6 * np.linalg.norm(g_o)

@@ -286,3 +286,86 @@ def test_gardner_density_range():
     w = workloads.model_2d_layered(nz=41, nx=81, h=10.0, nshots=2, freqs=(3.0,))
     rho = workloads.gardner_density(w.m)
     assert rho.shape == w.m.shape and rho.min() == 1.0 and rho.max() < 1.4
+
+
+def test_3d_variable_density_manufactured_second_order():
+    """Eq. (1) with d = 3: u* = cos(pi x/Lx) cos(pi y/Ly) cos(pi z/Lz)
+    exp(-j k0 x) with rho = 1 + 0.3 sin(2 pi x / Lx) cos(pi y / Ly) cos(pi z / Lz),
+    f = -div(rho grad u*) - k^2 (1 - j alpha) u* and on every face the flux
+    data rho du*/dn + j k sqrt(rho) u*."""
+    lengths, c, f, al = (600.0, 800.0, 1200.0), 2000.0, 1.5, 0.05
+    Lz, Ly, Lx = lengths
+    om = 2 * np.pi * f
+    k = om / c
+    k0 = 0.7 * k
+    errs = []
+    for nx in (13, 25, 49):
+        shape = ((nx - 1) // 2 + 1, (nx - 1) * 2 // 3 + 1, nx)
+        h = Lx / (nx - 1)
+        z, y, x = (np.arange(n) * h for n in shape)
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        ax, ay, az = np.pi / Lx, np.pi / Ly, np.pi / Lz
+        cx, sx = np.cos(ax * X), np.sin(ax * X)
+        cy, sy = np.cos(ay * Y), np.sin(ay * Y)
+        cz, sz = np.cos(az * Z), np.sin(az * Z)
+        ph = np.exp(-1j * k0 * X)
+        u = cx * cy * cz * ph
+        ux = (-ax * sx - 1j * k0 * cx) * cy * cz * ph
+        uy = -ay * cx * sy * cz * ph
+        uz = -az * cx * cy * sz * ph
+        uxx = (-ax ** 2 * cx + 2j * k0 * ax * sx - k0 ** 2 * cx) * cy * cz * ph
+        uyy = -ay ** 2 * u
+        uzz = -az ** 2 * u
+        a2 = 2 * np.pi / Lx
+        r = 1 + 0.3 * np.sin(a2 * X) * cy * cz
+        rx = 0.3 * a2 * np.cos(a2 * X) * cy * cz
+        ry = -0.3 * ay * np.sin(a2 * X) * sy * cz
+        rz = -0.3 * az * np.sin(a2 * X) * cy * sz
+        fs = -(rx * ux + ry * uy + rz * uz + r * (uxx + uyy + uzz)) - k ** 2 * (1 - 1j * al) * u
+        wz, wy, wx = (op.end_weights(n) for n in shape)
+        b = wz[:, None, None] * wy[None, :, None] * wx[None, None, :] * fs
+        fx = wz[:, None] * wy[None, :]
+        fy = wz[:, None] * wx[None, :]
+        fz = wy[:, None] * wx[None, :]
+        sr = np.sqrt(r)
+        b[:, :, 0] += fx * (-r[:, :, 0] * ux[:, :, 0] + 1j * k * sr[:, :, 0] * u[:, :, 0]) / h
+        b[:, :, -1] += fx * (r[:, :, -1] * ux[:, :, -1] + 1j * k * sr[:, :, -1] * u[:, :, -1]) / h
+        b[:, 0, :] += fy * (-r[:, 0, :] * uy[:, 0, :] + 1j * k * sr[:, 0, :] * u[:, 0, :]) / h
+        b[:, -1, :] += fy * (r[:, -1, :] * uy[:, -1, :] + 1j * k * sr[:, -1, :] * u[:, -1, :]) / h
+        b[0, :, :] += fz * (-r[0, :, :] * uz[0, :, :] + 1j * k * sr[0, :, :] * u[0, :, :]) / h
+        b[-1, :, :] += fz * (r[-1, :, :] * uz[-1, :, :] + 1j * k * sr[-1, :, :] * u[-1, :, :]) / h
+        B = op.operator_B(np.full(shape, 1 / c), h, om, al, r)
+        sol = direct.solve_superlu(B, b.ravel())
+        errs.append(np.linalg.norm(sol - u.ravel()) / np.linalg.norm(u))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.4 < r1 < 4.6 and 3.6 < r2 < 4.4, errs
+
+
+def test_3d_density_vcycle_equals_explicit_matrix():
+    shape = (9, 9, 17)
+    m, rho = _rand(shape, 12)
+    vc = mg.VCycle(m, 40.0, 2 * np.pi * 4.0, 1.0, 0.5, 2, 2, 2, [0.7], rho=rho)
+    C = mg.vcycle_matrix(vc)
+    b = workloads.random_vectors(1, m.size, 13)[0]
+    assert np.linalg.norm(vc(b) - C @ b) <= 1e-13 * np.linalg.norm(C @ b)
+    D = np.diag(op.operator_M(mg.inject(m), 80.0, 2 * np.pi * 4.0, 1.0, 0.5, mg.inject(rho)).toarray())
+    assert np.array_equal(vc.D[1], D)
+
+
+def test_3d_density_gradient_matches_central_differences():
+    nz, ny, nx, h = 7, 9, 11, 50.0
+    true = workloads.model_3d_layered(nz=nz, ny=ny, nx=nx, h=h, nshots=2, freqs=(2.0,))
+    start = workloads.model_3d_layered(nz=nz, ny=ny, nx=nx, h=h, nshots=2, freqs=(2.0,), seed=4)
+    rho = workloads.gardner_density(true.m)
+    src = [(s[0] * ny + s[1]) * nx + s[2] for s in true.src]
+    rec = list(range(0, ny * nx, 5)) + [nz * ny * nx - 1]
+    sv = og.Survey(true.shape, h, true.freqs, 0.05, src, rec, rho=rho)
+    d_obs = og.data(true.m, sv)
+    m = start.m
+    J, g = og.gradient(m, sv, d_obs, 0.0)
+    for (iz, iy, ix) in ((0, 4, 5), (3, 4, 5), (nz - 1, 0, nx - 1)):
+        v = np.zeros_like(m)
+        v[iz, iy, ix] = m[iz, iy, ix]
+        eps = 1e-5
+        fd = (og.misfit(m + eps * v, sv, d_obs, 0.0) - og.misfit(m - eps * v, sv, d_obs, 0.0)) / (2 * eps)
+        assert abs(fd - g[iz, iy, ix] * v[iz, iy, ix]) <= 1e-5 * abs(fd) + 1e-12 * J
