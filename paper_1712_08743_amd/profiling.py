@@ -29,12 +29,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # timing class -> kernel symbol(s) (finest level); a class with two symbols
 # launches each of them every second iteration
+# (the constant-density forms: the last template argument is the density flag)
 CLASS_SYMBOL = {
-    "presmooth": "hz::k_pre2r_s<4, true>",
-    "presmooth_s": "hz::k_pre2r_s<5, true>",
-    "prolong": "hz::k_post2_s<true>",
-    "apply": "hz::k_bicg_apply_t<0>",
-    "apply_s": "hz::k_bicg_apply_t<1>",
+    "presmooth": "hz::k_pre2r_s<4, true, false>",
+    "presmooth_s": "hz::k_pre2r_s<5, true, false>",
+    "prolong": "hz::k_post2_s<true, false>",
+    "apply": "hz::k_bicg_apply_t<0, false>",
+    "apply_s": "hz::k_bicg_apply_t<1, false>",
     "update": ("hz::k_bicg_xr<0>", "hz::k_bicg_xr<1>"),
     "coarse": "hz::k_coarse",
 }
