@@ -19,6 +19,8 @@ Prints one JSON line (see the field list at the end of main()).
                                   # Gauss-Newton schedules (a report, not a throughput line)
   python bench.py --3d            # batched solves on a 3D box (129^3, 16 right-hand sides) and its gradient; a report line
   python bench.py --density       # the same batch with a variable density (Eq. (1)); a report line
+  python bench.py --gmres         # the same batch with GMRES(30), its Gram-Schmidt kernels' roofline
+                                  # and BiCGSTAB beside it; a report line
   python bench.py --fwi           # gradient and Gauss-Newton step on the full inversion survey
                                   # (301 x 601, 32 shots x 6 frequencies; a report line)
   python bench.py --serving [--requests R] [--slots S]
@@ -713,6 +715,100 @@ def bench_density(args):
     print(json.dumps(out), flush=True)
 
 
+def gmres_step_bytes(iters, m, n, z=16):
+    """Algorithmic bytes of GMRES(m)'s Gram-Schmidt step kernels for one
+    right-hand side that took `iters` Arnoldi columns: step j of a cycle
+    reads the j finished basis vectors, u_j and the operator's product twice
+    (the dot pass and the update pass) and writes v_j and u_{j+1}; the step
+    that decides a cycle's last column k < m only makes the dot pass over
+    k + 2 vectors, and a cycle of m columns ends with a dot pass over its
+    m + 1 vectors. Cycles are taken as m columns each but the last (a restart
+    on a residual estimate that the true residual does not confirm would add
+    one more short cycle)."""
+    full, rest = divmod(int(iters), m)
+    cycles = [m] * full + ([rest] if rest else [])
+    vecs = 0
+    for k in cycles:
+        vecs += sum(2 * j + 6 for j in range(k)) + (k + 2 if k < m else m + 1)
+    return vecs * n * z
+
+
+def bench_gmres(args):
+    """GMRES(30), the paper's Krylov method, on the benchmark batch: the
+    layered 401 x 801 model, 64 surface shots x 3/5/8/12 Hz = 256 right-hand
+    sides, tolerance 1e-8, V(2,2) shifted-Laplace (1, 0.5) preconditioner.
+    A step = set the model + solve, inputs resident in HBM. The Gram-Schmidt
+    step kernels (the `update` timing class: the dot pass, the per-slot
+    scalars and the update pass of each Arnoldi step) are timed with HIP
+    events and priced by their algorithmic bytes; BiCGSTAB's rate on the same
+    batch is measured beside it. One JSON line, a report beside the headline
+    line."""
+    import torch
+    import numpy as np
+    import paper_1712_08743_amd as hz
+    import workloads
+    w = workloads.model_2d_layered()
+    nshot, nfreq = len(w.src), len(w.freqs)
+    nrhs = nshot * nfreq
+    gm = 30
+    ctx = hz.Context(0)
+    m = torch.from_numpy(w.m).cuda()
+    ctx.set_model(m, w.h)
+    b1 = ctx.point_rhs([0] * nshot, w.src)
+    b = torch.stack([b1] * nfreq).contiguous()
+    u = torch.empty_like(b)
+    tol = 1e-8
+    n0 = int(np.prod(w.shape))
+    out = {"metric": "Helmholtz solves/s (2D 401x801, 256 RHS, GMRES(30))", "unit": "solves/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "2d-layered-401x801, 64 surface shots x {3,5,8,12} Hz = 256 RHS, GMRES(30) "
+                                  "tol 1e-8, V(2,2) shifted-Laplace (1,0.5), LFA-planned weights"}}
+    for kr in ("gmres", "bicgstab"):
+        def step():
+            ctx.set_model(m, w.h)
+            _, info = ctx.solve(w.freqs, w.alpha, b, out=u, tol=tol, krylov=kr, gmres_m=gm)
+            return info
+        print(f"# {kr}: warm-up step", file=sys.stderr, flush=True)
+        step()
+        torch.cuda.synchronize()
+        steps = max(1, min(args.steps, 3))
+        if kr == "gmres":
+            ctx.timing_start(["update", "apply"])
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(step())
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        print(f"# {kr}: {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+        info = infos[-1]
+        iters = [i[1] for i in info]
+        res = {"value": nrhs / sec, "ms_per_step": sec * 1e3, "steps": steps, "warmup": 1,
+               "converged": sum(1 for i in info if i[0] == hz.HZ_RHS_CONVERGED and i[2] <= tol),
+               "iterations_mean_per_freq": {str(f): float(np.mean(iters[k * nshot:(k + 1) * nshot]))
+                                            for k, f in enumerate(w.freqs)}}
+        if kr == "gmres":
+            n_up, ms_up = ctx.timing_read("update")
+            n_ap, ms_ap = ctx.timing_read("apply")
+            ctx.timing_start([])
+            gs_bytes = sum(gmres_step_bytes(i[1], gm, n0) for inf in infos for i in inf)
+            achieved = gs_bytes / (ms_up * 1e-3) / 1e9
+            res["gram_schmidt"] = {"launch_groups": n_up, "ms_per_step": ms_up / steps,
+                                   "share_of_step": ms_up / steps / (sec * 1e3),
+                                   "algorithmic_GB_per_step": gs_bytes / steps / 1e9,
+                                   "operator_apply_ms_per_step": ms_ap / steps}
+            res["roofline"] = {"bound": "hbm", "kernel": "Gram-Schmidt step (k_gm_dots2 + k_gm_fin2 + "
+                                                         "k_gm_update2)",
+                               "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+            out.update(res)
+        else:
+            out["bicgstab"] = res
+    out["ratio_to_bicgstab"] = out["value"] / out["bicgstab"]["value"]
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -729,6 +825,7 @@ def main():
     ap.add_argument("--fwi", action="store_true")
     ap.add_argument("--3d", dest="three_d", action="store_true")
     ap.add_argument("--density", action="store_true")
+    ap.add_argument("--gmres", action="store_true")
     ap.add_argument("--compare-maxit", type=int, default=20000)
     ap.add_argument("--maxit", type=int, default=10000,
                     help="iteration cap (below convergence only for short hardware-counter runs)")
@@ -754,6 +851,9 @@ def main():
         return
     if args.density:
         bench_density(args)
+        return
+    if args.gmres:
+        bench_gmres(args)
         return
 
     import numpy as np

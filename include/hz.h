@@ -434,7 +434,8 @@ int  hz_server_stats(hz_server *s, int *queued, int *running, int *peak_running,
                                   (BiCGSTAB), B z (GMRES) */
 #define HZ_KERNEL_RESTRICT 2   /* residual and restriction (when not fused into the pre-smoothing) */
 #define HZ_KERNEL_PROLONG  3   /* prolongation and correction with the post-sweeps (2D: both) */
-#define HZ_KERNEL_UPDATE   4   /* Krylov iterate and residual update */
+#define HZ_KERNEL_UPDATE   4   /* Krylov iterate and residual update (GMRES: the Arnoldi
+                                  step's Gram-Schmidt passes and scalars) */
 #define HZ_KERNEL_COARSE   5   /* dense coarse solve */
 #define HZ_KERNEL_PRESMOOTH 6  /* right-hand side (BiCGSTAB: p = r + beta (p - omega v)) and two
                                   Jacobi sweeps from zero; on 2D grids also the residual and

@@ -1188,7 +1188,7 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
   const int m = o->gmres_m;
   const size_t n0 = c->lv[0].n();
   const size_t vstride = (size_t)nslots * n0;
-  const int tiles = vec_tiles(n0);
+  const int tiles = std::max(vec_tiles(n0), gm_dot_tiles(n0));
   const size_t vbytes = (size_t)(m + 1) * vstride * sizeof(double2);
   if (c->budget && vbytes > c->budget)
     return fail(c, HZ_ERR_NOMEM, "GMRES basis of %zu bytes exceeds the budget", vbytes);
@@ -1196,12 +1196,14 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
   const size_t m1 = (size_t)m + 1;
   const size_t nH = (size_t)nslots * m1 * m, ng = (size_t)nslots * m1, nsn = (size_t)nslots * m;
   const size_t nhc = (size_t)nslots * 2 * m1;
-  HZ_ALLOC(c, c->gm_small, (nH + ng + nsn + nsn + nhc) * sizeof(double2) + nsn * sizeof(double));
-  HZ_ALLOC(c, c->gm_part, (size_t)nslots * tiles * 2 * m1 * sizeof(double));
+  const int width = 4 * (m + 1) + 4;
+  HZ_ALLOC(c, c->gm_small, (2 * nH + ng + nsn + nsn + nhc) * sizeof(double2) + nsn * sizeof(double));
+  HZ_ALLOC(c, c->gm_part, (size_t)nslots * tiles * width * sizeof(double));
   Gmres gm;
   double2* base = c->gm_small.as<double2>();
   gm.H = base;
-  gm.g = gm.H + nH;
+  gm.Hu = gm.H + nH;
+  gm.g = gm.Hu + nH;
   gm.sn = gm.g + ng;
   gm.y = gm.sn + nsn;
   gm.hc = gm.y + nsn;
@@ -1209,6 +1211,7 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
   gm.partials = c->gm_part.as<double>();
   gm.m = m;
   gm.max_tiles = tiles;
+  gm.width = width;
 
   const Batch bt = batch_of(c);
   const Reduce rd = reducer(c);
@@ -1251,21 +1254,23 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
   const long long guard = (long long)o->maxit + 2;
   long long cycles = 0;
   while (cap > 0 && cycles++ <= guard) {
-    for (int j = 0; j < m && cap > 0; ++j) {
-      const double2* vj = V + (size_t)j * vstride;
+    // step j applies the operator to u_j (V_j, not yet normalised) into
+    // V_{j+1}; the step's kernels then finish v_j in place and overwrite
+    // V_{j+1} with u_{j+1}. Column j - 1 is decided at step j, column m - 1 by
+    // the finishing pass.
+    int j = 0;
+    for (; j < m && cap > 0; ++j) {
+      const double2* uj = V + (size_t)j * vstride;
       double2* w = V + (size_t)(j + 1) * vstride;
-      const double2* zin = vj;
+      const double2* zin = uj;
       if (!identity) {
-        HZ_HIP(c, precond_apply(c, cy, cap, vj, z));
+        HZ_HIP(c, precond_apply(c, cy, cap, uj, z));
         zin = z;
       }
       HZ_HIP(c, timed(c, HZ_KERNEL_APPLY, [&] { return launch_apply(c->dim, g0, 0, 0, bt, cap, zin, w, n0, st); }));
-      HZ_HIP(c, launch_gm_dots(n0, bt, cap, gm, j, 0, V, vstride, w, n0, st));
-      HZ_HIP(c, launch_gm_orth(n0, bt, cap, rd, gm, j, V, vstride, w, n0, st));
-      HZ_HIP(c, launch_gm_dots(n0, bt, cap, gm, j, 1, V, vstride, w, n0, st));
-      HZ_HIP(c, launch_gm_orth_fin(bt, cap, gm, j, o->tol, o->maxit, st));
-      HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE,
-                      [&] { return launch_gm_orth_scale(n0, bt, cap, gm, j, V, vstride, w, n0, st); }));
+      HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
+               return launch_gm_step(n0, bt, cap, gm, j, 0, o->tol, o->maxit, V, vstride, w, n0, st);
+             }));
       if ((rc = close_unit(0)) != HZ_OK) return rc;
       while ((int)pending.size() > (cy.plain ? 0 : kLag)) {
         const int k = pending.front().second;
@@ -1273,6 +1278,12 @@ int run_gmres(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots, co
         HZ_HIP(c, hipEventSynchronize(c->ev[k]));
         cap = std::min(cap, c->ring_host[k].nactive);
       }
+    }
+    if (j == m && cap > 0) {
+      HZ_HIP(c, timed(c, HZ_KERNEL_UPDATE, [&] {
+               return launch_gm_step(n0, bt, cap, gm, m, 1, o->tol, o->maxit, V, vstride, nullptr, n0, st);
+             }));
+      if ((rc = close_unit(0)) != HZ_OK) return rc;
     }
     if ((rc = drain(&sm)) != HZ_OK) return rc;
     // cycle end for every slot waiting in phase 1

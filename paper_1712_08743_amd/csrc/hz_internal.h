@@ -88,15 +88,17 @@ constexpr int kFineVectors = 13;
 // H[slot][j*(m+1) + i], right-hand side g, rotations (cs, sn), solution y and the
 // two Gram-Schmidt coefficient vectors of the current column.
 struct Gmres {
-  double2* H;
+  double2* H;        // Hessenberg matrix after the Givens rotations, [slots][m][m+1] (column-major)
+  double2* Hu;       // the Arnoldi coefficients themselves, the same layout
   double2* g;
   double* cs;
   double2* sn;
   double2* y;
-  double2* hc;       // [slots][2][m+1]
-  double* partials;  // [slots][max_tiles][2 (m+1)]
+  double2* hc;       // [slots][2][m+1]: a step's coefficients s and c (k_gm_fin2)
+  double* partials;  // [slots][max_tiles][width]
   int m;
   int max_tiles;
+  int width;         // doubles per tile of the partials, 4 (m + 1) + 4
 };
 
 // The batch every kernel works on: the compacted list of active slots.
@@ -290,20 +292,12 @@ hipError_t launch_gm_residual(int dim, const Grid& g, const Batch& bt, int cap, 
                               double2* x, double2* v0, size_t stride, hipStream_t st);
 hipError_t launch_gm_scale(size_t n, const Batch& bt, int cap, double2* v, size_t stride,
                            hipStream_t st);
-hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, int pass,
-                          const double2* V, size_t vstride, const double2* w, size_t stride,
-                          hipStream_t st);
-// Gram-Schmidt against V_0..V_j (k_gm_* in hz_krylov.hip): launch_gm_dots
-// (pass 0), launch_gm_orth (first update and the reorthogonalisation test),
-// launch_gm_dots (pass 1, only the slots that reorthogonalise),
-// launch_gm_orth_fin (H column j, rotations, cycle-end test), then
-// launch_gm_orth_scale (second update where made, and the normalisation)
-hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm, int j,
-                          const double2* V, size_t vstride, double2* w, size_t stride, hipStream_t st);
-hipError_t launch_gm_orth_fin(const Batch& bt, int cap, const Gmres& gm, int j, double tol, int maxit,
-                              hipStream_t st);
-hipError_t launch_gm_orth_scale(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, const double2* V,
-                                size_t vstride, double2* w, size_t stride, hipStream_t st);
+// One Arnoldi step j of GMRES (k_gm_dots2, k_gm_fin2, k_gm_update2 in
+// hz_krylov.hip) for u_j = V_j and z = B M^-1 u_j; finish (z null): the pass
+// that completes the cycle's last column only.
+int gm_dot_tiles(size_t n);  // tiles of GMRES's dot pass over n nodes (partials per slot)
+hipError_t launch_gm_step(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, int finish, double tol,
+                          int maxit, double2* V, size_t vstride, const double2* z, size_t stride, hipStream_t st);
 hipError_t launch_gm_solve(const Batch& bt, int cap, const Gmres& gm, hipStream_t st);
 hipError_t launch_gm_combine(size_t n, const Batch& bt, int cap, const Gmres& gm,
                              const double2* V, size_t vstride, double2* t, size_t stride,

@@ -717,15 +717,18 @@ __global__ void __launch_bounds__(kBlock) k_true_residual_fin(int tiles, Batch b
 // Right-preconditioned restarted GMRES, one Arnoldi process per slot, all
 // slots of a cycle in lockstep. The basis vector i of slot s lives at
 // V + i * vstride + s * stride. Orthogonalisation is classical Gram-Schmidt
-// with the reorthogonalisation test of Daniel, Gragg, Kaufman and Stewart
-// (1976): w' = w - V (V^H w); a second pass w'' = w' - V (V^H w') is made
-// only for the slots where ||w'|| < ||w|| / sqrt(2) (much of w lay in the
-// basis, so w' carries the rounding of that cancellation). The norm of the
-// result is ||w'||^2 - sum |h'_i|^2 (h' = V^H w', rounding-sized after one
-// pass), and the last update is fused with the normalisation. Per slot the
-// scalars hc[0][m].x = ||w||^2 and hc[1][m] = (||w'||^2, reorthogonalise?)
-// use the entries the coefficients of the first m - 1 steps leave free.
-// Every per-slot sum is a fixed-order two-kernel reduction.
+// applied twice with the second pass of each vector delayed to the next
+// step (the DCGS2 scheme of Swirydowicz, Langou, Ananthan, Yang and Thomas,
+// low-synchronisation Gram-Schmidt for GMRES): step j holds u_j, the first
+// pass's result for the last product, and applies the operator to u_j
+// itself. One pass over the basis gives s = V^H u_j, ||u_j||^2, p = V^H z
+// and <u_j, z> for z = B M^-1 u_j; from these scalars alone come u_j's second
+// pass (v_j = (u_j - V s) / r, r^2 = ||u_j||^2 - ||s||^2, completing column
+// j - 1 of the Hessenberg matrix: its Givens rotation and the convergence
+// test are made then) and the first pass of the next product (B M^-1 v_j =
+// (z - V H s) / r by the Arnoldi relation of the finished columns). A second
+// pass writes v_j and u_{j+1}. Every per-slot sum is a fixed-order
+// two-kernel reduction.
 
 // r = b - B x (x = 0 on the first cycle, which also zeroes x) into V_0;
 // partial ||r||^2.
@@ -834,143 +837,105 @@ __global__ void __launch_bounds__(kBlock) k_gm_scale(Batch bt, int tiles, size_t
   }
 }
 
-// Partials of h_i = <V_i, w>, i = 0..j, in chunks of 8 basis vectors; pass 0
-// also ||w||^2 (after the dots, entry 2 (j + 1)). Pass 1 runs only for the
-// slots that reorthogonalise.
-__global__ void __launch_bounds__(kBlock) k_gm_dots(Batch bt, int tiles, size_t n, Gmres gm, int j, int pass,
-                                                    const double2* __restrict__ V, size_t vstride,
-                                                    const double2* __restrict__ w, size_t stride) {
+// Sum K doubles over the 64 lanes of a wave in a fixed order; valid in every lane.
+template <int K>
+__device__ __forceinline__ void wave_sum(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  }
+}
+
+// The step's one pass over the basis (partials per tile of kGmDotNodes
+// nodes, width gm.width): s_i = <V_i, u> at 2i, p_i = <V_i, z> at 2 (j + i)
+// (i < j), ||u||^2 at 4j and <u, z> at 4j + 1 for u = V_j (the first pass's
+// result) and z = B M^-1 u; z null (the finishing pass of a cycle): s and
+// ||u||^2 only. The basis is taken kGmChunk vectors at a time; the thread's
+// nodes of u and z stay in registers. Each wave reduces its own sums and
+// keeps them in LDS (4j + 3 doubles per wave), so the waves of a block meet
+// only once, at the end, where the tile's partials are the sums over the
+// waves in wave order.
+constexpr int kGmE = 4;      // nodes per thread of the dot pass
+constexpr int kGmChunk = 1;  // basis vectors per pass over a tile
+constexpr int kGmDotNodes = kGmE * kBlock;
+constexpr int kWaves = kBlock / 64;
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_gm_dots2(Batch bt, int tiles, size_t n, Gmres gm, int j,
+                                                     const double2* __restrict__ V, size_t vstride,
+                                                     const double2* __restrict__ z, size_t stride) {
+  extern __shared__ double wsum[];  // [kWaves][4j + 3]
   int slot, tile;
   if (!decode_vec(bt, tiles, slot, tile)) return;
-  if (pass == 1 && gm.hc[((size_t)slot * 2 + 1) * (gm.m + 1) + gm.m].y == 0.0) return;
+  const int nsum = 4 * j + 3;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double* mine = wsum + wid * nsum;
   const size_t base = (size_t)slot * stride;
-  const int nv = j + 1;
-  const int width = 2 * (gm.m + 1);
-  double* part = gm.partials + ((size_t)slot * gm.max_tiles + tile) * width;
-  for (int c0 = 0; c0 < nv; c0 += 8) {
-    double acc[18];
+  const double2* u = V + (size_t)j * vstride + base;
+  const double2* zs = z ? z + base : nullptr;
+  const size_t i0 = (size_t)tile * kGmDotNodes + threadIdx.x;
+  double2 ur[kGmE], zr[kGmE];  // the thread's nodes of u and z, held across the chunks
 #pragma unroll
-    for (int q = 0; q < 18; ++q) acc[q] = 0.0;
+  for (int e = 0; e < kGmE; ++e) {
+    const size_t i = i0 + (size_t)e * kBlock;
+    ur[e] = i < n ? u[i] : c2(0.0, 0.0);
+    zr[e] = i < n && zs ? zs[i] : c2(0.0, 0.0);
+  }
+  for (int c0 = 0; c0 < j; c0 += kGmChunk) {
+    double acc[4 * kGmChunk];
 #pragma unroll
-    for (int e = 0; e < kVecPerThread; ++e) {
-      const size_t i = vec_index(tile, e);
+    for (int q = 0; q < 4 * kGmChunk; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int e = 0; e < kGmE; ++e) {
+      const size_t i = i0 + (size_t)e * kBlock;
       if (i < n) {
-        const double2 wi = w[base + i];
-        if (pass == 0 && c0 == 0) acc[16] += wi.x * wi.x + wi.y * wi.y;
+        const double2 ui = ur[e];
+        const double2 zi = zr[e];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (c0 + q < nv) {
-            const double2 d = cconjmul(V[(size_t)(c0 + q) * vstride + base + i], wi);
-            acc[2 * q] += d.x;
-            acc[2 * q + 1] += d.y;
+        for (int q = 0; q < kGmChunk; ++q) {
+          if (c0 + q < j) {
+            const double2 vq = V[(size_t)(c0 + q) * vstride + base + i];
+            const double2 ds = cconjmul(vq, ui), dp = cconjmul(vq, zi);
+            acc[4 * q] += ds.x;
+            acc[4 * q + 1] += ds.y;
+            acc[4 * q + 2] += dp.x;
+            acc[4 * q + 3] += dp.y;
           }
         }
       }
     }
-    block_sum<18>(acc);
-    if (threadIdx.x == 0) {
-      for (int q = 0; q < 8 && c0 + q < nv; ++q) {
-        part[2 * (c0 + q)] = acc[2 * q];
-        part[2 * (c0 + q) + 1] = acc[2 * q + 1];
+    wave_sum<4 * kGmChunk>(acc);
+    if (lane == 0) {
+      for (int q = 0; q < kGmChunk && c0 + q < j; ++q) {
+        mine[2 * (c0 + q)] = acc[4 * q];
+        mine[2 * (c0 + q) + 1] = acc[4 * q + 1];
+        mine[2 * (j + c0 + q)] = acc[4 * q + 2];
+        mine[2 * (j + c0 + q) + 1] = acc[4 * q + 3];
       }
-      if (pass == 0 && c0 == 0) part[2 * nv] = acc[16];
     }
   }
-}
-
-// Sums of the dots in tile order: hc[pass] and column j of H (pass 0 sets,
-// pass 1 adds; a slot that does not reorthogonalise gets hc[1] = 0); pass 0
-// also ||w||^2 into hc[0][m].x.
-__global__ void __launch_bounds__(kBlock) k_gm_dots_fin(int tiles, Batch bt, Gmres gm, int j, int pass) {
-  int slot;
-  if (!decode_slot_block(bt, slot)) return;
-  const int nv = j + 1;
-  const int width = 2 * (gm.m + 1);
-  const double* src = gm.partials + (size_t)slot * gm.max_tiles * width;
-  double2* hc = gm.hc + ((size_t)slot * 2 + pass) * (gm.m + 1);
-  double2* Hc = gm.H + (size_t)slot * (gm.m + 1) * gm.m + (size_t)j * (gm.m + 1);
-  if (pass == 1 && hc[gm.m].y == 0.0) {
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) hc[i] = c2(0.0, 0.0);
-    return;
-  }
-  const int nsum = pass == 0 ? 2 * nv + 1 : 2 * nv;
-  for (int v = threadIdx.x; v < nsum; v += blockDim.x) {
-    double sum = 0.0;
-    for (int tt = 0; tt < tiles; ++tt) sum += src[(size_t)tt * width + v];
-    if (v == 2 * nv) {  // ||w||^2
-      hc[gm.m].x = sum;
-      continue;
-    }
-    const int i = v >> 1;
-    if (v & 1) {
-      hc[i].y = sum;
-      Hc[i].y = pass ? Hc[i].y + sum : sum;
-    } else {
-      hc[i].x = sum;
-      Hc[i].x = pass ? Hc[i].x + sum : sum;
-    }
-  }
-}
-
-// The first update w' = w - sum_i hc[0]_i V_i (stored) and the partials of
-// ||w'||^2.
-__global__ void __launch_bounds__(kBlock) k_gm_orth(Batch bt, int tiles, size_t n, Reduce rd, Gmres gm, int j,
-                                                    const double2* __restrict__ V, size_t vstride,
-                                                    double2* __restrict__ w, size_t stride) {
-  int slot, tile;
-  if (!decode_vec(bt, tiles, slot, tile)) return;
-  const size_t base = (size_t)slot * stride;
-  const double2* hc = gm.hc + (size_t)slot * 2 * (gm.m + 1);
-  double acc[1] = {0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int e = 0; e < kVecPerThread; ++e) {
-    const size_t i = vec_index(tile, e);
-    if (i < n) {
-      double2 wi = w[base + i];
-      for (int q = 0; q <= j; ++q) wi = csub(wi, cmul(hc[q], V[(size_t)q * vstride + base + i]));
-      w[base + i] = wi;
-      acc[0] += wi.x * wi.x + wi.y * wi.y;
-    }
+  for (int e = 0; e < kGmE; ++e) {
+    const double2 ui = ur[e];
+    acc[0] += ui.x * ui.x + ui.y * ui.y;
+    const double2 d = cconjmul(ui, zr[e]);
+    acc[1] += d.x;
+    acc[2] += d.y;
   }
-  store_partial<1>(acc, rd, slot, tile);
-}
-
-// hc[1][m] = (||w'||^2, 1 where the slot reorthogonalises, else 0): where
-// ||w'||^2 < ||w||^2 / 2, or either is not finite.
-__global__ void __launch_bounds__(kBlock) k_gm_reorth_test(int tiles, Batch bt, Reduce rd, Gmres gm) {
-  int slot;
-  if (!decode_slot_block(bt, slot)) return;
-  double acc[1];
-  sum_partials<1>(acc, rd, slot, tiles);
-  if (threadIdx.x != 0) return;
-  const double2* h0 = gm.hc + (size_t)slot * 2 * (gm.m + 1);
-  double2* h1 = gm.hc + ((size_t)slot * 2 + 1) * (gm.m + 1);
-  const bool keep_one = acc[0] >= 0.5 * h0[gm.m].x;
-  h1[gm.m] = c2(acc[0], keep_one ? 0.0 : 1.0);
-}
-
-// The normalisation, fused with the second update where the slot
-// reorthogonalises: w = (w' - sum_i hc[1]_i V_i) / scal, else w' / scal;
-// scal = H[j+1, j] from k_gm_orth_fin (a zero norm leaves w unscaled).
-__global__ void __launch_bounds__(kBlock) k_gm_orth_scale(Batch bt, int tiles, size_t n, Gmres gm, int j,
-                                                          const double2* __restrict__ V, size_t vstride,
-                                                          double2* __restrict__ w, size_t stride) {
-  int slot, tile;
-  if (!decode_vec(bt, tiles, slot, tile)) return;
-  const size_t base = (size_t)slot * stride;
-  const double2* hc = gm.hc + ((size_t)slot * 2 + 1) * (gm.m + 1);
-  const bool second = hc[gm.m].y != 0.0;
-  const double d = bt.slots[slot].scal.x;
-  const double inv = d == 0.0 ? 1.0 : 1.0 / d;
+  wave_sum<3>(acc);
+  if (lane == 0) {
+    mine[4 * j] = acc[0];
+    mine[4 * j + 1] = acc[1];
+    mine[4 * j + 2] = acc[2];
+  }
+  __syncthreads();
+  double* part = gm.partials + ((size_t)slot * gm.max_tiles + tile) * gm.width;
+  for (int v = threadIdx.x; v < nsum; v += kBlock) {
+    double a = 0.0;
 #pragma unroll
-  for (int e = 0; e < kVecPerThread; ++e) {
-    const size_t i = vec_index(tile, e);
-    if (i < n) {
-      double2 wi = w[base + i];
-      if (second)
-        for (int q = 0; q <= j; ++q) wi = csub(wi, cmul(hc[q], V[(size_t)q * vstride + base + i]));
-      w[base + i] = cscale(inv, wi);
-    }
+    for (int w = 0; w < kWaves; ++w) a += wsum[w * nsum + v];
+    part[v] = a;
   }
 }
 
@@ -991,49 +956,184 @@ __device__ __forceinline__ void givens(double2 a, double2 b, double& c, double2&
   }
 }
 
-// After the second pass's dots: ||w''|| = sqrt(||w'||^2 - sum_i |hc[1]_i|^2)
-// (||w'|| where the slot does not reorthogonalise) becomes H[j+1, j], the
-// earlier rotations are applied to column j, the new rotation annihilates
-// H[j+1, j] and updates g, and the cycle-end test is made.
-__global__ void __launch_bounds__(kBlock) k_gm_orth_fin(Batch bt, Gmres gm, int j, double tol, int maxit) {
+// The step's scalars, per slot (one block): the partials summed in tile
+// order, then (thread 0) for j >= 1 u_j's second pass r = sqrt(||u_j||^2 -
+// ||s||^2) completing column j - 1 of the Arnoldi matrix Hu (Hu[i, j-1] += s_i,
+// Hu[j, j-1] = r), its rotated copy in H with the Givens rotations and g, the
+// iteration count and the convergence test (or, with finish, the cycle's
+// end); where the slot goes on, the first pass of column j from the scalars
+// (thread k its row): h_k = (p_k - (Hu s)_k) / r (k < j) and h_j = ((<u_j, z> -
+// s^H p) / r - (Hu s)_j) / r, and the update coefficients c = Hu s / r + h
+// (hc[1]) beside s (hc[0]) and scal = r for k_gm_update2. j = 0: V_0 is final,
+// h_0 = <V_0, z>. Shared memory: 4j + 3 doubles of sums, then column j - 1
+// (j + 1 complex) and two flags.
+__global__ void __launch_bounds__(kBlock) k_gm_fin2(int tiles, Batch bt, Gmres gm, int j, double tol, int maxit,
+                                                    int finish) {
+  extern __shared__ double sum[];
   int slot;
   if (!decode_slot_block(bt, slot)) return;
-  if (threadIdx.x != 0) return;
+  const double* src = gm.partials + (size_t)slot * gm.max_tiles * gm.width;
+  const int nsum = 4 * j + 3;
+  for (int v = threadIdx.x; v < nsum; v += blockDim.x) {
+    // tile order; eight loads in flight at a time
+    double a = 0.0;
+    int tt = 0;
+    for (; tt + 8 <= tiles; tt += 8) {
+      double x[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = src[(size_t)(tt + k) * gm.width + v];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a += x[k];
+    }
+    for (; tt < tiles; ++tt) a += src[(size_t)tt * gm.width + v];
+    sum[v] = a;
+  }
+  double2* colj = reinterpret_cast<double2*>(sum + ((nsum + 1) & ~1));  // column j - 1 of Hu
+  double* flag = reinterpret_cast<double*>(colj + j + 1);               // [0]: go on, [1]: r
+  __syncthreads();
   Slot& S = bt.slots[slot];
   const int m1 = gm.m + 1;
-  double2* Hc = gm.H + (size_t)slot * m1 * gm.m + (size_t)j * m1;
-  double* cs = gm.cs + (size_t)slot * gm.m;
-  double2* sn = gm.sn + (size_t)slot * gm.m;
-  double2* gg = gm.g + (size_t)slot * m1;
-  const double2* h1 = gm.hc + ((size_t)slot * 2 + 1) * m1;
-  double nrm2 = h1[gm.m].x;
-  for (int i = 0; i <= j; ++i) nrm2 -= h1[i].x * h1[i].x + h1[i].y * h1[i].y;
-  const double nrm = sqrt(fmax(nrm2, 0.0));
-  Hc[j + 1] = c2(nrm, 0.0);
-  for (int i = 0; i < j; ++i) {
-    const double2 a = Hc[i], bb = Hc[i + 1];
-    Hc[i] = cadd(cscale(cs[i], a), cmul(sn[i], bb));
-    Hc[i + 1] = csub(cscale(cs[i], bb), cmul(c2(sn[i].x, -sn[i].y), a));
+  double2* Hu = gm.Hu + (size_t)slot * m1 * gm.m;  // column i at Hu + i * m1
+  double2* H = gm.H + (size_t)slot * m1 * gm.m;
+  double2* sv = gm.hc + (size_t)slot * 2 * m1;
+  double2* cv = sv + m1;
+  const double2 q = c2(sum[4 * j + 1], sum[4 * j + 2]);
+  auto s_at = [&](int i) { return c2(sum[2 * i], sum[2 * i + 1]); };
+  auto p_at = [&](int i) { return c2(sum[2 * (j + i)], sum[2 * (j + i) + 1]); };
+  if (j == 0) {
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < m1; ++k) Hu[k] = c2(0.0, 0.0);
+    Hu[0] = q;
+    cv[0] = q;
+    S.scal = c2(1.0, 0.0);
+    return;
   }
-  double cj;
-  double2 sj;
-  givens(Hc[j], Hc[j + 1], cj, sj);
-  cs[j] = cj;
-  sn[j] = sj;
-  Hc[j] = cadd(cscale(cj, Hc[j]), cmul(sj, Hc[j + 1]));
-  Hc[j + 1] = c2(0.0, 0.0);
-  const double2 gj = gg[j];
-  gg[j + 1] = cmul(c2(-sj.x, sj.y), gj);  // -conj(s) g_j
-  gg[j] = cscale(cj, gj);
-  S.iters += 1;
-  S.cyc_k = j + 1;
-  S.t1 = wall_clock64();
-  S.scal = c2(nrm, 0.0);
-  const double est = sqrt(gg[j + 1].x * gg[j + 1].x + gg[j + 1].y * gg[j + 1].y);
-  if (!isfinite(est) || !isfinite(nrm)) {
-    S.status = kNonfinite;
-  } else if (est <= tol * sqrt(S.bnorm2) || S.iters >= maxit || j + 1 == gm.m) {
-    S.phase = 1;
+  if (threadIdx.x == 0) {
+    flag[0] = 0.0;
+    double nrm2 = sum[4 * j];
+    for (int i = 0; i < j; ++i) {
+      const double2 si = s_at(i);
+      nrm2 -= si.x * si.x + si.y * si.y;
+    }
+    const double r = sqrt(fmax(nrm2, 0.0));
+    flag[1] = r;
+    // column j - 1 completed, then rotated
+    double2* Huc = Hu + (size_t)(j - 1) * m1;
+    for (int i = 0; i < j; ++i) {
+      colj[i] = cadd(Huc[i], s_at(i));
+      Huc[i] = colj[i];
+    }
+    colj[j] = c2(r, 0.0);
+    Huc[j] = colj[j];
+    double2* Hc = H + (size_t)(j - 1) * m1;
+    for (int i = 0; i <= j; ++i) Hc[i] = colj[i];
+    double* cs = gm.cs + (size_t)slot * gm.m;
+    double2* sn = gm.sn + (size_t)slot * gm.m;
+    double2* gg = gm.g + (size_t)slot * m1;
+    const int k = j - 1;
+    for (int i = 0; i < k; ++i) {
+      const double2 a = Hc[i], bb = Hc[i + 1];
+      Hc[i] = cadd(cscale(cs[i], a), cmul(sn[i], bb));
+      Hc[i + 1] = csub(cscale(cs[i], bb), cmul(c2(sn[i].x, -sn[i].y), a));
+    }
+    double ck;
+    double2 sk;
+    givens(Hc[k], Hc[k + 1], ck, sk);
+    cs[k] = ck;
+    sn[k] = sk;
+    Hc[k] = cadd(cscale(ck, Hc[k]), cmul(sk, Hc[k + 1]));
+    Hc[k + 1] = c2(0.0, 0.0);
+    const double2 gk = gg[k];
+    gg[k + 1] = cmul(c2(-sk.x, sk.y), gk);  // -conj(s) g_k
+    gg[k] = cscale(ck, gk);
+    S.iters += 1;
+    S.cyc_k = j;
+    S.t1 = wall_clock64();
+    const double est = sqrt(gg[k + 1].x * gg[k + 1].x + gg[k + 1].y * gg[k + 1].y);
+    if (!isfinite(est) || !isfinite(r)) {
+      S.status = kNonfinite;
+    } else if (finish || r == 0.0 || est <= tol * sqrt(S.bnorm2) || S.iters >= maxit) {
+      S.phase = 1;
+    } else {
+      flag[0] = 1.0;
+      S.scal = c2(r, 0.0);
+    }
+  }
+  __syncthreads();
+  if (flag[0] == 0.0) return;
+  // first pass of column j: h = V^H (B M^-1 v_j) from the scalars, with
+  // B M^-1 v_j = (z - sum_{i<j} s_i B M^-1 V_i) / r = (z - V (Hu s)) / r
+  const double ir = 1.0 / flag[1];
+  double2* Hn = Hu + (size_t)j * m1;
+  for (int kk = threadIdx.x; kk < m1; kk += blockDim.x) {
+    if (kk > j) {
+      Hn[kk] = c2(0.0, 0.0);
+      continue;
+    }
+    double2 hs = c2(0.0, 0.0);  // (Hu s)_kk over the finished columns i >= kk - 1
+    for (int i = max(kk - 1, 0); i < j; ++i)
+      hs = cadd(hs, cmul(i == j - 1 ? colj[kk] : Hu[(size_t)i * m1 + kk], s_at(i)));
+    double2 num;
+    if (kk < j) {
+      num = p_at(kk);
+    } else {
+      double2 vz = q;  // <v_j, z> r
+      for (int i = 0; i < j; ++i) vz = csub(vz, cconjmul(s_at(i), p_at(i)));
+      num = cscale(ir, vz);
+    }
+    const double2 h = cscale(ir, csub(num, hs));
+    Hn[kk] = h;
+    cv[kk] = cadd(cscale(ir, hs), h);
+    if (kk < j) sv[kk] = s_at(kk);
+  }
+}
+
+// The step's second pass over the basis, for the slots that go on: v_j =
+// (u_j - sum_{i<j} s_i V_i) / r into V_j, and the next first-pass result
+// u_{j+1} = z / r - sum_{i<j} c_i V_i - c_j v_j into V_{j+1}.
+__global__ void __launch_bounds__(kBlock) k_gm_update2(Batch bt, int tiles, size_t n, Gmres gm, int j,
+                                                       double2* __restrict__ V, size_t vstride,
+                                                       const double2* __restrict__ z, size_t stride) {
+  int slot, tile;
+  if (!decode_vec(bt, tiles, slot, tile)) return;
+  const Slot& S = bt.slots[slot];
+  if (S.status != kActive || S.phase != 0) return;
+  const size_t base = (size_t)slot * stride;
+  const double2* sv = gm.hc + (size_t)slot * 2 * (gm.m + 1);
+  const double2* cv = sv + gm.m + 1;
+  const double ir = 1.0 / S.scal.x;
+  double2* uj = V + (size_t)j * vstride + base;
+  double2* un = V + (size_t)(j + 1) * vstride + base;
+  // basis vector by basis vector, the thread's kVecPerThread nodes of each in
+  // flight together
+  double2 av[kVecPerThread], au[kVecPerThread];
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    av[e] = i < n ? uj[i] : c2(0.0, 0.0);
+    au[e] = i < n ? cscale(ir, z[base + i]) : c2(0.0, 0.0);
+  }
+  for (int q = 0; q < j; ++q) {
+    const double2 sq = sv[q], cq = cv[q];
+    const double2* vq = V + (size_t)q * vstride + base;
+#pragma unroll
+    for (int e = 0; e < kVecPerThread; ++e) {
+      const size_t i = vec_index(tile, e);
+      if (i < n) {
+        const double2 x = vq[i];
+        av[e] = csub(av[e], cmul(sq, x));
+        au[e] = csub(au[e], cmul(cq, x));
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kVecPerThread; ++e) {
+    const size_t i = vec_index(tile, e);
+    if (i < n) {
+      const double2 vj = cscale(ir, av[e]);
+      uj[i] = vj;
+      un[i] = csub(au[e], cmul(cv[j], vj));
+    }
   }
 }
 
@@ -1279,40 +1379,23 @@ hipError_t launch_gm_scale(size_t n, const Batch& bt, int cap, double2* v, size_
   return hipGetLastError();
 }
 
-hipError_t launch_gm_dots(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, int pass,
-                          const double2* V, size_t vstride, const double2* w, size_t stride,
-                          hipStream_t st) {
-  if (cap <= 0) return hipSuccess;
-  const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_gm_dots, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, j, pass, V,
-                     vstride, w, stride);
-  hipLaunchKernelGGL(k_gm_dots_fin, dim3(cap), dim3(kBlock), 0, st, tiles, bt, gm, j, pass);
-  return hipGetLastError();
-}
+int gm_dot_tiles(size_t n) { return (int)((n + kGmDotNodes - 1) / kGmDotNodes); }
 
-hipError_t launch_gm_orth(size_t n, const Batch& bt, int cap, const Reduce& rd, const Gmres& gm, int j,
-                          const double2* V, size_t vstride, double2* w, size_t stride, hipStream_t st) {
+hipError_t launch_gm_step(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, int finish, double tol,
+                          int maxit, double2* V, size_t vstride, const double2* z, size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  if (finish ? z != nullptr : z == nullptr) return hipErrorInvalidValue;
   const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_gm_orth, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, gm, j, V,
-                     vstride, w, stride);
-  hipLaunchKernelGGL(k_gm_reorth_test, dim3(cap), dim3(kBlock), 0, st, tiles, bt, rd, gm);
-  return hipGetLastError();
-}
-
-hipError_t launch_gm_orth_fin(const Batch& bt, int cap, const Gmres& gm, int j, double tol, int maxit,
-                              hipStream_t st) {
-  if (cap <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gm_orth_fin, dim3(cap), dim3(kBlock), 0, st, bt, gm, j, tol, maxit);
-  return hipGetLastError();
-}
-
-hipError_t launch_gm_orth_scale(size_t n, const Batch& bt, int cap, const Gmres& gm, int j, const double2* V,
-                                size_t vstride, double2* w, size_t stride, hipStream_t st) {
-  if (cap <= 0) return hipSuccess;
-  const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_gm_orth_scale, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, j, V,
-                     vstride, w, stride);
+  const int dtiles = gm_dot_tiles(n);
+  if (dtiles > gm.max_tiles) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gm_dots2, grid1((long long)cap * dtiles), dim3(kBlock),
+                     (size_t)kWaves * (4 * j + 3) * sizeof(double), st, bt, dtiles, n, gm, j, V, vstride, z, stride);
+  const size_t fin_lds = (size_t)((4 * j + 4) & ~1) * sizeof(double) + (size_t)(j + 1) * sizeof(double2) +
+                         2 * sizeof(double);
+  hipLaunchKernelGGL(k_gm_fin2, dim3(cap), dim3(kBlock), fin_lds, st, dtiles, bt, gm, j, tol, maxit, finish);
+  if (!finish)
+    hipLaunchKernelGGL(k_gm_update2, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, gm, j, V,
+                       vstride, z, stride);
   return hipGetLastError();
 }
 

@@ -303,7 +303,13 @@ size_t hz_footprint(int dim, int nz, int nx, int nfreq, int nrhs, const hz_solve
     for (int l = 0; l + 1 < L; ++l) bytes += (size_t)nfreq * n[l] * z;  // tabulated w / diag(M)
     bytes += 2 * (size_t)nfreq * n[L - 1] * n[L - 1] * z;              // coarse inverse and its work copy
   }
-  if (o->krylov == HZ_GMRES) bytes += (size_t)(o->gmres_m + 1) * slots * n[0] * z;
+  if (o->krylov == HZ_GMRES) {
+    const size_t m1 = (size_t)o->gmres_m + 1;
+    bytes += m1 * slots * n[0] * z;                                                          // basis
+    const size_t tiles = (size_t)std::max(hz::vec_tiles(n[0]), hz::gm_dot_tiles(n[0]));
+    bytes += slots * tiles * (4 * m1 + 4) * sizeof(double);                                  // partial sums
+    bytes += slots * (2 * m1 * o->gmres_m + 3 * m1 + 2 * (size_t)o->gmres_m) * z;           // small matrices
+  }
   bytes += slots * (sizeof(hz::Slot) + 64) + slots * n[0] / 64 * 4 * sizeof(double);  // reductions
   return bytes;
 }
