@@ -481,7 +481,8 @@ def test_full_size_batched_configuration(hz):
 def test_gmres_matches_oracle(hz, m, tol):
     """GMRES(m) (the paper's data-modelling engine) with the V-cycle: the
     wavefield against LU and the inner-step count against the oracle's
-    GMRES(m) (modified vs classical-twice Gram-Schmidt: same mathematics)."""
+    GMRES(m) (modified Gram-Schmidt there, delayed classical Gram-Schmidt
+    twice here: the same mathematics)."""
     w = workloads.model_2d_lens(sign=-1.0)
     c = make_ctx(hz, w.m, w.h)
     f = w.freqs[0]
@@ -499,6 +500,76 @@ def test_gmres_matches_oracle(hz, m, tol):
         assert rel(to_np(u)[0, s].ravel(), ulu) < 1e-6
         _, it_o, _, st_o = krylov.gmres(B, bn, vc, m=m, tol=tol, maxit=3000)
         assert st_o == krylov.CONVERGED and iters_close(it, it_o), (it, it_o)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 7])
+def test_gmres_short_restarts(hz, m):
+    """GMRES(m) with short cycles, where the Arnoldi steps' delayed second
+    pass meets the cycle's end at every few columns (m = 1: every column is
+    completed by a cycle's closing pass): three shots against LU and the
+    oracle's GMRES(m) iteration counts, with the planned V-cycle."""
+    w = workloads.model_2d_lens(n=65, h=20.0)
+    f, alpha = 6.0, 0.01
+    om = 2 * np.pi * f
+    c = make_ctx(hz, w.m, w.h)
+    xs = [8, 32, 56]
+    b = c.point_rhs([0] * 3, xs)
+    u, info = c.solve([f], alpha, b[None], krylov="gmres", gmres_m=m, tol=1e-8, maxit=2000)
+    L, wj = c.plan(f)
+    B = op.operator_B(w.m, w.h, om, alpha)
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
+    lu = direct.factor_superlu(B)
+    for s, ix in enumerate(xs):
+        st, it, rr = info[s]
+        assert st == hz.HZ_RHS_CONVERGED and rr <= 1e-8, info[s]
+        bn = op.point_source(w.shape, w.h, [ix])
+        assert rel(to_np(u)[0, s].ravel(), lu.solve(bn)) < 1e-6
+        _, it_o, _, st_o = krylov.gmres(B, bn, vc, m=m, tol=1e-8, maxit=2000)
+        assert st_o == krylov.CONVERGED and iters_close(it, it_o), (m, ix, it, it_o)
+
+
+@pytest.mark.parametrize("maxit", [4, 5, 6, 10])
+def test_gmres_maxit_at_and_off_cycle_ends(hz, maxit):
+    """An iteration limit that falls inside a cycle, on its last column
+    (maxit = 5, 10 with m = 5) or one past it stops the solve after exactly
+    maxit columns, with the iterate of those columns: its true residual is
+    the oracle's GMRES(5) residual after maxit columns."""
+    w = workloads.model_2d_lens(n=65, h=20.0)
+    f, alpha = 6.0, 0.01
+    om = 2 * np.pi * f
+    c = make_ctx(hz, w.m, w.h)
+    b = c.point_rhs([0], [32])
+    u, info = c.solve([f], alpha, b[None], krylov="gmres", gmres_m=5, tol=1e-14, maxit=maxit)
+    st, it, rr = info[0]
+    assert st == hz.HZ_RHS_MAXIT and it == maxit, info[0]
+    L, wj = c.plan(f)
+    B = op.operator_B(w.m, w.h, om, alpha)
+    vc = mg.VCycle(w.m, w.h, om, 1.0, 0.5, L, 2, 2, wj, coarse="auto")
+    bn = op.point_source(w.shape, w.h, [32])
+    x_o, it_o, rr_o, st_o = krylov.gmres(B, bn, vc, m=5, tol=1e-14, maxit=maxit)
+    assert st_o == krylov.MAXIT and it_o == maxit
+    # a few columns of a well-conditioned minimisation: the two residuals agree closely
+    assert abs(rr - rr_o) <= 1e-6 * rr_o, (rr, rr_o)
+    assert rel(to_np(u)[0, 0].ravel(), x_o) < 1e-8
+
+
+def test_gmres_batch_invariance_bitwise(hz):
+    """A GMRES right-hand side gives the same bits alone and inside a batch
+    of slots that finish at different Arnoldi steps."""
+    import torch
+    w = workloads.model_2d_lens(n=129, h=15.0)
+    c = make_ctx(hz, w.m, w.h)
+    rng = np.random.default_rng(5)
+    xs = rng.integers(0, 129, size=6)
+    b = c.point_rhs([0] * 6, xs)
+    kw = dict(krylov="gmres", gmres_m=7)
+    u_all, info_all = c.solve([4.0, 6.0], 0.01, torch.stack([b, b.flip(0)]), **kw)
+    u_one, info_one = c.solve([6.0], 0.01, b[2:3][None], **kw)
+    assert torch.equal(u_all[1, 3], u_one[0, 0])  # b.flip(0)[3] == b[2]
+    assert info_all[6 + 3][1] == info_one[0][1]
+    u_one4, _ = c.solve([4.0], 0.01, b[4:5][None], **kw)
+    assert torch.equal(u_all[0, 4], u_one4[0, 0])
+    assert len({i[1] for i in info_all}) > 1  # the slots stop at different steps
 
 
 def test_gmres_unpreconditioned_and_maxit(hz):
