@@ -797,10 +797,21 @@ def bench_gmres(args):
                                    "share_of_step": ms_up / steps / (sec * 1e3),
                                    "algorithmic_GB_per_step": gs_bytes / steps / 1e9,
                                    "operator_apply_ms_per_step": ms_ap / steps}
+            traffic = None
+            tf = os.path.join(ROOT, "profiles", "gmres_step_traffic.json")
+            if os.path.exists(tf):
+                from paper_1712_08743_amd import profiling
+                with open(tf) as fh:
+                    tr = json.load(fh)
+                if tr.get("kernel_source_hash") == profiling.kernel_source_hash():
+                    traffic = tr["bytes_per_step"]
             res["roofline"] = {"bound": "hbm", "kernel": "Gram-Schmidt step (k_gm_dots2 + k_gm_fin2 + "
                                                          "k_gm_update2)",
                                "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                               "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+                               "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                               "traffic_unit": "HBM bytes per benchmark step (rocprofv3 FETCH_SIZE + WRITE_SIZE "
+                                               "over the step's Gram-Schmidt kernels, copy-calibrated)",
+                               "algorithmic_bytes_per_step": gs_bytes / steps}
             out.update(res)
         else:
             out["bicgstab"] = res

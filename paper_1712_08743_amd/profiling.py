@@ -6,6 +6,9 @@
         [--out FILE.md] [--json FILE.json]
 
     python -m paper_1712_08743_amd.profiling stalls CSV [CSV ...] --command CMD [--out FILE.md]
+    python -m paper_1712_08743_amd.profiling gmres-traffic --fetch CSV --write CSV \\
+        --copy-fetch CSV --copy-write CSV --copy-bytes N --steps S --report JSON --command CMD \\
+        [--out FILE.md] [--json FILE.json]
 
 ``stats`` reads a ``--kernel-trace`` CSV and tabulates, per kernel symbol,
 the launches, total and average duration; the finest-level kernels are named
@@ -16,6 +19,11 @@ by what it reads for the library's plain copy kernel of ``N`` bytes read and
 ``N`` written, and reports bytes per dispatch and per right-hand side. ``stalls`` reads
 ``--pmc`` runs of the SQ wave counters and tabulates, per kernel, where its
 waves spend their cycles and the instructions each wave issues.
+``gmres-traffic`` sums the two counters over every dispatch of GMRES's
+Gram-Schmidt step kernels and compares the bytes per step with the
+algorithmic bytes of the ``bench.py --gmres`` report of the same run
+(``--json``: the bytes per step with the kernel source hash, which
+``bench.py --gmres`` reports as its roofline's traffic while the hash holds).
 """
 
 import argparse
@@ -123,6 +131,56 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, rh
         rows[sym] = {"dispatches": len(vals), "fetch_bytes": fb, "write_bytes": wb,
                      "fetch_bytes_per_rhs": fb / rhs, "write_bytes_per_rhs": wb / rhs}
     return {"fetch_factor": ffac, "write_factor": wfac, "kernels": rows}
+
+
+GMRES_STEP_KERNELS = ("hz::k_gm_dots2", "hz::k_gm_fin2", "hz::k_gm_update2")
+
+
+def counter_totals(csv_path, symbols):
+    """symbol -> (dispatches, summed counter value in KiB) over every dispatch."""
+    out = {s: [0, 0.0] for s in symbols}
+    for r in csv.DictReader(open(csv_path)):
+        s = symbol(r["Kernel_Name"])
+        if s in out:
+            out[s][0] += 1
+            out[s][1] += float(r["Counter_Value"])
+    return out
+
+
+def gmres_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, steps):
+    """HBM bytes per step of GMRES's Gram-Schmidt step kernels: FETCH_SIZE and
+    WRITE_SIZE summed over all their dispatches (their grids shrink as the
+    right-hand sides converge), scaled by the copy kernel, over `steps`
+    identical GMRES solves of the profiled run."""
+    cF, cW = counters(copy_fetch_csv), counters(copy_write_csv)
+    cf, cw = cF["hz::k_copy"], cW["hz::k_copy"]
+    ffac = copy_bytes / (1024.0 * sum(cf) / len(cf))
+    wfac = copy_bytes / (1024.0 * sum(cw) / len(cw))
+    F = counter_totals(fetch_csv, GMRES_STEP_KERNELS)
+    W = counter_totals(write_csv, GMRES_STEP_KERNELS)
+    rows = {}
+    for s in GMRES_STEP_KERNELS:
+        rows[s] = {"dispatches": F[s][0], "fetch_bytes_per_step": 1024.0 * ffac * F[s][1] / steps,
+                   "write_bytes_per_step": 1024.0 * wfac * W[s][1] / steps}
+    return {"fetch_factor": ffac, "write_factor": wfac, "kernels": rows}
+
+
+def _gmres_traffic_md(t, command, algorithmic_gb):
+    lines = ["# HBM traffic of GMRES(30)'s Gram-Schmidt step kernels (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)",
+             "", "Commands:", "", "```", command, "```", "",
+             f"Counters summed over every dispatch and scaled by the library's copy kernel (FETCH_SIZE x "
+             f"{t['fetch_factor']:.4f}, WRITE_SIZE x {t['write_factor']:.4f}), per GMRES step of the "
+             "benchmark batch (256 right-hand sides, all four frequencies).", "",
+             "| kernel | dispatches | read GB/step | write GB/step |", "|---|---:|---:|---:|"]
+    tot = 0.0
+    for s, r in t["kernels"].items():
+        lines.append(f"| `{s}` | {r['dispatches']} | {r['fetch_bytes_per_step'] / 1e9:.1f} | "
+                     f"{r['write_bytes_per_step'] / 1e9:.1f} |")
+        tot += r["fetch_bytes_per_step"] + r["write_bytes_per_step"]
+    lines += ["", f"Measured: {tot / 1e9:.1f} GB per step; algorithmic (the dot pass reads j + 2 vectors, the "
+              f"update pass reads j + 2 and writes 2, per right-hand side and Arnoldi step j): "
+              f"{algorithmic_gb:.1f} GB per step; ratio {tot / 1e9 / algorithmic_gb:.3f}."]
+    return "\n".join(lines) + "\n"
 
 
 def counter_means(csv_paths):
@@ -238,9 +296,31 @@ def main():
     b.add_argument("--command", required=True)
     b.add_argument("--out")
     b.add_argument("--json")
+    g = sub.add_parser("gmres-traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        g.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    g.add_argument("--copy-bytes", type=float, required=True)
+    g.add_argument("--steps", type=int, required=True, help="GMRES solves of the batch in the profiled run")
+    g.add_argument("--report", required=True, help="the run's bench.py --gmres JSON line")
+    g.add_argument("--command", required=True)
+    g.add_argument("--out")
+    g.add_argument("--json")
     args = ap.parse_args()
     if args.what == "stalls":
         text = _stalls_md(args.csv, args.command)
+    elif args.what == "gmres-traffic":
+        t = gmres_traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes, args.steps)
+        with open(args.report) as fh:
+            rep = json.loads(fh.read().strip().splitlines()[-1])
+        text = _gmres_traffic_md(t, args.command, rep["gram_schmidt"]["algorithmic_GB_per_step"])
+        if args.json:
+            with open(args.json, "w") as fh:
+                json.dump({"kernel_source_hash": kernel_source_hash(), "fetch_factor": t["fetch_factor"],
+                           "write_factor": t["write_factor"],
+                           "workload": rep["config"]["workload"],
+                           "bytes_per_step": sum(r["fetch_bytes_per_step"] + r["write_bytes_per_step"]
+                                                 for r in t["kernels"].values()),
+                           "kernels": t["kernels"]}, fh, indent=1)
     elif args.what == "stats":
         between = (args.between[0], int(args.between[1]), int(args.between[2])) if args.between else None
         text = _stats_md(args.trace, args.command, between)
