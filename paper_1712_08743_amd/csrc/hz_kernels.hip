@@ -822,17 +822,22 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
 // u1 = (w/D) b, formed wherever the march reads u (u_in is not read), and the
 // pass stores the second sweep from u1.
 constexpr int kMarchW = 62;
-constexpr int kMarchZ = 16;  // even: the march takes two planes per step
+// Short chunks and small blocks: more wavefronts in flight on every level
+// (z-chunks of 4, 6, 8, 12, 16, 32 planes and 2, 4, 8, 16 wavefronts per
+// block measured; 4 planes and 2 wavefronts the fastest, 6 % over 16 and 4).
+constexpr int kMarchZ = 4;  // even: the march takes two planes per step
+constexpr int kMarchWaves = 2;  // wavefronts (neighbouring y-rows) per block
+constexpr int kMarchBlock = 64 * kMarchWaves;
 
 template <bool FROM_ZERO>
-__global__ void __launch_bounds__(kBlock) k_smooth3m(Grid g, int nstrip, int nchunk, int groups, int lvl, Batch bt,
+__global__ void __launch_bounds__(kMarchBlock) k_smooth3m(Grid g, int nstrip, int nchunk, int groups, int lvl, Batch bt,
                                                      const double2* __restrict__ b,
                                                      const double2* __restrict__ u_in,
                                                      double2* __restrict__ u_out, size_t stride) {
   int slot, grp;
   if (!decode_tile(bt, groups, slot, grp)) return;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
-  const int tile = grp * (kBlock / 64) + wv;
+  const int tile = grp * kMarchWaves + wv;
   if (tile >= g.ny * nstrip * nchunk) return;
   const int iy = tile % g.ny;  // y fastest: a block's wavefronts are neighbouring rows
   const int rest = tile / g.ny;
@@ -1126,13 +1131,13 @@ hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool 
   if (cap <= 0) return hipSuccess;
   if (g.rho) return hipErrorInvalidValue;  // constant density only
   const int nstrip = (g.nx + kMarchW - 1) / kMarchW, nchunk = (g.nz + kMarchZ - 1) / kMarchZ;
-  const int groups = (g.ny * nstrip * nchunk + 3) / 4;
+  const int groups = (g.ny * nstrip * nchunk + kMarchWaves - 1) / kMarchWaves;
   if (from_zero)
-    hipLaunchKernelGGL(k_smooth3m<true>, grid1(tile_blocks(groups, cap)), dim3(kBlock), 0, st, g, nstrip, nchunk,
-                       groups, lvl, bt, b, u_in, u_out, stride);
+    hipLaunchKernelGGL(k_smooth3m<true>, grid1(tile_blocks(groups, cap)), dim3(kMarchBlock), 0, st, g, nstrip,
+                       nchunk, groups, lvl, bt, b, u_in, u_out, stride);
   else
-    hipLaunchKernelGGL(k_smooth3m<false>, grid1(tile_blocks(groups, cap)), dim3(kBlock), 0, st, g, nstrip, nchunk,
-                       groups, lvl, bt, b, u_in, u_out, stride);
+    hipLaunchKernelGGL(k_smooth3m<false>, grid1(tile_blocks(groups, cap)), dim3(kMarchBlock), 0, st, g, nstrip,
+                       nchunk, groups, lvl, bt, b, u_in, u_out, stride);
   return hipGetLastError();
 }
 
