@@ -308,7 +308,8 @@ size_t hz_footprint(int dim, int nz, int nx, int nfreq, int nrhs, const hz_solve
     bytes += m1 * slots * n[0] * z;                                                          // basis
     const size_t tiles = (size_t)std::max(hz::vec_tiles(n[0]), hz::gm_dot_tiles(n[0]));
     bytes += slots * tiles * (4 * m1 + 4) * sizeof(double);                                  // partial sums
-    bytes += slots * (2 * m1 * o->gmres_m + 3 * m1 + 2 * (size_t)o->gmres_m) * z;           // small matrices
+    bytes += slots * ((2 * m1 * o->gmres_m + 3 * m1 + 2 * (size_t)o->gmres_m) * z +          // small matrices
+                      (size_t)o->gmres_m * sizeof(double));                                   // and rotations
   }
   bytes += slots * (sizeof(hz::Slot) + 64) + slots * n[0] / 64 * 4 * sizeof(double);  // reductions
   return bytes;
