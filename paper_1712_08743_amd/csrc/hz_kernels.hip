@@ -813,40 +813,48 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
 // One damped-Jacobi sweep on a 3D level from a given iterate with the
 // level's tabulated w/D, marching along z: a wavefront owns kMarchW columns of
 // one y-row (lane = column, from xs - 1; lanes 1 .. kMarchW store) and
-// kMarchZ z-planes. z-neighbours stay in registers, x-neighbours come from
-// the adjacent lanes, y-neighbours are the rows of the block's other
-// wavefronts (tile order puts neighbouring rows in one block), read from
-// cache. Written in the Jacobi form (1 - w) u + (w/D)(b + (fz sz + fy sy +
-// fx sx) / h^2), so the slowness is not read.
+// kMarchZ z-planes, two planes per step with all their loads issued
+// together. z-neighbours stay in registers, x-neighbours come from the
+// adjacent lanes. A block of kMarchWaves wavefronts owns that many
+// neighbouring y-rows of one strip and z-chunk: every step each wavefront
+// puts its row's iterate on the step's two planes in LDS (the planes it holds
+// in registers anyway), the first and the last wavefront also the rows just
+// below and above the block, and after one barrier every wavefront reads its
+// y-neighbours there, so a row is read from memory once per block instead of
+// by each of its neighbours. Rows past the grid are zero; their wavefronts
+// load and store nothing and only take part in the barriers. The LDS rows
+// are double-buffered by step parity: one barrier per step. Written in the
+// Jacobi form (1 - w) u + (w/D)(b + (fz sz + fy sy + fx sx) / h^2), so the
+// slowness is not read.
 // FROM_ZERO: the two sweeps from u = 0 in one pass. The first gives
 // u1 = (w/D) b, formed wherever the march reads u (u_in is not read), and the
 // pass stores the second sweep from u1.
+// Shapes measured on the 129^3 benchmark box (step time): z-chunks of 4 to
+// 32 planes, 1 to 16 wavefronts per block, with and without the LDS rows;
+// 6 planes and 4 wavefronts sharing rows through LDS the fastest.
 constexpr int kMarchW = 62;
-// Short chunks and small blocks: more wavefronts in flight on every level
-// (z-chunks of 4, 6, 8, 12, 16, 32 planes and 2, 4, 8, 16 wavefronts per
-// block measured; 4 planes and 2 wavefronts the fastest, 6 % over 16 and 4).
-constexpr int kMarchZ = 4;  // even: the march takes two planes per step
-constexpr int kMarchWaves = 2;  // wavefronts (neighbouring y-rows) per block
-constexpr int kMarchBlock = 64 * kMarchWaves;
+constexpr int kMarchZ = 6;      // even: the march takes two planes per step
+constexpr int kMarchWaves = 4;  // wavefronts (neighbouring y-rows) per block
 
 template <bool FROM_ZERO>
-__global__ void __launch_bounds__(kMarchBlock) k_smooth3m(Grid g, int nstrip, int nchunk, int groups, int lvl, Batch bt,
-                                                     const double2* __restrict__ b,
-                                                     const double2* __restrict__ u_in,
-                                                     double2* __restrict__ u_out, size_t stride) {
+__global__ void __launch_bounds__(64 * kMarchWaves) k_smooth3m(Grid g, int nstrip, int nchunk, int nyg, int groups,
+                                                               int lvl, Batch bt, const double2* __restrict__ b,
+                                                               const double2* __restrict__ u_in,
+                                                               double2* __restrict__ u_out, size_t stride) {
+  __shared__ double2 ysh[2][2][kMarchWaves + 2][64];  // [step parity][plane of the step][row slot][lane]
   int slot, grp;
   if (!decode_tile(bt, groups, slot, grp)) return;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
-  const int tile = grp * kMarchWaves + wv;
-  if (tile >= g.ny * nstrip * nchunk) return;
-  const int iy = tile % g.ny;  // y fastest: a block's wavefronts are neighbouring rows
-  const int rest = tile / g.ny;
+  const int yg = grp % nyg, rest = grp / nyg;
   const int strip = rest % nstrip, chunk = rest / nstrip;
+  const int iy0 = yg * kMarchWaves, iy = iy0 + wv;
+  const bool row = iy < g.ny;          // the wavefront's row is in the grid
+  const int iyc = min(iy, g.ny - 1);   // an address inside the grid for every wavefront
   const int lane = threadIdx.x % 64;
   const int x = strip * kMarchW - 1 + lane;
   const bool xin = x >= 0 && x < g.nx;
   const int xx = min(max(x, 0), g.nx - 1);
-  const bool own = lane >= 1 && lane <= kMarchW && xin;
+  const bool own = lane >= 1 && lane <= kMarchW && xin && row;
   const int z0 = chunk * kMarchZ, z1 = min(g.nz, z0 + kMarchZ);
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const double2* wd = f.winv[lvl];
@@ -857,25 +865,27 @@ __global__ void __launch_bounds__(kMarchBlock) k_smooth3m(Grid g, int nstrip, in
   const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
   const double wy = (iy == 0 || iy == g.ny - 1) ? 0.5 : 1.0, wx = (x == 0 || x == g.nx - 1) ? 0.5 : 1.0;
   const double2 zero = c2(0.0, 0.0);
-  // node (z, iy, xx); z inside the grid
-  auto at = [&](int z) { return (size_t)z * sz + (size_t)iy * sy + xx; };
-  // the iterate the sweep starts from at node q
+  // the first wavefront also puts the row below the block in LDS (slot 0),
+  // the last the row above it (slot kMarchWaves + 1); zero where that row is
+  // outside the grid
+  const bool edge = wv == 0 || wv == kMarchWaves - 1;
+  const int hr = wv == 0 ? iy0 - 1 : iy0 + kMarchWaves;
+  const bool halo = edge && hr >= 0 && hr < g.ny;
+  const int hslot = wv == 0 ? 0 : kMarchWaves + 1;
+  auto at_row = [&](int r, int z) { return (size_t)z * sz + (size_t)r * sy + xx; };
+  auto at = [&](int z) { return at_row(iyc, z); };
   auto uval = [&](size_t q) { return FROM_ZERO ? cmul(b[base + q], wd[q]) : us[q]; };
-  // u on plane z of the wavefront's row, zero outside the grid
-  auto plane = [&](int z) { return (z >= 0 && z < g.nz) ? keep(xin, uval(at(z))) : zero; };
-  struct Row {  // loads for output plane z: u on z + 1, the y-neighbours on z, b, w/D
+  // the iterate on plane z of the wavefront's row, zero outside the grid
+  auto plane = [&](int z) { return (row && z >= 0 && z < g.nz) ? keep(xin, uval(at(z))) : zero; };
+  // the halo row's iterate on plane z (clamped into the grid: a second plane past it is not stored)
+  auto hval = [&](int z) { return halo ? uval(at_row(hr, min(z, g.nz - 1))) : zero; };
+  struct Row {
     double2 uc, ul, ur, bz, wdz;
   };
-  auto load = [&](int z) {
-    Row r;
-    r.uc = plane(z + 1);
-    const int zc = min(z, g.nz - 1);  // the second plane of a step may be past the grid (not stored)
-    const size_t q = at(zc);
-    r.ul = iy > 0 ? uval(q - sy) : zero;
-    r.ur = iy < g.ny - 1 ? uval(q + sy) : zero;
-    r.bz = b[base + q];
-    r.wdz = wd[q];
-    return r;
+  auto centre = [&](int z, Row& r) {  // b and w/D at plane z of the row (clamped: a second plane past the grid)
+    const size_t q = at(min(z, g.nz - 1));
+    r.bz = row ? b[base + q] : zero;
+    r.wdz = row ? wd[q] : zero;
   };
   auto step = [&](int z, const Row& r, double2 ua, double2 ub) {
     const double wz = (z == 0 || z == g.nz - 1) ? 0.5 : 1.0;
@@ -889,18 +899,29 @@ __global__ void __launch_bounds__(kMarchBlock) k_smooth3m(Grid g, int nstrip, in
         c2(omw * ub.x + (r.wdz.x * tx - r.wdz.y * ty), omw * ub.y + (r.wdz.x * ty + r.wdz.y * tx));
     if (own && z < z1) u_out[base + at(z)] = out;
   };
+  // the step's exchange: this row's iterate on planes z (p0) and z + 1 (p1)
+  // and the halo row's go to LDS; the y-neighbours come back
+  auto exchange = [&](int z, double2 p0, double2 p1, Row& r0, Row& r1) {
+    const int buf = ((z - z0) >> 1) & 1;
+    const double2 h0 = hval(z), h1 = hval(z + 1);
+    ysh[buf][0][wv + 1][lane] = p0;
+    ysh[buf][1][wv + 1][lane] = p1;
+    if (edge) {
+      ysh[buf][0][hslot][lane] = h0;
+      ysh[buf][1][hslot][lane] = h1;
+    }
+    __syncthreads();
+    r0.ul = ysh[buf][0][wv][lane];
+    r0.ur = ysh[buf][0][wv + 2][lane];
+    r1.ul = ysh[buf][1][wv][lane];
+    r1.ur = ysh[buf][1][wv + 2][lane];
+  };
   if constexpr (FROM_ZERO) {
-    // b and w/D of the centre plane were loaded a step earlier, as the plane above
     auto raw = [&](int z, double2& bq, double2& wq) {
-      const bool in = z >= 0 && z < g.nz;
+      const bool in = row && z >= 0 && z < g.nz;
       const size_t q = at(in ? z : 0);
       bq = in ? b[base + q] : zero;
       wq = in ? wd[q] : zero;
-    };
-    auto yrow = [&](int z, Row& r) {
-      const size_t q = at(min(z, g.nz - 1));
-      r.ul = iy > 0 ? uval(q - sy) : zero;
-      r.ur = iy < g.ny - 1 ? uval(q + sy) : zero;
     };
     double2 bq, wq;
     raw(z0 - 1, bq, wq);
@@ -913,10 +934,9 @@ __global__ void __launch_bounds__(kMarchBlock) k_smooth3m(Grid g, int nstrip, in
       r0.wdz = wq;
       raw(z + 1, r1.bz, r1.wdz);
       raw(z + 2, bq, wq);
-      yrow(z, r0);
-      yrow(z + 1, r1);
       r0.uc = keep(xin, cmul(r1.bz, r1.wdz));
       r1.uc = keep(xin, cmul(bq, wq));
+      exchange(z, ub, r0.uc, r0, r1);
       step(z, r0, ua, ub);
       step(z + 1, r1, ub, r0.uc);
       ua = r0.uc;
@@ -925,7 +945,12 @@ __global__ void __launch_bounds__(kMarchBlock) k_smooth3m(Grid g, int nstrip, in
   } else {
     double2 ua = plane(z0 - 1), ub = plane(z0);
     for (int z = z0; z < z1; z += 2) {
-      const Row r0 = load(z), r1 = load(z + 1);
+      Row r0, r1;
+      r0.uc = plane(z + 1);
+      r1.uc = plane(z + 2);
+      centre(z, r0);
+      centre(z + 1, r1);
+      exchange(z, ub, r0.uc, r0, r1);
       step(z, r0, ua, ub);
       step(z + 1, r1, ub, r0.uc);
       ua = r0.uc;
@@ -1131,13 +1156,14 @@ hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool 
   if (cap <= 0) return hipSuccess;
   if (g.rho) return hipErrorInvalidValue;  // constant density only
   const int nstrip = (g.nx + kMarchW - 1) / kMarchW, nchunk = (g.nz + kMarchZ - 1) / kMarchZ;
-  const int groups = (g.ny * nstrip * nchunk + kMarchWaves - 1) / kMarchWaves;
+  const int nyg = (g.ny + kMarchWaves - 1) / kMarchWaves;
+  const int groups = nyg * nstrip * nchunk;
   if (from_zero)
-    hipLaunchKernelGGL(k_smooth3m<true>, grid1(tile_blocks(groups, cap)), dim3(kMarchBlock), 0, st, g, nstrip,
-                       nchunk, groups, lvl, bt, b, u_in, u_out, stride);
+    hipLaunchKernelGGL(k_smooth3m<true>, grid1(tile_blocks(groups, cap)), dim3(64 * kMarchWaves), 0, st, g, nstrip,
+                       nchunk, nyg, groups, lvl, bt, b, u_in, u_out, stride);
   else
-    hipLaunchKernelGGL(k_smooth3m<false>, grid1(tile_blocks(groups, cap)), dim3(kMarchBlock), 0, st, g, nstrip,
-                       nchunk, groups, lvl, bt, b, u_in, u_out, stride);
+    hipLaunchKernelGGL(k_smooth3m<false>, grid1(tile_blocks(groups, cap)), dim3(64 * kMarchWaves), 0, st, g, nstrip,
+                       nchunk, nyg, groups, lvl, bt, b, u_in, u_out, stride);
   return hipGetLastError();
 }
 
