@@ -84,9 +84,10 @@ constexpr int kShadowMax = 256;
 // buffers, v, two p^ buffers, s, two s^ buffers, t and two smoothing buffers).
 constexpr int kFineVectors = 13;
 
-// GMRES(m) per-slot small arrays (device): Hessenberg matrix column-major
-// H[slot][j*(m+1) + i], right-hand side g, rotations (cs, sn), solution y and the
-// two Gram-Schmidt coefficient vectors of the current column.
+// GMRES(m) per-slot small arrays (device): the Hessenberg matrix column-major
+// H[slot][j*(m+1) + i] (rotated) and Hu (as the Arnoldi process forms it),
+// right-hand side g, rotations (cs, sn), solution y and the current step's two
+// coefficient vectors (the second pass's s and the update's c).
 struct Gmres {
   double2* H;        // Hessenberg matrix after the Givens rotations, [slots][m][m+1] (column-major)
   double2* Hu;       // the Arnoldi coefficients themselves, the same layout

@@ -32,6 +32,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -49,12 +50,21 @@ CLASS_SYMBOL = {
 }
 
 
+def _code_only(text):
+    """C++ source without its comments and with whitespace runs collapsed
+    (string literals in these files hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """Hash of the kernel sources; a traffic measurement is valid for it only."""
+    """Hash of the kernel sources' code (comments and layout left out); a
+    traffic measurement is valid for it only."""
     h = hashlib.sha256()
     for f in ("hz_kernels.hip", "hz_stream.hip", "hz_krylov.hip", "hz_device.h", "hz_internal.h"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
