@@ -871,9 +871,12 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
              return tuned_launch(c, cy, 3, g, cap, [&](int ch) {
                return launch_post2(g, gc, l, bt, cap, ec, bll, dst, nl, c->lv[l + 1].n(), ch, st);
              });
+           if (dim == 3 && !g.rho && !cy.unfused)
+             // 3D: the marching sweep forms u + P e where it reads the iterate
+             return launch_march3(g, l, bt, cap, false, bll, u, dst, nl, st, &gc, ec, c->lv[l + 1].n());
            if (dim == 3) {
-             // 3D: u += P e in place (the pre-smoothed iterate is not needed after), then a plain
-             // sweep; the fused form interpolates at all seven stencil nodes of every node
+             // 3D with a density: u += P e in place (the pre-smoothed iterate is not needed
+             // after), then a sweep
              hipError_t e3 = launch_prolong(dim, g, gc, bt, cap, ec, u, u, nl, c->lv[l + 1].n(), st);
              if (e3 == hipSuccess) e3 = launch_smooth(dim, g, l, 0.0, bt, cap, bll, u, dst, nl, st);
              return e3;

@@ -176,9 +176,12 @@ hipError_t launch_apply(int dim, const Grid& g, int lvl, int which, const Batch&
 hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, const Batch& bt,
                          int cap, const double2* b, const double2* u_in, double2* u_out,
                          size_t stride, hipStream_t st);
-// 3D: one marching sweep from u_in, or (from_zero, u_in unused) two sweeps from u = 0
+// 3D: one marching sweep from u_in, or (from_zero, u_in unused) two sweeps from
+// u = 0, or (e given) one sweep from u_in + P e with e on the coarser level gc
+// (slot stride sc); constant density only
 hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool from_zero, const double2* b,
-                         const double2* u_in, double2* u_out, size_t stride, hipStream_t st);
+                         const double2* u_in, double2* u_out, size_t stride, hipStream_t st,
+                         const Grid* gc = nullptr, const double2* e = nullptr, size_t sc = 0);
 hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                            const double2* b, const double2* u, double2* bc, size_t sf,
                            size_t sc, hipStream_t st);

@@ -829,6 +829,12 @@ __global__ void __launch_bounds__(kBlock) k_smooth3(Grid g, Tiles t, int lvl, do
 // FROM_ZERO: the two sweeps from u = 0 in one pass. The first gives
 // u1 = (w/D) b, formed wherever the march reads u (u_in is not read), and the
 // pass stores the second sweep from u1.
+// PROLONG: the sweep starts from u_in + P e (e on the next coarser level gc,
+// trilinear P), formed wherever the march reads the iterate: once per node,
+// since the y-neighbour rows come through LDS (the block's edge wavefronts
+// also form it on their halo rows), with each coarse plane interpolated to
+// the row once and carried along the march. The prolongation then needs no
+// pass of its own, and the corrected iterate is never stored.
 // Shapes measured on the 129^3 benchmark box (step time): z-chunks of 4 to
 // 32 planes, 1 to 16 wavefronts per block, with and without the LDS rows;
 // 6 planes and 4 wavefronts sharing rows through LDS the fastest.
@@ -836,11 +842,13 @@ constexpr int kMarchW = 62;
 constexpr int kMarchZ = 6;      // even: the march takes two planes per step
 constexpr int kMarchWaves = 4;  // wavefronts (neighbouring y-rows) per block
 
-template <bool FROM_ZERO>
+template <bool FROM_ZERO, bool PROLONG>
 __global__ void __launch_bounds__(64 * kMarchWaves) k_smooth3m(Grid g, int nstrip, int nchunk, int nyg, int groups,
                                                                int lvl, Batch bt, const double2* __restrict__ b,
                                                                const double2* __restrict__ u_in,
-                                                               double2* __restrict__ u_out, size_t stride) {
+                                                               double2* __restrict__ u_out, size_t stride, Grid gc,
+                                                               const double2* __restrict__ e, size_t sc) {
+  static_assert(!(FROM_ZERO && PROLONG), "the prolongation corrects a given iterate");
   __shared__ double2 ysh[2][2][kMarchWaves + 2][64];  // [step parity][plane of the step][row slot][lane]
   int slot, grp;
   if (!decode_tile(bt, groups, slot, grp)) return;
@@ -874,11 +882,16 @@ __global__ void __launch_bounds__(64 * kMarchWaves) k_smooth3m(Grid g, int nstri
   const int hslot = wv == 0 ? 0 : kMarchWaves + 1;
   auto at_row = [&](int r, int z) { return (size_t)z * sz + (size_t)r * sy + xx; };
   auto at = [&](int z) { return at_row(iyc, z); };
-  auto uval = [&](size_t q) { return FROM_ZERO ? cmul(b[base + q], wd[q]) : us[q]; };
+  // the iterate the sweep starts from at node (z, r, xx) (PROLONG: without P e)
+  auto uval = [&](int r, int z) {
+    const size_t q = at_row(r, z);
+    if constexpr (FROM_ZERO) return cmul(b[base + q], wd[q]);
+    return us[q];
+  };
   // the iterate on plane z of the wavefront's row, zero outside the grid
-  auto plane = [&](int z) { return (row && z >= 0 && z < g.nz) ? keep(xin, uval(at(z))) : zero; };
+  auto plane = [&](int z) { return (row && z >= 0 && z < g.nz) ? keep(xin, uval(iyc, z)) : zero; };
   // the halo row's iterate on plane z (clamped into the grid: a second plane past it is not stored)
-  auto hval = [&](int z) { return halo ? uval(at_row(hr, min(z, g.nz - 1))) : zero; };
+  auto hval = [&](int z) { return halo ? uval(hr, min(z, g.nz - 1)) : zero; };
   struct Row {
     double2 uc, ul, ur, bz, wdz;
   };
@@ -901,9 +914,8 @@ __global__ void __launch_bounds__(64 * kMarchWaves) k_smooth3m(Grid g, int nstri
   };
   // the step's exchange: this row's iterate on planes z (p0) and z + 1 (p1)
   // and the halo row's go to LDS; the y-neighbours come back
-  auto exchange = [&](int z, double2 p0, double2 p1, Row& r0, Row& r1) {
+  auto exchange = [&](int z, double2 p0, double2 p1, double2 h0, double2 h1, Row& r0, Row& r1) {
     const int buf = ((z - z0) >> 1) & 1;
-    const double2 h0 = hval(z), h1 = hval(z + 1);
     ysh[buf][0][wv + 1][lane] = p0;
     ysh[buf][1][wv + 1][lane] = p1;
     if (edge) {
@@ -936,11 +948,54 @@ __global__ void __launch_bounds__(64 * kMarchWaves) k_smooth3m(Grid g, int nstri
       raw(z + 2, bq, wq);
       r0.uc = keep(xin, cmul(r1.bz, r1.wdz));
       r1.uc = keep(xin, cmul(bq, wq));
-      exchange(z, ub, r0.uc, r0, r1);
+      exchange(z, ub, r0.uc, hval(z), hval(z + 1), r0, r1);
       step(z, r0, ua, ub);
       step(z + 1, r1, ub, r0.uc);
       ua = r0.uc;
       ub = r1.uc;
+    }
+  } else if constexpr (PROLONG) {
+    // P e on fine plane z: the coarse plane z/2 (z even) or the mean of the
+    // coarse planes around it, each interpolated in y and x to the lane's
+    // node (the order of interp3); a coarse plane serves two steps, so it is
+    // formed once and carried
+    const double2* es = e + (size_t)slot * sc;
+    const int ox = xx & 1, Jx = xx >> 1, Jx1 = min(Jx + 1, gc.nx - 1);
+    auto cline = [&](int Z, int Y) {
+      const double2* r = es + ((size_t)Z * gc.ny + Y) * gc.nx;
+      return ox ? cscale(0.5, cadd(r[Jx], r[Jx1])) : r[Jx];
+    };
+    auto cplane = [&](int r, int Z) {  // coarse plane Z (clamped into the grid) at the lane's node of row r
+      Z = min(max(Z, 0), gc.nz - 1);
+      const int Y = r >> 1, Y1 = min(Y + 1, gc.ny - 1);
+      return (r & 1) ? cscale(0.5, cadd(cline(Z, Y), cline(Z, Y1))) : cline(Z, Y);
+    };
+    auto mean = [](double2 a, double2 c) { return cscale(0.5, cadd(a, c)); };
+    // u + P e on plane z of the wavefront's row, zero outside the grid
+    auto corrected = [&](int z, double2 pe) {
+      return (row && z >= 0 && z < g.nz) ? keep(xin, cadd(us[at(z)], pe)) : zero;
+    };
+    // the halo row's u + P e on plane z (clamped into the grid: a second plane past it is not stored)
+    auto hcorr = [&](int z, double2 pe) { return halo ? cadd(us[at_row(hr, min(z, g.nz - 1))], pe) : zero; };
+    const int Z0 = z0 >> 1;  // z0 is even
+    double2 cp = row ? cplane(iyc, Z0 - 1) : zero, cc = row ? cplane(iyc, Z0) : zero;
+    double2 hc = halo ? cplane(hr, Z0) : zero;
+    double2 ua = corrected(z0 - 1, mean(cp, cc)), ub = corrected(z0, cc);
+    for (int z = z0; z < z1; z += 2) {
+      const int Z = z >> 1;
+      const double2 cn = row ? cplane(iyc, Z + 1) : zero, hn = halo ? cplane(hr, Z + 1) : zero;
+      Row r0, r1;
+      r0.uc = corrected(z + 1, mean(cc, cn));
+      r1.uc = corrected(z + 2, cn);
+      centre(z, r0);
+      centre(z + 1, r1);
+      exchange(z, ub, r0.uc, hcorr(z, hc), hcorr(z + 1, mean(hc, hn)), r0, r1);
+      step(z, r0, ua, ub);
+      step(z + 1, r1, ub, r0.uc);
+      ua = r0.uc;
+      ub = r1.uc;
+      cc = cn;
+      hc = hn;
     }
   } else {
     double2 ua = plane(z0 - 1), ub = plane(z0);
@@ -950,7 +1005,7 @@ __global__ void __launch_bounds__(64 * kMarchWaves) k_smooth3m(Grid g, int nstri
       r1.uc = plane(z + 2);
       centre(z, r0);
       centre(z + 1, r1);
-      exchange(z, ub, r0.uc, r0, r1);
+      exchange(z, ub, r0.uc, hval(z), hval(z + 1), r0, r1);
       step(z, r0, ua, ub);
       step(z + 1, r1, ub, r0.uc);
       ua = r0.uc;
@@ -1152,18 +1207,27 @@ hipError_t launch_apply(int dim, const Grid& g, int lvl, int which, const Batch&
 
 // the marching 3D sweep (from u_in, or both sweeps from zero)
 hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool from_zero, const double2* b,
-                         const double2* u_in, double2* u_out, size_t stride, hipStream_t st) {
+                         const double2* u_in, double2* u_out, size_t stride, hipStream_t st, const Grid* gc,
+                         const double2* e, size_t sc) {
   if (cap <= 0) return hipSuccess;
   if (g.rho) return hipErrorInvalidValue;  // constant density only
+  if (e && (!gc || from_zero || !u_in || gc->nz != coarse_n(g.nz) || gc->ny != coarse_n(g.ny) ||
+            gc->nx != coarse_n(g.nx)))
+    return hipErrorInvalidValue;
   const int nstrip = (g.nx + kMarchW - 1) / kMarchW, nchunk = (g.nz + kMarchZ - 1) / kMarchZ;
   const int nyg = (g.ny + kMarchWaves - 1) / kMarchWaves;
   const int groups = nyg * nstrip * nchunk;
+  const dim3 gr = grid1(tile_blocks(groups, cap)), bl(64 * kMarchWaves);
+  const Grid gcc = e ? *gc : g;
   if (from_zero)
-    hipLaunchKernelGGL(k_smooth3m<true>, grid1(tile_blocks(groups, cap)), dim3(64 * kMarchWaves), 0, st, g, nstrip,
-                       nchunk, nyg, groups, lvl, bt, b, u_in, u_out, stride);
+    hipLaunchKernelGGL((k_smooth3m<true, false>), gr, bl, 0, st, g, nstrip, nchunk, nyg, groups, lvl, bt, b, u_in,
+                       u_out, stride, gcc, nullptr, (size_t)0);
+  else if (e)
+    hipLaunchKernelGGL((k_smooth3m<false, true>), gr, bl, 0, st, g, nstrip, nchunk, nyg, groups, lvl, bt, b, u_in,
+                       u_out, stride, gcc, e, sc);
   else
-    hipLaunchKernelGGL(k_smooth3m<false>, grid1(tile_blocks(groups, cap)), dim3(64 * kMarchWaves), 0, st, g, nstrip,
-                       nchunk, nyg, groups, lvl, bt, b, u_in, u_out, stride);
+    hipLaunchKernelGGL((k_smooth3m<false, false>), gr, bl, 0, st, g, nstrip, nchunk, nyg, groups, lvl, bt, b, u_in,
+                       u_out, stride, gcc, nullptr, (size_t)0);
   return hipGetLastError();
 }
 
