@@ -536,9 +536,9 @@ def bench_3d(args):
     z = 16
     # algorithmic bytes per right-hand side and iteration of the finest-level classes (two V-cycles;
     # the p and s updates are not timed)
-    cb = {"smooth": 2 * (2 + 3) * n0 * z,            # both pre-sweeps from zero: b / u; the last post-sweep: b, u / u
+    cb = {"smooth": 2 * 2 * n0 * z,                  # both pre-sweeps from zero: b / u
           "restrict": 2 * (2 * n0 * z + n1 * z),     # b, u / coarse b
-          "prolong": 2 * (3 * n0 * z + n1 * z),      # coarse e, b, u / u (with one post-sweep)
+          "prolong": 2 * (3 * n0 * z + n1 * z),      # coarse e, b, u / u (with both post-sweeps)
           "apply": 2 * n0 * z,                       # p^ / v
           "apply_s": 3 * n0 * z,                     # s^, s / t
           "update": 6 * n0 * z}                      # s, t / r; x every second iteration

@@ -863,10 +863,13 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
         return e;
       continue;
     }
-    // prolongation fused with the first post-sweep (2D: with the first two)
-    const int fused = (dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.unfused) ? 2 : 1;
+    // prolongation fused with the first post-sweep (2D, and 3D with a constant density: with
+    // the first two)
+    const bool post3 = dim == 3 && !g.rho && cy.nu2 >= 2 && !cy.unfused;
+    const int fused = ((dim == 2 && cy.nu1 == 2 && cy.nu2 >= 2 && !cy.unfused) || post3) ? 2 : 1;
     double2* dst = (cy.nu2 == fused) ? R : ((u == X) ? Y : X);
     if ((e = timed(c, l == 0 ? HZ_KERNEL_PROLONG : HZ_KERNEL_LEVELS, [&] {
+           if (post3) return launch_post3(g, gc, l, bt, cap, bll, u, ec, dst, nl, c->lv[l + 1].n(), st);
            if (fused == 2)
              return tuned_launch(c, cy, 3, g, cap, [&](int ch) {
                return launch_post2(g, gc, l, bt, cap, ec, bll, dst, nl, c->lv[l + 1].n(), ch, st);

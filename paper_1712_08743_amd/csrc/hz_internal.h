@@ -182,6 +182,11 @@ hipError_t launch_smooth(int dim, const Grid& g, int lvl, double w_override, con
 hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool from_zero, const double2* b,
                          const double2* u_in, double2* u_out, size_t stride, hipStream_t st,
                          const Grid* gc = nullptr, const double2* e = nullptr, size_t sc = 0);
+// 3D, constant density: u_out = two sweeps from u_in + P e (e on the coarser
+// level gc, slot stride sc) in one march; u_out must not be u_in
+hipError_t launch_post3(const Grid& g, const Grid& gc, int lvl, const Batch& bt, int cap, const double2* b,
+                        const double2* u_in, const double2* e, double2* u_out, size_t stride, size_t sc,
+                        hipStream_t st);
 hipError_t launch_restrict(int dim, const Grid& gf, const Grid& gc, const Batch& bt, int cap,
                            const double2* b, const double2* u, double2* bc, size_t sf,
                            size_t sc, hipStream_t st);

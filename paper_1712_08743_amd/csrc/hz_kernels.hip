@@ -1014,6 +1014,145 @@ __global__ void __launch_bounds__(64 * kMarchWaves) k_smooth3m(Grid g, int nstri
   }
 }
 
+// Prolongation and both post-sweeps of a 3D level in one march (nu2 >= 2,
+// constant density): u1 = sweep(u + P e) as k_smooth3m<false, true> forms
+// it, and u2 = sweep(u1) one plane behind; neither u + P e nor u1 is stored.
+// The second sweep needs the first on a ring of nodes around what it stores,
+// so the blocks overlap: a block of kPostWaves wavefronts runs the first
+// sweep on kPostWaves neighbouring y-rows and the second on the inner
+// kPostWaves - 2 of them; a wavefront owns kPostW + 4 columns, the first
+// sweep is right on all but its outer lanes and the second is stored on the
+// inner kPostW; a chunk of planes starts one step (two planes) early. The
+// first sweep's y-neighbours come through one LDS exchange per step (the
+// edge wavefronts also put the rows just outside the block there), the
+// second's through another; with two barriers per step one buffer of each
+// suffices. The arithmetic is k_smooth3m's.
+// Measured on the 129^3 benchmark box (step time): 8 wavefronts and 12 planes
+// 460 ms (16 planes 462, 8 planes 474; 6 or 16 wavefronts at 8 planes 550 and
+// 473), against 472 ms for the two sweeps as separate marches.
+constexpr int kPostW = 60;
+constexpr int kPostZ = 12;     // planes per chunk (even)
+constexpr int kPostWaves = 8;  // wavefronts (y-rows of the first sweep) per block
+
+__global__ void __launch_bounds__(64 * kPostWaves) k_post3m(Grid g, Grid gc, int nstrip, int nchunk, int nyg,
+                                                            int groups, int lvl, Batch bt,
+                                                            const double2* __restrict__ b,
+                                                            const double2* __restrict__ u_in,
+                                                            const double2* __restrict__ e,
+                                                            double2* __restrict__ u_out, size_t stride, size_t sc) {
+  __shared__ double2 ysh0[2][kPostWaves + 2][64];  // u + P e: [plane of the step][row slot][lane]
+  __shared__ double2 ysh1[2][kPostWaves][64];      // the first sweep
+  int slot, grp;
+  if (!decode_tile(bt, groups, slot, grp)) return;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+  const int yg = grp % nyg, rest = grp / nyg;
+  const int strip = rest % nstrip, chunk = rest / nstrip;
+  const int iy = yg * (kPostWaves - 2) - 1 + wv;  // this wavefront's row; the block stores rows of waves 1 .. W - 2
+  const bool row = iy >= 0 && iy < g.ny;
+  const int iyc = min(max(iy, 0), g.ny - 1);       // an address inside the grid for every wavefront
+  const bool inner = wv >= 1 && wv <= kPostWaves - 2;
+  const int lane = threadIdx.x % 64;
+  const int x = strip * kPostW - 2 + lane;
+  const bool xin = x >= 0 && x < g.nx;
+  const int xx = min(max(x, 0), g.nx - 1);
+  const bool own = lane >= 2 && lane <= kPostW + 1 && xin && row && inner;
+  const int z0 = chunk * kPostZ, z1 = min(g.nz, z0 + kPostZ);
+  const FreqTab& f = bt.ft[bt.slots[slot].freq];
+  const double2* wd = f.winv[lvl];
+  const double omw = 1.0 - f.wj[lvl];
+  const double ih2 = 1.0 / (g.h * g.h);
+  const size_t base = (size_t)slot * stride;
+  const double2* us = u_in + base;
+  const double2* es = e + (size_t)slot * sc;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const double wy = (iy == 0 || iy == g.ny - 1) ? 0.5 : 1.0, wx = (x == 0 || x == g.nx - 1) ? 0.5 : 1.0;
+  const double2 zero = c2(0.0, 0.0);
+  const bool edge = wv == 0 || wv == kPostWaves - 1;
+  const int hr = wv == 0 ? iy - 1 : iy + 1;
+  const bool halo = edge && hr >= 0 && hr < g.ny;
+  const int hslot = wv == 0 ? 0 : kPostWaves + 1;
+  auto at_row = [&](int r, int z) { return (size_t)z * sz + (size_t)r * sy + xx; };
+  auto inz = [&](int z) { return z >= 0 && z < g.nz; };
+  auto clz = [&](int z) { return min(max(z, 0), g.nz - 1); };
+  // P e (as k_smooth3m<false, true>: coarse planes interpolated to the row and carried)
+  const int ox = xx & 1, Jx = xx >> 1, Jx1 = min(Jx + 1, gc.nx - 1);
+  auto cline = [&](int Z, int Y) {
+    const double2* r = es + ((size_t)Z * gc.ny + Y) * gc.nx;
+    return ox ? cscale(0.5, cadd(r[Jx], r[Jx1])) : r[Jx];
+  };
+  auto cplane = [&](int r, int Z) {
+    Z = min(max(Z, 0), gc.nz - 1);
+    const int Y = r >> 1, Y1 = min(Y + 1, gc.ny - 1);
+    return (r & 1) ? cscale(0.5, cadd(cline(Z, Y), cline(Z, Y1))) : cline(Z, Y);
+  };
+  auto mean = [](double2 a, double2 c) { return cscale(0.5, cadd(a, c)); };
+  auto corrected = [&](int z, double2 pe) {
+    return (row && inz(z)) ? keep(xin, cadd(us[at_row(iyc, z)], pe)) : zero;
+  };
+  auto hcorr = [&](int z, double2 pe) { return halo ? cadd(us[at_row(hr, clz(z))], pe) : zero; };
+  // one sweep at plane z of the row from (ua, ub, uc) on planes z - 1, z, z + 1 and the y-neighbours
+  auto jac = [&](int z, double2 ua, double2 ub, double2 uc, double2 ul, double2 ur, double2 bz, double2 wdz) {
+    const double wz = (z == 0 || z == g.nz - 1) ? 0.5 : 1.0;
+    const double fz = wy * wx, fy = wz * wx, fx = wz * wy;
+    const double2 sxv = cadd(from_left(ub), from_right(ub));
+    const double2 syv = cadd(ul, ur);
+    const double2 szv = cadd(ua, uc);
+    const double tx = ih2 * (fz * szv.x + fy * syv.x + fx * sxv.x) + bz.x;
+    const double ty = ih2 * (fz * szv.y + fy * syv.y + fx * sxv.y) + bz.y;
+    return c2(omw * ub.x + (wdz.x * tx - wdz.y * ty), omw * ub.y + (wdz.x * ty + wdz.y * tx));
+  };
+  auto centre = [&](int z, double2& bz, double2& wdz) {
+    const bool in = row && inz(z);
+    const size_t q = at_row(iyc, clz(z));
+    bz = in ? b[base + q] : zero;
+    wdz = in ? wd[q] : zero;
+  };
+  const int zs = z0 - 2;  // the march starts a step early
+  const int Zs = zs >> 1;
+  double2 cc = row ? cplane(iyc, Zs) : zero, hc = halo ? cplane(hr, Zs) : zero;
+  double2 ua = corrected(zs - 1, mean(row ? cplane(iyc, Zs - 1) : zero, cc)), ub = corrected(zs, cc);
+  double2 v1a = zero, v1b = zero;  // the first sweep on planes z - 2, z - 1
+  double2 bp = zero, wp = zero;    // b and w/D on plane z - 1
+  for (int z = zs; z <= z1; z += 2) {
+    const int Z = z >> 1;
+    const double2 cn = row ? cplane(iyc, Z + 1) : zero, hn = halo ? cplane(hr, Z + 1) : zero;
+    const double2 u0c1 = corrected(z + 1, mean(cc, cn)), u0c2 = corrected(z + 2, cn);
+    double2 b0, w0, b1, w1;
+    centre(z, b0, w0);
+    centre(z + 1, b1, w1);
+    // the first sweep on planes z and z + 1
+    ysh0[0][wv + 1][lane] = ub;
+    ysh0[1][wv + 1][lane] = u0c1;
+    if (edge) {
+      ysh0[0][hslot][lane] = hcorr(z, hc);
+      ysh0[1][hslot][lane] = hcorr(z + 1, mean(hc, hn));
+    }
+    __syncthreads();
+    double2 u1z = jac(z, ua, ub, u0c1, ysh0[0][wv][lane], ysh0[0][wv + 2][lane], b0, w0);
+    double2 u1z1 = jac(z + 1, ub, u0c1, u0c2, ysh0[1][wv][lane], ysh0[1][wv + 2][lane], b1, w1);
+    u1z = (row && inz(z)) ? keep(xin, u1z) : zero;
+    u1z1 = (row && inz(z + 1)) ? keep(xin, u1z1) : zero;
+    // the second on planes z - 1 and z
+    ysh1[0][wv][lane] = v1b;
+    ysh1[1][wv][lane] = u1z;
+    __syncthreads();
+    if (inner) {
+      const double2 o0 = jac(z - 1, v1a, v1b, u1z, ysh1[0][wv - 1][lane], ysh1[0][wv + 1][lane], bp, wp);
+      const double2 o1 = jac(z, v1b, u1z, u1z1, ysh1[1][wv - 1][lane], ysh1[1][wv + 1][lane], b0, w0);
+      if (own && z - 1 >= z0 && z - 1 < z1) u_out[base + at_row(iyc, z - 1)] = o0;
+      if (own && z >= z0 && z < z1) u_out[base + at_row(iyc, z)] = o1;
+    }
+    ua = u0c1;
+    ub = u0c2;
+    v1a = u1z;
+    v1b = u1z1;
+    bp = b1;
+    wp = w1;
+    cc = cn;
+    hc = hn;
+  }
+}
+
 __global__ void k_winv3(Grid g, double omega, double s_re, double s_im, double w, double2* __restrict__ winv) {
   const size_t n = (size_t)g.nz * g.ny * g.nx;
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1228,6 +1367,20 @@ hipError_t launch_march3(const Grid& g, int lvl, const Batch& bt, int cap, bool 
   else
     hipLaunchKernelGGL((k_smooth3m<false, false>), gr, bl, 0, st, g, nstrip, nchunk, nyg, groups, lvl, bt, b, u_in,
                        u_out, stride, gcc, nullptr, (size_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_post3(const Grid& g, const Grid& gc, int lvl, const Batch& bt, int cap, const double2* b,
+                        const double2* u_in, const double2* e, double2* u_out, size_t stride, size_t sc,
+                        hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  if (g.rho || !u_in || !e || u_in == u_out) return hipErrorInvalidValue;  // constant density; u_out apart
+  if (gc.nz != coarse_n(g.nz) || gc.ny != coarse_n(g.ny) || gc.nx != coarse_n(g.nx)) return hipErrorInvalidValue;
+  const int nstrip = (g.nx + kPostW - 1) / kPostW, nchunk = (g.nz + kPostZ - 1) / kPostZ;
+  const int nyg = (g.ny + kPostWaves - 3) / (kPostWaves - 2);
+  const int groups = nyg * nstrip * nchunk;
+  hipLaunchKernelGGL(k_post3m, grid1(tile_blocks(groups, cap)), dim3(64 * kPostWaves), 0, st, g, gc, nstrip, nchunk,
+                     nyg, groups, lvl, bt, b, u_in, e, u_out, stride, sc);
   return hipGetLastError();
 }
 
