@@ -861,9 +861,10 @@ constexpr int kGmChunk = 1;  // basis vectors per pass over a tile
 constexpr int kGmDotNodes = kGmE * kBlock;
 constexpr int kWaves = kBlock / 64;
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_gm_dots2(Batch bt, int tiles, size_t n, Gmres gm, int j,
-                                                     const double2* __restrict__ V, size_t vstride,
-                                                     const double2* __restrict__ z, size_t stride) {
+// six waves per SIMD (74 VGPRs): the fastest of the 2 to 8 measured
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_gm_dots2(Batch bt, int tiles, size_t n, Gmres gm, int j, const double2* __restrict__ V, size_t vstride,
+           const double2* __restrict__ z, size_t stride) {
   extern __shared__ double wsum[];  // [kWaves][4j + 3]
   int slot, tile;
   if (!decode_vec(bt, tiles, slot, tile)) return;
