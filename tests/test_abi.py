@@ -140,3 +140,15 @@ def test_every_context_call_refuses_a_null_context():
         f = getattr(lib, name)
         f.argtypes, f.restype = argtypes, ctypes.c_int
         assert f(*args) == hz.HZ_ERR_ARG, name
+
+
+def test_traffic_hash_follows_the_code_not_its_comments():
+    """A stored HBM-traffic measurement stays valid across comment and layout
+    edits of the kernel sources, and not across a change of the code."""
+    from paper_1712_08743_amd import profiling
+    code = "__global__ void k(double* a) {\n  a[0] = 1.0;  // one\n}\n"
+    commented = "/* the kernel\n   sets one value */\n__global__ void k(double* a) {\n    a[0] = 1.0;\n}\n"
+    changed = "__global__ void k(double* a) {\n  a[0] = 2.0;  // one\n}\n"
+    assert profiling._code_only(code) == profiling._code_only(commented)
+    assert profiling._code_only(code) != profiling._code_only(changed)
+    assert len(profiling.kernel_source_hash()) == 16
