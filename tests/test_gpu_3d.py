@@ -110,12 +110,14 @@ def test_3d_smoother_restriction_prolongation(hz, shape, h):
 @pytest.mark.parametrize("shape,h,levels,nu", [((17, 17, 17), 40.0, 3, (2, 2)),
                                                ((16, 18, 20), 30.0, 2, (1, 1)),
                                                ((9, 12, 65), 20.0, 3, (2, 1)),
-                                               ((20, 22, 70), 20.0, 3, (2, 2))])
+                                               ((20, 22, 70), 20.0, 3, (2, 2)),
+                                               ((17, 13, 66), 20.0, 3, (1, 3))])
 def test_3d_vcycle(hz, shape, h, levels, nu):
     """One V-cycle against the oracle's: the marching sweeps on grids whose y
     rows do not fill the last block of four, whose z-planes end in a short
     chunk, with even node counts (the coarse grid ends a fine spacing short)
-    and more than one 62-column strip, the first post-sweep forming u + P e."""
+    and more than one 62-column strip, the first post-sweep forming u + P e
+    (or both post-sweeps in one march, then a third sweep of its own)."""
     import torch
     m = random_model(shape, 9)
     c = ctx_for(hz, m, h)
