@@ -111,21 +111,23 @@ def stats(trace_csv, between=None):
     return sorted(agg.items(), key=lambda kv: -kv[1][1])
 
 
-def counters(csv_path):
+def counters(csv_path, largest=False):
     """kernel symbol -> list of counter values (KiB per dispatch), over the
     dispatches with the symbol's most frequent grid size (a launch-shape
-    tuner's trial launches of other shapes are left out)."""
+    tuner's trial launches of other shapes are left out), or with its largest
+    grid size (largest: the finest level with the whole batch, where a
+    kernel also runs on the coarser levels)."""
     by = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in csv.DictReader(open(csv_path)):
         by[symbol(r["Kernel_Name"])][int(r["Grid_Size"])].append(float(r["Counter_Value"]))
     out = {}
     for sym, grids in by.items():
-        out[sym] = max(grids.values(), key=len)
+        out[sym] = grids[max(grids)] if largest else max(grids.values(), key=len)
     return out
 
 
-def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, rhs):
-    F, W = counters(fetch_csv), counters(write_csv)
+def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, rhs, largest=False):
+    F, W = counters(fetch_csv, largest), counters(write_csv, largest)
     cF, cW = counters(copy_fetch_csv), counters(copy_write_csv)
     cf = cF["hz::k_copy"]
     cw = cW["hz::k_copy"]
@@ -266,13 +268,14 @@ def _stats_md(trace_csv, command, between=None):
     return "\n".join(lines) + "\n"
 
 
-def _traffic_md(t, command, rhs):
+def _traffic_md(t, command, rhs, largest=False):
     lines = ["# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)", "",
              "Commands:", "", "```", command, "```", "",
              f"Counters are scaled by the library's copy kernel: FETCH_SIZE x {t['fetch_factor']:.4f}, "
-             f"WRITE_SIZE x {t['write_factor']:.4f} (bytes it moves / KiB the counter reads). "
-             f"Every dispatch carries {rhs} right-hand sides. Writes are counted when the L2 writes "
-             "them back, which can be during a later kernel.", "",
+             f"WRITE_SIZE x {t['write_factor']:.4f} (bytes it moves / KiB the counter reads). " +
+             (f"Per kernel the dispatches of its largest grid (the finest level), each carrying {rhs} "
+              "right-hand sides. " if largest else f"Every dispatch carries {rhs} right-hand sides. ") +
+             "Writes are counted when the L2 writes them back, which can be during a later kernel.", "",
              "| kernel | timing class | dispatches | read MB | write MB | read B/RHS/node | write B/RHS/node |",
              "|---|---|---:|---:|---:|---:|---:|"]
     n0 = t.get("nodes", 0)
@@ -303,6 +306,8 @@ def main():
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--rhs", type=int, required=True)
     b.add_argument("--nodes", type=int, default=0)
+    b.add_argument("--largest-grid", action="store_true",
+                   help="per kernel the dispatches with its largest grid (the finest level), not its most frequent")
     b.add_argument("--command", required=True)
     b.add_argument("--out")
     b.add_argument("--json")
@@ -337,9 +342,10 @@ def main():
         if args.stats_csv:
             text += _whole_run_md(args.stats_csv)
     else:
-        t = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes, args.rhs)
+        t = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes, args.rhs,
+                    args.largest_grid)
         t["nodes"] = args.nodes
-        text = _traffic_md(t, args.command, args.rhs)
+        text = _traffic_md(t, args.command, args.rhs, args.largest_grid)
         if args.json:
             per_class = {}
             for k in CLASS_SYMBOL:
