@@ -60,12 +60,15 @@ def bytes_per_iteration(sizes):
     sides and read from cache). The benchmark's right-hand sides are point
     sources, so the shadow residual r^ = b is held as a one-entry list and
     the inner products with it stream no vector; v = B p^ is then never
-    stored (the pre-smoothing kernels form it from p^). The iterate x is
-    advanced every second iteration (with both iterations' p^ and s^)."""
+    stored (the pre-smoothing kernels form it from p^), nor t = B s^ (the
+    dot-product pass and the update each form it from s^). The iterate x
+    is advanced every second iteration (with both iterations' p^ and s^;
+    the current s^ is already read for t)."""
     z = 16
     n0 = sizes[0]
     total = n0 * z * (4 + 3)        # p and s updates (B p^ formed in the kernel) fused with the pre-sweeps
-    total += n0 * z * (3 + 6)       # B s^ (with dots), r update (+ x every second iteration)
+    total += n0 * z * 2             # <B s^, s>, <B s^, B s^>: reads s^, s
+    total += n0 * z * 11 // 2       # r = s - omega B s^ (s^, s / r), x every second iteration (x, ph, ph0, sh0 / x)
     for l, n in enumerate(sizes[:-1]):
         nc = sizes[l + 1]
         per_cycle = nc * z                      # restricted residual
@@ -88,10 +91,10 @@ def class_bytes_per_iteration(sizes):
         "presmooth_s": n0 * z * 3 + n1 * z,     # reads r, p^; writes s; coarse right-hand side
         "prolong": 2 * (n0 * z * 2 + n1 * z),   # reads b, coarse e; writes u (two V-cycles)
         "apply": n0 * z * 2,                    # reads p^, r^ (only while some r^ is dense)
-        "apply_s": n0 * z * 3,                  # reads s^, s; writes t
-        # r = s - omega t every iteration (reads s, t; writes r), x every second one
-        # (reads x, two p^, two s^; writes x): 6 vectors per iteration on average
-        "update": n0 * z * 6,
+        "apply_s": n0 * z * 2,                  # reads s^, s (t = B s^ is not stored)
+        # r = s - omega B s^ every iteration (reads s^, s; writes r), x every second
+        # one (reads x, two p^, the other s^; writes x): 5.5 vectors per iteration
+        "update": n0 * z * 11 // 2,
     }
 
 

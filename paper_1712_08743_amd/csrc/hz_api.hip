@@ -1019,17 +1019,20 @@ struct BicgIter {
         if ((e = launch_bicg_s(n0, bt, capx, r, v, s, n0, sx)) != hipSuccess) break;
         if (!identity && (e = precond_apply(c, cy, capx, s, sh)) != hipSuccess) break;
       }
+      // 2D fused path: t = B s^ is not stored; the update forms it again from s^
       if ((e = timed(c, HZ_KERNEL_APPLY_S, [&] {
-             return launch_bicg_apply_omega(c->dim, g0, bt, capx, rd, sh, s, t, n0, sx);
+             return launch_bicg_apply_omega(c->dim, g0, bt, capx, rd, sh, s, vfree ? nullptr : t, n0, sx);
            })) != hipSuccess)
         break;
       if ((e = launch_bicg_fin(kFinOmega, gt, bt, capx, rd, o->tol, o->maxit, nullptr, n0, sx)) != hipSuccess)
         break;
       if ((e = timed(c, HZ_KERNEL_UPDATE, [&] {
-             return launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx, rg, phr[0], shr[0]);
+             return vfree ? launch_bicg_xr_t(g0, bt, capx, rd, x, ph, sh, s, r, rh, n0, sx, rg, phr[0], shr[0])
+                          : launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx, rg, phr[0], shr[0]);
            })) != hipSuccess)
         break;
-      e = launch_bicg_fin(kFinStep, vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx, rg, o->restart_at);
+      e = launch_bicg_fin(kFinStep, vfree ? gt : vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx, rg,
+                          o->restart_at);
     } while (false);
     c->stream = saved;
     return e;

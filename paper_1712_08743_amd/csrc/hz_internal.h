@@ -253,6 +253,7 @@ hipError_t launch_bicg_apply_sigma(int dim, const Grid& g, const Batch& bt, int 
                                    double2* v, size_t stride, hipStream_t st);
 hipError_t launch_bicg_s(size_t n, const Batch& bt, int cap, const double2* r, const double2* v,
                          double2* s, size_t stride, hipStream_t st);
+// t null (2D only): no store, only the partials <t, s>, <t, t>.
 hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int cap,
                                    const Reduce& rd, const double2* sh, const double2* s,
                                    double2* t, size_t stride, hipStream_t st);
@@ -263,6 +264,12 @@ hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, 
                           const double2* ph, const double2* sh, const double2* s, const double2* t,
                           double2* r, const double2* rh, size_t stride, hipStream_t st, int ring = -1,
                           const double2* ph0 = nullptr, const double2* sh0 = nullptr);
+// The same update on a 2D grid with t = B sh formed from sh (no stored t; the
+// partials per LDS tile, reduce_tiles(nz, nx, 2) of them per slot).
+hipError_t launch_bicg_xr_t(const Grid& g, const Batch& bt, int cap, const Reduce& rd, double2* x,
+                            const double2* ph, const double2* sh, const double2* s, double2* r,
+                            const double2* rh, size_t stride, hipStream_t st, int ring, const double2* ph0,
+                            const double2* sh0);
 // Adds the pending term to x (all nslots slots, or only those about to restart).
 // (slots slot0 .. slot0 + nslots - 1)
 hipError_t launch_bicg_flush(size_t n, int nslots, const Batch& bt, int only_restart, double2* x,

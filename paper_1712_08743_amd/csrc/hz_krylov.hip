@@ -105,11 +105,37 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
   store_partial<2>(acc, rd, slot, tile);
 }
 
+// (B x) at grid node (iz, ix) = p of a 2D grid (slowness mp), with x staged
+// in the LDS tile X (the node at tile position (lz, lx)). RHO: with a density
+// (Eq. (1)), the couplings from the level's table (Grid::dc). Both kernels
+// that apply B to s^ call it, so they form the same values.
+template <bool RHO>
+__device__ __forceinline__ double2 apply_b_tile(const Grid& g, const FreqTab& f, const double2 (*X)[kHX], int lz,
+                                                int lx, int iz, int ix, int p, double mp, double ih, double ih2) {
+  if (RHO) {
+    const size_t n = (size_t)g.nz * g.nx;
+    RhoC rc;
+    rc.l = ix > 0 ? g.dc[p - 1] : 0.0;
+    rc.r = g.dc[p];
+    rc.u = iz > 0 ? g.dc[n + p - g.nx] : 0.0;
+    rc.d = g.dc[n + p];
+    const double wxz = ((ix == 0 || ix == g.nx - 1) ? 0.5 : 1.0) * ((iz == 0 || iz == g.nz - 1) ? 0.5 : 1.0);
+    const double om2 = f.omega * f.omega;
+    return apply_m_rho(rc, g.dc[2 * n + p], wxz, mp, -om2 * f.sB_re, -om2 * f.sB_im, f.omega * ih, ih2,
+                       X[lz + 1][lx + 1], X[lz + 1][lx], X[lz + 1][lx + 2], X[lz][lx + 1], X[lz + 2][lx + 1]);
+  }
+  const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, mp, f.omega, f.sB_re, f.sB_im);
+  double2 sx, sz;
+  halo_sums(X, lz, lx, sx, sz);
+  return stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
+}
+
 // LDS-tiled forms (2D): x staged on the tile and its halo, two nodes per thread.
 // WHICH 0: v = B ph, partial <rh, v>; WHICH 1: t = B sh, partials <t, s>, <t, t>.
-// WHICH 0 with y null stores nothing and serves only the slots whose r^ is
-// dense (the others leave at once): their partial <rh, B ph>. RHO: with a
-// density (Eq. (1)), the couplings from the level's table (Grid::dc).
+// With y null nothing is stored: WHICH 0 then serves only the slots whose r^
+// is dense (the others leave at once) with their partial <rh, B ph>; WHICH 1
+// forms only the partials (k_bicg_xr_t forms t again). RHO: with a density
+// (Eq. (1)), the couplings from the level's table (Grid::dc).
 template <int WHICH, bool RHO>
 __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int per_slot, Batch bt, Reduce rd,
                                                          const double2* __restrict__ xin,
@@ -122,12 +148,25 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
   const FreqTab& f = bt.ft[bt.slots[slot].freq];
   const TileOrg t = tile_org(tile, ntx);
   const size_t base = (size_t)slot * stride;
+  // WHICH 0 with a sparse r^: <rh, v> is formed from the list by the reduction kernel
+  const bool dots = WHICH == 1 || bt.slots[slot].rh_nnz < 0;
+  // the thread's own nodes' inputs are loaded before the halo fill and its
+  // barrier, so that their latency overlaps the fill's
+  double2 ov[kRowsPerThread];
+  double mv[kRowsPerThread];
+  const double* m = model_m(g, f);
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) {
+    const int iz = t.z0 + threadIdx.x / kTX + (kBlock / kTX) * r, ix = t.x0 + threadIdx.x % kTX;
+    const bool in = iz < g.nz && ix < g.nx;
+    const int p = in ? iz * g.nx + ix : 0;
+    ov[r] = in && dots ? other[base + p] : c2(0.0, 0.0);
+    mv[r] = in ? m[p] : 0.0;
+  }
   const double2* xs = xin + base;
   fill_halo(X, g, t, [&](int q, int, int) { return xs[q]; });
   __syncthreads();
   const double ih = 1.0 / g.h, ih2 = ih * ih;
-  // WHICH 0 with a sparse r^: <rh, v> is formed from the list by the reduction kernel
-  const bool dots = WHICH == 1 || bt.slots[slot].rh_nnz < 0;
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < kRowsPerThread; ++r) {
@@ -135,33 +174,16 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= g.nz || ix >= g.nx) continue;
     const int p = iz * g.nx + ix;
-    double2 yp;
-    if (RHO) {
-      const size_t n = (size_t)g.nz * g.nx;
-      RhoC rc;
-      rc.l = ix > 0 ? g.dc[p - 1] : 0.0;
-      rc.r = g.dc[p];
-      rc.u = iz > 0 ? g.dc[n + p - g.nx] : 0.0;
-      rc.d = g.dc[n + p];
-      const double wxz = ((ix == 0 || ix == g.nx - 1) ? 0.5 : 1.0) * ((iz == 0 || iz == g.nz - 1) ? 0.5 : 1.0);
-      const double om2 = f.omega * f.omega;
-      yp = apply_m_rho(rc, g.dc[2 * n + p], wxz, model_m(g, f)[p], -om2 * f.sB_re, -om2 * f.sB_im, f.omega * ih,
-                       ih2, X[lz + 1][lx + 1], X[lz + 1][lx], X[lz + 1][lx + 2], X[lz][lx + 1], X[lz + 2][lx + 1]);
-    } else {
-      const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
-      double2 sx, sz;
-      halo_sums(X, lz, lx, sx, sz);
-      yp = stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
-    }
-    if (WHICH == 1 || y) st_nt(y + base + p, yp);
+    const double2 yp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, p, mv[r], ih, ih2);
+    if (y) st_nt(y + base + p, yp);
     if (WHICH == 0) {
       if (dots) {
-        const double2 d = cconjmul(other[base + p], yp);
+        const double2 d = cconjmul(ov[r], yp);
         acc[0] += d.x;
         acc[1] += d.y;
       }
     } else {
-      const double2 d = cconjmul(yp, other[base + p]);
+      const double2 d = cconjmul(yp, ov[r]);
       acc[0] += d.x;
       acc[1] += d.y;
       acc[2] += yp.x * yp.x + yp.y * yp.y;
@@ -319,6 +341,79 @@ k_bicg_xr(Batch bt, int tiles, size_t n, Reduce rd, double2* __restrict__ x, con
              pend ? ph0[q] : zero, pend ? sh0[q] : zero, s[q], t[q], dense_rh ? rh[q] : zero);
       }
     }
+  }
+  store_partial<3>(acc, rd, slot, tile);
+}
+
+// The update of k_bicg_xr on a 2D grid with t = B s^ formed here from an LDS
+// copy of s^ and its halo (the stencil of k_bicg_apply_t, which then stores
+// no t): r = s - omega t, x as in k_bicg_xr (XMODE), the partials <rh, r>,
+// <r, r> per tile of the LDS-staged kernels. s^ at the node comes from the
+// tile, so t costs no HBM traffic of its own: per node s^, s / r (and x,
+// ph, ph0, sh0 / x in ring 1) instead of s, t / r and s^ again.
+template <int XMODE, bool RHO>
+__global__ void __launch_bounds__(kBlock) k_bicg_xr_t(Grid g, int ntx, int per_slot, Batch bt, Reduce rd,
+                                                      double2* __restrict__ x, const double2* __restrict__ ph,
+                                                      const double2* __restrict__ sh,
+                                                      const double2* __restrict__ ph0,
+                                                      const double2* __restrict__ sh0,
+                                                      const double2* __restrict__ s, double2* __restrict__ r,
+                                                      const double2* __restrict__ rh, size_t stride) {
+  __shared__ double2 X[kHZ][kHX];
+  int slot, tile;
+  if (!decode_tile(bt, per_slot, slot, tile)) return;
+  const Slot& S0 = bt.slots[slot];
+  const FreqTab& f = bt.ft[S0.freq];
+  const double2 al = S0.alpha, om = S0.omega;
+  const double2 al0 = S0.pend_alpha, om0 = S0.pend_omega;
+  const bool pend = XMODE == 1 && S0.pending;
+  const bool dense_rh = S0.rh_nnz < 0;  // else <rh, r> is formed from the sparse list
+  const TileOrg t = tile_org(tile, ntx);
+  const size_t base = (size_t)slot * stride;
+  // the thread's own nodes' inputs are loaded before the halo fill and its
+  // barrier, so that their latency overlaps the fill's
+  const double2 zero = c2(0.0, 0.0);
+  double2 S[kRowsPerThread], XV[kRowsPerThread], PH[kRowsPerThread], P0[kRowsPerThread], S0v[kRowsPerThread],
+      RH[kRowsPerThread];
+  double mv[kRowsPerThread];
+  const double* m = model_m(g, f);
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int iz = t.z0 + threadIdx.x / kTX + (kBlock / kTX) * k, ix = t.x0 + threadIdx.x % kTX;
+    const bool in = iz < g.nz && ix < g.nx;
+    const size_t q = base + (in ? iz * g.nx + ix : 0);
+    S[k] = in ? ld_nt(s + q) : zero;
+    XV[k] = in && XMODE != 0 ? ld_nt(x + q) : zero;
+    PH[k] = in && XMODE != 0 ? ld_nt(ph + q) : zero;
+    P0[k] = in && pend ? ld_nt(ph0 + q) : zero;
+    S0v[k] = in && pend ? ld_nt(sh0 + q) : zero;
+    RH[k] = in && dense_rh ? ld_nt(rh + q) : zero;
+    mv[k] = in ? m[q - base] : 0.0;
+  }
+  const double2* shs = sh + base;
+  fill_halo(X, g, t, [&](int q, int, int) { return shs[q]; });
+  __syncthreads();
+  const double ih = 1.0 / g.h, ih2 = ih * ih;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int lz = threadIdx.x / kTX + (kBlock / kTX) * k, lx = threadIdx.x % kTX;
+    const int iz = t.z0 + lz, ix = t.x0 + lx;
+    if (iz >= g.nz || ix >= g.nx) continue;
+    const int p = iz * g.nx + ix;
+    const size_t q = base + p;
+    const double2 tp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, p, mv[k], ih, ih2);
+    const double2 ri = csub(S[k], cmul(om, tp));
+    st_nt(r + q, ri);
+    if (XMODE != 0) {
+      double2 dx = cadd(cmul(al, PH[k]), cmul(om, X[lz + 1][lx + 1]));
+      if (pend) dx = cadd(cadd(cmul(al0, P0[k]), cmul(om0, S0v[k])), dx);
+      st_nt(x + q, cadd(XV[k], dx));
+    }
+    const double2 d = cconjmul(RH[k], ri);
+    acc[0] += d.x;
+    acc[1] += d.y;
+    acc[2] += ri.x * ri.x + ri.y * ri.y;
   }
   store_partial<3>(acc, rd, slot, tile);
 }
@@ -1257,6 +1352,7 @@ hipError_t launch_bicg_apply_omega(int dim, const Grid& g, const Batch& bt, int 
                                    const Reduce& rd, const double2* sh, const double2* s,
                                    double2* t, size_t stride, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  if (!t && dim != 2) return hipErrorInvalidValue;
   if (dim == 3) {
     const Tiles t3 = grid_tiles(g.nz * g.ny, g.nx, 3);
     hipLaunchKernelGGL(k_bicg_apply3<1>, grid1(tile_blocks(t3.per_slot, cap)), dim3(kBlock), 0, st, g, t3, bt, rd,
@@ -1296,6 +1392,31 @@ hipError_t launch_bicg_xr(size_t n, const Batch& bt, int cap, const Reduce& rd, 
   else
     hipLaunchKernelGGL(k_bicg_xr<1>, gr, dim3(kBlock), 0, st, bt, tiles, n, rd, x, ph, sh, ph0, sh0, s, t, r, rh,
                        stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_xr_t(const Grid& g, const Batch& bt, int cap, const Reduce& rd, double2* x,
+                            const double2* ph, const double2* sh, const double2* s, double2* r,
+                            const double2* rh, size_t stride, hipStream_t st, int ring, const double2* ph0,
+                            const double2* sh0) {
+  if (cap <= 0) return hipSuccess;
+  if (ring == 1 && (!ph0 || !sh0)) return hipErrorInvalidValue;
+  if (g.rho && !g.dc) return hipErrorInvalidValue;  // a density needs the level's coupling table
+  if (stride < (size_t)g.nz * g.nx || ring < -1 || ring > 1) return hipErrorInvalidValue;
+  const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
+  const dim3 gr = grid1(tile_blocks(per, cap));
+#define HZ_XR_T(XM, RH)                                                                                          \
+  hipLaunchKernelGGL((k_bicg_xr_t<XM, RH>), gr, dim3(kBlock), 0, st, g, ntx, per, bt, rd, x, ph, sh, ph0, sh0, s, \
+                     r, rh, stride)
+  const bool dc = g.dc != nullptr;
+  if (ring < 0) {
+    if (dc) HZ_XR_T(-1, true); else HZ_XR_T(-1, false);
+  } else if (ring == 0) {
+    if (dc) HZ_XR_T(0, true); else HZ_XR_T(0, false);
+  } else {
+    if (dc) HZ_XR_T(1, true); else HZ_XR_T(1, false);
+  }
+#undef HZ_XR_T
   return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ CLASS_SYMBOL = {
     "prolong": "hz::k_post2_s<true, false>",
     "apply": "hz::k_bicg_apply_t<0, false>",
     "apply_s": "hz::k_bicg_apply_t<1, false>",
-    "update": ("hz::k_bicg_xr<0>", "hz::k_bicg_xr<1>"),
+    "update": ("hz::k_bicg_xr_t<0, false>", "hz::k_bicg_xr_t<1, false>"),
     "coarse": "hz::k_coarse",
 }
 
