@@ -105,29 +105,47 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_sigma(Grid g, Tiles t, Ba
   store_partial<2>(acc, rd, slot, tile);
 }
 
-// (B x) at grid node (iz, ix) = p of a 2D grid (slowness mp), with x staged
-// in the LDS tile X (the node at tile position (lz, lx)). RHO: with a density
-// (Eq. (1)), the couplings from the level's table (Grid::dc). Both kernels
-// that apply B to s^ call it, so they form the same values.
+// The per-node coefficients of B at grid node (iz, ix) = p of a 2D grid
+// that do not depend on the right-hand side: the slowness and, with a
+// density (RHO, Eq. (1)), the couplings and g sqrt(rho) from the level's
+// table (Grid::dc). Loaded apart from the stencil so that a kernel can issue
+// these loads before its LDS fill and barrier.
+struct TileCoef {
+  double m;
+  RhoC rc;
+  double gb;
+};
 template <bool RHO>
-__device__ __forceinline__ double2 apply_b_tile(const Grid& g, const FreqTab& f, const double2 (*X)[kHX], int lz,
-                                                int lx, int iz, int ix, int p, double mp, double ih, double ih2) {
+__device__ __forceinline__ TileCoef tile_coef(const Grid& g, const double* m, int iz, int ix, int p) {
+  TileCoef c;
+  c.m = m[p];
   if (RHO) {
     const size_t n = (size_t)g.nz * g.nx;
-    RhoC rc;
-    rc.l = ix > 0 ? g.dc[p - 1] : 0.0;
-    rc.r = g.dc[p];
-    rc.u = iz > 0 ? g.dc[n + p - g.nx] : 0.0;
-    rc.d = g.dc[n + p];
+    c.rc.l = ix > 0 ? g.dc[p - 1] : 0.0;
+    c.rc.r = g.dc[p];
+    c.rc.u = iz > 0 ? g.dc[n + p - g.nx] : 0.0;
+    c.rc.d = g.dc[n + p];
+    c.gb = g.dc[2 * n + p];
+  }
+  return c;
+}
+
+// (B x) at grid node (iz, ix) with coefficients c, x staged in the LDS tile X
+// (the node at tile position (lz, lx)). Both kernels that apply B to s^ call
+// it, so they form the same values.
+template <bool RHO>
+__device__ __forceinline__ double2 apply_b_tile(const Grid& g, const FreqTab& f, const double2 (*X)[kHX], int lz,
+                                                int lx, int iz, int ix, const TileCoef& c, double ih, double ih2) {
+  if (RHO) {
     const double wxz = ((ix == 0 || ix == g.nx - 1) ? 0.5 : 1.0) * ((iz == 0 || iz == g.nz - 1) ? 0.5 : 1.0);
     const double om2 = f.omega * f.omega;
-    return apply_m_rho(rc, g.dc[2 * n + p], wxz, mp, -om2 * f.sB_re, -om2 * f.sB_im, f.omega * ih, ih2,
-                       X[lz + 1][lx + 1], X[lz + 1][lx], X[lz + 1][lx + 2], X[lz][lx + 1], X[lz + 2][lx + 1]);
+    return apply_m_rho(c.rc, c.gb, wxz, c.m, -om2 * f.sB_re, -om2 * f.sB_im, f.omega * ih, ih2, X[lz + 1][lx + 1],
+                       X[lz + 1][lx], X[lz + 1][lx + 2], X[lz][lx + 1], X[lz + 2][lx + 1]);
   }
-  const NodeC c = node_coef<true>(iz, ix, g.nz, g.nx, ih, mp, f.omega, f.sB_re, f.sB_im);
+  const NodeC nc = node_coef<true>(iz, ix, g.nz, g.nx, ih, c.m, f.omega, f.sB_re, f.sB_im);
   double2 sx, sz;
   halo_sums(X, lz, lx, sx, sz);
-  return stencil(c, ih2, X[lz + 1][lx + 1], sx, sz);
+  return stencil(nc, ih2, X[lz + 1][lx + 1], sx, sz);
 }
 
 // LDS-tiled forms (2D): x staged on the tile and its halo, two nodes per thread.
@@ -153,7 +171,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
   // the thread's own nodes' inputs are loaded before the halo fill and its
   // barrier, so that their latency overlaps the fill's
   double2 ov[kRowsPerThread];
-  double mv[kRowsPerThread];
+  TileCoef cv[kRowsPerThread];
   const double* m = model_m(g, f);
 #pragma unroll
   for (int r = 0; r < kRowsPerThread; ++r) {
@@ -161,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     const bool in = iz < g.nz && ix < g.nx;
     const int p = in ? iz * g.nx + ix : 0;
     ov[r] = in && dots ? other[base + p] : c2(0.0, 0.0);
-    mv[r] = in ? m[p] : 0.0;
+    cv[r] = tile_coef<RHO>(g, m, in ? iz : 0, in ? ix : 0, p);
   }
   const double2* xs = xin + base;
   fill_halo(X, g, t, [&](int q, int, int) { return xs[q]; });
@@ -174,7 +192,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= g.nz || ix >= g.nx) continue;
     const int p = iz * g.nx + ix;
-    const double2 yp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, p, mv[r], ih, ih2);
+    const double2 yp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, cv[r], ih, ih2);
     if (y) st_nt(y + base + p, yp);
     if (WHICH == 0) {
       if (dots) {
@@ -375,20 +393,21 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr_t(Grid g, int ntx, int per_s
   const double2 zero = c2(0.0, 0.0);
   double2 S[kRowsPerThread], XV[kRowsPerThread], PH[kRowsPerThread], P0[kRowsPerThread], S0v[kRowsPerThread],
       RH[kRowsPerThread];
-  double mv[kRowsPerThread];
+  TileCoef cv[kRowsPerThread];
   const double* m = model_m(g, f);
 #pragma unroll
   for (int k = 0; k < kRowsPerThread; ++k) {
     const int iz = t.z0 + threadIdx.x / kTX + (kBlock / kTX) * k, ix = t.x0 + threadIdx.x % kTX;
     const bool in = iz < g.nz && ix < g.nx;
-    const size_t q = base + (in ? iz * g.nx + ix : 0);
+    const int p = in ? iz * g.nx + ix : 0;
+    const size_t q = base + p;
     S[k] = in ? ld_nt(s + q) : zero;
     XV[k] = in && XMODE != 0 ? ld_nt(x + q) : zero;
     PH[k] = in && XMODE != 0 ? ld_nt(ph + q) : zero;
     P0[k] = in && pend ? ld_nt(ph0 + q) : zero;
     S0v[k] = in && pend ? ld_nt(sh0 + q) : zero;
     RH[k] = in && dense_rh ? ld_nt(rh + q) : zero;
-    mv[k] = in ? m[q - base] : 0.0;
+    cv[k] = tile_coef<RHO>(g, m, in ? iz : 0, in ? ix : 0, p);
   }
   const double2* shs = sh + base;
   fill_halo(X, g, t, [&](int q, int, int) { return shs[q]; });
@@ -402,7 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr_t(Grid g, int ntx, int per_s
     if (iz >= g.nz || ix >= g.nx) continue;
     const int p = iz * g.nx + ix;
     const size_t q = base + p;
-    const double2 tp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, p, mv[k], ih, ih2);
+    const double2 tp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, cv[k], ih, ih2);
     const double2 ri = csub(S[k], cmul(om, tp));
     st_nt(r + q, ri);
     if (XMODE != 0) {
