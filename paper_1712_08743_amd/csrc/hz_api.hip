@@ -140,8 +140,11 @@ struct hz_ctx {
   int has_rho = 0;  // a density of Eq. (1) is set
   LevelInfo lv[kMaxLevels];
   int model_version = 0;
-  // solver workspace
+  // solver workspace (the finest-level vectors hold fine_nodes() nodes per slot)
   DevBuf fine[kNumFine];
+  // > 0 while a fused 2D BiCGSTAB solve runs with pitched finest-level vectors:
+  // their row pitch (grid_of(c, 0) and level_stride(c, 0) follow it)
+  int fine_px = 0;
   DevBuf lev[kMaxLevels][kNumLevelVec];
   int ws_slots = 0, ws_levels = 0;
   DevBuf slots, active, nactive, freqtab, partials, resid, fstart;
@@ -227,7 +230,13 @@ Grid grid_of(const hz_ctx* c, int l) {
   g.mstride = c->lv[l].mstride;
   g.rho = c->has_rho ? c->lv[l].rho.as<double>() : nullptr;
   g.dc = (c->has_rho && c->dim == 2) ? c->lv[l].dc.as<double>() : nullptr;
+  if (l == 0) g.px = c->fine_px;
   return g;
+}
+
+// the slot stride of level l's vectors (the finest level's rows may be pitched)
+size_t level_stride(const hz_ctx* c, int l) {
+  return (l == 0 && c->fine_px > 0) ? (size_t)c->lv[0].nz * c->fine_px : c->lv[l].n();
 }
 
 // Local Fourier analysis of damped Jacobi on h^2 M: for a mode with Laplacian
@@ -418,7 +427,7 @@ int check_opts(hz_ctx* c, const hz_solve_opts* o) {
 
 // ---------------------------------------------------------------- workspace
 int ensure_workspace(hz_ctx* c, int nslots, int levels) {
-  const size_t n0 = c->lv[0].n();
+  const size_t n0 = fine_nodes(c->dim, c->lv[0].nz, c->lv[0].ny, c->lv[0].nx);
   size_t total = 0;
   total += (size_t)kNumFine * nslots * n0 * sizeof(double2);
   for (int l = 1; l < levels; ++l) total += (size_t)kNumLevelVec * nslots * c->lv[l].n() * sizeof(double2);
@@ -757,7 +766,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   double2* cur[kMaxLevels];
   for (int l = 0; l < ldesc; ++l) {
     const Grid g = grid_of(c, l);
-    const size_t nl = c->lv[l].n();
+    const size_t nl = level_stride(c, l);
     double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
     double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
     double2* u = nullptr;
@@ -849,7 +858,7 @@ hipError_t precond_apply(hz_ctx* c, const Cycle& cy, int cap, const double2* b0,
   for (int l = ldesc - 1; l >= 0; --l) {
     const Grid g = grid_of(c, l);
     const Grid gc = grid_of(c, l + 1);
-    const size_t nl = c->lv[l].n();
+    const size_t nl = level_stride(c, l);
     double2* X = l == 0 ? c->fine[kT1].as<double2>() : c->lev[l][kLx].as<double2>();
     double2* Y = l == 0 ? c->fine[kT2].as<double2>() : c->lev[l][kLy].as<double2>();
     double2* R = l == 0 ? out : c->lev[l][kLu].as<double2>();
@@ -915,10 +924,23 @@ struct BicgIter {
   double2 *phr[2], *shr[2], *ph, *sh;
   bool identity, fused, vfree, defer;
   bool dense_rh = false;  // some active slot's r^ is a dense vector
+  // pitched: the finest-level vectors, the iterate and a copy of b have rows
+  // of pitch c->fine_px (the caller's b and x stay [nz][nx])
+  bool pitched = false;
+  double2 *xp = nullptr, *bp = nullptr;
   int vt, gt;
 
-  BicgIter(hz_ctx* cc, const hz_solve_opts* oo, const Cycle& cyy, double2* xx) : c(cc), o(oo), cy(cyy), x(xx) {
-    n0 = c->lv[0].n();
+  // allow_pitch: the solve may lay the finest level out with pitched rows
+  // (hz_solve; the serving engine keeps [nz][nx])
+  BicgIter(hz_ctx* cc, const hz_solve_opts* oo, const Cycle& cyy, double2* xx, bool allow_pitch = false)
+      : c(cc), o(oo), cy(cyy), x(xx) {
+    fused = fused_pre(cy) && c->dim != 3;
+    vfree = fused && c->dim == 2;
+    // every finest-level kernel of the fused 2D path with V(2,2) reads the
+    // pitch; other shapes sweep the finest level with kernels that do not
+    pitched = allow_pitch && vfree && cy.nu2 == 2 && fine_pitch(c->lv[0].nx) != c->lv[0].nx;
+    c->fine_px = pitched ? fine_pitch(c->lv[0].nx) : 0;
+    n0 = level_stride(c, 0);
     bt = batch_of(c);
     rd = reducer(c);
     g0 = grid_of(c, 0);
@@ -930,15 +952,20 @@ struct BicgIter {
     v = c->fine[kV].as<double2>();
     s = c->fine[kS].as<double2>();
     t = c->fine[kT].as<double2>();
+    if (pitched) {  // v and t are not stored on this path: their buffers hold the iterate and b
+      xp = v;
+      bp = t;
+      x = xp;
+      v = nullptr;
+      t = nullptr;
+    }
     identity = cy.precond == HZ_PRECOND_NONE;
-    fused = fused_pre(cy) && c->dim != 3;
     // 2D with the fused pre-smoothing kernel: v = B p^ is never stored. The
     // pre-smoothing kernels form it from p^ (the last iteration's p^ for the p
     // update, the current one for s), and sigma = <r^, B p^> is formed at the
     // nodes of r^'s sparse list. Slots whose r^ is dense (a right-hand side
     // with many nonzeros, or after a restart) take sigma from an operator pass
-    // that stores nothing, launched while any active slot needs it.
-    vfree = fused && c->dim == 2;
+    // that stores nothing, launched while any active slot needs it (vfree).
     // The iterate is advanced every second iteration: p^ and s^ of iteration
     // 2k (ring 0) stay in their buffers while 2k+1 (ring 1) writes the others,
     // and ring 1's update adds both terms (one read and write of x instead of
@@ -960,12 +987,29 @@ struct BicgIter {
   // slot0 .. slot0 + nlist - 1.
   hipError_t start(const Batch& lb, int cap, const double2* b, int slot0, int nlist) {
     hipStream_t st = c->stream;
-    hipError_t e = launch_bicg_init(n0, lb, cap, rd, b, x, r, rh, p, v, n0, st);
+    const size_t nd = c->lv[0].n();  // the caller's b: [nz][nx] per slot
+    hipError_t e = hipSuccess;
+    const double2* b0 = b;
+    if (pitched) {  // b with pitched rows, zero past column nx (every slot of the list's range)
+      const int nz = c->lv[0].nz, nx = c->lv[0].nx;
+      e = launch_repitch(nlist, nz, nx, b + (size_t)slot0 * nd, nx, nd, bp + (size_t)slot0 * n0, c->fine_px, n0,
+                         st);
+      b0 = bp;
+    }
+    if (e == hipSuccess) e = launch_bicg_init(n0, lb, cap, rd, b0, x, r, rh, p, v, n0, st);
     if (e == hipSuccess) e = launch_bicg_fin(kFinInit, vt, lb, cap, rd, o->tol, o->maxit, nullptr, n0, st);
-    // the plain path keeps every r^ dense (rh_nnz = -1 in the slot records)
+    // the plain path keeps every r^ dense (rh_nnz = -1 in the slot records); the
+    // list holds node indices iz * nx + ix
     if (e == hipSuccess && !cy.plain)
-      e = launch_rh_sparse(n0, nlist, lb, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), n0, st, slot0);
+      e = launch_rh_sparse(nd, nlist, lb, b, c->rh_idx.as<int>(), c->rh_val.as<double2>(), nd, st, slot0);
     return e;
+  }
+
+  // The pitched iterate into the caller's x ([nz][nx] per slot).
+  hipError_t finish(double2* xout, int nslots) {
+    if (!pitched) return hipSuccess;
+    const int nz = c->lv[0].nz, nx = c->lv[0].nx;
+    return launch_repitch(nslots, nz, nx, xp, c->fine_px, n0, xout, nx, c->lv[0].n(), c->stream);
   }
 
   // One BiCGSTAB iteration for the first `capx` entries of the active list,
@@ -1031,8 +1075,9 @@ struct BicgIter {
                           : launch_bicg_xr(n0, bt, capx, rd, x, ph, sh, s, t, r, rh, n0, sx, rg, phr[0], shr[0]);
            })) != hipSuccess)
         break;
+      // (the fused path gathers r at the list's nodes through the grid: its rows may be pitched)
       e = launch_bicg_fin(kFinStep, vfree ? gt : vt, bt, capx, rd, o->tol, o->maxit, r, n0, sx, rg,
-                          o->restart_at);
+                          o->restart_at, vfree ? &g0 : nullptr);
     } while (false);
     c->stream = saved;
     return e;
@@ -1053,7 +1098,11 @@ struct BicgIter {
 
 int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
                  const double2* b, double2* x) {
-  BicgIter it(c, o, cy, x);
+  BicgIter it(c, o, cy, x, true);
+  struct PitchReset {  // the pitched layout ends with this solve, on every return
+    hz_ctx* c;
+    ~PitchReset() { c->fine_px = 0; }
+  } pitch_reset{c};
   const Batch bt = it.bt;
   const size_t n0 = it.n0;
   hipStream_t st = c->stream;
@@ -1180,7 +1229,8 @@ int run_bicgstab(hz_ctx* c, const hz_solve_opts* o, const Cycle& cy, int nslots,
     if ((rc = close_unit()) != HZ_OK) return rc;
   }
   // terms of slots that stopped after a ring-0 update
-  if (it.defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 0, x, it.phr[0], it.shr[0], n0, st));
+  if (it.defer) HZ_HIP(c, launch_bicg_flush(n0, nslots, bt, 0, it.x, it.phr[0], it.shr[0], n0, st));
+  HZ_HIP(c, it.finish(x, nslots));
   HZ_HIP(c, hipStreamSynchronize(st));
   fold_timing(c);
   return HZ_OK;
@@ -2431,7 +2481,8 @@ size_t engine_bytes(int nz, int nx, int lanes, int width, const hz_solve_opts* o
   size_t bytes = 0;
   const size_t n0 = (size_t)nz * nx;
   for (int l = 0; l < L; ++l) bytes += lanes * level_nodes(nz, nx, l) * sizeof(double);  // models
-  bytes += (size_t)(kNumFine + 2) * slots * n0 * z;  // Krylov vectors, right-hand sides, iterates
+  bytes += (size_t)kNumFine * slots * fine_nodes(2, nz, 1, nx) * z;  // Krylov vectors
+  bytes += (size_t)2 * slots * n0 * z;                               // right-hand sides, iterates
   for (int l = 1; l < L; ++l) bytes += (size_t)kNumLevelVec * slots * level_nodes(nz, nx, l) * z;
   for (int l = 0; l + 1 < L; ++l) bytes += lanes * level_nodes(nz, nx, l) * z;  // w / D tables
   const size_t nc = level_nodes(nz, nx, L - 1);

@@ -340,14 +340,16 @@ __device__ __forceinline__ TileOrg tile_org(int tile, int ntx) {
   return TileOrg{tzi * kTZ, (tile - tzi * ntx) * kTX};
 }
 
-// S[hz][hx] = val(q) at grid node (z0 - 1 + hz, x0 - 1 + hx) if it exists, else 0.
+// S[hz][hx] = val(q) at grid node (z0 - 1 + hz, x0 - 1 + hx) if it exists, else 0;
+// q is the node's index in the level's vectors (row pitch vpitch(g)).
 template <class F>
 __device__ __forceinline__ void fill_halo(double2 (*S)[kHX], const Grid& g, TileOrg t, F val) {
+  const int vp = vpitch(g);
   for (int e = threadIdx.x; e < kHZ * kHX; e += kBlock) {
     const int hz = e / kHX, hx = e - hz * kHX;
     const int gz = t.z0 - 1 + hz, gx = t.x0 - 1 + hx;
     double2 v = make_double2(0.0, 0.0);
-    if (gz >= 0 && gz < g.nz && gx >= 0 && gx < g.nx) v = val(gz * g.nx + gx, hz, hx);
+    if (gz >= 0 && gz < g.nz && gx >= 0 && gx < g.nx) v = val(gz * vp + gx, hz, hx);
     S[hz][hx] = v;
   }
 }

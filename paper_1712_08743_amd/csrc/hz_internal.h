@@ -46,7 +46,22 @@ struct Grid {
   // 2D grids with a density: the level's coupling table (RhoC in hz_device.h),
   // [3][nz][nx]; the fused kernels read it instead of rho
   const double* dc = nullptr;
+  // 2D finest level of the fused BiCGSTAB path: the row pitch of the level's
+  // vectors, > nx so that every row starts on a 128-byte line (0: nx). The
+  // tables above stay [nz][nx]. Only the kernels of that path read it.
+  int px = 0;
 };
+
+// the row pitch of a 2D level's vectors
+__host__ __device__ inline int vpitch(const Grid& g) { return g.px > 0 ? g.px : g.nx; }
+
+// The row pitch of the finest level's vectors on the fused 2D BiCGSTAB path:
+// nx rounded up to 8 complex values (128 bytes), and the nodes per slot the
+// finest-level vector buffers hold (the pitched rows on 2D grids).
+inline int fine_pitch(int nx) { return (nx + 7) & ~7; }
+inline size_t fine_nodes(int dim, int nz, int ny, int nx) {
+  return dim == 2 ? (size_t)nz * fine_pitch(nx) : (size_t)nz * ny * nx;
+}
 
 // Per-frequency constants (device table).
 struct FreqTab {
@@ -242,6 +257,7 @@ hipError_t launch_gj_step(int nc, int nfreq, int k, const double2* A_in, double2
 // BiCGSTAB pieces. Each producer stores block partials; launch_bicg_fin
 // (one block per slot) sums them in a fixed order and updates the slot's
 // scalars and status.
+// (v null in init and restart: v is not stored)
 hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd,
                             const double2* b, double2* x, double2* r, double2* rh, double2* p,
                             double2* v, size_t stride, hipStream_t st);
@@ -296,6 +312,10 @@ hipError_t launch_compact(int nslots, int nrhs, int nfreq, Slot* slots, int* act
                           int* fstart, Summary* sum, int want_phase, hipStream_t st);
 hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, double2* y,
                        size_t stride, hipStream_t st);
+// dst = src for nslots slots of an nz x nx grid, rows of pitch sp in src
+// (slot stride ss) and dp in dst (slot stride ds); dst's padding is zeroed
+hipError_t launch_repitch(int nslots, int nz, int nx, const double2* src, int sp, size_t ss, double2* dst, int dp,
+                          size_t ds, hipStream_t st);
 
 // ||b - B x||^2 and ||b||^2 per slot of the list into out[slot*2 + {0,1}]
 hipError_t launch_true_residual(int dim, const Grid& g, const Batch& bt, int cap,

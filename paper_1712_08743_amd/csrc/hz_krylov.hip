@@ -28,7 +28,21 @@ __global__ void __launch_bounds__(kBlock) k_copy(Batch bt, int tiles, size_t n,
   }
 }
 
-// x = 0, r = rh = b, p = v = 0; partial ||b||^2.
+// dst = src row by row for nslots slots of an nz x nx grid whose rows have
+// pitch sp (slot stride ss) in src and dp (slot stride ds) in dst; dst's
+// columns nx .. dp - 1 are set to zero.
+__global__ void __launch_bounds__(kBlock) k_repitch(int nz, int nx, const double2* __restrict__ src, int sp,
+                                                    size_t ss, double2* __restrict__ dst, int dp, size_t ds,
+                                                    size_t total) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const size_t per = (size_t)nz * dp;
+  const size_t slot = i / per, rem = i - slot * per;
+  const int row = (int)(rem / dp), col = (int)(rem - (size_t)row * dp);
+  dst[slot * ds + rem] = col < nx ? src[slot * ss + (size_t)row * sp + col] : c2(0.0, 0.0);
+}
+
+// x = 0, r = rh = b, p = v = 0 (v null: not stored); partial ||b||^2.
 __global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt, int tiles, size_t n, Reduce rd,
                                                       const double2* __restrict__ b,
                                                       double2* __restrict__ x, double2* __restrict__ r,
@@ -48,7 +62,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt, int tiles, size_
       r[base + i] = bi;
       rh[base + i] = bi;
       p[base + i] = z;
-      v[base + i] = z;
+      if (v) v[base + i] = z;
       acc[0] += bi.x * bi.x + bi.y * bi.y;
     }
   }
@@ -170,6 +184,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
   const bool dots = WHICH == 1 || bt.slots[slot].rh_nnz < 0;
   // the thread's own nodes' inputs are loaded before the halo fill and its
   // barrier, so that their latency overlaps the fill's
+  // (node indices: p in the tables, pv in the vectors, whose rows have pitch vp)
+  const int vp = vpitch(g);
   double2 ov[kRowsPerThread];
   TileCoef cv[kRowsPerThread];
   const double* m = model_m(g, f);
@@ -177,8 +193,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
   for (int r = 0; r < kRowsPerThread; ++r) {
     const int iz = t.z0 + threadIdx.x / kTX + (kBlock / kTX) * r, ix = t.x0 + threadIdx.x % kTX;
     const bool in = iz < g.nz && ix < g.nx;
-    const int p = in ? iz * g.nx + ix : 0;
-    ov[r] = in && dots ? other[base + p] : c2(0.0, 0.0);
+    const int p = in ? iz * g.nx + ix : 0, pv = in ? iz * vp + ix : 0;
+    ov[r] = in && dots ? other[base + pv] : c2(0.0, 0.0);
     cv[r] = tile_coef<RHO>(g, m, in ? iz : 0, in ? ix : 0, p);
   }
   const double2* xs = xin + base;
@@ -191,9 +207,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_apply_t(Grid g, int ntx, int pe
     const int lz = threadIdx.x / kTX + (kBlock / kTX) * r, lx = threadIdx.x % kTX;
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= g.nz || ix >= g.nx) continue;
-    const int p = iz * g.nx + ix;
     const double2 yp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, cv[r], ih, ih2);
-    if (y) st_nt(y + base + p, yp);
+    if (y) st_nt(y + base + (size_t)iz * vp + ix, yp);
     if (WHICH == 0) {
       if (dots) {
         const double2 d = cconjmul(ov[r], yp);
@@ -395,12 +410,13 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr_t(Grid g, int ntx, int per_s
       RH[kRowsPerThread];
   TileCoef cv[kRowsPerThread];
   const double* m = model_m(g, f);
+  const int vp = vpitch(g);  // row pitch of the vectors (the tables have nx)
 #pragma unroll
   for (int k = 0; k < kRowsPerThread; ++k) {
     const int iz = t.z0 + threadIdx.x / kTX + (kBlock / kTX) * k, ix = t.x0 + threadIdx.x % kTX;
     const bool in = iz < g.nz && ix < g.nx;
     const int p = in ? iz * g.nx + ix : 0;
-    const size_t q = base + p;
+    const size_t q = base + (in ? (size_t)iz * vp + ix : 0);
     S[k] = in ? ld_nt(s + q) : zero;
     XV[k] = in && XMODE != 0 ? ld_nt(x + q) : zero;
     PH[k] = in && XMODE != 0 ? ld_nt(ph + q) : zero;
@@ -419,8 +435,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr_t(Grid g, int ntx, int per_s
     const int lz = threadIdx.x / kTX + (kBlock / kTX) * k, lx = threadIdx.x % kTX;
     const int iz = t.z0 + lz, ix = t.x0 + lx;
     if (iz >= g.nz || ix >= g.nx) continue;
-    const int p = iz * g.nx + ix;
-    const size_t q = base + p;
+    const size_t q = base + (size_t)iz * vp + ix;
     const double2 tp = apply_b_tile<RHO>(g, f, X, lz, lx, iz, ix, cv[k], ih, ih2);
     const double2 ri = csub(S[k], cmul(om, tp));
     st_nt(r + q, ri);
@@ -476,7 +491,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_restart(int tiles, size_t n, Ba
       const double2 ri = r[base + i];
       rh[base + i] = ri;
       p[base + i] = c2(0.0, 0.0);
-      v[base + i] = c2(0.0, 0.0);
+      if (v) v[base + i] = c2(0.0, 0.0);
       const double2 d = cconjmul(ri, ri);
       acc[0] += d.x;
       acc[1] += d.y;
@@ -562,15 +577,20 @@ __global__ void __launch_bounds__(kBlock) k_bicg_fin(int which, int tiles, Batch
     const double2* val = bt.rh_val + (size_t)slot * kShadowMax;
     const double2* vs = vec + (size_t)slot * stride;
     const FreqTab& f = bt.ft[bt.slots[slot].freq];
+    // the list holds node indices iz * nx + ix (of the tables); with a grid
+    // (form_b, and every 2D step reduction) the vector's rows have pitch vp
+    const int vp = g.nx > 0 ? vpitch(g) : 0;
     for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
       const int p = idx[k];
+      const int iz = g.nx > 0 ? p / g.nx : 0, ix = p - iz * g.nx;
+      const int pv = g.nx > 0 ? iz * vp + ix : p;
       double2 y;
       if (form_b) {
-        const int iz = p / g.nx, ix = p - iz * g.nx;
         const NodeOp o = node_op<true>(g, iz, ix, p, model_m(g, f)[p], f.omega, f.sB_re, f.sB_im);
-        y = apply_op<true>(g, o, vs, p, iz, ix, 1.0 / (g.h * g.h), vs[p]);
+        y = apply_op_at<true>(g, o, iz, ix, 1.0 / (g.h * g.h), vs[pv],
+                              [&](int dz, int dx) { return vs[pv + dz * vp + dx]; });
       } else {
-        y = vs[p];
+        y = vs[pv];
       }
       const double2 d = cconjmul(val[k], y);
       acc[0] += d.x;
@@ -1315,6 +1335,17 @@ hipError_t launch_copy(const Batch& bt, int cap, size_t n, const double2* x, dou
   return hipGetLastError();
 }
 
+hipError_t launch_repitch(int nslots, int nz, int nx, const double2* src, int sp, size_t ss, double2* dst, int dp,
+                          size_t ds, hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  if (nz <= 0 || nx <= 0 || sp < nx || dp < nx || ss < (size_t)nz * sp || ds < (size_t)nz * dp || !src || !dst)
+    return hipErrorInvalidValue;
+  const size_t total = (size_t)nslots * nz * dp;
+  hipLaunchKernelGGL(k_repitch, grid1((long long)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nz, nx, src,
+                     sp, ss, dst, dp, ds, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd, const double2* b,
                             double2* x, double2* r, double2* rh, double2* p, double2* v,
                             size_t stride, hipStream_t st) {
@@ -1421,7 +1452,7 @@ hipError_t launch_bicg_xr_t(const Grid& g, const Batch& bt, int cap, const Reduc
   if (cap <= 0) return hipSuccess;
   if (ring == 1 && (!ph0 || !sh0)) return hipErrorInvalidValue;
   if (g.rho && !g.dc) return hipErrorInvalidValue;  // a density needs the level's coupling table
-  if (stride < (size_t)g.nz * g.nx || ring < -1 || ring > 1) return hipErrorInvalidValue;
+  if (stride < (size_t)g.nz * vpitch(g) || vpitch(g) < g.nx || ring < -1 || ring > 1) return hipErrorInvalidValue;
   const int ntx = (g.nx + kTX - 1) / kTX, per = lds_tiles(g.nz, g.nx);
   const dim3 gr = grid1(tile_blocks(per, cap));
 #define HZ_XR_T(XM, RH)                                                                                          \

@@ -296,7 +296,7 @@ size_t hz_footprint(int dim, int nz, int nx, int nfreq, int nrhs, const hz_solve
   }
   size_t bytes = 0;
   for (int l = 0; l < L; ++l) bytes += n[l] * sizeof(double);  // slowness per level
-  bytes += (size_t)hz::kFineVectors * slots * n[0] * z;         // Krylov and smoothing vectors
+  bytes += (size_t)hz::kFineVectors * slots * hz::fine_nodes(dim, nz, 1, nx) * z;  // Krylov and smoothing vectors
   bytes += slots * hz::kShadowMax * (sizeof(int) + z);          // sparse shadow residuals
   for (int l = 1; l < L; ++l) bytes += 4 * slots * n[l] * z;     // level vectors
   if (o->precond == HZ_PRECOND_MG) {

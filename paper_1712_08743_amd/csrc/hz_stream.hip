@@ -174,15 +174,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
   const AxisC cx = axis_coef(x, g.nx);
   const double cwx = ih2 * cx.w;
   const double2 zero = c2(0.0, 0.0);
+  // node (j, xx) in the tables ([nz][nx]) and in the vectors (row pitch vp)
+  const int vp = vpitch(g);
   auto row_index = [&](int j) { return (size_t)min(max(j, 0), g.nz - 1) * g.nx + xx; };
+  auto vrow_index = [&](int j) { return (size_t)min(max(j, 0), g.nz - 1) * vp + xx; };
   const size_t nn = (size_t)g.nz * g.nx;
   auto load_row = [&](int j) {
     PreRow<MODE> r;
-    const size_t q = row_index(j);
-    r.a = in.a[base + q];
-    if (MODE != 0 && MODE != 5) r.b = in.b[base + q];
-    if (MODE == 1) r.c = in.c[base + q];
-    if (MODE >= 4) r.c = in.c[base + row_index(j + 1)];
+    const size_t q = row_index(j), qv = vrow_index(j);
+    r.a = in.a[base + qv];
+    if (MODE != 0 && MODE != 5) r.b = in.b[base + qv];
+    if (MODE == 1) r.c = in.c[base + qv];
+    if (MODE >= 4) r.c = in.c[base + vrow_index(j + 1)];
     r.wd = wd[q];
     r.m = model_m(g, f)[q];
     if (RHO) {
@@ -207,8 +210,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
   // MODE 4, 5: p^ on rows j-1 and j
   double2 q0 = zero, q1 = zero;
   if (MODE >= 4) {
-    q0 = p_hat(w.z0 - 4, in.c[base + row_index(w.z0 - 4)]);
-    q1 = p_hat(w.z0 - 3, in.c[base + row_index(w.z0 - 3)]);
+    q0 = p_hat(w.z0 - 4, in.c[base + vrow_index(w.z0 - 4)]);
+    q1 = p_hat(w.z0 - 3, in.c[base + vrow_index(w.z0 - 3)]);
     // B p^ on the first row of the march couples to the row above it
     if (RHO) cd1 = g.dc[nn + row_index(w.z0 - 4)];
   }
@@ -254,7 +257,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MOD
       u2c = keep(xin && i2 >= 0 && i2 < g.nz, v);
     }
     if (own && i2 >= w.z0 && i2 < w.z1) {
-      const size_t q = base + (size_t)i2 * g.nx + x;
+      const size_t q = base + (size_t)i2 * vp + x;
       if (MODE != 0) st_nt(bout + q, b1);
       if (u2) u2[q] = u2c;
     }
@@ -355,10 +358,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RHO
   const int ox = x & 1;
   const int Jx = xx >> 1, Jx1 = min(Jx + 1, gc.nx - 1);
   const size_t nn = (size_t)gf.nz * gf.nx;
+  const int vp = vpitch(gf);  // row pitch of b and u_out (the tables have nx)
   auto load_row = [&](int j) {
     PostRow r;
-    const size_t q = (size_t)min(max(j, 0), gf.nz - 1) * gf.nx + xx;
-    r.b = bs[q];
+    const int jc = min(max(j, 0), gf.nz - 1);
+    const size_t q = (size_t)jc * gf.nx + xx;
+    r.b = bs[(size_t)jc * vp + xx];
     r.wd = wd[q];
     if (RHO) {
       const size_t q1 = (size_t)min(max(j - 1, 0), gf.nz - 1) * gf.nx + xx;
@@ -421,12 +426,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RHO
       const RhoC c5 = rho_row(x, i5, cr3, cd3, cd4);
       const double2 ul = from_left(u4b), ur = from_right(u4b);
       if (own && i5 >= w.z0 && i5 < w.z1)
-        st_nt(u_out + base + (size_t)i5 * gf.nx + x, jacobi_rho(u4b, b3, w3, c5, ul, ur, u4a, u4c, ih2, omw));
+        st_nt(u_out + base + (size_t)i5 * vp + x, jacobi_rho(u4b, b3, w3, c5, ul, ur, u4a, u4c, ih2, omw));
     } else {
       const double2 sx = cadd(from_left(u4b), from_right(u4b));
       if (own && i5 >= w.z0 && i5 < w.z1) {
         const double2 sz = cadd(u4a, u4c);
-        st_nt(u_out + base + (size_t)i5 * gf.nx + x, jacobi(u4b, b3, w3, sx, sz, ih2 * axis_coef(i5, gf.nz).w, cwx, omw));
+        st_nt(u_out + base + (size_t)i5 * vp + x, jacobi(u4b, b3, w3, sx, sz, ih2 * axis_coef(i5, gf.nz).w, cwx, omw));
       }
     }
     u1a = u1b;
