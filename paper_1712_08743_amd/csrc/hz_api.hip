@@ -924,10 +924,10 @@ struct BicgIter {
   double2 *phr[2], *shr[2], *ph, *sh;
   bool identity, fused, vfree, defer;
   bool dense_rh = false;  // some active slot's r^ is a dense vector
-  // pitched: the finest-level vectors, the iterate and a copy of b have rows
-  // of pitch c->fine_px (the caller's b and x stay [nz][nx])
+  // pitched: the finest-level vectors and the iterate have rows of pitch
+  // c->fine_px (the caller's b and x stay [nz][nx])
   bool pitched = false;
-  double2 *xp = nullptr, *bp = nullptr;
+  double2* xp = nullptr;
   int vt, gt;
 
   // allow_pitch: the solve may lay the finest level out with pitched rows
@@ -952,9 +952,8 @@ struct BicgIter {
     v = c->fine[kV].as<double2>();
     s = c->fine[kS].as<double2>();
     t = c->fine[kT].as<double2>();
-    if (pitched) {  // v and t are not stored on this path: their buffers hold the iterate and b
+    if (pitched) {  // v and t are not stored on this path: v's buffer holds the iterate
       xp = v;
-      bp = t;
       x = xp;
       v = nullptr;
       t = nullptr;
@@ -978,7 +977,7 @@ struct BicgIter {
     shr[1] = identity ? s : c->fine[kSh2].as<double2>();
     ph = phr[0];
     sh = shr[0];
-    vt = vec_tiles(n0);
+    vt = vec_tiles(c->lv[0].n());  // tiles of the init and restart passes (and of the flat update)
     gt = reduce_tiles(c->lv[0].rows(), c->lv[0].nx, c->dim);  // tiles of the operator-apply kernels
   }
 
@@ -988,15 +987,8 @@ struct BicgIter {
   hipError_t start(const Batch& lb, int cap, const double2* b, int slot0, int nlist) {
     hipStream_t st = c->stream;
     const size_t nd = c->lv[0].n();  // the caller's b: [nz][nx] per slot
-    hipError_t e = hipSuccess;
-    const double2* b0 = b;
-    if (pitched) {  // b with pitched rows, zero past column nx (every slot of the list's range)
-      const int nz = c->lv[0].nz, nx = c->lv[0].nx;
-      e = launch_repitch(nlist, nz, nx, b + (size_t)slot0 * nd, nx, nd, bp + (size_t)slot0 * n0, c->fine_px, n0,
-                         st);
-      b0 = bp;
-    }
-    if (e == hipSuccess) e = launch_bicg_init(n0, lb, cap, rd, b0, x, r, rh, p, v, n0, st);
+    // (pitched: r, r^, p and x take the nodes at their pitched places; the padding is never read)
+    hipError_t e = launch_bicg_init(nd, lb, cap, rd, b, x, r, rh, p, v, n0, st, nd, c->lv[0].nx, c->fine_px);
     if (e == hipSuccess) e = launch_bicg_fin(kFinInit, vt, lb, cap, rd, o->tol, o->maxit, nullptr, n0, st);
     // the plain path keeps every r^ dense (rh_nnz = -1 in the slot records); the
     // list holds node indices iz * nx + ix
@@ -1089,7 +1081,8 @@ struct BicgIter {
     hipStream_t st = c->stream;
     hipError_t e = hipSuccess;
     if (defer) e = launch_bicg_flush(n0, nslots, bt, 1, x, phr[0], shr[0], n0, st);
-    if (e == hipSuccess) e = launch_bicg_restart(n0, nslots, bt, rd, r, rh, p, v, n0, st);  // current p buffer
+    if (e == hipSuccess)  // current p buffer
+      e = launch_bicg_restart(c->lv[0].n(), nslots, bt, rd, r, rh, p, v, n0, st, c->lv[0].nx, c->fine_px);
     if (e == hipSuccess) e = launch_bicg_fin(kFinRestart, vt, bt, nslots, rd, o->tol, o->maxit, nullptr, n0, st);
     dense_rh = true;  // r^ = r for the restarted slots
     return e;

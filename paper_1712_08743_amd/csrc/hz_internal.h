@@ -257,10 +257,15 @@ hipError_t launch_gj_step(int nc, int nfreq, int k, const double2* A_in, double2
 // BiCGSTAB pieces. Each producer stores block partials; launch_bicg_fin
 // (one block per slot) sums them in a fixed order and updates the slot's
 // scalars and status.
-// (v null in init and restart: v is not stored)
+// (v null in init and restart: v is not stored). Init and restart take n
+// nodes in [nz][nx] order: px > 0 places node i of row i / nx at
+// (i / nx) * px + i % nx in x, r, rh, p and v (rows of pitch px; b keeps
+// [nz][nx] rows, slot stride bstride, 0: stride); their sums then group as
+// with px = 0.
 hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd,
                             const double2* b, double2* x, double2* r, double2* rh, double2* p,
-                            double2* v, size_t stride, hipStream_t st);
+                            double2* v, size_t stride, hipStream_t st, size_t bstride = 0, int nx = 0,
+                            int px = 0);
 hipError_t launch_bicg_p(size_t n, const Batch& bt, int cap, const double2* r, const double2* p_old,
                          const double2* v, double2* p_new, size_t stride, hipStream_t st);
 // v null (2D only): no store; only the slots whose r^ is dense get a partial.
@@ -292,7 +297,7 @@ hipError_t launch_bicg_flush(size_t n, int nslots, const Batch& bt, int only_res
                              const double2* ph0, const double2* sh0, size_t stride, hipStream_t st, int slot0 = 0);
 hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
                                const double2* r, double2* rh, double2* p, double2* v,
-                               size_t stride, hipStream_t st);
+                               size_t stride, hipStream_t st, int nx = 0, int px = 0);
 // The sparse list of r^ = b for every one of the nslots slots (rh_nnz = -1
 // where b has more than kShadowMax nonzeros). idx/val: the arrays Batch
 // points to, writable.

@@ -42,27 +42,40 @@ __global__ void __launch_bounds__(kBlock) k_repitch(int nz, int nx, const double
   dst[slot * ds + rem] = col < nx ? src[slot * ss + (size_t)row * sp + col] : c2(0.0, 0.0);
 }
 
-// x = 0, r = rh = b, p = v = 0 (v null: not stored); partial ||b||^2.
+// Node i of n in [nz][nx] order at its place in a vector whose rows have
+// pitch px (px = 0: the same index). Init and restart walk the nodes in this
+// order whatever the pitch, so their sums group as without one.
+__device__ __forceinline__ size_t pitched_at(size_t i, int nx, int px) {
+  if (px == 0) return i;
+  const size_t row = i / (size_t)nx;
+  return row * px + (i - row * nx);
+}
+
+// x = 0, r = rh = b, p = v = 0 (v null: not stored); partial ||b||^2. b has
+// slot stride bstride and rows of nx; the others stride and rows of pitch px
+// (0: nx). A pitched vector's padding is not written.
 __global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt, int tiles, size_t n, Reduce rd,
                                                       const double2* __restrict__ b,
                                                       double2* __restrict__ x, double2* __restrict__ r,
                                                       double2* __restrict__ rh, double2* __restrict__ p,
-                                                      double2* __restrict__ v, size_t stride) {
+                                                      double2* __restrict__ v, size_t stride, size_t bstride,
+                                                      int nx, int px) {
   int slot, tile;
   if (!decode_vec(bt, tiles, slot, tile)) return;
-  const size_t base = (size_t)slot * stride;
+  const size_t base = (size_t)slot * stride, bbase = (size_t)slot * bstride;
   double acc[1] = {0.0};
 #pragma unroll
   for (int e = 0; e < kVecPerThread; ++e) {
     const size_t i = vec_index(tile, e);
     if (i < n) {
-      const double2 bi = b[base + i];
+      const double2 bi = b[bbase + i];
+      const size_t a = base + pitched_at(i, nx, px);
       const double2 z = c2(0.0, 0.0);
-      x[base + i] = z;
-      r[base + i] = bi;
-      rh[base + i] = bi;
-      p[base + i] = z;
-      if (v) v[base + i] = z;
+      x[a] = z;
+      r[a] = bi;
+      rh[a] = bi;
+      p[a] = z;
+      if (v) v[a] = z;
       acc[0] += bi.x * bi.x + bi.y * bi.y;
     }
   }
@@ -474,11 +487,12 @@ __global__ void __launch_bounds__(kBlock) k_bicg_flush(Batch bt, int tiles, size
 }
 
 // The one restart after a breakdown: rh = r, p = v = 0; partial <r, r>.
+// (n nodes in [nz][nx] order; the vectors' rows have pitch px, 0: nx)
 __global__ void __launch_bounds__(kBlock) k_bicg_restart(int tiles, size_t n, Batch bt, Reduce rd,
                                                          const double2* __restrict__ r,
                                                          double2* __restrict__ rh,
                                                          double2* __restrict__ p,
-                                                         double2* __restrict__ v, size_t stride) {
+                                                         double2* __restrict__ v, size_t stride, int nx, int px) {
   const int slot = blockIdx.x / tiles;
   const int tile = blockIdx.x - slot * tiles;
   if (bt.slots[slot].status != kRestart) return;
@@ -488,10 +502,11 @@ __global__ void __launch_bounds__(kBlock) k_bicg_restart(int tiles, size_t n, Ba
   for (int e = 0; e < kVecPerThread; ++e) {
     const size_t i = vec_index(tile, e);
     if (i < n) {
-      const double2 ri = r[base + i];
-      rh[base + i] = ri;
-      p[base + i] = c2(0.0, 0.0);
-      if (v) v[base + i] = c2(0.0, 0.0);
+      const size_t a = base + pitched_at(i, nx, px);
+      const double2 ri = r[a];
+      rh[a] = ri;
+      p[a] = c2(0.0, 0.0);
+      if (v) v[a] = c2(0.0, 0.0);
       const double2 d = cconjmul(ri, ri);
       acc[0] += d.x;
       acc[1] += d.y;
@@ -1348,10 +1363,12 @@ hipError_t launch_repitch(int nslots, int nz, int nx, const double2* src, int sp
 
 hipError_t launch_bicg_init(size_t n, const Batch& bt, int cap, const Reduce& rd, const double2* b,
                             double2* x, double2* r, double2* rh, double2* p, double2* v,
-                            size_t stride, hipStream_t st) {
+                            size_t stride, hipStream_t st, size_t bstride, int nx, int px) {
   if (cap <= 0) return hipSuccess;
+  if (px != 0 && (nx <= 0 || px < nx || n % (size_t)nx != 0 || stride < n / nx * px)) return hipErrorInvalidValue;
   const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_bicg_init, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, b, x, r, rh, p, v, stride);
+  hipLaunchKernelGGL(k_bicg_init, grid1((long long)cap * tiles), dim3(kBlock), 0, st, bt, tiles, n, rd, b, x, r, rh, p,
+                     v, stride, bstride ? bstride : stride, nx, px);
   return hipGetLastError();
 }
 
@@ -1481,9 +1498,11 @@ hipError_t launch_bicg_flush(size_t n, int nslots, const Batch& bt, int only_res
 
 hipError_t launch_bicg_restart(size_t n, int nslots, const Batch& bt, const Reduce& rd,
                                const double2* r, double2* rh, double2* p, double2* v,
-                               size_t stride, hipStream_t st) {
+                               size_t stride, hipStream_t st, int nx, int px) {
+  if (px != 0 && (nx <= 0 || px < nx || n % (size_t)nx != 0 || stride < n / nx * px)) return hipErrorInvalidValue;
   const int tiles = vec_tiles(n);
-  hipLaunchKernelGGL(k_bicg_restart, grid1((long long)nslots * tiles), dim3(kBlock), 0, st, tiles, n, bt, rd, r, rh, p, v, stride);
+  hipLaunchKernelGGL(k_bicg_restart, grid1((long long)nslots * tiles), dim3(kBlock), 0, st, tiles, n, bt, rd, r, rh,
+                     p, v, stride, nx, px);
   return hipGetLastError();
 }
 

@@ -80,6 +80,31 @@ def test_concurrent_requests_match_standalone_bitwise(hz, slots):
         srv.close()
 
 
+def test_dense_right_hand_sides_match_standalone_bitwise(hz):
+    """Dense right-hand sides (every node nonzero, so r^ stays a dense vector
+    and ||b||^2 sums every node): a standalone solve lays the finest level
+    out with pitched rows (nx = 65 and 129 are not multiples of 8), the
+    server's engine with [nz][nx] rows, and the results agree bit for bit."""
+    import torch
+    lens = workloads.model_2d_lens(n=65, h=20.0)
+    lay = workloads.model_2d_layered(nz=33, nx=129, h=20.0, nshots=2, freqs=(3.0, 5.0))
+    reqs = []
+    for k, (mdl, freqs, nrhs) in enumerate([(lens, (4.0,), 2), (lay, (3.0, 5.0), 2)]):
+        b = workloads.random_vectors(len(freqs) * nrhs, mdl.m.size, 20 + k)
+        reqs.append((mdl.m, mdl.h, freqs, torch.from_numpy(b.reshape((len(freqs), nrhs) + mdl.shape))))
+    ref = _standalone(hz, reqs, tol=1e-9)
+    srv = hz.Server(0, slots=1)
+    try:
+        tickets = [srv.submit(torch.from_numpy(m), h, freqs, 0.02, b, tol=1e-9) for m, h, freqs, b in reqs]
+        for (u_ref, info_ref), tk in zip(ref, tickets):
+            u, info, _ = srv.wait(tk)
+            assert [i[0] for i in info] == [hz.HZ_RHS_CONVERGED] * len(info)
+            assert [i[1] for i in info] == [i[1] for i in info_ref]
+            assert torch.equal(u, u_ref)
+    finally:
+        srv.close()
+
+
 def test_budget_admission_and_refusal(hz):
     """With a budget that holds one large request but not two, the large
     requests never run together; small ones fill in beside them; results are
