@@ -28,6 +28,13 @@ namespace hz {
 // ---------------------------------------------------------------- grid geometry
 Tiles grid_tiles(int nz, int nx, int dim) {
   Tiles t;
+  if (dim == 3) {
+    // 3D (nz counts the nz * ny rows): kBlock consecutive nodes per tile in
+    // flat order (node3_of), so no thread idles at the end of a row
+    t.tx = t.tz = t.ntx = t.ntz = 0;
+    t.per_slot = (int)(((size_t)nz * nx + kBlock - 1) / kBlock);
+    return t;
+  }
   if (dim == 1) {
     t.tx = kBlock;
     t.tz = 1;

@@ -6,9 +6,9 @@
 // (1/2 at an end node, else 1); the boundary term carries the exposed face
 // area; the mass term the volume, the product of all three weights.
 //
-// The 3D kernels tile the grid as a 2D one of nz * ny rows by nx columns
-// (tile_node<true> over grid_tiles(nz * ny, nx, 3)), so the flat index and
-// the reduction tiles are those of a 2D grid of that shape.
+// The one-node-per-thread 3D kernels take kBlock consecutive nodes of the
+// flat index per tile (node3_of over grid_tiles(nz * ny, nx, 3)); the
+// reduction tiles are those tiles.
 #pragma once
 
 #include "hz_device.h"
@@ -130,15 +130,19 @@ __device__ __forceinline__ double2 apply_op3(const Grid& g, const NodeOp3& o, co
   });
 }
 
-// The node of a thread in the row-tiled 3D grid: false past the grid.
+// The node of a thread: node tile * kBlock + thread of the flat index
+// (iz * ny + iy) * nx + ix; false past the grid. (Rows of 129 nodes tiled
+// 64 columns wide left a third of the threads idle.)
 __device__ __forceinline__ bool node3_of(const Tiles& t, int tile, const Grid& g, int& iz, int& iy, int& ix,
                                          size_t& p) {
-  int r;
-  tile_node<true>(t, tile, r, ix);
-  if (r >= g.nz * g.ny || ix >= g.nx) return false;
+  (void)t;
+  const size_t q = (size_t)tile * kBlock + threadIdx.x;
+  if (q >= (size_t)g.nz * g.ny * g.nx) return false;
+  const int r = (int)(q / (size_t)g.nx);
+  ix = (int)(q - (size_t)r * g.nx);
   iz = r / g.ny;
   iy = r - iz * g.ny;
-  p = (size_t)r * g.nx + ix;
+  p = q;
   return true;
 }
 
